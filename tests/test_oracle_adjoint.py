@@ -1,0 +1,87 @@
+"""Pins of the oracle's implicit adjoint: tangent mapping by finite differences and the
+adjoint by central differences of converged re-solves on noise-free scenes (where the
+dropped second-order residual term vanishes)."""
+import numpy as np
+
+from oracle.adjoint import adjoint, tangent_gradient
+from oracle.geometry import retract_cameras
+from oracle.model import Problem
+from oracle.lm import Options, State, solve
+from scenes import make_scene
+
+rng = np.random.default_rng(11)
+
+
+def test_tangent_gradient_matches_finite_differences():
+    q = rng.normal(size=(5, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    c = rng.normal(size=(5, 3))
+    A = rng.normal(size=(5, 7))
+    B = rng.normal(size=(5, 7))
+
+    def L(qq, cc):
+        z = np.concatenate([qq, cc], axis=1)
+        return float(np.sum(A * z) + 0.5 * np.sum(B * z * z))
+
+    gq = A[:, :4] + B[:, :4] * q
+    gc = A[:, 4:] + B[:, 4:] * c
+    st = State(q=q, c=c, X=np.zeros((1, 3)), lam=0.0)
+    gt = tangent_gradient(st, np.arange(5), np.concatenate([gq, gc], axis=1))
+    h = 1e-6
+    for i in range(5):
+        for j in range(6):
+            d = np.zeros((1, 6))
+            d[0, j] = h
+            vals = []
+            for s in (1, -1):
+                qq, cc = q.copy(), c.copy()
+                qq[i:i + 1], cc[i:i + 1] = retract_cameras(q[i:i + 1], c[i:i + 1], s * d)
+                vals.append(L(qq, cc))
+            fd = (vals[0] - vals[1]) / (2 * h)
+            assert abs(fd - gt[i, j]) < 1e-7 * max(1, abs(fd)), (i, j, fd, gt[i, j])
+
+
+def _adjoint_scene():
+    sc = make_scene("tiny", n_points=60, noise_px=0.0, prior_frac=1.0, depth_sigma=0.0,
+                    use_depth=True, lambda_d=50.0, exact=True)
+    sc.fixed = np.array([0], np.int32)
+    return sc
+
+
+def test_adjoint_matches_central_differences_noise_free():
+    sc = _adjoint_scene()
+    opts = Options(lambda_init=1e-4, cost_rel_tol=0.0, grad_tol=1e-13, max_iters=60)
+    prob = Problem.from_scene(sc)
+    st, _ = solve(prob, State.initial(sc.cams0, sc.points0, opts), opts)
+    gt_c = sc.cams_gt[:, 4:]
+    W = rng.normal(size=sc.points_gt.shape)
+
+    def loss(s):
+        return float(np.sum((s.c - gt_c) ** 2) + np.sum(W * s.X))
+
+    grad_cams = np.zeros((sc.n_cams, 7))
+    grad_cams[:, 4:] = 2 * (st.c - gt_c)
+    gxy, gd, _ = adjoint(prob, st, opts, grad_cams, W)
+    # central differences: 1e-3 px for pixels, 1e-4 relative for depths. The re-solves
+    # reach the float32 rounding floor of the inputs (gradient noise ~1e-9), which bounds
+    # how small the step can be.
+    picks = rng.choice(prob.n_obs, size=6, replace=False)
+    fds, refs = [], []
+    for k in picks:
+        for j in range(3):
+            h = 1e-3 if j < 2 else 1e-4 / prob.dinv[k]
+            vals = []
+            for s in (1, -1):
+                p2 = Problem.from_scene(sc)
+                if j < 2:
+                    p2.xy[k, j] += s * h
+                else:
+                    p2.dinv[k] = 1.0 / (1.0 / prob.dinv[k] + s * h)
+                warm = st.copy()
+                warm.lam, warm.nu = opts.lambda_init, 2.0     # warm start, fresh damping
+                s2, _ = solve(p2, warm, opts)
+                vals.append(loss(s2))
+            fds.append((vals[0] - vals[1]) / (2 * h))
+            refs.append(gxy[k, j] if j < 2 else gd[k])
+    fds, refs = np.array(fds), np.array(refs)
+    assert np.max(np.abs(fds - refs)) <= 1e-5 * np.max(np.abs(refs)), np.c_[fds, refs]
