@@ -1,0 +1,233 @@
+"""Benchmark of the LM bundle-adjustment step on one MI355X.
+
+One "step" is one ``ba_lm_step``: extraction, linearisation, Schur complement set-up, PCG,
+back-substitution, candidate evaluation and accept/scatter, over the whole synthetic
+1000-camera scene (10 random walks, 500k points, ~4M observations, 5 % outliers, depth priors
+on 50 %). Inputs are resident in HBM before the timed region. The mixed-precision path is the
+headline value; the float64 path runs the same steps from the same start for the ratio.
+
+Prints one JSON line. ``--gpus N`` with N > 1 is not supported (single-GPU build).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "BA LM iters/s + Jacobian obs/s, FP32-mixed vs FP64, 1000-cam synthetic scene"
+HBM_PEAK_GBS = 8000.0
+LINEARIZE_KERNELS = ("lin_point", "gather_cm_metric", "cam_assemble")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--scene", default="large")
+    ap.add_argument("--precision", default="both", choices=["both", "mixed", "fp64"])
+    ap.add_argument("--pcg-tol", type=float, default=1e-6)
+    ap.add_argument("--pcg-max", type=int, default=100)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-frac", type=float, default=0.05,
+                    help="fraction of points in the oracle's timed sample")
+    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run a 1 GiB device copy first (counter calibration)")
+    ap.add_argument("--verbose", action="store_true")
+    return ap.parse_args()
+
+
+def run_gpu(sc, precision, steps, warmup, args, torch):
+    from paper_2510_13310_amd import BundleAdjuster
+    dev = torch.device("cuda:0")
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    ba = BundleAdjuster(t(sc.cams0, torch.float64), t(sc.intr, torch.float64),
+                        t(sc.points0, torch.float64), precision=precision,
+                        huber_px=sc.huber_px, filter_px=sc.filter_px, img_w=sc.img_w,
+                        img_h=sc.img_h, pcg_rel_tol=args.pcg_tol, pcg_max_iters=args.pcg_max,
+                        timing=1)
+    ba.set_observations(t(sc.cam_idx, torch.int32), t(sc.pt_idx, torch.int32),
+                        t(sc.xy, torch.float32))
+    if sc.use_depth:
+        ba.set_depth_priors(t(sc.depth, torch.float32), t(sc.depth_valid, torch.uint8),
+                            sc.lambda_d)
+    for _ in range(warmup):
+        ba.lm_step()
+    torch.cuda.synchronize()
+    ba.reset_kernel_stats()
+    reps = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        reps.append(ba.lm_step())
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stats = ba.kernel_stats()
+    mem = ba.device_bytes()
+    ba.close()
+    return dict(seconds=dt, reports=reps, stats=stats, device_bytes=mem)
+
+
+def summarize(res, n_obs_total):
+    reps = res["reports"]
+    K = len(reps)
+    its = K / res["seconds"]
+    nh = float(np.mean([r["n_obs_active"] for r in reps]))
+    st = {s["name"]: s for s in res["stats"]}
+    lin_ms = sum(st[k]["total_ms"] for k in LINEARIZE_KERNELS if k in st)
+    lin_launch = max((st[k]["launches"] for k in LINEARIZE_KERNELS if k in st), default=0)
+    jac = (nh * lin_launch) / (lin_ms / 1e3) if lin_ms > 0 else None
+    kern_ms = sum(s["total_ms"] for s in res["stats"])
+    return dict(
+        lm_iters_per_s=its, ms_per_step=1e3 * res["seconds"] / K, obs_per_s=its * nh,
+        jacobian_obs_per_s=jac, n_obs_active=nh, n_obs_total=n_obs_total,
+        pcg_iters_mean=float(np.mean([r["pcg_iters"] for r in reps])),
+        accepted=int(sum(r["accepted"] for r in reps)),
+        relinearized=int(sum(r["relinearized"] for r in reps)),
+        rms_px_first=reps[0]["rms_px"], rms_px_last=reps[-1]["rms_px"],
+        cost_last=reps[-1]["cost_before"], kernel_ms_per_step=kern_ms / K,
+        device_gb=res["device_bytes"] / 1e9,
+        kernels={s["name"]: dict(launches=s["launches"], ms=round(s["total_ms"], 4),
+                                 gbs=(s["total_bytes"] / (s["total_ms"] * 1e6)
+                                      if s["total_ms"] > 0 else None))
+                 for s in res["stats"]},
+    )
+
+
+def roofline(res):
+    """Dominant kernel by total time: algorithmic bytes per launch / mean launch time."""
+    stats = [s for s in res["stats"] if s["launches"] > 0]
+    dom = max(stats, key=lambda s: s["total_ms"])
+    avg_ms = dom["total_ms"] / dom["launches"]
+    bytes_per_launch = dom["total_bytes"] / dom["launches"]
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    return dict(kernel=dom["name"], bound="hbm", achieved=round(achieved, 1),
+                peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
+                traffic=None, avg_launch_us=round(avg_ms * 1e3, 2),
+                bytes_per_launch=int(bytes_per_launch), launches=dom["launches"])
+
+
+def cpu_baseline(sc, frac, steps, n_obs_full):
+    """The FP64 oracle on a random fraction of the points (all cameras), timed per LM step;
+    the rate is rescaled to the full observation count (per-observation work dominates)."""
+    from dataclasses import replace
+    from oracle.lm import Options, State, lm_step
+    from oracle.model import Problem
+    rng = np.random.default_rng(1234)
+    keep = np.sort(rng.choice(sc.n_points, max(1, int(frac * sc.n_points)), replace=False))
+    m = np.zeros(sc.n_points, bool)
+    m[keep] = True
+    ob = m[sc.pt_idx]
+    pmap = np.full(sc.n_points, -1)
+    pmap[keep] = np.arange(keep.size)
+    sub = replace(sc, points_gt=sc.points_gt[keep], points0=sc.points0[keep],
+                  cam_idx=sc.cam_idx[ob], pt_idx=pmap[sc.pt_idx[ob]].astype(np.int32),
+                  xy=sc.xy[ob], depth=sc.depth[ob], depth_valid=sc.depth_valid[ob],
+                  is_outlier=sc.is_outlier[ob])
+    opts = Options(huber_px=sc.huber_px, filter_px=sc.filter_px)
+    prob = Problem.from_scene(sub)
+    st = State.initial(sub.cams0, sub.points0, opts)
+    t0 = time.perf_counter()
+    nobs = []
+    for _ in range(steps):
+        st, rep = lm_step(prob, st, opts)
+        nobs.append(rep.n_obs)
+    dt = time.perf_counter() - t0
+    its_sample = steps / dt
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=round(its_sample * sub.n_obs / n_obs_full, 5), unit="LM iters/s",
+                cores=cores, kind="oracle",
+                sample=(f"{steps} FP64 oracle LM steps on {100 * frac:.0f}% of the points "
+                        f"({sub.n_obs} of {n_obs_full} observations, all cameras), "
+                        f"{dt:.1f} s; rate rescaled by the observation ratio"),
+                sample_iters_per_s=round(its_sample, 4),
+                obs_per_s=round(its_sample * float(np.mean(nobs)), 1))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(multi-GPU point sharding is design-only).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    from paper_2510_13310_amd import _abi
+    if not os.path.exists(_abi.LIB_PATH):
+        from paper_2510_13310_amd.build import build
+        build()
+    from scenes import make_scene
+
+    if args.calib_copy:
+        n = 1 << 28   # 2^28 float32 = 1 GiB read + 1 GiB written
+        a = torch.ones(n, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    t0 = time.perf_counter()
+    sc = make_scene(args.scene)
+    t_gen = time.perf_counter() - t0
+    if args.verbose:
+        print(f"scene {args.scene}: C={sc.n_cams} P={sc.n_points} N={sc.n_obs} "
+              f"({t_gen:.1f} s)", flush=True)
+
+    precs = ["mixed", "fp64"] if args.precision == "both" else [args.precision]
+    out = {}
+    for p in precs:
+        res = run_gpu(sc, p, args.steps, args.warmup, args, torch)
+        out[p] = (res, summarize(res, sc.n_obs))
+        if args.verbose:
+            print(p, json.dumps({k: v for k, v in out[p][1].items() if k != "kernels"}),
+                  flush=True)
+
+    head = precs[0]
+    res, summ = out[head]
+    line = {
+        "metric": METRIC,
+        "value": round(summ["lm_iters_per_s"], 3),
+        "unit": "LM iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(summ["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64 mixed" if head == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": (f"{args.scene}: {sc.n_cams} cameras in random walks, "
+                                f"{sc.n_points} points, {sc.n_obs} observations, 5% outliers, "
+                                "depth priors on 50%, Huber 2 px, 4 px filter"),
+                   "pcg_rel_tol": args.pcg_tol, "pcg_max_iters": args.pcg_max},
+        "obs_per_s": round(summ["obs_per_s"], 1),
+        "jacobian_obs_per_s": (round(summ["jacobian_obs_per_s"], 1)
+                               if summ["jacobian_obs_per_s"] else None),
+        "roofline": roofline(res),
+    }
+    for p in precs:
+        s = out[p][1]
+        line[p] = {k: (round(v, 6) if isinstance(v, float) else v) for k, v in s.items()
+                   if k != "kernels"}
+        line[p]["kernels"] = s["kernels"]
+    if "fp64" in out and "mixed" in out:
+        line["mixed_over_fp64"] = round(out["mixed"][1]["lm_iters_per_s"] /
+                                        out["fp64"][1]["lm_iters_per_s"], 3)
+        line["rms_diff_px"] = abs(out["mixed"][1]["rms_px_last"] - out["fp64"][1]["rms_px_last"])
+    line["cpu_baseline"] = (None if args.no_cpu else
+                            cpu_baseline(sc, args.cpu_frac, args.cpu_steps, sc.n_obs))
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,203 @@
+/*
+ * ba.h -- C ABI of the MI355X (gfx950) Levenberg-Marquardt bundle-adjustment step.
+ *
+ * One LM iteration of the BA stage of InstantSfM (arXiv 2510.13310):
+ *   - residuals of every active observation: reprojection (Eq. (2)) stacked with the
+ *     weighted inverse-depth prior residual (Eqs. (6), (7)) whose reference is the masked
+ *     inverse depth m / d_hat (Eq. (9)); one Huber robustifier on the stacked norm;
+ *   - their SE(3) (6) and point (3) Jacobian blocks, the depth-constrained sparse Jacobian of
+ *     Sec. IV-A, built in one uniform pass;
+ *   - the block-sparse J^T J / J^T r of the LM system (Eq. (3), Marquardt diagonal), reduced
+ *     to the camera Schur complement and solved by PCG with a 6x6 block-Jacobi preconditioner;
+ *   - dynamic parameter extraction (Sec. IV-B, Eqs. (10)-(15)) at the start of every
+ *     iteration, and the scatter of the compact update back into the full arrays.
+ *
+ * Conventions
+ *   cams    C x 7 float64, row-major [qw, qx, qy, qz, cx, cy, cz]: unit quaternion of the
+ *           world-to-camera rotation R and the camera centre c (the paper's {centre,
+ *           quaternion} extrinsics, Sec. III-B). A world point X has camera coordinates
+ *           R (X - c); pixels are (f x/z + cx, f y/z + cy).
+ *   intr    C x 3 float64 [f, cx, cy] in pixels, held fixed.
+ *   points  P x 3 float64.
+ *   The LM update of a camera is the left SE(3) perturbation T <- Exp(xi) T, xi = (rho, phi).
+ *
+ * Pointers: every array argument may be host memory or device memory of the current HIP
+ * device (unified addressing). Inputs are copied into library-owned device buffers before
+ * the call returns; the caller keeps ownership and may free or reuse them afterwards.
+ * Outputs are written to caller-provided buffers of the stated size.
+ *
+ * Errors: no exception crosses the ABI. On an error the context keeps its previous state
+ * and ba_last_error() describes the failure. A context is not thread-safe; distinct
+ * contexts are independent.
+ */
+#ifndef INSTANTBA_BA_H
+#define INSTANTBA_BA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ba_ctx ba_ctx;
+
+typedef int32_t ba_status;
+#define BA_OK 0            /* success */
+#define BA_EMPTY 1         /* no active observation: the step changed nothing */
+#define BA_ERR_ARG (-1)    /* invalid argument (size, index out of range, NULL) */
+#define BA_ERR_STATE (-2)  /* call out of order (e.g. lm_step before set_observations) */
+#define BA_ERR_OOM (-3)    /* device allocation failed */
+#define BA_ERR_DEVICE (-4) /* no usable GPU, or a HIP runtime error */
+#define BA_ERR_NUMERIC (-5)/* non-finite cost at the current parameters */
+
+#define BA_PRECISION_FP64 0  /* every stage in float64 */
+#define BA_PRECISION_MIXED 1 /* float32 Jacobians, J^T J blocks and PCG matvecs; float64
+                                PCG dots and norms, cost, gain ratio, 3x3 inversions */
+
+#define BA_ACTIVITY_ROWS 0    /* point active with >= 3 residual rows, camera with >= 6
+                                 (rows: 2 per observation, +1 with a valid depth prior) */
+#define BA_ACTIVITY_LITERAL 1 /* active with >= 1 valid observation (Eqs. (11)-(12)) */
+
+typedef struct ba_options {
+  int32_t precision;       /* BA_PRECISION_*; default MIXED */
+  int32_t img_w, img_h;    /* frustum for the validity test; default 640 x 480 */
+  int32_t activity_rule;   /* BA_ACTIVITY_*; default ROWS */
+  double min_depth;        /* validity needs camera-frame z > min_depth (Eq. (10)); 0.1 */
+  double huber_px;         /* Huber threshold on the stacked residual norm; <= 0: L2 */
+  double filter_px;        /* validity needs 2-D reprojection error <= filter_px; <= 0 off */
+  double lambda_init;      /* initial LM damping; 1e-3 */
+  double lambda_min, lambda_max; /* damping clamp; 1e-12, 1e12 */
+  double diag_min, diag_max;     /* clamp of the Marquardt diagonal diag(J^T J); 1e-6, 1e32 */
+  double accept_ratio;     /* accept a step when the cost drops and gain ratio > this; 1e-3 */
+  int32_t pcg_max_iters;   /* 100 */
+  int32_t pcg_check_every; /* PCG iterations enqueued between host convergence checks; 4 */
+  double pcg_rel_tol;      /* stop when |r| <= tol |b|; 1e-6 */
+  double cost_rel_tol;     /* ba_solve: stop when an accepted step lowers the cost by at most
+                              this fraction; 1e-10 */
+  double grad_tol;         /* ba_solve: stop when max |g| <= grad_tol; 1e-10 */
+  int32_t max_lm_iters;    /* ba_solve iteration cap; 100 */
+  int32_t timing;          /* 1: time phases and kernels with HIP events (ba_kernel_stats) */
+  void* hip_stream;        /* hipStream_t to run on; NULL: a stream owned by the context */
+} ba_options;
+
+typedef struct ba_step_report {
+  int32_t status;          /* BA_OK or BA_EMPTY */
+  int32_t accepted;        /* 1 if the step was applied */
+  int32_t relinearized;    /* 1 if extraction + linearisation ran (0 after a rejection) */
+  int32_t fixpoint_rounds; /* rounds of the activity fixpoint */
+  int32_t pcg_iters;
+  int32_t pcg_breakdown;   /* 1 if PCG met a non-positive curvature (step rejected) */
+  int32_t n_cams_active, n_points_active;
+  int64_t n_obs_active;
+  double cost_before;      /* F = 1/2 sum rho(|e|^2) over the active observations */
+  double cost_after;       /* F at the candidate (+inf if a depth drops below min_depth) */
+  double model_decrease;   /* -(g.delta + 1/2 sum w |J delta|^2) */
+  double gain_ratio;
+  double lambda;           /* damping used by this step */
+  double pcg_rel_residual; /* |r| / |b| at exit (recursive residual) */
+  double rms_px;           /* sqrt(mean |r_2d|^2) over the active observations, before */
+  double grad_inf;         /* max |g| over the compact parameters, before */
+  double ms_extract, ms_linearize, ms_setup, ms_pcg, ms_candidate, ms_total;
+} ba_step_report;
+
+typedef struct ba_solve_report {
+  int32_t iterations, accepted;
+  int32_t stop_reason;     /* 0 max iters, 1 cost tol, 2 grad tol, 3 lambda max, 4 empty */
+  int64_t total_pcg_iters;
+  double initial_cost, final_cost;
+  double initial_rms_px, final_rms_px;
+  double lambda;
+  double ms_total;
+} ba_solve_report;
+
+typedef struct ba_kernel_stat {
+  char name[32];
+  int64_t launches;        /* launches that did work */
+  double total_ms;         /* sum of HIP-event durations on the context's stream */
+  double total_bytes;      /* algorithmic bytes moved (sizes of the arrays it must read and
+                              write once), summed over launches */
+} ba_kernel_stat;
+
+/* Fill *opt with the defaults listed above. */
+void ba_default_options(ba_options* opt);
+
+/* Create a context on the current HIP device holding the parameters. opt may be NULL
+ * (defaults). n_cams >= 1, n_points >= 1. Returns BA_ERR_DEVICE when no GPU is usable. */
+ba_status ba_create(const ba_options* opt, int32_t n_cams, int32_t n_points,
+                    const double* cams, const double* intr, const double* points,
+                    ba_ctx** out);
+
+/* Set the observation list: observation k sees point pt_idx[k] in camera cam_idx[k] at pixel
+ * (xy[2k], xy[2k+1]) (float32). 0 <= n_obs < 2^31. Indices are range-checked (BA_ERR_ARG).
+ * Resets the LM state (lambda), clears depth priors and invalidates the linearisation. The
+ * library sorts the observations point-major and renumbers points internally; every output
+ * is reported in the caller's order. */
+ba_status ba_set_observations(ba_ctx* ctx, int64_t n_obs, const int32_t* cam_idx,
+                              const int32_t* pt_idx, const float* xy);
+
+/* Metric depth priors d_hat (metres, camera-frame z), one per observation, with optional
+ * validity mask (NULL: all valid). Non-finite or <= 0 depths count as invalid (m = 0).
+ * lambda_d >= 0 weighs the depth row (px * m); 0 disables the depth rows. */
+ba_status ba_set_depth_priors(ba_ctx* ctx, const float* depth, const uint8_t* valid,
+                              double lambda_d);
+
+/* Hold the listed cameras fixed (gauge anchors); they never enter the solve but their
+ * observations constrain points. n = 0 clears the list. */
+ba_status ba_set_fixed_cameras(ba_ctx* ctx, int32_t n, const int32_t* cam_ids);
+
+/* Exactly one LM iteration (extraction, linearisation, Schur-PCG solve, candidate, accept or
+ * reject, scatter). rep may be NULL. Returns BA_EMPTY when nothing is active. */
+ba_status ba_lm_step(ba_ctx* ctx, ba_step_report* rep);
+
+/* Iterate ba_lm_step until max_lm_iters, the cost or gradient tolerance, or lambda_max. */
+ba_status ba_solve(ba_ctx* ctx, ba_solve_report* rep);
+
+/* Copy the current parameters out (cams C x 7, points P x 3; either may be NULL). */
+ba_status ba_get_params(const ba_ctx* ctx, double* cams, double* points);
+
+/* Overwrite the parameters (cams C x 7, points P x 3; either may be NULL), e.g. to warm-start
+ * a re-solve. Resets lambda to lambda_init and invalidates the linearisation. */
+ba_status ba_set_params(ba_ctx* ctx, const double* cams, const double* points);
+
+/* Activity of the last extraction, in the caller's order (any pointer may be NULL):
+ * cams C, points P, obs N bytes, 1 = active. BA_ERR_STATE before the first step. */
+ba_status ba_get_active(const ba_ctx* ctx, uint8_t* cams, uint8_t* points, uint8_t* obs);
+
+/* The last computed LM step in tangent coordinates: cams C x 6 (rho, phi), points P x 3;
+ * zero for inactive or fixed entries. */
+ba_status ba_get_last_step(const ba_ctx* ctx, double* dcams, double* dpoints);
+
+/* Undamped normal-equation blocks of the last linearisation, caller's order, zero for
+ * inactive entries: U C x 36 (J_c^T W J_c, row-major 6x6), gc C x 6 (J_c^T W e),
+ * V P x 9 (J_p^T W J_p), gp P x 3 (J_p^T W e). Any pointer may be NULL. */
+ba_status ba_get_normal_blocks(const ba_ctx* ctx, double* U, double* gc, double* V,
+                               double* gp);
+
+/* Implicit adjoint of the current (converged) solution: given dL/dcams (C x 7) and
+ * dL/dpoints (P x 3), write dL/dxy (N x 2 float32) and dL/ddepth (N float32, zeros without
+ * depth rows). Solves H v = dL/dtheta with H = sum J^T M J, M = rho' I + 2 rho'' e e^T, by
+ * the same Schur-PCG, then maps v per observation. Needs at least one fixed camera and a
+ * fixed scale (depth rows with lambda_d > 0, or two fixed cameras): BA_ERR_STATE otherwise.
+ * Inactive observations get zero gradients. */
+ba_status ba_adjoint(ba_ctx* ctx, const double* grad_cams, const double* grad_points,
+                     float* grad_xy, float* grad_depth);
+
+/* Per-kernel HIP-event statistics accumulated while opt.timing = 1. Writes up to max entries
+ * and returns their count in *n. ba_reset_kernel_stats clears them. */
+ba_status ba_kernel_stats(const ba_ctx* ctx, ba_kernel_stat* out, int32_t max, int32_t* n);
+ba_status ba_reset_kernel_stats(ba_ctx* ctx);
+
+/* Device bytes currently allocated by the context. */
+int64_t ba_device_bytes(const ba_ctx* ctx);
+
+/* Message of the last error on ctx (or of the last failed ba_create when ctx is NULL). */
+const char* ba_last_error(const ba_ctx* ctx);
+
+/* Release every device buffer; NULL is ignored. */
+void ba_destroy(ba_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* INSTANTBA_BA_H */

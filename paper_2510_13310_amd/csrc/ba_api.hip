@@ -1,0 +1,1276 @@
+// Host side of the MI355X LM bundle-adjustment library: the C ABI of include/ba.h, device
+// memory ownership, observation sorting, the extraction fixpoint driver, the LM loop and the
+// PCG driver. Every per-observation step runs in the kernels of ba_kernels.hip.
+#include "ba.h"
+#include "ba_kernels.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+using namespace iba;
+
+namespace {
+
+struct BaError {
+  ba_status code;
+  std::string msg;
+};
+
+thread_local std::string g_create_error;
+
+#define HIP_CHECK(expr)                                                                    \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      throw BaError{BA_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)};     \
+  } while (0)
+
+#define HIP_LAUNCH_CHECK()                                                                 \
+  do {                                                                                     \
+    hipError_t e_ = hipGetLastError();                                                     \
+    if (e_ != hipSuccess)                                                                  \
+      throw BaError{BA_ERR_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e_)}; \
+  } while (0)
+
+// Device allocations of one lifetime group, released together.
+struct Arena {
+  std::vector<void*> ptrs;
+  int64_t bytes = 0;
+  template <typename T>
+  T* alloc(size_t n) {
+    if (n == 0) n = 1;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, n * sizeof(T));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw BaError{BA_ERR_OOM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed"};
+    }
+    ptrs.push_back(p);
+    bytes += int64_t(n * sizeof(T));
+    return static_cast<T*>(p);
+  }
+  void release() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+    bytes = 0;
+  }
+};
+
+struct KStat {
+  std::string name;
+  int64_t launches = 0;
+  double ms = 0.0;
+  double bytes = 0.0;
+};
+
+struct Pending {
+  int kid;
+  hipEvent_t a, b;
+  double bytes;
+  int pcg_iter;   // -1 outside the PCG loop
+};
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+struct ba_ctx {
+  ba_options opt{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int C = 0, P = 0;
+  int64_t N = 0;
+  std::string err;
+
+  Arena par, obs;
+  // parameters: cameras in caller order, points in internal order
+  double *d_cams = nullptr, *d_intr = nullptr, *d_pts = nullptr;
+  uint8_t* d_fixed = nullptr;
+  Cam<double>* d_camd = nullptr;
+  Cam<float>* d_camf = nullptr;
+  Cam<double>* d_cand_tab = nullptr;
+  double* d_cand_cams = nullptr;
+  std::vector<int32_t> pt_user;      // internal -> caller point index
+  std::vector<int32_t> pt_internal;  // caller -> internal
+  std::vector<uint8_t> fixed_h;
+  int n_fixed = 0;
+
+  // observations (point-major, full)
+  bool have_obs = false, have_priors = false;
+  double lam_d = 0.0;
+  int *pm_cam = nullptr, *pm_pt = nullptr, *pm_orig = nullptr, *pt_off = nullptr;
+  int *cm_off = nullptr, *cm_perm = nullptr, *pt_user_d = nullptr;
+  float2* pm_xy = nullptr;
+  float* pm_depth = nullptr;
+  std::vector<int32_t> pm_orig_h;  // point-major position -> caller observation index
+
+  // extraction
+  uint8_t *vrow = nullptr, *act_c = nullptr, *act_p = nullptr;
+  int *rank_c = nullptr, *rank_p = nullptr, *pos_pm = nullptr, *pos_cm = nullptr;
+  int *scan_tmp = nullptr, *flags = nullptr;   // flags[0] changed, flags[1] bad damping
+  int *cam_hat = nullptr, *orig_hat = nullptr, *off_hat = nullptr, *pt_src = nullptr;
+  int *cam_src = nullptr, *slot = nullptr, *cm_off_hat = nullptr, *cm_pt = nullptr,
+      *cm_pm = nullptr;
+  float2* xy_hat = nullptr;
+  float* depth_hat = nullptr;
+  double* Xd = nullptr;
+  float* Xf = nullptr;
+
+  // precision-typed buffers (float in MIXED, double in FP64)
+  void *w = nullptr, *eh = nullptr, *cm_w = nullptr, *cm_eh = nullptr, *V = nullptr,
+       *Vinv = nullptr, *zq = nullptr, *Ustar = nullptr, *pT = nullptr;
+  double *gp = nullptr, *hp = nullptr, *dp = nullptr, *Xcand = nullptr, *rhs_p = nullptr;
+  double *Uraw = nullptr, *gc = nullptr, *b = nullptr, *Minv = nullptr, *rhs_c = nullptr;
+  double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr,
+         *pq_part = nullptr;
+  double *partials = nullptr, *scal = nullptr;
+  double *grad_cams_d = nullptr, *grad_pts_d = nullptr;
+  float *gxy_d = nullptr, *gdepth_d = nullptr;
+  PcgState* pcg = nullptr;
+  double* h_pin = nullptr;   // pinned host readback buffer
+
+  // LM state
+  double lam = 1e-3, nu = 2.0;
+  bool lin_valid = false, ext_valid = false, step_valid = false, blocks_valid = false;
+  int Ca = 0, Pa = 0, rounds = 0;
+  int64_t Nh = 0, Nc = 0;
+
+  // timing
+  std::vector<KStat> stats;
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+
+  ~ba_ctx() {
+    for (auto& pe : pending) {
+      (void)hipEventDestroy(pe.a);
+      (void)hipEventDestroy(pe.b);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+    obs.release();
+    par.release();
+    if (h_pin) (void)hipHostFree(h_pin);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+
+  size_t tsize() const { return opt.precision == BA_PRECISION_FP64 ? 8 : 4; }
+  int need_pt() const { return opt.activity_rule == BA_ACTIVITY_LITERAL ? 1 : 3; }
+  int need_cam() const { return opt.activity_rule == BA_ACTIVITY_LITERAL ? 1 : 6; }
+
+  Model model() const {
+    Model m;
+    m.lam_d = have_priors ? lam_d : 0.0;
+    m.huber = opt.huber_px;
+    m.min_depth = opt.min_depth;
+    m.filter_px = opt.filter_px;
+    m.img_w = opt.img_w;
+    m.img_h = opt.img_h;
+    return m;
+  }
+
+  // ---------------------------------------------------------------- timing helpers
+  int kid(const char* name) {
+    for (size_t i = 0; i < stats.size(); ++i)
+      if (stats[i].name == name) return int(i);
+    stats.push_back(KStat{name});
+    return int(stats.size() - 1);
+  }
+  hipEvent_t get_event() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    HIP_CHECK(hipEventCreate(&e));
+    return e;
+  }
+  template <class F>
+  void timed(const char* name, double bytes, int pcg_iter, F&& launch) {
+    if (!opt.timing) {
+      launch();
+      HIP_LAUNCH_CHECK();
+      return;
+    }
+    Pending pe{kid(name), get_event(), get_event(), bytes, pcg_iter};
+    HIP_CHECK(hipEventRecord(pe.a, stream));
+    launch();
+    HIP_LAUNCH_CHECK();
+    HIP_CHECK(hipEventRecord(pe.b, stream));
+    pending.push_back(pe);
+  }
+  // After a stream sync: fold event pairs into the statistics. PCG launches beyond the
+  // iteration that converged only test the done flag and are not counted.
+  void flush_timing(int pcg_iters_done) {
+    for (auto& pe : pending) {
+      if (pe.pcg_iter < 0 || pe.pcg_iter < pcg_iters_done) {
+        float ms = 0.f;
+        HIP_CHECK(hipEventElapsedTime(&ms, pe.a, pe.b));
+        KStat& s = stats[pe.kid];
+        s.launches += 1;
+        s.ms += ms;
+        s.bytes += pe.bytes;
+      }
+      pool.push_back(pe.a);
+      pool.push_back(pe.b);
+    }
+    pending.clear();
+  }
+
+  void sync() { HIP_CHECK(hipStreamSynchronize(stream)); }
+  void to_device(void* dst, const void* src, size_t bytes) {
+    if (bytes == 0) return;
+    HIP_CHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDefault, stream));
+  }
+};
+
+namespace {
+
+// Copy caller memory (host or device) into a host vector.
+template <typename T>
+void fetch(ba_ctx& c, std::vector<T>& dst, const T* src, size_t n) {
+  dst.resize(n);
+  if (n == 0) return;
+  HIP_CHECK(hipMemcpyAsync(dst.data(), src, n * sizeof(T), hipMemcpyDefault, c.stream));
+  c.sync();
+}
+
+template <typename T>
+void store(ba_ctx& c, T* dst, const T* src_host, size_t n) {
+  if (n == 0) return;
+  HIP_CHECK(hipMemcpyAsync(dst, src_host, n * sizeof(T), hipMemcpyDefault, c.stream));
+  c.sync();
+}
+
+template <typename T>
+void download(ba_ctx& c, std::vector<T>& dst, const T* dev, size_t n) {
+  dst.resize(n);
+  if (n == 0) return;
+  HIP_CHECK(hipMemcpyAsync(dst.data(), dev, n * sizeof(T), hipMemcpyDeviceToHost, c.stream));
+  c.sync();
+}
+
+ba_status fail(ba_ctx* c, ba_status code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+template <class F>
+ba_status guarded(ba_ctx* c, F&& f) {
+  if (!c) return BA_ERR_ARG;
+  try {
+    return f();
+  } catch (const BaError& e) {
+    c->err = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    c->err = "host allocation failed";
+    return BA_ERR_OOM;
+  } catch (const std::exception& e) {
+    c->err = e.what();
+    return BA_ERR_DEVICE;
+  }
+}
+
+// ------------------------------------------------------------------ buffers
+void alloc_obs_buffers(ba_ctx& c) {
+  c.obs.release();
+  Arena& A = c.obs;
+  const int64_t N = c.N;
+  const int C = c.C, P = c.P;
+  const size_t ts = c.tsize();
+  c.pm_cam = A.alloc<int>(N);
+  c.pm_pt = A.alloc<int>(N);
+  c.pm_orig = A.alloc<int>(N);
+  c.pm_xy = A.alloc<float2>(N);
+  c.pm_depth = A.alloc<float>(N);
+  c.pt_off = A.alloc<int>(P + 1);
+  c.cm_off = A.alloc<int>(C + 1);
+  c.cm_perm = A.alloc<int>(N);
+  c.pt_user_d = A.alloc<int>(P);
+  c.vrow = A.alloc<uint8_t>(N);
+  c.act_c = A.alloc<uint8_t>(C);
+  c.act_p = A.alloc<uint8_t>(P);
+  c.rank_c = A.alloc<int>(C + 1);
+  c.rank_p = A.alloc<int>(P + 1);
+  c.pos_pm = A.alloc<int>(N + 1);
+  c.pos_cm = A.alloc<int>(N + 1);
+  c.scan_tmp = A.alloc<int>(scan_tmp_ints(std::max<int64_t>({N, int64_t(P), int64_t(C)})));
+  c.flags = A.alloc<int>(4);
+  c.cam_hat = A.alloc<int>(N);
+  c.orig_hat = A.alloc<int>(N);
+  c.xy_hat = A.alloc<float2>(N);
+  c.depth_hat = A.alloc<float>(N);
+  c.off_hat = A.alloc<int>(P + 1);
+  c.pt_src = A.alloc<int>(P);
+  c.cam_src = A.alloc<int>(C);
+  c.slot = A.alloc<int>(C);
+  c.cm_off_hat = A.alloc<int>(C + 1);
+  c.cm_pt = A.alloc<int>(N);
+  c.cm_pm = A.alloc<int>(N);
+  c.Xd = A.alloc<double>(3 * size_t(P));
+  c.Xf = A.alloc<float>(3 * size_t(P));
+  c.w = A.alloc<char>(ts * N);
+  c.cm_w = A.alloc<char>(ts * N);
+  c.eh = nullptr;
+  c.cm_eh = nullptr;
+  c.V = A.alloc<char>(ts * 6 * P);
+  c.Vinv = A.alloc<char>(ts * 6 * P);
+  c.zq = A.alloc<char>(ts * 3 * P);
+  c.Ustar = A.alloc<char>(ts * 21 * C);
+  c.pT = A.alloc<char>(ts * 6 * C);
+  c.gp = A.alloc<double>(3 * size_t(P));
+  c.hp = A.alloc<double>(3 * size_t(P));
+  c.dp = A.alloc<double>(3 * size_t(P));
+  c.Xcand = A.alloc<double>(3 * size_t(P));
+  c.rhs_p = A.alloc<double>(3 * size_t(P));
+  c.Uraw = A.alloc<double>(21 * size_t(C));
+  c.gc = A.alloc<double>(6 * size_t(C));
+  c.b = A.alloc<double>(6 * size_t(C));
+  c.Minv = A.alloc<double>(21 * size_t(C));
+  c.rhs_c = A.alloc<double>(6 * size_t(C));
+  c.x = A.alloc<double>(6 * size_t(C));
+  c.r = A.alloc<double>(6 * size_t(C));
+  c.z = A.alloc<double>(6 * size_t(C));
+  c.p = A.alloc<double>(6 * size_t(C));
+  c.q = A.alloc<double>(6 * size_t(C));
+  c.pq_part = A.alloc<double>(size_t(C));
+  c.partials = A.alloc<double>(4 * (size_t(P) / kBlock + 2));
+  c.scal = A.alloc<double>(16);
+  c.pcg = A.alloc<PcgState>(1);
+  c.grad_cams_d = nullptr;
+  c.grad_pts_d = nullptr;
+  c.gxy_d = nullptr;
+  c.gdepth_d = nullptr;
+}
+
+void ensure_adjoint_buffers(ba_ctx& c) {
+  if (c.eh) return;
+  const size_t ts = c.tsize();
+  c.eh = c.obs.alloc<char>(ts * 3 * size_t(c.N));
+  c.cm_eh = c.obs.alloc<char>(ts * 3 * size_t(c.N));
+  c.grad_cams_d = c.obs.alloc<double>(7 * size_t(c.C));
+  c.grad_pts_d = c.obs.alloc<double>(3 * size_t(c.P));
+  c.gxy_d = c.obs.alloc<float>(2 * size_t(c.N));
+  c.gdepth_d = c.obs.alloc<float>(size_t(c.N));
+}
+
+template <typename T>
+Compact<T> compact_view(ba_ctx& c) {
+  Compact<T> cp;
+  cp.Pa = c.Pa;
+  cp.Ca = c.Ca;
+  cp.off = c.off_hat;
+  cp.cam = c.cam_hat;
+  cp.xy = c.xy_hat;
+  cp.depth = c.depth_hat;
+  cp.slot = c.slot;
+  cp.cam_src = c.cam_src;
+  cp.cm_off = c.cm_off_hat;
+  cp.cm_pt = c.cm_pt;
+  cp.cm_pm = c.cm_pm;
+  cp.Xd = c.Xd;
+  cp.camd = c.d_camd;
+  if constexpr (sizeof(T) == 8) {
+    cp.Xt = reinterpret_cast<const T*>(c.Xd);
+    cp.camt = reinterpret_cast<const Cam<T>*>(c.d_camd);
+  } else {
+    cp.Xt = reinterpret_cast<const T*>(c.Xf);
+    cp.camt = reinterpret_cast<const Cam<T>*>(c.d_camf);
+  }
+  return cp;
+}
+
+template <typename T>
+ObsMetric<T> metric_view(ba_ctx& c) {
+  ObsMetric<T> om;
+  om.w = static_cast<T*>(c.w);
+  om.cm_w = static_cast<T*>(c.cm_w);
+  om.eh = static_cast<T*>(c.eh);
+  om.cm_eh = static_cast<T*>(c.cm_eh);
+  return om;
+}
+
+// ------------------------------------------------------------------ extraction
+// Validity, activity fixpoint, ranks and compaction at the current parameters.
+void extract(ba_ctx& c) {
+  const Model m = c.model();
+  hipStream_t s = c.stream;
+  const int64_t N = c.N;
+  c.timed("cam_table", double(c.C) * (56 + 24 + 120 + 60), -1,
+          [&] { launch_cam_table(s, c.C, c.d_cams, c.d_intr, c.d_camd, c.d_camf); });
+  c.timed("validate", double(N) * (4 + 4 + 8 + 4 + 24 + 1), -1, [&] {
+    launch_validate(s, N, m, c.pm_cam, c.pm_pt, c.pm_xy, c.pm_depth, c.d_pts, c.d_camd,
+                    c.vrow);
+  });
+  int rounds = 0;
+  while (true) {
+    ++rounds;
+    HIP_CHECK(hipMemsetAsync(c.flags, 0, sizeof(int), s));
+    c.timed("cam_rows", double(N) * 5, -1, [&] {
+      launch_cam_rows(s, c.C, c.cm_off, c.cm_perm, c.vrow, c.d_fixed, c.need_cam(), c.act_c);
+    });
+    c.timed("point_rows_prune", double(N) * 5 + double(c.P) * 5, -1, [&] {
+      launch_point_rows_prune(s, c.P, c.pt_off, c.pm_cam, c.act_c, c.d_fixed, c.need_pt(),
+                              c.vrow, c.act_p, c.flags);
+    });
+    HIP_CHECK(hipMemcpyAsync(c.h_pin, c.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    c.sync();
+    int changed = 0;
+    std::memcpy(&changed, c.h_pin, sizeof(int));
+    if (!changed) break;
+    if (rounds > 1000000) throw BaError{BA_ERR_DEVICE, "activity fixpoint did not settle"};
+  }
+  c.rounds = rounds;
+  c.timed("scan", double(c.C) * 5 + double(c.P) * 5 + double(N) * 14, -1, [&] {
+    launch_scan_u8(s, c.C, c.act_c, c.rank_c, c.scan_tmp);
+    launch_scan_u8(s, c.P, c.act_p, c.rank_p, c.scan_tmp);
+    launch_scan_u8(s, N, c.vrow, c.pos_pm, c.scan_tmp);
+    launch_scan_cm(s, N, c.cm_perm, c.vrow, c.pm_cam, c.d_fixed, c.pos_cm, c.scan_tmp);
+  });
+  int* hp = reinterpret_cast<int*>(c.h_pin);
+  HIP_CHECK(hipMemcpyAsync(hp + 0, c.rank_c + c.C, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(hp + 1, c.rank_p + c.P, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(hp + 2, c.pos_pm + N, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(hp + 3, c.pos_cm + N, sizeof(int), hipMemcpyDeviceToHost, s));
+  c.sync();
+  c.Ca = hp[0];
+  c.Pa = hp[1];
+  c.Nh = hp[2];
+  c.Nc = hp[3];
+  c.timed("compact", double(N) * 40 + double(c.P) * 60, -1, [&] {
+    launch_compact_points(s, c.P, c.act_p, c.rank_p, c.pt_off, c.pos_pm, c.d_pts, c.pt_src,
+                          c.off_hat, c.Xd, c.Xf);
+    launch_compact_obs(s, N, c.vrow, c.pos_pm, c.pm_cam, c.pm_xy, c.pm_depth, c.pm_orig,
+                       c.cam_hat, c.xy_hat, c.depth_hat, c.orig_hat);
+    launch_compact_cams(s, c.C, c.act_c, c.rank_c, c.cm_off, c.pos_cm, c.slot, c.cam_src,
+                        c.cm_off_hat);
+    launch_compact_cm(s, N, c.cm_perm, c.vrow, c.pm_cam, c.pm_pt, c.d_fixed, c.pos_cm,
+                      c.pos_pm, c.rank_p, c.cm_pt, c.cm_pm);
+  });
+  c.ext_valid = true;
+}
+
+// Algorithmic bytes of the two PCG passes (unique data each must touch once).
+double bytes_schur_point(const ba_ctx& c) {
+  const double ts = double(c.tsize());
+  return double(c.Nh) * (4 + ts) + double(c.Pa) * (4 + 12 * ts) +
+         double(c.C) * (4 + 15 * ts) + double(c.Ca) * 6 * ts;
+}
+double bytes_schur_cam(const ba_ctx& c) {
+  const double ts = double(c.tsize());
+  return double(c.Nc) * (4 + ts) + double(c.Pa) * 6 * ts +
+         double(c.Ca) * (4 + 4 + 21 * ts + 6 * ts + 6 * 8 + 6 * 8 + 8 + 15 * ts);
+}
+
+template <typename T>
+void linearize(ba_ctx& c, bool adj) {
+  hipStream_t s = c.stream;
+  const Model m = c.model();
+  Compact<T> cp = compact_view<T>(c);
+  ObsMetric<T> om = metric_view<T>(c);
+  const double ts = double(sizeof(T));
+  c.timed("lin_point", double(c.Nh) * (4 + 8 + 4 + ts + (adj ? 3 * ts : 0)) +
+                           double(c.Pa) * (4 + 24 + 6 * ts + 24) + double(c.C) * 120,
+          -1, [&] {
+            launch_lin_point<T>(s, adj, m, cp, om, static_cast<T*>(c.V), c.gp, c.partials);
+          });
+  const int nb = int((c.Pa + kBlock - 1) / kBlock);
+  launch_reduce_partials(s, nb, 3, c.partials, 0x4u, 0, nullptr, nullptr, c.scal);
+  HIP_LAUNCH_CHECK();
+  c.timed("gather_cm_metric", double(c.Nc) * (4 + 2 * ts + (adj ? 6 * ts : 0)), -1,
+          [&] { launch_gather_cm_metric<T>(s, adj, c.Nc, c.cm_pm, om); });
+}
+
+// Damping-dependent setup: point inverses, camera blocks, Schur RHS, preconditioner.
+template <typename T>
+void setup_system(ba_ctx& c, bool adj, double lam, const double* rhs_c, const double* rhs_p) {
+  hipStream_t s = c.stream;
+  const Model m = c.model();
+  Compact<T> cp = compact_view<T>(c);
+  ObsMetric<T> om = metric_view<T>(c);
+  const double ts = double(sizeof(T));
+  HIP_CHECK(hipMemsetAsync(c.flags + 1, 0, sizeof(int), s));
+  c.timed("point_damp", double(c.Pa) * (6 * ts + 24 + 6 * ts + 24), -1, [&] {
+    launch_point_damp<T>(s, c.Pa, lam, c.opt.diag_min, c.opt.diag_max,
+                         static_cast<const T*>(c.V), c.gp, rhs_p, static_cast<T*>(c.Vinv), c.hp,
+                         c.flags + 1);
+  });
+  c.timed("cam_assemble",
+          double(c.Nc) * (8 + ts + 12 + (adj ? 3 * ts : 0)) + double(c.Pa) * (24 + 6 * ts + 24) +
+              double(c.Ca) * (21 * 8 + 21 * ts + 6 * 8 * 2 + 21 * 8),
+          -1, [&] {
+            launch_cam_assemble<T>(s, adj, m, cp, om, lam, c.opt.diag_min, c.opt.diag_max,
+                                   static_cast<const T*>(c.Vinv), c.hp, rhs_c, c.Uraw,
+                                   static_cast<T*>(c.Ustar), c.gc, c.b, c.Minv);
+          });
+}
+
+// PCG on the camera Schur complement; returns the iteration count. The loop enqueues
+// pcg_check_every iterations between host reads of the device-side state; iterations after
+// convergence return at their first instruction.
+template <typename T>
+int run_pcg(ba_ctx& c, bool adj, double rel_tol, int max_iters, PcgState* out_state) {
+  hipStream_t s = c.stream;
+  const Model m = c.model();
+  Compact<T> cp = compact_view<T>(c);
+  ObsMetric<T> om = metric_view<T>(c);
+  PcgState st{};
+  if (c.Ca == 0) {
+    *out_state = st;
+    out_state->done = 1;
+    return 0;
+  }
+  launch_pcg_init<T>(s, c.Ca, c.b, c.Minv, c.x, c.r, c.z, c.p, static_cast<T*>(c.pT), c.pcg,
+                     rel_tol * rel_tol, max_iters);
+  HIP_LAUNCH_CHECK();
+  const int every = std::max(1, c.opt.pcg_check_every);
+  const double bp = bytes_schur_point(c), bc = bytes_schur_cam(c);
+  int it = 0;
+  while (true) {
+    for (int k = 0; k < every && it < max_iters; ++k, ++it) {
+      c.timed("schur_point", bp, it, [&] {
+        launch_schur_point<T>(s, adj, m, cp, om, static_cast<const T*>(c.Vinv),
+                              static_cast<const T*>(c.pT), static_cast<T*>(c.zq), c.pcg);
+      });
+      c.timed("schur_cam", bc, it, [&] {
+        launch_schur_cam<T>(s, adj, m, cp, om, static_cast<const T*>(c.Ustar),
+                            static_cast<const T*>(c.pT), c.p, static_cast<const T*>(c.zq), c.q,
+                            c.pq_part, c.pcg);
+      });
+      c.timed("pcg_update", double(c.Ca) * (21 * 8 + 6 * 8 * 8 + 8 + 6 * double(sizeof(T))), it,
+              [&] {
+                launch_pcg_update<T>(s, c.Ca, c.Minv, c.q, c.pq_part, c.x, c.r, c.z, c.p,
+                                     static_cast<T*>(c.pT), c.pcg);
+              });
+    }
+    HIP_CHECK(hipMemcpyAsync(c.h_pin, c.pcg, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+    c.sync();
+    std::memcpy(&st, c.h_pin, sizeof(PcgState));
+    if (st.done || it >= max_iters) break;
+  }
+  *out_state = st;
+  return st.iter;
+}
+
+template <typename T>
+void backsub(ba_ctx& c, bool adj, const double* rhs_p) {
+  hipStream_t s = c.stream;
+  const Model m = c.model();
+  Compact<T> cp = compact_view<T>(c);
+  ObsMetric<T> om = metric_view<T>(c);
+  c.timed("backsub", bytes_schur_point(c) + double(c.Pa) * 48, -1, [&] {
+    launch_backsub<T>(s, adj, m, cp, om, static_cast<const T*>(c.Vinv), c.x, c.gp, rhs_p,
+                      c.dp);
+  });
+}
+
+template <typename T>
+ba_status lm_step_impl(ba_ctx& c, ba_step_report* rep) {
+  const double t0 = now_ms();
+  ba_step_report R;
+  std::memset(&R, 0, sizeof(R));
+  R.lambda = c.lam;
+  hipStream_t s = c.stream;
+  const Model m = c.model();
+  const double ts = double(sizeof(T));
+  double t_ext = 0, t_lin = 0, t_setup = 0, t_pcg = 0, t_cand = 0;
+
+  if (!c.lin_valid) {
+    double ta = now_ms();
+    extract(c);
+    t_ext = now_ms() - ta;
+    R.relinearized = 1;
+    if (c.Nh == 0) {
+      c.flush_timing(0);
+      R.status = BA_EMPTY;
+      R.fixpoint_rounds = c.rounds;
+      R.ms_extract = t_ext;
+      R.ms_total = now_ms() - t0;
+      c.step_valid = false;
+      c.blocks_valid = false;
+      if (rep) *rep = R;
+      return BA_EMPTY;
+    }
+    ta = now_ms();
+    linearize<T>(c, false);
+    c.sync();
+    t_lin = now_ms() - ta;
+    c.lin_valid = true;
+  }
+  R.fixpoint_rounds = c.rounds;
+  R.n_cams_active = c.Ca;
+  R.n_points_active = c.Pa;
+  R.n_obs_active = c.Nh;
+
+  double ta = now_ms();
+  setup_system<T>(c, false, c.lam, nullptr, nullptr);
+  c.sync();
+  t_setup = now_ms() - ta;
+  c.blocks_valid = true;
+
+  ta = now_ms();
+  PcgState st{};
+  const int iters = run_pcg<T>(c, false, c.opt.pcg_rel_tol, c.opt.pcg_max_iters, &st);
+  t_pcg = now_ms() - ta;
+  R.pcg_iters = iters;
+  R.pcg_breakdown = st.breakdown;
+  R.pcg_rel_residual = st.bb > 0 ? std::sqrt(std::max(0.0, st.rr) / st.bb) : 0.0;
+
+  ta = now_ms();
+  backsub<T>(c, false, nullptr);
+  c.timed("cam_candidate", double(c.C) * (56 + 120 + 56 + 120) + double(c.Ca) * 48, -1, [&] {
+    launch_cam_candidate(s, c.C, c.slot, c.x, c.d_cams, c.d_intr, c.d_camd, c.d_cand_cams,
+                         c.d_cand_tab);
+  });
+  Compact<T> cp = compact_view<T>(c);
+  c.timed("point_candidate",
+          double(c.Nh) * (4 + 8 + 4 + ts) + double(c.Pa) * (4 + 24 * 4) + double(c.C) * 240, -1,
+          [&] {
+            launch_point_candidate<T>(s, m, cp, c.d_cand_tab, c.x, c.dp, c.gp,
+                                      static_cast<const T*>(c.w), c.Xcand, c.partials);
+          });
+  const int nb = int((c.Pa + kBlock - 1) / kBlock);
+  launch_reduce_partials(s, nb, 4, c.partials, 0x0u, c.Ca, c.gc, c.x, c.scal + 4);
+  HIP_LAUNCH_CHECK();
+  HIP_CHECK(hipMemcpyAsync(c.h_pin, c.scal, 10 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(c.h_pin + 10, c.flags + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+  c.sync();
+  double sc[10];
+  std::memcpy(sc, c.h_pin, sizeof(sc));
+  int damp_bad = 0;
+  std::memcpy(&damp_bad, c.h_pin + 10, sizeof(int));
+  const double F = sc[0];
+  R.cost_before = F;
+  R.rms_px = std::sqrt(sc[1] / double(c.Nh));
+  const double Fc = sc[7] > 0 ? std::numeric_limits<double>::infinity() : sc[4];
+  R.cost_after = Fc;
+  const double model = -(sc[6] + sc[8] + 0.5 * sc[5]);
+  R.model_decrease = model;
+  // max |g| over the compact parameters: points from the linearisation partials, cameras
+  // from gc (downloaded: 6 Ca values)
+  {
+    std::vector<double> g;
+    download(c, g, c.gc, size_t(6) * c.Ca);
+    double gm = sc[2];
+    for (double v : g) gm = std::max(gm, std::fabs(v));
+    R.grad_inf = gm;
+  }
+  if (!std::isfinite(F)) {
+    c.flush_timing(iters);
+    R.ms_total = now_ms() - t0;
+    if (rep) *rep = R;
+    throw BaError{BA_ERR_NUMERIC, "non-finite cost at the current parameters"};
+  }
+  const bool finite_c = std::isfinite(Fc);
+  const double ratio = (model > 0 && finite_c) ? (F - Fc) / model
+                                               : -std::numeric_limits<double>::infinity();
+  R.gain_ratio = ratio;
+  const bool ok = finite_c && Fc < F && ratio > c.opt.accept_ratio && !st.breakdown && !damp_bad;
+  R.accepted = ok ? 1 : 0;
+  c.step_valid = true;
+  if (ok) {
+    c.timed("scatter", double(c.Pa) * 52 + double(c.C) * 60, -1, [&] {
+      launch_scatter(s, c.Pa, c.C, c.pt_src, c.Xcand, c.slot, c.d_cand_cams, c.d_pts, c.d_cams);
+    });
+    c.lin_valid = false;
+    const double f = std::max(1.0 / 3.0, 1.0 - std::pow(2.0 * ratio - 1.0, 3));
+    c.lam = std::max(c.opt.lambda_min, std::min(c.opt.lambda_max, c.lam * f));
+    c.nu = 2.0;
+  } else {
+    c.lam = std::min(c.lam * c.nu, c.opt.lambda_max);
+    c.nu *= 2.0;
+  }
+  c.sync();
+  t_cand = now_ms() - ta;
+  c.flush_timing(iters);
+  R.ms_extract = t_ext;
+  R.ms_linearize = t_lin;
+  R.ms_setup = t_setup;
+  R.ms_pcg = t_pcg;
+  R.ms_candidate = t_cand;
+  R.ms_total = now_ms() - t0;
+  if (rep) *rep = R;
+  return BA_OK;
+}
+
+ba_status lm_step_dispatch(ba_ctx& c, ba_step_report* rep) {
+  if (!c.have_obs) throw BaError{BA_ERR_STATE, "ba_set_observations has not been called"};
+  return c.opt.precision == BA_PRECISION_FP64 ? lm_step_impl<double>(c, rep)
+                                              : lm_step_impl<float>(c, rep);
+}
+
+template <typename T>
+void adjoint_impl(ba_ctx& c, const double* grad_cams, const double* grad_points, float* gxy,
+                  float* gdepth) {
+  hipStream_t s = c.stream;
+  ensure_adjoint_buffers(c);
+  c.to_device(c.grad_cams_d, grad_cams, sizeof(double) * 7 * size_t(c.C));
+  c.to_device(c.grad_pts_d, grad_points, sizeof(double) * 3 * size_t(c.P));
+  HIP_CHECK(hipMemsetAsync(c.gxy_d, 0, sizeof(float) * 2 * size_t(c.N), s));
+  HIP_CHECK(hipMemsetAsync(c.gdepth_d, 0, sizeof(float) * size_t(c.N), s));
+  extract(c);
+  c.lin_valid = false;   // the LM linearisation buffers are reused below
+  c.blocks_valid = false;
+  c.step_valid = false;
+  if (c.Nh > 0) {
+    linearize<T>(c, true);
+    launch_adjoint_rhs(s, c.Ca, c.Pa, c.cam_src, c.d_cams, c.grad_cams_d, c.pt_src, c.pt_user_d,
+                       c.grad_pts_d, c.rhs_c, c.rhs_p);
+    HIP_LAUNCH_CHECK();
+    setup_system<T>(c, true, 0.0, c.rhs_c, c.rhs_p);
+    PcgState st{};
+    const double tol = std::min(c.opt.pcg_rel_tol, 1e-10);
+    const int maxit = std::max(c.opt.pcg_max_iters, 6 * c.Ca + 10);
+    run_pcg<T>(c, true, tol, maxit, &st);
+    backsub<T>(c, true, c.rhs_p);
+    Compact<T> cp = compact_view<T>(c);
+    launch_adjoint_obs<T>(s, c.model(), cp, metric_view<T>(c), c.x, c.dp, c.orig_hat, c.gxy_d,
+                          c.gdepth_d);
+    HIP_LAUNCH_CHECK();
+    int bad = 0;
+    HIP_CHECK(hipMemcpyAsync(c.h_pin, c.flags + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    c.sync();
+    std::memcpy(&bad, c.h_pin, sizeof(int));
+    c.flush_timing(st.iter);
+    if (bad) throw BaError{BA_ERR_NUMERIC, "singular point block in the adjoint system"};
+    if (st.breakdown) throw BaError{BA_ERR_NUMERIC, "adjoint PCG broke down"};
+  }
+  c.sync();
+  HIP_CHECK(hipMemcpyAsync(gxy, c.gxy_d, sizeof(float) * 2 * size_t(c.N), hipMemcpyDefault, s));
+  if (gdepth)
+    HIP_CHECK(hipMemcpyAsync(gdepth, c.gdepth_d, sizeof(float) * size_t(c.N), hipMemcpyDefault,
+                             s));
+  c.sync();
+}
+
+// Counting sort by an integer key in [0, K): stable.
+void counting_order(const std::vector<int32_t>& key, int K, std::vector<int32_t>& order,
+                    std::vector<int32_t>& offsets) {
+  offsets.assign(size_t(K) + 1, 0);
+  for (int32_t k : key) offsets[size_t(k) + 1]++;
+  for (int i = 0; i < K; ++i) offsets[i + 1] += offsets[i];
+  std::vector<int32_t> next(offsets.begin(), offsets.end() - 1);
+  order.resize(key.size());
+  for (size_t i = 0; i < key.size(); ++i) order[next[key[i]]++] = int32_t(i);
+}
+
+void points_user_to_internal(ba_ctx& c, const std::vector<double>& user,
+                             std::vector<double>& internal) {
+  internal.resize(user.size());
+  for (int i = 0; i < c.P; ++i)
+    for (int k = 0; k < 3; ++k) internal[3 * size_t(i) + k] = user[3 * size_t(c.pt_user[i]) + k];
+}
+
+void points_internal_to_user(ba_ctx& c, const std::vector<double>& internal,
+                             std::vector<double>& user) {
+  user.resize(internal.size());
+  for (int i = 0; i < c.P; ++i)
+    for (int k = 0; k < 3; ++k) user[3 * size_t(c.pt_user[i]) + k] = internal[3 * size_t(i) + k];
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+extern "C" {
+
+void ba_default_options(ba_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = BA_PRECISION_MIXED;
+  o->img_w = 640;
+  o->img_h = 480;
+  o->activity_rule = BA_ACTIVITY_ROWS;
+  o->min_depth = 0.1;
+  o->huber_px = 0.0;
+  o->filter_px = 0.0;
+  o->lambda_init = 1e-3;
+  o->lambda_min = 1e-12;
+  o->lambda_max = 1e12;
+  o->diag_min = 1e-6;
+  o->diag_max = 1e32;
+  o->accept_ratio = 1e-3;
+  o->pcg_max_iters = 100;
+  o->pcg_check_every = 4;
+  o->pcg_rel_tol = 1e-6;
+  o->cost_rel_tol = 1e-10;
+  o->grad_tol = 1e-10;
+  o->max_lm_iters = 100;
+  o->timing = 0;
+  o->hip_stream = nullptr;
+}
+
+ba_status ba_create(const ba_options* opt, int32_t n_cams, int32_t n_points, const double* cams,
+                    const double* intr, const double* points, ba_ctx** out) {
+  g_create_error.clear();
+  if (!out) {
+    g_create_error = "out is NULL";
+    return BA_ERR_ARG;
+  }
+  *out = nullptr;
+  ba_options o;
+  if (opt)
+    o = *opt;
+  else
+    ba_default_options(&o);
+  if (n_cams < 1 || n_points < 1 || !cams || !intr || !points) {
+    g_create_error = "need n_cams >= 1, n_points >= 1 and non-NULL cams, intr, points";
+    return BA_ERR_ARG;
+  }
+  if ((o.precision != BA_PRECISION_FP64 && o.precision != BA_PRECISION_MIXED) ||
+      (o.activity_rule != BA_ACTIVITY_ROWS && o.activity_rule != BA_ACTIVITY_LITERAL) ||
+      o.img_w <= 0 || o.img_h <= 0 || !(o.lambda_min > 0) || !(o.lambda_max >= o.lambda_min) ||
+      !(o.lambda_init > 0) || o.pcg_max_iters < 0 || !(o.pcg_rel_tol >= 0) ||
+      !(o.diag_min > 0) || !(o.diag_max >= o.diag_min)) {
+    g_create_error = "invalid options";
+    return BA_ERR_ARG;
+  }
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev == 0) {
+    (void)hipGetLastError();
+    g_create_error = "no HIP device available";
+    return BA_ERR_DEVICE;
+  }
+  ba_ctx* c = new (std::nothrow) ba_ctx();
+  if (!c) {
+    g_create_error = "host allocation failed";
+    return BA_ERR_OOM;
+  }
+  c->opt = o;
+  c->C = n_cams;
+  c->P = n_points;
+  c->lam = o.lambda_init;
+  try {
+    if (o.hip_stream) {
+      c->stream = static_cast<hipStream_t>(o.hip_stream);
+    } else {
+      HIP_CHECK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+      c->own_stream = true;
+    }
+    HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&c->h_pin), 64 * sizeof(double)));
+    Arena& A = c->par;
+    c->d_cams = A.alloc<double>(7 * size_t(n_cams));
+    c->d_intr = A.alloc<double>(3 * size_t(n_cams));
+    c->d_pts = A.alloc<double>(3 * size_t(n_points));
+    c->d_fixed = A.alloc<uint8_t>(n_cams);
+    c->d_camd = A.alloc<Cam<double>>(n_cams);
+    c->d_camf = A.alloc<Cam<float>>(n_cams);
+    c->d_cand_tab = A.alloc<Cam<double>>(n_cams);
+    c->d_cand_cams = A.alloc<double>(7 * size_t(n_cams));
+    std::vector<double> hc, hi, hpnt;
+    fetch(*c, hc, cams, 7 * size_t(n_cams));
+    fetch(*c, hi, intr, 3 * size_t(n_cams));
+    fetch(*c, hpnt, points, 3 * size_t(n_points));
+    for (double v : hc)
+      if (!std::isfinite(v)) throw BaError{BA_ERR_ARG, "non-finite camera parameter"};
+    for (double v : hpnt)
+      if (!std::isfinite(v)) throw BaError{BA_ERR_ARG, "non-finite point"};
+    for (int i = 0; i < n_cams; ++i) {
+      const double* q = &hc[7 * size_t(i)];
+      if (!(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3] > 0))
+        throw BaError{BA_ERR_ARG, "zero quaternion"};
+      if (!(hi[3 * size_t(i)] > 0)) throw BaError{BA_ERR_ARG, "focal length must be > 0"};
+    }
+    c->pt_user.resize(n_points);
+    c->pt_internal.resize(n_points);
+    for (int i = 0; i < n_points; ++i) c->pt_user[i] = c->pt_internal[i] = i;
+    c->fixed_h.assign(n_cams, 0);
+    store(*c, c->d_cams, hc.data(), hc.size());
+    store(*c, c->d_intr, hi.data(), hi.size());
+    store(*c, c->d_pts, hpnt.data(), hpnt.size());
+    store(*c, c->d_fixed, c->fixed_h.data(), c->fixed_h.size());
+  } catch (const BaError& err) {
+    g_create_error = err.msg;
+    delete c;
+    return err.code;
+  }
+  *out = c;
+  return BA_OK;
+}
+
+ba_status ba_set_observations(ba_ctx* c, int64_t n_obs, const int32_t* cam_idx,
+                              const int32_t* pt_idx, const float* xy) {
+  return guarded(c, [&]() -> ba_status {
+    if (n_obs < 0 || n_obs >= (int64_t(1) << 31))
+      return fail(c, BA_ERR_ARG, "n_obs must be in [0, 2^31)");
+    if (n_obs > 0 && (!cam_idx || !pt_idx || !xy))
+      return fail(c, BA_ERR_ARG, "NULL observation array");
+    std::vector<int32_t> hc, hp;
+    std::vector<float> hxy;
+    fetch(*c, hc, cam_idx, size_t(n_obs));
+    fetch(*c, hp, pt_idx, size_t(n_obs));
+    fetch(*c, hxy, xy, 2 * size_t(n_obs));
+    for (int64_t k = 0; k < n_obs; ++k) {
+      if (hc[k] < 0 || hc[k] >= c->C)
+        return fail(c, BA_ERR_ARG, "camera index out of range at observation " + std::to_string(k));
+      if (hp[k] < 0 || hp[k] >= c->P)
+        return fail(c, BA_ERR_ARG, "point index out of range at observation " + std::to_string(k));
+    }
+    // current points back to caller order before renumbering
+    std::vector<double> pts_int, pts_user;
+    download(*c, pts_int, c->d_pts, 3 * size_t(c->P));
+    points_internal_to_user(*c, pts_int, pts_user);
+
+    // internal point order: by smallest observing camera (points seen by the same cameras
+    // become neighbours, which keeps the camera-major gathers local), stable
+    const int C = c->C, P = c->P;
+    std::vector<int32_t> key(P, C);
+    for (int64_t k = 0; k < n_obs; ++k) key[hp[k]] = std::min(key[hp[k]], hc[k]);
+    std::vector<int32_t> order, offs;
+    counting_order(key, C + 1, order, offs);
+    c->pt_user = order;                       // internal -> caller
+    for (int i = 0; i < P; ++i) c->pt_internal[order[i]] = i;
+    // point-major observation order (stable in the caller's order within a point)
+    std::vector<int32_t> pint(n_obs);
+    for (int64_t k = 0; k < n_obs; ++k) pint[k] = c->pt_internal[hp[k]];
+    std::vector<int32_t> pm_order, pt_off;
+    counting_order(pint, P, pm_order, pt_off);
+    std::vector<int32_t> pm_cam(n_obs), pm_pt(n_obs);
+    std::vector<float> pm_xy(2 * size_t(n_obs));
+    for (int64_t j = 0; j < n_obs; ++j) {
+      const int32_t k = pm_order[j];
+      pm_cam[j] = hc[k];
+      pm_pt[j] = pint[k];
+      pm_xy[2 * j] = hxy[2 * size_t(k)];
+      pm_xy[2 * j + 1] = hxy[2 * size_t(k) + 1];
+    }
+    // camera-major order over the point-major positions (stable: increasing point)
+    std::vector<int32_t> cm_perm, cm_off;
+    counting_order(pm_cam, C, cm_perm, cm_off);
+
+    c->N = n_obs;
+    c->have_obs = false;
+    alloc_obs_buffers(*c);
+    std::vector<float> zeros(size_t(n_obs), 0.0f);
+    store(*c, c->pm_cam, pm_cam.data(), pm_cam.size());
+    store(*c, c->pm_pt, pm_pt.data(), pm_pt.size());
+    store(*c, c->pm_orig, pm_order.data(), pm_order.size());
+    store(*c, reinterpret_cast<float*>(c->pm_xy), pm_xy.data(), pm_xy.size());
+    store(*c, c->pm_depth, zeros.data(), zeros.size());
+    store(*c, c->pt_off, pt_off.data(), pt_off.size());
+    store(*c, c->cm_off, cm_off.data(), cm_off.size());
+    store(*c, c->cm_perm, cm_perm.data(), cm_perm.size());
+    store(*c, c->pt_user_d, c->pt_user.data(), c->pt_user.size());
+    points_user_to_internal(*c, pts_user, pts_int);
+    store(*c, c->d_pts, pts_int.data(), pts_int.size());
+    c->pm_orig_h = pm_order;
+    c->have_obs = true;
+    c->have_priors = false;
+    c->lam_d = 0.0;
+    c->lam = c->opt.lambda_init;
+    c->nu = 2.0;
+    c->lin_valid = c->ext_valid = c->step_valid = c->blocks_valid = false;
+    return BA_OK;
+  });
+}
+
+ba_status ba_set_depth_priors(ba_ctx* c, const float* depth, const uint8_t* valid,
+                              double lambda_d) {
+  return guarded(c, [&]() -> ba_status {
+    if (!c->have_obs) return fail(c, BA_ERR_STATE, "set observations before depth priors");
+    if (!(lambda_d >= 0) || !std::isfinite(lambda_d))
+      return fail(c, BA_ERR_ARG, "lambda_d must be finite and >= 0");
+    if (c->N > 0 && !depth) return fail(c, BA_ERR_ARG, "depth is NULL");
+    std::vector<float> hd;
+    std::vector<uint8_t> hv;
+    fetch(*c, hd, depth, size_t(c->N));
+    if (valid) fetch(*c, hv, valid, size_t(c->N));
+    std::vector<float> pm(size_t(c->N));
+    for (int64_t j = 0; j < c->N; ++j) {
+      const int32_t k = c->pm_orig_h[j];
+      const float d = hd[k];
+      const bool ok = (!valid || hv[k] != 0) && std::isfinite(d) && d > 0.0f;
+      pm[j] = ok ? d : 0.0f;
+    }
+    store(*c, c->pm_depth, pm.data(), pm.size());
+    c->have_priors = true;
+    c->lam_d = lambda_d;
+    c->lin_valid = c->ext_valid = c->step_valid = c->blocks_valid = false;
+    return BA_OK;
+  });
+}
+
+ba_status ba_set_fixed_cameras(ba_ctx* c, int32_t n, const int32_t* ids) {
+  return guarded(c, [&]() -> ba_status {
+    if (n < 0 || (n > 0 && !ids)) return fail(c, BA_ERR_ARG, "invalid fixed camera list");
+    std::vector<int32_t> h;
+    fetch(*c, h, ids, size_t(n));
+    std::vector<uint8_t> f(size_t(c->C), 0);
+    for (int32_t i : h) {
+      if (i < 0 || i >= c->C) return fail(c, BA_ERR_ARG, "fixed camera index out of range");
+      f[i] = 1;
+    }
+    c->fixed_h = f;
+    c->n_fixed = 0;
+    for (uint8_t v : f) c->n_fixed += v;
+    store(*c, c->d_fixed, f.data(), f.size());
+    c->lin_valid = c->ext_valid = c->step_valid = c->blocks_valid = false;
+    return BA_OK;
+  });
+}
+
+ba_status ba_lm_step(ba_ctx* c, ba_step_report* rep) {
+  return guarded(c, [&]() -> ba_status { return lm_step_dispatch(*c, rep); });
+}
+
+ba_status ba_solve(ba_ctx* c, ba_solve_report* rep) {
+  return guarded(c, [&]() -> ba_status {
+    const double t0 = now_ms();
+    ba_solve_report S;
+    std::memset(&S, 0, sizeof(S));
+    ba_step_report R;
+    ba_status st = BA_OK;
+    bool first = true;
+    for (int it = 0; it < c->opt.max_lm_iters; ++it) {
+      st = lm_step_dispatch(*c, &R);
+      S.iterations += 1;
+      if (st == BA_EMPTY) {
+        S.stop_reason = 4;
+        break;
+      }
+      if (first) {
+        S.initial_cost = R.cost_before;
+        S.initial_rms_px = R.rms_px;
+        first = false;
+      }
+      S.total_pcg_iters += R.pcg_iters;
+      S.accepted += R.accepted;
+      S.final_cost = R.accepted ? R.cost_after : R.cost_before;
+      S.final_rms_px = R.rms_px;
+      if (R.grad_inf <= c->opt.grad_tol) {
+        S.stop_reason = 2;
+        break;
+      }
+      if (R.accepted && R.cost_before - R.cost_after <= c->opt.cost_rel_tol * R.cost_before) {
+        S.stop_reason = 1;
+        break;
+      }
+      if (!R.accepted && R.lambda >= c->opt.lambda_max) {
+        S.stop_reason = 3;
+        break;
+      }
+    }
+    S.lambda = c->lam;
+    S.ms_total = now_ms() - t0;
+    if (rep) *rep = S;
+    return st == BA_EMPTY ? BA_EMPTY : BA_OK;
+  });
+}
+
+ba_status ba_get_params(const ba_ctx* cc, double* cams, double* points) {
+  ba_ctx* c = const_cast<ba_ctx*>(cc);
+  return guarded(c, [&]() -> ba_status {
+    if (cams) {
+      HIP_CHECK(hipMemcpyAsync(cams, c->d_cams, sizeof(double) * 7 * size_t(c->C),
+                               hipMemcpyDefault, c->stream));
+      c->sync();
+    }
+    if (points) {
+      std::vector<double> in, user;
+      download(*c, in, c->d_pts, 3 * size_t(c->P));
+      points_internal_to_user(*c, in, user);
+      store(*c, points, user.data(), user.size());
+    }
+    return BA_OK;
+  });
+}
+
+ba_status ba_set_params(ba_ctx* c, const double* cams, const double* points) {
+  return guarded(c, [&]() -> ba_status {
+    if (cams) {
+      std::vector<double> h;
+      fetch(*c, h, cams, 7 * size_t(c->C));
+      for (double v : h)
+        if (!std::isfinite(v)) return fail(c, BA_ERR_ARG, "non-finite camera parameter");
+      store(*c, c->d_cams, h.data(), h.size());
+    }
+    if (points) {
+      std::vector<double> h, in;
+      fetch(*c, h, points, 3 * size_t(c->P));
+      for (double v : h)
+        if (!std::isfinite(v)) return fail(c, BA_ERR_ARG, "non-finite point");
+      points_user_to_internal(*c, h, in);
+      store(*c, c->d_pts, in.data(), in.size());
+    }
+    c->lam = c->opt.lambda_init;
+    c->nu = 2.0;
+    c->lin_valid = c->step_valid = c->blocks_valid = false;
+    return BA_OK;
+  });
+}
+
+ba_status ba_get_active(const ba_ctx* cc, uint8_t* cams, uint8_t* points, uint8_t* obs) {
+  ba_ctx* c = const_cast<ba_ctx*>(cc);
+  return guarded(c, [&]() -> ba_status {
+    if (!c->ext_valid) return fail(c, BA_ERR_STATE, "no extraction has run yet");
+    if (cams) {
+      std::vector<uint8_t> h;
+      download(*c, h, c->act_c, size_t(c->C));
+      store(*c, cams, h.data(), h.size());
+    }
+    if (points) {
+      std::vector<uint8_t> h, u(size_t(c->P));
+      download(*c, h, c->act_p, size_t(c->P));
+      for (int i = 0; i < c->P; ++i) u[c->pt_user[i]] = h[i];
+      store(*c, points, u.data(), u.size());
+    }
+    if (obs) {
+      std::vector<uint8_t> h, u(size_t(c->N));
+      download(*c, h, c->vrow, size_t(c->N));
+      for (int64_t j = 0; j < c->N; ++j) u[c->pm_orig_h[j]] = h[j] ? 1 : 0;
+      store(*c, obs, u.data(), u.size());
+    }
+    return BA_OK;
+  });
+}
+
+ba_status ba_get_last_step(const ba_ctx* cc, double* dcams, double* dpoints) {
+  ba_ctx* c = const_cast<ba_ctx*>(cc);
+  return guarded(c, [&]() -> ba_status {
+    if (!c->step_valid) return fail(c, BA_ERR_STATE, "no LM step has been computed");
+    std::vector<int> src;
+    if (dcams) {
+      std::vector<double> x, out(6 * size_t(c->C), 0.0);
+      download(*c, x, c->x, 6 * size_t(c->Ca));
+      download(*c, src, c->cam_src, size_t(c->Ca));
+      for (int s = 0; s < c->Ca; ++s)
+        for (int k = 0; k < 6; ++k) out[6 * size_t(src[s]) + k] = x[6 * size_t(s) + k];
+      store(*c, dcams, out.data(), out.size());
+    }
+    if (dpoints) {
+      std::vector<double> d, out(3 * size_t(c->P), 0.0);
+      download(*c, d, c->dp, 3 * size_t(c->Pa));
+      download(*c, src, c->pt_src, size_t(c->Pa));
+      for (int r = 0; r < c->Pa; ++r)
+        for (int k = 0; k < 3; ++k)
+          out[3 * size_t(c->pt_user[src[r]]) + k] = d[3 * size_t(r) + k];
+      store(*c, dpoints, out.data(), out.size());
+    }
+    return BA_OK;
+  });
+}
+
+ba_status ba_get_normal_blocks(const ba_ctx* cc, double* U, double* gcv, double* V,
+                               double* gpv) {
+  ba_ctx* c = const_cast<ba_ctx*>(cc);
+  return guarded(c, [&]() -> ba_status {
+    if (!c->blocks_valid) return fail(c, BA_ERR_STATE, "no linearisation is available");
+    std::vector<int> csrc, psrc;
+    download(*c, csrc, c->cam_src, size_t(c->Ca));
+    download(*c, psrc, c->pt_src, size_t(c->Pa));
+    if (U || gcv) {
+      std::vector<double> u, g, Uo(36 * size_t(c->C), 0.0), go(6 * size_t(c->C), 0.0);
+      download(*c, u, c->Uraw, 21 * size_t(c->Ca));
+      download(*c, g, c->gc, 6 * size_t(c->Ca));
+      for (int s = 0; s < c->Ca; ++s) {
+        const size_t cam = size_t(csrc[s]);
+        for (int i = 0; i < 6; ++i) {
+          go[6 * cam + i] = g[6 * size_t(s) + i];
+          for (int j = 0; j < 6; ++j) {
+            const int a = std::min(i, j), b = std::max(i, j);
+            const int idx = a * 6 - (a * (a - 1)) / 2 + (b - a);
+            Uo[36 * cam + 6 * i + j] = u[21 * size_t(s) + idx];
+          }
+        }
+      }
+      if (U) store(*c, U, Uo.data(), Uo.size());
+      if (gcv) store(*c, gcv, go.data(), go.size());
+    }
+    if (V || gpv) {
+      std::vector<double> Vo(9 * size_t(c->P), 0.0), go(3 * size_t(c->P), 0.0), g, v;
+      download(*c, g, c->gp, 3 * size_t(c->Pa));
+      if (c->tsize() == 8) {
+        download(*c, v, static_cast<const double*>(c->V), 6 * size_t(c->Pa));
+      } else {
+        std::vector<float> vf;
+        download(*c, vf, static_cast<const float*>(c->V), 6 * size_t(c->Pa));
+        v.assign(vf.begin(), vf.end());
+      }
+      static const int m3[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+      for (int r = 0; r < c->Pa; ++r) {
+        const size_t pu = size_t(c->pt_user[psrc[r]]);
+        for (int i = 0; i < 3; ++i) {
+          go[3 * pu + i] = g[3 * size_t(r) + i];
+          for (int j = 0; j < 3; ++j) Vo[9 * pu + 3 * i + j] = v[6 * size_t(r) + m3[i][j]];
+        }
+      }
+      if (V) store(*c, V, Vo.data(), Vo.size());
+      if (gpv) store(*c, gpv, go.data(), go.size());
+    }
+    return BA_OK;
+  });
+}
+
+ba_status ba_adjoint(ba_ctx* c, const double* grad_cams, const double* grad_points,
+                     float* grad_xy, float* grad_depth) {
+  return guarded(c, [&]() -> ba_status {
+    if (!c->have_obs) return fail(c, BA_ERR_STATE, "ba_set_observations has not been called");
+    if (!grad_cams || !grad_points || !grad_xy)
+      return fail(c, BA_ERR_ARG, "grad_cams, grad_points and grad_xy are required");
+    const bool metric = c->have_priors && c->lam_d > 0;
+    if (c->n_fixed < 1 || (!metric && c->n_fixed < 2))
+      return fail(c, BA_ERR_STATE,
+                  "the adjoint needs a fixed gauge: >= 1 fixed camera and depth rows "
+                  "(lambda_d > 0), or >= 2 fixed cameras");
+    if (c->opt.precision == BA_PRECISION_FP64)
+      adjoint_impl<double>(*c, grad_cams, grad_points, grad_xy, grad_depth);
+    else
+      adjoint_impl<float>(*c, grad_cams, grad_points, grad_xy, grad_depth);
+    return BA_OK;
+  });
+}
+
+ba_status ba_kernel_stats(const ba_ctx* cc, ba_kernel_stat* out, int32_t max, int32_t* n) {
+  ba_ctx* c = const_cast<ba_ctx*>(cc);
+  return guarded(c, [&]() -> ba_status {
+    if (!n || (max > 0 && !out)) return fail(c, BA_ERR_ARG, "NULL output");
+    int k = 0;
+    for (const KStat& s : c->stats) {
+      if (k >= max) break;
+      std::memset(&out[k], 0, sizeof(ba_kernel_stat));
+      std::snprintf(out[k].name, sizeof(out[k].name), "%s", s.name.c_str());
+      out[k].launches = s.launches;
+      out[k].total_ms = s.ms;
+      out[k].total_bytes = s.bytes;
+      ++k;
+    }
+    *n = k;
+    return BA_OK;
+  });
+}
+
+ba_status ba_reset_kernel_stats(ba_ctx* c) {
+  return guarded(c, [&]() -> ba_status {
+    for (KStat& s : c->stats) {
+      s.launches = 0;
+      s.ms = 0;
+      s.bytes = 0;
+    }
+    return BA_OK;
+  });
+}
+
+int64_t ba_device_bytes(const ba_ctx* c) { return c ? c->par.bytes + c->obs.bytes : 0; }
+
+const char* ba_last_error(const ba_ctx* c) {
+  return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+void ba_destroy(ba_ctx* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  delete c;
+}
+
+}  // extern "C"

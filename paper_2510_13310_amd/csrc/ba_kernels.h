@@ -1,0 +1,182 @@
+// Internal interface between the host orchestration (ba_api.hip) and the gfx950 kernels
+// (ba_kernels.hip). Not installed; the public ABI is include/ba.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace iba {
+
+constexpr int kBlock = 256;           // threads per block for streaming kernels
+constexpr int kScanItems = 16;        // elements per thread in the block scan
+constexpr int kScanTile = kBlock * kScanItems;
+
+// Camera table entry: rotation (row-major, world to camera), centre, intrinsics.
+template <typename T>
+struct Cam {
+  T R[9];
+  T c[3];
+  T f, cx, cy;
+};
+
+// Residual-model constants shared by the kernels.
+struct Model {
+  double lam_d;       // weight of the inverse-depth row (0: no depth row)
+  double huber;       // Huber threshold on the stacked norm (<= 0: plain L2)
+  double min_depth;   // validity: z > min_depth
+  double filter_px;   // validity: 2-D error <= filter_px (<= 0: off)
+  int img_w, img_h;   // validity: projection inside [0, w) x [0, h)
+};
+
+// Device-side PCG scalars (one instance per context).
+struct PcgState {
+  double rz;          // r.z of the current iterate
+  double bb;          // b.b
+  double rr;          // r.r of the current iterate
+  double tol2;        // (relative tolerance)^2
+  int iter;
+  int max_iter;
+  int done;
+  int breakdown;      // p.S.p <= 0 or non-finite
+};
+
+// Compact problem view shared by the point-major and camera-major passes.
+template <typename T>
+struct Compact {
+  int Pa, Ca;
+  const int* off;         // Pa + 1: point-major CSR over compact observations
+  const int* cam;         // Nh: original camera index of each compact observation
+  const float2* xy;       // Nh
+  const float* depth;     // Nh: prior depth, 0 where invalid (m = 0)
+  const int* slot;        // C: solve slot of each camera, -1 if not in the solve
+  const int* cam_src;     // Ca: original camera index of each solve slot
+  const int* cm_off;      // Ca + 1: camera-major segments
+  const int* cm_pt;       // Nc: point rank of each camera-major observation
+  const int* cm_pm;       // Nc: position of that observation in the point-major stream
+  const double* Xd;       // Pa x 3 compact points (float64)
+  const T* Xt;            // Pa x 3 compact points (T)
+  const Cam<double>* camd;// C camera table (float64)
+  const Cam<T>* camt;     // C camera table (T)
+};
+
+// Per-observation metric data written by the linearisation. The LM step weighs an
+// observation by M = w I (w = rho'). The adjoint uses the robust-corrected metric
+// M = rho' I + 2 rho'' e e^T; for the Huber function in its linear regime this equals
+// w (I - eh eh^T) with eh = e / |e|, so the adjoint stores eh (zero in the quadratic regime)
+// and every kernel projects the rows of de/dX_c with (I - eh eh^T).
+template <typename T>
+struct ObsMetric {
+  T* w;      // Nh: rho'
+  T* eh;     // Nh x 3: unit residual direction (adjoint only, else nullptr)
+  T* cm_w;   // Nc: copies in camera-major order
+  T* cm_eh;  // Nc x 3 (adjoint only)
+};
+
+// ------------------------------------------------------------------ extraction
+void launch_cam_table(hipStream_t s, int C, const double* cams, const double* intr,
+                      Cam<double>* camd, Cam<float>* camf);
+void launch_validate(hipStream_t s, int64_t N, const Model& m, const int* pm_cam,
+                     const int* pm_pt, const float2* xy, const float* depth,
+                     const double* pts, const Cam<double>* camd, uint8_t* vrow);
+void launch_cam_rows(hipStream_t s, int C, const int* cm_off, const int* cm_perm,
+                     const uint8_t* vrow, const uint8_t* fixed, int need, uint8_t* act_c);
+void launch_point_rows_prune(hipStream_t s, int P, const int* pt_off, const int* pm_cam,
+                             const uint8_t* act_c, const uint8_t* fixed, int need,
+                             uint8_t* vrow, uint8_t* act_p, int* changed);
+// Exclusive scan of 0/1 flags; out has n + 1 entries (out[n] = total). tmp needs
+// scan_tmp_ints(n) ints.
+int64_t scan_tmp_ints(int64_t n);
+void launch_scan_u8(hipStream_t s, int64_t n, const uint8_t* flags, int* out, int* tmp);
+void launch_scan_cm(hipStream_t s, int64_t n, const int* cm_perm, const uint8_t* vrow,
+                    const int* pm_cam, const uint8_t* fixed, int* out, int* tmp);
+void launch_compact_points(hipStream_t s, int P, const uint8_t* act_p, const int* rank_p,
+                           const int* pt_off, const int* pos_pm, const double* pts,
+                           int* pt_src, int* off_hat, double* Xd, float* Xf);
+void launch_compact_obs(hipStream_t s, int64_t N, const uint8_t* vrow, const int* pos_pm,
+                        const int* pm_cam, const float2* pm_xy, const float* pm_depth,
+                        const int* pm_orig, int* cam_hat, float2* xy_hat, float* depth_hat,
+                        int* orig_hat);
+void launch_compact_cams(hipStream_t s, int C, const uint8_t* act_c, const int* rank_c,
+                         const int* cm_off, const int* pos_cm, int* slot, int* cam_src,
+                         int* cm_off_hat);
+void launch_compact_cm(hipStream_t s, int64_t N, const int* cm_perm, const uint8_t* vrow,
+                       const int* pm_cam, const int* pm_pt, const uint8_t* fixed,
+                       const int* pos_cm, const int* pos_pm, const int* rank_p, int* cm_pt,
+                       int* cm_pm);
+
+// ------------------------------------------------------------------ linearisation
+// Per point: residuals (float64), robust weights, V = J_p^T M J_p (T), gp = J_p^T M e
+// (float64); per block: cost, sum |r_2d|^2 and max |gp| into partials[3 * block].
+template <typename T>
+void launch_lin_point(hipStream_t s, bool adj, const Model& m, const Compact<T>& cp,
+                      ObsMetric<T> om, T* V, double* gp, double* partials);
+template <typename T>
+void launch_gather_cm_metric(hipStream_t s, bool adj, int64_t Nc, const int* cm_pm,
+                             ObsMetric<T> om);
+// V* = V + lam clamp(diag V); Vinv (inverted in float64, stored as T); hp = Vinv rhs_p.
+// rhs_p = -gp when rhs_p == nullptr.
+template <typename T>
+void launch_point_damp(hipStream_t s, int Pa, double lam, double dmin, double dmax,
+                       const T* V, const double* gp, const double* rhs_p, T* Vinv,
+                       double* hp, int* bad);
+// Per camera: U = J_c^T M J_c, gc, b = rhs_c - sum W hp, S_cc = U* - sum W Vinv W^T and its
+// inverse (Cholesky, float64). rhs_c = -gc when rhs_c == nullptr.
+template <typename T>
+void launch_cam_assemble(hipStream_t s, bool adj, const Model& m, const Compact<T>& cp,
+                         ObsMetric<T> om, double lam, double dmin, double dmax,
+                         const T* Vinv, const double* hp, const double* rhs_c,
+                         double* Uraw, T* Ustar, double* gc, double* b, double* Minv);
+
+// ------------------------------------------------------------------ PCG on S
+template <typename T>
+void launch_pcg_init(hipStream_t s, int Ca, const double* b, const double* Minv, double* x,
+                     double* r, double* z, double* p, T* pt, PcgState* st, double tol2,
+                     int max_iter);
+// z_p = Vinv sum_k W_k^T p_c  (point-major pass)
+template <typename T>
+void launch_schur_point(hipStream_t s, bool adj, const Model& m, const Compact<T>& cp,
+                        ObsMetric<T> om, const T* Vinv, const T* pvec, T* zq,
+                        const PcgState* st);
+// q_c = U*_c p_c - sum_k W_k z_p (camera-major pass) and p_c.q_c partials
+template <typename T>
+void launch_schur_cam(hipStream_t s, bool adj, const Model& m, const Compact<T>& cp,
+                      ObsMetric<T> om, const T* Ustar, const T* pvec, const double* p64,
+                      const T* zq, double* q, double* pq_part, const PcgState* st);
+template <typename T>
+void launch_pcg_update(hipStream_t s, int Ca, const double* Minv, const double* q,
+                       const double* pq_part, double* x, double* r, double* z, double* p,
+                       T* pt, PcgState* st);
+// dp = Vinv (rhs_p - sum_k W_k^T x_c), rhs_p = -gp when nullptr.
+template <typename T>
+void launch_backsub(hipStream_t s, bool adj, const Model& m, const Compact<T>& cp,
+                    ObsMetric<T> om, const T* Vinv, const double* x, const double* gp,
+                    const double* rhs_p, double* dp);
+
+// ------------------------------------------------------------------ candidate
+void launch_cam_candidate(hipStream_t s, int C, const int* slot, const double* x,
+                          const double* cams, const double* intr, const Cam<double>* camd,
+                          double* cand_cams, Cam<double>* cand_tab);
+template <typename T>
+void launch_point_candidate(hipStream_t s, const Model& m, const Compact<T>& cp,
+                            const Cam<double>* cand_tab, const double* x, const double* dp,
+                            const double* gp, const T* w, double* Xcand, double* partials);
+// Sums per-block partials (K doubles per block) in a fixed order; also adds gc.x when
+// gc != nullptr into out[K].
+void launch_reduce_partials(hipStream_t s, int nblocks, int K, const double* partials,
+                            unsigned max_mask, int Ca, const double* gc, const double* x,
+                            double* out);
+void launch_scatter(hipStream_t s, int Pa, int C, const int* pt_src, const double* Xcand,
+                    const int* slot, const double* cand_cams, double* pts, double* cams);
+
+// ------------------------------------------------------------------ adjoint
+// rhs for the adjoint solve: tangent-mapped camera gradients and point gradients (both
+// gathered from caller-order device arrays).
+void launch_adjoint_rhs(hipStream_t s, int Ca, int Pa, const int* cam_src, const double* cams,
+                        const double* grad_cams, const int* pt_src, const int* pt_user,
+                        const double* grad_pts, double* rhs_c, double* rhs_p);
+template <typename T>
+void launch_adjoint_obs(hipStream_t s, const Model& m, const Compact<T>& cp, ObsMetric<T> om,
+                        const double* x, const double* dp, const int* orig, float* gxy,
+                        float* gdepth);
+
+}  // namespace iba

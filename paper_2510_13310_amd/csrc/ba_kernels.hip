@@ -1,0 +1,1541 @@
+// gfx950 kernels of the LM bundle-adjustment step (InstantSfM, arXiv 2510.13310).
+//
+// Every kernel streams structure-of-arrays observation data in one of two fixed orders:
+//   point-major  (compact observations grouped by point, CSR offsets `off`), one thread per
+//                point walks its segment and reduces in registers;
+//   camera-major (the same observations grouped by camera, `cm_off`), one block per camera
+//                reduces its segment with wave shuffles and LDS in a fixed order.
+// No global atomics are used for sums, so every result is bitwise reproducible.
+//
+// The per-observation Jacobian blocks are never stored: both PCG passes recompute
+// de/dX_c, J_c = de/dX_c [I | -[X_c]x] and J_p = de/dX_c R from the point, the camera table
+// (a few KB, cache resident) and the stored robust weight. This trades ~60 flops per
+// observation for the 72-144 bytes a stored W_k = J_c^T J_p block would cost per pass.
+#include "ba_kernels.h"
+
+#include <cmath>
+
+namespace iba {
+namespace {
+
+constexpr int kWave = 64;
+
+// ------------------------------------------------------------------ reductions
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    T u = __shfl_xor(v, o, kWave);
+    v = u > v ? u : v;
+  }
+  return v;
+}
+
+// Sums K per-thread values over the block; the result is valid in thread 0.
+// smem holds K * (blockDim.x / 64) values.
+template <typename T, int K>
+__device__ __forceinline__ void block_sum(T (&v)[K], T* smem) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) smem[wid * K + k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < K; ++k) {
+      T a = smem[k];
+      for (int w = 1; w < nw; ++w) a += smem[w * K + k];
+      v[k] = a;
+    }
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------ small linear algebra
+// Symmetric 6x6 stored as the upper triangle, row-major (21 values).
+__host__ __device__ constexpr int sym6(int i, int j) {
+  return i <= j ? i * 6 - (i * (i - 1)) / 2 + (j - i) : j * 6 - (j * (j - 1)) / 2 + (i - j);
+}
+// Symmetric 3x3: [00, 01, 02, 11, 12, 22].
+__host__ __device__ constexpr int sym3(int i, int j) {
+  return i <= j ? i * 3 - (i * (i - 1)) / 2 + (j - i) : j * 3 - (j * (j - 1)) / 2 + (i - j);
+}
+
+template <typename T>
+__device__ __forceinline__ void cross3(const T a[3], const T b[3], T o[3]) {
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// Camera-frame coordinates R (X - c).
+template <typename T, typename S>
+__device__ __forceinline__ void cam_frame(const Cam<S>& cm, T X0, T X1, T X2, T Xc[3]) {
+  const T d0 = X0 - T(cm.c[0]), d1 = X1 - T(cm.c[1]), d2 = X2 - T(cm.c[2]);
+  Xc[0] = T(cm.R[0]) * d0 + T(cm.R[1]) * d1 + T(cm.R[2]) * d2;
+  Xc[1] = T(cm.R[3]) * d0 + T(cm.R[4]) * d1 + T(cm.R[5]) * d2;
+  Xc[2] = T(cm.R[6]) * d0 + T(cm.R[7]) * d1 + T(cm.R[8]) * d2;
+}
+
+// R v and R^T v for a row-major camera rotation.
+template <typename T, typename S>
+__device__ __forceinline__ void rot_mul(const Cam<S>& cm, const T v[3], T o[3]) {
+  o[0] = T(cm.R[0]) * v[0] + T(cm.R[1]) * v[1] + T(cm.R[2]) * v[2];
+  o[1] = T(cm.R[3]) * v[0] + T(cm.R[4]) * v[1] + T(cm.R[5]) * v[2];
+  o[2] = T(cm.R[6]) * v[0] + T(cm.R[7]) * v[1] + T(cm.R[8]) * v[2];
+}
+template <typename T, typename S>
+__device__ __forceinline__ void rot_tmul(const Cam<S>& cm, const T v[3], T o[3]) {
+  o[0] = T(cm.R[0]) * v[0] + T(cm.R[3]) * v[1] + T(cm.R[6]) * v[2];
+  o[1] = T(cm.R[1]) * v[0] + T(cm.R[4]) * v[1] + T(cm.R[7]) * v[2];
+  o[2] = T(cm.R[2]) * v[0] + T(cm.R[5]) * v[1] + T(cm.R[8]) * v[2];
+}
+
+// Rows of de/dX_c (3 x 3): pinhole rows (f/z)[1 0 -x/z], (f/z)[0 1 -y/z] and the
+// inverse-depth row [0 0 -lam_d/z^2]. The plain form keeps the five structural non-zeros;
+// the projected form (adjoint metric) is a full matrix (I - eh eh^T) A.
+template <typename T, bool PROJ>
+struct AMat;
+
+template <typename T>
+struct AMat<T, false> {
+  T a00, a02, a11, a12, a22;
+  __device__ __forceinline__ void set(T f, T lam_d, const T Xc[3]) {
+    const T iz = T(1) / Xc[2];
+    a00 = f * iz;
+    a11 = a00;
+    a02 = -a00 * Xc[0] * iz;
+    a12 = -a00 * Xc[1] * iz;
+    a22 = -lam_d * iz * iz;
+  }
+  __device__ __forceinline__ void project(const T*) {}
+  __device__ __forceinline__ void apply(const T d[3], T t[3]) const {
+    t[0] = a00 * d[0] + a02 * d[2];
+    t[1] = a11 * d[1] + a12 * d[2];
+    t[2] = a22 * d[2];
+  }
+  __device__ __forceinline__ void applyT(const T t[3], T m[3]) const {
+    m[0] = a00 * t[0];
+    m[1] = a11 * t[1];
+    m[2] = a02 * t[0] + a12 * t[1] + a22 * t[2];
+  }
+  __device__ __forceinline__ void row(int i, T r[3]) const {
+    r[0] = i == 0 ? a00 : T(0);
+    r[1] = i == 1 ? a11 : T(0);
+    r[2] = i == 0 ? a02 : (i == 1 ? a12 : a22);
+  }
+};
+
+template <typename T>
+struct AMat<T, true> {
+  T a[9];
+  __device__ __forceinline__ void set(T f, T lam_d, const T Xc[3]) {
+    const T iz = T(1) / Xc[2];
+    const T fz = f * iz;
+    a[0] = fz; a[1] = T(0); a[2] = -fz * Xc[0] * iz;
+    a[3] = T(0); a[4] = fz; a[5] = -fz * Xc[1] * iz;
+    a[6] = T(0); a[7] = T(0); a[8] = -lam_d * iz * iz;
+  }
+  // A <- (I - eh eh^T) A, column by column.
+  __device__ __forceinline__ void project(const T* eh) {
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      const T s = eh[0] * a[l] + eh[1] * a[3 + l] + eh[2] * a[6 + l];
+      a[l] -= eh[0] * s;
+      a[3 + l] -= eh[1] * s;
+      a[6 + l] -= eh[2] * s;
+    }
+  }
+  __device__ __forceinline__ void apply(const T d[3], T t[3]) const {
+    t[0] = a[0] * d[0] + a[1] * d[1] + a[2] * d[2];
+    t[1] = a[3] * d[0] + a[4] * d[1] + a[5] * d[2];
+    t[2] = a[6] * d[0] + a[7] * d[1] + a[8] * d[2];
+  }
+  __device__ __forceinline__ void applyT(const T t[3], T m[3]) const {
+    m[0] = a[0] * t[0] + a[3] * t[1] + a[6] * t[2];
+    m[1] = a[1] * t[0] + a[4] * t[1] + a[7] * t[2];
+    m[2] = a[2] * t[0] + a[5] * t[1] + a[8] * t[2];
+  }
+  __device__ __forceinline__ void row(int i, T r[3]) const {
+    r[0] = a[3 * i];
+    r[1] = a[3 * i + 1];
+    r[2] = a[3 * i + 2];
+  }
+};
+
+// Huber on the squared norm s: rho, rho', rho''.
+__device__ __forceinline__ void huber(double s, double delta, double& rho, double& d1,
+                                      double& d2) {
+  if (delta > 0.0 && s > delta * delta) {
+    const double rs = sqrt(s);
+    rho = 2.0 * delta * rs - delta * delta;
+    d1 = delta / rs;
+    d2 = -0.5 * delta / (rs * rs * rs);
+  } else {
+    rho = s;
+    d1 = 1.0;
+    d2 = 0.0;
+  }
+}
+
+// Stacked residual e = [Pi - x ; lam_d (1/z - m/d_hat)] of one observation (float64).
+__device__ __forceinline__ void residual(const Cam<double>& cm, const double Xc[3], float2 xy,
+                                        float depth, double lam_d, double e[3]) {
+  const double iz = 1.0 / Xc[2];
+  e[0] = cm.f * Xc[0] * iz + cm.cx - double(xy.x);
+  e[1] = cm.f * Xc[1] * iz + cm.cy - double(xy.y);
+  const double dinv = depth > 0.0f ? 1.0 / double(depth) : 0.0;
+  e[2] = lam_d * (iz - dinv);
+}
+
+// ------------------------------------------------------------------ extraction kernels
+__global__ void __launch_bounds__(kBlock)
+k_cam_table(int C, const double* __restrict__ cams, const double* __restrict__ intr,
+            Cam<double>* __restrict__ camd, Cam<float>* __restrict__ camf) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  double qw = cams[7 * c], qx = cams[7 * c + 1], qy = cams[7 * c + 2], qz = cams[7 * c + 3];
+  const double n = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+  qw /= n; qx /= n; qy /= n; qz /= n;
+  Cam<double> d;
+  d.R[0] = 1 - 2 * (qy * qy + qz * qz);
+  d.R[1] = 2 * (qx * qy - qw * qz);
+  d.R[2] = 2 * (qx * qz + qw * qy);
+  d.R[3] = 2 * (qx * qy + qw * qz);
+  d.R[4] = 1 - 2 * (qx * qx + qz * qz);
+  d.R[5] = 2 * (qy * qz - qw * qx);
+  d.R[6] = 2 * (qx * qz - qw * qy);
+  d.R[7] = 2 * (qy * qz + qw * qx);
+  d.R[8] = 1 - 2 * (qx * qx + qy * qy);
+  d.c[0] = cams[7 * c + 4];
+  d.c[1] = cams[7 * c + 5];
+  d.c[2] = cams[7 * c + 6];
+  d.f = intr[3 * c];
+  d.cx = intr[3 * c + 1];
+  d.cy = intr[3 * c + 2];
+  camd[c] = d;
+  Cam<float> f;
+  for (int i = 0; i < 9; ++i) f.R[i] = float(d.R[i]);
+  for (int i = 0; i < 3; ++i) f.c[i] = float(d.c[i]);
+  f.f = float(d.f);
+  f.cx = float(d.cx);
+  f.cy = float(d.cy);
+  camf[c] = f;
+}
+
+// Validity of every observation (Eq. (10) + frustum + reprojection filter), written as the
+// number of residual rows it contributes (0 when invalid).
+__global__ void __launch_bounds__(kBlock)
+k_validate(int64_t N, Model m, const int* __restrict__ pm_cam, const int* __restrict__ pm_pt,
+           const float2* __restrict__ xy, const float* __restrict__ depth,
+           const double* __restrict__ pts, const Cam<double>* __restrict__ camd,
+           uint8_t* __restrict__ vrow) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  const Cam<double> cm = camd[pm_cam[k]];
+  const int p = pm_pt[k];
+  double Xc[3];
+  cam_frame(cm, pts[3 * p], pts[3 * p + 1], pts[3 * p + 2], Xc);
+  bool ok = Xc[2] > m.min_depth;
+  if (ok) {
+    const double u = cm.f * Xc[0] / Xc[2] + cm.cx;
+    const double v = cm.f * Xc[1] / Xc[2] + cm.cy;
+    ok = u >= 0.0 && u < double(m.img_w) && v >= 0.0 && v < double(m.img_h);
+    if (ok && m.filter_px > 0.0) {
+      double e[3];
+      residual(cm, Xc, xy[k], 0.0f, 0.0, e);
+      ok = e[0] * e[0] + e[1] * e[1] <= m.filter_px * m.filter_px;
+    }
+  }
+  const int rows = 2 + ((m.lam_d > 0.0 && depth[k] > 0.0f) ? 1 : 0);
+  vrow[k] = ok ? uint8_t(rows) : uint8_t(0);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_cam_rows(const int* __restrict__ cm_off, const int* __restrict__ cm_perm,
+           const uint8_t* __restrict__ vrow, const uint8_t* __restrict__ fixed, int need,
+           uint8_t* __restrict__ act_c) {
+  __shared__ int smem[kBlock / kWave];
+  const int c = blockIdx.x;
+  int sum[1] = {0};
+  for (int i = cm_off[c] + threadIdx.x; i < cm_off[c + 1]; i += blockDim.x)
+    sum[0] += vrow[cm_perm[i]];
+  block_sum<int, 1>(sum, smem);
+  if (threadIdx.x == 0) act_c[c] = (sum[0] >= need && !fixed[c]) ? 1 : 0;
+}
+
+// One round of the activity fixpoint on the point side: point rows from the current
+// observations, then drop observations whose point is inactive or whose free camera is.
+__global__ void __launch_bounds__(kBlock)
+k_point_rows_prune(int P, const int* __restrict__ pt_off, const int* __restrict__ pm_cam,
+                   const uint8_t* __restrict__ act_c, const uint8_t* __restrict__ fixed,
+                   int need, uint8_t* __restrict__ vrow, uint8_t* __restrict__ act_p,
+                   int* __restrict__ changed) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const int b = pt_off[p], e = pt_off[p + 1];
+  int rows = 0;
+  for (int k = b; k < e; ++k) rows += vrow[k];
+  const bool a = rows >= need;
+  act_p[p] = a ? 1 : 0;
+  bool drop = false;
+  for (int k = b; k < e; ++k) {
+    if (!vrow[k]) continue;
+    const int c = pm_cam[k];
+    if (!a || !(act_c[c] || fixed[c])) {
+      vrow[k] = 0;
+      drop = true;
+    }
+  }
+  if (drop) *changed = 1;   // every writer stores the same value
+}
+
+// ------------------------------------------------------------------ exclusive scan
+struct FlagU8 {
+  const uint8_t* a;
+  __device__ __forceinline__ int operator()(int64_t i) const { return a[i] != 0; }
+};
+struct FlagCM {
+  const int* perm;
+  const uint8_t* vrow;
+  const int* cam;
+  const uint8_t* fixed;
+  __device__ __forceinline__ int operator()(int64_t m) const {
+    const int k = perm[m];
+    return vrow[k] != 0 && !fixed[cam[k]];
+  }
+};
+
+template <class F>
+__global__ void __launch_bounds__(kBlock)
+k_scan_tile(int64_t n, F flag, int* __restrict__ out, int* __restrict__ tile_sums) {
+  __shared__ int s_wave[kBlock / kWave];
+  const int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * kScanItems;
+  int vals[kScanItems];
+  int sum = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    const int64_t idx = base + i;
+    const int f = idx < n ? flag(idx) : 0;
+    vals[i] = sum;
+    sum += f;
+  }
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  int incl = sum;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int t = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += t;
+  }
+  if (lane == kWave - 1) s_wave[wid] = incl;
+  __syncthreads();
+  int woff = 0;
+  for (int w = 0; w < wid; ++w) woff += s_wave[w];
+  const int excl = woff + incl - sum;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    const int64_t idx = base + i;
+    if (idx < n) out[idx] = vals[i] + excl;
+  }
+  if (threadIdx.x == blockDim.x - 1) tile_sums[blockIdx.x] = excl + sum;
+}
+
+// Exclusive scan of the tile sums in one block; writes the grand total to *total.
+__global__ void __launch_bounds__(1024)
+k_scan_tiles(int nt, int* __restrict__ tile_sums, int* __restrict__ total) {
+  __shared__ int s_wave[1024 / kWave];
+  const int per = (nt + blockDim.x - 1) / blockDim.x;
+  const int b = threadIdx.x * per;
+  int sum = 0;
+  for (int i = 0; i < per; ++i)
+    if (b + i < nt) sum += tile_sums[b + i];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  int incl = sum;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int t = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += t;
+  }
+  if (lane == kWave - 1) s_wave[wid] = incl;
+  __syncthreads();
+  int woff = 0;
+  for (int w = 0; w < wid; ++w) woff += s_wave[w];
+  int run = woff + incl - sum;
+  for (int i = 0; i < per; ++i) {
+    if (b + i < nt) {
+      const int v = tile_sums[b + i];
+      tile_sums[b + i] = run;
+      run += v;
+    }
+  }
+  if (threadIdx.x == blockDim.x - 1) *total = woff + incl;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_scan_add(int64_t n, const int* __restrict__ tile_sums, int* __restrict__ out) {
+  const int add = tile_sums[blockIdx.x];
+  const int64_t base = int64_t(blockIdx.x) * kScanTile;
+  for (int i = threadIdx.x; i < kScanTile; i += blockDim.x) {
+    const int64_t idx = base + i;
+    if (idx < n) out[idx] += add;
+  }
+}
+
+template <class F>
+void scan_impl(hipStream_t s, int64_t n, F flag, int* out, int* tmp) {
+  const int nt = int((n + kScanTile - 1) / kScanTile);
+  if (nt == 0) {
+    hipMemsetAsync(out, 0, sizeof(int), s);
+    return;
+  }
+  hipLaunchKernelGGL(k_scan_tile<F>, dim3(nt), dim3(kBlock), 0, s, n, flag, out, tmp);
+  hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, nt, tmp, out + n);
+  hipLaunchKernelGGL(k_scan_add, dim3(nt), dim3(kBlock), 0, s, n, tmp, out);
+}
+
+// ------------------------------------------------------------------ compaction kernels
+__global__ void __launch_bounds__(kBlock)
+k_compact_points(int P, const uint8_t* __restrict__ act_p, const int* __restrict__ rank_p,
+                 const int* __restrict__ pt_off, const int* __restrict__ pos_pm,
+                 const double* __restrict__ pts, int* __restrict__ pt_src,
+                 int* __restrict__ off_hat, double* __restrict__ Xd, float* __restrict__ Xf) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P || !act_p[p]) return;
+  const int r = rank_p[p];
+  pt_src[r] = p;
+  // start and end of the point's compact segment; neighbours store identical values
+  off_hat[r] = pos_pm[pt_off[p]];
+  off_hat[r + 1] = pos_pm[pt_off[p + 1]];
+  for (int i = 0; i < 3; ++i) {
+    Xd[3 * r + i] = pts[3 * p + i];
+    Xf[3 * r + i] = float(pts[3 * p + i]);
+  }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_compact_obs(int64_t N, const uint8_t* __restrict__ vrow, const int* __restrict__ pos_pm,
+              const int* __restrict__ pm_cam, const float2* __restrict__ pm_xy,
+              const float* __restrict__ pm_depth, const int* __restrict__ pm_orig,
+              int* __restrict__ cam_hat, float2* __restrict__ xy_hat,
+              float* __restrict__ depth_hat, int* __restrict__ orig_hat) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= N || !vrow[k]) return;
+  const int j = pos_pm[k];
+  cam_hat[j] = pm_cam[k];
+  xy_hat[j] = pm_xy[k];
+  depth_hat[j] = pm_depth[k];
+  orig_hat[j] = pm_orig[k];
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_compact_cams(int C, const uint8_t* __restrict__ act_c, const int* __restrict__ rank_c,
+               const int* __restrict__ cm_off, const int* __restrict__ pos_cm,
+               int* __restrict__ slot, int* __restrict__ cam_src, int* __restrict__ cm_off_hat) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  if (!act_c[c]) {
+    slot[c] = -1;
+    return;
+  }
+  const int s = rank_c[c];
+  slot[c] = s;
+  cam_src[s] = c;
+  cm_off_hat[s] = pos_cm[cm_off[c]];
+  cm_off_hat[s + 1] = pos_cm[cm_off[c + 1]];
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_compact_cm(int64_t N, const int* __restrict__ cm_perm, const uint8_t* __restrict__ vrow,
+             const int* __restrict__ pm_cam, const int* __restrict__ pm_pt,
+             const uint8_t* __restrict__ fixed, const int* __restrict__ pos_cm,
+             const int* __restrict__ pos_pm, const int* __restrict__ rank_p,
+             int* __restrict__ cm_pt, int* __restrict__ cm_pm) {
+  const int64_t m = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (m >= N) return;
+  const int k = cm_perm[m];
+  if (!vrow[k] || fixed[pm_cam[k]]) return;
+  const int i = pos_cm[m];
+  cm_pt[i] = rank_p[pm_pt[k]];
+  cm_pm[i] = pos_pm[k];
+}
+
+// ------------------------------------------------------------------ linearisation
+template <typename T, bool ADJ>
+__global__ void __launch_bounds__(kBlock)
+k_lin_point(Model m, Compact<T> cp, ObsMetric<T> om, T* __restrict__ V,
+            double* __restrict__ gp, double* __restrict__ partials) {
+  __shared__ double smem[3 * (kBlock / kWave)];
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  double acc[3] = {0.0, 0.0, 0.0};   // cost, sum |r_2d|^2, max |gp|
+  if (r < cp.Pa) {
+    const double X0 = cp.Xd[3 * r], X1 = cp.Xd[3 * r + 1], X2 = cp.Xd[3 * r + 2];
+    T v[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+    double g[3] = {0.0, 0.0, 0.0};
+    for (int j = cp.off[r]; j < cp.off[r + 1]; ++j) {
+      const Cam<double> cm = cp.camd[cp.cam[j]];
+      double Xc[3], e[3];
+      cam_frame(cm, X0, X1, X2, Xc);
+      residual(cm, Xc, cp.xy[j], cp.depth[j], m.lam_d, e);
+      const double s = e[0] * e[0] + e[1] * e[1] + e[2] * e[2];
+      double rho, w, d2;
+      huber(s, m.huber, rho, w, d2);
+      acc[0] += 0.5 * rho;
+      acc[1] += e[0] * e[0] + e[1] * e[1];
+      om.w[j] = T(w);
+      const T Xt[3] = {T(Xc[0]), T(Xc[1]), T(Xc[2])};
+      AMat<T, ADJ> A;
+      A.set(T(cm.f), T(m.lam_d), Xt);
+      if constexpr (ADJ) {
+        const double inv = d2 != 0.0 ? 1.0 / sqrt(s) : 0.0;
+        const T eh[3] = {T(e[0] * inv), T(e[1] * inv), T(e[2] * inv)};
+        om.eh[3 * j] = eh[0];
+        om.eh[3 * j + 1] = eh[1];
+        om.eh[3 * j + 2] = eh[2];
+        A.project(eh);
+      }
+      const T wt = T(w);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        T a[3], jp[3];
+        A.row(i, a);
+        rot_tmul(cm, a, jp);
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+#pragma unroll
+          for (int q = p; q < 3; ++q) v[sym3(p, q)] += wt * jp[p] * jp[q];
+        }
+        if constexpr (!ADJ) {
+          const double we = w * e[i];
+          g[0] += we * double(jp[0]);
+          g[1] += we * double(jp[1]);
+          g[2] += we * double(jp[2]);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) V[6 * r + i] = v[i];
+    gp[3 * r] = g[0];
+    gp[3 * r + 1] = g[1];
+    gp[3 * r + 2] = g[2];
+    acc[2] = fmax(fabs(g[0]), fmax(fabs(g[1]), fabs(g[2])));
+  }
+  // block reduction: two sums and one max
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  acc[0] = wave_sum(acc[0]);
+  acc[1] = wave_sum(acc[1]);
+  acc[2] = wave_max(acc[2]);
+  if (lane == 0) {
+    smem[3 * wid] = acc[0];
+    smem[3 * wid + 1] = acc[1];
+    smem[3 * wid + 2] = acc[2];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int w = 0; w < int(blockDim.x) / kWave; ++w) {
+      a0 += smem[3 * w];
+      a1 += smem[3 * w + 1];
+      a2 = fmax(a2, smem[3 * w + 2]);
+    }
+    partials[3 * blockIdx.x] = a0;
+    partials[3 * blockIdx.x + 1] = a1;
+    partials[3 * blockIdx.x + 2] = a2;
+  }
+}
+
+template <typename T, bool ADJ>
+__global__ void __launch_bounds__(kBlock)
+k_gather_cm_metric(int64_t Nc, const int* __restrict__ cm_pm, ObsMetric<T> om) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= Nc) return;
+  const int j = cm_pm[i];
+  om.cm_w[i] = om.w[j];
+  if constexpr (ADJ) {
+    om.cm_eh[3 * i] = om.eh[3 * j];
+    om.cm_eh[3 * i + 1] = om.eh[3 * j + 1];
+    om.cm_eh[3 * i + 2] = om.eh[3 * j + 2];
+  }
+}
+
+// Damped 3x3 point block, inverted in float64 by cofactors.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_point_damp(int Pa, double lam, double dmin, double dmax, const T* __restrict__ V,
+             const double* __restrict__ gp, const double* __restrict__ rhs_p,
+             T* __restrict__ Vinv, double* __restrict__ hp, int* __restrict__ bad) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= Pa) return;
+  double v00 = V[6 * r], v01 = V[6 * r + 1], v02 = V[6 * r + 2];
+  double v11 = V[6 * r + 3], v12 = V[6 * r + 4], v22 = V[6 * r + 5];
+  v00 += lam * fmin(fmax(v00, dmin), dmax);
+  v11 += lam * fmin(fmax(v11, dmin), dmax);
+  v22 += lam * fmin(fmax(v22, dmin), dmax);
+  const double c00 = v11 * v22 - v12 * v12;
+  const double c01 = v02 * v12 - v01 * v22;
+  const double c02 = v01 * v12 - v02 * v11;
+  const double c11 = v00 * v22 - v02 * v02;
+  const double c12 = v01 * v02 - v00 * v12;
+  const double c22 = v00 * v11 - v01 * v01;
+  const double det = v00 * c00 + v01 * c01 + v02 * c02;
+  double inv[6] = {0, 0, 0, 0, 0, 0};
+  if (det > 0.0 && isfinite(det)) {
+    const double id = 1.0 / det;
+    inv[0] = c00 * id; inv[1] = c01 * id; inv[2] = c02 * id;
+    inv[3] = c11 * id; inv[4] = c12 * id; inv[5] = c22 * id;
+  } else {
+    *bad = 1;
+  }
+#pragma unroll
+  for (int i = 0; i < 6; ++i) Vinv[6 * r + i] = T(inv[i]);
+  double b[3];
+  for (int i = 0; i < 3; ++i) b[i] = rhs_p ? rhs_p[3 * r + i] : -gp[3 * r + i];
+  hp[3 * r] = inv[0] * b[0] + inv[1] * b[1] + inv[2] * b[2];
+  hp[3 * r + 1] = inv[1] * b[0] + inv[3] * b[1] + inv[4] * b[2];
+  hp[3 * r + 2] = inv[2] * b[0] + inv[4] * b[1] + inv[5] * b[2];
+}
+
+// 6x6 SPD inverse through Cholesky (float64); returns false if not positive definite.
+__device__ bool spd6_inverse(const double* A21, double* out21) {
+  double L[6][6];
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) L[i][j] = 0.0;
+  for (int j = 0; j < 6; ++j) {
+    double d = A21[sym6(j, j)];
+    for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
+    if (!(d > 0.0) || !isfinite(d)) return false;
+    const double ljj = sqrt(d);
+    L[j][j] = ljj;
+    for (int i = j + 1; i < 6; ++i) {
+      double s = A21[sym6(i, j)];
+      for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
+      L[i][j] = s / ljj;
+    }
+  }
+  // inverse of L (lower triangular), then A^-1 = L^-T L^-1
+  double Li[6][6];
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) Li[i][j] = 0.0;
+  for (int j = 0; j < 6; ++j) {
+    Li[j][j] = 1.0 / L[j][j];
+    for (int i = j + 1; i < 6; ++i) {
+      double s = 0.0;
+      for (int k = j; k < i; ++k) s += L[i][k] * Li[k][j];
+      Li[i][j] = -s / L[i][i];
+    }
+  }
+  for (int i = 0; i < 6; ++i)
+    for (int j = i; j < 6; ++j) {
+      double s = 0.0;
+      for (int k = j; k < 6; ++k) s += Li[k][i] * Li[k][j];
+      out21[sym6(i, j)] = s;
+    }
+  return true;
+}
+
+template <typename T, bool ADJ>
+__global__ void __launch_bounds__(kBlock)
+k_cam_assemble(Model m, Compact<T> cp, ObsMetric<T> om, double lam, double dmin, double dmax,
+               const T* __restrict__ Vinv, const double* __restrict__ hp,
+               const double* __restrict__ rhs_c, double* __restrict__ Uraw,
+               T* __restrict__ Ustar, double* __restrict__ gc, double* __restrict__ b,
+               double* __restrict__ Minv) {
+  constexpr int K = 21 + 21 + 6 + 6;
+  __shared__ double smem[K * (kBlock / kWave)];
+  const int s = blockIdx.x;
+  const int c = cp.cam_src[s];
+  const Cam<double> cm = cp.camd[c];
+  double acc[K];   // U (21), S = sum W Vinv W^T (21), gc (6), sum W hp (6)
+#pragma unroll
+  for (int i = 0; i < K; ++i) acc[i] = 0.0;
+  for (int i = cp.cm_off[s] + threadIdx.x; i < cp.cm_off[s + 1]; i += blockDim.x) {
+    const int r = cp.cm_pt[i];
+    const int j = cp.cm_pm[i];
+    double Xc[3], e[3];
+    cam_frame(cm, cp.Xd[3 * r], cp.Xd[3 * r + 1], cp.Xd[3 * r + 2], Xc);
+    residual(cm, Xc, cp.xy[j], cp.depth[j], m.lam_d, e);
+    const T wt = om.cm_w[i];
+    const T Xt[3] = {T(Xc[0]), T(Xc[1]), T(Xc[2])};
+    AMat<T, ADJ> A;
+    A.set(T(cm.f), T(m.lam_d), Xt);
+    if constexpr (ADJ) A.project(om.cm_eh + 3 * i);
+    T U[21], W[18];
+#pragma unroll
+    for (int q = 0; q < 21; ++q) U[q] = T(0);
+#pragma unroll
+    for (int q = 0; q < 18; ++q) W[q] = T(0);
+    double g6[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int row = 0; row < 3; ++row) {
+      T a[3], jc[6], jp[3];
+      A.row(row, a);
+      jc[0] = a[0]; jc[1] = a[1]; jc[2] = a[2];
+      cross3(Xt, a, jc + 3);
+      rot_tmul(cm, a, jp);
+#pragma unroll
+      for (int p = 0; p < 6; ++p) {
+#pragma unroll
+        for (int q = p; q < 6; ++q) U[sym6(p, q)] += wt * jc[p] * jc[q];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) W[3 * p + q] += wt * jc[p] * jp[q];
+      }
+      if constexpr (!ADJ) {
+        const double we = double(wt) * e[row];
+#pragma unroll
+        for (int p = 0; p < 6; ++p) g6[p] += we * double(jc[p]);
+      }
+    }
+    // W Vinv W^T and W hp
+    T vi[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) vi[q] = Vinv[6 * r + q];
+    const double h0 = hp[3 * r], h1 = hp[3 * r + 1], h2 = hp[3 * r + 2];
+    T WV[18];
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        WV[3 * p + q] = W[3 * p] * vi[sym3(0, q)] + W[3 * p + 1] * vi[sym3(1, q)] +
+                        W[3 * p + 2] * vi[sym3(2, q)];
+      acc[42 + p] += g6[p];
+      acc[48 + p] += double(W[3 * p]) * h0 + double(W[3 * p + 1]) * h1 + double(W[3 * p + 2]) * h2;
+    }
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+#pragma unroll
+      for (int q = p; q < 6; ++q) {
+        acc[sym6(p, q)] += double(U[sym6(p, q)]);
+        acc[21 + sym6(p, q)] += double(WV[3 * p] * W[3 * q] + WV[3 * p + 1] * W[3 * q + 1] +
+                                       WV[3 * p + 2] * W[3 * q + 2]);
+      }
+    }
+  }
+  block_sum<double, K>(acc, smem);
+  if (threadIdx.x != 0) return;
+  double Us[21], Sc[21];
+#pragma unroll
+  for (int q = 0; q < 21; ++q) {
+    Uraw[21 * s + q] = acc[q];
+    Us[q] = acc[q];
+  }
+#pragma unroll
+  for (int p = 0; p < 6; ++p) {
+    const int d = sym6(p, p);
+    Us[d] += lam * fmin(fmax(acc[d], dmin), dmax);
+  }
+#pragma unroll
+  for (int q = 0; q < 21; ++q) {
+    Ustar[21 * s + q] = T(Us[q]);
+    Sc[q] = Us[q] - acc[21 + q];
+  }
+#pragma unroll
+  for (int p = 0; p < 6; ++p) {
+    gc[6 * s + p] = acc[42 + p];
+    const double rhs = rhs_c ? rhs_c[6 * s + p] : -acc[42 + p];
+    b[6 * s + p] = rhs - acc[48 + p];
+  }
+  double inv[21];
+  if (!spd6_inverse(Sc, inv)) {
+    // block not positive definite (rounding at tiny damping): Jacobi fallback on U*
+#pragma unroll
+    for (int q = 0; q < 21; ++q) inv[q] = 0.0;
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+      const double d = Us[sym6(p, p)];
+      inv[sym6(p, p)] = d > 0.0 ? 1.0 / d : 0.0;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 21; ++q) Minv[21 * s + q] = inv[q];
+}
+
+// ------------------------------------------------------------------ PCG
+__device__ __forceinline__ void sym6_mul(const double* M, const double* x, double* y) {
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    double a = 0.0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) a += M[sym6(i, j)] * x[j];
+    y[i] = a;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024)
+k_pcg_init(int Ca, const double* __restrict__ b, const double* __restrict__ Minv,
+           double* __restrict__ x, double* __restrict__ r, double* __restrict__ z,
+           double* __restrict__ p, T* __restrict__ pt, PcgState* st, double tol2, int max_iter) {
+  __shared__ double smem[2 * (1024 / kWave)];
+  double acc[2] = {0.0, 0.0};   // r.z, b.b
+  for (int s = threadIdx.x; s < Ca; s += blockDim.x) {
+    double rv[6], zv[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      rv[i] = b[6 * s + i];
+      x[6 * s + i] = 0.0;
+      r[6 * s + i] = rv[i];
+    }
+    sym6_mul(Minv + 21 * s, rv, zv);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      z[6 * s + i] = zv[i];
+      p[6 * s + i] = zv[i];
+      pt[6 * s + i] = T(zv[i]);
+      acc[0] += rv[i] * zv[i];
+      acc[1] += rv[i] * rv[i];
+    }
+  }
+  block_sum<double, 2>(acc, smem);
+  if (threadIdx.x == 0) {
+    st->rz = acc[0];
+    st->bb = acc[1];
+    st->rr = acc[1];
+    st->tol2 = tol2;
+    st->iter = 0;
+    st->max_iter = max_iter;
+    st->breakdown = 0;
+    st->done = (acc[1] == 0.0 || max_iter <= 0) ? 1 : 0;
+    if (!isfinite(acc[0]) || !isfinite(acc[1])) {
+      st->breakdown = 1;
+      st->done = 1;
+    }
+  }
+}
+
+template <typename T, bool ADJ>
+__global__ void __launch_bounds__(kBlock)
+k_schur_point(Model m, Compact<T> cp, ObsMetric<T> om, const T* __restrict__ Vinv,
+              const T* __restrict__ pvec, T* __restrict__ zq, const PcgState* __restrict__ st) {
+  if (st->done) return;
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= cp.Pa) return;
+  const T X0 = cp.Xt[3 * r], X1 = cp.Xt[3 * r + 1], X2 = cp.Xt[3 * r + 2];
+  T y[3] = {T(0), T(0), T(0)};
+  for (int j = cp.off[r]; j < cp.off[r + 1]; ++j) {
+    const int c = cp.cam[j];
+    const int sl = cp.slot[c];
+    if (sl < 0) continue;
+    const Cam<T>& cm = cp.camt[c];
+    T Xc[3];
+    cam_frame(cm, X0, X1, X2, Xc);
+    AMat<T, ADJ> A;
+    A.set(cm.f, T(m.lam_d), Xc);
+    if constexpr (ADJ) A.project(om.eh + 3 * j);
+    const T* pv = pvec + 6 * sl;
+    T om3[3], d[3], t[3], mm[3], rt[3];
+    const T w3[3] = {pv[3], pv[4], pv[5]};
+    cross3(w3, Xc, om3);
+    d[0] = pv[0] + om3[0];
+    d[1] = pv[1] + om3[1];
+    d[2] = pv[2] + om3[2];
+    A.apply(d, t);
+    A.applyT(t, mm);
+    const T w = om.w[j];
+    mm[0] *= w; mm[1] *= w; mm[2] *= w;
+    rot_tmul(cm, mm, rt);
+    y[0] += rt[0];
+    y[1] += rt[1];
+    y[2] += rt[2];
+  }
+  const T* vi = Vinv + 6 * r;
+  zq[3 * r] = vi[0] * y[0] + vi[1] * y[1] + vi[2] * y[2];
+  zq[3 * r + 1] = vi[1] * y[0] + vi[3] * y[1] + vi[4] * y[2];
+  zq[3 * r + 2] = vi[2] * y[0] + vi[4] * y[1] + vi[5] * y[2];
+}
+
+template <typename T, bool ADJ>
+__global__ void __launch_bounds__(kBlock)
+k_schur_cam(Model m, Compact<T> cp, ObsMetric<T> om, const T* __restrict__ Ustar,
+            const T* __restrict__ pvec, const double* __restrict__ p64,
+            const T* __restrict__ zq, double* __restrict__ q, double* __restrict__ pq_part,
+            const PcgState* __restrict__ st) {
+  if (st->done) return;
+  __shared__ T smem[6 * (kBlock / kWave)];
+  const int s = blockIdx.x;
+  const Cam<T> cm = cp.camt[cp.cam_src[s]];
+  T acc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+  for (int i = cp.cm_off[s] + threadIdx.x; i < cp.cm_off[s + 1]; i += blockDim.x) {
+    const int r = cp.cm_pt[i];
+    T Xc[3];
+    cam_frame(cm, cp.Xt[3 * r], cp.Xt[3 * r + 1], cp.Xt[3 * r + 2], Xc);
+    AMat<T, ADJ> A;
+    A.set(cm.f, T(m.lam_d), Xc);
+    if constexpr (ADJ) A.project(om.cm_eh + 3 * i);
+    const T zv[3] = {zq[3 * r], zq[3 * r + 1], zq[3 * r + 2]};
+    T u[3], t[3], mm[3], xm[3];
+    rot_mul(cm, zv, u);
+    A.apply(u, t);
+    A.applyT(t, mm);
+    const T w = om.cm_w[i];
+    mm[0] *= w; mm[1] *= w; mm[2] *= w;
+    cross3(Xc, mm, xm);
+    acc[0] += mm[0]; acc[1] += mm[1]; acc[2] += mm[2];
+    acc[3] += xm[0]; acc[4] += xm[1]; acc[5] += xm[2];
+  }
+  block_sum<T, 6>(acc, smem);
+  if (threadIdx.x != 0) return;
+  double pv[6], qv[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) pv[i] = p64[6 * s + i];
+  double pq = 0.0;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    double a = 0.0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) a += double(Ustar[21 * s + sym6(i, j)]) * pv[j];
+    qv[i] = a - double(acc[i]);
+    q[6 * s + i] = qv[i];
+    pq += pv[i] * qv[i];
+  }
+  pq_part[s] = pq;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024)
+k_pcg_update(int Ca, const double* __restrict__ Minv, const double* __restrict__ q,
+             const double* __restrict__ pq_part, double* __restrict__ x, double* __restrict__ r,
+             double* __restrict__ z, double* __restrict__ p, T* __restrict__ pt, PcgState* st) {
+  __shared__ double smem[2 * (1024 / kWave)];
+  __shared__ double s_bcast[2];
+  __shared__ int s_done;
+  if (threadIdx.x == 0) s_done = st->done;
+  __syncthreads();
+  if (s_done) return;
+  double acc1[1] = {0.0};
+  for (int s = threadIdx.x; s < Ca; s += blockDim.x) acc1[0] += pq_part[s];
+  block_sum<double, 1>(acc1, smem);
+  if (threadIdx.x == 0) {
+    const double pq = acc1[0];
+    int bad = !(pq > 0.0) || !isfinite(pq);
+    s_bcast[0] = bad ? 0.0 : st->rz / pq;
+    s_done = bad;
+    if (bad) {
+      st->breakdown = 1;
+      st->done = 1;
+    }
+  }
+  __syncthreads();
+  if (s_done) return;
+  const double alpha = s_bcast[0];
+  double acc[2] = {0.0, 0.0};   // r.r, r.z
+  for (int s = threadIdx.x; s < Ca; s += blockDim.x) {
+    double rv[6], zv[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      x[6 * s + i] += alpha * p[6 * s + i];
+      rv[i] = r[6 * s + i] - alpha * q[6 * s + i];
+      r[6 * s + i] = rv[i];
+    }
+    sym6_mul(Minv + 21 * s, rv, zv);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      z[6 * s + i] = zv[i];
+      acc[0] += rv[i] * rv[i];
+      acc[1] += rv[i] * zv[i];
+    }
+  }
+  block_sum<double, 2>(acc, smem);
+  if (threadIdx.x == 0) {
+    const double beta = acc[1] / st->rz;
+    s_bcast[1] = beta;
+    st->rz = acc[1];
+    st->rr = acc[0];
+    st->iter += 1;
+    int done = (acc[0] <= st->tol2 * st->bb) || (st->iter >= st->max_iter);
+    if (!isfinite(acc[0]) || !isfinite(acc[1])) {
+      st->breakdown = 1;
+      done = 1;
+    }
+    st->done = done;
+  }
+  __syncthreads();
+  const double beta = s_bcast[1];
+  for (int s = threadIdx.x; s < Ca; s += blockDim.x) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      const double pv = z[6 * s + i] + beta * p[6 * s + i];
+      p[6 * s + i] = pv;
+      pt[6 * s + i] = T(pv);
+    }
+  }
+}
+
+template <typename T, bool ADJ>
+__global__ void __launch_bounds__(kBlock)
+k_backsub(Model m, Compact<T> cp, ObsMetric<T> om, const T* __restrict__ Vinv,
+          const double* __restrict__ x, const double* __restrict__ gp,
+          const double* __restrict__ rhs_p, double* __restrict__ dp) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= cp.Pa) return;
+  const T X0 = cp.Xt[3 * r], X1 = cp.Xt[3 * r + 1], X2 = cp.Xt[3 * r + 2];
+  T y[3] = {T(0), T(0), T(0)};
+  for (int j = cp.off[r]; j < cp.off[r + 1]; ++j) {
+    const int c = cp.cam[j];
+    const int sl = cp.slot[c];
+    if (sl < 0) continue;
+    const Cam<T>& cm = cp.camt[c];
+    T Xc[3];
+    cam_frame(cm, X0, X1, X2, Xc);
+    AMat<T, ADJ> A;
+    A.set(cm.f, T(m.lam_d), Xc);
+    if constexpr (ADJ) A.project(om.eh + 3 * j);
+    const double* xv = x + 6 * sl;
+    const T w3[3] = {T(xv[3]), T(xv[4]), T(xv[5])};
+    T om3[3], d[3], t[3], mm[3], rt[3];
+    cross3(w3, Xc, om3);
+    d[0] = T(xv[0]) + om3[0];
+    d[1] = T(xv[1]) + om3[1];
+    d[2] = T(xv[2]) + om3[2];
+    A.apply(d, t);
+    A.applyT(t, mm);
+    const T w = om.w[j];
+    mm[0] *= w; mm[1] *= w; mm[2] *= w;
+    rot_tmul(cm, mm, rt);
+    y[0] += rt[0]; y[1] += rt[1]; y[2] += rt[2];
+  }
+  double b[3];
+  for (int i = 0; i < 3; ++i) b[i] = (rhs_p ? rhs_p[3 * r + i] : -gp[3 * r + i]) - double(y[i]);
+  const T* vi = Vinv + 6 * r;
+  dp[3 * r] = double(vi[0]) * b[0] + double(vi[1]) * b[1] + double(vi[2]) * b[2];
+  dp[3 * r + 1] = double(vi[1]) * b[0] + double(vi[3]) * b[1] + double(vi[4]) * b[2];
+  dp[3 * r + 2] = double(vi[2]) * b[0] + double(vi[4]) * b[1] + double(vi[5]) * b[2];
+}
+
+// ------------------------------------------------------------------ candidate
+// Left SE(3) update of a (quaternion, centre) camera: q' = q(phi) (x) q, c' = c - R'^T V rho.
+__global__ void __launch_bounds__(kBlock)
+k_cam_candidate(int C, const int* __restrict__ slot, const double* __restrict__ x,
+                const double* __restrict__ cams, const double* __restrict__ intr,
+                const Cam<double>* __restrict__ camd, double* __restrict__ cand_cams,
+                Cam<double>* __restrict__ cand_tab) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  const int sl = slot[c];
+  if (sl < 0) {
+    for (int i = 0; i < 7; ++i) cand_cams[7 * c + i] = cams[7 * c + i];
+    cand_tab[c] = camd[c];
+    return;
+  }
+  const double* xi = x + 6 * sl;
+  const double rho[3] = {xi[0], xi[1], xi[2]};
+  const double phi[3] = {xi[3], xi[4], xi[5]};
+  const double t2 = phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2];
+  const double th = sqrt(t2);
+  double bco, cco, hco, cw;
+  if (th < 1e-2) {   // Taylor series where the closed forms lose digits
+    bco = 0.5 - t2 / 24.0 + t2 * t2 / 720.0;
+    cco = 1.0 / 6.0 - t2 / 120.0 + t2 * t2 / 5040.0;
+    hco = 0.5 - t2 / 48.0 + t2 * t2 / 3840.0;
+  } else {
+    bco = (1.0 - cos(th)) / t2;
+    cco = (th - sin(th)) / (t2 * th);
+    hco = sin(0.5 * th) / th;
+  }
+  cw = cos(0.5 * th);
+  // q' = (cw, hco phi) (x) q
+  double qw = cams[7 * c], qx = cams[7 * c + 1], qy = cams[7 * c + 2], qz = cams[7 * c + 3];
+  double n = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+  qw /= n; qx /= n; qy /= n; qz /= n;
+  const double aw = cw, ax = hco * phi[0], ay = hco * phi[1], az = hco * phi[2];
+  double nw = aw * qw - ax * qx - ay * qy - az * qz;
+  double nx = aw * qx + qw * ax + (ay * qz - az * qy);
+  double ny = aw * qy + qw * ay + (az * qx - ax * qz);
+  double nz = aw * qz + qw * az + (ax * qy - ay * qx);
+  n = sqrt(nw * nw + nx * nx + ny * ny + nz * nz);
+  nw /= n; nx /= n; ny /= n; nz /= n;
+  Cam<double> d;
+  d.R[0] = 1 - 2 * (ny * ny + nz * nz);
+  d.R[1] = 2 * (nx * ny - nw * nz);
+  d.R[2] = 2 * (nx * nz + nw * ny);
+  d.R[3] = 2 * (nx * ny + nw * nz);
+  d.R[4] = 1 - 2 * (nx * nx + nz * nz);
+  d.R[5] = 2 * (ny * nz - nw * nx);
+  d.R[6] = 2 * (nx * nz - nw * ny);
+  d.R[7] = 2 * (ny * nz + nw * nx);
+  d.R[8] = 1 - 2 * (nx * nx + ny * ny);
+  double pr[3], ppr[3], vr[3];
+  cross3(phi, rho, pr);
+  cross3(phi, pr, ppr);
+  for (int i = 0; i < 3; ++i) vr[i] = rho[i] + bco * pr[i] + cco * ppr[i];
+  double rv[3];
+  rot_tmul(d, vr, rv);
+  d.c[0] = cams[7 * c + 4] - rv[0];
+  d.c[1] = cams[7 * c + 5] - rv[1];
+  d.c[2] = cams[7 * c + 6] - rv[2];
+  d.f = intr[3 * c];
+  d.cx = intr[3 * c + 1];
+  d.cy = intr[3 * c + 2];
+  cand_tab[c] = d;
+  cand_cams[7 * c] = nw;
+  cand_cams[7 * c + 1] = nx;
+  cand_cams[7 * c + 2] = ny;
+  cand_cams[7 * c + 3] = nz;
+  cand_cams[7 * c + 4] = d.c[0];
+  cand_cams[7 * c + 5] = d.c[1];
+  cand_cams[7 * c + 6] = d.c[2];
+}
+
+// Candidate cost (float64) over the same active observations, the quadratic term of the
+// model decrease sum w |J delta|^2 (float64 Jacobian at the linearisation point), g_p.dp,
+// and the number of candidate depths <= min_depth.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_point_candidate(Model m, Compact<T> cp, const Cam<double>* __restrict__ cand_tab,
+                  const double* __restrict__ x, const double* __restrict__ dp,
+                  const double* __restrict__ gp, const T* __restrict__ w,
+                  double* __restrict__ Xcand, double* __restrict__ partials) {
+  __shared__ double smem[4 * (kBlock / kWave)];
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};   // cost', quad, g_p.dp, bad
+  if (r < cp.Pa) {
+    const double X[3] = {cp.Xd[3 * r], cp.Xd[3 * r + 1], cp.Xd[3 * r + 2]};
+    const double d[3] = {dp[3 * r], dp[3 * r + 1], dp[3 * r + 2]};
+    const double Xn[3] = {X[0] + d[0], X[1] + d[1], X[2] + d[2]};
+    Xcand[3 * r] = Xn[0];
+    Xcand[3 * r + 1] = Xn[1];
+    Xcand[3 * r + 2] = Xn[2];
+    acc[2] = gp[3 * r] * d[0] + gp[3 * r + 1] * d[1] + gp[3 * r + 2] * d[2];
+    for (int j = cp.off[r]; j < cp.off[r + 1]; ++j) {
+      const int c = cp.cam[j];
+      const Cam<double> cn = cand_tab[c];
+      double Xc[3];
+      cam_frame(cn, Xn[0], Xn[1], Xn[2], Xc);
+      if (!(Xc[2] > m.min_depth)) {
+        acc[3] += 1.0;
+      } else {
+        double e[3], rho, d1, d2;
+        residual(cn, Xc, cp.xy[j], cp.depth[j], m.lam_d, e);
+        huber(e[0] * e[0] + e[1] * e[1] + e[2] * e[2], m.huber, rho, d1, d2);
+        acc[0] += 0.5 * rho;
+      }
+      // model term at the linearisation point
+      const Cam<double> cm = cp.camd[c];
+      double Xl[3], v[3], t[3];
+      cam_frame(cm, X[0], X[1], X[2], Xl);
+      rot_mul(cm, d, v);
+      const int sl = cp.slot[c];
+      if (sl >= 0) {
+        const double* xv = x + 6 * sl;
+        const double w3[3] = {xv[3], xv[4], xv[5]};
+        double o3[3];
+        cross3(w3, Xl, o3);
+        v[0] += xv[0] + o3[0];
+        v[1] += xv[1] + o3[1];
+        v[2] += xv[2] + o3[2];
+      }
+      AMat<double, false> A;
+      A.set(cm.f, m.lam_d, Xl);
+      A.apply(v, t);
+      acc[1] += double(w[j]) * (t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+    }
+  }
+  block_sum<double, 4>(acc, smem);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) partials[4 * blockIdx.x + i] = acc[i];
+  }
+}
+
+__global__ void __launch_bounds__(1024)
+k_reduce_partials(int nb, int K, const double* __restrict__ partials, unsigned max_mask,
+                  int Ca, const double* __restrict__ gc, const double* __restrict__ x,
+                  double* __restrict__ out) {
+  __shared__ double smem[8 * (1024 / kWave)];
+  double acc[8];
+  for (int k = 0; k < 8; ++k) acc[k] = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    for (int k = 0; k < K; ++k) {
+      const double v = partials[K * b + k];
+      acc[k] = ((max_mask >> k) & 1u) ? fmax(acc[k], v) : acc[k] + v;
+    }
+  }
+  if (gc) {
+    for (int s = threadIdx.x; s < Ca; s += blockDim.x)
+      for (int i = 0; i < 6; ++i) acc[K] += gc[6 * s + i] * x[6 * s + i];
+  }
+  // fixed-order reduction: sums via wave_sum, maxima via wave_max
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  for (int k = 0; k <= K && k < 8; ++k)
+    acc[k] = ((max_mask >> k) & 1u) ? wave_max(acc[k]) : wave_sum(acc[k]);
+  if (lane == 0)
+    for (int k = 0; k < 8; ++k) smem[8 * wid + k] = acc[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 0; k <= K && k < 8; ++k) {
+      double a = smem[k];
+      for (int w = 1; w < int(blockDim.x) / kWave; ++w)
+        a = ((max_mask >> k) & 1u) ? fmax(a, smem[8 * w + k]) : a + smem[8 * w + k];
+      out[k] = a;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_scatter(int Pa, int C, const int* __restrict__ pt_src, const double* __restrict__ Xcand,
+          const int* __restrict__ slot, const double* __restrict__ cand_cams,
+          double* __restrict__ pts, double* __restrict__ cams) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < Pa) {
+    const int p = pt_src[i];
+    pts[3 * p] = Xcand[3 * i];
+    pts[3 * p + 1] = Xcand[3 * i + 1];
+    pts[3 * p + 2] = Xcand[3 * i + 2];
+  }
+  if (i < C && slot[i] >= 0) {
+    for (int k = 0; k < 7; ++k) cams[7 * i + k] = cand_cams[7 * i + k];
+  }
+}
+
+// ------------------------------------------------------------------ adjoint
+// Tangent mapping of camera gradients: dL/drho = -R dL/dc, dL/dphi = (dq/dphi)^T dL/dq with
+// dq/dphi = 1/2 [-q_v^T ; q_w I - [q_v]x].
+__global__ void __launch_bounds__(kBlock)
+k_adjoint_rhs(int Ca, int Pa, const int* __restrict__ cam_src, const double* __restrict__ cams,
+              const double* __restrict__ grad_cams, const int* __restrict__ pt_src,
+              const int* __restrict__ pt_user, const double* __restrict__ grad_pts,
+              double* __restrict__ rhs_c, double* __restrict__ rhs_p) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < Ca) {
+    const int c = cam_src[i];
+    double qw = cams[7 * c], qx = cams[7 * c + 1], qy = cams[7 * c + 2], qz = cams[7 * c + 3];
+    const double n = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+    qw /= n; qx /= n; qy /= n; qz /= n;
+    Cam<double> d;
+    d.R[0] = 1 - 2 * (qy * qy + qz * qz);
+    d.R[1] = 2 * (qx * qy - qw * qz);
+    d.R[2] = 2 * (qx * qz + qw * qy);
+    d.R[3] = 2 * (qx * qy + qw * qz);
+    d.R[4] = 1 - 2 * (qx * qx + qz * qz);
+    d.R[5] = 2 * (qy * qz - qw * qx);
+    d.R[6] = 2 * (qx * qz - qw * qy);
+    d.R[7] = 2 * (qy * qz + qw * qx);
+    d.R[8] = 1 - 2 * (qx * qx + qy * qy);
+    const double* g = grad_cams + 7 * c;
+    const double gcn[3] = {g[4], g[5], g[6]};
+    double rg[3];
+    rot_mul(d, gcn, rg);
+    const double qv[3] = {qx, qy, qz}, gv[3] = {g[1], g[2], g[3]};
+    double cx[3];
+    cross3(qv, gv, cx);
+    for (int k = 0; k < 3; ++k) {
+      rhs_c[6 * i + k] = -rg[k];
+      rhs_c[6 * i + 3 + k] = 0.5 * (-g[0] * qv[k] + qw * gv[k] + cx[k]);
+    }
+  }
+  if (i < Pa) {
+    const int u = pt_user[pt_src[i]];
+    rhs_p[3 * i] = grad_pts[3 * u];
+    rhs_p[3 * i + 1] = grad_pts[3 * u + 1];
+    rhs_p[3 * i + 2] = grad_pts[3 * u + 2];
+  }
+}
+
+// Per observation: t = J v, u = M t = w (I - eh eh^T) t; dL/dx = u[0:2],
+// dL/dd_hat = -u[2] lam_d m / d_hat^2.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_adjoint_obs(Model m, Compact<T> cp, ObsMetric<T> om, const double* __restrict__ x,
+              const double* __restrict__ dp, const int* __restrict__ orig,
+              float* __restrict__ gxy, float* __restrict__ gdepth) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= cp.Pa) return;
+  const double X0 = cp.Xd[3 * r], X1 = cp.Xd[3 * r + 1], X2 = cp.Xd[3 * r + 2];
+  const double vp[3] = {dp[3 * r], dp[3 * r + 1], dp[3 * r + 2]};
+  for (int j = cp.off[r]; j < cp.off[r + 1]; ++j) {
+    const int c = cp.cam[j];
+    const Cam<double> cm = cp.camd[c];
+    double Xc[3], d[3], t[3];
+    cam_frame(cm, X0, X1, X2, Xc);
+    rot_mul(cm, vp, d);
+    const int sl = cp.slot[c];
+    if (sl >= 0) {
+      const double* xv = x + 6 * sl;
+      const double w3[3] = {xv[3], xv[4], xv[5]};
+      double o3[3];
+      cross3(w3, Xc, o3);
+      d[0] += xv[0] + o3[0];
+      d[1] += xv[1] + o3[1];
+      d[2] += xv[2] + o3[2];
+    }
+    AMat<double, true> A;
+    A.set(cm.f, m.lam_d, Xc);
+    const double eh[3] = {double(om.eh[3 * j]), double(om.eh[3 * j + 1]),
+                          double(om.eh[3 * j + 2])};
+    A.project(eh);
+    A.apply(d, t);
+    const double w = double(om.w[j]);
+    const int o = orig[j];
+    gxy[2 * o] = float(w * t[0]);
+    gxy[2 * o + 1] = float(w * t[1]);
+    const float dh = cp.depth[j];
+    const double dinv = dh > 0.0f ? 1.0 / double(dh) : 0.0;
+    gdepth[o] = float(-w * t[2] * m.lam_d * dinv * dinv);
+  }
+}
+
+inline unsigned blocks_for(int64_t n, int b = kBlock) { return unsigned((n + b - 1) / b); }
+
+}  // namespace
+
+// ================================================================== launchers
+void launch_cam_table(hipStream_t s, int C, const double* cams, const double* intr,
+                      Cam<double>* camd, Cam<float>* camf) {
+  hipLaunchKernelGGL(k_cam_table, dim3(blocks_for(C)), dim3(kBlock), 0, s, C, cams, intr, camd,
+                     camf);
+}
+
+void launch_validate(hipStream_t s, int64_t N, const Model& m, const int* pm_cam,
+                     const int* pm_pt, const float2* xy, const float* depth,
+                     const double* pts, const Cam<double>* camd, uint8_t* vrow) {
+  if (N == 0) return;
+  hipLaunchKernelGGL(k_validate, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, m, pm_cam, pm_pt,
+                     xy, depth, pts, camd, vrow);
+}
+
+void launch_cam_rows(hipStream_t s, int C, const int* cm_off, const int* cm_perm,
+                     const uint8_t* vrow, const uint8_t* fixed, int need, uint8_t* act_c) {
+  hipLaunchKernelGGL(k_cam_rows, dim3(C), dim3(kBlock), 0, s, cm_off, cm_perm, vrow, fixed,
+                     need, act_c);
+}
+
+void launch_point_rows_prune(hipStream_t s, int P, const int* pt_off, const int* pm_cam,
+                             const uint8_t* act_c, const uint8_t* fixed, int need,
+                             uint8_t* vrow, uint8_t* act_p, int* changed) {
+  hipLaunchKernelGGL(k_point_rows_prune, dim3(blocks_for(P)), dim3(kBlock), 0, s, P, pt_off,
+                     pm_cam, act_c, fixed, need, vrow, act_p, changed);
+}
+
+int64_t scan_tmp_ints(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
+void launch_scan_u8(hipStream_t s, int64_t n, const uint8_t* flags, int* out, int* tmp) {
+  scan_impl(s, n, FlagU8{flags}, out, tmp);
+}
+
+void launch_scan_cm(hipStream_t s, int64_t n, const int* cm_perm, const uint8_t* vrow,
+                    const int* pm_cam, const uint8_t* fixed, int* out, int* tmp) {
+  scan_impl(s, n, FlagCM{cm_perm, vrow, pm_cam, fixed}, out, tmp);
+}
+
+void launch_compact_points(hipStream_t s, int P, const uint8_t* act_p, const int* rank_p,
+                           const int* pt_off, const int* pos_pm, const double* pts,
+                           int* pt_src, int* off_hat, double* Xd, float* Xf) {
+  hipLaunchKernelGGL(k_compact_points, dim3(blocks_for(P)), dim3(kBlock), 0, s, P, act_p,
+                     rank_p, pt_off, pos_pm, pts, pt_src, off_hat, Xd, Xf);
+}
+
+void launch_compact_obs(hipStream_t s, int64_t N, const uint8_t* vrow, const int* pos_pm,
+                        const int* pm_cam, const float2* pm_xy, const float* pm_depth,
+                        const int* pm_orig, int* cam_hat, float2* xy_hat, float* depth_hat,
+                        int* orig_hat) {
+  if (N == 0) return;
+  hipLaunchKernelGGL(k_compact_obs, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, vrow, pos_pm,
+                     pm_cam, pm_xy, pm_depth, pm_orig, cam_hat, xy_hat, depth_hat, orig_hat);
+}
+
+void launch_compact_cams(hipStream_t s, int C, const uint8_t* act_c, const int* rank_c,
+                         const int* cm_off, const int* pos_cm, int* slot, int* cam_src,
+                         int* cm_off_hat) {
+  hipLaunchKernelGGL(k_compact_cams, dim3(blocks_for(C)), dim3(kBlock), 0, s, C, act_c, rank_c,
+                     cm_off, pos_cm, slot, cam_src, cm_off_hat);
+}
+
+void launch_compact_cm(hipStream_t s, int64_t N, const int* cm_perm, const uint8_t* vrow,
+                       const int* pm_cam, const int* pm_pt, const uint8_t* fixed,
+                       const int* pos_cm, const int* pos_pm, const int* rank_p, int* cm_pt,
+                       int* cm_pm) {
+  if (N == 0) return;
+  hipLaunchKernelGGL(k_compact_cm, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, cm_perm, vrow,
+                     pm_cam, pm_pt, fixed, pos_cm, pos_pm, rank_p, cm_pt, cm_pm);
+}
+
+template <typename T>
+void launch_lin_point(hipStream_t s, bool adj, const Model& m, const Compact<T>& cp,
+                      ObsMetric<T> om, T* V, double* gp, double* partials) {
+  const unsigned nb = blocks_for(cp.Pa);
+  if (adj)
+    hipLaunchKernelGGL((k_lin_point<T, true>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, V, gp,
+                       partials);
+  else
+    hipLaunchKernelGGL((k_lin_point<T, false>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, V, gp,
+                       partials);
+}
+
+template <typename T>
+void launch_gather_cm_metric(hipStream_t s, bool adj, int64_t Nc, const int* cm_pm,
+                             ObsMetric<T> om) {
+  if (Nc == 0) return;
+  if (adj)
+    hipLaunchKernelGGL((k_gather_cm_metric<T, true>), dim3(blocks_for(Nc)), dim3(kBlock), 0, s,
+                       Nc, cm_pm, om);
+  else
+    hipLaunchKernelGGL((k_gather_cm_metric<T, false>), dim3(blocks_for(Nc)), dim3(kBlock), 0,
+                       s, Nc, cm_pm, om);
+}
+
+template <typename T>
+void launch_point_damp(hipStream_t s, int Pa, double lam, double dmin, double dmax,
+                       const T* V, const double* gp, const double* rhs_p, T* Vinv,
+                       double* hp, int* bad) {
+  hipLaunchKernelGGL(k_point_damp<T>, dim3(blocks_for(Pa)), dim3(kBlock), 0, s, Pa, lam, dmin,
+                     dmax, V, gp, rhs_p, Vinv, hp, bad);
+}
+
+template <typename T>
+void launch_cam_assemble(hipStream_t s, bool adj, const Model& m, const Compact<T>& cp,
+                         ObsMetric<T> om, double lam, double dmin, double dmax,
+                         const T* Vinv, const double* hp, const double* rhs_c,
+                         double* Uraw, T* Ustar, double* gc, double* b, double* Minv) {
+  if (cp.Ca == 0) return;
+  if (adj)
+    hipLaunchKernelGGL((k_cam_assemble<T, true>), dim3(cp.Ca), dim3(kBlock), 0, s, m, cp, om,
+                       lam, dmin, dmax, Vinv, hp, rhs_c, Uraw, Ustar, gc, b, Minv);
+  else
+    hipLaunchKernelGGL((k_cam_assemble<T, false>), dim3(cp.Ca), dim3(kBlock), 0, s, m, cp, om,
+                       lam, dmin, dmax, Vinv, hp, rhs_c, Uraw, Ustar, gc, b, Minv);
+}
+
+template <typename T>
+void launch_pcg_init(hipStream_t s, int Ca, const double* b, const double* Minv, double* x,
+                     double* r, double* z, double* p, T* pt, PcgState* st, double tol2,
+                     int max_iter) {
+  hipLaunchKernelGGL(k_pcg_init<T>, dim3(1), dim3(1024), 0, s, Ca, b, Minv, x, r, z, p, pt, st,
+                     tol2, max_iter);
+}
+
+template <typename T>
+void launch_schur_point(hipStream_t s, bool adj, const Model& m, const Compact<T>& cp,
+                        ObsMetric<T> om, const T* Vinv, const T* pvec, T* zq,
+                        const PcgState* st) {
+  const unsigned nb = blocks_for(cp.Pa);
+  if (adj)
+    hipLaunchKernelGGL((k_schur_point<T, true>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, Vinv,
+                       pvec, zq, st);
+  else
+    hipLaunchKernelGGL((k_schur_point<T, false>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, Vinv,
+                       pvec, zq, st);
+}
+
+template <typename T>
+void launch_schur_cam(hipStream_t s, bool adj, const Model& m, const Compact<T>& cp,
+                      ObsMetric<T> om, const T* Ustar, const T* pvec, const double* p64,
+                      const T* zq, double* q, double* pq_part, const PcgState* st) {
+  if (adj)
+    hipLaunchKernelGGL((k_schur_cam<T, true>), dim3(cp.Ca), dim3(kBlock), 0, s, m, cp, om, Ustar,
+                       pvec, p64, zq, q, pq_part, st);
+  else
+    hipLaunchKernelGGL((k_schur_cam<T, false>), dim3(cp.Ca), dim3(kBlock), 0, s, m, cp, om,
+                       Ustar, pvec, p64, zq, q, pq_part, st);
+}
+
+template <typename T>
+void launch_pcg_update(hipStream_t s, int Ca, const double* Minv, const double* q,
+                       const double* pq_part, double* x, double* r, double* z, double* p,
+                       T* pt, PcgState* st) {
+  hipLaunchKernelGGL(k_pcg_update<T>, dim3(1), dim3(1024), 0, s, Ca, Minv, q, pq_part, x, r, z,
+                     p, pt, st);
+}
+
+template <typename T>
+void launch_backsub(hipStream_t s, bool adj, const Model& m, const Compact<T>& cp,
+                    ObsMetric<T> om, const T* Vinv, const double* x, const double* gp,
+                    const double* rhs_p, double* dp) {
+  const unsigned nb = blocks_for(cp.Pa);
+  if (adj)
+    hipLaunchKernelGGL((k_backsub<T, true>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, Vinv, x,
+                       gp, rhs_p, dp);
+  else
+    hipLaunchKernelGGL((k_backsub<T, false>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, Vinv, x,
+                       gp, rhs_p, dp);
+}
+
+void launch_cam_candidate(hipStream_t s, int C, const int* slot, const double* x,
+                          const double* cams, const double* intr, const Cam<double>* camd,
+                          double* cand_cams, Cam<double>* cand_tab) {
+  hipLaunchKernelGGL(k_cam_candidate, dim3(blocks_for(C)), dim3(kBlock), 0, s, C, slot, x, cams,
+                     intr, camd, cand_cams, cand_tab);
+}
+
+template <typename T>
+void launch_point_candidate(hipStream_t s, const Model& m, const Compact<T>& cp,
+                            const Cam<double>* cand_tab, const double* x, const double* dp,
+                            const double* gp, const T* w, double* Xcand, double* partials) {
+  hipLaunchKernelGGL(k_point_candidate<T>, dim3(blocks_for(cp.Pa)), dim3(kBlock), 0, s, m, cp,
+                     cand_tab, x, dp, gp, w, Xcand, partials);
+}
+
+void launch_reduce_partials(hipStream_t s, int nblocks, int K, const double* partials,
+                            unsigned max_mask, int Ca, const double* gc, const double* x,
+                            double* out) {
+  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(1024), 0, s, nblocks, K, partials,
+                     max_mask, Ca, gc, x, out);
+}
+
+void launch_scatter(hipStream_t s, int Pa, int C, const int* pt_src, const double* Xcand,
+                    const int* slot, const double* cand_cams, double* pts, double* cams) {
+  const int n = Pa > C ? Pa : C;
+  hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n)), dim3(kBlock), 0, s, Pa, C, pt_src, Xcand,
+                     slot, cand_cams, pts, cams);
+}
+
+void launch_adjoint_rhs(hipStream_t s, int Ca, int Pa, const int* cam_src, const double* cams,
+                        const double* grad_cams, const int* pt_src, const int* pt_user,
+                        const double* grad_pts, double* rhs_c, double* rhs_p) {
+  const int n = Pa > Ca ? Pa : Ca;
+  hipLaunchKernelGGL(k_adjoint_rhs, dim3(blocks_for(n)), dim3(kBlock), 0, s, Ca, Pa, cam_src,
+                     cams, grad_cams, pt_src, pt_user, grad_pts, rhs_c, rhs_p);
+}
+
+template <typename T>
+void launch_adjoint_obs(hipStream_t s, const Model& m, const Compact<T>& cp, ObsMetric<T> om,
+                        const double* x, const double* dp, const int* orig, float* gxy,
+                        float* gdepth) {
+  hipLaunchKernelGGL(k_adjoint_obs<T>, dim3(blocks_for(cp.Pa)), dim3(kBlock), 0, s, m, cp, om,
+                     x, dp, orig, gxy, gdepth);
+}
+
+// explicit instantiations for the two precisions
+#define IBA_INSTANTIATE(T)                                                                    \
+  template void launch_lin_point<T>(hipStream_t, bool, const Model&, const Compact<T>&,       \
+                                    ObsMetric<T>, T*, double*, double*);                      \
+  template void launch_gather_cm_metric<T>(hipStream_t, bool, int64_t, const int*,            \
+                                           ObsMetric<T>);                                      \
+  template void launch_point_damp<T>(hipStream_t, int, double, double, double, const T*,      \
+                                     const double*, const double*, T*, double*, int*);        \
+  template void launch_cam_assemble<T>(hipStream_t, bool, const Model&, const Compact<T>&,    \
+                                       ObsMetric<T>, double, double, double, const T*,        \
+                                       const double*, const double*, double*, T*, double*,    \
+                                       double*, double*);                                      \
+  template void launch_pcg_init<T>(hipStream_t, int, const double*, const double*, double*,   \
+                                   double*, double*, double*, T*, PcgState*, double, int);    \
+  template void launch_schur_point<T>(hipStream_t, bool, const Model&, const Compact<T>&,     \
+                                      ObsMetric<T>, const T*, const T*, T*, const PcgState*); \
+  template void launch_schur_cam<T>(hipStream_t, bool, const Model&, const Compact<T>&,       \
+                                    ObsMetric<T>, const T*, const T*, const double*,          \
+                                    const T*, double*, double*, const PcgState*);             \
+  template void launch_pcg_update<T>(hipStream_t, int, const double*, const double*,          \
+                                     const double*, double*, double*, double*, double*, T*,   \
+                                     PcgState*);                                               \
+  template void launch_backsub<T>(hipStream_t, bool, const Model&, const Compact<T>&,         \
+                                  ObsMetric<T>, const T*, const double*, const double*,       \
+                                  const double*, double*);                                     \
+  template void launch_point_candidate<T>(hipStream_t, const Model&, const Compact<T>&,       \
+                                          const Cam<double>*, const double*, const double*,   \
+                                          const double*, const T*, double*, double*);         \
+  template void launch_adjoint_obs<T>(hipStream_t, const Model&, const Compact<T>&,           \
+                                      ObsMetric<T>, const double*, const double*, const int*, \
+                                      float*, float*);
+
+IBA_INSTANTIATE(float)
+IBA_INSTANTIATE(double)
+
+}  // namespace iba

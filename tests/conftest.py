@@ -11,3 +11,11 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: larger CPU cases")
+
+
+def pytest_sessionstart(session):
+    """Load what is built; build the HIP library only when none exists."""
+    from paper_2510_13310_amd import _abi
+    if not os.path.exists(_abi.LIB_PATH):
+        from paper_2510_13310_amd.build import build
+        build()

@@ -1,0 +1,74 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports every entry
+point declared in include/ba.h, and validates arguments before touching a device."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2510_13310_amd as P
+from paper_2510_13310_amd import _abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "ba.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ba_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = _abi.load()
+    names = _declared()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in _abi.EXPORTS, n
+
+
+def test_struct_sizes_match_header_layout():
+    import ctypes
+    # ba_options: 4 int32, 9 doubles, 2 int32, 3 doubles, 2 int32, pointer
+    assert ctypes.sizeof(_abi.BaOptions) == 4 * 4 + 9 * 8 + 2 * 4 + 3 * 8 + 2 * 4 + 8
+    assert ctypes.sizeof(_abi.BaKernelStat) == 32 + 8 + 8 + 8
+
+
+def test_default_options():
+    o = P.ba_default_options()
+    assert o.precision == P.BA_PRECISION_MIXED
+    assert (o.img_w, o.img_h) == (640, 480)
+    assert o.min_depth == 0.1 and o.lambda_init == 1e-3
+    assert o.pcg_max_iters == 100 and o.pcg_rel_tol == 1e-6
+    assert o.diag_min == 1e-6 and o.lambda_max == 1e12
+
+
+def test_argument_errors_before_device():
+    opts = P.ba_default_options()
+    with pytest.raises(P.BAError) as e:
+        P.ba_create(opts, 0, 5, np.zeros((0, 7)), np.zeros((0, 3)), np.zeros((5, 3)))
+    assert e.value.status == P.BA_ERR_ARG
+    opts.precision = 7
+    with pytest.raises(P.BAError) as e:
+        P.ba_create(opts, 1, 1, np.zeros((1, 7)), np.ones((1, 3)), np.zeros((1, 3)))
+    assert e.value.status == P.BA_ERR_ARG
+    assert "options" in P.ba_last_error(None)
+
+
+def test_create_without_gpu_reports_device_error():
+    cams = np.zeros((2, 7))
+    cams[:, 0] = 1
+    try:
+        h = P.ba_create(P.ba_default_options(), 2, 3, cams, np.ones((2, 3)), np.zeros((3, 3)))
+    except P.BAError as e:
+        assert e.status == P.BA_ERR_DEVICE
+        return
+    P.ba_destroy(h)
+    pytest.skip("a GPU is present: the no-device path does not apply")
+
+
+def test_null_context_is_rejected():
+    lib = _abi.load()
+    assert lib.ba_lm_step(None, None) == P.BA_ERR_ARG
+    lib.ba_destroy(None)
+    assert lib.ba_device_bytes(None) == 0
