@@ -70,7 +70,7 @@ typedef struct ba_options {
   double diag_min, diag_max;     /* clamp of the Marquardt diagonal diag(J^T J); 1e-6, 1e32 */
   double accept_ratio;     /* accept a step when the cost drops and gain ratio > this; 1e-3 */
   int32_t pcg_max_iters;   /* 100 */
-  int32_t pcg_check_every; /* PCG iterations enqueued between host convergence checks; 4 */
+  int32_t pcg_check_every; /* PCG iterations enqueued between host convergence checks; 8 */
   double pcg_rel_tol;      /* stop when |r| <= tol |b|; 1e-6 */
   double cost_rel_tol;     /* ba_solve: stop when an accepted step lowers the cost by at most
                               this fraction; 1e-10 */

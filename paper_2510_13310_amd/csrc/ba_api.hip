@@ -105,6 +105,7 @@ struct ba_ctx {
   std::vector<int32_t> pt_internal;  // caller -> internal
   std::vector<uint8_t> fixed_h;
   int n_fixed = 0;
+  int* d_fixed_rank = nullptr;       // rank of each fixed camera among the fixed ones
 
   // observations (point-major, full)
   bool have_obs = false, have_priors = false;
@@ -120,20 +121,22 @@ struct ba_ctx {
   int *rank_c = nullptr, *rank_p = nullptr, *pos_pm = nullptr, *pos_cm = nullptr;
   int *scan_tmp = nullptr, *flags = nullptr;   // flags[0] changed, flags[1] bad damping
   int *cam_hat = nullptr, *orig_hat = nullptr, *off_hat = nullptr, *pt_src = nullptr;
-  int *cam_src = nullptr, *slot = nullptr, *cm_off_hat = nullptr, *cm_pt = nullptr,
+  int *cam_src = nullptr, *slot_all = nullptr, *cm_off_hat = nullptr, *cm_pt = nullptr,
       *cm_pm = nullptr;
+  Cam<double>* camd_hat = nullptr;
+  Cam<float>* camf_hat = nullptr;
   float2* xy_hat = nullptr;
   float* depth_hat = nullptr;
   double* Xd = nullptr;
   float* Xf = nullptr;
 
   // precision-typed buffers (float in MIXED, double in FP64)
-  void *w = nullptr, *eh = nullptr, *cm_w = nullptr, *cm_eh = nullptr, *V = nullptr,
-       *Vinv = nullptr, *zq = nullptr, *Ustar = nullptr, *pT = nullptr;
+  void *w = nullptr, *eh = nullptr, *xcw = nullptr, *pm_xcw = nullptr, *cm_eh = nullptr,
+       *V = nullptr, *Vinv = nullptr, *zq = nullptr, *Ustar = nullptr, *mvt = nullptr;
   double *gp = nullptr, *hp = nullptr, *dp = nullptr, *Xcand = nullptr, *rhs_p = nullptr;
   double *Uraw = nullptr, *gc = nullptr, *b = nullptr, *Minv = nullptr, *rhs_c = nullptr;
-  double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr,
-         *pq_part = nullptr;
+  double *x = nullptr, *r = nullptr, *u = nullptr, *p = nullptr, *sv = nullptr,
+         *wv = nullptr, *dots = nullptr;
   double *partials = nullptr, *scal = nullptr;
   double *grad_cams_d = nullptr, *grad_pts_d = nullptr;
   float *gxy_d = nullptr, *gdepth_d = nullptr;
@@ -314,21 +317,24 @@ void alloc_obs_buffers(ba_ctx& c) {
   c.off_hat = A.alloc<int>(P + 1);
   c.pt_src = A.alloc<int>(P);
   c.cam_src = A.alloc<int>(C);
-  c.slot = A.alloc<int>(C);
+  c.slot_all = A.alloc<int>(C);
+  c.camd_hat = A.alloc<Cam<double>>(C);
+  c.camf_hat = A.alloc<Cam<float>>(C);
   c.cm_off_hat = A.alloc<int>(C + 1);
   c.cm_pt = A.alloc<int>(N);
   c.cm_pm = A.alloc<int>(N);
   c.Xd = A.alloc<double>(3 * size_t(P));
   c.Xf = A.alloc<float>(3 * size_t(P));
   c.w = A.alloc<char>(ts * N);
-  c.cm_w = A.alloc<char>(ts * N);
+  c.xcw = A.alloc<char>(4 * ts * N);
+  c.pm_xcw = A.alloc<char>(4 * ts * N);
   c.eh = nullptr;
   c.cm_eh = nullptr;
   c.V = A.alloc<char>(ts * 6 * P);
   c.Vinv = A.alloc<char>(ts * 6 * P);
-  c.zq = A.alloc<char>(ts * 3 * P);
+  c.zq = A.alloc<char>(4 * ts * P);
   c.Ustar = A.alloc<char>(ts * 21 * C);
-  c.pT = A.alloc<char>(ts * 6 * C);
+  c.mvt = A.alloc<char>(ts * 16 * C);
   c.gp = A.alloc<double>(3 * size_t(P));
   c.hp = A.alloc<double>(3 * size_t(P));
   c.dp = A.alloc<double>(3 * size_t(P));
@@ -341,10 +347,11 @@ void alloc_obs_buffers(ba_ctx& c) {
   c.rhs_c = A.alloc<double>(6 * size_t(C));
   c.x = A.alloc<double>(6 * size_t(C));
   c.r = A.alloc<double>(6 * size_t(C));
-  c.z = A.alloc<double>(6 * size_t(C));
+  c.u = A.alloc<double>(6 * size_t(C));
   c.p = A.alloc<double>(6 * size_t(C));
-  c.q = A.alloc<double>(6 * size_t(C));
-  c.pq_part = A.alloc<double>(size_t(C));
+  c.sv = A.alloc<double>(6 * size_t(C));
+  c.wv = A.alloc<double>(6 * size_t(C));
+  c.dots = A.alloc<double>(3 * size_t(C));
   c.partials = A.alloc<double>(4 * (size_t(P) / kBlock + 2));
   c.scal = A.alloc<double>(16);
   c.pcg = A.alloc<PcgState>(1);
@@ -370,23 +377,23 @@ Compact<T> compact_view(ba_ctx& c) {
   Compact<T> cp;
   cp.Pa = c.Pa;
   cp.Ca = c.Ca;
+  cp.Cf = c.n_fixed;
   cp.off = c.off_hat;
   cp.cam = c.cam_hat;
   cp.xy = c.xy_hat;
   cp.depth = c.depth_hat;
-  cp.slot = c.slot;
   cp.cam_src = c.cam_src;
   cp.cm_off = c.cm_off_hat;
   cp.cm_pt = c.cm_pt;
   cp.cm_pm = c.cm_pm;
   cp.Xd = c.Xd;
-  cp.camd = c.d_camd;
+  cp.camd = c.camd_hat;
   if constexpr (sizeof(T) == 8) {
     cp.Xt = reinterpret_cast<const T*>(c.Xd);
-    cp.camt = reinterpret_cast<const Cam<T>*>(c.d_camd);
+    cp.camt = reinterpret_cast<const Cam<T>*>(c.camd_hat);
   } else {
     cp.Xt = reinterpret_cast<const T*>(c.Xf);
-    cp.camt = reinterpret_cast<const Cam<T>*>(c.d_camf);
+    cp.camt = reinterpret_cast<const Cam<T>*>(c.camf_hat);
   }
   return cp;
 }
@@ -395,7 +402,8 @@ template <typename T>
 ObsMetric<T> metric_view(ba_ctx& c) {
   ObsMetric<T> om;
   om.w = static_cast<T*>(c.w);
-  om.cm_w = static_cast<T*>(c.cm_w);
+  om.xcw = static_cast<V4<T>*>(c.xcw);
+  om.pm_xcw = static_cast<V4<T>*>(c.pm_xcw);
   om.eh = static_cast<T*>(c.eh);
   om.cm_eh = static_cast<T*>(c.cm_eh);
   return om;
@@ -449,28 +457,43 @@ void extract(ba_ctx& c) {
   c.Nh = hp[2];
   c.Nc = hp[3];
   c.timed("compact", double(N) * 40 + double(c.P) * 60, -1, [&] {
+    launch_compact_cams(s, c.C, c.act_c, c.rank_c, c.d_fixed, c.d_fixed_rank, c.cm_off,
+                        c.pos_cm, c.slot_all, c.cam_src, c.cm_off_hat);
+    launch_compact_cam_table(s, c.Ca + c.n_fixed, c.cam_src, c.d_camd, c.d_camf, c.camd_hat,
+                             c.camf_hat);
     launch_compact_points(s, c.P, c.act_p, c.rank_p, c.pt_off, c.pos_pm, c.d_pts, c.pt_src,
                           c.off_hat, c.Xd, c.Xf);
-    launch_compact_obs(s, N, c.vrow, c.pos_pm, c.pm_cam, c.pm_xy, c.pm_depth, c.pm_orig,
-                       c.cam_hat, c.xy_hat, c.depth_hat, c.orig_hat);
-    launch_compact_cams(s, c.C, c.act_c, c.rank_c, c.cm_off, c.pos_cm, c.slot, c.cam_src,
-                        c.cm_off_hat);
+    launch_compact_obs(s, N, c.vrow, c.pos_pm, c.pm_cam, c.slot_all, c.pm_xy, c.pm_depth,
+                       c.pm_orig, c.cam_hat, c.xy_hat, c.depth_hat, c.orig_hat);
     launch_compact_cm(s, N, c.cm_perm, c.vrow, c.pm_cam, c.pm_pt, c.d_fixed, c.pos_cm,
                       c.pos_pm, c.rank_p, c.cm_pt, c.cm_pm);
+    if (c.tsize() == 8)
+      launch_mv_table<double>(s, c.Ca + c.n_fixed, c.camd_hat, static_cast<MvCam<double>*>(c.mvt));
+    else
+      launch_mv_table<float>(s, c.Ca + c.n_fixed, c.camd_hat, static_cast<MvCam<float>*>(c.mvt));
   });
   c.ext_valid = true;
 }
 
 // Algorithmic bytes of the two PCG passes (unique data each must touch once).
+// Point pass: per observation its slot and (X_c, w) 4-vector; per point the CSR offset, Vinv
+// and the 4-vector z written; every matvec record once.
 double bytes_schur_point(const ba_ctx& c) {
   const double ts = double(c.tsize());
-  return double(c.Nh) * (4 + ts) + double(c.Pa) * (4 + 12 * ts) +
-         double(c.C) * (4 + 15 * ts) + double(c.Ca) * 6 * ts;
+  return double(c.Nh) * (4 + 4 * ts) + double(c.Pa) * (4 + 6 * ts + 4 * ts) +
+         double(c.Ca) * 16 * ts;
 }
+// Camera pass: per observation the point rank and the (X_c, w) 4-vector; every active
+// point's z 4-vector at least once; per camera its offsets, table entry, U*, u, r, and the
+// w and dot terms written.
 double bytes_schur_cam(const ba_ctx& c) {
   const double ts = double(c.tsize());
-  return double(c.Nc) * (4 + ts) + double(c.Pa) * 6 * ts +
-         double(c.Ca) * (4 + 4 + 21 * ts + 6 * ts + 6 * 8 + 6 * 8 + 8 + 15 * ts);
+  return double(c.Nc) * (4 + 4 * ts) + double(c.Pa) * 4 * ts +
+         double(c.Ca) * (4 + 15 * ts + 21 * ts + 12 * 8 + 9 * 8);
+}
+int lanes_per_point(const ba_ctx& c) {
+  const double mean = c.Pa > 0 ? double(c.Nh) / c.Pa : 1.0;
+  return mean <= 2.5 ? 2 : mean <= 4.5 ? 4 : mean <= 9.0 ? 8 : 16;
 }
 
 template <typename T>
@@ -488,8 +511,8 @@ void linearize(ba_ctx& c, bool adj) {
   const int nb = int((c.Pa + kBlock - 1) / kBlock);
   launch_reduce_partials(s, nb, 3, c.partials, 0x4u, 0, nullptr, nullptr, c.scal);
   HIP_LAUNCH_CHECK();
-  c.timed("gather_cm_metric", double(c.Nc) * (4 + 2 * ts + (adj ? 6 * ts : 0)), -1,
-          [&] { launch_gather_cm_metric<T>(s, adj, c.Nc, c.cm_pm, om); });
+  c.timed("cm_prepare", double(c.Nc) * (8 + ts + 24 + 4 * ts + (adj ? 6 * ts : 0)), -1,
+          [&] { launch_cm_prepare<T>(s, adj, c.Nc, cp, om); });
 }
 
 // Damping-dependent setup: point inverses, camera blocks, Schur RHS, preconditioner.
@@ -531,27 +554,29 @@ int run_pcg(ba_ctx& c, bool adj, double rel_tol, int max_iters, PcgState* out_st
     out_state->done = 1;
     return 0;
   }
-  launch_pcg_init<T>(s, c.Ca, c.b, c.Minv, c.x, c.r, c.z, c.p, static_cast<T*>(c.pT), c.pcg,
+  MvCam<T>* mvt = static_cast<MvCam<T>*>(c.mvt);
+  launch_pcg_init<T>(s, c.Ca, c.b, c.Minv, c.x, c.r, c.u, c.p, c.sv, mvt, c.pcg,
                      rel_tol * rel_tol, max_iters);
   HIP_LAUNCH_CHECK();
   const int every = std::max(1, c.opt.pcg_check_every);
   const double bp = bytes_schur_point(c), bc = bytes_schur_cam(c);
+  const int G = lanes_per_point(c);
+  V4<T>* zq = static_cast<V4<T>*>(c.zq);
   int it = 0;
   while (true) {
     for (int k = 0; k < every && it < max_iters; ++k, ++it) {
       c.timed("schur_point", bp, it, [&] {
-        launch_schur_point<T>(s, adj, m, cp, om, static_cast<const T*>(c.Vinv),
-                              static_cast<const T*>(c.pT), static_cast<T*>(c.zq), c.pcg);
+        launch_schur_point<T>(s, adj, G, m, cp, om, mvt, static_cast<const T*>(c.Vinv), zq,
+                              c.pcg);
       });
       c.timed("schur_cam", bc, it, [&] {
-        launch_schur_cam<T>(s, adj, m, cp, om, static_cast<const T*>(c.Ustar),
-                            static_cast<const T*>(c.pT), c.p, static_cast<const T*>(c.zq), c.q,
-                            c.pq_part, c.pcg);
+        launch_schur_cam<T>(s, adj, m, cp, om, static_cast<const T*>(c.Ustar), c.u, c.r, zq,
+                            c.wv, c.dots, c.pcg);
       });
-      c.timed("pcg_update", double(c.Ca) * (21 * 8 + 6 * 8 * 8 + 8 + 6 * double(sizeof(T))), it,
-              [&] {
-                launch_pcg_update<T>(s, c.Ca, c.Minv, c.q, c.pq_part, c.x, c.r, c.z, c.p,
-                                     static_cast<T*>(c.pT), c.pcg);
+      c.timed("pcg_update", double(c.Ca) * (3 * 8 + 21 * 8 + 6 * 8 * 10 + 6 * double(sizeof(T))),
+              it, [&] {
+                launch_pcg_update<T>(s, c.Ca, c.Minv, c.dots, c.x, c.r, c.u, c.p, c.sv, c.wv,
+                                     mvt, c.pcg);
               });
     }
     HIP_CHECK(hipMemcpyAsync(c.h_pin, c.pcg, sizeof(PcgState), hipMemcpyDeviceToHost, s));
@@ -560,7 +585,7 @@ int run_pcg(ba_ctx& c, bool adj, double rel_tol, int max_iters, PcgState* out_st
     if (st.done || it >= max_iters) break;
   }
   *out_state = st;
-  return st.iter;
+  return st.matvecs;
 }
 
 template <typename T>
@@ -570,8 +595,8 @@ void backsub(ba_ctx& c, bool adj, const double* rhs_p) {
   Compact<T> cp = compact_view<T>(c);
   ObsMetric<T> om = metric_view<T>(c);
   c.timed("backsub", bytes_schur_point(c) + double(c.Pa) * 48, -1, [&] {
-    launch_backsub<T>(s, adj, m, cp, om, static_cast<const T*>(c.Vinv), c.x, c.gp, rhs_p,
-                      c.dp);
+    launch_backsub<T>(s, adj, lanes_per_point(c), m, cp, om, static_cast<const T*>(c.Vinv),
+                      c.x, c.gp, rhs_p, c.dp);
   });
 }
 
@@ -623,16 +648,17 @@ ba_status lm_step_impl(ba_ctx& c, ba_step_report* rep) {
   PcgState st{};
   const int iters = run_pcg<T>(c, false, c.opt.pcg_rel_tol, c.opt.pcg_max_iters, &st);
   t_pcg = now_ms() - ta;
-  R.pcg_iters = iters;
+  R.pcg_iters = st.iter;
   R.pcg_breakdown = st.breakdown;
   R.pcg_rel_residual = st.bb > 0 ? std::sqrt(std::max(0.0, st.rr) / st.bb) : 0.0;
 
   ta = now_ms();
   backsub<T>(c, false, nullptr);
-  c.timed("cam_candidate", double(c.C) * (56 + 120 + 56 + 120) + double(c.Ca) * 48, -1, [&] {
-    launch_cam_candidate(s, c.C, c.slot, c.x, c.d_cams, c.d_intr, c.d_camd, c.d_cand_cams,
-                         c.d_cand_tab);
-  });
+  c.timed("cam_candidate", double(c.Ca + c.n_fixed) * (56 + 120 + 56 + 120) + double(c.Ca) * 48,
+          -1, [&] {
+            launch_cam_candidate(s, c.Ca, c.n_fixed, c.cam_src, c.x, c.d_cams, c.camd_hat,
+                                 c.d_cand_cams, c.d_cand_tab);
+          });
   Compact<T> cp = compact_view<T>(c);
   c.timed("point_candidate",
           double(c.Nh) * (4 + 8 + 4 + ts) + double(c.Pa) * (4 + 24 * 4) + double(c.C) * 240, -1,
@@ -657,15 +683,8 @@ ba_status lm_step_impl(ba_ctx& c, ba_step_report* rep) {
   R.cost_after = Fc;
   const double model = -(sc[6] + sc[8] + 0.5 * sc[5]);
   R.model_decrease = model;
-  // max |g| over the compact parameters: points from the linearisation partials, cameras
-  // from gc (downloaded: 6 Ca values)
-  {
-    std::vector<double> g;
-    download(c, g, c.gc, size_t(6) * c.Ca);
-    double gm = sc[2];
-    for (double v : g) gm = std::max(gm, std::fabs(v));
-    R.grad_inf = gm;
-  }
+  // max |g| over the compact parameters: points from the linearisation, cameras from gc
+  R.grad_inf = std::max(sc[2], c.Ca > 0 ? sc[9] : 0.0);
   if (!std::isfinite(F)) {
     c.flush_timing(iters);
     R.ms_total = now_ms() - t0;
@@ -681,7 +700,8 @@ ba_status lm_step_impl(ba_ctx& c, ba_step_report* rep) {
   c.step_valid = true;
   if (ok) {
     c.timed("scatter", double(c.Pa) * 52 + double(c.C) * 60, -1, [&] {
-      launch_scatter(s, c.Pa, c.C, c.pt_src, c.Xcand, c.slot, c.d_cand_cams, c.d_pts, c.d_cams);
+      launch_scatter(s, c.Pa, c.Ca, c.pt_src, c.Xcand, c.cam_src, c.d_cand_cams, c.d_pts,
+                     c.d_cams);
     });
     c.lin_valid = false;
     const double f = std::max(1.0 / 3.0, 1.0 - std::pow(2.0 * ratio - 1.0, 3));
@@ -732,7 +752,7 @@ void adjoint_impl(ba_ctx& c, const double* grad_cams, const double* grad_points,
     PcgState st{};
     const double tol = std::min(c.opt.pcg_rel_tol, 1e-10);
     const int maxit = std::max(c.opt.pcg_max_iters, 6 * c.Ca + 10);
-    run_pcg<T>(c, true, tol, maxit, &st);
+    const int mv = run_pcg<T>(c, true, tol, maxit, &st);
     backsub<T>(c, true, c.rhs_p);
     Compact<T> cp = compact_view<T>(c);
     launch_adjoint_obs<T>(s, c.model(), cp, metric_view<T>(c), c.x, c.dp, c.orig_hat, c.gxy_d,
@@ -742,7 +762,7 @@ void adjoint_impl(ba_ctx& c, const double* grad_cams, const double* grad_points,
     HIP_CHECK(hipMemcpyAsync(c.h_pin, c.flags + 1, sizeof(int), hipMemcpyDeviceToHost, s));
     c.sync();
     std::memcpy(&bad, c.h_pin, sizeof(int));
-    c.flush_timing(st.iter);
+    c.flush_timing(mv);
     if (bad) throw BaError{BA_ERR_NUMERIC, "singular point block in the adjoint system"};
     if (st.breakdown) throw BaError{BA_ERR_NUMERIC, "adjoint PCG broke down"};
   }
@@ -801,7 +821,7 @@ void ba_default_options(ba_options* o) {
   o->diag_max = 1e32;
   o->accept_ratio = 1e-3;
   o->pcg_max_iters = 100;
-  o->pcg_check_every = 4;
+  o->pcg_check_every = 8;
   o->pcg_rel_tol = 1e-6;
   o->cost_rel_tol = 1e-10;
   o->grad_tol = 1e-10;
@@ -864,6 +884,7 @@ ba_status ba_create(const ba_options* opt, int32_t n_cams, int32_t n_points, con
     c->d_intr = A.alloc<double>(3 * size_t(n_cams));
     c->d_pts = A.alloc<double>(3 * size_t(n_points));
     c->d_fixed = A.alloc<uint8_t>(n_cams);
+    c->d_fixed_rank = A.alloc<int>(n_cams);
     c->d_camd = A.alloc<Cam<double>>(n_cams);
     c->d_camf = A.alloc<Cam<float>>(n_cams);
     c->d_cand_tab = A.alloc<Cam<double>>(n_cams);
@@ -890,6 +911,8 @@ ba_status ba_create(const ba_options* opt, int32_t n_cams, int32_t n_points, con
     store(*c, c->d_intr, hi.data(), hi.size());
     store(*c, c->d_pts, hpnt.data(), hpnt.size());
     store(*c, c->d_fixed, c->fixed_h.data(), c->fixed_h.size());
+    std::vector<int32_t> fr(size_t(n_cams), -1);
+    store(*c, c->d_fixed_rank, fr.data(), fr.size());
   } catch (const BaError& err) {
     g_create_error = err.msg;
     delete c;
@@ -1013,8 +1036,11 @@ ba_status ba_set_fixed_cameras(ba_ctx* c, int32_t n, const int32_t* ids) {
     }
     c->fixed_h = f;
     c->n_fixed = 0;
-    for (uint8_t v : f) c->n_fixed += v;
+    std::vector<int32_t> fr(size_t(c->C), -1);
+    for (int i = 0; i < c->C; ++i)
+      if (f[i]) fr[i] = c->n_fixed++;
     store(*c, c->d_fixed, f.data(), f.size());
+    store(*c, c->d_fixed_rank, fr.data(), fr.size());
     c->lin_valid = c->ext_valid = c->step_valid = c->blocks_valid = false;
     return BA_OK;
   });
@@ -1145,7 +1171,7 @@ ba_status ba_get_last_step(const ba_ctx* cc, double* dcams, double* dpoints) {
       download(*c, x, c->x, 6 * size_t(c->Ca));
       download(*c, src, c->cam_src, size_t(c->Ca));
       for (int s = 0; s < c->Ca; ++s)
-        for (int k = 0; k < 6; ++k) out[6 * size_t(src[s]) + k] = x[6 * size_t(s) + k];
+        for (int k = 0; k < 6; ++k) out[6 * size_t(src[s]) + k] = x[size_t(k) * c->Ca + s];
       store(*c, dcams, out.data(), out.size());
     }
     if (dpoints) {
@@ -1176,7 +1202,7 @@ ba_status ba_get_normal_blocks(const ba_ctx* cc, double* U, double* gcv, double*
       for (int s = 0; s < c->Ca; ++s) {
         const size_t cam = size_t(csrc[s]);
         for (int i = 0; i < 6; ++i) {
-          go[6 * cam + i] = g[6 * size_t(s) + i];
+          go[6 * cam + i] = g[size_t(i) * c->Ca + s];
           for (int j = 0; j < 6; ++j) {
             const int a = std::min(i, j), b = std::max(i, j);
             const int idx = a * 6 - (a * (a - 1)) / 2 + (b - a);

@@ -1,5 +1,13 @@
 // Internal interface between the host orchestration (ba_api.hip) and the gfx950 kernels
 // (ba_kernels.hip). Not installed; the public ABI is include/ba.h.
+//
+// Layout conventions
+//   * compact camera slots: [0, Ca) are the active cameras in ascending original index
+//     (Eq. (15) ranks), [Ca, Ca + Cf) the fixed cameras; observations carry their slot.
+//   * per-camera solve vectors (x, r, u, p, s, w, b, gc) and blocks (Minv, Ustar) are stored
+//     structure-of-arrays: element i of camera s lives at [i * Ca + s].
+//   * the camera-major pass reads one aligned 4-vector per observation: the camera-frame
+//     point at the linearisation point and the robust weight.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -19,6 +27,22 @@ struct Cam {
   T f, cx, cy;
 };
 
+// Aligned 4-vector (one 16-byte load in float, two in double).
+template <typename T>
+struct alignas(4 * sizeof(T)) V4 {
+  T x, y, z, w;
+};
+
+// Per-slot record read by the PCG point pass: rotation, focal length and the current camera
+// direction u of the Schur matvec, 16 values so that one aligned half (float) or full
+// (double) cache line serves an observation.
+template <typename T>
+struct alignas(16 * sizeof(T)) MvCam {
+  T R[9];
+  T f;
+  T u[6];
+};
+
 // Residual-model constants shared by the kernels.
 struct Model {
   double lam_d;       // weight of the inverse-depth row (0: no depth row)
@@ -28,35 +52,38 @@ struct Model {
   int img_w, img_h;   // validity: projection inside [0, w) x [0, h)
 };
 
-// Device-side PCG scalars (one instance per context).
+// Device-side PCG scalars (one instance per context). The iteration is the
+// Chronopoulos-Gear form of preconditioned CG: one fused reduction per iteration.
 struct PcgState {
-  double rz;          // r.z of the current iterate
+  double gamma;       // r.u of the previous iteration (u = M^-1 r)
+  double alpha;       // previous step length
   double bb;          // b.b
-  double rr;          // r.r of the current iterate
+  double rr;          // r.r at the last convergence check
   double tol2;        // (relative tolerance)^2
-  int iter;
+  int iter;           // solution updates so far
+  int matvecs;        // Schur matvecs whose result was used
   int max_iter;
   int done;
-  int breakdown;      // p.S.p <= 0 or non-finite
+  int breakdown;      // non-positive curvature or non-finite scalar
+  int pad;
 };
 
 // Compact problem view shared by the point-major and camera-major passes.
 template <typename T>
 struct Compact {
-  int Pa, Ca;
+  int Pa, Ca, Cf;         // active points, active cameras, fixed cameras
   const int* off;         // Pa + 1: point-major CSR over compact observations
-  const int* cam;         // Nh: original camera index of each compact observation
+  const int* cam;         // Nh: compact camera slot of each observation
   const float2* xy;       // Nh
   const float* depth;     // Nh: prior depth, 0 where invalid (m = 0)
-  const int* slot;        // C: solve slot of each camera, -1 if not in the solve
-  const int* cam_src;     // Ca: original camera index of each solve slot
+  const int* cam_src;     // Ca + Cf: original camera index of each slot
   const int* cm_off;      // Ca + 1: camera-major segments
   const int* cm_pt;       // Nc: point rank of each camera-major observation
   const int* cm_pm;       // Nc: position of that observation in the point-major stream
   const double* Xd;       // Pa x 3 compact points (float64)
   const T* Xt;            // Pa x 3 compact points (T)
-  const Cam<double>* camd;// C camera table (float64)
-  const Cam<T>* camt;     // C camera table (T)
+  const Cam<double>* camd;// Ca + Cf compact camera table (float64)
+  const Cam<T>* camt;     // Ca + Cf compact camera table (T)
 };
 
 // Per-observation metric data written by the linearisation. The LM step weighs an
@@ -66,10 +93,11 @@ struct Compact {
 // and every kernel projects the rows of de/dX_c with (I - eh eh^T).
 template <typename T>
 struct ObsMetric {
-  T* w;      // Nh: rho'
-  T* eh;     // Nh x 3: unit residual direction (adjoint only, else nullptr)
-  T* cm_w;   // Nc: copies in camera-major order
-  T* cm_eh;  // Nc x 3 (adjoint only)
+  T* w;          // Nh: rho'
+  T* eh;         // Nh x 3: unit residual direction (adjoint only, else nullptr)
+  V4<T>* pm_xcw; // Nh: camera-frame point and w, point-major order
+  V4<T>* xcw;    // Nc: camera-frame point and w, camera-major order
+  T* cm_eh;      // Nc x 3 (adjoint only)
 };
 
 // ------------------------------------------------------------------ extraction
@@ -83,8 +111,7 @@ void launch_cam_rows(hipStream_t s, int C, const int* cm_off, const int* cm_perm
 void launch_point_rows_prune(hipStream_t s, int P, const int* pt_off, const int* pm_cam,
                              const uint8_t* act_c, const uint8_t* fixed, int need,
                              uint8_t* vrow, uint8_t* act_p, int* changed);
-// Exclusive scan of 0/1 flags; out has n + 1 entries (out[n] = total). tmp needs
-// scan_tmp_ints(n) ints.
+// Exclusive scans; out has n + 1 entries (out[n] = total). tmp needs scan_tmp_ints(n) ints.
 int64_t scan_tmp_ints(int64_t n);
 void launch_scan_u8(hipStream_t s, int64_t n, const uint8_t* flags, int* out, int* tmp);
 void launch_scan_cm(hipStream_t s, int64_t n, const int* cm_perm, const uint8_t* vrow,
@@ -92,17 +119,24 @@ void launch_scan_cm(hipStream_t s, int64_t n, const int* cm_perm, const uint8_t*
 void launch_compact_points(hipStream_t s, int P, const uint8_t* act_p, const int* rank_p,
                            const int* pt_off, const int* pos_pm, const double* pts,
                            int* pt_src, int* off_hat, double* Xd, float* Xf);
-void launch_compact_obs(hipStream_t s, int64_t N, const uint8_t* vrow, const int* pos_pm,
-                        const int* pm_cam, const float2* pm_xy, const float* pm_depth,
-                        const int* pm_orig, int* cam_hat, float2* xy_hat, float* depth_hat,
-                        int* orig_hat);
+// Slots: active cameras get their rank, fixed cameras Ca + fixed_rank, others -1.
 void launch_compact_cams(hipStream_t s, int C, const uint8_t* act_c, const int* rank_c,
-                         const int* cm_off, const int* pos_cm, int* slot, int* cam_src,
-                         int* cm_off_hat);
+                         const uint8_t* fixed, const int* fixed_rank, const int* cm_off,
+                         const int* pos_cm, int* slot_all, int* cam_src, int* cm_off_hat);
+void launch_compact_cam_table(hipStream_t s, int n, const int* cam_src,
+                              const Cam<double>* camd, const Cam<float>* camf,
+                              Cam<double>* camd_hat, Cam<float>* camf_hat);
+void launch_compact_obs(hipStream_t s, int64_t N, const uint8_t* vrow, const int* pos_pm,
+                        const int* pm_cam, const int* slot_all, const float2* pm_xy,
+                        const float* pm_depth, const int* pm_orig, int* cam_hat,
+                        float2* xy_hat, float* depth_hat, int* orig_hat);
 void launch_compact_cm(hipStream_t s, int64_t N, const int* cm_perm, const uint8_t* vrow,
                        const int* pm_cam, const int* pm_pt, const uint8_t* fixed,
                        const int* pos_cm, const int* pos_pm, const int* rank_p, int* cm_pt,
                        int* cm_pm);
+// Matvec records of every slot (R, f from the compact table; u = 0).
+template <typename T>
+void launch_mv_table(hipStream_t s, int n, const Cam<double>* camd_hat, MvCam<T>* mvt);
 
 // ------------------------------------------------------------------ linearisation
 // Per point: residuals (float64), robust weights, V = J_p^T M J_p (T), gp = J_p^T M e
@@ -110,17 +144,18 @@ void launch_compact_cm(hipStream_t s, int64_t N, const int* cm_perm, const uint8
 template <typename T>
 void launch_lin_point(hipStream_t s, bool adj, const Model& m, const Compact<T>& cp,
                       ObsMetric<T> om, T* V, double* gp, double* partials);
+// Camera-major stream of the PCG camera pass: X_c and w per observation (+ eh).
 template <typename T>
-void launch_gather_cm_metric(hipStream_t s, bool adj, int64_t Nc, const int* cm_pm,
-                             ObsMetric<T> om);
+void launch_cm_prepare(hipStream_t s, bool adj, int64_t Nc, const Compact<T>& cp,
+                       ObsMetric<T> om);
 // V* = V + lam clamp(diag V); Vinv (inverted in float64, stored as T); hp = Vinv rhs_p.
 // rhs_p = -gp when rhs_p == nullptr.
 template <typename T>
 void launch_point_damp(hipStream_t s, int Pa, double lam, double dmin, double dmax,
                        const T* V, const double* gp, const double* rhs_p, T* Vinv,
                        double* hp, int* bad);
-// Per camera: U = J_c^T M J_c, gc, b = rhs_c - sum W hp, S_cc = U* - sum W Vinv W^T and its
-// inverse (Cholesky, float64). rhs_c = -gc when rhs_c == nullptr.
+// Per camera slot: U = J_c^T M J_c, gc, b = rhs_c - sum W hp, S_cc = U* - sum W Vinv W^T and
+// its inverse (Cholesky, float64). rhs_c = -gc when rhs_c == nullptr. SoA outputs.
 template <typename T>
 void launch_cam_assemble(hipStream_t s, bool adj, const Model& m, const Compact<T>& cp,
                          ObsMetric<T> om, double lam, double dmin, double dmax,
@@ -128,49 +163,54 @@ void launch_cam_assemble(hipStream_t s, bool adj, const Model& m, const Compact<
                          double* Uraw, T* Ustar, double* gc, double* b, double* Minv);
 
 // ------------------------------------------------------------------ PCG on S
+// x = 0, r = b, u = M^-1 r (also into the matvec records), p = s = 0.
 template <typename T>
 void launch_pcg_init(hipStream_t s, int Ca, const double* b, const double* Minv, double* x,
-                     double* r, double* z, double* p, T* pt, PcgState* st, double tol2,
-                     int max_iter);
-// z_p = Vinv sum_k W_k^T p_c  (point-major pass)
+                     double* r, double* u, double* p, double* sv, MvCam<T>* mvt, PcgState* st,
+                     double tol2, int max_iter);
+// zq_p = Vinv sum_k W_k^T u_c  (point-major pass, G lanes per point)
 template <typename T>
-void launch_schur_point(hipStream_t s, bool adj, const Model& m, const Compact<T>& cp,
-                        ObsMetric<T> om, const T* Vinv, const T* pvec, T* zq,
+void launch_schur_point(hipStream_t s, bool adj, int G, const Model& m, const Compact<T>& cp,
+                        ObsMetric<T> om, const MvCam<T>* mvt, const T* Vinv, V4<T>* zq,
                         const PcgState* st);
-// q_c = U*_c p_c - sum_k W_k z_p (camera-major pass) and p_c.q_c partials
+// Camera-major pass, one workgroup per camera slot: w_s = U*_s u_s - sum_k W_k zq_p, and the
+// camera's terms of r.u, w.u and r.r (dots: 3 arrays of Ca, SoA).
 template <typename T>
 void launch_schur_cam(hipStream_t s, bool adj, const Model& m, const Compact<T>& cp,
-                      ObsMetric<T> om, const T* Ustar, const T* pvec, const double* p64,
-                      const T* zq, double* q, double* pq_part, const PcgState* st);
+                      ObsMetric<T> om, const T* Ustar, const double* u, const double* r,
+                      const V4<T>* zq, double* w, double* dots, const PcgState* st);
+// Fused reduction of the per-camera dots, convergence test, then p = u + beta p,
+// s = w + beta s, x += alpha p, r -= alpha s, u = M^-1 r.
 template <typename T>
-void launch_pcg_update(hipStream_t s, int Ca, const double* Minv, const double* q,
-                       const double* pq_part, double* x, double* r, double* z, double* p,
-                       T* pt, PcgState* st);
+void launch_pcg_update(hipStream_t s, int Ca, const double* Minv, const double* dots,
+                       double* x, double* r, double* u, double* p, double* sv, const double* w,
+                       MvCam<T>* mvt, PcgState* st);
 // dp = Vinv (rhs_p - sum_k W_k^T x_c), rhs_p = -gp when nullptr.
 template <typename T>
-void launch_backsub(hipStream_t s, bool adj, const Model& m, const Compact<T>& cp,
+void launch_backsub(hipStream_t s, bool adj, int G, const Model& m, const Compact<T>& cp,
                     ObsMetric<T> om, const T* Vinv, const double* x, const double* gp,
                     const double* rhs_p, double* dp);
 
 // ------------------------------------------------------------------ candidate
-void launch_cam_candidate(hipStream_t s, int C, const int* slot, const double* x,
-                          const double* cams, const double* intr, const Cam<double>* camd,
-                          double* cand_cams, Cam<double>* cand_tab);
+// Candidate camera table over all slots (retracted for s < Ca, copied for fixed slots).
+void launch_cam_candidate(hipStream_t s, int Ca, int Cf, const int* cam_src, const double* x,
+                          const double* cams, const Cam<double>* camd_hat, double* cand_cams,
+                          Cam<double>* cand_tab);
 template <typename T>
 void launch_point_candidate(hipStream_t s, const Model& m, const Compact<T>& cp,
                             const Cam<double>* cand_tab, const double* x, const double* dp,
                             const double* gp, const T* w, double* Xcand, double* partials);
-// Sums per-block partials (K doubles per block) in a fixed order; also adds gc.x when
-// gc != nullptr into out[K].
+// Sums per-block partials (K doubles per block) in a fixed order; with gc != nullptr also
+// out[K] = gc . x over 6 Ca values and out[K + 1] = max |gc|.
 void launch_reduce_partials(hipStream_t s, int nblocks, int K, const double* partials,
                             unsigned max_mask, int Ca, const double* gc, const double* x,
                             double* out);
-void launch_scatter(hipStream_t s, int Pa, int C, const int* pt_src, const double* Xcand,
-                    const int* slot, const double* cand_cams, double* pts, double* cams);
+void launch_scatter(hipStream_t s, int Pa, int Ca, const int* pt_src, const double* Xcand,
+                    const int* cam_src, const double* cand_cams, double* pts, double* cams);
 
 // ------------------------------------------------------------------ adjoint
-// rhs for the adjoint solve: tangent-mapped camera gradients and point gradients (both
-// gathered from caller-order device arrays).
+// rhs for the adjoint solve: tangent-mapped camera gradients (SoA) and point gradients, both
+// gathered from caller-order device arrays.
 void launch_adjoint_rhs(hipStream_t s, int Ca, int Pa, const int* cam_src, const double* cams,
                         const double* grad_cams, const int* pt_src, const int* pt_user,
                         const double* grad_pts, double* rhs_c, double* rhs_p);

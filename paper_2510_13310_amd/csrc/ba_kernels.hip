@@ -424,35 +424,53 @@ k_compact_points(int P, const uint8_t* __restrict__ act_p, const int* __restrict
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_compact_obs(int64_t N, const uint8_t* __restrict__ vrow, const int* __restrict__ pos_pm,
-              const int* __restrict__ pm_cam, const float2* __restrict__ pm_xy,
-              const float* __restrict__ pm_depth, const int* __restrict__ pm_orig,
-              int* __restrict__ cam_hat, float2* __restrict__ xy_hat,
-              float* __restrict__ depth_hat, int* __restrict__ orig_hat) {
-  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (k >= N || !vrow[k]) return;
-  const int j = pos_pm[k];
-  cam_hat[j] = pm_cam[k];
-  xy_hat[j] = pm_xy[k];
-  depth_hat[j] = pm_depth[k];
-  orig_hat[j] = pm_orig[k];
+k_compact_cams(int C, const uint8_t* __restrict__ act_c, const int* __restrict__ rank_c,
+               const uint8_t* __restrict__ fixed, const int* __restrict__ fixed_rank,
+               const int* __restrict__ cm_off, const int* __restrict__ pos_cm,
+               int* __restrict__ slot_all, int* __restrict__ cam_src,
+               int* __restrict__ cm_off_hat) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  if (act_c[c]) {
+    const int s = rank_c[c];
+    slot_all[c] = s;
+    cam_src[s] = c;
+    cm_off_hat[s] = pos_cm[cm_off[c]];
+    cm_off_hat[s + 1] = pos_cm[cm_off[c + 1]];
+  } else if (fixed[c]) {
+    const int s = rank_c[C] + fixed_rank[c];   // fixed cameras follow the active ones
+    slot_all[c] = s;
+    cam_src[s] = c;
+  } else {
+    slot_all[c] = -1;
+  }
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_compact_cams(int C, const uint8_t* __restrict__ act_c, const int* __restrict__ rank_c,
-               const int* __restrict__ cm_off, const int* __restrict__ pos_cm,
-               int* __restrict__ slot, int* __restrict__ cam_src, int* __restrict__ cm_off_hat) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= C) return;
-  if (!act_c[c]) {
-    slot[c] = -1;
-    return;
-  }
-  const int s = rank_c[c];
-  slot[c] = s;
-  cam_src[s] = c;
-  cm_off_hat[s] = pos_cm[cm_off[c]];
-  cm_off_hat[s + 1] = pos_cm[cm_off[c + 1]];
+k_compact_cam_table(int n, const int* __restrict__ cam_src, const Cam<double>* __restrict__ camd,
+                    const Cam<float>* __restrict__ camf, Cam<double>* __restrict__ camd_hat,
+                    Cam<float>* __restrict__ camf_hat) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int c = cam_src[s];
+  camd_hat[s] = camd[c];
+  camf_hat[s] = camf[c];
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_compact_obs(int64_t N, const uint8_t* __restrict__ vrow, const int* __restrict__ pos_pm,
+              const int* __restrict__ pm_cam, const int* __restrict__ slot_all,
+              const float2* __restrict__ pm_xy, const float* __restrict__ pm_depth,
+              const int* __restrict__ pm_orig, int* __restrict__ cam_hat,
+              float2* __restrict__ xy_hat, float* __restrict__ depth_hat,
+              int* __restrict__ orig_hat) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= N || !vrow[k]) return;
+  const int j = pos_pm[k];
+  cam_hat[j] = slot_all[pm_cam[k]];
+  xy_hat[j] = pm_xy[k];
+  depth_hat[j] = pm_depth[k];
+  orig_hat[j] = pm_orig[k];
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -468,6 +486,18 @@ k_compact_cm(int64_t N, const int* __restrict__ cm_perm, const uint8_t* __restri
   const int i = pos_cm[m];
   cm_pt[i] = rank_p[pm_pt[k]];
   cm_pm[i] = pos_pm[k];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_mv_table(int n, const Cam<double>* __restrict__ camd_hat, MvCam<T>* __restrict__ mvt) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  MvCam<T> v;
+  for (int i = 0; i < 9; ++i) v.R[i] = T(camd_hat[s].R[i]);
+  v.f = T(camd_hat[s].f);
+  for (int i = 0; i < 6; ++i) v.u[i] = T(0);
+  mvt[s] = v;
 }
 
 // ------------------------------------------------------------------ linearisation
@@ -494,6 +524,12 @@ k_lin_point(Model m, Compact<T> cp, ObsMetric<T> om, T* __restrict__ V,
       acc[1] += e[0] * e[0] + e[1] * e[1];
       om.w[j] = T(w);
       const T Xt[3] = {T(Xc[0]), T(Xc[1]), T(Xc[2])};
+      V4<T> xw;
+      xw.x = Xt[0];
+      xw.y = Xt[1];
+      xw.z = Xt[2];
+      xw.w = T(w);
+      om.pm_xcw[j] = xw;
       AMat<T, ADJ> A;
       A.set(T(cm.f), T(m.lam_d), Xt);
       if constexpr (ADJ) {
@@ -554,13 +590,24 @@ k_lin_point(Model m, Compact<T> cp, ObsMetric<T> om, T* __restrict__ V,
   }
 }
 
+// Camera-major stream for the PCG camera pass: the camera-frame point (computed in float64
+// at the linearisation point) and the robust weight, one aligned 4-vector per observation.
 template <typename T, bool ADJ>
 __global__ void __launch_bounds__(kBlock)
-k_gather_cm_metric(int64_t Nc, const int* __restrict__ cm_pm, ObsMetric<T> om) {
+k_cm_prepare(int64_t Nc, Compact<T> cp, ObsMetric<T> om) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= Nc) return;
-  const int j = cm_pm[i];
-  om.cm_w[i] = om.w[j];
+  const int j = cp.cm_pm[i];
+  const int r = cp.cm_pt[i];
+  const Cam<double>& cm = cp.camd[cp.cam[j]];
+  double Xc[3];
+  cam_frame(cm, cp.Xd[3 * r], cp.Xd[3 * r + 1], cp.Xd[3 * r + 2], Xc);
+  V4<T> v;
+  v.x = T(Xc[0]);
+  v.y = T(Xc[1]);
+  v.z = T(Xc[2]);
+  v.w = om.w[j];
+  om.xcw[i] = v;
   if constexpr (ADJ) {
     om.cm_eh[3 * i] = om.eh[3 * j];
     om.cm_eh[3 * i + 1] = om.eh[3 * j + 1];
@@ -643,6 +690,7 @@ __device__ bool spd6_inverse(const double* A21, double* out21) {
   return true;
 }
 
+
 template <typename T, bool ADJ>
 __global__ void __launch_bounds__(kBlock)
 k_cam_assemble(Model m, Compact<T> cp, ObsMetric<T> om, double lam, double dmin, double dmax,
@@ -653,8 +701,8 @@ k_cam_assemble(Model m, Compact<T> cp, ObsMetric<T> om, double lam, double dmin,
   constexpr int K = 21 + 21 + 6 + 6;
   __shared__ double smem[K * (kBlock / kWave)];
   const int s = blockIdx.x;
-  const int c = cp.cam_src[s];
-  const Cam<double> cm = cp.camd[c];
+  const int Ca = cp.Ca;
+  const Cam<double> cm = cp.camd[s];
   double acc[K];   // U (21), S = sum W Vinv W^T (21), gc (6), sum W hp (6)
 #pragma unroll
   for (int i = 0; i < K; ++i) acc[i] = 0.0;
@@ -664,7 +712,7 @@ k_cam_assemble(Model m, Compact<T> cp, ObsMetric<T> om, double lam, double dmin,
     double Xc[3], e[3];
     cam_frame(cm, cp.Xd[3 * r], cp.Xd[3 * r + 1], cp.Xd[3 * r + 2], Xc);
     residual(cm, Xc, cp.xy[j], cp.depth[j], m.lam_d, e);
-    const T wt = om.cm_w[i];
+    const T wt = om.w[j];
     const T Xt[3] = {T(Xc[0]), T(Xc[1]), T(Xc[2])};
     AMat<T, ADJ> A;
     A.set(T(cm.f), T(m.lam_d), Xt);
@@ -735,14 +783,14 @@ k_cam_assemble(Model m, Compact<T> cp, ObsMetric<T> om, double lam, double dmin,
   }
 #pragma unroll
   for (int q = 0; q < 21; ++q) {
-    Ustar[21 * s + q] = T(Us[q]);
+    Ustar[q * Ca + s] = T(Us[q]);
     Sc[q] = Us[q] - acc[21 + q];
   }
 #pragma unroll
   for (int p = 0; p < 6; ++p) {
-    gc[6 * s + p] = acc[42 + p];
-    const double rhs = rhs_c ? rhs_c[6 * s + p] : -acc[42 + p];
-    b[6 * s + p] = rhs - acc[48 + p];
+    gc[p * Ca + s] = acc[42 + p];
+    const double rhs = rhs_c ? rhs_c[p * Ca + s] : -acc[42 + p];
+    b[p * Ca + s] = rhs - acc[48 + p];
   }
   double inv[21];
   if (!spd6_inverse(Sc, inv)) {
@@ -756,16 +804,21 @@ k_cam_assemble(Model m, Compact<T> cp, ObsMetric<T> om, double lam, double dmin,
     }
   }
 #pragma unroll
-  for (int q = 0; q < 21; ++q) Minv[21 * s + q] = inv[q];
+  for (int q = 0; q < 21; ++q) Minv[q * Ca + s] = inv[q];
 }
 
 // ------------------------------------------------------------------ PCG
-__device__ __forceinline__ void sym6_mul(const double* M, const double* x, double* y) {
+// y = M x for a symmetric 6x6 block stored SoA (21 arrays of length Ca).
+__device__ __forceinline__ void sym6_mul_soa(const double* M, int Ca, int s, const double* x,
+                                             double* y) {
+  double m[21];
+#pragma unroll
+  for (int k = 0; k < 21; ++k) m[k] = M[k * Ca + s];
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     double a = 0.0;
 #pragma unroll
-    for (int j = 0; j < 6; ++j) a += M[sym6(i, j)] * x[j];
+    for (int j = 0; j < 6; ++j) a += m[sym6(i, j)] * x[j];
     y[i] = a;
   }
 }
@@ -773,265 +826,312 @@ __device__ __forceinline__ void sym6_mul(const double* M, const double* x, doubl
 template <typename T>
 __global__ void __launch_bounds__(1024)
 k_pcg_init(int Ca, const double* __restrict__ b, const double* __restrict__ Minv,
-           double* __restrict__ x, double* __restrict__ r, double* __restrict__ z,
-           double* __restrict__ p, T* __restrict__ pt, PcgState* st, double tol2, int max_iter) {
-  __shared__ double smem[2 * (1024 / kWave)];
-  double acc[2] = {0.0, 0.0};   // r.z, b.b
+           double* __restrict__ x, double* __restrict__ r, double* __restrict__ u,
+           double* __restrict__ p, double* __restrict__ sv, MvCam<T>* __restrict__ mvt,
+           PcgState* st, double tol2, int max_iter) {
+  __shared__ double smem[1024 / kWave];
+  double acc[1] = {0.0};   // b.b
   for (int s = threadIdx.x; s < Ca; s += blockDim.x) {
-    double rv[6], zv[6];
+    double rv[6], uv[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-      rv[i] = b[6 * s + i];
-      x[6 * s + i] = 0.0;
-      r[6 * s + i] = rv[i];
+      rv[i] = b[i * Ca + s];
+      x[i * Ca + s] = 0.0;
+      r[i * Ca + s] = rv[i];
+      p[i * Ca + s] = 0.0;
+      sv[i * Ca + s] = 0.0;
+      acc[0] += rv[i] * rv[i];
     }
-    sym6_mul(Minv + 21 * s, rv, zv);
+    sym6_mul_soa(Minv, Ca, s, rv, uv);
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-      z[6 * s + i] = zv[i];
-      p[6 * s + i] = zv[i];
-      pt[6 * s + i] = T(zv[i]);
-      acc[0] += rv[i] * zv[i];
-      acc[1] += rv[i] * rv[i];
+      u[i * Ca + s] = uv[i];
+      mvt[s].u[i] = T(uv[i]);
     }
   }
-  block_sum<double, 2>(acc, smem);
+  block_sum<double, 1>(acc, smem);
   if (threadIdx.x == 0) {
-    st->rz = acc[0];
-    st->bb = acc[1];
-    st->rr = acc[1];
+    st->gamma = 0.0;
+    st->alpha = 0.0;
+    st->bb = acc[0];
+    st->rr = acc[0];
     st->tol2 = tol2;
     st->iter = 0;
+    st->matvecs = 0;
     st->max_iter = max_iter;
     st->breakdown = 0;
-    st->done = (acc[1] == 0.0 || max_iter <= 0) ? 1 : 0;
-    if (!isfinite(acc[0]) || !isfinite(acc[1])) {
+    st->done = (acc[0] == 0.0 || max_iter <= 0) ? 1 : 0;
+    if (!isfinite(acc[0])) {
       st->breakdown = 1;
       st->done = 1;
     }
   }
 }
 
-template <typename T, bool ADJ>
+// Point-major pass of S u: G lanes share one point, each walks every G-th observation of
+// the point's segment, and the lanes combine their sums with shuffles (G divides 64). Per
+// observation: the streamed (X_c, w) 4-vector and one aligned matvec record of its camera.
+template <typename T, bool ADJ, int G>
 __global__ void __launch_bounds__(kBlock)
-k_schur_point(Model m, Compact<T> cp, ObsMetric<T> om, const T* __restrict__ Vinv,
-              const T* __restrict__ pvec, T* __restrict__ zq, const PcgState* __restrict__ st) {
+k_schur_point(Model m, Compact<T> cp, ObsMetric<T> om, const MvCam<T>* __restrict__ mvt,
+              const T* __restrict__ Vinv, V4<T>* __restrict__ zq,
+              const PcgState* __restrict__ st) {
   if (st->done) return;
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= cp.Pa) return;
-  const T X0 = cp.Xt[3 * r], X1 = cp.Xt[3 * r + 1], X2 = cp.Xt[3 * r + 2];
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = t / G;
+  const int l = t % G;
   T y[3] = {T(0), T(0), T(0)};
-  for (int j = cp.off[r]; j < cp.off[r + 1]; ++j) {
-    const int c = cp.cam[j];
-    const int sl = cp.slot[c];
-    if (sl < 0) continue;
-    const Cam<T>& cm = cp.camt[c];
-    T Xc[3];
-    cam_frame(cm, X0, X1, X2, Xc);
-    AMat<T, ADJ> A;
-    A.set(cm.f, T(m.lam_d), Xc);
-    if constexpr (ADJ) A.project(om.eh + 3 * j);
-    const T* pv = pvec + 6 * sl;
-    T om3[3], d[3], t[3], mm[3], rt[3];
-    const T w3[3] = {pv[3], pv[4], pv[5]};
-    cross3(w3, Xc, om3);
-    d[0] = pv[0] + om3[0];
-    d[1] = pv[1] + om3[1];
-    d[2] = pv[2] + om3[2];
-    A.apply(d, t);
-    A.applyT(t, mm);
-    const T w = om.w[j];
-    mm[0] *= w; mm[1] *= w; mm[2] *= w;
-    rot_tmul(cm, mm, rt);
-    y[0] += rt[0];
-    y[1] += rt[1];
-    y[2] += rt[2];
+  if (r < cp.Pa) {
+    const int e = cp.off[r + 1];
+    for (int j = cp.off[r] + l; j < e; j += G) {
+      const int s = cp.cam[j];
+      if (s >= cp.Ca) continue;   // fixed camera: no column in the solve
+      const V4<T> xw = om.pm_xcw[j];
+      const MvCam<T> mc = mvt[s];
+      const T Xc[3] = {xw.x, xw.y, xw.z};
+      AMat<T, ADJ> A;
+      A.set(mc.f, T(m.lam_d), Xc);
+      if constexpr (ADJ) A.project(om.eh + 3 * j);
+      T o3[3], d[3], tt[3], mm[3];
+      const T w3[3] = {mc.u[3], mc.u[4], mc.u[5]};
+      cross3(w3, Xc, o3);
+      d[0] = mc.u[0] + o3[0];
+      d[1] = mc.u[1] + o3[1];
+      d[2] = mc.u[2] + o3[2];
+      A.apply(d, tt);
+      A.applyT(tt, mm);
+      mm[0] *= xw.w; mm[1] *= xw.w; mm[2] *= xw.w;
+      // R^T m
+      y[0] += mc.R[0] * mm[0] + mc.R[3] * mm[1] + mc.R[6] * mm[2];
+      y[1] += mc.R[1] * mm[0] + mc.R[4] * mm[1] + mc.R[7] * mm[2];
+      y[2] += mc.R[2] * mm[0] + mc.R[5] * mm[1] + mc.R[8] * mm[2];
+    }
   }
-  const T* vi = Vinv + 6 * r;
-  zq[3 * r] = vi[0] * y[0] + vi[1] * y[1] + vi[2] * y[2];
-  zq[3 * r + 1] = vi[1] * y[0] + vi[3] * y[1] + vi[4] * y[2];
-  zq[3 * r + 2] = vi[2] * y[0] + vi[4] * y[1] + vi[5] * y[2];
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) {
+    y[0] += __shfl_xor(y[0], o, kWave);
+    y[1] += __shfl_xor(y[1], o, kWave);
+    y[2] += __shfl_xor(y[2], o, kWave);
+  }
+  if (r < cp.Pa && l == 0) {
+    const T* vi = Vinv + 6 * r;
+    V4<T> z;
+    z.x = vi[0] * y[0] + vi[1] * y[1] + vi[2] * y[2];
+    z.y = vi[1] * y[0] + vi[3] * y[1] + vi[4] * y[2];
+    z.z = vi[2] * y[0] + vi[4] * y[1] + vi[5] * y[2];
+    z.w = T(0);
+    zq[r] = z;
+  }
 }
 
+// Camera-major pass of S u, one 1024-thread workgroup per camera slot:
+//   w_s = U*_s u_s - sum_k W_k zq_p(k), then the camera's terms of r.u, w.u and r.r.
+// Per observation: the point rank and the streamed (X_c, w) 4-vector; zq is gathered.
+constexpr int kCamBlock = 1024;
+
 template <typename T, bool ADJ>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kCamBlock)
 k_schur_cam(Model m, Compact<T> cp, ObsMetric<T> om, const T* __restrict__ Ustar,
-            const T* __restrict__ pvec, const double* __restrict__ p64,
-            const T* __restrict__ zq, double* __restrict__ q, double* __restrict__ pq_part,
+            const double* __restrict__ u, const double* __restrict__ r,
+            const V4<T>* __restrict__ zq, double* __restrict__ w, double* __restrict__ dots,
             const PcgState* __restrict__ st) {
   if (st->done) return;
-  __shared__ T smem[6 * (kBlock / kWave)];
-  const int s = blockIdx.x;
-  const Cam<T> cm = cp.camt[cp.cam_src[s]];
+  // The grid is a multiple of 8: consecutive workgroups are dealt to the 8 XCDs in turn, and
+  // slot = xcd * per + i keeps each XCD on a contiguous camera range, so the z vectors of
+  // points shared by neighbouring cameras are reused from its own L2.
+  const int per = gridDim.x / 8;
+  const int s = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  const int Ca = cp.Ca;
+  if (s >= Ca) return;
+  __shared__ T smem[6 * (kCamBlock / kWave)];
+  const Cam<T> cm = cp.camt[s];
   T acc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
-  for (int i = cp.cm_off[s] + threadIdx.x; i < cp.cm_off[s + 1]; i += blockDim.x) {
-    const int r = cp.cm_pt[i];
-    T Xc[3];
-    cam_frame(cm, cp.Xt[3 * r], cp.Xt[3 * r + 1], cp.Xt[3 * r + 2], Xc);
+  const int end = cp.cm_off[s + 1];
+  for (int i = cp.cm_off[s] + threadIdx.x; i < end; i += blockDim.x) {
+    const V4<T> xw = om.xcw[i];
+    const V4<T> zv = zq[cp.cm_pt[i]];
+    const T Xc[3] = {xw.x, xw.y, xw.z};
     AMat<T, ADJ> A;
     A.set(cm.f, T(m.lam_d), Xc);
     if constexpr (ADJ) A.project(om.cm_eh + 3 * i);
-    const T zv[3] = {zq[3 * r], zq[3 * r + 1], zq[3 * r + 2]};
-    T u[3], t[3], mm[3], xm[3];
-    rot_mul(cm, zv, u);
-    A.apply(u, t);
+    const T z3[3] = {zv.x, zv.y, zv.z};
+    T uu[3], t[3], mm[3], xm[3];
+    rot_mul(cm, z3, uu);
+    A.apply(uu, t);
     A.applyT(t, mm);
-    const T w = om.cm_w[i];
-    mm[0] *= w; mm[1] *= w; mm[2] *= w;
+    mm[0] *= xw.w; mm[1] *= xw.w; mm[2] *= xw.w;
     cross3(Xc, mm, xm);
     acc[0] += mm[0]; acc[1] += mm[1]; acc[2] += mm[2];
     acc[3] += xm[0]; acc[4] += xm[1]; acc[5] += xm[2];
   }
   block_sum<T, 6>(acc, smem);
   if (threadIdx.x != 0) return;
-  double pv[6], qv[6];
+  double uv[6];
 #pragma unroll
-  for (int i = 0; i < 6; ++i) pv[i] = p64[6 * s + i];
-  double pq = 0.0;
+  for (int i = 0; i < 6; ++i) uv[i] = u[i * Ca + s];
+  double g = 0.0, d = 0.0, rr = 0.0;
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     double a = 0.0;
 #pragma unroll
-    for (int j = 0; j < 6; ++j) a += double(Ustar[21 * s + sym6(i, j)]) * pv[j];
-    qv[i] = a - double(acc[i]);
-    q[6 * s + i] = qv[i];
-    pq += pv[i] * qv[i];
+    for (int j = 0; j < 6; ++j) a += double(Ustar[sym6(i, j) * Ca + s]) * uv[j];
+    const double wi = a - double(acc[i]);
+    w[i * Ca + s] = wi;
+    const double ri = r[i * Ca + s];
+    g += ri * uv[i];
+    d += wi * uv[i];
+    rr += ri * ri;
   }
-  pq_part[s] = pq;
+  dots[s] = g;
+  dots[Ca + s] = d;
+  dots[2 * Ca + s] = rr;
 }
 
+// One Chronopoulos-Gear PCG iteration after the matvec w = S u:
+//   gamma = r.u, delta = w.u, rho = r.r (one reduction of the per-camera terms);
+//   stop if rho <= tol^2 b.b; beta = gamma / gamma_prev, alpha = gamma / (delta - beta gamma /
+//   alpha_prev); p = u + beta p; s = w + beta s; x += alpha p; r -= alpha s; u = M^-1 r.
+// One workgroup; every sum in a fixed order.
 template <typename T>
 __global__ void __launch_bounds__(1024)
-k_pcg_update(int Ca, const double* __restrict__ Minv, const double* __restrict__ q,
-             const double* __restrict__ pq_part, double* __restrict__ x, double* __restrict__ r,
-             double* __restrict__ z, double* __restrict__ p, T* __restrict__ pt, PcgState* st) {
-  __shared__ double smem[2 * (1024 / kWave)];
+k_pcg_update(int Ca, const double* __restrict__ Minv, const double* __restrict__ dots,
+             double* __restrict__ x, double* __restrict__ r, double* __restrict__ u,
+             double* __restrict__ p, double* __restrict__ sv, const double* __restrict__ w,
+             MvCam<T>* __restrict__ mvt, PcgState* st) {
+  __shared__ double smem[3 * (1024 / kWave)];
   __shared__ double s_bcast[2];
   __shared__ int s_done;
   if (threadIdx.x == 0) s_done = st->done;
   __syncthreads();
   if (s_done) return;
-  double acc1[1] = {0.0};
-  for (int s = threadIdx.x; s < Ca; s += blockDim.x) acc1[0] += pq_part[s];
-  block_sum<double, 1>(acc1, smem);
+  double acc[3] = {0.0, 0.0, 0.0};   // gamma, delta, rho
+  for (int s = threadIdx.x; s < Ca; s += blockDim.x) {
+    acc[0] += dots[s];
+    acc[1] += dots[Ca + s];
+    acc[2] += dots[2 * Ca + s];
+  }
+  block_sum<double, 3>(acc, smem);
   if (threadIdx.x == 0) {
-    const double pq = acc1[0];
-    int bad = !(pq > 0.0) || !isfinite(pq);
-    s_bcast[0] = bad ? 0.0 : st->rz / pq;
-    s_done = bad;
-    if (bad) {
-      st->breakdown = 1;
-      st->done = 1;
+    const double gamma = acc[0], delta = acc[1], rho = acc[2];
+    st->rr = rho;
+    st->matvecs += 1;
+    int done = rho <= st->tol2 * st->bb;
+    if (!done) {
+      const int it = st->iter;
+      const double beta = it == 0 ? 0.0 : gamma / st->gamma;
+      const double den = it == 0 ? delta : delta - beta * gamma / st->alpha;
+      const double alpha = gamma / den;
+      if (!(den > 0.0) || !(gamma > 0.0) || !isfinite(alpha) || !isfinite(beta)) {
+        st->breakdown = 1;
+        done = 1;
+      } else {
+        s_bcast[0] = alpha;
+        s_bcast[1] = beta;
+        st->gamma = gamma;
+        st->alpha = alpha;
+        st->iter = it + 1;
+        if (it + 1 >= st->max_iter) st->done = 1;
+      }
     }
+    if (done) st->done = 1;
+    s_done = done;
   }
   __syncthreads();
   if (s_done) return;
-  const double alpha = s_bcast[0];
-  double acc[2] = {0.0, 0.0};   // r.r, r.z
+  const double alpha = s_bcast[0], beta = s_bcast[1];
   for (int s = threadIdx.x; s < Ca; s += blockDim.x) {
-    double rv[6], zv[6];
+    double rv[6], uv[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-      x[6 * s + i] += alpha * p[6 * s + i];
-      rv[i] = r[6 * s + i] - alpha * q[6 * s + i];
-      r[6 * s + i] = rv[i];
+      const double pi = u[i * Ca + s] + beta * p[i * Ca + s];
+      const double si = w[i * Ca + s] + beta * sv[i * Ca + s];
+      p[i * Ca + s] = pi;
+      sv[i * Ca + s] = si;
+      x[i * Ca + s] += alpha * pi;
+      rv[i] = r[i * Ca + s] - alpha * si;
+      r[i * Ca + s] = rv[i];
     }
-    sym6_mul(Minv + 21 * s, rv, zv);
+    sym6_mul_soa(Minv, Ca, s, rv, uv);
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-      z[6 * s + i] = zv[i];
-      acc[0] += rv[i] * rv[i];
-      acc[1] += rv[i] * zv[i];
-    }
-  }
-  block_sum<double, 2>(acc, smem);
-  if (threadIdx.x == 0) {
-    const double beta = acc[1] / st->rz;
-    s_bcast[1] = beta;
-    st->rz = acc[1];
-    st->rr = acc[0];
-    st->iter += 1;
-    int done = (acc[0] <= st->tol2 * st->bb) || (st->iter >= st->max_iter);
-    if (!isfinite(acc[0]) || !isfinite(acc[1])) {
-      st->breakdown = 1;
-      done = 1;
-    }
-    st->done = done;
-  }
-  __syncthreads();
-  const double beta = s_bcast[1];
-  for (int s = threadIdx.x; s < Ca; s += blockDim.x) {
-#pragma unroll
-    for (int i = 0; i < 6; ++i) {
-      const double pv = z[6 * s + i] + beta * p[6 * s + i];
-      p[6 * s + i] = pv;
-      pt[6 * s + i] = T(pv);
+      u[i * Ca + s] = uv[i];
+      mvt[s].u[i] = T(uv[i]);
     }
   }
 }
 
-template <typename T, bool ADJ>
+// Back-substitution dp = Vinv (rhs_p - sum_k W_k^T x_c), same lane layout as the point pass.
+template <typename T, bool ADJ, int G>
 __global__ void __launch_bounds__(kBlock)
 k_backsub(Model m, Compact<T> cp, ObsMetric<T> om, const T* __restrict__ Vinv,
           const double* __restrict__ x, const double* __restrict__ gp,
           const double* __restrict__ rhs_p, double* __restrict__ dp) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= cp.Pa) return;
-  const T X0 = cp.Xt[3 * r], X1 = cp.Xt[3 * r + 1], X2 = cp.Xt[3 * r + 2];
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = t / G;
+  const int l = t % G;
+  const int Ca = cp.Ca;
   T y[3] = {T(0), T(0), T(0)};
-  for (int j = cp.off[r]; j < cp.off[r + 1]; ++j) {
-    const int c = cp.cam[j];
-    const int sl = cp.slot[c];
-    if (sl < 0) continue;
-    const Cam<T>& cm = cp.camt[c];
-    T Xc[3];
-    cam_frame(cm, X0, X1, X2, Xc);
-    AMat<T, ADJ> A;
-    A.set(cm.f, T(m.lam_d), Xc);
-    if constexpr (ADJ) A.project(om.eh + 3 * j);
-    const double* xv = x + 6 * sl;
-    const T w3[3] = {T(xv[3]), T(xv[4]), T(xv[5])};
-    T om3[3], d[3], t[3], mm[3], rt[3];
-    cross3(w3, Xc, om3);
-    d[0] = T(xv[0]) + om3[0];
-    d[1] = T(xv[1]) + om3[1];
-    d[2] = T(xv[2]) + om3[2];
-    A.apply(d, t);
-    A.applyT(t, mm);
-    const T w = om.w[j];
-    mm[0] *= w; mm[1] *= w; mm[2] *= w;
-    rot_tmul(cm, mm, rt);
-    y[0] += rt[0]; y[1] += rt[1]; y[2] += rt[2];
+  if (r < cp.Pa) {
+    const T X0 = cp.Xt[3 * r], X1 = cp.Xt[3 * r + 1], X2 = cp.Xt[3 * r + 2];
+    const int e = cp.off[r + 1];
+    for (int j = cp.off[r] + l; j < e; j += G) {
+      const int s = cp.cam[j];
+      if (s >= Ca) continue;
+      const Cam<T>& cm = cp.camt[s];
+      T Xc[3];
+      cam_frame(cm, X0, X1, X2, Xc);
+      AMat<T, ADJ> A;
+      A.set(cm.f, T(m.lam_d), Xc);
+      if constexpr (ADJ) A.project(om.eh + 3 * j);
+      const T w3[3] = {T(x[3 * Ca + s]), T(x[4 * Ca + s]), T(x[5 * Ca + s])};
+      T o3[3], d[3], tt[3], mm[3], rt[3];
+      cross3(w3, Xc, o3);
+      d[0] = T(x[s]) + o3[0];
+      d[1] = T(x[Ca + s]) + o3[1];
+      d[2] = T(x[2 * Ca + s]) + o3[2];
+      A.apply(d, tt);
+      A.applyT(tt, mm);
+      const T w = om.w[j];
+      mm[0] *= w; mm[1] *= w; mm[2] *= w;
+      rot_tmul(cm, mm, rt);
+      y[0] += rt[0]; y[1] += rt[1]; y[2] += rt[2];
+    }
   }
-  double b[3];
-  for (int i = 0; i < 3; ++i) b[i] = (rhs_p ? rhs_p[3 * r + i] : -gp[3 * r + i]) - double(y[i]);
-  const T* vi = Vinv + 6 * r;
-  dp[3 * r] = double(vi[0]) * b[0] + double(vi[1]) * b[1] + double(vi[2]) * b[2];
-  dp[3 * r + 1] = double(vi[1]) * b[0] + double(vi[3]) * b[1] + double(vi[4]) * b[2];
-  dp[3 * r + 2] = double(vi[2]) * b[0] + double(vi[4]) * b[1] + double(vi[5]) * b[2];
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) {
+    y[0] += __shfl_xor(y[0], o, kWave);
+    y[1] += __shfl_xor(y[1], o, kWave);
+    y[2] += __shfl_xor(y[2], o, kWave);
+  }
+  if (r < cp.Pa && l == 0) {
+    double b[3];
+    for (int i = 0; i < 3; ++i)
+      b[i] = (rhs_p ? rhs_p[3 * r + i] : -gp[3 * r + i]) - double(y[i]);
+    const T* vi = Vinv + 6 * r;
+    dp[3 * r] = double(vi[0]) * b[0] + double(vi[1]) * b[1] + double(vi[2]) * b[2];
+    dp[3 * r + 1] = double(vi[1]) * b[0] + double(vi[3]) * b[1] + double(vi[4]) * b[2];
+    dp[3 * r + 2] = double(vi[2]) * b[0] + double(vi[4]) * b[1] + double(vi[5]) * b[2];
+  }
 }
 
 // ------------------------------------------------------------------ candidate
 // Left SE(3) update of a (quaternion, centre) camera: q' = q(phi) (x) q, c' = c - R'^T V rho.
 __global__ void __launch_bounds__(kBlock)
-k_cam_candidate(int C, const int* __restrict__ slot, const double* __restrict__ x,
-                const double* __restrict__ cams, const double* __restrict__ intr,
-                const Cam<double>* __restrict__ camd, double* __restrict__ cand_cams,
-                Cam<double>* __restrict__ cand_tab) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= C) return;
-  const int sl = slot[c];
-  if (sl < 0) {
-    for (int i = 0; i < 7; ++i) cand_cams[7 * c + i] = cams[7 * c + i];
-    cand_tab[c] = camd[c];
+k_cam_candidate(int Ca, int Cf, const int* __restrict__ cam_src, const double* __restrict__ x,
+                const double* __restrict__ cams, const Cam<double>* __restrict__ camd_hat,
+                double* __restrict__ cand_cams, Cam<double>* __restrict__ cand_tab) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= Ca + Cf) return;
+  if (s >= Ca) {             // fixed camera: unchanged
+    cand_tab[s] = camd_hat[s];
     return;
   }
-  const double* xi = x + 6 * sl;
-  const double rho[3] = {xi[0], xi[1], xi[2]};
-  const double phi[3] = {xi[3], xi[4], xi[5]};
+  const int c = cam_src[s];
+  const double rho[3] = {x[s], x[Ca + s], x[2 * Ca + s]};
+  const double phi[3] = {x[3 * Ca + s], x[4 * Ca + s], x[5 * Ca + s]};
   const double t2 = phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2];
   const double th = sqrt(t2);
-  double bco, cco, hco, cw;
+  double bco, cco, hco;
   if (th < 1e-2) {   // Taylor series where the closed forms lose digits
     bco = 0.5 - t2 / 24.0 + t2 * t2 / 720.0;
     cco = 1.0 / 6.0 - t2 / 120.0 + t2 * t2 / 5040.0;
@@ -1041,8 +1141,7 @@ k_cam_candidate(int C, const int* __restrict__ slot, const double* __restrict__ 
     cco = (th - sin(th)) / (t2 * th);
     hco = sin(0.5 * th) / th;
   }
-  cw = cos(0.5 * th);
-  // q' = (cw, hco phi) (x) q
+  const double cw = cos(0.5 * th);
   double qw = cams[7 * c], qx = cams[7 * c + 1], qy = cams[7 * c + 2], qz = cams[7 * c + 3];
   double n = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
   qw /= n; qx /= n; qy /= n; qz /= n;
@@ -1053,7 +1152,7 @@ k_cam_candidate(int C, const int* __restrict__ slot, const double* __restrict__ 
   double nz = aw * qz + qw * az + (ax * qy - ay * qx);
   n = sqrt(nw * nw + nx * nx + ny * ny + nz * nz);
   nw /= n; nx /= n; ny /= n; nz /= n;
-  Cam<double> d;
+  Cam<double> d = camd_hat[s];
   d.R[0] = 1 - 2 * (ny * ny + nz * nz);
   d.R[1] = 2 * (nx * ny - nw * nz);
   d.R[2] = 2 * (nx * nz + nw * ny);
@@ -1072,17 +1171,14 @@ k_cam_candidate(int C, const int* __restrict__ slot, const double* __restrict__ 
   d.c[0] = cams[7 * c + 4] - rv[0];
   d.c[1] = cams[7 * c + 5] - rv[1];
   d.c[2] = cams[7 * c + 6] - rv[2];
-  d.f = intr[3 * c];
-  d.cx = intr[3 * c + 1];
-  d.cy = intr[3 * c + 2];
-  cand_tab[c] = d;
-  cand_cams[7 * c] = nw;
-  cand_cams[7 * c + 1] = nx;
-  cand_cams[7 * c + 2] = ny;
-  cand_cams[7 * c + 3] = nz;
-  cand_cams[7 * c + 4] = d.c[0];
-  cand_cams[7 * c + 5] = d.c[1];
-  cand_cams[7 * c + 6] = d.c[2];
+  cand_tab[s] = d;
+  cand_cams[7 * s] = nw;
+  cand_cams[7 * s + 1] = nx;
+  cand_cams[7 * s + 2] = ny;
+  cand_cams[7 * s + 3] = nz;
+  cand_cams[7 * s + 4] = d.c[0];
+  cand_cams[7 * s + 5] = d.c[1];
+  cand_cams[7 * s + 6] = d.c[2];
 }
 
 // Candidate cost (float64) over the same active observations, the quadratic term of the
@@ -1096,6 +1192,7 @@ k_point_candidate(Model m, Compact<T> cp, const Cam<double>* __restrict__ cand_t
                   double* __restrict__ Xcand, double* __restrict__ partials) {
   __shared__ double smem[4 * (kBlock / kWave)];
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int Ca = cp.Ca;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};   // cost', quad, g_p.dp, bad
   if (r < cp.Pa) {
     const double X[3] = {cp.Xd[3 * r], cp.Xd[3 * r + 1], cp.Xd[3 * r + 2]};
@@ -1106,8 +1203,8 @@ k_point_candidate(Model m, Compact<T> cp, const Cam<double>* __restrict__ cand_t
     Xcand[3 * r + 2] = Xn[2];
     acc[2] = gp[3 * r] * d[0] + gp[3 * r + 1] * d[1] + gp[3 * r + 2] * d[2];
     for (int j = cp.off[r]; j < cp.off[r + 1]; ++j) {
-      const int c = cp.cam[j];
-      const Cam<double> cn = cand_tab[c];
+      const int s = cp.cam[j];
+      const Cam<double> cn = cand_tab[s];
       double Xc[3];
       cam_frame(cn, Xn[0], Xn[1], Xn[2], Xc);
       if (!(Xc[2] > m.min_depth)) {
@@ -1119,19 +1216,17 @@ k_point_candidate(Model m, Compact<T> cp, const Cam<double>* __restrict__ cand_t
         acc[0] += 0.5 * rho;
       }
       // model term at the linearisation point
-      const Cam<double> cm = cp.camd[c];
+      const Cam<double> cm = cp.camd[s];
       double Xl[3], v[3], t[3];
       cam_frame(cm, X[0], X[1], X[2], Xl);
       rot_mul(cm, d, v);
-      const int sl = cp.slot[c];
-      if (sl >= 0) {
-        const double* xv = x + 6 * sl;
-        const double w3[3] = {xv[3], xv[4], xv[5]};
+      if (s < Ca) {
+        const double w3[3] = {x[3 * Ca + s], x[4 * Ca + s], x[5 * Ca + s]};
         double o3[3];
         cross3(w3, Xl, o3);
-        v[0] += xv[0] + o3[0];
-        v[1] += xv[1] + o3[1];
-        v[2] += xv[2] + o3[2];
+        v[0] += x[s] + o3[0];
+        v[1] += x[Ca + s] + o3[1];
+        v[2] += x[2 * Ca + s] + o3[2];
       }
       AMat<double, false> A;
       A.set(cm.f, m.lam_d, Xl);
@@ -1150,39 +1245,45 @@ __global__ void __launch_bounds__(1024)
 k_reduce_partials(int nb, int K, const double* __restrict__ partials, unsigned max_mask,
                   int Ca, const double* __restrict__ gc, const double* __restrict__ x,
                   double* __restrict__ out) {
-  __shared__ double smem[8 * (1024 / kWave)];
-  double acc[8];
-  for (int k = 0; k < 8; ++k) acc[k] = 0.0;
+  constexpr int KM = 8;
+  __shared__ double smem[KM * (1024 / kWave)];
+  double acc[KM];
+  for (int k = 0; k < KM; ++k) acc[k] = 0.0;
   for (int b = threadIdx.x; b < nb; b += blockDim.x) {
     for (int k = 0; k < K; ++k) {
       const double v = partials[K * b + k];
       acc[k] = ((max_mask >> k) & 1u) ? fmax(acc[k], v) : acc[k] + v;
     }
   }
+  unsigned mask = max_mask;
+  int nout = K;
   if (gc) {
-    for (int s = threadIdx.x; s < Ca; s += blockDim.x)
-      for (int i = 0; i < 6; ++i) acc[K] += gc[6 * s + i] * x[6 * s + i];
+    // gc . x over the 6 Ca camera unknowns, and max |gc|
+    for (int e = threadIdx.x; e < 6 * Ca; e += blockDim.x) {
+      acc[K] += gc[e] * x[e];
+      acc[K + 1] = fmax(acc[K + 1], fabs(gc[e]));
+    }
+    mask |= 1u << (K + 1);
+    nout = K + 2;
   }
-  // fixed-order reduction: sums via wave_sum, maxima via wave_max
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  for (int k = 0; k <= K && k < 8; ++k)
-    acc[k] = ((max_mask >> k) & 1u) ? wave_max(acc[k]) : wave_sum(acc[k]);
+  for (int k = 0; k < KM; ++k) acc[k] = ((mask >> k) & 1u) ? wave_max(acc[k]) : wave_sum(acc[k]);
   if (lane == 0)
-    for (int k = 0; k < 8; ++k) smem[8 * wid + k] = acc[k];
+    for (int k = 0; k < KM; ++k) smem[KM * wid + k] = acc[k];
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int k = 0; k <= K && k < 8; ++k) {
+    for (int k = 0; k < nout; ++k) {
       double a = smem[k];
       for (int w = 1; w < int(blockDim.x) / kWave; ++w)
-        a = ((max_mask >> k) & 1u) ? fmax(a, smem[8 * w + k]) : a + smem[8 * w + k];
+        a = ((mask >> k) & 1u) ? fmax(a, smem[KM * w + k]) : a + smem[KM * w + k];
       out[k] = a;
     }
   }
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_scatter(int Pa, int C, const int* __restrict__ pt_src, const double* __restrict__ Xcand,
-          const int* __restrict__ slot, const double* __restrict__ cand_cams,
+k_scatter(int Pa, int Ca, const int* __restrict__ pt_src, const double* __restrict__ Xcand,
+          const int* __restrict__ cam_src, const double* __restrict__ cand_cams,
           double* __restrict__ pts, double* __restrict__ cams) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < Pa) {
@@ -1191,14 +1292,15 @@ k_scatter(int Pa, int C, const int* __restrict__ pt_src, const double* __restric
     pts[3 * p + 1] = Xcand[3 * i + 1];
     pts[3 * p + 2] = Xcand[3 * i + 2];
   }
-  if (i < C && slot[i] >= 0) {
-    for (int k = 0; k < 7; ++k) cams[7 * i + k] = cand_cams[7 * i + k];
+  if (i < Ca) {
+    const int c = cam_src[i];
+    for (int k = 0; k < 7; ++k) cams[7 * c + k] = cand_cams[7 * i + k];
   }
 }
 
 // ------------------------------------------------------------------ adjoint
 // Tangent mapping of camera gradients: dL/drho = -R dL/dc, dL/dphi = (dq/dphi)^T dL/dq with
-// dq/dphi = 1/2 [-q_v^T ; q_w I - [q_v]x].
+// dq/dphi = 1/2 [-q_v^T ; q_w I - [q_v]x]. Output SoA like every camera vector.
 __global__ void __launch_bounds__(kBlock)
 k_adjoint_rhs(int Ca, int Pa, const int* __restrict__ cam_src, const double* __restrict__ cams,
               const double* __restrict__ grad_cams, const int* __restrict__ pt_src,
@@ -1228,8 +1330,8 @@ k_adjoint_rhs(int Ca, int Pa, const int* __restrict__ cam_src, const double* __r
     double cx[3];
     cross3(qv, gv, cx);
     for (int k = 0; k < 3; ++k) {
-      rhs_c[6 * i + k] = -rg[k];
-      rhs_c[6 * i + 3 + k] = 0.5 * (-g[0] * qv[k] + qw * gv[k] + cx[k]);
+      rhs_c[k * Ca + i] = -rg[k];
+      rhs_c[(3 + k) * Ca + i] = 0.5 * (-g[0] * qv[k] + qw * gv[k] + cx[k]);
     }
   }
   if (i < Pa) {
@@ -1249,23 +1351,22 @@ k_adjoint_obs(Model m, Compact<T> cp, ObsMetric<T> om, const double* __restrict_
               float* __restrict__ gxy, float* __restrict__ gdepth) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= cp.Pa) return;
+  const int Ca = cp.Ca;
   const double X0 = cp.Xd[3 * r], X1 = cp.Xd[3 * r + 1], X2 = cp.Xd[3 * r + 2];
   const double vp[3] = {dp[3 * r], dp[3 * r + 1], dp[3 * r + 2]};
   for (int j = cp.off[r]; j < cp.off[r + 1]; ++j) {
-    const int c = cp.cam[j];
-    const Cam<double> cm = cp.camd[c];
+    const int s = cp.cam[j];
+    const Cam<double> cm = cp.camd[s];
     double Xc[3], d[3], t[3];
     cam_frame(cm, X0, X1, X2, Xc);
     rot_mul(cm, vp, d);
-    const int sl = cp.slot[c];
-    if (sl >= 0) {
-      const double* xv = x + 6 * sl;
-      const double w3[3] = {xv[3], xv[4], xv[5]};
+    if (s < Ca) {
+      const double w3[3] = {x[3 * Ca + s], x[4 * Ca + s], x[5 * Ca + s]};
       double o3[3];
       cross3(w3, Xc, o3);
-      d[0] += xv[0] + o3[0];
-      d[1] += xv[1] + o3[1];
-      d[2] += xv[2] + o3[2];
+      d[0] += x[s] + o3[0];
+      d[1] += x[Ca + s] + o3[1];
+      d[2] += x[2 * Ca + s] + o3[2];
     }
     AMat<double, true> A;
     A.set(cm.f, m.lam_d, Xc);
@@ -1333,20 +1434,29 @@ void launch_compact_points(hipStream_t s, int P, const uint8_t* act_p, const int
                      rank_p, pt_off, pos_pm, pts, pt_src, off_hat, Xd, Xf);
 }
 
-void launch_compact_obs(hipStream_t s, int64_t N, const uint8_t* vrow, const int* pos_pm,
-                        const int* pm_cam, const float2* pm_xy, const float* pm_depth,
-                        const int* pm_orig, int* cam_hat, float2* xy_hat, float* depth_hat,
-                        int* orig_hat) {
-  if (N == 0) return;
-  hipLaunchKernelGGL(k_compact_obs, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, vrow, pos_pm,
-                     pm_cam, pm_xy, pm_depth, pm_orig, cam_hat, xy_hat, depth_hat, orig_hat);
+void launch_compact_cams(hipStream_t s, int C, const uint8_t* act_c, const int* rank_c,
+                         const uint8_t* fixed, const int* fixed_rank, const int* cm_off,
+                         const int* pos_cm, int* slot_all, int* cam_src, int* cm_off_hat) {
+  hipLaunchKernelGGL(k_compact_cams, dim3(blocks_for(C)), dim3(kBlock), 0, s, C, act_c, rank_c,
+                     fixed, fixed_rank, cm_off, pos_cm, slot_all, cam_src, cm_off_hat);
 }
 
-void launch_compact_cams(hipStream_t s, int C, const uint8_t* act_c, const int* rank_c,
-                         const int* cm_off, const int* pos_cm, int* slot, int* cam_src,
-                         int* cm_off_hat) {
-  hipLaunchKernelGGL(k_compact_cams, dim3(blocks_for(C)), dim3(kBlock), 0, s, C, act_c, rank_c,
-                     cm_off, pos_cm, slot, cam_src, cm_off_hat);
+void launch_compact_cam_table(hipStream_t s, int n, const int* cam_src,
+                              const Cam<double>* camd, const Cam<float>* camf,
+                              Cam<double>* camd_hat, Cam<float>* camf_hat) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_compact_cam_table, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, cam_src,
+                     camd, camf, camd_hat, camf_hat);
+}
+
+void launch_compact_obs(hipStream_t s, int64_t N, const uint8_t* vrow, const int* pos_pm,
+                        const int* pm_cam, const int* slot_all, const float2* pm_xy,
+                        const float* pm_depth, const int* pm_orig, int* cam_hat,
+                        float2* xy_hat, float* depth_hat, int* orig_hat) {
+  if (N == 0) return;
+  hipLaunchKernelGGL(k_compact_obs, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, vrow, pos_pm,
+                     pm_cam, slot_all, pm_xy, pm_depth, pm_orig, cam_hat, xy_hat, depth_hat,
+                     orig_hat);
 }
 
 void launch_compact_cm(hipStream_t s, int64_t N, const int* cm_perm, const uint8_t* vrow,
@@ -1371,15 +1481,15 @@ void launch_lin_point(hipStream_t s, bool adj, const Model& m, const Compact<T>&
 }
 
 template <typename T>
-void launch_gather_cm_metric(hipStream_t s, bool adj, int64_t Nc, const int* cm_pm,
-                             ObsMetric<T> om) {
+void launch_cm_prepare(hipStream_t s, bool adj, int64_t Nc, const Compact<T>& cp,
+                       ObsMetric<T> om) {
   if (Nc == 0) return;
   if (adj)
-    hipLaunchKernelGGL((k_gather_cm_metric<T, true>), dim3(blocks_for(Nc)), dim3(kBlock), 0, s,
-                       Nc, cm_pm, om);
+    hipLaunchKernelGGL((k_cm_prepare<T, true>), dim3(blocks_for(Nc)), dim3(kBlock), 0, s, Nc,
+                       cp, om);
   else
-    hipLaunchKernelGGL((k_gather_cm_metric<T, false>), dim3(blocks_for(Nc)), dim3(kBlock), 0,
-                       s, Nc, cm_pm, om);
+    hipLaunchKernelGGL((k_cm_prepare<T, false>), dim3(blocks_for(Nc)), dim3(kBlock), 0, s, Nc,
+                       cp, om);
 }
 
 template <typename T>
@@ -1405,64 +1515,114 @@ void launch_cam_assemble(hipStream_t s, bool adj, const Model& m, const Compact<
 }
 
 template <typename T>
-void launch_pcg_init(hipStream_t s, int Ca, const double* b, const double* Minv, double* x,
-                     double* r, double* z, double* p, T* pt, PcgState* st, double tol2,
-                     int max_iter) {
-  hipLaunchKernelGGL(k_pcg_init<T>, dim3(1), dim3(1024), 0, s, Ca, b, Minv, x, r, z, p, pt, st,
-                     tol2, max_iter);
+void launch_mv_table(hipStream_t s, int n, const Cam<double>* camd_hat, MvCam<T>* mvt) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_mv_table<T>, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, camd_hat, mvt);
 }
 
 template <typename T>
-void launch_schur_point(hipStream_t s, bool adj, const Model& m, const Compact<T>& cp,
-                        ObsMetric<T> om, const T* Vinv, const T* pvec, T* zq,
+void launch_pcg_init(hipStream_t s, int Ca, const double* b, const double* Minv, double* x,
+                     double* r, double* u, double* p, double* sv, MvCam<T>* mvt, PcgState* st,
+                     double tol2, int max_iter) {
+  hipLaunchKernelGGL(k_pcg_init<T>, dim3(1), dim3(1024), 0, s, Ca, b, Minv, x, r, u, p, sv, mvt,
+                     st, tol2, max_iter);
+}
+
+template <typename T, bool ADJ>
+void schur_point_g(hipStream_t s, int G, const Model& m, const Compact<T>& cp, ObsMetric<T> om,
+                   const MvCam<T>* mvt, const T* Vinv, V4<T>* zq, const PcgState* st) {
+  const unsigned nb = blocks_for(int64_t(cp.Pa) * G);
+  switch (G) {
+    case 2:
+      hipLaunchKernelGGL((k_schur_point<T, ADJ, 2>), dim3(nb), dim3(kBlock), 0, s, m, cp, om,
+                         mvt, Vinv, zq, st);
+      break;
+    case 4:
+      hipLaunchKernelGGL((k_schur_point<T, ADJ, 4>), dim3(nb), dim3(kBlock), 0, s, m, cp, om,
+                         mvt, Vinv, zq, st);
+      break;
+    case 16:
+      hipLaunchKernelGGL((k_schur_point<T, ADJ, 16>), dim3(nb), dim3(kBlock), 0, s, m, cp, om,
+                         mvt, Vinv, zq, st);
+      break;
+    default:
+      hipLaunchKernelGGL((k_schur_point<T, ADJ, 8>), dim3(nb), dim3(kBlock), 0, s, m, cp, om,
+                         mvt, Vinv, zq, st);
+  }
+}
+
+template <typename T>
+void launch_schur_point(hipStream_t s, bool adj, int G, const Model& m, const Compact<T>& cp,
+                        ObsMetric<T> om, const MvCam<T>* mvt, const T* Vinv, V4<T>* zq,
                         const PcgState* st) {
-  const unsigned nb = blocks_for(cp.Pa);
   if (adj)
-    hipLaunchKernelGGL((k_schur_point<T, true>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, Vinv,
-                       pvec, zq, st);
+    schur_point_g<T, true>(s, G, m, cp, om, mvt, Vinv, zq, st);
   else
-    hipLaunchKernelGGL((k_schur_point<T, false>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, Vinv,
-                       pvec, zq, st);
+    schur_point_g<T, false>(s, G, m, cp, om, mvt, Vinv, zq, st);
 }
 
 template <typename T>
 void launch_schur_cam(hipStream_t s, bool adj, const Model& m, const Compact<T>& cp,
-                      ObsMetric<T> om, const T* Ustar, const T* pvec, const double* p64,
-                      const T* zq, double* q, double* pq_part, const PcgState* st) {
+                      ObsMetric<T> om, const T* Ustar, const double* u, const double* r,
+                      const V4<T>* zq, double* w, double* dots, const PcgState* st) {
+  if (cp.Ca <= 0) return;
+  const unsigned grid = unsigned((cp.Ca + 7) / 8 * 8);   // one share per XCD
   if (adj)
-    hipLaunchKernelGGL((k_schur_cam<T, true>), dim3(cp.Ca), dim3(kBlock), 0, s, m, cp, om, Ustar,
-                       pvec, p64, zq, q, pq_part, st);
+    hipLaunchKernelGGL((k_schur_cam<T, true>), dim3(grid), dim3(kCamBlock), 0, s, m, cp, om,
+                       Ustar, u, r, zq, w, dots, st);
   else
-    hipLaunchKernelGGL((k_schur_cam<T, false>), dim3(cp.Ca), dim3(kBlock), 0, s, m, cp, om,
-                       Ustar, pvec, p64, zq, q, pq_part, st);
+    hipLaunchKernelGGL((k_schur_cam<T, false>), dim3(grid), dim3(kCamBlock), 0, s, m, cp, om,
+                       Ustar, u, r, zq, w, dots, st);
 }
 
 template <typename T>
-void launch_pcg_update(hipStream_t s, int Ca, const double* Minv, const double* q,
-                       const double* pq_part, double* x, double* r, double* z, double* p,
-                       T* pt, PcgState* st) {
-  hipLaunchKernelGGL(k_pcg_update<T>, dim3(1), dim3(1024), 0, s, Ca, Minv, q, pq_part, x, r, z,
-                     p, pt, st);
+void launch_pcg_update(hipStream_t s, int Ca, const double* Minv, const double* dots,
+                       double* x, double* r, double* u, double* p, double* sv, const double* w,
+                       MvCam<T>* mvt, PcgState* st) {
+  hipLaunchKernelGGL(k_pcg_update<T>, dim3(1), dim3(1024), 0, s, Ca, Minv, dots, x, r, u, p, sv,
+                     w, mvt, st);
+}
+
+template <typename T, bool ADJ>
+void backsub_g(hipStream_t s, int G, const Model& m, const Compact<T>& cp, ObsMetric<T> om,
+               const T* Vinv, const double* x, const double* gp, const double* rhs_p,
+               double* dp) {
+  const unsigned nb = blocks_for(int64_t(cp.Pa) * G);
+  switch (G) {
+    case 2:
+      hipLaunchKernelGGL((k_backsub<T, ADJ, 2>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, Vinv,
+                         x, gp, rhs_p, dp);
+      break;
+    case 4:
+      hipLaunchKernelGGL((k_backsub<T, ADJ, 4>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, Vinv,
+                         x, gp, rhs_p, dp);
+      break;
+    case 16:
+      hipLaunchKernelGGL((k_backsub<T, ADJ, 16>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, Vinv,
+                         x, gp, rhs_p, dp);
+      break;
+    default:
+      hipLaunchKernelGGL((k_backsub<T, ADJ, 8>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, Vinv,
+                         x, gp, rhs_p, dp);
+  }
 }
 
 template <typename T>
-void launch_backsub(hipStream_t s, bool adj, const Model& m, const Compact<T>& cp,
+void launch_backsub(hipStream_t s, bool adj, int G, const Model& m, const Compact<T>& cp,
                     ObsMetric<T> om, const T* Vinv, const double* x, const double* gp,
                     const double* rhs_p, double* dp) {
-  const unsigned nb = blocks_for(cp.Pa);
   if (adj)
-    hipLaunchKernelGGL((k_backsub<T, true>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, Vinv, x,
-                       gp, rhs_p, dp);
+    backsub_g<T, true>(s, G, m, cp, om, Vinv, x, gp, rhs_p, dp);
   else
-    hipLaunchKernelGGL((k_backsub<T, false>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, Vinv, x,
-                       gp, rhs_p, dp);
+    backsub_g<T, false>(s, G, m, cp, om, Vinv, x, gp, rhs_p, dp);
 }
 
-void launch_cam_candidate(hipStream_t s, int C, const int* slot, const double* x,
-                          const double* cams, const double* intr, const Cam<double>* camd,
-                          double* cand_cams, Cam<double>* cand_tab) {
-  hipLaunchKernelGGL(k_cam_candidate, dim3(blocks_for(C)), dim3(kBlock), 0, s, C, slot, x, cams,
-                     intr, camd, cand_cams, cand_tab);
+void launch_cam_candidate(hipStream_t s, int Ca, int Cf, const int* cam_src, const double* x,
+                          const double* cams, const Cam<double>* camd_hat, double* cand_cams,
+                          Cam<double>* cand_tab) {
+  if (Ca + Cf == 0) return;
+  hipLaunchKernelGGL(k_cam_candidate, dim3(blocks_for(Ca + Cf)), dim3(kBlock), 0, s, Ca, Cf,
+                     cam_src, x, cams, camd_hat, cand_cams, cand_tab);
 }
 
 template <typename T>
@@ -1480,17 +1640,19 @@ void launch_reduce_partials(hipStream_t s, int nblocks, int K, const double* par
                      max_mask, Ca, gc, x, out);
 }
 
-void launch_scatter(hipStream_t s, int Pa, int C, const int* pt_src, const double* Xcand,
-                    const int* slot, const double* cand_cams, double* pts, double* cams) {
-  const int n = Pa > C ? Pa : C;
-  hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n)), dim3(kBlock), 0, s, Pa, C, pt_src, Xcand,
-                     slot, cand_cams, pts, cams);
+void launch_scatter(hipStream_t s, int Pa, int Ca, const int* pt_src, const double* Xcand,
+                    const int* cam_src, const double* cand_cams, double* pts, double* cams) {
+  const int n = Pa > Ca ? Pa : Ca;
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n)), dim3(kBlock), 0, s, Pa, Ca, pt_src, Xcand,
+                     cam_src, cand_cams, pts, cams);
 }
 
 void launch_adjoint_rhs(hipStream_t s, int Ca, int Pa, const int* cam_src, const double* cams,
                         const double* grad_cams, const int* pt_src, const int* pt_user,
                         const double* grad_pts, double* rhs_c, double* rhs_p) {
   const int n = Pa > Ca ? Pa : Ca;
+  if (n == 0) return;
   hipLaunchKernelGGL(k_adjoint_rhs, dim3(blocks_for(n)), dim3(kBlock), 0, s, Ca, Pa, cam_src,
                      cams, grad_cams, pt_src, pt_user, grad_pts, rhs_c, rhs_p);
 }
@@ -1507,25 +1669,28 @@ void launch_adjoint_obs(hipStream_t s, const Model& m, const Compact<T>& cp, Obs
 #define IBA_INSTANTIATE(T)                                                                    \
   template void launch_lin_point<T>(hipStream_t, bool, const Model&, const Compact<T>&,       \
                                     ObsMetric<T>, T*, double*, double*);                      \
-  template void launch_gather_cm_metric<T>(hipStream_t, bool, int64_t, const int*,            \
-                                           ObsMetric<T>);                                      \
+  template void launch_cm_prepare<T>(hipStream_t, bool, int64_t, const Compact<T>&,           \
+                                     ObsMetric<T>);                                            \
   template void launch_point_damp<T>(hipStream_t, int, double, double, double, const T*,      \
                                      const double*, const double*, T*, double*, int*);        \
   template void launch_cam_assemble<T>(hipStream_t, bool, const Model&, const Compact<T>&,    \
                                        ObsMetric<T>, double, double, double, const T*,        \
                                        const double*, const double*, double*, T*, double*,    \
                                        double*, double*);                                      \
+  template void launch_mv_table<T>(hipStream_t, int, const Cam<double>*, MvCam<T>*);         \
   template void launch_pcg_init<T>(hipStream_t, int, const double*, const double*, double*,   \
-                                   double*, double*, double*, T*, PcgState*, double, int);    \
-  template void launch_schur_point<T>(hipStream_t, bool, const Model&, const Compact<T>&,     \
-                                      ObsMetric<T>, const T*, const T*, T*, const PcgState*); \
+                                   double*, double*, double*, double*, MvCam<T>*, PcgState*,  \
+                                   double, int);                                               \
+  template void launch_schur_point<T>(hipStream_t, bool, int, const Model&, const Compact<T>&,\
+                                      ObsMetric<T>, const MvCam<T>*, const T*, V4<T>*,        \
+                                      const PcgState*);                                        \
   template void launch_schur_cam<T>(hipStream_t, bool, const Model&, const Compact<T>&,       \
-                                    ObsMetric<T>, const T*, const T*, const double*,          \
-                                    const T*, double*, double*, const PcgState*);             \
-  template void launch_pcg_update<T>(hipStream_t, int, const double*, const double*,          \
-                                     const double*, double*, double*, double*, double*, T*,   \
-                                     PcgState*);                                               \
-  template void launch_backsub<T>(hipStream_t, bool, const Model&, const Compact<T>&,         \
+                                    ObsMetric<T>, const T*, const double*, const double*,     \
+                                    const V4<T>*, double*, double*, const PcgState*);         \
+  template void launch_pcg_update<T>(hipStream_t, int, const double*, const double*, double*, \
+                                     double*, double*, double*, double*, const double*,       \
+                                     MvCam<T>*, PcgState*);                                    \
+  template void launch_backsub<T>(hipStream_t, bool, int, const Model&, const Compact<T>&,    \
                                   ObsMetric<T>, const T*, const double*, const double*,       \
                                   const double*, double*);                                     \
   template void launch_point_candidate<T>(hipStream_t, const Model&, const Compact<T>&,       \
