@@ -73,10 +73,12 @@ typedef struct ba_options {
   int32_t pcg_check_every; /* PCG iterations enqueued between host convergence checks; 8 */
   double pcg_rel_tol;      /* stop when |r| <= tol |b|; 1e-6 */
   double cost_rel_tol;     /* ba_solve: stop when an accepted step lowers the cost by at most
-                              this fraction; 1e-10 */
+                              this fraction (per-observation sum of the changes); 1e-10 */
   double grad_tol;         /* ba_solve: stop when max |g| <= grad_tol; 1e-10 */
   int32_t max_lm_iters;    /* ba_solve iteration cap; 100 */
   int32_t timing;          /* 1: time phases and kernels with HIP events (ba_kernel_stats) */
+  int32_t adjoint_max_iters;/* PCG cap of the (undamped) adjoint solve; 5000 */
+  double adjoint_rel_tol;  /* PCG tolerance of the adjoint solve; 1e-10 */
   void* hip_stream;        /* hipStream_t to run on; NULL: a stream owned by the context */
 } ba_options;
 
@@ -90,7 +92,8 @@ typedef struct ba_step_report {
   int32_t n_cams_active, n_points_active;
   int64_t n_obs_active;
   double cost_before;      /* F = 1/2 sum rho(|e|^2) over the active observations */
-  double cost_after;       /* F at the candidate (+inf if a depth drops below min_depth) */
+  double cost_after;       /* F at the candidate, as F minus the per-observation sum of the
+                              changes (+inf if a depth drops below min_depth) */
   double model_decrease;   /* -(g.delta + 1/2 sum w |J delta|^2) */
   double gain_ratio;
   double lambda;           /* damping used by this step */

@@ -15,7 +15,8 @@ One LM iteration, following Sec. III-C and Sec. IV-B:
    back-substitution;
 5. the candidate ``theta (+) delta`` (left SE(3) update for cameras, additive for points),
    its cost over the same active observations (+inf if one of them has z <= min_depth),
-   the gain ratio against the model decrease ``-(g^T delta + 1/2 |W^(1/2) J delta|^2)``;
+   the gain ratio of the actual reduction (summed per observation) against the model
+   decrease ``-(g^T delta + 1/2 |W^(1/2) J delta|^2)``;
 6. accept when the cost drops and the ratio exceeds 1e-3, then scatter the compact update
    into the full arrays (inactive entries untouched); lambda follows Nielsen's rule
    (accept: lambda *= max(1/3, 1 - (2 rho - 1)^3), nu = 2; reject: lambda *= nu, nu *= 2).
@@ -248,13 +249,19 @@ def lm_step(prob: Problem, st: State, opts: Options):
     cand = candidate(st, ex, delta)
     e2, Xc2, _ = residuals(prob, cand.q, cand.c, cand.X, ex.obs)
     if np.any(Xc2[:, 2] <= opts.min_depth):
-        F2 = np.inf
+        F2, dF = np.inf, -np.inf
     else:
-        F2 = 0.5 * float(np.sum(huber(np.sum(e2 * e2, axis=1), opts.huber_px)[0]))
-    rep.cost_after = F2
-    ratio = (F - F2) / model if (model > 0 and np.isfinite(F2)) else -np.inf
+        rho2 = huber(np.sum(e2 * e2, axis=1), opts.huber_px)[0]
+        F2 = 0.5 * float(np.sum(rho2))
+        # actual reduction F(theta) - F(theta (+) delta), summed per observation so that its
+        # rounding error scales with the changes rather than with F
+        dF = 0.5 * float(np.sum(lin.rho - rho2))
+    # reported as F - (per-observation reduction), consistent with the acceptance test
+    rep.cost_after = F - dF if np.isfinite(F2) else np.inf
+    ratio = dF / model if (model > 0 and np.isfinite(F2)) else -np.inf
     rep.gain_ratio = ratio
-    rep.accepted = bool(np.isfinite(F2) and F2 < F and ratio > opts.accept_ratio)
+    rep.extra["actual_decrease"] = dF
+    rep.accepted = bool(np.isfinite(F2) and dF > 0 and ratio > opts.accept_ratio)
     if rep.accepted:
         cand.lam = max(opts.lambda_min,
                        min(opts.lambda_max, st.lam * max(1.0 / 3, 1 - (2 * ratio - 1) ** 3)))
@@ -273,7 +280,7 @@ def solve(prob: Problem, st: State, opts: Options, max_iters: int | None = None)
         reps.append(rep)
         if rep.status == "empty" or rep.grad_inf <= opts.grad_tol:
             break
-        if rep.accepted and rep.cost_before - rep.cost_after <= opts.cost_rel_tol * rep.cost_before:
+        if rep.accepted and rep.extra["actual_decrease"] <= opts.cost_rel_tol * rep.cost_before:
             break
         if not rep.accepted and rep.lam >= opts.lambda_max:
             break

@@ -148,6 +148,7 @@ struct ba_ctx {
   bool lin_valid = false, ext_valid = false, step_valid = false, blocks_valid = false;
   int Ca = 0, Pa = 0, rounds = 0;
   int64_t Nh = 0, Nc = 0;
+  double last_decrease = 0.0;   // per-observation actual reduction of the last step
 
   // timing
   std::vector<KStat> stats;
@@ -330,7 +331,7 @@ void alloc_obs_buffers(ba_ctx& c) {
   c.pm_xcw = A.alloc<char>(4 * ts * N);
   c.eh = nullptr;
   c.cm_eh = nullptr;
-  c.V = A.alloc<char>(ts * 6 * P);
+  c.V = A.alloc<char>(sizeof(double) * 6 * P);
   c.Vinv = A.alloc<char>(ts * 6 * P);
   c.zq = A.alloc<char>(4 * ts * P);
   c.Ustar = A.alloc<char>(ts * 21 * C);
@@ -352,7 +353,7 @@ void alloc_obs_buffers(ba_ctx& c) {
   c.sv = A.alloc<double>(6 * size_t(C));
   c.wv = A.alloc<double>(6 * size_t(C));
   c.dots = A.alloc<double>(3 * size_t(C));
-  c.partials = A.alloc<double>(4 * (size_t(P) / kBlock + 2));
+  c.partials = A.alloc<double>(5 * (size_t(P) / kBlock + 2));
   c.scal = A.alloc<double>(16);
   c.pcg = A.alloc<PcgState>(1);
   c.grad_cams_d = nullptr;
@@ -506,7 +507,7 @@ void linearize(ba_ctx& c, bool adj) {
   c.timed("lin_point", double(c.Nh) * (4 + 8 + 4 + ts + (adj ? 3 * ts : 0)) +
                            double(c.Pa) * (4 + 24 + 6 * ts + 24) + double(c.C) * 120,
           -1, [&] {
-            launch_lin_point<T>(s, adj, m, cp, om, static_cast<T*>(c.V), c.gp, c.partials);
+            launch_lin_point<T>(s, adj, m, cp, om, static_cast<double*>(c.V), c.gp, c.partials);
           });
   const int nb = int((c.Pa + kBlock - 1) / kBlock);
   launch_reduce_partials(s, nb, 3, c.partials, 0x4u, 0, nullptr, nullptr, c.scal);
@@ -526,8 +527,8 @@ void setup_system(ba_ctx& c, bool adj, double lam, const double* rhs_c, const do
   HIP_CHECK(hipMemsetAsync(c.flags + 1, 0, sizeof(int), s));
   c.timed("point_damp", double(c.Pa) * (6 * ts + 24 + 6 * ts + 24), -1, [&] {
     launch_point_damp<T>(s, c.Pa, lam, c.opt.diag_min, c.opt.diag_max,
-                         static_cast<const T*>(c.V), c.gp, rhs_p, static_cast<T*>(c.Vinv), c.hp,
-                         c.flags + 1);
+                         static_cast<const double*>(c.V), c.gp, rhs_p, static_cast<T*>(c.Vinv),
+                         c.hp, c.flags + 1);
   });
   c.timed("cam_assemble",
           double(c.Nc) * (8 + ts + 12 + (adj ? 3 * ts : 0)) + double(c.Pa) * (24 + 6 * ts + 24) +
@@ -667,35 +668,40 @@ ba_status lm_step_impl(ba_ctx& c, ba_step_report* rep) {
                                       static_cast<const T*>(c.w), c.Xcand, c.partials);
           });
   const int nb = int((c.Pa + kBlock - 1) / kBlock);
-  launch_reduce_partials(s, nb, 4, c.partials, 0x0u, c.Ca, c.gc, c.x, c.scal + 4);
+  // scal[4..] = decrease, quad, g_p.dp, bad, cost', g_c.x, max |g_c|
+  launch_reduce_partials(s, nb, 5, c.partials, 0x0u, c.Ca, c.gc, c.x, c.scal + 4);
   HIP_LAUNCH_CHECK();
-  HIP_CHECK(hipMemcpyAsync(c.h_pin, c.scal, 10 * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipMemcpyAsync(c.h_pin + 10, c.flags + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(c.h_pin, c.scal, 11 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(c.h_pin + 11, c.flags + 1, sizeof(int), hipMemcpyDeviceToHost, s));
   c.sync();
-  double sc[10];
+  double sc[11];
   std::memcpy(sc, c.h_pin, sizeof(sc));
   int damp_bad = 0;
-  std::memcpy(&damp_bad, c.h_pin + 10, sizeof(int));
+  std::memcpy(&damp_bad, c.h_pin + 11, sizeof(int));
   const double F = sc[0];
   R.cost_before = F;
   R.rms_px = std::sqrt(sc[1] / double(c.Nh));
-  const double Fc = sc[7] > 0 ? std::numeric_limits<double>::infinity() : sc[4];
+  const bool finite_c = !(sc[7] > 0) && std::isfinite(sc[8]);
+  const double dF = sc[4];   // actual reduction, summed per observation
+  c.last_decrease = dF;
+  // reported as F - dF, consistent with the acceptance test (the candidate's own sum, sc[8],
+  // carries the rounding of a full cost evaluation)
+  const double Fc = finite_c ? F - dF : std::numeric_limits<double>::infinity();
   R.cost_after = Fc;
-  const double model = -(sc[6] + sc[8] + 0.5 * sc[5]);
+  const double model = -(sc[6] + sc[9] + 0.5 * sc[5]);
   R.model_decrease = model;
   // max |g| over the compact parameters: points from the linearisation, cameras from gc
-  R.grad_inf = std::max(sc[2], c.Ca > 0 ? sc[9] : 0.0);
+  R.grad_inf = std::max(sc[2], c.Ca > 0 ? sc[10] : 0.0);
   if (!std::isfinite(F)) {
     c.flush_timing(iters);
     R.ms_total = now_ms() - t0;
     if (rep) *rep = R;
     throw BaError{BA_ERR_NUMERIC, "non-finite cost at the current parameters"};
   }
-  const bool finite_c = std::isfinite(Fc);
-  const double ratio = (model > 0 && finite_c) ? (F - Fc) / model
+  const double ratio = (model > 0 && finite_c) ? dF / model
                                                : -std::numeric_limits<double>::infinity();
   R.gain_ratio = ratio;
-  const bool ok = finite_c && Fc < F && ratio > c.opt.accept_ratio && !st.breakdown && !damp_bad;
+  const bool ok = finite_c && dF > 0 && ratio > c.opt.accept_ratio && !st.breakdown && !damp_bad;
   R.accepted = ok ? 1 : 0;
   c.step_valid = true;
   if (ok) {
@@ -750,8 +756,8 @@ void adjoint_impl(ba_ctx& c, const double* grad_cams, const double* grad_points,
     HIP_LAUNCH_CHECK();
     setup_system<T>(c, true, 0.0, c.rhs_c, c.rhs_p);
     PcgState st{};
-    const double tol = std::min(c.opt.pcg_rel_tol, 1e-10);
-    const int maxit = std::max(c.opt.pcg_max_iters, 6 * c.Ca + 10);
+    const double tol = c.opt.adjoint_rel_tol;
+    const int maxit = c.opt.adjoint_max_iters;
     const int mv = run_pcg<T>(c, true, tol, maxit, &st);
     backsub<T>(c, true, c.rhs_p);
     Compact<T> cp = compact_view<T>(c);
@@ -827,6 +833,8 @@ void ba_default_options(ba_options* o) {
   o->grad_tol = 1e-10;
   o->max_lm_iters = 100;
   o->timing = 0;
+  o->adjoint_max_iters = 5000;
+  o->adjoint_rel_tol = 1e-10;
   o->hip_stream = nullptr;
 }
 
@@ -851,7 +859,8 @@ ba_status ba_create(const ba_options* opt, int32_t n_cams, int32_t n_points, con
       (o.activity_rule != BA_ACTIVITY_ROWS && o.activity_rule != BA_ACTIVITY_LITERAL) ||
       o.img_w <= 0 || o.img_h <= 0 || !(o.lambda_min > 0) || !(o.lambda_max >= o.lambda_min) ||
       !(o.lambda_init > 0) || o.pcg_max_iters < 0 || !(o.pcg_rel_tol >= 0) ||
-      !(o.diag_min > 0) || !(o.diag_max >= o.diag_min)) {
+      !(o.diag_min > 0) || !(o.diag_max >= o.diag_min) || o.adjoint_max_iters < 0 ||
+      !(o.adjoint_rel_tol >= 0)) {
     g_create_error = "invalid options";
     return BA_ERR_ARG;
   }
@@ -1078,7 +1087,7 @@ ba_status ba_solve(ba_ctx* c, ba_solve_report* rep) {
         S.stop_reason = 2;
         break;
       }
-      if (R.accepted && R.cost_before - R.cost_after <= c->opt.cost_rel_tol * R.cost_before) {
+      if (R.accepted && c->last_decrease <= c->opt.cost_rel_tol * R.cost_before) {
         S.stop_reason = 1;
         break;
       }
@@ -1216,13 +1225,7 @@ ba_status ba_get_normal_blocks(const ba_ctx* cc, double* U, double* gcv, double*
     if (V || gpv) {
       std::vector<double> Vo(9 * size_t(c->P), 0.0), go(3 * size_t(c->P), 0.0), g, v;
       download(*c, g, c->gp, 3 * size_t(c->Pa));
-      if (c->tsize() == 8) {
-        download(*c, v, static_cast<const double*>(c->V), 6 * size_t(c->Pa));
-      } else {
-        std::vector<float> vf;
-        download(*c, vf, static_cast<const float*>(c->V), 6 * size_t(c->Pa));
-        v.assign(vf.begin(), vf.end());
-      }
+      download(*c, v, static_cast<const double*>(c->V), 6 * size_t(c->Pa));
       static const int m3[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
       for (int r = 0; r < c->Pa; ++r) {
         const size_t pu = size_t(c->pt_user[psrc[r]]);

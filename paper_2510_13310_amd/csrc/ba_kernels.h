@@ -139,11 +139,12 @@ template <typename T>
 void launch_mv_table(hipStream_t s, int n, const Cam<double>* camd_hat, MvCam<T>* mvt);
 
 // ------------------------------------------------------------------ linearisation
-// Per point: residuals (float64), robust weights, V = J_p^T M J_p (T), gp = J_p^T M e
-// (float64); per block: cost, sum |r_2d|^2 and max |gp| into partials[3 * block].
+// Per point: residuals (float64), robust weights, V = J_p^T M J_p (T products accumulated in
+// float64), gp = J_p^T M e (float64); per block: cost, sum |r_2d|^2 and max |gp| into
+// partials[3 * block].
 template <typename T>
 void launch_lin_point(hipStream_t s, bool adj, const Model& m, const Compact<T>& cp,
-                      ObsMetric<T> om, T* V, double* gp, double* partials);
+                      ObsMetric<T> om, double* V, double* gp, double* partials);
 // Camera-major stream of the PCG camera pass: X_c and w per observation (+ eh).
 template <typename T>
 void launch_cm_prepare(hipStream_t s, bool adj, int64_t Nc, const Compact<T>& cp,
@@ -152,7 +153,7 @@ void launch_cm_prepare(hipStream_t s, bool adj, int64_t Nc, const Compact<T>& cp
 // rhs_p = -gp when rhs_p == nullptr.
 template <typename T>
 void launch_point_damp(hipStream_t s, int Pa, double lam, double dmin, double dmax,
-                       const T* V, const double* gp, const double* rhs_p, T* Vinv,
+                       const double* V, const double* gp, const double* rhs_p, T* Vinv,
                        double* hp, int* bad);
 // Per camera slot: U = J_c^T M J_c, gc, b = rhs_c - sum W hp, S_cc = U* - sum W Vinv W^T and
 // its inverse (Cholesky, float64). rhs_c = -gc when rhs_c == nullptr. SoA outputs.

@@ -503,14 +503,14 @@ k_mv_table(int n, const Cam<double>* __restrict__ camd_hat, MvCam<T>* __restrict
 // ------------------------------------------------------------------ linearisation
 template <typename T, bool ADJ>
 __global__ void __launch_bounds__(kBlock)
-k_lin_point(Model m, Compact<T> cp, ObsMetric<T> om, T* __restrict__ V,
+k_lin_point(Model m, Compact<T> cp, ObsMetric<T> om, double* __restrict__ V,
             double* __restrict__ gp, double* __restrict__ partials) {
   __shared__ double smem[3 * (kBlock / kWave)];
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   double acc[3] = {0.0, 0.0, 0.0};   // cost, sum |r_2d|^2, max |gp|
   if (r < cp.Pa) {
     const double X0 = cp.Xd[3 * r], X1 = cp.Xd[3 * r + 1], X2 = cp.Xd[3 * r + 2];
-    T v[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     double g[3] = {0.0, 0.0, 0.0};
     for (int j = cp.off[r]; j < cp.off[r + 1]; ++j) {
       const Cam<double> cm = cp.camd[cp.cam[j]];
@@ -523,39 +523,39 @@ k_lin_point(Model m, Compact<T> cp, ObsMetric<T> om, T* __restrict__ V,
       acc[0] += 0.5 * rho;
       acc[1] += e[0] * e[0] + e[1] * e[1];
       om.w[j] = T(w);
-      const T Xt[3] = {T(Xc[0]), T(Xc[1]), T(Xc[2])};
       V4<T> xw;
-      xw.x = Xt[0];
-      xw.y = Xt[1];
-      xw.z = Xt[2];
+      xw.x = T(Xc[0]);
+      xw.y = T(Xc[1]);
+      xw.z = T(Xc[2]);
       xw.w = T(w);
       om.pm_xcw[j] = xw;
-      AMat<T, ADJ> A;
-      A.set(T(cm.f), T(m.lam_d), Xt);
+      // point block and gradient from float64 rows in both precisions: the depth direction
+      // of a weakly observed point can sit below float32 resolution
+      AMat<double, ADJ> A;
+      A.set(cm.f, m.lam_d, Xc);
       if constexpr (ADJ) {
         const double inv = d2 != 0.0 ? 1.0 / sqrt(s) : 0.0;
-        const T eh[3] = {T(e[0] * inv), T(e[1] * inv), T(e[2] * inv)};
-        om.eh[3 * j] = eh[0];
-        om.eh[3 * j + 1] = eh[1];
-        om.eh[3 * j + 2] = eh[2];
+        const double eh[3] = {e[0] * inv, e[1] * inv, e[2] * inv};
+        om.eh[3 * j] = T(eh[0]);
+        om.eh[3 * j + 1] = T(eh[1]);
+        om.eh[3 * j + 2] = T(eh[2]);
         A.project(eh);
       }
-      const T wt = T(w);
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        T a[3], jp[3];
+        double a[3], jp[3];
         A.row(i, a);
         rot_tmul(cm, a, jp);
 #pragma unroll
         for (int p = 0; p < 3; ++p) {
 #pragma unroll
-          for (int q = p; q < 3; ++q) v[sym3(p, q)] += wt * jp[p] * jp[q];
+          for (int q = p; q < 3; ++q) v[sym3(p, q)] += w * jp[p] * jp[q];
         }
         if constexpr (!ADJ) {
           const double we = w * e[i];
-          g[0] += we * double(jp[0]);
-          g[1] += we * double(jp[1]);
-          g[2] += we * double(jp[2]);
+          g[0] += we * jp[0];
+          g[1] += we * jp[1];
+          g[2] += we * jp[2];
         }
       }
     }
@@ -618,7 +618,7 @@ k_cm_prepare(int64_t Nc, Compact<T> cp, ObsMetric<T> om) {
 // Damped 3x3 point block, inverted in float64 by cofactors.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_point_damp(int Pa, double lam, double dmin, double dmax, const T* __restrict__ V,
+k_point_damp(int Pa, double lam, double dmin, double dmax, const double* __restrict__ V,
              const double* __restrict__ gp, const double* __restrict__ rhs_p,
              T* __restrict__ Vinv, double* __restrict__ hp, int* __restrict__ bad) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1181,19 +1181,21 @@ k_cam_candidate(int Ca, int Cf, const int* __restrict__ cam_src, const double* _
   cand_cams[7 * s + 6] = d.c[2];
 }
 
-// Candidate cost (float64) over the same active observations, the quadratic term of the
-// model decrease sum w |J delta|^2 (float64 Jacobian at the linearisation point), g_p.dp,
-// and the number of candidate depths <= min_depth.
+// Candidate evaluation over the same active observations (float64): the actual reduction
+// sum_k (rho_k - rho'_k) / 2, summed per observation so that its rounding error scales with
+// the changes rather than with the cost; the quadratic term of the model decrease
+// sum w |J delta|^2 (Jacobian at the linearisation point); g_p.dp; the number of candidate
+// depths <= min_depth; and the candidate cost itself.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_point_candidate(Model m, Compact<T> cp, const Cam<double>* __restrict__ cand_tab,
                   const double* __restrict__ x, const double* __restrict__ dp,
                   const double* __restrict__ gp, const T* __restrict__ w,
                   double* __restrict__ Xcand, double* __restrict__ partials) {
-  __shared__ double smem[4 * (kBlock / kWave)];
+  __shared__ double smem[5 * (kBlock / kWave)];
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   const int Ca = cp.Ca;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};   // cost', quad, g_p.dp, bad
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // decrease, quad, g_p.dp, bad, cost'
   if (r < cp.Pa) {
     const double X[3] = {cp.Xd[3 * r], cp.Xd[3 * r + 1], cp.Xd[3 * r + 2]};
     const double d[3] = {dp[3 * r], dp[3 * r + 1], dp[3 * r + 2]};
@@ -1204,21 +1206,25 @@ k_point_candidate(Model m, Compact<T> cp, const Cam<double>* __restrict__ cand_t
     acc[2] = gp[3 * r] * d[0] + gp[3 * r + 1] * d[1] + gp[3 * r + 2] * d[2];
     for (int j = cp.off[r]; j < cp.off[r + 1]; ++j) {
       const int s = cp.cam[j];
+      const Cam<double> cm = cp.camd[s];
+      double Xl[3], e[3], rho0, d1, d2;
+      cam_frame(cm, X[0], X[1], X[2], Xl);
+      residual(cm, Xl, cp.xy[j], cp.depth[j], m.lam_d, e);
+      huber(e[0] * e[0] + e[1] * e[1] + e[2] * e[2], m.huber, rho0, d1, d2);
       const Cam<double> cn = cand_tab[s];
       double Xc[3];
       cam_frame(cn, Xn[0], Xn[1], Xn[2], Xc);
       if (!(Xc[2] > m.min_depth)) {
         acc[3] += 1.0;
       } else {
-        double e[3], rho, d1, d2;
-        residual(cn, Xc, cp.xy[j], cp.depth[j], m.lam_d, e);
-        huber(e[0] * e[0] + e[1] * e[1] + e[2] * e[2], m.huber, rho, d1, d2);
-        acc[0] += 0.5 * rho;
+        double e2[3], rho;
+        residual(cn, Xc, cp.xy[j], cp.depth[j], m.lam_d, e2);
+        huber(e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2], m.huber, rho, d1, d2);
+        acc[0] += 0.5 * (rho0 - rho);
+        acc[4] += 0.5 * rho;
       }
       // model term at the linearisation point
-      const Cam<double> cm = cp.camd[s];
-      double Xl[3], v[3], t[3];
-      cam_frame(cm, X[0], X[1], X[2], Xl);
+      double v[3], t[3];
       rot_mul(cm, d, v);
       if (s < Ca) {
         const double w3[3] = {x[3 * Ca + s], x[4 * Ca + s], x[5 * Ca + s]};
@@ -1234,10 +1240,10 @@ k_point_candidate(Model m, Compact<T> cp, const Cam<double>* __restrict__ cand_t
       acc[1] += double(w[j]) * (t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
     }
   }
-  block_sum<double, 4>(acc, smem);
+  block_sum<double, 5>(acc, smem);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) partials[4 * blockIdx.x + i] = acc[i];
+    for (int i = 0; i < 5; ++i) partials[5 * blockIdx.x + i] = acc[i];
   }
 }
 
@@ -1470,7 +1476,7 @@ void launch_compact_cm(hipStream_t s, int64_t N, const int* cm_perm, const uint8
 
 template <typename T>
 void launch_lin_point(hipStream_t s, bool adj, const Model& m, const Compact<T>& cp,
-                      ObsMetric<T> om, T* V, double* gp, double* partials) {
+                      ObsMetric<T> om, double* V, double* gp, double* partials) {
   const unsigned nb = blocks_for(cp.Pa);
   if (adj)
     hipLaunchKernelGGL((k_lin_point<T, true>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, V, gp,
@@ -1494,7 +1500,7 @@ void launch_cm_prepare(hipStream_t s, bool adj, int64_t Nc, const Compact<T>& cp
 
 template <typename T>
 void launch_point_damp(hipStream_t s, int Pa, double lam, double dmin, double dmax,
-                       const T* V, const double* gp, const double* rhs_p, T* Vinv,
+                       const double* V, const double* gp, const double* rhs_p, T* Vinv,
                        double* hp, int* bad) {
   hipLaunchKernelGGL(k_point_damp<T>, dim3(blocks_for(Pa)), dim3(kBlock), 0, s, Pa, lam, dmin,
                      dmax, V, gp, rhs_p, Vinv, hp, bad);
@@ -1668,10 +1674,10 @@ void launch_adjoint_obs(hipStream_t s, const Model& m, const Compact<T>& cp, Obs
 // explicit instantiations for the two precisions
 #define IBA_INSTANTIATE(T)                                                                    \
   template void launch_lin_point<T>(hipStream_t, bool, const Model&, const Compact<T>&,       \
-                                    ObsMetric<T>, T*, double*, double*);                      \
+                                    ObsMetric<T>, double*, double*, double*);                 \
   template void launch_cm_prepare<T>(hipStream_t, bool, int64_t, const Compact<T>&,           \
                                      ObsMetric<T>);                                            \
-  template void launch_point_damp<T>(hipStream_t, int, double, double, double, const T*,      \
+  template void launch_point_damp<T>(hipStream_t, int, double, double, double, const double*, \
                                      const double*, const double*, T*, double*, int*);        \
   template void launch_cam_assemble<T>(hipStream_t, bool, const Model&, const Compact<T>&,    \
                                        ObsMetric<T>, double, double, double, const T*,        \

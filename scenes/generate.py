@@ -326,7 +326,9 @@ def make_scene(name: str, seed: int | None = None, **overrides) -> Scene:
                 by 3 degrees and 200 points whose observations are all outliers.
     ``large``   1000 cameras in 10 random walks, 500k points, 8 views, 5 % outliers,
                 priors on 50 % of observations.
-    ``adjoint`` the ``medium`` scene with camera 0 held fixed (gauge anchor).
+    ``adjoint`` the ``medium`` scene with camera 0 held fixed (gauge anchor) and depth rows
+                weighted lambda_d = 300 px m (about 1 / sigma of the priors' inverse depth)
+                so that the undamped implicit-function system is well conditioned.
     ``xl``      5000 cameras in 50 random walks, 2M points, 6 views, 5 % outliers,
                 priors on 30 % of observations.
     Keyword overrides resize a scene (``n_points``, ``n_cams``, ``n_seq`` ...) or change its
@@ -339,7 +341,9 @@ def make_scene(name: str, seed: int | None = None, **overrides) -> Scene:
     if name == "medium":
         return _medium(seed, **overrides)
     if name == "adjoint":
-        sc = _medium(seed, **overrides)
+        kw = dict(lambda_d=300.0)
+        kw.update(overrides)
+        sc = _medium(seed, **kw)
         return replace(sc, name="adjoint", fixed=np.array([0], np.int32))
     if name == "large":
         kw = dict(n_seq=10, n_points=500_000, half_extent=100.0, height=20.0, views=8,

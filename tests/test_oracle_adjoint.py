@@ -85,3 +85,62 @@ def test_adjoint_matches_central_differences_noise_free():
             refs.append(gxy[k, j] if j < 2 else gd[k])
     fds, refs = np.array(fds), np.array(refs)
     assert np.max(np.abs(fds - refs)) <= 1e-5 * np.max(np.abs(refs)), np.c_[fds, refs]
+
+
+def test_robust_corrected_metric_is_needed_with_huber():
+    """A noisy scene with Huber delta = 1 px (about half the observations in the linear
+    regime): central differences of converged re-solves agree with the robust-corrected
+    adjoint (rho' I + 2 rho'' e e^T) within a few percent -- the dropped second-order
+    residual term -- and much better than with the IRLS metric rho' I alone."""
+    import sys
+    from dataclasses import replace
+    from oracle.lm import extract
+    from oracle.model import residuals
+    A = sys.modules["oracle.adjoint"]
+    rng_l = np.random.default_rng(5)
+    sc = make_scene("tiny", n_points=80, noise_px=1.0, prior_frac=1.0, use_depth=True,
+                    lambda_d=50.0, exact=True)
+    sc = replace(sc, fixed=np.array([0], np.int32), huber_px=1.0)
+    opts = Options(huber_px=1.0, lambda_init=1e-4, cost_rel_tol=0.0, grad_tol=0.0,
+                   max_iters=400)
+    prob = Problem.from_scene(sc)
+    st, _ = solve(prob, State.initial(sc.cams0, sc.points0, opts), opts)
+    ex = extract(prob, st, opts)
+    e, _, _ = residuals(prob, st.q, st.c, st.X, ex.obs)
+    s = np.sqrt(np.sum(e * e, axis=1))
+    assert np.mean(s > 1.0) > 0.3
+    gt_c = sc.cams_gt[:, 4:]
+    gcam = np.zeros((sc.n_cams, 7))
+    gcam[:, 4:] = 2 * (st.c - gt_c)
+    gxy, gd, _ = adjoint(prob, st, opts, gcam, np.zeros_like(st.X))
+    # the same solve with the IRLS metric only
+    ne, mb = A.normal_equations, A.metric_blocks
+    A.normal_equations = lambda lin, robust_correction=False: ne(lin, False)
+    A.metric_blocks = lambda lin, robust_correction=False: mb(lin, False)
+    try:
+        gxy0, gd0, _ = adjoint(prob, st, opts, gcam, np.zeros_like(st.X))
+    finally:
+        A.normal_equations, A.metric_blocks = ne, mb
+    obs = ex.obs[np.abs(s - 1.0) > 0.05]
+    e_corr, e_irls = [], []
+    for k in rng_l.choice(obs, 4, replace=False):
+        for j in (0, 2):
+            h = 1e-4 if j < 2 else 1e-5 / prob.dinv[k]
+            vals = []
+            for sg in (1, -1):
+                p2 = Problem.from_scene(sc)
+                if j < 2:
+                    p2.xy[k, j] += sg * h
+                else:
+                    p2.dinv[k] = 1.0 / (1.0 / prob.dinv[k] + sg * h)
+                warm = st.copy()
+                warm.lam, warm.nu = 1e-4, 2.0
+                s2, _ = solve(p2, warm, opts)
+                vals.append(float(np.sum((s2.c - gt_c) ** 2)))
+            fd = (vals[0] - vals[1]) / (2 * h)
+            ref = gxy[k, j] if j < 2 else gd[k]
+            ref0 = gxy0[k, j] if j < 2 else gd0[k]
+            e_corr.append(abs(fd - ref) / abs(fd))
+            e_irls.append(abs(fd - ref0) / abs(fd))
+    assert np.median(e_corr) < 0.05 and max(e_corr) < 0.15, e_corr
+    assert np.median(e_corr) < 0.3 * np.median(e_irls), (e_corr, e_irls)
