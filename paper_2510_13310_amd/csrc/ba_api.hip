@@ -122,7 +122,7 @@ struct ba_ctx {
   int *scan_tmp = nullptr, *flags = nullptr;   // flags[0] changed, flags[1] bad damping
   int *cam_hat = nullptr, *orig_hat = nullptr, *off_hat = nullptr, *pt_src = nullptr;
   int *cam_src = nullptr, *slot_all = nullptr, *cm_off_hat = nullptr, *cm_pt = nullptr,
-      *cm_pm = nullptr;
+      *cm_pm = nullptr, *pm_cm = nullptr;
   Cam<double>* camd_hat = nullptr;
   Cam<float>* camf_hat = nullptr;
   float2* xy_hat = nullptr;
@@ -324,6 +324,7 @@ void alloc_obs_buffers(ba_ctx& c) {
   c.cm_off_hat = A.alloc<int>(C + 1);
   c.cm_pt = A.alloc<int>(N);
   c.cm_pm = A.alloc<int>(N);
+  c.pm_cm = A.alloc<int>(N);
   c.Xd = A.alloc<double>(3 * size_t(P));
   c.Xf = A.alloc<float>(3 * size_t(P));
   c.w = A.alloc<char>(ts * N);
@@ -333,7 +334,7 @@ void alloc_obs_buffers(ba_ctx& c) {
   c.cm_eh = nullptr;
   c.V = A.alloc<char>(sizeof(double) * 6 * P);
   c.Vinv = A.alloc<char>(ts * 6 * P);
-  c.zq = A.alloc<char>(4 * ts * P);
+  c.zq = A.alloc<char>(4 * ts * N);
   c.Ustar = A.alloc<char>(ts * 21 * C);
   c.mvt = A.alloc<char>(ts * 16 * C);
   c.gp = A.alloc<double>(3 * size_t(P));
@@ -387,6 +388,7 @@ Compact<T> compact_view(ba_ctx& c) {
   cp.cm_off = c.cm_off_hat;
   cp.cm_pt = c.cm_pt;
   cp.cm_pm = c.cm_pm;
+  cp.pm_cm = c.pm_cm;
   cp.Xd = c.Xd;
   cp.camd = c.camd_hat;
   if constexpr (sizeof(T) == 8) {
@@ -467,7 +469,7 @@ void extract(ba_ctx& c) {
     launch_compact_obs(s, N, c.vrow, c.pos_pm, c.pm_cam, c.slot_all, c.pm_xy, c.pm_depth,
                        c.pm_orig, c.cam_hat, c.xy_hat, c.depth_hat, c.orig_hat);
     launch_compact_cm(s, N, c.cm_perm, c.vrow, c.pm_cam, c.pm_pt, c.d_fixed, c.pos_cm,
-                      c.pos_pm, c.rank_p, c.cm_pt, c.cm_pm);
+                      c.pos_pm, c.rank_p, c.cm_pt, c.cm_pm, c.pm_cm);
     if (c.tsize() == 8)
       launch_mv_table<double>(s, c.Ca + c.n_fixed, c.camd_hat, static_cast<MvCam<double>*>(c.mvt));
     else
@@ -477,20 +479,19 @@ void extract(ba_ctx& c) {
 }
 
 // Algorithmic bytes of the two PCG passes (unique data each must touch once).
-// Point pass: per observation its slot and (X_c, w) 4-vector; per point the CSR offset, Vinv
-// and the 4-vector z written; every matvec record once.
+// Point pass: per observation its slot and (X_c, w) 4-vector, and for solve cameras its
+// camera-major position and the z 4-vector written there; per point the CSR offset and
+// Vinv; every matvec record once.
 double bytes_schur_point(const ba_ctx& c) {
   const double ts = double(c.tsize());
-  return double(c.Nh) * (4 + 4 * ts) + double(c.Pa) * (4 + 6 * ts + 4 * ts) +
-         double(c.Ca) * 16 * ts;
+  return double(c.Nh) * (4 + 4 * ts) + double(c.Nc) * (4 + 4 * ts) +
+         double(c.Pa) * (4 + 6 * ts) + double(c.Ca) * 16 * ts;
 }
-// Camera pass: per observation the point rank and the (X_c, w) 4-vector; every active
-// point's z 4-vector at least once; per camera its offsets, table entry, U*, u, r, and the
-// w and dot terms written.
+// Camera pass: per observation the (X_c, w) and z 4-vectors; per camera its offsets, table
+// entry, U*, u, r, and the w and dot terms written.
 double bytes_schur_cam(const ba_ctx& c) {
   const double ts = double(c.tsize());
-  return double(c.Nc) * (4 + 4 * ts) + double(c.Pa) * 4 * ts +
-         double(c.Ca) * (4 + 15 * ts + 21 * ts + 12 * 8 + 9 * 8);
+  return double(c.Nc) * 8 * ts + double(c.Ca) * (4 + 15 * ts + 21 * ts + 12 * 8 + 9 * 8);
 }
 int lanes_per_point(const ba_ctx& c) {
   const double mean = c.Pa > 0 ? double(c.Nh) / c.Pa : 1.0;

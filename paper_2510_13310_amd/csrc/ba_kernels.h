@@ -80,6 +80,7 @@ struct Compact {
   const int* cm_off;      // Ca + 1: camera-major segments
   const int* cm_pt;       // Nc: point rank of each camera-major observation
   const int* cm_pm;       // Nc: position of that observation in the point-major stream
+  const int* pm_cm;       // Nh: camera-major position of each observation (solve slots only)
   const double* Xd;       // Pa x 3 compact points (float64)
   const T* Xt;            // Pa x 3 compact points (T)
   const Cam<double>* camd;// Ca + Cf compact camera table (float64)
@@ -133,7 +134,7 @@ void launch_compact_obs(hipStream_t s, int64_t N, const uint8_t* vrow, const int
 void launch_compact_cm(hipStream_t s, int64_t N, const int* cm_perm, const uint8_t* vrow,
                        const int* pm_cam, const int* pm_pt, const uint8_t* fixed,
                        const int* pos_cm, const int* pos_pm, const int* rank_p, int* cm_pt,
-                       int* cm_pm);
+                       int* cm_pm, int* pm_cm);
 // Matvec records of every slot (R, f from the compact table; u = 0).
 template <typename T>
 void launch_mv_table(hipStream_t s, int n, const Cam<double>* camd_hat, MvCam<T>* mvt);
@@ -169,13 +170,15 @@ template <typename T>
 void launch_pcg_init(hipStream_t s, int Ca, const double* b, const double* Minv, double* x,
                      double* r, double* u, double* p, double* sv, MvCam<T>* mvt, PcgState* st,
                      double tol2, int max_iter);
-// zq_p = Vinv sum_k W_k^T u_c  (point-major pass, G lanes per point)
+// z_p = Vinv sum_k W_k^T u_c (point-major pass, G lanes per point), written to the
+// camera-major position of every observation of p in a solve camera (zq_cm, Nc entries)
 template <typename T>
 void launch_schur_point(hipStream_t s, bool adj, int G, const Model& m, const Compact<T>& cp,
-                        ObsMetric<T> om, const MvCam<T>* mvt, const T* Vinv, V4<T>* zq,
+                        ObsMetric<T> om, const MvCam<T>* mvt, const T* Vinv, V4<T>* zq_cm,
                         const PcgState* st);
-// Camera-major pass, one workgroup per camera slot: w_s = U*_s u_s - sum_k W_k zq_p, and the
-// camera's terms of r.u, w.u and r.r (dots: 3 arrays of Ca, SoA).
+// Camera-major pass, one workgroup per camera slot: w_s = U*_s u_s - sum_k W_k z_k with z
+// streamed in camera-major order, and the camera's terms of r.u, w.u and r.r (dots: 3
+// arrays of Ca, SoA).
 template <typename T>
 void launch_schur_cam(hipStream_t s, bool adj, const Model& m, const Compact<T>& cp,
                       ObsMetric<T> om, const T* Ustar, const double* u, const double* r,

@@ -478,7 +478,7 @@ k_compact_cm(int64_t N, const int* __restrict__ cm_perm, const uint8_t* __restri
              const int* __restrict__ pm_cam, const int* __restrict__ pm_pt,
              const uint8_t* __restrict__ fixed, const int* __restrict__ pos_cm,
              const int* __restrict__ pos_pm, const int* __restrict__ rank_p,
-             int* __restrict__ cm_pt, int* __restrict__ cm_pm) {
+             int* __restrict__ cm_pt, int* __restrict__ cm_pm, int* __restrict__ pm_cm) {
   const int64_t m = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (m >= N) return;
   const int k = cm_perm[m];
@@ -486,6 +486,7 @@ k_compact_cm(int64_t N, const int* __restrict__ cm_perm, const uint8_t* __restri
   const int i = pos_cm[m];
   cm_pt[i] = rank_p[pm_pt[k]];
   cm_pm[i] = pos_pm[k];
+  pm_cm[pos_pm[k]] = i;
 }
 
 template <typename T>
@@ -871,19 +872,23 @@ k_pcg_init(int Ca, const double* __restrict__ b, const double* __restrict__ Minv
 // Point-major pass of S u: G lanes share one point, each walks every G-th observation of
 // the point's segment, and the lanes combine their sums with shuffles (G divides 64). Per
 // observation: the streamed (X_c, w) 4-vector and one aligned matvec record of its camera.
+// The point's z = Vinv y is then stored at the camera-major position of each of its
+// observations, so that the camera pass streams z instead of gathering it.
 template <typename T, bool ADJ, int G>
 __global__ void __launch_bounds__(kBlock)
 k_schur_point(Model m, Compact<T> cp, ObsMetric<T> om, const MvCam<T>* __restrict__ mvt,
-              const T* __restrict__ Vinv, V4<T>* __restrict__ zq,
+              const T* __restrict__ Vinv, V4<T>* __restrict__ zq_cm,
               const PcgState* __restrict__ st) {
   if (st->done) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = t / G;
   const int l = t % G;
   T y[3] = {T(0), T(0), T(0)};
+  int b = 0, e = 0;
   if (r < cp.Pa) {
-    const int e = cp.off[r + 1];
-    for (int j = cp.off[r] + l; j < e; j += G) {
+    b = cp.off[r];
+    e = cp.off[r + 1];
+    for (int j = b + l; j < e; j += G) {
       const int s = cp.cam[j];
       if (s >= cp.Ca) continue;   // fixed camera: no column in the solve
       const V4<T> xw = om.pm_xcw[j];
@@ -913,20 +918,23 @@ k_schur_point(Model m, Compact<T> cp, ObsMetric<T> om, const MvCam<T>* __restric
     y[1] += __shfl_xor(y[1], o, kWave);
     y[2] += __shfl_xor(y[2], o, kWave);
   }
-  if (r < cp.Pa && l == 0) {
+  // every lane of the group now holds y; each computes z and stores its observations' copies
+  if (r < cp.Pa) {
     const T* vi = Vinv + 6 * r;
     V4<T> z;
     z.x = vi[0] * y[0] + vi[1] * y[1] + vi[2] * y[2];
     z.y = vi[1] * y[0] + vi[3] * y[1] + vi[4] * y[2];
     z.z = vi[2] * y[0] + vi[4] * y[1] + vi[5] * y[2];
     z.w = T(0);
-    zq[r] = z;
+    for (int j = b + l; j < e; j += G) {
+      if (cp.cam[j] < cp.Ca) zq_cm[cp.pm_cm[j]] = z;
+    }
   }
 }
 
 // Camera-major pass of S u, one 1024-thread workgroup per camera slot:
-//   w_s = U*_s u_s - sum_k W_k zq_p(k), then the camera's terms of r.u, w.u and r.r.
-// Per observation: the point rank and the streamed (X_c, w) 4-vector; zq is gathered.
+//   w_s = U*_s u_s - sum_k W_k z_k, then the camera's terms of r.u, w.u and r.r.
+// Per observation two streamed 4-vectors: (X_c, w) and z (stored by the point pass).
 constexpr int kCamBlock = 1024;
 
 template <typename T, bool ADJ>
@@ -949,7 +957,7 @@ k_schur_cam(Model m, Compact<T> cp, ObsMetric<T> om, const T* __restrict__ Ustar
   const int end = cp.cm_off[s + 1];
   for (int i = cp.cm_off[s] + threadIdx.x; i < end; i += blockDim.x) {
     const V4<T> xw = om.xcw[i];
-    const V4<T> zv = zq[cp.cm_pt[i]];
+    const V4<T> zv = zq[i];
     const T Xc[3] = {xw.x, xw.y, xw.z};
     AMat<T, ADJ> A;
     A.set(cm.f, T(m.lam_d), Xc);
@@ -1468,10 +1476,10 @@ void launch_compact_obs(hipStream_t s, int64_t N, const uint8_t* vrow, const int
 void launch_compact_cm(hipStream_t s, int64_t N, const int* cm_perm, const uint8_t* vrow,
                        const int* pm_cam, const int* pm_pt, const uint8_t* fixed,
                        const int* pos_cm, const int* pos_pm, const int* rank_p, int* cm_pt,
-                       int* cm_pm) {
+                       int* cm_pm, int* pm_cm) {
   if (N == 0) return;
   hipLaunchKernelGGL(k_compact_cm, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, cm_perm, vrow,
-                     pm_cam, pm_pt, fixed, pos_cm, pos_pm, rank_p, cm_pt, cm_pm);
+                     pm_cam, pm_pt, fixed, pos_cm, pos_pm, rank_p, cm_pt, cm_pm, pm_cm);
 }
 
 template <typename T>
