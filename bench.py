@@ -6,6 +6,13 @@ back-substitution, candidate evaluation and accept/scatter, over the whole synth
 on 50 %). Inputs are resident in HBM before the timed region. The mixed-precision path is the
 headline value; the float64 path runs the same steps from the same start for the ratio.
 
+Each precision runs two timed regions of the same steps from the same start: the first
+without instrumentation gives the throughput (``value``); the second attaches HIP start/stop
+events to every kernel launch and gives the per-kernel durations and the roofline of the
+dominant kernel (the event records slow the step itself by ~15 %, so they stay out of the
+throughput region). Both regions execute the same launches (the solver is deterministic;
+``same_steps`` checks it).
+
 Prints one JSON line. ``--gpus N`` with N > 1 is not supported (single-GPU build).
 """
 from __future__ import annotations
@@ -23,7 +30,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "BA LM iters/s + Jacobian obs/s, FP32-mixed vs FP64, 1000-cam synthetic scene"
 HBM_PEAK_GBS = 8000.0
-LINEARIZE_KERNELS = ("lin_point", "gather_cm_metric", "cam_assemble")
+LINEARIZE_KERNELS = ("lin_point", "cm_prepare", "cam_assemble")
 
 
 def parse():
@@ -39,13 +46,15 @@ def parse():
     ap.add_argument("--cpu-frac", type=float, default=0.05,
                     help="fraction of points in the oracle's timed sample")
     ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--check-every", type=int, default=8,
+                    help="PCG iterations enqueued between convergence read-backs")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a 1 GiB device copy first (counter calibration)")
     ap.add_argument("--verbose", action="store_true")
     return ap.parse_args()
 
 
-def run_gpu(sc, precision, steps, warmup, args, torch):
+def run_gpu(sc, precision, steps, warmup, args, torch, timing):
     from paper_2510_13310_amd import BundleAdjuster
     dev = torch.device("cuda:0")
     t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
@@ -53,7 +62,7 @@ def run_gpu(sc, precision, steps, warmup, args, torch):
                         t(sc.points0, torch.float64), precision=precision,
                         huber_px=sc.huber_px, filter_px=sc.filter_px, img_w=sc.img_w,
                         img_h=sc.img_h, pcg_rel_tol=args.pcg_tol, pcg_max_iters=args.pcg_max,
-                        timing=1)
+                        pcg_check_every=args.check_every, timing=timing)
     ba.set_observations(t(sc.cam_idx, torch.int32), t(sc.pt_idx, torch.int32),
                         t(sc.xy, torch.float32))
     if sc.use_depth:
@@ -76,9 +85,25 @@ def run_gpu(sc, precision, steps, warmup, args, torch):
 
 
 def summarize(res, n_obs_total):
+    """Throughput of one timed region (every step counted, accepted or rejected)."""
     reps = res["reports"]
     K = len(reps)
     its = K / res["seconds"]
+    nh = float(np.mean([r["n_obs_active"] for r in reps]))
+    return dict(
+        lm_iters_per_s=its, ms_per_step=1e3 * res["seconds"] / K, obs_per_s=its * nh,
+        n_obs_active=nh, n_obs_total=n_obs_total,
+        pcg_iters_mean=float(np.mean([r["pcg_iters"] for r in reps])),
+        accepted=int(sum(r["accepted"] for r in reps)),
+        relinearized=int(sum(r["relinearized"] for r in reps)),
+        rms_px_first=reps[0]["rms_px"], rms_px_last=reps[-1]["rms_px"],
+        cost_last=reps[-1]["cost_before"], device_gb=res["device_bytes"] / 1e9)
+
+
+def kernel_summary(res):
+    """Per-kernel launches, time and algorithmic GB/s of an instrumented region."""
+    reps = res["reports"]
+    K = len(reps)
     nh = float(np.mean([r["n_obs_active"] for r in reps]))
     st = {s["name"]: s for s in res["stats"]}
     lin_ms = sum(st[k]["total_ms"] for k in LINEARIZE_KERNELS if k in st)
@@ -86,18 +111,13 @@ def summarize(res, n_obs_total):
     jac = (nh * lin_launch) / (lin_ms / 1e3) if lin_ms > 0 else None
     kern_ms = sum(s["total_ms"] for s in res["stats"])
     return dict(
-        lm_iters_per_s=its, ms_per_step=1e3 * res["seconds"] / K, obs_per_s=its * nh,
-        jacobian_obs_per_s=jac, n_obs_active=nh, n_obs_total=n_obs_total,
-        pcg_iters_mean=float(np.mean([r["pcg_iters"] for r in reps])),
-        accepted=int(sum(r["accepted"] for r in reps)),
-        relinearized=int(sum(r["relinearized"] for r in reps)),
-        rms_px_first=reps[0]["rms_px"], rms_px_last=reps[-1]["rms_px"],
-        cost_last=reps[-1]["cost_before"], kernel_ms_per_step=kern_ms / K,
-        device_gb=res["device_bytes"] / 1e9,
+        ms_per_step_instrumented=1e3 * res["seconds"] / K, kernel_ms_per_step=kern_ms / K,
+        jacobian_obs_per_s=jac,
         kernels={s["name"]: dict(launches=s["launches"], ms=round(s["total_ms"], 4),
-                                 gbs=(s["total_bytes"] / (s["total_ms"] * 1e6)
+                                 avg_us=round(1e3 * s["total_ms"] / s["launches"], 2),
+                                 gbs=(round(s["total_bytes"] / (s["total_ms"] * 1e6), 1)
                                       if s["total_ms"] > 0 else None))
-                 for s in res["stats"]},
+                 for s in res["stats"] if s["launches"] > 0},
     )
 
 
@@ -185,14 +205,20 @@ def main():
     precs = ["mixed", "fp64"] if args.precision == "both" else [args.precision]
     out = {}
     for p in precs:
-        res = run_gpu(sc, p, args.steps, args.warmup, args, torch)
-        out[p] = (res, summarize(res, sc.n_obs))
+        # region 1: the throughput, no instrumentation; region 2: the same steps from the
+        # same start with HIP events attached to every launch (kernel durations, roofline)
+        res = run_gpu(sc, p, args.steps, args.warmup, args, torch, timing=0)
+        ins = run_gpu(sc, p, args.steps, args.warmup, args, torch, timing=1)
+        summ = summarize(res, sc.n_obs)
+        summ.update(kernel_summary(ins))
+        summ["same_steps"] = ([r["cost_before"] for r in res["reports"]] ==
+                              [r["cost_before"] for r in ins["reports"]])
+        out[p] = (ins, summ)
         if args.verbose:
-            print(p, json.dumps({k: v for k, v in out[p][1].items() if k != "kernels"}),
-                  flush=True)
+            print(p, json.dumps({k: v for k, v in summ.items() if k != "kernels"}), flush=True)
 
     head = precs[0]
-    res, summ = out[head]
+    ins, summ = out[head]
     line = {
         "metric": METRIC,
         "value": round(summ["lm_iters_per_s"], 3),
@@ -209,11 +235,12 @@ def main():
         "config": {"workload": (f"{args.scene}: {sc.n_cams} cameras in random walks, "
                                 f"{sc.n_points} points, {sc.n_obs} observations, 5% outliers, "
                                 "depth priors on 50%, Huber 2 px, 4 px filter"),
-                   "pcg_rel_tol": args.pcg_tol, "pcg_max_iters": args.pcg_max},
+                   "pcg_rel_tol": args.pcg_tol, "pcg_max_iters": args.pcg_max,
+                   "pcg_check_every": args.check_every},
         "obs_per_s": round(summ["obs_per_s"], 1),
         "jacobian_obs_per_s": (round(summ["jacobian_obs_per_s"], 1)
                                if summ["jacobian_obs_per_s"] else None),
-        "roofline": roofline(res),
+        "roofline": roofline(ins),
     }
     for p in precs:
         s = out[p][1]

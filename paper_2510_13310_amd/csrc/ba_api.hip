@@ -150,6 +150,7 @@ struct ba_ctx {
   int64_t Nh = 0, Nc = 0;
   double last_decrease = 0.0;   // per-observation actual reduction of the last step
 
+  iba::DevLimits dl;   // compute units and LDS sizes of the context's device
   // timing
   std::vector<KStat> stats;
   std::vector<Pending> pending;
@@ -199,6 +200,7 @@ struct ba_ctx {
     HIP_CHECK(hipEventCreate(&e));
     return e;
   }
+  // One kernel: its own start and end timestamps (events handed to the launch itself).
   template <class F>
   void timed(const char* name, double bytes, int pcg_iter, F&& launch) {
     if (!opt.timing) {
@@ -207,6 +209,30 @@ struct ba_ctx {
       return;
     }
     Pending pe{kid(name), get_event(), get_event(), bytes, pcg_iter};
+    const int64_t before = iba::launches_issued();
+    iba::set_launch_events(pe.a, pe.b);
+    launch();
+    iba::set_launch_events(nullptr, nullptr);
+    HIP_LAUNCH_CHECK();
+    const int64_t n = iba::launches_issued() - before;
+    if (n == 0) {   // nothing to do for an empty range
+      pool.push_back(pe.a);
+      pool.push_back(pe.b);
+      return;
+    }
+    if (n != 1) throw BaError{BA_ERR_STATE, std::string("internal: timed scope ") + name +
+                                                " launched several kernels"};
+    pending.push_back(pe);
+  }
+  // Several kernels: events recorded in the stream around them.
+  template <class F>
+  void timed_multi(const char* name, double bytes, F&& launch) {
+    if (!opt.timing) {
+      launch();
+      HIP_LAUNCH_CHECK();
+      return;
+    }
+    Pending pe{kid(name), get_event(), get_event(), bytes, -1};
     HIP_CHECK(hipEventRecord(pe.a, stream));
     launch();
     HIP_LAUNCH_CHECK();
@@ -443,7 +469,7 @@ void extract(ba_ctx& c) {
     if (rounds > 1000000) throw BaError{BA_ERR_DEVICE, "activity fixpoint did not settle"};
   }
   c.rounds = rounds;
-  c.timed("scan", double(c.C) * 5 + double(c.P) * 5 + double(N) * 14, -1, [&] {
+  c.timed_multi("scan", double(c.C) * 5 + double(c.P) * 5 + double(N) * 14, [&] {
     launch_scan_u8(s, c.C, c.act_c, c.rank_c, c.scan_tmp);
     launch_scan_u8(s, c.P, c.act_p, c.rank_p, c.scan_tmp);
     launch_scan_u8(s, N, c.vrow, c.pos_pm, c.scan_tmp);
@@ -459,7 +485,7 @@ void extract(ba_ctx& c) {
   c.Pa = hp[1];
   c.Nh = hp[2];
   c.Nc = hp[3];
-  c.timed("compact", double(N) * 40 + double(c.P) * 60, -1, [&] {
+  c.timed_multi("compact", double(N) * 40 + double(c.P) * 60, [&] {
     launch_compact_cams(s, c.C, c.act_c, c.rank_c, c.d_fixed, c.d_fixed_rank, c.cm_off,
                         c.pos_cm, c.slot_all, c.cam_src, c.cm_off_hat);
     launch_compact_cam_table(s, c.Ca + c.n_fixed, c.cam_src, c.d_camd, c.d_camf, c.camd_hat,
@@ -467,7 +493,7 @@ void extract(ba_ctx& c) {
     launch_compact_points(s, c.P, c.act_p, c.rank_p, c.pt_off, c.pos_pm, c.d_pts, c.pt_src,
                           c.off_hat, c.Xd, c.Xf);
     launch_compact_obs(s, N, c.vrow, c.pos_pm, c.pm_cam, c.slot_all, c.pm_xy, c.pm_depth,
-                       c.pm_orig, c.cam_hat, c.xy_hat, c.depth_hat, c.orig_hat);
+                       c.pm_orig, c.Ca, c.cam_hat, c.xy_hat, c.depth_hat, c.orig_hat, c.pm_cm);
     launch_compact_cm(s, N, c.cm_perm, c.vrow, c.pm_cam, c.pm_pt, c.d_fixed, c.pos_cm,
                       c.pos_pm, c.rank_p, c.cm_pt, c.cm_pm, c.pm_cm);
     if (c.tsize() == 8)
@@ -569,15 +595,17 @@ int run_pcg(ba_ctx& c, bool adj, double rel_tol, int max_iters, PcgState* out_st
     for (int k = 0; k < every && it < max_iters; ++k, ++it) {
       c.timed("schur_point", bp, it, [&] {
         launch_schur_point<T>(s, adj, G, m, cp, om, mvt, static_cast<const T*>(c.Vinv), zq,
-                              c.pcg);
+                              c.pcg, c.dl);
       });
       c.timed("schur_cam", bc, it, [&] {
         launch_schur_cam<T>(s, adj, m, cp, om, static_cast<const T*>(c.Ustar), c.u, c.r, zq,
                             c.wv, c.dots, c.pcg);
       });
-      c.timed("pcg_update", double(c.Ca) * (3 * 8 + 21 * 8 + 6 * 8 * 10 + 6 * double(sizeof(T))),
+      // per camera: its dot terms, M^-1, reads of u p w s x r, writes of p s x r u and its
+      // matvec record's u
+      c.timed("pcg_update", double(c.Ca) * (3 * 8 + 21 * 8 + 6 * 8 * 11 + 6 * double(sizeof(T))),
               it, [&] {
-                launch_pcg_update<T>(s, c.Ca, c.Minv, c.dots, c.x, c.r, c.u, c.p, c.sv, c.wv,
+                launch_pcg_update<T>(s, c.Ca, it, c.Minv, c.dots, c.x, c.r, c.u, c.p, c.sv, c.wv,
                                      mvt, c.pcg);
               });
     }
@@ -889,6 +917,13 @@ ba_status ba_create(const ba_options* opt, int32_t n_cams, int32_t n_points, con
       c->own_stream = true;
     }
     HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&c->h_pin), 64 * sizeof(double)));
+    int dev = 0;
+    HIP_CHECK(hipGetDevice(&dev));
+    HIP_CHECK(hipDeviceGetAttribute(&c->dl.n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    HIP_CHECK(hipDeviceGetAttribute(&c->dl.lds_per_block,
+                                    hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    HIP_CHECK(hipDeviceGetAttribute(&c->dl.lds_per_cu,
+                                    hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev));
     Arena& A = c->par;
     c->d_cams = A.alloc<double>(7 * size_t(n_cams));
     c->d_intr = A.alloc<double>(3 * size_t(n_cams));

@@ -54,9 +54,13 @@ struct Model {
 
 // Device-side PCG scalars (one instance per context). The iteration is the
 // Chronopoulos-Gear form of preconditioned CG: one fused reduction per iteration.
+// Iteration k reads gamma and alpha of iteration k-1 from slot (k+1)&1 and writes its own to
+// slot k&1, so the workgroups of one update never read a value written in the same launch.
+// The host bounds the iteration count; done is set only on convergence or breakdown, which
+// every workgroup of the update decides identically.
 struct PcgState {
-  double gamma;       // r.u of the previous iteration (u = M^-1 r)
-  double alpha;       // previous step length
+  double gam[2];      // r.u (u = M^-1 r) by iteration parity
+  double alp[2];      // step length by iteration parity
   double bb;          // b.b
   double rr;          // r.r at the last convergence check
   double tol2;        // (relative tolerance)^2
@@ -67,6 +71,12 @@ struct PcgState {
   int breakdown;      // non-positive curvature or non-finite scalar
   int pad;
 };
+
+// Per-launch timing: the next kernel launched by this host thread records its start and
+// end in these events (both created by the caller; nullptr disarms).
+void set_launch_events(hipEvent_t start, hipEvent_t stop);
+// Number of kernel launches issued by this host thread so far.
+int64_t launches_issued();
 
 // Compact problem view shared by the point-major and camera-major passes.
 template <typename T>
@@ -127,10 +137,11 @@ void launch_compact_cams(hipStream_t s, int C, const uint8_t* act_c, const int* 
 void launch_compact_cam_table(hipStream_t s, int n, const int* cam_src,
                               const Cam<double>* camd, const Cam<float>* camf,
                               Cam<double>* camd_hat, Cam<float>* camf_hat);
+// (also marks pm_cm = -1 for the observations of fixed cameras, slots >= Ca)
 void launch_compact_obs(hipStream_t s, int64_t N, const uint8_t* vrow, const int* pos_pm,
                         const int* pm_cam, const int* slot_all, const float2* pm_xy,
-                        const float* pm_depth, const int* pm_orig, int* cam_hat,
-                        float2* xy_hat, float* depth_hat, int* orig_hat);
+                        const float* pm_depth, const int* pm_orig, int Ca, int* cam_hat,
+                        float2* xy_hat, float* depth_hat, int* orig_hat, int* pm_cm);
 void launch_compact_cm(hipStream_t s, int64_t N, const int* cm_perm, const uint8_t* vrow,
                        const int* pm_cam, const int* pm_pt, const uint8_t* fixed,
                        const int* pos_cm, const int* pos_pm, const int* rank_p, int* cm_pt,
@@ -170,12 +181,20 @@ template <typename T>
 void launch_pcg_init(hipStream_t s, int Ca, const double* b, const double* Minv, double* x,
                      double* r, double* u, double* p, double* sv, MvCam<T>* mvt, PcgState* st,
                      double tol2, int max_iter);
+// Device figures the launchers size persistent grids and LDS tables with.
+struct DevLimits {
+  int n_cu = 0;            // compute units
+  int lds_per_block = 0;   // bytes of LDS one workgroup may use
+  int lds_per_cu = 0;      // bytes of LDS per compute unit
+};
+
 // z_p = Vinv sum_k W_k^T u_c (point-major pass, G lanes per point), written to the
-// camera-major position of every observation of p in a solve camera (zq_cm, Nc entries)
+// camera-major position of every observation of p in a solve camera (zq_cm, Nc entries).
+// When the Ca matvec records fit in LDS, a persistent grid stages them there.
 template <typename T>
 void launch_schur_point(hipStream_t s, bool adj, int G, const Model& m, const Compact<T>& cp,
                         ObsMetric<T> om, const MvCam<T>* mvt, const T* Vinv, V4<T>* zq_cm,
-                        const PcgState* st);
+                        const PcgState* st, const DevLimits& dl);
 // Camera-major pass, one workgroup per camera slot: w_s = U*_s u_s - sum_k W_k z_k with z
 // streamed in camera-major order, and the camera's terms of r.u, w.u and r.r (dots: 3
 // arrays of Ca, SoA).
@@ -186,7 +205,7 @@ void launch_schur_cam(hipStream_t s, bool adj, const Model& m, const Compact<T>&
 // Fused reduction of the per-camera dots, convergence test, then p = u + beta p,
 // s = w + beta s, x += alpha p, r -= alpha s, u = M^-1 r.
 template <typename T>
-void launch_pcg_update(hipStream_t s, int Ca, const double* Minv, const double* dots,
+void launch_pcg_update(hipStream_t s, int Ca, int k, const double* Minv, const double* dots,
                        double* x, double* r, double* u, double* p, double* sv, const double* w,
                        MvCam<T>* mvt, PcgState* st);
 // dp = Vinv (rhs_p - sum_k W_k^T x_c), rhs_p = -gp when nullptr.

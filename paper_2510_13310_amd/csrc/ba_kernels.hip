@@ -13,12 +13,34 @@
 // observation for the 72-144 bytes a stored W_k = J_c^T J_p block would cost per pass.
 #include "ba_kernels.h"
 
+#include <hip/hip_ext.h>
+
 #include <cmath>
 
 namespace iba {
 namespace {
 
 constexpr int kWave = 64;
+
+// ------------------------------------------------------------------ launches
+// Events armed by set_launch_events are handed to the next launch on this host thread, which
+// records its start and end in them (hipExtLaunchKernel): no extra packets in the stream.
+thread_local hipEvent_t g_ev_start = nullptr;
+thread_local hipEvent_t g_ev_stop = nullptr;
+thread_local int64_t g_launches = 0;
+
+template <typename... KArgs, typename... Args>
+void launch_k(void (*kernel)(KArgs...), dim3 grid, dim3 block, uint32_t shmem, hipStream_t s,
+              Args... args) {
+  ++g_launches;
+  if (g_ev_start != nullptr) {
+    hipEvent_t a = g_ev_start, b = g_ev_stop;
+    g_ev_start = g_ev_stop = nullptr;
+    hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, a, b, 0u, static_cast<KArgs>(args)...);
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, shmem, s, static_cast<KArgs>(args)...);
+  }
+}
 
 // ------------------------------------------------------------------ reductions
 template <typename T>
@@ -399,9 +421,9 @@ void scan_impl(hipStream_t s, int64_t n, F flag, int* out, int* tmp) {
     hipMemsetAsync(out, 0, sizeof(int), s);
     return;
   }
-  hipLaunchKernelGGL(k_scan_tile<F>, dim3(nt), dim3(kBlock), 0, s, n, flag, out, tmp);
-  hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, nt, tmp, out + n);
-  hipLaunchKernelGGL(k_scan_add, dim3(nt), dim3(kBlock), 0, s, n, tmp, out);
+  launch_k(k_scan_tile<F>, dim3(nt), dim3(kBlock), 0, s, n, flag, out, tmp);
+  launch_k(k_scan_tiles, dim3(1), dim3(1024), 0, s, nt, tmp, out + n);
+  launch_k(k_scan_add, dim3(nt), dim3(kBlock), 0, s, n, tmp, out);
 }
 
 // ------------------------------------------------------------------ compaction kernels
@@ -461,13 +483,15 @@ __global__ void __launch_bounds__(kBlock)
 k_compact_obs(int64_t N, const uint8_t* __restrict__ vrow, const int* __restrict__ pos_pm,
               const int* __restrict__ pm_cam, const int* __restrict__ slot_all,
               const float2* __restrict__ pm_xy, const float* __restrict__ pm_depth,
-              const int* __restrict__ pm_orig, int* __restrict__ cam_hat,
+              const int* __restrict__ pm_orig, int Ca, int* __restrict__ cam_hat,
               float2* __restrict__ xy_hat, float* __restrict__ depth_hat,
-              int* __restrict__ orig_hat) {
+              int* __restrict__ orig_hat, int* __restrict__ pm_cm) {
   const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (k >= N || !vrow[k]) return;
   const int j = pos_pm[k];
-  cam_hat[j] = slot_all[pm_cam[k]];
+  const int slot = slot_all[pm_cam[k]];
+  cam_hat[j] = slot;
+  if (slot >= Ca) pm_cm[j] = -1;   // fixed camera: no camera-major entry
   xy_hat[j] = pm_xy[k];
   depth_hat[j] = pm_depth[k];
   orig_hat[j] = pm_orig[k];
@@ -852,8 +876,8 @@ k_pcg_init(int Ca, const double* __restrict__ b, const double* __restrict__ Minv
   }
   block_sum<double, 1>(acc, smem);
   if (threadIdx.x == 0) {
-    st->gamma = 0.0;
-    st->alpha = 0.0;
+    st->gam[0] = st->gam[1] = 0.0;
+    st->alp[0] = st->alp[1] = 0.0;
     st->bb = acc[0];
     st->rr = acc[0];
     st->tol2 = tol2;
@@ -871,28 +895,36 @@ k_pcg_init(int Ca, const double* __restrict__ b, const double* __restrict__ Minv
 
 // Point-major pass of S u: G lanes share one point, each walks every G-th observation of
 // the point's segment, and the lanes combine their sums with shuffles (G divides 64). Per
-// observation: the streamed (X_c, w) 4-vector and one aligned matvec record of its camera.
+// observation: the streamed (X_c, w) 4-vector and the matvec record of its camera (R, f, u).
 // The point's z = Vinv y is then stored at the camera-major position of each of its
 // observations, so that the camera pass streams z instead of gathering it.
+// Every lane of a wave must call this together (shuffles); lanes with r >= rend do nothing.
 template <typename T, bool ADJ, int G>
-__global__ void __launch_bounds__(kBlock)
-k_schur_point(Model m, Compact<T> cp, ObsMetric<T> om, const MvCam<T>* __restrict__ mvt,
-              const T* __restrict__ Vinv, V4<T>* __restrict__ zq_cm,
-              const PcgState* __restrict__ st) {
-  if (st->done) return;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = t / G;
-  const int l = t % G;
+__device__ __forceinline__ void schur_point_one(const Model& m, const Compact<T>& cp,
+                                                const ObsMetric<T>& om,
+                                                const MvCam<T>* __restrict__ tab,
+                                                const T* __restrict__ Vinv,
+                                                V4<T>* __restrict__ zq_cm, int r, int rend,
+                                                int l) {
   T y[3] = {T(0), T(0), T(0)};
-  int b = 0, e = 0;
-  if (r < cp.Pa) {
+  T vi[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+  int b = 0, e = 0, pos0 = -1;
+  const bool live = r < rend;
+  if (live) {
     b = cp.off[r];
     e = cp.off[r + 1];
+    // loads needed only after the reduction, issued now to overlap the stream (float32: the
+    // registers are free; float64 keeps them for the stream)
+    if constexpr (sizeof(T) == 4) {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) vi[q] = Vinv[6 * r + q];
+    }
+    if (b + l < e) pos0 = cp.pm_cm[b + l];
     for (int j = b + l; j < e; j += G) {
       const int s = cp.cam[j];
       if (s >= cp.Ca) continue;   // fixed camera: no column in the solve
       const V4<T> xw = om.pm_xcw[j];
-      const MvCam<T> mc = mvt[s];
+      const MvCam<T> mc = tab[s];
       const T Xc[3] = {xw.x, xw.y, xw.z};
       AMat<T, ADJ> A;
       A.set(mc.f, T(m.lam_d), Xc);
@@ -919,23 +951,73 @@ k_schur_point(Model m, Compact<T> cp, ObsMetric<T> om, const MvCam<T>* __restric
     y[2] += __shfl_xor(y[2], o, kWave);
   }
   // every lane of the group now holds y; each computes z and stores its observations' copies
-  if (r < cp.Pa) {
-    const T* vi = Vinv + 6 * r;
+  // (pm_cm is -1 for an observation of a fixed camera)
+  if (live) {
+    if constexpr (sizeof(T) != 4) {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) vi[q] = Vinv[6 * r + q];
+    }
     V4<T> z;
     z.x = vi[0] * y[0] + vi[1] * y[1] + vi[2] * y[2];
     z.y = vi[1] * y[0] + vi[3] * y[1] + vi[4] * y[2];
     z.z = vi[2] * y[0] + vi[4] * y[1] + vi[5] * y[2];
     z.w = T(0);
-    for (int j = b + l; j < e; j += G) {
-      if (cp.cam[j] < cp.Ca) zq_cm[cp.pm_cm[j]] = z;
+    if (pos0 >= 0) zq_cm[pos0] = z;
+    for (int j = b + l + G; j < e; j += G) {
+      const int pos = cp.pm_cm[j];
+      if (pos >= 0) zq_cm[pos] = z;
     }
   }
+}
+
+// One thread group per point, matvec records read from global memory (any camera count).
+// The grid is a multiple of 8 and consecutive workgroups go to the 8 XCDs in turn; each XCD
+// takes one contiguous eighth of the point ranks, so the z stores of one XCD fill whole
+// cache lines of every camera segment (segments are sorted by point rank) in its own L2.
+template <typename T, bool ADJ, int G>
+__global__ void __launch_bounds__(kBlock)
+k_schur_point(Model m, Compact<T> cp, ObsMetric<T> om, const MvCam<T>* __restrict__ mvt,
+              const T* __restrict__ Vinv, V4<T>* __restrict__ zq_cm,
+              const PcgState* __restrict__ st) {
+  if (st->done) return;
+  const int per = gridDim.x / 8;
+  const int blk = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  const int t = blk * blockDim.x + threadIdx.x;
+  schur_point_one<T, ADJ, G>(m, cp, om, mvt, Vinv, zq_cm, t / G, cp.Pa, t % G);
+}
+
+// Persistent variant for tables that fit in LDS: a few 1024-thread workgroups per CU each
+// copy the camera records into LDS once, then walk a contiguous range of ppb points (XCD
+// ranges as above). Random per-observation record reads then hit LDS instead of costing
+// one L1 tag lookup per lane.
+constexpr int kPtLdsBlock = 1024;
+
+template <typename T, bool ADJ, int G>
+__global__ void __launch_bounds__(kPtLdsBlock)
+k_schur_point_lds(Model m, Compact<T> cp, ObsMetric<T> om, const MvCam<T>* __restrict__ mvt,
+                  const T* __restrict__ Vinv, V4<T>* __restrict__ zq_cm,
+                  const PcgState* __restrict__ st, int ppb) {
+  extern __shared__ uint4 lds_tab[];   // cp.Ca records
+  if (st->done) return;
+  const int nchunk = cp.Ca * int(sizeof(MvCam<T>) / sizeof(uint4));
+  const uint4* src = reinterpret_cast<const uint4*>(mvt);
+  for (int i = threadIdx.x; i < nchunk; i += kPtLdsBlock) lds_tab[i] = src[i];
+  __syncthreads();
+  const MvCam<T>* tab = reinterpret_cast<const MvCam<T>*>(lds_tab);
+  const int per = gridDim.x / 8;
+  const int blk = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  const int lo = blk * ppb;
+  const int hi = min(cp.Pa, lo + ppb);
+  constexpr int tile = kPtLdsBlock / G;
+  for (int base = lo; base < hi; base += tile)
+    schur_point_one<T, ADJ, G>(m, cp, om, tab, Vinv, zq_cm, base + int(threadIdx.x) / G, hi,
+                               int(threadIdx.x) % G);
 }
 
 // Camera-major pass of S u, one 1024-thread workgroup per camera slot:
 //   w_s = U*_s u_s - sum_k W_k z_k, then the camera's terms of r.u, w.u and r.r.
 // Per observation two streamed 4-vectors: (X_c, w) and z (stored by the point pass).
-constexpr int kCamBlock = 1024;
+constexpr int kCamBlock = 512;   // 4 workgroups per CU: ~1000 cameras in one round
 
 template <typename T, bool ADJ>
 __global__ void __launch_bounds__(kCamBlock)
@@ -952,6 +1034,13 @@ k_schur_cam(Model m, Compact<T> cp, ObsMetric<T> om, const T* __restrict__ Ustar
   const int Ca = cp.Ca;
   if (s >= Ca) return;
   __shared__ T smem[6 * (kCamBlock / kWave)];
+  __shared__ double tail[33];   // U*_s (21), u_s (6), r_s (6), loaded while the stream runs
+  if (threadIdx.x < 21)
+    tail[threadIdx.x] = double(Ustar[threadIdx.x * Ca + s]);
+  else if (threadIdx.x < 27)
+    tail[threadIdx.x] = u[(threadIdx.x - 21) * Ca + s];
+  else if (threadIdx.x < 33)
+    tail[threadIdx.x] = r[(threadIdx.x - 27) * Ca + s];
   const Cam<T> cm = cp.camt[s];
   T acc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
   const int end = cp.cm_off[s + 1];
@@ -972,20 +1061,18 @@ k_schur_cam(Model m, Compact<T> cp, ObsMetric<T> om, const T* __restrict__ Ustar
     acc[0] += mm[0]; acc[1] += mm[1]; acc[2] += mm[2];
     acc[3] += xm[0]; acc[4] += xm[1]; acc[5] += xm[2];
   }
-  block_sum<T, 6>(acc, smem);
+  block_sum<T, 6>(acc, smem);   // its barriers also publish tail[]
   if (threadIdx.x != 0) return;
-  double uv[6];
-#pragma unroll
-  for (int i = 0; i < 6; ++i) uv[i] = u[i * Ca + s];
+  const double* uv = tail + 21;
   double g = 0.0, d = 0.0, rr = 0.0;
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     double a = 0.0;
 #pragma unroll
-    for (int j = 0; j < 6; ++j) a += double(Ustar[sym6(i, j) * Ca + s]) * uv[j];
+    for (int j = 0; j < 6; ++j) a += tail[sym6(i, j)] * uv[j];
     const double wi = a - double(acc[i]);
     w[i * Ca + s] = wi;
-    const double ri = r[i * Ca + s];
+    const double ri = tail[27 + i];
     g += ri * uv[i];
     d += wi * uv[i];
     rr += ri * ri;
@@ -995,76 +1082,110 @@ k_schur_cam(Model m, Compact<T> cp, ObsMetric<T> om, const T* __restrict__ Ustar
   dots[2 * Ca + s] = rr;
 }
 
-// One Chronopoulos-Gear PCG iteration after the matvec w = S u:
+// One Chronopoulos-Gear PCG iteration k after the matvec w = S u:
 //   gamma = r.u, delta = w.u, rho = r.r (one reduction of the per-camera terms);
 //   stop if rho <= tol^2 b.b; beta = gamma / gamma_prev, alpha = gamma / (delta - beta gamma /
 //   alpha_prev); p = u + beta p; s = w + beta s; x += alpha p; r -= alpha s; u = M^-1 r.
-// One workgroup; every sum in a fixed order.
+// Every workgroup reduces all per-camera terms in the same fixed order (so all of them take
+// the same scalars and the same decision) and updates its own kUpdCams cameras, whose vectors
+// it loads before the reduction. Workgroup 0 records the scalars.
+constexpr int kUpdBlock = 256;
+constexpr int kUpdCams = 64;
+
 template <typename T>
-__global__ void __launch_bounds__(1024)
-k_pcg_update(int Ca, const double* __restrict__ Minv, const double* __restrict__ dots,
+__global__ void __launch_bounds__(kUpdBlock)
+k_pcg_update(int Ca, int k, const double* __restrict__ Minv, const double* __restrict__ dots,
              double* __restrict__ x, double* __restrict__ r, double* __restrict__ u,
              double* __restrict__ p, double* __restrict__ sv, const double* __restrict__ w,
              MvCam<T>* __restrict__ mvt, PcgState* st) {
-  __shared__ double smem[3 * (1024 / kWave)];
+  __shared__ double smem[3 * (kUpdBlock / kWave)];
   __shared__ double s_bcast[2];
-  __shared__ int s_done;
-  if (threadIdx.x == 0) s_done = st->done;
-  __syncthreads();
-  if (s_done) return;
-  double acc[3] = {0.0, 0.0, 0.0};   // gamma, delta, rho
-  for (int s = threadIdx.x; s < Ca; s += blockDim.x) {
-    acc[0] += dots[s];
-    acc[1] += dots[Ca + s];
-    acc[2] += dots[2 * Ca + s];
+  __shared__ int s_go;
+  const int s = blockIdx.x * kUpdCams + threadIdx.x;
+  const bool own = threadIdx.x < kUpdCams && s < Ca;
+  double pv[6], wv[6], sv0[6], rv[6], uv[6], m[21];
+  if (own) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      pv[i] = p[i * Ca + s];
+      wv[i] = w[i * Ca + s];
+      sv0[i] = sv[i * Ca + s];
+      rv[i] = r[i * Ca + s];
+      uv[i] = u[i * Ca + s];
+    }
+#pragma unroll
+    for (int q = 0; q < 21; ++q) m[q] = Minv[q * Ca + s];
   }
+  double acc[3] = {0.0, 0.0, 0.0};   // gamma, delta, rho
+  for (int c = threadIdx.x; c < Ca; c += kUpdBlock) {
+    acc[0] += dots[c];
+    acc[1] += dots[Ca + c];
+    acc[2] += dots[2 * Ca + c];
+  }
+  // thread 0 reads the state once for the whole workgroup
+  int done0 = 0;
+  double tol2 = 0.0, bb = 0.0, gprev = 0.0, aprev = 0.0;
+  if (threadIdx.x == 0) {
+    done0 = st->done;
+    tol2 = st->tol2;
+    bb = st->bb;
+    gprev = st->gam[(k + 1) & 1];
+    aprev = st->alp[(k + 1) & 1];
+    s_go = !done0;
+  }
+  __syncthreads();
+  if (!s_go) return;   // converged or broken down in an earlier iteration
   block_sum<double, 3>(acc, smem);
   if (threadIdx.x == 0) {
     const double gamma = acc[0], delta = acc[1], rho = acc[2];
-    st->rr = rho;
-    st->matvecs += 1;
-    int done = rho <= st->tol2 * st->bb;
-    if (!done) {
-      const int it = st->iter;
-      const double beta = it == 0 ? 0.0 : gamma / st->gamma;
-      const double den = it == 0 ? delta : delta - beta * gamma / st->alpha;
-      const double alpha = gamma / den;
+    int go = !(rho <= tol2 * bb);
+    int broke = 0;
+    double alpha = 0.0, beta = 0.0;
+    if (go) {
+      beta = k == 0 ? 0.0 : gamma / gprev;
+      const double den = k == 0 ? delta : delta - beta * gamma / aprev;
+      alpha = gamma / den;
       if (!(den > 0.0) || !(gamma > 0.0) || !isfinite(alpha) || !isfinite(beta)) {
-        st->breakdown = 1;
-        done = 1;
-      } else {
-        s_bcast[0] = alpha;
-        s_bcast[1] = beta;
-        st->gamma = gamma;
-        st->alpha = alpha;
-        st->iter = it + 1;
-        if (it + 1 >= st->max_iter) st->done = 1;
+        broke = 1;
+        go = 0;
       }
     }
-    if (done) st->done = 1;
-    s_done = done;
+    s_bcast[0] = alpha;
+    s_bcast[1] = beta;
+    s_go = go;
+    if (blockIdx.x == 0) {
+      st->rr = rho;
+      st->matvecs += 1;
+      if (go) {
+        st->gam[k & 1] = gamma;
+        st->alp[k & 1] = alpha;
+        st->iter = k + 1;
+      } else {
+        st->breakdown = broke;
+        st->done = 1;
+      }
+    }
   }
   __syncthreads();
-  if (s_done) return;
+  if (!s_go || !own) return;
   const double alpha = s_bcast[0], beta = s_bcast[1];
-  for (int s = threadIdx.x; s < Ca; s += blockDim.x) {
-    double rv[6], uv[6];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) {
-      const double pi = u[i * Ca + s] + beta * p[i * Ca + s];
-      const double si = w[i * Ca + s] + beta * sv[i * Ca + s];
-      p[i * Ca + s] = pi;
-      sv[i * Ca + s] = si;
-      x[i * Ca + s] += alpha * pi;
-      rv[i] = r[i * Ca + s] - alpha * si;
-      r[i * Ca + s] = rv[i];
-    }
-    sym6_mul_soa(Minv, Ca, s, rv, uv);
+  for (int i = 0; i < 6; ++i) {
+    const double pi = uv[i] + beta * pv[i];
+    const double si = wv[i] + beta * sv0[i];
+    p[i * Ca + s] = pi;
+    sv[i * Ca + s] = si;
+    x[i * Ca + s] += alpha * pi;
+    rv[i] -= alpha * si;
+    r[i * Ca + s] = rv[i];
+  }
 #pragma unroll
-    for (int i = 0; i < 6; ++i) {
-      u[i * Ca + s] = uv[i];
-      mvt[s].u[i] = T(uv[i]);
-    }
+  for (int i = 0; i < 6; ++i) {
+    double a = 0.0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) a += m[sym6(i, j)] * rv[j];
+    u[i * Ca + s] = a;
+    mvt[s].u[i] = T(a);
   }
 }
 
@@ -1405,7 +1526,7 @@ inline unsigned blocks_for(int64_t n, int b = kBlock) { return unsigned((n + b -
 // ================================================================== launchers
 void launch_cam_table(hipStream_t s, int C, const double* cams, const double* intr,
                       Cam<double>* camd, Cam<float>* camf) {
-  hipLaunchKernelGGL(k_cam_table, dim3(blocks_for(C)), dim3(kBlock), 0, s, C, cams, intr, camd,
+  launch_k(k_cam_table, dim3(blocks_for(C)), dim3(kBlock), 0, s, C, cams, intr, camd,
                      camf);
 }
 
@@ -1413,20 +1534,20 @@ void launch_validate(hipStream_t s, int64_t N, const Model& m, const int* pm_cam
                      const int* pm_pt, const float2* xy, const float* depth,
                      const double* pts, const Cam<double>* camd, uint8_t* vrow) {
   if (N == 0) return;
-  hipLaunchKernelGGL(k_validate, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, m, pm_cam, pm_pt,
+  launch_k(k_validate, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, m, pm_cam, pm_pt,
                      xy, depth, pts, camd, vrow);
 }
 
 void launch_cam_rows(hipStream_t s, int C, const int* cm_off, const int* cm_perm,
                      const uint8_t* vrow, const uint8_t* fixed, int need, uint8_t* act_c) {
-  hipLaunchKernelGGL(k_cam_rows, dim3(C), dim3(kBlock), 0, s, cm_off, cm_perm, vrow, fixed,
+  launch_k(k_cam_rows, dim3(C), dim3(kBlock), 0, s, cm_off, cm_perm, vrow, fixed,
                      need, act_c);
 }
 
 void launch_point_rows_prune(hipStream_t s, int P, const int* pt_off, const int* pm_cam,
                              const uint8_t* act_c, const uint8_t* fixed, int need,
                              uint8_t* vrow, uint8_t* act_p, int* changed) {
-  hipLaunchKernelGGL(k_point_rows_prune, dim3(blocks_for(P)), dim3(kBlock), 0, s, P, pt_off,
+  launch_k(k_point_rows_prune, dim3(blocks_for(P)), dim3(kBlock), 0, s, P, pt_off,
                      pm_cam, act_c, fixed, need, vrow, act_p, changed);
 }
 
@@ -1444,14 +1565,14 @@ void launch_scan_cm(hipStream_t s, int64_t n, const int* cm_perm, const uint8_t*
 void launch_compact_points(hipStream_t s, int P, const uint8_t* act_p, const int* rank_p,
                            const int* pt_off, const int* pos_pm, const double* pts,
                            int* pt_src, int* off_hat, double* Xd, float* Xf) {
-  hipLaunchKernelGGL(k_compact_points, dim3(blocks_for(P)), dim3(kBlock), 0, s, P, act_p,
+  launch_k(k_compact_points, dim3(blocks_for(P)), dim3(kBlock), 0, s, P, act_p,
                      rank_p, pt_off, pos_pm, pts, pt_src, off_hat, Xd, Xf);
 }
 
 void launch_compact_cams(hipStream_t s, int C, const uint8_t* act_c, const int* rank_c,
                          const uint8_t* fixed, const int* fixed_rank, const int* cm_off,
                          const int* pos_cm, int* slot_all, int* cam_src, int* cm_off_hat) {
-  hipLaunchKernelGGL(k_compact_cams, dim3(blocks_for(C)), dim3(kBlock), 0, s, C, act_c, rank_c,
+  launch_k(k_compact_cams, dim3(blocks_for(C)), dim3(kBlock), 0, s, C, act_c, rank_c,
                      fixed, fixed_rank, cm_off, pos_cm, slot_all, cam_src, cm_off_hat);
 }
 
@@ -1459,18 +1580,17 @@ void launch_compact_cam_table(hipStream_t s, int n, const int* cam_src,
                               const Cam<double>* camd, const Cam<float>* camf,
                               Cam<double>* camd_hat, Cam<float>* camf_hat) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_compact_cam_table, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, cam_src,
+  launch_k(k_compact_cam_table, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, cam_src,
                      camd, camf, camd_hat, camf_hat);
 }
 
 void launch_compact_obs(hipStream_t s, int64_t N, const uint8_t* vrow, const int* pos_pm,
                         const int* pm_cam, const int* slot_all, const float2* pm_xy,
-                        const float* pm_depth, const int* pm_orig, int* cam_hat,
-                        float2* xy_hat, float* depth_hat, int* orig_hat) {
+                        const float* pm_depth, const int* pm_orig, int Ca, int* cam_hat,
+                        float2* xy_hat, float* depth_hat, int* orig_hat, int* pm_cm) {
   if (N == 0) return;
-  hipLaunchKernelGGL(k_compact_obs, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, vrow, pos_pm,
-                     pm_cam, slot_all, pm_xy, pm_depth, pm_orig, cam_hat, xy_hat, depth_hat,
-                     orig_hat);
+  launch_k(k_compact_obs, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, vrow, pos_pm, pm_cam,
+           slot_all, pm_xy, pm_depth, pm_orig, Ca, cam_hat, xy_hat, depth_hat, orig_hat, pm_cm);
 }
 
 void launch_compact_cm(hipStream_t s, int64_t N, const int* cm_perm, const uint8_t* vrow,
@@ -1478,7 +1598,7 @@ void launch_compact_cm(hipStream_t s, int64_t N, const int* cm_perm, const uint8
                        const int* pos_cm, const int* pos_pm, const int* rank_p, int* cm_pt,
                        int* cm_pm, int* pm_cm) {
   if (N == 0) return;
-  hipLaunchKernelGGL(k_compact_cm, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, cm_perm, vrow,
+  launch_k(k_compact_cm, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, cm_perm, vrow,
                      pm_cam, pm_pt, fixed, pos_cm, pos_pm, rank_p, cm_pt, cm_pm, pm_cm);
 }
 
@@ -1487,10 +1607,10 @@ void launch_lin_point(hipStream_t s, bool adj, const Model& m, const Compact<T>&
                       ObsMetric<T> om, double* V, double* gp, double* partials) {
   const unsigned nb = blocks_for(cp.Pa);
   if (adj)
-    hipLaunchKernelGGL((k_lin_point<T, true>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, V, gp,
+    launch_k((k_lin_point<T, true>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, V, gp,
                        partials);
   else
-    hipLaunchKernelGGL((k_lin_point<T, false>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, V, gp,
+    launch_k((k_lin_point<T, false>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, V, gp,
                        partials);
 }
 
@@ -1499,10 +1619,10 @@ void launch_cm_prepare(hipStream_t s, bool adj, int64_t Nc, const Compact<T>& cp
                        ObsMetric<T> om) {
   if (Nc == 0) return;
   if (adj)
-    hipLaunchKernelGGL((k_cm_prepare<T, true>), dim3(blocks_for(Nc)), dim3(kBlock), 0, s, Nc,
+    launch_k((k_cm_prepare<T, true>), dim3(blocks_for(Nc)), dim3(kBlock), 0, s, Nc,
                        cp, om);
   else
-    hipLaunchKernelGGL((k_cm_prepare<T, false>), dim3(blocks_for(Nc)), dim3(kBlock), 0, s, Nc,
+    launch_k((k_cm_prepare<T, false>), dim3(blocks_for(Nc)), dim3(kBlock), 0, s, Nc,
                        cp, om);
 }
 
@@ -1510,7 +1630,7 @@ template <typename T>
 void launch_point_damp(hipStream_t s, int Pa, double lam, double dmin, double dmax,
                        const double* V, const double* gp, const double* rhs_p, T* Vinv,
                        double* hp, int* bad) {
-  hipLaunchKernelGGL(k_point_damp<T>, dim3(blocks_for(Pa)), dim3(kBlock), 0, s, Pa, lam, dmin,
+  launch_k(k_point_damp<T>, dim3(blocks_for(Pa)), dim3(kBlock), 0, s, Pa, lam, dmin,
                      dmax, V, gp, rhs_p, Vinv, hp, bad);
 }
 
@@ -1521,58 +1641,70 @@ void launch_cam_assemble(hipStream_t s, bool adj, const Model& m, const Compact<
                          double* Uraw, T* Ustar, double* gc, double* b, double* Minv) {
   if (cp.Ca == 0) return;
   if (adj)
-    hipLaunchKernelGGL((k_cam_assemble<T, true>), dim3(cp.Ca), dim3(kBlock), 0, s, m, cp, om,
+    launch_k((k_cam_assemble<T, true>), dim3(cp.Ca), dim3(kBlock), 0, s, m, cp, om,
                        lam, dmin, dmax, Vinv, hp, rhs_c, Uraw, Ustar, gc, b, Minv);
   else
-    hipLaunchKernelGGL((k_cam_assemble<T, false>), dim3(cp.Ca), dim3(kBlock), 0, s, m, cp, om,
+    launch_k((k_cam_assemble<T, false>), dim3(cp.Ca), dim3(kBlock), 0, s, m, cp, om,
                        lam, dmin, dmax, Vinv, hp, rhs_c, Uraw, Ustar, gc, b, Minv);
 }
 
 template <typename T>
 void launch_mv_table(hipStream_t s, int n, const Cam<double>* camd_hat, MvCam<T>* mvt) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_mv_table<T>, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, camd_hat, mvt);
+  launch_k(k_mv_table<T>, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, camd_hat, mvt);
 }
 
 template <typename T>
 void launch_pcg_init(hipStream_t s, int Ca, const double* b, const double* Minv, double* x,
                      double* r, double* u, double* p, double* sv, MvCam<T>* mvt, PcgState* st,
                      double tol2, int max_iter) {
-  hipLaunchKernelGGL(k_pcg_init<T>, dim3(1), dim3(1024), 0, s, Ca, b, Minv, x, r, u, p, sv, mvt,
+  launch_k(k_pcg_init<T>, dim3(1), dim3(1024), 0, s, Ca, b, Minv, x, r, u, p, sv, mvt,
                      st, tol2, max_iter);
+}
+
+template <typename T, bool ADJ, int G>
+void schur_point_launch(hipStream_t s, const Model& m, const Compact<T>& cp, ObsMetric<T> om,
+                        const MvCam<T>* mvt, const T* Vinv, V4<T>* zq, const PcgState* st,
+                        const DevLimits& dl) {
+  const size_t tab = size_t(cp.Ca) * sizeof(MvCam<T>);
+  bool use_lds = dl.n_cu > 0 && cp.Ca > 0 && tab <= size_t(dl.lds_per_block);
+  if (use_lds && tab > 65536)
+    use_lds = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_schur_point_lds<T, ADJ, G>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  int(tab)) == hipSuccess;
+  if (use_lds) {
+    const int per_cu = 2 * tab <= size_t(dl.lds_per_cu) ? 2 : 1;
+    const int grid = (dl.n_cu * per_cu + 7) / 8 * 8;
+    const int ppb = (cp.Pa + grid - 1) / grid;
+    launch_k(k_schur_point_lds<T, ADJ, G>, dim3(grid), dim3(kPtLdsBlock), uint32_t(tab), s, m,
+             cp, om, mvt, Vinv, zq, st, ppb);
+  } else {
+    const unsigned nb = (blocks_for(int64_t(cp.Pa) * G) + 7) / 8 * 8;   // one share per XCD
+    launch_k(k_schur_point<T, ADJ, G>, dim3(nb), dim3(kBlock), 0, s, m, cp, om, mvt, Vinv, zq,
+             st);
+  }
 }
 
 template <typename T, bool ADJ>
 void schur_point_g(hipStream_t s, int G, const Model& m, const Compact<T>& cp, ObsMetric<T> om,
-                   const MvCam<T>* mvt, const T* Vinv, V4<T>* zq, const PcgState* st) {
-  const unsigned nb = blocks_for(int64_t(cp.Pa) * G);
+                   const MvCam<T>* mvt, const T* Vinv, V4<T>* zq, const PcgState* st,
+                   const DevLimits& dl) {
   switch (G) {
-    case 2:
-      hipLaunchKernelGGL((k_schur_point<T, ADJ, 2>), dim3(nb), dim3(kBlock), 0, s, m, cp, om,
-                         mvt, Vinv, zq, st);
-      break;
-    case 4:
-      hipLaunchKernelGGL((k_schur_point<T, ADJ, 4>), dim3(nb), dim3(kBlock), 0, s, m, cp, om,
-                         mvt, Vinv, zq, st);
-      break;
-    case 16:
-      hipLaunchKernelGGL((k_schur_point<T, ADJ, 16>), dim3(nb), dim3(kBlock), 0, s, m, cp, om,
-                         mvt, Vinv, zq, st);
-      break;
-    default:
-      hipLaunchKernelGGL((k_schur_point<T, ADJ, 8>), dim3(nb), dim3(kBlock), 0, s, m, cp, om,
-                         mvt, Vinv, zq, st);
+    case 2: schur_point_launch<T, ADJ, 2>(s, m, cp, om, mvt, Vinv, zq, st, dl); break;
+    case 4: schur_point_launch<T, ADJ, 4>(s, m, cp, om, mvt, Vinv, zq, st, dl); break;
+    case 16: schur_point_launch<T, ADJ, 16>(s, m, cp, om, mvt, Vinv, zq, st, dl); break;
+    default: schur_point_launch<T, ADJ, 8>(s, m, cp, om, mvt, Vinv, zq, st, dl);
   }
 }
 
 template <typename T>
 void launch_schur_point(hipStream_t s, bool adj, int G, const Model& m, const Compact<T>& cp,
                         ObsMetric<T> om, const MvCam<T>* mvt, const T* Vinv, V4<T>* zq,
-                        const PcgState* st) {
+                        const PcgState* st, const DevLimits& dl) {
   if (adj)
-    schur_point_g<T, true>(s, G, m, cp, om, mvt, Vinv, zq, st);
+    schur_point_g<T, true>(s, G, m, cp, om, mvt, Vinv, zq, st, dl);
   else
-    schur_point_g<T, false>(s, G, m, cp, om, mvt, Vinv, zq, st);
+    schur_point_g<T, false>(s, G, m, cp, om, mvt, Vinv, zq, st, dl);
 }
 
 template <typename T>
@@ -1582,19 +1714,20 @@ void launch_schur_cam(hipStream_t s, bool adj, const Model& m, const Compact<T>&
   if (cp.Ca <= 0) return;
   const unsigned grid = unsigned((cp.Ca + 7) / 8 * 8);   // one share per XCD
   if (adj)
-    hipLaunchKernelGGL((k_schur_cam<T, true>), dim3(grid), dim3(kCamBlock), 0, s, m, cp, om,
+    launch_k((k_schur_cam<T, true>), dim3(grid), dim3(kCamBlock), 0, s, m, cp, om,
                        Ustar, u, r, zq, w, dots, st);
   else
-    hipLaunchKernelGGL((k_schur_cam<T, false>), dim3(grid), dim3(kCamBlock), 0, s, m, cp, om,
+    launch_k((k_schur_cam<T, false>), dim3(grid), dim3(kCamBlock), 0, s, m, cp, om,
                        Ustar, u, r, zq, w, dots, st);
 }
 
 template <typename T>
-void launch_pcg_update(hipStream_t s, int Ca, const double* Minv, const double* dots,
+void launch_pcg_update(hipStream_t s, int Ca, int k, const double* Minv, const double* dots,
                        double* x, double* r, double* u, double* p, double* sv, const double* w,
                        MvCam<T>* mvt, PcgState* st) {
-  hipLaunchKernelGGL(k_pcg_update<T>, dim3(1), dim3(1024), 0, s, Ca, Minv, dots, x, r, u, p, sv,
-                     w, mvt, st);
+  if (Ca <= 0) return;
+  launch_k(k_pcg_update<T>, dim3((Ca + kUpdCams - 1) / kUpdCams), dim3(kUpdBlock), 0,
+                     s, Ca, k, Minv, dots, x, r, u, p, sv, w, mvt, st);
 }
 
 template <typename T, bool ADJ>
@@ -1604,19 +1737,19 @@ void backsub_g(hipStream_t s, int G, const Model& m, const Compact<T>& cp, ObsMe
   const unsigned nb = blocks_for(int64_t(cp.Pa) * G);
   switch (G) {
     case 2:
-      hipLaunchKernelGGL((k_backsub<T, ADJ, 2>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, Vinv,
+      launch_k((k_backsub<T, ADJ, 2>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, Vinv,
                          x, gp, rhs_p, dp);
       break;
     case 4:
-      hipLaunchKernelGGL((k_backsub<T, ADJ, 4>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, Vinv,
+      launch_k((k_backsub<T, ADJ, 4>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, Vinv,
                          x, gp, rhs_p, dp);
       break;
     case 16:
-      hipLaunchKernelGGL((k_backsub<T, ADJ, 16>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, Vinv,
+      launch_k((k_backsub<T, ADJ, 16>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, Vinv,
                          x, gp, rhs_p, dp);
       break;
     default:
-      hipLaunchKernelGGL((k_backsub<T, ADJ, 8>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, Vinv,
+      launch_k((k_backsub<T, ADJ, 8>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, Vinv,
                          x, gp, rhs_p, dp);
   }
 }
@@ -1635,7 +1768,7 @@ void launch_cam_candidate(hipStream_t s, int Ca, int Cf, const int* cam_src, con
                           const double* cams, const Cam<double>* camd_hat, double* cand_cams,
                           Cam<double>* cand_tab) {
   if (Ca + Cf == 0) return;
-  hipLaunchKernelGGL(k_cam_candidate, dim3(blocks_for(Ca + Cf)), dim3(kBlock), 0, s, Ca, Cf,
+  launch_k(k_cam_candidate, dim3(blocks_for(Ca + Cf)), dim3(kBlock), 0, s, Ca, Cf,
                      cam_src, x, cams, camd_hat, cand_cams, cand_tab);
 }
 
@@ -1643,14 +1776,14 @@ template <typename T>
 void launch_point_candidate(hipStream_t s, const Model& m, const Compact<T>& cp,
                             const Cam<double>* cand_tab, const double* x, const double* dp,
                             const double* gp, const T* w, double* Xcand, double* partials) {
-  hipLaunchKernelGGL(k_point_candidate<T>, dim3(blocks_for(cp.Pa)), dim3(kBlock), 0, s, m, cp,
+  launch_k(k_point_candidate<T>, dim3(blocks_for(cp.Pa)), dim3(kBlock), 0, s, m, cp,
                      cand_tab, x, dp, gp, w, Xcand, partials);
 }
 
 void launch_reduce_partials(hipStream_t s, int nblocks, int K, const double* partials,
                             unsigned max_mask, int Ca, const double* gc, const double* x,
                             double* out) {
-  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(1024), 0, s, nblocks, K, partials,
+  launch_k(k_reduce_partials, dim3(1), dim3(1024), 0, s, nblocks, K, partials,
                      max_mask, Ca, gc, x, out);
 }
 
@@ -1658,7 +1791,7 @@ void launch_scatter(hipStream_t s, int Pa, int Ca, const int* pt_src, const doub
                     const int* cam_src, const double* cand_cams, double* pts, double* cams) {
   const int n = Pa > Ca ? Pa : Ca;
   if (n == 0) return;
-  hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n)), dim3(kBlock), 0, s, Pa, Ca, pt_src, Xcand,
+  launch_k(k_scatter, dim3(blocks_for(n)), dim3(kBlock), 0, s, Pa, Ca, pt_src, Xcand,
                      cam_src, cand_cams, pts, cams);
 }
 
@@ -1667,7 +1800,7 @@ void launch_adjoint_rhs(hipStream_t s, int Ca, int Pa, const int* cam_src, const
                         const double* grad_pts, double* rhs_c, double* rhs_p) {
   const int n = Pa > Ca ? Pa : Ca;
   if (n == 0) return;
-  hipLaunchKernelGGL(k_adjoint_rhs, dim3(blocks_for(n)), dim3(kBlock), 0, s, Ca, Pa, cam_src,
+  launch_k(k_adjoint_rhs, dim3(blocks_for(n)), dim3(kBlock), 0, s, Ca, Pa, cam_src,
                      cams, grad_cams, pt_src, pt_user, grad_pts, rhs_c, rhs_p);
 }
 
@@ -1675,7 +1808,7 @@ template <typename T>
 void launch_adjoint_obs(hipStream_t s, const Model& m, const Compact<T>& cp, ObsMetric<T> om,
                         const double* x, const double* dp, const int* orig, float* gxy,
                         float* gdepth) {
-  hipLaunchKernelGGL(k_adjoint_obs<T>, dim3(blocks_for(cp.Pa)), dim3(kBlock), 0, s, m, cp, om,
+  launch_k(k_adjoint_obs<T>, dim3(blocks_for(cp.Pa)), dim3(kBlock), 0, s, m, cp, om,
                      x, dp, orig, gxy, gdepth);
 }
 
@@ -1697,11 +1830,11 @@ void launch_adjoint_obs(hipStream_t s, const Model& m, const Compact<T>& cp, Obs
                                    double, int);                                               \
   template void launch_schur_point<T>(hipStream_t, bool, int, const Model&, const Compact<T>&,\
                                       ObsMetric<T>, const MvCam<T>*, const T*, V4<T>*,        \
-                                      const PcgState*);                                        \
+                                      const PcgState*, const DevLimits&);                      \
   template void launch_schur_cam<T>(hipStream_t, bool, const Model&, const Compact<T>&,       \
                                     ObsMetric<T>, const T*, const double*, const double*,     \
                                     const V4<T>*, double*, double*, const PcgState*);         \
-  template void launch_pcg_update<T>(hipStream_t, int, const double*, const double*, double*, \
+  template void launch_pcg_update<T>(hipStream_t, int, int, const double*, const double*, double*, \
                                      double*, double*, double*, double*, const double*,       \
                                      MvCam<T>*, PcgState*);                                    \
   template void launch_backsub<T>(hipStream_t, bool, int, const Model&, const Compact<T>&,    \
@@ -1716,5 +1849,12 @@ void launch_adjoint_obs(hipStream_t s, const Model& m, const Compact<T>& cp, Obs
 
 IBA_INSTANTIATE(float)
 IBA_INSTANTIATE(double)
+
+void set_launch_events(hipEvent_t start, hipEvent_t stop) {
+  g_ev_start = start;
+  g_ev_stop = stop;
+}
+
+int64_t launches_issued() { return g_launches; }
 
 }  // namespace iba

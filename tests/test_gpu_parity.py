@@ -182,17 +182,24 @@ def test_converged_medium_rms_both_precisions():
 
 
 def test_inactive_parameters_bit_identical_and_deterministic():
+    """Two runs, the second with per-launch timing events: bitwise identical results, and
+    the timing statistics cover every kernel of the step."""
     sc = scene("medium")
     runs = []
-    for _ in range(2):
-        ba = gpu_setup(sc, "mixed")
+    for timing in (0, 1):
+        ba = gpu_setup(sc, "mixed", timing=timing)
         for _ in range(4):
             ba.lm_step()
         ac, ap, _ = ba.get_active()
         runs.append(ba.get_params() + (ac, ap))
+        stats = {k["name"]: k for k in ba.kernel_stats()}
     (c1, p1, ac, ap), (c2, p2, _, _) = runs
     np.testing.assert_array_equal(c1, c2)          # bitwise reproducible
     np.testing.assert_array_equal(p1, p2)
+    for name in ("validate", "scan", "compact", "lin_point", "cam_assemble", "schur_point",
+                 "schur_cam", "pcg_update", "backsub", "point_candidate"):
+        assert stats[name]["launches"] > 0 and stats[name]["total_ms"] > 0, (name, stats)
+    assert stats["schur_point"]["launches"] == stats["pcg_update"]["launches"]
     bad = sc.notes["perturbed_cameras"]
     np.testing.assert_array_equal(c1[bad], sc.cams0[bad])
     outl = sc.notes["all_outlier_points"]
