@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "BA LM iters/s + Jacobian obs/s, FP32-mixed vs FP64, 1000-cam synthetic scene"
 HBM_PEAK_GBS = 8000.0
-LINEARIZE_KERNELS = ("lin_point", "cm_prepare", "cam_assemble")
+LINEARIZE_KERNELS = ("lin_point", "cam_assemble")
 
 
 def parse():

@@ -131,6 +131,7 @@ struct ba_ctx {
   float* Xf = nullptr;
 
   // precision-typed buffers (float in MIXED, double in FP64)
+  void *cm_e = nullptr, *prec = nullptr;
   void *w = nullptr, *eh = nullptr, *xcw = nullptr, *pm_xcw = nullptr, *cm_eh = nullptr,
        *V = nullptr, *Vinv = nullptr, *zq = nullptr, *Ustar = nullptr, *mvt = nullptr;
   double *gp = nullptr, *hp = nullptr, *dp = nullptr, *Xcand = nullptr, *rhs_p = nullptr;
@@ -355,11 +356,13 @@ void alloc_obs_buffers(ba_ctx& c) {
   c.Xf = A.alloc<float>(3 * size_t(P));
   c.w = A.alloc<char>(ts * N);
   c.xcw = A.alloc<char>(4 * ts * N);
+  c.cm_e = A.alloc<char>(4 * ts * N);
   c.pm_xcw = A.alloc<char>(4 * ts * N);
   c.eh = nullptr;
   c.cm_eh = nullptr;
   c.V = A.alloc<char>(sizeof(double) * 6 * P);
   c.Vinv = A.alloc<char>(ts * 6 * P);
+  c.prec = A.alloc<char>((ts == 8 ? sizeof(PtRec<double>) : sizeof(PtRec<float>)) * P);
   c.zq = A.alloc<char>(4 * ts * N);
   c.Ustar = A.alloc<char>(ts * 21 * C);
   c.mvt = A.alloc<char>(ts * 16 * C);
@@ -380,7 +383,7 @@ void alloc_obs_buffers(ba_ctx& c) {
   c.sv = A.alloc<double>(6 * size_t(C));
   c.wv = A.alloc<double>(6 * size_t(C));
   c.dots = A.alloc<double>(3 * size_t(C));
-  c.partials = A.alloc<double>(5 * (size_t(P) / kBlock + 2));
+  c.partials = A.alloc<double>(5 * (size_t(P) / kBlock + 16));
   c.scal = A.alloc<double>(16);
   c.pcg = A.alloc<PcgState>(1);
   c.grad_cams_d = nullptr;
@@ -432,6 +435,7 @@ ObsMetric<T> metric_view(ba_ctx& c) {
   ObsMetric<T> om;
   om.w = static_cast<T*>(c.w);
   om.xcw = static_cast<V4<T>*>(c.xcw);
+  om.cm_e = static_cast<V4<T>*>(c.cm_e);
   om.pm_xcw = static_cast<V4<T>*>(c.pm_xcw);
   om.eh = static_cast<T*>(c.eh);
   om.cm_eh = static_cast<T*>(c.cm_eh);
@@ -531,16 +535,18 @@ void linearize(ba_ctx& c, bool adj) {
   Compact<T> cp = compact_view<T>(c);
   ObsMetric<T> om = metric_view<T>(c);
   const double ts = double(sizeof(T));
-  c.timed("lin_point", double(c.Nh) * (4 + 8 + 4 + ts + (adj ? 3 * ts : 0)) +
-                           double(c.Pa) * (4 + 24 + 6 * ts + 24) + double(c.C) * 120,
+  // per observation: slot, xy, depth and camera-major position read; w and the (X_c, w)
+  // stream written, plus the camera-major (X_c, w) and e (and eh) for solve cameras
+  c.timed("lin_point", double(c.Nh) * (4 + 8 + 4 + 4 + ts + 4 * ts + (adj ? 3 * ts : 0)) +
+                           double(c.Nc) * (8 * ts + (adj ? 3 * ts : 0)) +
+                           double(c.Pa) * (4 + 24 + 48 + 24) + double(c.C) * 120,
           -1, [&] {
-            launch_lin_point<T>(s, adj, m, cp, om, static_cast<double*>(c.V), c.gp, c.partials);
+            launch_lin_point<T>(s, adj, lanes_per_point(c), m, cp, om,
+                                static_cast<double*>(c.V), c.gp, c.partials);
           });
-  const int nb = int((c.Pa + kBlock - 1) / kBlock);
+  const int nb = lin_point_blocks(c.Pa);
   launch_reduce_partials(s, nb, 3, c.partials, 0x4u, 0, nullptr, nullptr, c.scal);
   HIP_LAUNCH_CHECK();
-  c.timed("cm_prepare", double(c.Nc) * (8 + ts + 24 + 4 * ts + (adj ? 6 * ts : 0)), -1,
-          [&] { launch_cm_prepare<T>(s, adj, c.Nc, cp, om); });
 }
 
 // Damping-dependent setup: point inverses, camera blocks, Schur RHS, preconditioner.
@@ -552,17 +558,21 @@ void setup_system(ba_ctx& c, bool adj, double lam, const double* rhs_c, const do
   ObsMetric<T> om = metric_view<T>(c);
   const double ts = double(sizeof(T));
   HIP_CHECK(hipMemsetAsync(c.flags + 1, 0, sizeof(int), s));
-  c.timed("point_damp", double(c.Pa) * (6 * ts + 24 + 6 * ts + 24), -1, [&] {
+  c.timed("point_damp", double(c.Pa) * (48 + 24 + 6 * ts + 24 + double(sizeof(PtRec<T>))), -1,
+          [&] {
     launch_point_damp<T>(s, c.Pa, lam, c.opt.diag_min, c.opt.diag_max,
                          static_cast<const double*>(c.V), c.gp, rhs_p, static_cast<T*>(c.Vinv),
-                         c.hp, c.flags + 1);
+                         c.hp, static_cast<PtRec<T>*>(c.prec), c.flags + 1);
   });
+  // per camera-major observation: the point rank, the (X_c, w) and e streams (+ eh); every
+  // point record once; per camera its blocks written
   c.timed("cam_assemble",
-          double(c.Nc) * (8 + ts + 12 + (adj ? 3 * ts : 0)) + double(c.Pa) * (24 + 6 * ts + 24) +
+          double(c.Nc) * (4 + 8 * ts + (adj ? 3 * ts : 0)) +
+              double(c.Pa) * double(sizeof(PtRec<T>)) +
               double(c.Ca) * (21 * 8 + 21 * ts + 6 * 8 * 2 + 21 * 8),
           -1, [&] {
             launch_cam_assemble<T>(s, adj, m, cp, om, lam, c.opt.diag_min, c.opt.diag_max,
-                                   static_cast<const T*>(c.Vinv), c.hp, rhs_c, c.Uraw,
+                                   static_cast<const PtRec<T>*>(c.prec), rhs_c, c.Uraw,
                                    static_cast<T*>(c.Ustar), c.gc, c.b, c.Minv);
           });
 }

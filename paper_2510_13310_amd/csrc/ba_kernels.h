@@ -108,7 +108,15 @@ struct ObsMetric {
   T* eh;         // Nh x 3: unit residual direction (adjoint only, else nullptr)
   V4<T>* pm_xcw; // Nh: camera-frame point and w, point-major order
   V4<T>* xcw;    // Nc: camera-frame point and w, camera-major order
+  V4<T>* cm_e;   // Nc: residual e (3, w slot unused) at the linearisation point, camera-major
   T* cm_eh;      // Nc x 3 (adjoint only)
+};
+
+// Point data the camera assembly gathers once per observation, packed in one record.
+template <typename T>
+struct alignas(16) PtRec {
+  double hp[3];   // Vinv rhs_p
+  T vinv[6];      // damped inverse point block (symmetric 3x3)
 };
 
 // ------------------------------------------------------------------ extraction
@@ -153,27 +161,27 @@ void launch_mv_table(hipStream_t s, int n, const Cam<double>* camd_hat, MvCam<T>
 // ------------------------------------------------------------------ linearisation
 // Per point: residuals (float64), robust weights, V = J_p^T M J_p (T products accumulated in
 // float64), gp = J_p^T M e (float64); per block: cost, sum |r_2d|^2 and max |gp| into
-// partials[3 * block].
+// partials[3 * block]. Per observation the (X_c, w) stream in both orders, and e (and eh in
+// adjoint mode) at the camera-major position of the observations of solve cameras.
+// G lanes per point; one workgroup per 256 points, grid lin_point_blocks(Pa) (partials
+// needs 3 doubles per workgroup).
+inline int lin_point_blocks(int Pa) { return ((Pa + kBlock - 1) / kBlock + 7) / 8 * 8; }
 template <typename T>
-void launch_lin_point(hipStream_t s, bool adj, const Model& m, const Compact<T>& cp,
+void launch_lin_point(hipStream_t s, bool adj, int G, const Model& m, const Compact<T>& cp,
                       ObsMetric<T> om, double* V, double* gp, double* partials);
-// Camera-major stream of the PCG camera pass: X_c and w per observation (+ eh).
-template <typename T>
-void launch_cm_prepare(hipStream_t s, bool adj, int64_t Nc, const Compact<T>& cp,
-                       ObsMetric<T> om);
 // V* = V + lam clamp(diag V); Vinv (inverted in float64, stored as T); hp = Vinv rhs_p.
 // rhs_p = -gp when rhs_p == nullptr.
 template <typename T>
 void launch_point_damp(hipStream_t s, int Pa, double lam, double dmin, double dmax,
                        const double* V, const double* gp, const double* rhs_p, T* Vinv,
-                       double* hp, int* bad);
+                       double* hp, PtRec<T>* prec, int* bad);
 // Per camera slot: U = J_c^T M J_c, gc, b = rhs_c - sum W hp, S_cc = U* - sum W Vinv W^T and
 // its inverse (Cholesky, float64). rhs_c = -gc when rhs_c == nullptr. SoA outputs.
 template <typename T>
 void launch_cam_assemble(hipStream_t s, bool adj, const Model& m, const Compact<T>& cp,
                          ObsMetric<T> om, double lam, double dmin, double dmax,
-                         const T* Vinv, const double* hp, const double* rhs_c,
-                         double* Uraw, T* Ustar, double* gc, double* b, double* Minv);
+                         const PtRec<T>* prec, const double* rhs_c, double* Uraw, T* Ustar,
+                         double* gc, double* b, double* Minv);
 
 // ------------------------------------------------------------------ PCG on S
 // x = 0, r = b, u = M^-1 r (also into the matvec records), p = s = 0.

@@ -526,70 +526,104 @@ k_mv_table(int n, const Cam<double>* __restrict__ camd_hat, MvCam<T>* __restrict
 }
 
 // ------------------------------------------------------------------ linearisation
-template <typename T, bool ADJ>
+// Workgroup b (XCD-mapped as in the PCG point pass) linearises points [256 b, 256 b + 256) in
+// G tiles, with G lanes per point; lanes combine V and gp with shuffles. Partials per
+// workgroup: cost, sum |r_2d|^2, max |gp|.
+template <typename T, bool ADJ, int G>
 __global__ void __launch_bounds__(kBlock)
 k_lin_point(Model m, Compact<T> cp, ObsMetric<T> om, double* __restrict__ V,
             double* __restrict__ gp, double* __restrict__ partials) {
   __shared__ double smem[3 * (kBlock / kWave)];
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int per = gridDim.x / 8;
+  const int blk = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  constexpr int tile = kBlock / G;
+  const int l = int(threadIdx.x) % G;
   double acc[3] = {0.0, 0.0, 0.0};   // cost, sum |r_2d|^2, max |gp|
-  if (r < cp.Pa) {
-    const double X0 = cp.Xd[3 * r], X1 = cp.Xd[3 * r + 1], X2 = cp.Xd[3 * r + 2];
+  for (int t = 0; t < G; ++t) {
+    const int r = blk * kBlock + t * tile + int(threadIdx.x) / G;
+    const bool live = r < cp.Pa;
     double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     double g[3] = {0.0, 0.0, 0.0};
-    for (int j = cp.off[r]; j < cp.off[r + 1]; ++j) {
-      const Cam<double> cm = cp.camd[cp.cam[j]];
-      double Xc[3], e[3];
-      cam_frame(cm, X0, X1, X2, Xc);
-      residual(cm, Xc, cp.xy[j], cp.depth[j], m.lam_d, e);
-      const double s = e[0] * e[0] + e[1] * e[1] + e[2] * e[2];
-      double rho, w, d2;
-      huber(s, m.huber, rho, w, d2);
-      acc[0] += 0.5 * rho;
-      acc[1] += e[0] * e[0] + e[1] * e[1];
-      om.w[j] = T(w);
-      V4<T> xw;
-      xw.x = T(Xc[0]);
-      xw.y = T(Xc[1]);
-      xw.z = T(Xc[2]);
-      xw.w = T(w);
-      om.pm_xcw[j] = xw;
-      // point block and gradient from float64 rows in both precisions: the depth direction
-      // of a weakly observed point can sit below float32 resolution
-      AMat<double, ADJ> A;
-      A.set(cm.f, m.lam_d, Xc);
-      if constexpr (ADJ) {
-        const double inv = d2 != 0.0 ? 1.0 / sqrt(s) : 0.0;
-        const double eh[3] = {e[0] * inv, e[1] * inv, e[2] * inv};
-        om.eh[3 * j] = T(eh[0]);
-        om.eh[3 * j + 1] = T(eh[1]);
-        om.eh[3 * j + 2] = T(eh[2]);
-        A.project(eh);
-      }
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        double a[3], jp[3];
-        A.row(i, a);
-        rot_tmul(cm, a, jp);
-#pragma unroll
-        for (int p = 0; p < 3; ++p) {
-#pragma unroll
-          for (int q = p; q < 3; ++q) v[sym3(p, q)] += w * jp[p] * jp[q];
+    if (live) {
+      const double X0 = cp.Xd[3 * r], X1 = cp.Xd[3 * r + 1], X2 = cp.Xd[3 * r + 2];
+      for (int j = cp.off[r] + l; j < cp.off[r + 1]; j += G) {
+        const Cam<double> cm = cp.camd[cp.cam[j]];
+        double Xc[3], e[3];
+        cam_frame(cm, X0, X1, X2, Xc);
+        residual(cm, Xc, cp.xy[j], cp.depth[j], m.lam_d, e);
+        const double s = e[0] * e[0] + e[1] * e[1] + e[2] * e[2];
+        double rho, w, d2;
+        huber(s, m.huber, rho, w, d2);
+        acc[0] += 0.5 * rho;
+        acc[1] += e[0] * e[0] + e[1] * e[1];
+        om.w[j] = T(w);
+        V4<T> xw;
+        xw.x = T(Xc[0]);
+        xw.y = T(Xc[1]);
+        xw.z = T(Xc[2]);
+        xw.w = T(w);
+        om.pm_xcw[j] = xw;
+        const int ic = cp.pm_cm[j];   // camera-major copies (solve cameras only)
+        if (ic >= 0) {
+          om.xcw[ic] = xw;
+          V4<T> ev;
+          ev.x = T(e[0]);
+          ev.y = T(e[1]);
+          ev.z = T(e[2]);
+          ev.w = T(0);
+          om.cm_e[ic] = ev;
         }
-        if constexpr (!ADJ) {
-          const double we = w * e[i];
-          g[0] += we * jp[0];
-          g[1] += we * jp[1];
-          g[2] += we * jp[2];
+        // point block and gradient from float64 rows in both precisions: the depth direction
+        // of a weakly observed point can sit below float32 resolution
+        AMat<double, ADJ> A;
+        A.set(cm.f, m.lam_d, Xc);
+        if constexpr (ADJ) {
+          const double inv = d2 != 0.0 ? 1.0 / sqrt(s) : 0.0;
+          const double eh[3] = {e[0] * inv, e[1] * inv, e[2] * inv};
+          om.eh[3 * j] = T(eh[0]);
+          om.eh[3 * j + 1] = T(eh[1]);
+          om.eh[3 * j + 2] = T(eh[2]);
+          if (ic >= 0) {
+            om.cm_eh[3 * ic] = T(eh[0]);
+            om.cm_eh[3 * ic + 1] = T(eh[1]);
+            om.cm_eh[3 * ic + 2] = T(eh[2]);
+          }
+          A.project(eh);
+        }
+  #pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          double a[3], jp[3];
+          A.row(i, a);
+          rot_tmul(cm, a, jp);
+  #pragma unroll
+          for (int p = 0; p < 3; ++p) {
+  #pragma unroll
+            for (int q = p; q < 3; ++q) v[sym3(p, q)] += w * jp[p] * jp[q];
+          }
+          if constexpr (!ADJ) {
+            const double we = w * e[i];
+            g[0] += we * jp[0];
+            g[1] += we * jp[1];
+            g[2] += we * jp[2];
+          }
         }
       }
     }
 #pragma unroll
-    for (int i = 0; i < 6; ++i) V[6 * r + i] = v[i];
-    gp[3 * r] = g[0];
-    gp[3 * r + 1] = g[1];
-    gp[3 * r + 2] = g[2];
-    acc[2] = fmax(fabs(g[0]), fmax(fabs(g[1]), fabs(g[2])));
+    for (int o = G / 2; o > 0; o >>= 1) {
+#pragma unroll
+      for (int i = 0; i < 6; ++i) v[i] += __shfl_xor(v[i], o, kWave);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) g[i] += __shfl_xor(g[i], o, kWave);
+    }
+    if (live && l == 0) {
+#pragma unroll
+      for (int i = 0; i < 6; ++i) V[6 * r + i] = v[i];
+      gp[3 * r] = g[0];
+      gp[3 * r + 1] = g[1];
+      gp[3 * r + 2] = g[2];
+      acc[2] = fmax(acc[2], fmax(fabs(g[0]), fmax(fabs(g[1]), fabs(g[2]))));
+    }
   }
   // block reduction: two sums and one max
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
@@ -609,34 +643,9 @@ k_lin_point(Model m, Compact<T> cp, ObsMetric<T> om, double* __restrict__ V,
       a1 += smem[3 * w + 1];
       a2 = fmax(a2, smem[3 * w + 2]);
     }
-    partials[3 * blockIdx.x] = a0;
-    partials[3 * blockIdx.x + 1] = a1;
-    partials[3 * blockIdx.x + 2] = a2;
-  }
-}
-
-// Camera-major stream for the PCG camera pass: the camera-frame point (computed in float64
-// at the linearisation point) and the robust weight, one aligned 4-vector per observation.
-template <typename T, bool ADJ>
-__global__ void __launch_bounds__(kBlock)
-k_cm_prepare(int64_t Nc, Compact<T> cp, ObsMetric<T> om) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= Nc) return;
-  const int j = cp.cm_pm[i];
-  const int r = cp.cm_pt[i];
-  const Cam<double>& cm = cp.camd[cp.cam[j]];
-  double Xc[3];
-  cam_frame(cm, cp.Xd[3 * r], cp.Xd[3 * r + 1], cp.Xd[3 * r + 2], Xc);
-  V4<T> v;
-  v.x = T(Xc[0]);
-  v.y = T(Xc[1]);
-  v.z = T(Xc[2]);
-  v.w = om.w[j];
-  om.xcw[i] = v;
-  if constexpr (ADJ) {
-    om.cm_eh[3 * i] = om.eh[3 * j];
-    om.cm_eh[3 * i + 1] = om.eh[3 * j + 1];
-    om.cm_eh[3 * i + 2] = om.eh[3 * j + 2];
+    partials[3 * blk] = a0;
+    partials[3 * blk + 1] = a1;
+    partials[3 * blk + 2] = a2;
   }
 }
 
@@ -645,7 +654,8 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_point_damp(int Pa, double lam, double dmin, double dmax, const double* __restrict__ V,
              const double* __restrict__ gp, const double* __restrict__ rhs_p,
-             T* __restrict__ Vinv, double* __restrict__ hp, int* __restrict__ bad) {
+             T* __restrict__ Vinv, double* __restrict__ hp, PtRec<T>* __restrict__ prec,
+             int* __restrict__ bad) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= Pa) return;
   double v00 = V[6 * r], v01 = V[6 * r + 1], v02 = V[6 * r + 2];
@@ -672,9 +682,15 @@ k_point_damp(int Pa, double lam, double dmin, double dmax, const double* __restr
   for (int i = 0; i < 6; ++i) Vinv[6 * r + i] = T(inv[i]);
   double b[3];
   for (int i = 0; i < 3; ++i) b[i] = rhs_p ? rhs_p[3 * r + i] : -gp[3 * r + i];
-  hp[3 * r] = inv[0] * b[0] + inv[1] * b[1] + inv[2] * b[2];
-  hp[3 * r + 1] = inv[1] * b[0] + inv[3] * b[1] + inv[4] * b[2];
-  hp[3 * r + 2] = inv[2] * b[0] + inv[4] * b[1] + inv[5] * b[2];
+  PtRec<T> rec;
+  rec.hp[0] = inv[0] * b[0] + inv[1] * b[1] + inv[2] * b[2];
+  rec.hp[1] = inv[1] * b[0] + inv[3] * b[1] + inv[4] * b[2];
+  rec.hp[2] = inv[2] * b[0] + inv[4] * b[1] + inv[5] * b[2];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) hp[3 * r + i] = rec.hp[i];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) rec.vinv[i] = T(inv[i]);
+  prec[r] = rec;
 }
 
 // 6x6 SPD inverse through Cholesky (float64); returns false if not positive definite.
@@ -719,7 +735,7 @@ __device__ bool spd6_inverse(const double* A21, double* out21) {
 template <typename T, bool ADJ>
 __global__ void __launch_bounds__(kBlock)
 k_cam_assemble(Model m, Compact<T> cp, ObsMetric<T> om, double lam, double dmin, double dmax,
-               const T* __restrict__ Vinv, const double* __restrict__ hp,
+               const PtRec<T>* __restrict__ prec,
                const double* __restrict__ rhs_c, double* __restrict__ Uraw,
                T* __restrict__ Ustar, double* __restrict__ gc, double* __restrict__ b,
                double* __restrict__ Minv) {
@@ -732,13 +748,13 @@ k_cam_assemble(Model m, Compact<T> cp, ObsMetric<T> om, double lam, double dmin,
 #pragma unroll
   for (int i = 0; i < K; ++i) acc[i] = 0.0;
   for (int i = cp.cm_off[s] + threadIdx.x; i < cp.cm_off[s + 1]; i += blockDim.x) {
-    const int r = cp.cm_pt[i];
-    const int j = cp.cm_pm[i];
-    double Xc[3], e[3];
-    cam_frame(cm, cp.Xd[3 * r], cp.Xd[3 * r + 1], cp.Xd[3 * r + 2], Xc);
-    residual(cm, Xc, cp.xy[j], cp.depth[j], m.lam_d, e);
-    const T wt = om.w[j];
-    const T Xt[3] = {T(Xc[0]), T(Xc[1]), T(Xc[2])};
+    // streamed: (X_c, w) and e of this observation; gathered: one packed point record
+    const V4<T> xw = om.xcw[i];
+    const V4<T> ev = om.cm_e[i];
+    const PtRec<T> pr = prec[cp.cm_pt[i]];
+    const double e[3] = {double(ev.x), double(ev.y), double(ev.z)};
+    const T wt = xw.w;
+    const T Xt[3] = {xw.x, xw.y, xw.z};
     AMat<T, ADJ> A;
     A.set(T(cm.f), T(m.lam_d), Xt);
     if constexpr (ADJ) A.project(om.cm_eh + 3 * i);
@@ -771,8 +787,8 @@ k_cam_assemble(Model m, Compact<T> cp, ObsMetric<T> om, double lam, double dmin,
     // W Vinv W^T and W hp
     T vi[6];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) vi[q] = Vinv[6 * r + q];
-    const double h0 = hp[3 * r], h1 = hp[3 * r + 1], h2 = hp[3 * r + 2];
+    for (int q = 0; q < 6; ++q) vi[q] = pr.vinv[q];
+    const double h0 = pr.hp[0], h1 = pr.hp[1], h2 = pr.hp[2];
     T WV[18];
 #pragma unroll
     for (int p = 0; p < 6; ++p) {
@@ -987,16 +1003,17 @@ k_schur_point(Model m, Compact<T> cp, ObsMetric<T> om, const MvCam<T>* __restric
 }
 
 // Persistent variant for tables that fit in LDS: a few 1024-thread workgroups per CU each
-// copy the camera records into LDS once, then walk a contiguous range of ppb points (XCD
-// ranges as above). Random per-observation record reads then hit LDS instead of costing
-// one L1 tag lookup per lane.
+// copy the camera records into LDS once, so the random per-observation record reads hit LDS.
+// XCD x owns the x-th eighth of the point ranks (ppx points) and its workgroups take that
+// range's tiles round-robin: the XCD works on consecutive tiles at any moment, so the z
+// stores into each camera segment fill whole cache lines while they are in its L2.
 constexpr int kPtLdsBlock = 1024;
 
 template <typename T, bool ADJ, int G>
 __global__ void __launch_bounds__(kPtLdsBlock)
 k_schur_point_lds(Model m, Compact<T> cp, ObsMetric<T> om, const MvCam<T>* __restrict__ mvt,
                   const T* __restrict__ Vinv, V4<T>* __restrict__ zq_cm,
-                  const PcgState* __restrict__ st, int ppb) {
+                  const PcgState* __restrict__ st, int ppx) {
   extern __shared__ uint4 lds_tab[];   // cp.Ca records
   if (st->done) return;
   const int nchunk = cp.Ca * int(sizeof(MvCam<T>) / sizeof(uint4));
@@ -1004,12 +1021,13 @@ k_schur_point_lds(Model m, Compact<T> cp, ObsMetric<T> om, const MvCam<T>* __res
   for (int i = threadIdx.x; i < nchunk; i += kPtLdsBlock) lds_tab[i] = src[i];
   __syncthreads();
   const MvCam<T>* tab = reinterpret_cast<const MvCam<T>*>(lds_tab);
-  const int per = gridDim.x / 8;
-  const int blk = (blockIdx.x % 8) * per + blockIdx.x / 8;
-  const int lo = blk * ppb;
-  const int hi = min(cp.Pa, lo + ppb);
+  const int per = gridDim.x / 8;            // workgroups per XCD
+  const int xcd = blockIdx.x % 8;
+  const int j = blockIdx.x / 8;
+  const int lo = xcd * ppx;
+  const int hi = min(cp.Pa, lo + ppx);
   constexpr int tile = kPtLdsBlock / G;
-  for (int base = lo; base < hi; base += tile)
+  for (int base = lo + j * tile; base < hi; base += per * tile)
     schur_point_one<T, ADJ, G>(m, cp, om, tab, Vinv, zq_cm, base + int(threadIdx.x) / G, hi,
                                int(threadIdx.x) % G);
 }
@@ -1044,6 +1062,7 @@ k_schur_cam(Model m, Compact<T> cp, ObsMetric<T> om, const T* __restrict__ Ustar
   const Cam<T> cm = cp.camt[s];
   T acc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
   const int end = cp.cm_off[s + 1];
+#pragma unroll 2
   for (int i = cp.cm_off[s] + threadIdx.x; i < end; i += blockDim.x) {
     const V4<T> xw = om.xcw[i];
     const V4<T> zv = zq[i];
@@ -1602,50 +1621,47 @@ void launch_compact_cm(hipStream_t s, int64_t N, const int* cm_perm, const uint8
                      pm_cam, pm_pt, fixed, pos_cm, pos_pm, rank_p, cm_pt, cm_pm, pm_cm);
 }
 
-template <typename T>
-void launch_lin_point(hipStream_t s, bool adj, const Model& m, const Compact<T>& cp,
-                      ObsMetric<T> om, double* V, double* gp, double* partials) {
-  const unsigned nb = blocks_for(cp.Pa);
-  if (adj)
-    launch_k((k_lin_point<T, true>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, V, gp,
-                       partials);
-  else
-    launch_k((k_lin_point<T, false>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, V, gp,
-                       partials);
+template <typename T, bool ADJ>
+void lin_point_g(hipStream_t s, int G, const Model& m, const Compact<T>& cp, ObsMetric<T> om,
+                 double* V, double* gp, double* partials) {
+  const unsigned nb = unsigned(lin_point_blocks(cp.Pa));
+  switch (G) {
+    case 2: launch_k(k_lin_point<T, ADJ, 2>, dim3(nb), dim3(kBlock), 0, s, m, cp, om, V, gp, partials); break;
+    case 4: launch_k(k_lin_point<T, ADJ, 4>, dim3(nb), dim3(kBlock), 0, s, m, cp, om, V, gp, partials); break;
+    case 16: launch_k(k_lin_point<T, ADJ, 16>, dim3(nb), dim3(kBlock), 0, s, m, cp, om, V, gp, partials); break;
+    default: launch_k(k_lin_point<T, ADJ, 8>, dim3(nb), dim3(kBlock), 0, s, m, cp, om, V, gp, partials);
+  }
 }
 
 template <typename T>
-void launch_cm_prepare(hipStream_t s, bool adj, int64_t Nc, const Compact<T>& cp,
-                       ObsMetric<T> om) {
-  if (Nc == 0) return;
+void launch_lin_point(hipStream_t s, bool adj, int G, const Model& m, const Compact<T>& cp,
+                      ObsMetric<T> om, double* V, double* gp, double* partials) {
   if (adj)
-    launch_k((k_cm_prepare<T, true>), dim3(blocks_for(Nc)), dim3(kBlock), 0, s, Nc,
-                       cp, om);
+    lin_point_g<T, true>(s, G, m, cp, om, V, gp, partials);
   else
-    launch_k((k_cm_prepare<T, false>), dim3(blocks_for(Nc)), dim3(kBlock), 0, s, Nc,
-                       cp, om);
+    lin_point_g<T, false>(s, G, m, cp, om, V, gp, partials);
 }
 
 template <typename T>
 void launch_point_damp(hipStream_t s, int Pa, double lam, double dmin, double dmax,
                        const double* V, const double* gp, const double* rhs_p, T* Vinv,
-                       double* hp, int* bad) {
-  launch_k(k_point_damp<T>, dim3(blocks_for(Pa)), dim3(kBlock), 0, s, Pa, lam, dmin,
-                     dmax, V, gp, rhs_p, Vinv, hp, bad);
+                       double* hp, PtRec<T>* prec, int* bad) {
+  launch_k(k_point_damp<T>, dim3(blocks_for(Pa)), dim3(kBlock), 0, s, Pa, lam, dmin, dmax, V,
+           gp, rhs_p, Vinv, hp, prec, bad);
 }
 
 template <typename T>
 void launch_cam_assemble(hipStream_t s, bool adj, const Model& m, const Compact<T>& cp,
                          ObsMetric<T> om, double lam, double dmin, double dmax,
-                         const T* Vinv, const double* hp, const double* rhs_c,
-                         double* Uraw, T* Ustar, double* gc, double* b, double* Minv) {
+                         const PtRec<T>* prec, const double* rhs_c, double* Uraw, T* Ustar,
+                         double* gc, double* b, double* Minv) {
   if (cp.Ca == 0) return;
   if (adj)
-    launch_k((k_cam_assemble<T, true>), dim3(cp.Ca), dim3(kBlock), 0, s, m, cp, om,
-                       lam, dmin, dmax, Vinv, hp, rhs_c, Uraw, Ustar, gc, b, Minv);
+    launch_k((k_cam_assemble<T, true>), dim3(cp.Ca), dim3(kBlock), 0, s, m, cp, om, lam, dmin,
+             dmax, prec, rhs_c, Uraw, Ustar, gc, b, Minv);
   else
-    launch_k((k_cam_assemble<T, false>), dim3(cp.Ca), dim3(kBlock), 0, s, m, cp, om,
-                       lam, dmin, dmax, Vinv, hp, rhs_c, Uraw, Ustar, gc, b, Minv);
+    launch_k((k_cam_assemble<T, false>), dim3(cp.Ca), dim3(kBlock), 0, s, m, cp, om, lam, dmin,
+             dmax, prec, rhs_c, Uraw, Ustar, gc, b, Minv);
 }
 
 template <typename T>
@@ -1675,9 +1691,9 @@ void schur_point_launch(hipStream_t s, const Model& m, const Compact<T>& cp, Obs
   if (use_lds) {
     const int per_cu = 2 * tab <= size_t(dl.lds_per_cu) ? 2 : 1;
     const int grid = (dl.n_cu * per_cu + 7) / 8 * 8;
-    const int ppb = (cp.Pa + grid - 1) / grid;
+    const int ppx = (cp.Pa + 7) / 8;
     launch_k(k_schur_point_lds<T, ADJ, G>, dim3(grid), dim3(kPtLdsBlock), uint32_t(tab), s, m,
-             cp, om, mvt, Vinv, zq, st, ppb);
+             cp, om, mvt, Vinv, zq, st, ppx);
   } else {
     const unsigned nb = (blocks_for(int64_t(cp.Pa) * G) + 7) / 8 * 8;   // one share per XCD
     launch_k(k_schur_point<T, ADJ, G>, dim3(nb), dim3(kBlock), 0, s, m, cp, om, mvt, Vinv, zq,
@@ -1814,16 +1830,14 @@ void launch_adjoint_obs(hipStream_t s, const Model& m, const Compact<T>& cp, Obs
 
 // explicit instantiations for the two precisions
 #define IBA_INSTANTIATE(T)                                                                    \
-  template void launch_lin_point<T>(hipStream_t, bool, const Model&, const Compact<T>&,       \
+  template void launch_lin_point<T>(hipStream_t, bool, int, const Model&, const Compact<T>&,  \
                                     ObsMetric<T>, double*, double*, double*);                 \
-  template void launch_cm_prepare<T>(hipStream_t, bool, int64_t, const Compact<T>&,           \
-                                     ObsMetric<T>);                                            \
   template void launch_point_damp<T>(hipStream_t, int, double, double, double, const double*, \
-                                     const double*, const double*, T*, double*, int*);        \
+                                     const double*, const double*, T*, double*, PtRec<T>*,    \
+                                     int*);                                                    \
   template void launch_cam_assemble<T>(hipStream_t, bool, const Model&, const Compact<T>&,    \
-                                       ObsMetric<T>, double, double, double, const T*,        \
-                                       const double*, const double*, double*, T*, double*,    \
-                                       double*, double*);                                      \
+                                       ObsMetric<T>, double, double, double, const PtRec<T>*, \
+                                       const double*, double*, T*, double*, double*, double*); \
   template void launch_mv_table<T>(hipStream_t, int, const Cam<double>*, MvCam<T>*);         \
   template void launch_pcg_init<T>(hipStream_t, int, const double*, const double*, double*,   \
                                    double*, double*, double*, double*, MvCam<T>*, PcgState*,  \
