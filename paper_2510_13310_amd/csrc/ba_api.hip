@@ -363,7 +363,7 @@ void alloc_obs_buffers(ba_ctx& c) {
   c.V = A.alloc<char>(sizeof(double) * 6 * P);
   c.Vinv = A.alloc<char>(ts * 6 * P);
   c.prec = A.alloc<char>((ts == 8 ? sizeof(PtRec<double>) : sizeof(PtRec<float>)) * P);
-  c.zq = A.alloc<char>(4 * ts * N);
+  c.zq = A.alloc<char>(3 * ts * N);
   c.Ustar = A.alloc<char>(ts * 21 * C);
   c.mvt = A.alloc<char>(ts * 16 * C);
   c.gp = A.alloc<double>(3 * size_t(P));
@@ -510,18 +510,18 @@ void extract(ba_ctx& c) {
 
 // Algorithmic bytes of the two PCG passes (unique data each must touch once).
 // Point pass: per observation its slot and (X_c, w) 4-vector, and for solve cameras its
-// camera-major position and the z 4-vector written there; per point the CSR offset and
-// Vinv; every matvec record once.
+// camera-major position and the packed z 3-vector written there; per point the CSR offset
+// and Vinv; every matvec record once.
 double bytes_schur_point(const ba_ctx& c) {
   const double ts = double(c.tsize());
-  return double(c.Nh) * (4 + 4 * ts) + double(c.Nc) * (4 + 4 * ts) +
+  return double(c.Nh) * (4 + 4 * ts) + double(c.Nc) * (4 + 3 * ts) +
          double(c.Pa) * (4 + 6 * ts) + double(c.Ca) * 16 * ts;
 }
-// Camera pass: per observation the (X_c, w) and z 4-vectors; per camera its offsets, table
-// entry, U*, u, r, and the w and dot terms written.
+// Camera pass: per observation the (X_c, w) 4-vector and the z 3-vector; per camera its
+// offsets, table entry, U*, u, r, and the w and dot terms written.
 double bytes_schur_cam(const ba_ctx& c) {
   const double ts = double(c.tsize());
-  return double(c.Nc) * 8 * ts + double(c.Ca) * (4 + 15 * ts + 21 * ts + 12 * 8 + 9 * 8);
+  return double(c.Nc) * 7 * ts + double(c.Ca) * (4 + 15 * ts + 21 * ts + 12 * 8 + 9 * 8);
 }
 int lanes_per_point(const ba_ctx& c) {
   const double mean = c.Pa > 0 ? double(c.Nh) / c.Pa : 1.0;
@@ -599,7 +599,7 @@ int run_pcg(ba_ctx& c, bool adj, double rel_tol, int max_iters, PcgState* out_st
   const int every = std::max(1, c.opt.pcg_check_every);
   const double bp = bytes_schur_point(c), bc = bytes_schur_cam(c);
   const int G = lanes_per_point(c);
-  V4<T>* zq = static_cast<V4<T>*>(c.zq);
+  P3<T>* zq = static_cast<P3<T>*>(c.zq);
   int it = 0;
   while (true) {
     for (int k = 0; k < every && it < max_iters; ++k, ++it) {

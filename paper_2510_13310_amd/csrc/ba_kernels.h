@@ -33,6 +33,12 @@ struct alignas(4 * sizeof(T)) V4 {
   T x, y, z, w;
 };
 
+// Packed 3-vector (no padding): the per-observation z of the PCG passes.
+template <typename T>
+struct P3 {
+  T x, y, z;
+};
+
 // Per-slot record read by the PCG point pass: rotation, focal length and the current camera
 // direction u of the Schur matvec, 16 values so that one aligned half (float) or full
 // (double) cache line serves an observation.
@@ -201,7 +207,7 @@ struct DevLimits {
 // When the Ca matvec records fit in LDS, a persistent grid stages them there.
 template <typename T>
 void launch_schur_point(hipStream_t s, bool adj, int G, const Model& m, const Compact<T>& cp,
-                        ObsMetric<T> om, const MvCam<T>* mvt, const T* Vinv, V4<T>* zq_cm,
+                        ObsMetric<T> om, const MvCam<T>* mvt, const T* Vinv, P3<T>* zq_cm,
                         const PcgState* st, const DevLimits& dl);
 // Camera-major pass, one workgroup per camera slot: w_s = U*_s u_s - sum_k W_k z_k with z
 // streamed in camera-major order, and the camera's terms of r.u, w.u and r.r (dots: 3
@@ -209,7 +215,7 @@ void launch_schur_point(hipStream_t s, bool adj, int G, const Model& m, const Co
 template <typename T>
 void launch_schur_cam(hipStream_t s, bool adj, const Model& m, const Compact<T>& cp,
                       ObsMetric<T> om, const T* Ustar, const double* u, const double* r,
-                      const V4<T>* zq, double* w, double* dots, const PcgState* st);
+                      const P3<T>* zq, double* w, double* dots, const PcgState* st);
 // Fused reduction of the per-camera dots, convergence test, then p = u + beta p,
 // s = w + beta s, x += alpha p, r -= alpha s, u = M^-1 r.
 template <typename T>

@@ -920,7 +920,7 @@ __device__ __forceinline__ void schur_point_one(const Model& m, const Compact<T>
                                                 const ObsMetric<T>& om,
                                                 const MvCam<T>* __restrict__ tab,
                                                 const T* __restrict__ Vinv,
-                                                V4<T>* __restrict__ zq_cm, int r, int rend,
+                                                P3<T>* __restrict__ zq_cm, int r, int rend,
                                                 int l) {
   T y[3] = {T(0), T(0), T(0)};
   T vi[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
@@ -973,11 +973,10 @@ __device__ __forceinline__ void schur_point_one(const Model& m, const Compact<T>
 #pragma unroll
       for (int q = 0; q < 6; ++q) vi[q] = Vinv[6 * r + q];
     }
-    V4<T> z;
+    P3<T> z;
     z.x = vi[0] * y[0] + vi[1] * y[1] + vi[2] * y[2];
     z.y = vi[1] * y[0] + vi[3] * y[1] + vi[4] * y[2];
     z.z = vi[2] * y[0] + vi[4] * y[1] + vi[5] * y[2];
-    z.w = T(0);
     if (pos0 >= 0) zq_cm[pos0] = z;
     for (int j = b + l + G; j < e; j += G) {
       const int pos = cp.pm_cm[j];
@@ -993,7 +992,7 @@ __device__ __forceinline__ void schur_point_one(const Model& m, const Compact<T>
 template <typename T, bool ADJ, int G>
 __global__ void __launch_bounds__(kBlock)
 k_schur_point(Model m, Compact<T> cp, ObsMetric<T> om, const MvCam<T>* __restrict__ mvt,
-              const T* __restrict__ Vinv, V4<T>* __restrict__ zq_cm,
+              const T* __restrict__ Vinv, P3<T>* __restrict__ zq_cm,
               const PcgState* __restrict__ st) {
   if (st->done) return;
   const int per = gridDim.x / 8;
@@ -1012,7 +1011,7 @@ constexpr int kPtLdsBlock = 1024;
 template <typename T, bool ADJ, int G>
 __global__ void __launch_bounds__(kPtLdsBlock)
 k_schur_point_lds(Model m, Compact<T> cp, ObsMetric<T> om, const MvCam<T>* __restrict__ mvt,
-                  const T* __restrict__ Vinv, V4<T>* __restrict__ zq_cm,
+                  const T* __restrict__ Vinv, P3<T>* __restrict__ zq_cm,
                   const PcgState* __restrict__ st, int ppx) {
   extern __shared__ uint4 lds_tab[];   // cp.Ca records
   if (st->done) return;
@@ -1041,7 +1040,7 @@ template <typename T, bool ADJ>
 __global__ void __launch_bounds__(kCamBlock)
 k_schur_cam(Model m, Compact<T> cp, ObsMetric<T> om, const T* __restrict__ Ustar,
             const double* __restrict__ u, const double* __restrict__ r,
-            const V4<T>* __restrict__ zq, double* __restrict__ w, double* __restrict__ dots,
+            const P3<T>* __restrict__ zq, double* __restrict__ w, double* __restrict__ dots,
             const PcgState* __restrict__ st) {
   if (st->done) return;
   // The grid is a multiple of 8: consecutive workgroups are dealt to the 8 XCDs in turn, and
@@ -1065,7 +1064,7 @@ k_schur_cam(Model m, Compact<T> cp, ObsMetric<T> om, const T* __restrict__ Ustar
 #pragma unroll 2
   for (int i = cp.cm_off[s] + threadIdx.x; i < end; i += blockDim.x) {
     const V4<T> xw = om.xcw[i];
-    const V4<T> zv = zq[i];
+    const P3<T> zv = zq[i];
     const T Xc[3] = {xw.x, xw.y, xw.z};
     AMat<T, ADJ> A;
     A.set(cm.f, T(m.lam_d), Xc);
@@ -1680,7 +1679,7 @@ void launch_pcg_init(hipStream_t s, int Ca, const double* b, const double* Minv,
 
 template <typename T, bool ADJ, int G>
 void schur_point_launch(hipStream_t s, const Model& m, const Compact<T>& cp, ObsMetric<T> om,
-                        const MvCam<T>* mvt, const T* Vinv, V4<T>* zq, const PcgState* st,
+                        const MvCam<T>* mvt, const T* Vinv, P3<T>* zq, const PcgState* st,
                         const DevLimits& dl) {
   const size_t tab = size_t(cp.Ca) * sizeof(MvCam<T>);
   bool use_lds = dl.n_cu > 0 && cp.Ca > 0 && tab <= size_t(dl.lds_per_block);
@@ -1703,7 +1702,7 @@ void schur_point_launch(hipStream_t s, const Model& m, const Compact<T>& cp, Obs
 
 template <typename T, bool ADJ>
 void schur_point_g(hipStream_t s, int G, const Model& m, const Compact<T>& cp, ObsMetric<T> om,
-                   const MvCam<T>* mvt, const T* Vinv, V4<T>* zq, const PcgState* st,
+                   const MvCam<T>* mvt, const T* Vinv, P3<T>* zq, const PcgState* st,
                    const DevLimits& dl) {
   switch (G) {
     case 2: schur_point_launch<T, ADJ, 2>(s, m, cp, om, mvt, Vinv, zq, st, dl); break;
@@ -1715,7 +1714,7 @@ void schur_point_g(hipStream_t s, int G, const Model& m, const Compact<T>& cp, O
 
 template <typename T>
 void launch_schur_point(hipStream_t s, bool adj, int G, const Model& m, const Compact<T>& cp,
-                        ObsMetric<T> om, const MvCam<T>* mvt, const T* Vinv, V4<T>* zq,
+                        ObsMetric<T> om, const MvCam<T>* mvt, const T* Vinv, P3<T>* zq,
                         const PcgState* st, const DevLimits& dl) {
   if (adj)
     schur_point_g<T, true>(s, G, m, cp, om, mvt, Vinv, zq, st, dl);
@@ -1726,7 +1725,7 @@ void launch_schur_point(hipStream_t s, bool adj, int G, const Model& m, const Co
 template <typename T>
 void launch_schur_cam(hipStream_t s, bool adj, const Model& m, const Compact<T>& cp,
                       ObsMetric<T> om, const T* Ustar, const double* u, const double* r,
-                      const V4<T>* zq, double* w, double* dots, const PcgState* st) {
+                      const P3<T>* zq, double* w, double* dots, const PcgState* st) {
   if (cp.Ca <= 0) return;
   const unsigned grid = unsigned((cp.Ca + 7) / 8 * 8);   // one share per XCD
   if (adj)
@@ -1843,11 +1842,11 @@ void launch_adjoint_obs(hipStream_t s, const Model& m, const Compact<T>& cp, Obs
                                    double*, double*, double*, double*, MvCam<T>*, PcgState*,  \
                                    double, int);                                               \
   template void launch_schur_point<T>(hipStream_t, bool, int, const Model&, const Compact<T>&,\
-                                      ObsMetric<T>, const MvCam<T>*, const T*, V4<T>*,        \
+                                      ObsMetric<T>, const MvCam<T>*, const T*, P3<T>*,        \
                                       const PcgState*, const DevLimits&);                      \
   template void launch_schur_cam<T>(hipStream_t, bool, const Model&, const Compact<T>&,       \
                                     ObsMetric<T>, const T*, const double*, const double*,     \
-                                    const V4<T>*, double*, double*, const PcgState*);         \
+                                    const P3<T>*, double*, double*, const PcgState*);         \
   template void launch_pcg_update<T>(hipStream_t, int, int, const double*, const double*, double*, \
                                      double*, double*, double*, double*, const double*,       \
                                      MvCam<T>*, PcgState*);                                    \
