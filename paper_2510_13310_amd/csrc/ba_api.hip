@@ -111,18 +111,20 @@ struct ba_ctx {
   bool have_obs = false, have_priors = false;
   double lam_d = 0.0;
   int *pm_cam = nullptr, *pm_pt = nullptr, *pm_orig = nullptr, *pt_off = nullptr;
-  int *cm_off = nullptr, *cm_perm = nullptr, *pt_user_d = nullptr;
+  int *cm_off = nullptr, *pt_user_d = nullptr;
+  int *inv_cm = nullptr;   // point-major position -> position in the camera-major order
+  int *cm_cam = nullptr;   // camera of each camera-major position
   float2* pm_xy = nullptr;
   float* pm_depth = nullptr;
   std::vector<int32_t> pm_orig_h;  // point-major position -> caller observation index
 
   // extraction
-  uint8_t *vrow = nullptr, *act_c = nullptr, *act_p = nullptr;
+  uint8_t *vrow = nullptr, *vrow_cm = nullptr, *act_c = nullptr, *act_p = nullptr;
   int *rank_c = nullptr, *rank_p = nullptr, *pos_pm = nullptr, *pos_cm = nullptr;
   int *scan_tmp = nullptr, *flags = nullptr;   // flags[0] changed, flags[1] bad damping
   int *cam_hat = nullptr, *orig_hat = nullptr, *off_hat = nullptr, *pt_src = nullptr;
   int *cam_src = nullptr, *slot_all = nullptr, *cm_off_hat = nullptr, *cm_pt = nullptr,
-      *cm_pm = nullptr, *pm_cm = nullptr;
+      *pm_cm = nullptr;
   Cam<double>* camd_hat = nullptr;
   Cam<float>* camf_hat = nullptr;
   float2* xy_hat = nullptr;
@@ -327,9 +329,11 @@ void alloc_obs_buffers(ba_ctx& c) {
   c.pm_depth = A.alloc<float>(N);
   c.pt_off = A.alloc<int>(P + 1);
   c.cm_off = A.alloc<int>(C + 1);
-  c.cm_perm = A.alloc<int>(N);
+  c.inv_cm = A.alloc<int>(N);
+  c.cm_cam = A.alloc<int>(N);
   c.pt_user_d = A.alloc<int>(P);
   c.vrow = A.alloc<uint8_t>(N);
+  c.vrow_cm = A.alloc<uint8_t>(N);
   c.act_c = A.alloc<uint8_t>(C);
   c.act_p = A.alloc<uint8_t>(P);
   c.rank_c = A.alloc<int>(C + 1);
@@ -350,7 +354,6 @@ void alloc_obs_buffers(ba_ctx& c) {
   c.camf_hat = A.alloc<Cam<float>>(C);
   c.cm_off_hat = A.alloc<int>(C + 1);
   c.cm_pt = A.alloc<int>(N);
-  c.cm_pm = A.alloc<int>(N);
   c.pm_cm = A.alloc<int>(N);
   c.Xd = A.alloc<double>(3 * size_t(P));
   c.Xf = A.alloc<float>(3 * size_t(P));
@@ -416,7 +419,6 @@ Compact<T> compact_view(ba_ctx& c) {
   cp.cam_src = c.cam_src;
   cp.cm_off = c.cm_off_hat;
   cp.cm_pt = c.cm_pt;
-  cp.cm_pm = c.cm_pm;
   cp.pm_cm = c.pm_cm;
   cp.Xd = c.Xd;
   cp.camd = c.camd_hat;
@@ -450,20 +452,20 @@ void extract(ba_ctx& c) {
   const int64_t N = c.N;
   c.timed("cam_table", double(c.C) * (56 + 24 + 120 + 60), -1,
           [&] { launch_cam_table(s, c.C, c.d_cams, c.d_intr, c.d_camd, c.d_camf); });
-  c.timed("validate", double(N) * (4 + 4 + 8 + 4 + 24 + 1), -1, [&] {
+  c.timed("validate", double(N) * (4 + 4 + 8 + 4 + 24 + 1 + 4 + 1), -1, [&] {
     launch_validate(s, N, m, c.pm_cam, c.pm_pt, c.pm_xy, c.pm_depth, c.d_pts, c.d_camd,
-                    c.vrow);
+                    c.inv_cm, c.vrow, c.vrow_cm);
   });
   int rounds = 0;
   while (true) {
     ++rounds;
     HIP_CHECK(hipMemsetAsync(c.flags, 0, sizeof(int), s));
-    c.timed("cam_rows", double(N) * 5, -1, [&] {
-      launch_cam_rows(s, c.C, c.cm_off, c.cm_perm, c.vrow, c.d_fixed, c.need_cam(), c.act_c);
+    c.timed("cam_rows", double(N) * 1, -1, [&] {
+      launch_cam_rows(s, c.C, c.cm_off, c.vrow_cm, c.d_fixed, c.need_cam(), c.act_c);
     });
     c.timed("point_rows_prune", double(N) * 5 + double(c.P) * 5, -1, [&] {
       launch_point_rows_prune(s, c.P, c.pt_off, c.pm_cam, c.act_c, c.d_fixed, c.need_pt(),
-                              c.vrow, c.act_p, c.flags);
+                              c.inv_cm, c.vrow, c.vrow_cm, c.act_p, c.flags);
     });
     HIP_CHECK(hipMemcpyAsync(c.h_pin, c.flags, sizeof(int), hipMemcpyDeviceToHost, s));
     c.sync();
@@ -477,7 +479,7 @@ void extract(ba_ctx& c) {
     launch_scan_u8(s, c.C, c.act_c, c.rank_c, c.scan_tmp);
     launch_scan_u8(s, c.P, c.act_p, c.rank_p, c.scan_tmp);
     launch_scan_u8(s, N, c.vrow, c.pos_pm, c.scan_tmp);
-    launch_scan_cm(s, N, c.cm_perm, c.vrow, c.pm_cam, c.d_fixed, c.pos_cm, c.scan_tmp);
+    launch_scan_cm(s, N, c.vrow_cm, c.cm_cam, c.d_fixed, c.pos_cm, c.scan_tmp);
   });
   int* hp = reinterpret_cast<int*>(c.h_pin);
   HIP_CHECK(hipMemcpyAsync(hp + 0, c.rank_c + c.C, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -489,7 +491,7 @@ void extract(ba_ctx& c) {
   c.Pa = hp[1];
   c.Nh = hp[2];
   c.Nc = hp[3];
-  c.timed_multi("compact", double(N) * 40 + double(c.P) * 60, [&] {
+  c.timed_multi("compact", double(N) * 72 + double(c.P) * 60, [&] {
     launch_compact_cams(s, c.C, c.act_c, c.rank_c, c.d_fixed, c.d_fixed_rank, c.cm_off,
                         c.pos_cm, c.slot_all, c.cam_src, c.cm_off_hat);
     launch_compact_cam_table(s, c.Ca + c.n_fixed, c.cam_src, c.d_camd, c.d_camf, c.camd_hat,
@@ -497,9 +499,8 @@ void extract(ba_ctx& c) {
     launch_compact_points(s, c.P, c.act_p, c.rank_p, c.pt_off, c.pos_pm, c.d_pts, c.pt_src,
                           c.off_hat, c.Xd, c.Xf);
     launch_compact_obs(s, N, c.vrow, c.pos_pm, c.pm_cam, c.slot_all, c.pm_xy, c.pm_depth,
-                       c.pm_orig, c.Ca, c.cam_hat, c.xy_hat, c.depth_hat, c.orig_hat, c.pm_cm);
-    launch_compact_cm(s, N, c.cm_perm, c.vrow, c.pm_cam, c.pm_pt, c.d_fixed, c.pos_cm,
-                      c.pos_pm, c.rank_p, c.cm_pt, c.cm_pm, c.pm_cm);
+                       c.pm_orig, c.Ca, c.inv_cm, c.pos_cm, c.pm_pt, c.rank_p, c.cam_hat,
+                       c.xy_hat, c.depth_hat, c.orig_hat, c.pm_cm, c.cm_pt);
     if (c.tsize() == 8)
       launch_mv_table<double>(s, c.Ca + c.n_fixed, c.camd_hat, static_cast<MvCam<double>*>(c.mvt));
     else
@@ -1026,6 +1027,11 @@ ba_status ba_set_observations(ba_ctx* c, int64_t n_obs, const int32_t* cam_idx,
     // camera-major order over the point-major positions (stable: increasing point)
     std::vector<int32_t> cm_perm, cm_off;
     counting_order(pm_cam, C, cm_perm, cm_off);
+    std::vector<int32_t> inv_cm(static_cast<size_t>(n_obs)), cm_cam(static_cast<size_t>(n_obs));
+    for (int64_t mm = 0; mm < n_obs; ++mm) {
+      inv_cm[size_t(cm_perm[size_t(mm)])] = int32_t(mm);
+      cm_cam[size_t(mm)] = pm_cam[size_t(cm_perm[size_t(mm)])];
+    }
 
     c->N = n_obs;
     c->have_obs = false;
@@ -1038,7 +1044,8 @@ ba_status ba_set_observations(ba_ctx* c, int64_t n_obs, const int32_t* cam_idx,
     store(*c, c->pm_depth, zeros.data(), zeros.size());
     store(*c, c->pt_off, pt_off.data(), pt_off.size());
     store(*c, c->cm_off, cm_off.data(), cm_off.size());
-    store(*c, c->cm_perm, cm_perm.data(), cm_perm.size());
+    store(*c, c->inv_cm, inv_cm.data(), inv_cm.size());
+    store(*c, c->cm_cam, cm_cam.data(), cm_cam.size());
     store(*c, c->pt_user_d, c->pt_user.data(), c->pt_user.size());
     points_user_to_internal(*c, pts_user, pts_int);
     store(*c, c->d_pts, pts_int.data(), pts_int.size());

@@ -95,7 +95,6 @@ struct Compact {
   const int* cam_src;     // Ca + Cf: original camera index of each slot
   const int* cm_off;      // Ca + 1: camera-major segments
   const int* cm_pt;       // Nc: point rank of each camera-major observation
-  const int* cm_pm;       // Nc: position of that observation in the point-major stream
   const int* pm_cm;       // Nh: camera-major position of each observation (solve slots only)
   const double* Xd;       // Pa x 3 compact points (float64)
   const T* Xt;            // Pa x 3 compact points (T)
@@ -128,19 +127,23 @@ struct alignas(16) PtRec {
 // ------------------------------------------------------------------ extraction
 void launch_cam_table(hipStream_t s, int C, const double* cams, const double* intr,
                       Cam<double>* camd, Cam<float>* camf);
+// Validity rows per observation, point-major (vrow) and camera-major (vrow_cm, through
+// inv_cm: point-major position -> position in the full camera-major order).
 void launch_validate(hipStream_t s, int64_t N, const Model& m, const int* pm_cam,
                      const int* pm_pt, const float2* xy, const float* depth,
-                     const double* pts, const Cam<double>* camd, uint8_t* vrow);
-void launch_cam_rows(hipStream_t s, int C, const int* cm_off, const int* cm_perm,
-                     const uint8_t* vrow, const uint8_t* fixed, int need, uint8_t* act_c);
+                     const double* pts, const Cam<double>* camd, const int* inv_cm,
+                     uint8_t* vrow, uint8_t* vrow_cm);
+void launch_cam_rows(hipStream_t s, int C, const int* cm_off, const uint8_t* vrow_cm,
+                     const uint8_t* fixed, int need, uint8_t* act_c);
 void launch_point_rows_prune(hipStream_t s, int P, const int* pt_off, const int* pm_cam,
                              const uint8_t* act_c, const uint8_t* fixed, int need,
-                             uint8_t* vrow, uint8_t* act_p, int* changed);
+                             const int* inv_cm, uint8_t* vrow, uint8_t* vrow_cm,
+                             uint8_t* act_p, int* changed);
 // Exclusive scans; out has n + 1 entries (out[n] = total). tmp needs scan_tmp_ints(n) ints.
 int64_t scan_tmp_ints(int64_t n);
 void launch_scan_u8(hipStream_t s, int64_t n, const uint8_t* flags, int* out, int* tmp);
-void launch_scan_cm(hipStream_t s, int64_t n, const int* cm_perm, const uint8_t* vrow,
-                    const int* pm_cam, const uint8_t* fixed, int* out, int* tmp);
+void launch_scan_cm(hipStream_t s, int64_t n, const uint8_t* vrow_cm, const int* cm_cam,
+                    const uint8_t* fixed, int* out, int* tmp);
 void launch_compact_points(hipStream_t s, int P, const uint8_t* act_p, const int* rank_p,
                            const int* pt_off, const int* pos_pm, const double* pts,
                            int* pt_src, int* off_hat, double* Xd, float* Xf);
@@ -151,15 +154,14 @@ void launch_compact_cams(hipStream_t s, int C, const uint8_t* act_c, const int* 
 void launch_compact_cam_table(hipStream_t s, int n, const int* cam_src,
                               const Cam<double>* camd, const Cam<float>* camf,
                               Cam<double>* camd_hat, Cam<float>* camf_hat);
-// (also marks pm_cm = -1 for the observations of fixed cameras, slots >= Ca)
+// Compact point-major observations, and for those of solve cameras (slots < Ca) their
+// camera-major position pm_cm and the point rank there (cm_pt); pm_cm = -1 otherwise.
 void launch_compact_obs(hipStream_t s, int64_t N, const uint8_t* vrow, const int* pos_pm,
                         const int* pm_cam, const int* slot_all, const float2* pm_xy,
-                        const float* pm_depth, const int* pm_orig, int Ca, int* cam_hat,
-                        float2* xy_hat, float* depth_hat, int* orig_hat, int* pm_cm);
-void launch_compact_cm(hipStream_t s, int64_t N, const int* cm_perm, const uint8_t* vrow,
-                       const int* pm_cam, const int* pm_pt, const uint8_t* fixed,
-                       const int* pos_cm, const int* pos_pm, const int* rank_p, int* cm_pt,
-                       int* cm_pm, int* pm_cm);
+                        const float* pm_depth, const int* pm_orig, int Ca, const int* inv_cm,
+                        const int* pos_cm, const int* pm_pt, const int* rank_p, int* cam_hat,
+                        float2* xy_hat, float* depth_hat, int* orig_hat, int* pm_cm,
+                        int* cm_pt);
 // Matvec records of every slot (R, f from the compact table; u = 0).
 template <typename T>
 void launch_mv_table(hipStream_t s, int n, const Cam<double>* camd_hat, MvCam<T>* mvt);

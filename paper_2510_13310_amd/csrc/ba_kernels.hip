@@ -262,7 +262,8 @@ __global__ void __launch_bounds__(kBlock)
 k_validate(int64_t N, Model m, const int* __restrict__ pm_cam, const int* __restrict__ pm_pt,
            const float2* __restrict__ xy, const float* __restrict__ depth,
            const double* __restrict__ pts, const Cam<double>* __restrict__ camd,
-           uint8_t* __restrict__ vrow) {
+           const int* __restrict__ inv_cm, uint8_t* __restrict__ vrow,
+           uint8_t* __restrict__ vrow_cm) {
   const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (k >= N) return;
   const Cam<double> cm = camd[pm_cam[k]];
@@ -281,18 +282,19 @@ k_validate(int64_t N, Model m, const int* __restrict__ pm_cam, const int* __rest
     }
   }
   const int rows = 2 + ((m.lam_d > 0.0 && depth[k] > 0.0f) ? 1 : 0);
-  vrow[k] = ok ? uint8_t(rows) : uint8_t(0);
+  const uint8_t v = ok ? uint8_t(rows) : uint8_t(0);
+  vrow[k] = v;
+  vrow_cm[inv_cm[k]] = v;
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_cam_rows(const int* __restrict__ cm_off, const int* __restrict__ cm_perm,
-           const uint8_t* __restrict__ vrow, const uint8_t* __restrict__ fixed, int need,
-           uint8_t* __restrict__ act_c) {
+k_cam_rows(const int* __restrict__ cm_off, const uint8_t* __restrict__ vrow_cm,
+           const uint8_t* __restrict__ fixed, int need, uint8_t* __restrict__ act_c) {
   __shared__ int smem[kBlock / kWave];
   const int c = blockIdx.x;
   int sum[1] = {0};
   for (int i = cm_off[c] + threadIdx.x; i < cm_off[c + 1]; i += blockDim.x)
-    sum[0] += vrow[cm_perm[i]];
+    sum[0] += vrow_cm[i];
   block_sum<int, 1>(sum, smem);
   if (threadIdx.x == 0) act_c[c] = (sum[0] >= need && !fixed[c]) ? 1 : 0;
 }
@@ -302,7 +304,8 @@ k_cam_rows(const int* __restrict__ cm_off, const int* __restrict__ cm_perm,
 __global__ void __launch_bounds__(kBlock)
 k_point_rows_prune(int P, const int* __restrict__ pt_off, const int* __restrict__ pm_cam,
                    const uint8_t* __restrict__ act_c, const uint8_t* __restrict__ fixed,
-                   int need, uint8_t* __restrict__ vrow, uint8_t* __restrict__ act_p,
+                   int need, const int* __restrict__ inv_cm, uint8_t* __restrict__ vrow,
+                   uint8_t* __restrict__ vrow_cm, uint8_t* __restrict__ act_p,
                    int* __restrict__ changed) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= P) return;
@@ -317,6 +320,7 @@ k_point_rows_prune(int P, const int* __restrict__ pt_off, const int* __restrict_
     const int c = pm_cam[k];
     if (!a || !(act_c[c] || fixed[c])) {
       vrow[k] = 0;
+      vrow_cm[inv_cm[k]] = 0;
       drop = true;
     }
   }
@@ -328,14 +332,13 @@ struct FlagU8 {
   const uint8_t* a;
   __device__ __forceinline__ int operator()(int64_t i) const { return a[i] != 0; }
 };
+// Camera-major observation m stays in the solve: valid and its camera not fixed.
 struct FlagCM {
-  const int* perm;
-  const uint8_t* vrow;
-  const int* cam;
+  const uint8_t* vrow_cm;
+  const int* cm_cam;
   const uint8_t* fixed;
   __device__ __forceinline__ int operator()(int64_t m) const {
-    const int k = perm[m];
-    return vrow[k] != 0 && !fixed[cam[k]];
+    return vrow_cm[m] != 0 && !fixed[cm_cam[m]];
   }
 };
 
@@ -483,35 +486,28 @@ __global__ void __launch_bounds__(kBlock)
 k_compact_obs(int64_t N, const uint8_t* __restrict__ vrow, const int* __restrict__ pos_pm,
               const int* __restrict__ pm_cam, const int* __restrict__ slot_all,
               const float2* __restrict__ pm_xy, const float* __restrict__ pm_depth,
-              const int* __restrict__ pm_orig, int Ca, int* __restrict__ cam_hat,
+              const int* __restrict__ pm_orig, int Ca, const int* __restrict__ inv_cm,
+              const int* __restrict__ pos_cm, const int* __restrict__ pm_pt,
+              const int* __restrict__ rank_p, int* __restrict__ cam_hat,
               float2* __restrict__ xy_hat, float* __restrict__ depth_hat,
-              int* __restrict__ orig_hat, int* __restrict__ pm_cm) {
+              int* __restrict__ orig_hat, int* __restrict__ pm_cm, int* __restrict__ cm_pt) {
   const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (k >= N || !vrow[k]) return;
   const int j = pos_pm[k];
   const int slot = slot_all[pm_cam[k]];
   cam_hat[j] = slot;
-  if (slot >= Ca) pm_cm[j] = -1;   // fixed camera: no camera-major entry
+  if (slot < Ca) {   // solve camera: its camera-major entry and the cross references
+    const int i = pos_cm[inv_cm[k]];
+    pm_cm[j] = i;
+    cm_pt[i] = rank_p[pm_pt[k]];
+  } else {
+    pm_cm[j] = -1;   // fixed camera: no camera-major entry
+  }
   xy_hat[j] = pm_xy[k];
   depth_hat[j] = pm_depth[k];
   orig_hat[j] = pm_orig[k];
 }
 
-__global__ void __launch_bounds__(kBlock)
-k_compact_cm(int64_t N, const int* __restrict__ cm_perm, const uint8_t* __restrict__ vrow,
-             const int* __restrict__ pm_cam, const int* __restrict__ pm_pt,
-             const uint8_t* __restrict__ fixed, const int* __restrict__ pos_cm,
-             const int* __restrict__ pos_pm, const int* __restrict__ rank_p,
-             int* __restrict__ cm_pt, int* __restrict__ cm_pm, int* __restrict__ pm_cm) {
-  const int64_t m = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (m >= N) return;
-  const int k = cm_perm[m];
-  if (!vrow[k] || fixed[pm_cam[k]]) return;
-  const int i = pos_cm[m];
-  cm_pt[i] = rank_p[pm_pt[k]];
-  cm_pm[i] = pos_pm[k];
-  pm_cm[pos_pm[k]] = i;
-}
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
@@ -1550,23 +1546,24 @@ void launch_cam_table(hipStream_t s, int C, const double* cams, const double* in
 
 void launch_validate(hipStream_t s, int64_t N, const Model& m, const int* pm_cam,
                      const int* pm_pt, const float2* xy, const float* depth,
-                     const double* pts, const Cam<double>* camd, uint8_t* vrow) {
+                     const double* pts, const Cam<double>* camd, const int* inv_cm,
+                     uint8_t* vrow, uint8_t* vrow_cm) {
   if (N == 0) return;
-  launch_k(k_validate, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, m, pm_cam, pm_pt,
-                     xy, depth, pts, camd, vrow);
+  launch_k(k_validate, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, m, pm_cam, pm_pt, xy, depth,
+           pts, camd, inv_cm, vrow, vrow_cm);
 }
 
-void launch_cam_rows(hipStream_t s, int C, const int* cm_off, const int* cm_perm,
-                     const uint8_t* vrow, const uint8_t* fixed, int need, uint8_t* act_c) {
-  launch_k(k_cam_rows, dim3(C), dim3(kBlock), 0, s, cm_off, cm_perm, vrow, fixed,
-                     need, act_c);
+void launch_cam_rows(hipStream_t s, int C, const int* cm_off, const uint8_t* vrow_cm,
+                     const uint8_t* fixed, int need, uint8_t* act_c) {
+  launch_k(k_cam_rows, dim3(C), dim3(kBlock), 0, s, cm_off, vrow_cm, fixed, need, act_c);
 }
 
 void launch_point_rows_prune(hipStream_t s, int P, const int* pt_off, const int* pm_cam,
                              const uint8_t* act_c, const uint8_t* fixed, int need,
-                             uint8_t* vrow, uint8_t* act_p, int* changed) {
-  launch_k(k_point_rows_prune, dim3(blocks_for(P)), dim3(kBlock), 0, s, P, pt_off,
-                     pm_cam, act_c, fixed, need, vrow, act_p, changed);
+                             const int* inv_cm, uint8_t* vrow, uint8_t* vrow_cm,
+                             uint8_t* act_p, int* changed) {
+  launch_k(k_point_rows_prune, dim3(blocks_for(P)), dim3(kBlock), 0, s, P, pt_off, pm_cam,
+           act_c, fixed, need, inv_cm, vrow, vrow_cm, act_p, changed);
 }
 
 int64_t scan_tmp_ints(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
@@ -1575,9 +1572,9 @@ void launch_scan_u8(hipStream_t s, int64_t n, const uint8_t* flags, int* out, in
   scan_impl(s, n, FlagU8{flags}, out, tmp);
 }
 
-void launch_scan_cm(hipStream_t s, int64_t n, const int* cm_perm, const uint8_t* vrow,
-                    const int* pm_cam, const uint8_t* fixed, int* out, int* tmp) {
-  scan_impl(s, n, FlagCM{cm_perm, vrow, pm_cam, fixed}, out, tmp);
+void launch_scan_cm(hipStream_t s, int64_t n, const uint8_t* vrow_cm, const int* cm_cam,
+                    const uint8_t* fixed, int* out, int* tmp) {
+  scan_impl(s, n, FlagCM{vrow_cm, cm_cam, fixed}, out, tmp);
 }
 
 void launch_compact_points(hipStream_t s, int P, const uint8_t* act_p, const int* rank_p,
@@ -1604,21 +1601,16 @@ void launch_compact_cam_table(hipStream_t s, int n, const int* cam_src,
 
 void launch_compact_obs(hipStream_t s, int64_t N, const uint8_t* vrow, const int* pos_pm,
                         const int* pm_cam, const int* slot_all, const float2* pm_xy,
-                        const float* pm_depth, const int* pm_orig, int Ca, int* cam_hat,
-                        float2* xy_hat, float* depth_hat, int* orig_hat, int* pm_cm) {
+                        const float* pm_depth, const int* pm_orig, int Ca, const int* inv_cm,
+                        const int* pos_cm, const int* pm_pt, const int* rank_p, int* cam_hat,
+                        float2* xy_hat, float* depth_hat, int* orig_hat, int* pm_cm,
+                        int* cm_pt) {
   if (N == 0) return;
   launch_k(k_compact_obs, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, vrow, pos_pm, pm_cam,
-           slot_all, pm_xy, pm_depth, pm_orig, Ca, cam_hat, xy_hat, depth_hat, orig_hat, pm_cm);
+           slot_all, pm_xy, pm_depth, pm_orig, Ca, inv_cm, pos_cm, pm_pt, rank_p, cam_hat,
+           xy_hat, depth_hat, orig_hat, pm_cm, cm_pt);
 }
 
-void launch_compact_cm(hipStream_t s, int64_t N, const int* cm_perm, const uint8_t* vrow,
-                       const int* pm_cam, const int* pm_pt, const uint8_t* fixed,
-                       const int* pos_cm, const int* pos_pm, const int* rank_p, int* cm_pt,
-                       int* cm_pm, int* pm_cm) {
-  if (N == 0) return;
-  launch_k(k_compact_cm, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, cm_perm, vrow,
-                     pm_cam, pm_pt, fixed, pos_cm, pos_pm, rank_p, cm_pt, cm_pm, pm_cm);
-}
 
 template <typename T, bool ADJ>
 void lin_point_g(hipStream_t s, int G, const Model& m, const Compact<T>& cp, ObsMetric<T> om,
