@@ -121,6 +121,30 @@ def kernel_summary(res):
     )
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "schur_point_large_mixed_traffic.txt")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or None when the
+    summary is for another kernel or the library sources changed since it was taken."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if line.strip() and not line.startswith("#"):
+            k, _, v = line.strip().partition(" ")
+            kv[k] = v.strip()
+    if kv.get("kernel") != kernel:
+        return None
+    h = hashlib.sha256()
+    for f in kv.get("sources", "").split():
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest() != kv.get("sources_sha256"):
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def roofline(res):
     """Dominant kernel by total time: algorithmic bytes per launch / mean launch time."""
     stats = [s for s in res["stats"] if s["launches"] > 0]
@@ -128,10 +152,14 @@ def roofline(res):
     avg_ms = dom["total_ms"] / dom["launches"]
     bytes_per_launch = dom["total_bytes"] / dom["launches"]
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    return dict(kernel=dom["name"], bound="hbm", achieved=round(achieved, 1),
-                peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
-                traffic=None, avg_launch_us=round(avg_ms * 1e3, 2),
-                bytes_per_launch=int(bytes_per_launch), launches=dom["launches"])
+    traffic = measured_traffic(dom["name"])
+    out = dict(kernel=dom["name"], bound="hbm", achieved=round(achieved, 1),
+               peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
+               traffic=traffic, avg_launch_us=round(avg_ms * 1e3, 2),
+               bytes_per_launch=int(bytes_per_launch), launches=dom["launches"])
+    if traffic is not None:
+        out["traffic_gbs"] = round(traffic / (avg_ms * 1e-3) / 1e9, 1)
+    return out
 
 
 def cpu_baseline(sc, frac, steps, n_obs_full):
