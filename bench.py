@@ -50,6 +50,12 @@ def parse():
                     help="PCG iterations enqueued between convergence read-backs")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a 1 GiB device copy first (counter calibration)")
+    ap.add_argument("--forward-adjoint", type=int, default=0, metavar="ITERS",
+                    help="also time a solve of at most ITERS LM iterations (camera 0 fixed) "
+                         "and the implicit adjoint of sum |c - c_gt|^2 (mixed precision)")
+    ap.add_argument("--adjoint-lambda-d", type=float, default=300.0,
+                    help="depth-row weight of the --forward-adjoint problem (the undamped "
+                         "adjoint system needs well-weighted priors)")
     ap.add_argument("--verbose", action="store_true")
     return ap.parse_args()
 
@@ -82,6 +88,57 @@ def run_gpu(sc, precision, steps, warmup, args, torch, timing):
     mem = ba.device_bytes()
     ba.close()
     return dict(seconds=dt, reports=reps, stats=stats, device_bytes=mem)
+
+
+def forward_adjoint(sc, iters, args, torch):
+    """Wall time of a mixed-precision solve (camera 0 fixed, bench PCG settings) and of the
+    implicit adjoint of L = sum_i |c_i - c_i^gt|^2 with respect to all observations."""
+    from paper_2510_13310_amd import BundleAdjuster, BAError
+    dev = torch.device("cuda:0")
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    torch.cuda.reset_peak_memory_stats()
+    ba = BundleAdjuster(t(sc.cams0, torch.float64), t(sc.intr, torch.float64),
+                        t(sc.points0, torch.float64), precision="mixed",
+                        huber_px=sc.huber_px, filter_px=sc.filter_px, img_w=sc.img_w,
+                        img_h=sc.img_h, pcg_rel_tol=args.pcg_tol, pcg_max_iters=args.pcg_max,
+                        max_lm_iters=iters, timing=1)
+    ba.set_observations(t(sc.cam_idx, torch.int32), t(sc.pt_idx, torch.int32),
+                        t(sc.xy, torch.float32))
+    ba.set_depth_priors(t(sc.depth, torch.float32), t(sc.depth_valid, torch.uint8),
+                        args.adjoint_lambda_d)
+    ba.set_fixed_cameras(np.array([0], np.int32))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    srep = ba.solve()
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t0
+    cams, pts = ba.get_params()
+    g_c = np.zeros_like(cams)
+    g_c[:, 4:7] = 2.0 * (cams[:, 4:7] - sc.cams_gt[:, 4:7])
+    gxy = torch.empty((sc.n_obs, 2), dtype=torch.float32, device=dev)
+    gd = torch.empty(sc.n_obs, dtype=torch.float32, device=dev)
+    ba.reset_kernel_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    status = "ok"
+    try:
+        ba.adjoint(t(g_c, torch.float64), t(np.zeros_like(pts), torch.float64), gxy, gd)
+    except BAError as e:
+        status = str(e)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    st = {k["name"]: k for k in ba.kernel_stats()}
+    out = dict(lambda_d=args.adjoint_lambda_d, fixed_cameras=[0],
+               lm_iterations=srep["iterations"], stop_reason=srep["stop_reason"],
+               initial_rms_px=round(srep["initial_rms_px"], 6),
+               final_rms_px=round(srep["final_rms_px"], 6), solve_s=round(t_solve, 4),
+               adjoint_s=round(t_adj, 4), adjoint_status=status,
+               adjoint_pcg_iters=int(st["schur_point"]["launches"]) if "schur_point" in st else 0,
+               forward_plus_adjoint_s=round(t_solve + t_adj, 4),
+               library_device_gb=round(ba.device_bytes() / 1e9, 3),
+               torch_peak_gb=round(torch.cuda.max_memory_allocated() / 1e9, 3))
+    ba.close()
+    return out
 
 
 def summarize(res, n_obs_total):
@@ -124,9 +181,9 @@ def kernel_summary(res):
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "schur_point_large_mixed_traffic.txt")
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, scene):
     """HBM bytes per launch of `kernel` from the committed counter summary, or None when the
-    summary is for another kernel or the library sources changed since it was taken."""
+    summary is for another kernel or workload, or the library sources changed since."""
     import hashlib
     if not os.path.exists(TRAFFIC_FILE):
         return None
@@ -135,7 +192,7 @@ def measured_traffic(kernel):
         if line.strip() and not line.startswith("#"):
             k, _, v = line.strip().partition(" ")
             kv[k] = v.strip()
-    if kv.get("kernel") != kernel:
+    if kv.get("kernel") != kernel or kv.get("workload") != scene:
         return None
     h = hashlib.sha256()
     for f in kv.get("sources", "").split():
@@ -145,14 +202,14 @@ def measured_traffic(kernel):
     return float(kv["traffic_bytes_per_launch"])
 
 
-def roofline(res):
+def roofline(res, scene):
     """Dominant kernel by total time: algorithmic bytes per launch / mean launch time."""
     stats = [s for s in res["stats"] if s["launches"] > 0]
     dom = max(stats, key=lambda s: s["total_ms"])
     avg_ms = dom["total_ms"] / dom["launches"]
     bytes_per_launch = dom["total_bytes"] / dom["launches"]
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    traffic = measured_traffic(dom["name"])
+    traffic = measured_traffic(dom["name"], scene)
     out = dict(kernel=dom["name"], bound="hbm", achieved=round(achieved, 1),
                peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
                traffic=traffic, avg_launch_us=round(avg_ms * 1e3, 2),
@@ -261,14 +318,16 @@ def main():
         "dtype": "f32+f64 mixed" if head == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": (f"{args.scene}: {sc.n_cams} cameras in random walks, "
-                                f"{sc.n_points} points, {sc.n_obs} observations, 5% outliers, "
-                                "depth priors on 50%, Huber 2 px, 4 px filter"),
+                                f"{sc.n_points} points, {sc.n_obs} observations, "
+                                f"{100 * sc.is_outlier.mean():.0f}% outliers, depth priors on "
+                                f"{100 * sc.depth_valid.mean():.0f}%, Huber "
+                                f"{sc.huber_px:g} px, {sc.filter_px:g} px filter"),
                    "pcg_rel_tol": args.pcg_tol, "pcg_max_iters": args.pcg_max,
                    "pcg_check_every": args.check_every},
         "obs_per_s": round(summ["obs_per_s"], 1),
         "jacobian_obs_per_s": (round(summ["jacobian_obs_per_s"], 1)
                                if summ["jacobian_obs_per_s"] else None),
-        "roofline": roofline(ins),
+        "roofline": roofline(ins, args.scene),
     }
     for p in precs:
         s = out[p][1]
@@ -279,6 +338,8 @@ def main():
         line["mixed_over_fp64"] = round(out["mixed"][1]["lm_iters_per_s"] /
                                         out["fp64"][1]["lm_iters_per_s"], 3)
         line["rms_diff_px"] = abs(out["mixed"][1]["rms_px_last"] - out["fp64"][1]["rms_px_last"])
+    if args.forward_adjoint > 0:
+        line["forward_adjoint"] = forward_adjoint(sc, args.forward_adjoint, args, torch)
     line["cpu_baseline"] = (None if args.no_cpu else
                             cpu_baseline(sc, args.cpu_frac, args.cpu_steps, sc.n_obs))
     print(json.dumps(line), flush=True)
