@@ -56,6 +56,10 @@ def parse():
     ap.add_argument("--adjoint-lambda-d", type=float, default=300.0,
                     help="depth-row weight of the --forward-adjoint problem (the undamped "
                          "adjoint system needs well-weighted priors)")
+    ap.add_argument("--adjoint-damping", type=float, default=1e-6,
+                    help="Tikhonov damping of the --forward-adjoint system (singular point "
+                         "blocks under the robust-corrected metric)")
+    ap.add_argument("--adjoint-precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--verbose", action="store_true")
     return ap.parse_args()
 
@@ -91,17 +95,17 @@ def run_gpu(sc, precision, steps, warmup, args, torch, timing):
 
 
 def forward_adjoint(sc, iters, args, torch):
-    """Wall time of a mixed-precision solve (camera 0 fixed, bench PCG settings) and of the
-    implicit adjoint of L = sum_i |c_i - c_i^gt|^2 with respect to all observations."""
+    """Wall time of a solve (camera 0 fixed, bench PCG settings) and of the implicit adjoint
+    of L = sum_i |c_i - c_i^gt|^2 with respect to all observations."""
     from paper_2510_13310_amd import BundleAdjuster, BAError
     dev = torch.device("cuda:0")
     t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
     torch.cuda.reset_peak_memory_stats()
     ba = BundleAdjuster(t(sc.cams0, torch.float64), t(sc.intr, torch.float64),
-                        t(sc.points0, torch.float64), precision="mixed",
+                        t(sc.points0, torch.float64), precision=args.adjoint_precision,
                         huber_px=sc.huber_px, filter_px=sc.filter_px, img_w=sc.img_w,
                         img_h=sc.img_h, pcg_rel_tol=args.pcg_tol, pcg_max_iters=args.pcg_max,
-                        max_lm_iters=iters, timing=1)
+                        max_lm_iters=iters, adjoint_damping=args.adjoint_damping, timing=1)
     ba.set_observations(t(sc.cam_idx, torch.int32), t(sc.pt_idx, torch.int32),
                         t(sc.xy, torch.float32))
     ba.set_depth_priors(t(sc.depth, torch.float32), t(sc.depth_valid, torch.uint8),
@@ -128,7 +132,9 @@ def forward_adjoint(sc, iters, args, torch):
     torch.cuda.synchronize()
     t_adj = time.perf_counter() - t0
     st = {k["name"]: k for k in ba.kernel_stats()}
-    out = dict(lambda_d=args.adjoint_lambda_d, fixed_cameras=[0],
+    out = dict(precision=args.adjoint_precision, lambda_d=args.adjoint_lambda_d,
+               adjoint_damping=args.adjoint_damping,
+               fixed_cameras=[0],
                lm_iterations=srep["iterations"], stop_reason=srep["stop_reason"],
                initial_rms_px=round(srep["initial_rms_px"], 6),
                final_rms_px=round(srep["final_rms_px"], 6), solve_s=round(t_solve, 4),

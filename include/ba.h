@@ -79,6 +79,11 @@ typedef struct ba_options {
   int32_t timing;          /* 1: time phases and kernels with HIP events (ba_kernel_stats) */
   int32_t adjoint_max_iters;/* PCG cap of the (undamped) adjoint solve; 5000 */
   double adjoint_rel_tol;  /* PCG tolerance of the adjoint solve; 1e-10 */
+  double adjoint_damping;  /* Tikhonov damping of the adjoint system, added as
+                              lambda clamp(diag H) like the LM damping: 0 (the exact implicit
+                              derivative) fails with BA_ERR_NUMERIC when H is singular, e.g.
+                              a two-view point whose observations are both in the Huber
+                              regime; a small value (1e-6) regularises such blocks; 0 */
   void* hip_stream;        /* hipStream_t to run on; NULL: a stream owned by the context */
 } ba_options;
 

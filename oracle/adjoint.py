@@ -25,7 +25,7 @@ import numpy as np
 import scipy.sparse.linalg as spla
 
 from .geometry import quat_normalize, quat_to_rot
-from .lm import extract, linearize, metric_blocks, normal_equations, Options, State
+from .lm import damped, extract, linearize, metric_blocks, normal_equations, Options, State
 from .model import Problem
 
 
@@ -42,8 +42,13 @@ def tangent_gradient(st: State, cams: np.ndarray, grad_cams: np.ndarray) -> np.n
 
 
 def adjoint(prob: Problem, st: State, opts: Options, grad_cams: np.ndarray,
-            grad_points: np.ndarray):
-    """Returns (grad_xy N x 2, grad_depth N, v) for the loss gradient at state ``st``."""
+            grad_points: np.ndarray, damping: float = 0.0):
+    """Returns (grad_xy N x 2, grad_depth N, v) for the loss gradient at state ``st``.
+
+    ``damping`` > 0 solves (H + damping D) v = dL/dtheta with Marquardt's D = diag(H) clamped
+    like the LM damping: a Tikhonov-regularised derivative for systems where H is singular
+    (parity unpinned for damping > 0 beyond its damping -> 0 limit).
+    """
     if prob.fixed.size == 0:
         raise ValueError("the adjoint needs a fixed gauge (at least one fixed camera)")
     ex = extract(prob, st, opts)
@@ -51,6 +56,8 @@ def adjoint(prob: Problem, st: State, opts: Options, grad_cams: np.ndarray,
     H, _ = normal_equations(lin, robust_correction=True)
     gbar = np.concatenate([tangent_gradient(st, ex.cams, grad_cams).ravel(),
                            np.asarray(grad_points, np.float64)[ex.pts].ravel()])
+    if damping > 0:
+        H = damped(H, damping, opts)
     v = spla.spsolve(H.tocsc(), gbar)
     M = metric_blocks(lin, robust_correction=True)
     u = (M @ (lin.J @ v)).reshape(lin.e.shape)

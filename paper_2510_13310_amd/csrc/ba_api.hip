@@ -794,7 +794,7 @@ void adjoint_impl(ba_ctx& c, const double* grad_cams, const double* grad_points,
     launch_adjoint_rhs(s, c.Ca, c.Pa, c.cam_src, c.d_cams, c.grad_cams_d, c.pt_src, c.pt_user_d,
                        c.grad_pts_d, c.rhs_c, c.rhs_p);
     HIP_LAUNCH_CHECK();
-    setup_system<T>(c, true, 0.0, c.rhs_c, c.rhs_p);
+    setup_system<T>(c, true, c.opt.adjoint_damping, c.rhs_c, c.rhs_p);
     PcgState st{};
     const double tol = c.opt.adjoint_rel_tol;
     const int maxit = c.opt.adjoint_max_iters;
@@ -874,6 +874,7 @@ void ba_default_options(ba_options* o) {
   o->max_lm_iters = 100;
   o->timing = 0;
   o->adjoint_max_iters = 5000;
+  o->adjoint_damping = 0.0;
   o->adjoint_rel_tol = 1e-10;
   o->hip_stream = nullptr;
 }
@@ -900,6 +901,7 @@ ba_status ba_create(const ba_options* opt, int32_t n_cams, int32_t n_points, con
       o.img_w <= 0 || o.img_h <= 0 || !(o.lambda_min > 0) || !(o.lambda_max >= o.lambda_min) ||
       !(o.lambda_init > 0) || o.pcg_max_iters < 0 || !(o.pcg_rel_tol >= 0) ||
       !(o.diag_min > 0) || !(o.diag_max >= o.diag_min) || o.adjoint_max_iters < 0 ||
+      !(o.adjoint_damping >= 0) ||
       !(o.adjoint_rel_tol >= 0)) {
     g_create_error = "invalid options";
     return BA_ERR_ARG;

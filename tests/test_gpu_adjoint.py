@@ -83,6 +83,28 @@ def test_adjoint_matches_oracle_direct_solve(which):
     assert np.all(gxy[~act] == 0) and np.all(gd[~act] == 0)
 
 
+def test_damped_adjoint_matches_oracle():
+    """adjoint_damping > 0: the GPU's damped Schur/PCG solve against the oracle's damped
+    direct solve (same Marquardt diagonal), float64, 1e-5 of the largest gradient."""
+    rng = np.random.default_rng(9)
+    sc = subscene(make_scene("adjoint"), np.arange(10), max_points=1500, seed=1)
+    ba = gpu_setup(sc, "fp64", adjoint_damping=1e-2, **SOLVE)
+    ba.solve()
+    cams, pts = ba.get_params()
+    g_c, g_p = _loss_grads(sc, cams, pts, rng)
+    gxy, gd = ba.adjoint(g_c, g_p)
+    prob = Problem.from_scene(sc)
+    opts = Options(huber_px=sc.huber_px, filter_px=sc.filter_px)
+    st = State(q=cams[:, :4].copy(), c=cams[:, 4:7].copy(), X=pts.copy(), lam=0.0)
+    ogxy, ogd, _ = oracle_adjoint(prob, st, opts, g_c, g_p, damping=1e-2)
+    ugxy, _, _ = oracle_adjoint(prob, st, opts, g_c, g_p)
+    scale = max(np.abs(ogxy).max(), np.abs(ogd).max())
+    err = max(np.abs(gxy - ogxy).max(), np.abs(gd - ogd).max()) / scale
+    print(f"damped adjoint vs oracle: max rel error {err:.3e} (damping moves the gradient by "
+          f"{np.abs(ogxy - ugxy).max() / scale:.2e})")
+    assert err < 1e-5, err
+
+
 def test_adjoint_mixed_precision_close_to_fp64():
     rng = np.random.default_rng(4)
     sc = subscene(make_scene("adjoint"), np.arange(10), max_points=1500, seed=1)

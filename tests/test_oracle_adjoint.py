@@ -144,3 +144,23 @@ def test_robust_corrected_metric_is_needed_with_huber():
             e_irls.append(abs(fd - ref0) / abs(fd))
     assert np.median(e_corr) < 0.05 and max(e_corr) < 0.15, e_corr
     assert np.median(e_corr) < 0.3 * np.median(e_irls), (e_corr, e_irls)
+
+
+def test_damped_adjoint_limit_and_effect():
+    """The Tikhonov-damped adjoint tends to the exact one as the damping goes to 0 (pinned
+    above by central differences), and a finite damping changes it."""
+    sc = _adjoint_scene()
+    opts = Options(lambda_init=1e-4, cost_rel_tol=0.0, grad_tol=1e-13, max_iters=60)
+    prob = Problem.from_scene(sc)
+    st, _ = solve(prob, State.initial(sc.cams0, sc.points0, opts), opts)
+    grad_cams = np.zeros((sc.n_cams, 7))
+    grad_cams[:, 4:] = 2 * (st.c - sc.cams_gt[:, 4:])
+    W = rng.normal(size=sc.points_gt.shape)
+    ref = adjoint(prob, st, opts, grad_cams, W)[0]
+    scale = np.max(np.abs(ref))
+    d10 = np.max(np.abs(adjoint(prob, st, opts, grad_cams, W, damping=1e-10)[0] - ref))
+    d11 = np.max(np.abs(adjoint(prob, st, opts, grad_cams, W, damping=1e-11)[0] - ref))
+    big = adjoint(prob, st, opts, grad_cams, W, damping=1e-1)[0]
+    # first-order in the damping: ten times smaller damping, ten times smaller change
+    assert d10 <= 1e-6 * scale and 5.0 < d10 / d11 < 20.0, (d10, d11)
+    assert np.max(np.abs(big - ref)) >= 1e-3 * scale
