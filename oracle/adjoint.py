@@ -51,6 +51,8 @@ def adjoint(prob: Problem, st: State, opts: Options, grad_cams: np.ndarray,
     """
     if prob.fixed.size == 0:
         raise ValueError("the adjoint needs a fixed gauge (at least one fixed camera)")
+    if opts.refine_focal:
+        raise ValueError("the adjoint covers poses and points only (focal lengths fixed)")
     ex = extract(prob, st, opts)
     lin = linearize(prob, st, ex, opts.huber_px)
     H, _ = normal_equations(lin, robust_correction=True)

@@ -46,13 +46,13 @@ def observation_rows(prob: Problem) -> np.ndarray:
     return rows
 
 
-def activity_fixpoint(prob: Problem, valid: np.ndarray, rule: str = "rows"):
-    """Greatest fixpoint of the pruning rule. Returns (obs_active, cam_active, pt_active,
-    rounds)."""
+def activity_fixpoint(prob: Problem, valid: np.ndarray, rule: str = "rows", cam_dim: int = 6):
+    """Greatest fixpoint of the pruning rule (a camera needs cam_dim rows). Returns
+    (obs_active, cam_active, pt_active, rounds)."""
     fixed = np.zeros(prob.n_cams, bool)
     fixed[prob.fixed] = True
     rows = observation_rows(prob)
-    need_p, need_c = (3, 6) if rule == "rows" else (1, 1)
+    need_p, need_c = (3, cam_dim) if rule == "rows" else (1, 1)
     act = valid.copy()
     rounds = 0
     while True:

@@ -20,10 +20,14 @@ One LM iteration, following Sec. III-C and Sec. IV-B:
 6. accept when the cost drops and the ratio exceeds 1e-3, then scatter the compact update
    into the full arrays (inactive entries untouched); lambda follows Nielsen's rule
    (accept: lambda *= max(1/3, 1 - (2 rho - 1)^3), nu = 2; reject: lambda *= nu, nu *= 2).
+
+With ``refine_focal`` the per-camera focal length of the intrinsics (Sec. III-B lists K among
+the BA parameters) becomes a seventh camera parameter: the camera block is 7 x 7, de/df =
+[x/z, y/z, 0], the update is additive, and a camera needs 7 residual rows to be active.
 """
 from __future__ import annotations
 
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
@@ -48,6 +52,11 @@ class Options:
     cost_rel_tol: float = 1e-10
     grad_tol: float = 1e-10
     max_iters: int = 100
+    refine_focal: bool = False
+
+    @property
+    def cam_dim(self) -> int:
+        return 7 if self.refine_focal else 6
 
 
 @dataclass
@@ -57,18 +66,31 @@ class State:
     X: np.ndarray
     lam: float
     nu: float = 2.0
+    f: np.ndarray | None = None   # per-camera focal length when it is refined
 
     @classmethod
-    def initial(cls, cams: np.ndarray, points: np.ndarray, opts: Options) -> "State":
+    def initial(cls, cams: np.ndarray, points: np.ndarray, opts: Options,
+                focal: np.ndarray | None = None) -> "State":
         cams = np.asarray(cams, np.float64)
+        f = np.asarray(focal, np.float64).copy() if opts.refine_focal else None
         return cls(q=cams[:, :4].copy(), c=cams[:, 4:7].copy(),
-                   X=np.asarray(points, np.float64).copy(), lam=opts.lambda_init)
+                   X=np.asarray(points, np.float64).copy(), lam=opts.lambda_init, f=f)
 
     def cams(self) -> np.ndarray:
         return np.concatenate([self.q, self.c], axis=1)
 
     def copy(self) -> "State":
-        return State(self.q.copy(), self.c.copy(), self.X.copy(), self.lam, self.nu)
+        return State(self.q.copy(), self.c.copy(), self.X.copy(), self.lam, self.nu,
+                     None if self.f is None else self.f.copy())
+
+
+def problem_at(prob: Problem, st: State) -> Problem:
+    """The problem with the state's focal lengths in its intrinsics (when refined)."""
+    if st.f is None:
+        return prob
+    intr = prob.intr.copy()
+    intr[:, 0] = st.f
+    return replace(prob, intr=intr)
 
 
 @dataclass
@@ -86,8 +108,9 @@ class Extraction:
 
 
 def extract(prob: Problem, st: State, opts: Options) -> Extraction:
+    prob = problem_at(prob, st)
     valid = geometric_validity(prob, st.q, st.c, st.X, opts.min_depth, opts.filter_px)
-    oa, ca, pa, rounds = activity_fixpoint(prob, valid, opts.rule)
+    oa, ca, pa, rounds = activity_fixpoint(prob, valid, opts.rule, opts.cam_dim)
     cr, cams = ranks(ca)
     pr, pts = ranks(pa)
     return Extraction(valid, oa, ca, pa, rounds, np.nonzero(oa)[0], cr, cams, pr, pts)
@@ -97,30 +120,38 @@ def extract(prob: Problem, st: State, opts: Options) -> Extraction:
 class Linearization:
     obs: np.ndarray
     e: np.ndarray          # n x r
-    Jc: np.ndarray         # n x r x 6
+    Jc: np.ndarray         # n x r x d (d = 6, or 7 with the focal length)
     Jp: np.ndarray         # n x r x 3
     rho: np.ndarray        # n
     w: np.ndarray          # n   rho'
     d2: np.ndarray         # n   rho''
-    J: sp.csr_matrix       # (n r) x (6 Ca + 3 Pa)
+    J: sp.csr_matrix       # (n r) x (d Ca + 3 Pa)
     ncol_cam: int
 
 
 def linearize(prob: Problem, st: State, ex: Extraction, delta: float) -> Linearization:
+    prob = problem_at(prob, st)
     obs = ex.obs
     e, Xc, R = residuals(prob, st.q, st.c, st.X, obs)
     cam, pt = prob.cam_idx[obs], prob.pt_idx[obs]
     Jc, Jp = jacobians(prob, Xc, R, cam)
+    if st.f is not None:
+        # de/df of the pinhole rows: (x/z, y/z); the inverse-depth row does not depend on f
+        Jf = np.zeros(e.shape + (1,))
+        Jf[:, 0, 0] = Xc[:, 0] / Xc[:, 2]
+        Jf[:, 1, 0] = Xc[:, 1] / Xc[:, 2]
+        Jc = np.concatenate([Jc, Jf], axis=2)
+    d = Jc.shape[2]
     rho, w, d2 = huber(np.sum(e * e, axis=1), delta)
     n, r = e.shape
-    nc = 6 * ex.cams.size
+    nc = d * ex.cams.size
     ncols = nc + 3 * ex.pts.size
     rows = np.arange(n * r).reshape(n, r)
     crank = ex.cam_rank[cam]
     has_cam = crank >= 0                   # observations of fixed cameras have no camera block
     ri, ci, vi = [], [], []
-    rr = np.broadcast_to(rows[:, :, None], (n, r, 6))[has_cam]
-    cc = np.broadcast_to((6 * crank)[:, None, None] + np.arange(6), (n, r, 6))[has_cam]
+    rr = np.broadcast_to(rows[:, :, None], (n, r, d))[has_cam]
+    cc = np.broadcast_to((d * crank)[:, None, None] + np.arange(d), (n, r, d))[has_cam]
     ri.append(rr.ravel()); ci.append(cc.ravel()); vi.append(Jc[has_cam].ravel())
     rr = np.broadcast_to(rows[:, :, None], (n, r, 3))
     cc = np.broadcast_to((nc + 3 * ex.pt_rank[pt])[:, None, None] + np.arange(3), (n, r, 3))
@@ -211,11 +242,15 @@ class StepReport:
 
 
 def candidate(st: State, ex: Extraction, delta: np.ndarray) -> State:
-    nc = 6 * ex.cams.size
+    d = 6 if st.f is None else 7
+    nc = d * ex.cams.size
     new = st.copy()
     if ex.cams.size:
-        xi = delta[:nc].reshape(-1, 6)
-        new.q[ex.cams], new.c[ex.cams] = retract_cameras(st.q[ex.cams], st.c[ex.cams], xi)
+        xi = delta[:nc].reshape(-1, d)
+        new.q[ex.cams], new.c[ex.cams] = retract_cameras(st.q[ex.cams], st.c[ex.cams],
+                                                         xi[:, :6])
+        if st.f is not None:
+            new.f[ex.cams] = st.f[ex.cams] + xi[:, 6]
     new.X[ex.pts] = st.X[ex.pts] + delta[nc:].reshape(-1, 3)
     return new
 
@@ -247,7 +282,7 @@ def lm_step(prob: Problem, st: State, opts: Options):
     model = -(float(g @ delta) + 0.5 * float(np.sum(lin.w[:, None] * Jd * Jd)))
     rep.model_decrease = model
     cand = candidate(st, ex, delta)
-    e2, Xc2, _ = residuals(prob, cand.q, cand.c, cand.X, ex.obs)
+    e2, Xc2, _ = residuals(problem_at(prob, cand), cand.q, cand.c, cand.X, ex.obs)
     if np.any(Xc2[:, 2] <= opts.min_depth):
         F2, dF = np.inf, -np.inf
     else:
