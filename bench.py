@@ -60,8 +60,20 @@ def parse():
                     help="Tikhonov damping of the --forward-adjoint system (singular point "
                          "blocks under the robust-corrected metric)")
     ap.add_argument("--adjoint-precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--refine-focal", action="store_true",
+                    help="refine each camera's focal length too (7-parameter cameras), "
+                         "starting from focal lengths off by up to 2%%")
     ap.add_argument("--verbose", action="store_true")
     return ap.parse_args()
+
+
+def focal_start(sc):
+    """The scene with every camera's focal length scaled by a seeded factor in [0.98, 1.02]."""
+    from dataclasses import replace
+    rng = np.random.default_rng(77)
+    intr = sc.intr.copy()
+    intr[:, 0] *= 1.0 + rng.uniform(-0.02, 0.02, size=sc.n_cams)
+    return replace(sc, intr=intr)
 
 
 def run_gpu(sc, precision, steps, warmup, args, torch, timing):
@@ -72,7 +84,8 @@ def run_gpu(sc, precision, steps, warmup, args, torch, timing):
                         t(sc.points0, torch.float64), precision=precision,
                         huber_px=sc.huber_px, filter_px=sc.filter_px, img_w=sc.img_w,
                         img_h=sc.img_h, pcg_rel_tol=args.pcg_tol, pcg_max_iters=args.pcg_max,
-                        pcg_check_every=args.check_every, timing=timing)
+                        pcg_check_every=args.check_every, timing=timing,
+                        refine_focal=int(args.refine_focal))
     ba.set_observations(t(sc.cam_idx, torch.int32), t(sc.pt_idx, torch.int32),
                         t(sc.xy, torch.float32))
     if sc.use_depth:
@@ -225,7 +238,7 @@ def roofline(res, scene):
     return out
 
 
-def cpu_baseline(sc, frac, steps, n_obs_full):
+def cpu_baseline(sc, frac, steps, n_obs_full, refine_focal=False):
     """The FP64 oracle on a random fraction of the points (all cameras), timed per LM step;
     the rate is rescaled to the full observation count (per-observation work dominates)."""
     from dataclasses import replace
@@ -242,9 +255,9 @@ def cpu_baseline(sc, frac, steps, n_obs_full):
                   cam_idx=sc.cam_idx[ob], pt_idx=pmap[sc.pt_idx[ob]].astype(np.int32),
                   xy=sc.xy[ob], depth=sc.depth[ob], depth_valid=sc.depth_valid[ob],
                   is_outlier=sc.is_outlier[ob])
-    opts = Options(huber_px=sc.huber_px, filter_px=sc.filter_px)
+    opts = Options(huber_px=sc.huber_px, filter_px=sc.filter_px, refine_focal=refine_focal)
     prob = Problem.from_scene(sub)
-    st = State.initial(sub.cams0, sub.points0, opts)
+    st = State.initial(sub.cams0, sub.points0, opts, focal=sub.intr[:, 0])
     t0 = time.perf_counter()
     nobs = []
     for _ in range(steps):
@@ -268,6 +281,10 @@ def main():
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(multi-GPU point sharding is design-only).", file=sys.stderr)
         sys.exit(2)
+    if args.refine_focal and args.forward_adjoint:
+        print("bench.py: the adjoint covers poses and points; --forward-adjoint needs focal "
+              "refinement off", file=sys.stderr)
+        sys.exit(2)
     import torch
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -288,6 +305,9 @@ def main():
 
     t0 = time.perf_counter()
     sc = make_scene(args.scene)
+    if args.refine_focal:
+        sc = focal_start(sc)
+    workload_key = args.scene + ("+focal" if args.refine_focal else "")
     t_gen = time.perf_counter() - t0
     if args.verbose:
         print(f"scene {args.scene}: C={sc.n_cams} P={sc.n_points} N={sc.n_obs} "
@@ -327,13 +347,15 @@ def main():
                                 f"{sc.n_points} points, {sc.n_obs} observations, "
                                 f"{100 * sc.is_outlier.mean():.0f}% outliers, depth priors on "
                                 f"{100 * sc.depth_valid.mean():.0f}%, Huber "
-                                f"{sc.huber_px:g} px, {sc.filter_px:g} px filter"),
+                                f"{sc.huber_px:g} px, {sc.filter_px:g} px filter"
+                                + (", focal lengths refined (7-parameter cameras, start "
+                                   "off by up to 2%)" if args.refine_focal else "")),
                    "pcg_rel_tol": args.pcg_tol, "pcg_max_iters": args.pcg_max,
                    "pcg_check_every": args.check_every},
         "obs_per_s": round(summ["obs_per_s"], 1),
         "jacobian_obs_per_s": (round(summ["jacobian_obs_per_s"], 1)
                                if summ["jacobian_obs_per_s"] else None),
-        "roofline": roofline(ins, args.scene),
+        "roofline": roofline(ins, workload_key),
     }
     for p in precs:
         s = out[p][1]
@@ -347,7 +369,8 @@ def main():
     if args.forward_adjoint > 0:
         line["forward_adjoint"] = forward_adjoint(sc, args.forward_adjoint, args, torch)
     line["cpu_baseline"] = (None if args.no_cpu else
-                            cpu_baseline(sc, args.cpu_frac, args.cpu_steps, sc.n_obs))
+                            cpu_baseline(sc, args.cpu_frac, args.cpu_steps, sc.n_obs,
+                                         args.refine_focal))
     print(json.dumps(line), flush=True)
 
 

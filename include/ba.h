@@ -78,6 +78,11 @@ typedef struct ba_options {
   int32_t max_lm_iters;    /* ba_solve iteration cap; 100 */
   int32_t timing;          /* 1: time phases and kernels with HIP events (ba_kernel_stats) */
   int32_t adjoint_max_iters;/* PCG cap of the (undamped) adjoint solve; 5000 */
+  int32_t refine_focal;    /* 1: the focal length f of each camera's intrinsics (Sec. III-B
+                              lists K among the BA parameters) is a seventh camera unknown:
+                              7 x 7 camera blocks, de/df = (x/z, y/z, 0), additive update, a
+                              camera needs 7 residual rows; cx, cy stay fixed. The adjoint
+                              needs it off. Default 0 */
   double adjoint_rel_tol;  /* PCG tolerance of the adjoint solve; 1e-10 */
   double adjoint_damping;  /* Tikhonov damping of the adjoint system, added as
                               lambda clamp(diag H) like the LM damping: 0 (the exact implicit
@@ -167,17 +172,22 @@ ba_status ba_get_params(const ba_ctx* ctx, double* cams, double* points);
  * a re-solve. Resets lambda to lambda_init and invalidates the linearisation. */
 ba_status ba_set_params(ba_ctx* ctx, const double* cams, const double* points);
 
+/* Copy the current intrinsics out (C x 3 [f, cx, cy]): the focal lengths as refined so far
+ * when refine_focal, else the values given to ba_create. */
+ba_status ba_get_intrinsics(const ba_ctx* ctx, double* intr);
+
 /* Activity of the last extraction, in the caller's order (any pointer may be NULL):
  * cams C, points P, obs N bytes, 1 = active. BA_ERR_STATE before the first step. */
 ba_status ba_get_active(const ba_ctx* ctx, uint8_t* cams, uint8_t* points, uint8_t* obs);
 
-/* The last computed LM step in tangent coordinates: cams C x 6 (rho, phi), points P x 3;
- * zero for inactive or fixed entries. */
+/* The last computed LM step in tangent coordinates: cams C x d (rho, phi, and the focal step
+ * when refine_focal: d = 7, else d = 6), points P x 3; zero for inactive or fixed entries. */
 ba_status ba_get_last_step(const ba_ctx* ctx, double* dcams, double* dpoints);
 
 /* Undamped normal-equation blocks of the last linearisation, caller's order, zero for
- * inactive entries: U C x 36 (J_c^T W J_c, row-major 6x6), gc C x 6 (J_c^T W e),
- * V P x 9 (J_p^T W J_p), gp P x 3 (J_p^T W e). Any pointer may be NULL. */
+ * inactive entries: U C x d*d (J_c^T W J_c, row-major d x d), gc C x d (J_c^T W e),
+ * V P x 9 (J_p^T W J_p), gp P x 3 (J_p^T W e), with d = 7 when refine_focal, else 6.
+ * Any pointer may be NULL. */
 ba_status ba_get_normal_blocks(const ba_ctx* ctx, double* U, double* gc, double* V,
                                double* gp);
 
@@ -189,6 +199,7 @@ ba_status ba_get_normal_blocks(const ba_ctx* ctx, double* U, double* gc, double*
  * Inactive observations get zero gradients. */
 ba_status ba_adjoint(ba_ctx* ctx, const double* grad_cams, const double* grad_points,
                      float* grad_xy, float* grad_depth);
+/* (with refine_focal set, ba_adjoint returns BA_ERR_STATE: it covers poses and points) */
 
 /* Per-kernel HIP-event statistics accumulated while opt.timing = 1. Writes up to max entries
  * and returns their count in *n. ba_reset_kernel_stats clears them. */

@@ -9,7 +9,8 @@ from ._abi import (BAError, BA_OK, BA_EMPTY, BA_ERR_ARG, BA_ERR_STATE, BA_ERR_OO
                    LIB_PATH, load)
 from .api import (BundleAdjuster, make_options, ba_default_options, ba_create,
                   ba_set_observations, ba_set_depth_priors, ba_set_fixed_cameras, ba_lm_step,
-                  ba_solve, ba_get_params, ba_set_params, ba_get_active, ba_get_last_step,
+                  ba_solve, ba_get_params, ba_get_intrinsics, ba_set_params, ba_get_active,
+                  ba_get_last_step,
                   ba_get_normal_blocks, ba_adjoint, ba_kernel_stats, ba_reset_kernel_stats,
                   ba_device_bytes, ba_last_error, ba_destroy)
 
@@ -18,7 +19,8 @@ __all__ = [
     "BA_ERR_DEVICE", "BA_ERR_NUMERIC", "BA_PRECISION_FP64", "BA_PRECISION_MIXED", "LIB_PATH",
     "load", "BundleAdjuster", "make_options", "ba_default_options", "ba_create",
     "ba_set_observations", "ba_set_depth_priors", "ba_set_fixed_cameras", "ba_lm_step",
-    "ba_solve", "ba_get_params", "ba_set_params", "ba_get_active", "ba_get_last_step",
+    "ba_solve", "ba_get_params", "ba_get_intrinsics", "ba_set_params", "ba_get_active",
+    "ba_get_last_step",
     "ba_get_normal_blocks", "ba_adjoint", "ba_kernel_stats", "ba_reset_kernel_stats",
     "ba_device_bytes", "ba_last_error", "ba_destroy",
 ]

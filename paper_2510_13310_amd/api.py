@@ -114,6 +114,12 @@ def ba_get_params(ctx: int, cams_out, points_out) -> int:
     return _check(lib, ctx, lib.ba_get_params(ctx, pc, pp))
 
 
+def ba_get_intrinsics(ctx: int, intr_out) -> int:
+    lib = _abi.load()
+    pi, _ = _ptr(intr_out, F64)
+    return _check(lib, ctx, lib.ba_get_intrinsics(ctx, pi))
+
+
 def ba_set_params(ctx: int, cams, points) -> int:
     lib = _abi.load()
     pc, kc = _ptr(cams, F64)
@@ -214,6 +220,7 @@ class BundleAdjuster:
         self.opts = make_options(precision, **opts)
         self.n_cams = int(cams.shape[0])
         self.n_points = int(points.shape[0])
+        self.cam_dim = 7 if self.opts.refine_focal else 6
         self.n_obs = 0
         self.ctx = ba_create(self.opts, self.n_cams, self.n_points, cams, intr, points)
 
@@ -266,6 +273,11 @@ class BundleAdjuster:
     def set_params(self, cams=None, points=None):
         return ba_set_params(self.ctx, cams, points)
 
+    def get_intrinsics(self):
+        intr = np.empty((self.n_cams, 3))
+        ba_get_intrinsics(self.ctx, intr)
+        return intr
+
     def get_active(self):
         c = np.empty(self.n_cams, np.uint8)
         p = np.empty(self.n_points, np.uint8)
@@ -274,14 +286,15 @@ class BundleAdjuster:
         return c.astype(bool), p.astype(bool), o.astype(bool)
 
     def get_last_step(self):
-        dc = np.empty((self.n_cams, 6))
+        dc = np.empty((self.n_cams, self.cam_dim))
         dp = np.empty((self.n_points, 3))
         ba_get_last_step(self.ctx, dc, dp)
         return dc, dp
 
     def get_normal_blocks(self):
-        U = np.empty((self.n_cams, 6, 6))
-        gc = np.empty((self.n_cams, 6))
+        d = self.cam_dim
+        U = np.empty((self.n_cams, d, d))
+        gc = np.empty((self.n_cams, d))
         V = np.empty((self.n_points, 3, 3))
         gp = np.empty((self.n_points, 3))
         ba_get_normal_blocks(self.ctx, U, gc, V, gp)

@@ -173,7 +173,9 @@ struct ba_ctx {
 
   size_t tsize() const { return opt.precision == BA_PRECISION_FP64 ? 8 : 4; }
   int need_pt() const { return opt.activity_rule == BA_ACTIVITY_LITERAL ? 1 : 3; }
-  int need_cam() const { return opt.activity_rule == BA_ACTIVITY_LITERAL ? 1 : 6; }
+  // camera unknowns: pose (6), plus the focal length when it is refined (7)
+  int D = 6;
+  int need_cam() const { return opt.activity_rule == BA_ACTIVITY_LITERAL ? 1 : D; }
 
   Model model() const {
     Model m;
@@ -367,24 +369,26 @@ void alloc_obs_buffers(ba_ctx& c) {
   c.Vinv = A.alloc<char>(ts * 6 * P);
   c.prec = A.alloc<char>((ts == 8 ? sizeof(PtRec<double>) : sizeof(PtRec<float>)) * P);
   c.zq = A.alloc<char>(3 * ts * N);
-  c.Ustar = A.alloc<char>(ts * 21 * C);
-  c.mvt = A.alloc<char>(ts * 16 * C);
+  const size_t ns = size_t(c.D) * (c.D + 1) / 2;   // entries of a symmetric camera block
+  const size_t nd = size_t(c.D);
+  c.Ustar = A.alloc<char>(ts * ns * C);
+  c.mvt = A.alloc<char>(ts * 20 * C);   // MvCam (16 T) or MvCamF (20 T) records
   c.gp = A.alloc<double>(3 * size_t(P));
   c.hp = A.alloc<double>(3 * size_t(P));
   c.dp = A.alloc<double>(3 * size_t(P));
   c.Xcand = A.alloc<double>(3 * size_t(P));
   c.rhs_p = A.alloc<double>(3 * size_t(P));
-  c.Uraw = A.alloc<double>(21 * size_t(C));
-  c.gc = A.alloc<double>(6 * size_t(C));
-  c.b = A.alloc<double>(6 * size_t(C));
-  c.Minv = A.alloc<double>(21 * size_t(C));
-  c.rhs_c = A.alloc<double>(6 * size_t(C));
-  c.x = A.alloc<double>(6 * size_t(C));
-  c.r = A.alloc<double>(6 * size_t(C));
-  c.u = A.alloc<double>(6 * size_t(C));
-  c.p = A.alloc<double>(6 * size_t(C));
-  c.sv = A.alloc<double>(6 * size_t(C));
-  c.wv = A.alloc<double>(6 * size_t(C));
+  c.Uraw = A.alloc<double>(ns * size_t(C));
+  c.gc = A.alloc<double>(nd * size_t(C));
+  c.b = A.alloc<double>(nd * size_t(C));
+  c.Minv = A.alloc<double>(ns * size_t(C));
+  c.rhs_c = A.alloc<double>(nd * size_t(C));
+  c.x = A.alloc<double>(nd * size_t(C));
+  c.r = A.alloc<double>(nd * size_t(C));
+  c.u = A.alloc<double>(nd * size_t(C));
+  c.p = A.alloc<double>(nd * size_t(C));
+  c.sv = A.alloc<double>(nd * size_t(C));
+  c.wv = A.alloc<double>(nd * size_t(C));
   c.dots = A.alloc<double>(3 * size_t(C));
   c.partials = A.alloc<double>(5 * (size_t(P) / kBlock + 16));
   c.scal = A.alloc<double>(16);
@@ -502,9 +506,9 @@ void extract(ba_ctx& c) {
                        c.pm_orig, c.Ca, c.inv_cm, c.pos_cm, c.pm_pt, c.rank_p, c.cam_hat,
                        c.xy_hat, c.depth_hat, c.orig_hat, c.pm_cm, c.cm_pt);
     if (c.tsize() == 8)
-      launch_mv_table<double>(s, c.Ca + c.n_fixed, c.camd_hat, static_cast<MvCam<double>*>(c.mvt));
+      launch_mv_table<double>(s, c.D, c.Ca + c.n_fixed, c.camd_hat, c.mvt);
     else
-      launch_mv_table<float>(s, c.Ca + c.n_fixed, c.camd_hat, static_cast<MvCam<float>*>(c.mvt));
+      launch_mv_table<float>(s, c.D, c.Ca + c.n_fixed, c.camd_hat, c.mvt);
   });
   c.ext_valid = true;
 }
@@ -522,7 +526,8 @@ double bytes_schur_point(const ba_ctx& c) {
 // offsets, table entry, U*, u, r, and the w and dot terms written.
 double bytes_schur_cam(const ba_ctx& c) {
   const double ts = double(c.tsize());
-  return double(c.Nc) * 7 * ts + double(c.Ca) * (4 + 15 * ts + 21 * ts + 12 * 8 + 9 * 8);
+  const double D = c.D, ns = D * (D + 1) / 2;
+  return double(c.Nc) * 7 * ts + double(c.Ca) * (4 + 15 * ts + ns * ts + 2 * D * 8 + (D + 3) * 8);
 }
 int lanes_per_point(const ba_ctx& c) {
   const double mean = c.Pa > 0 ? double(c.Nh) / c.Pa : 1.0;
@@ -570,9 +575,9 @@ void setup_system(ba_ctx& c, bool adj, double lam, const double* rhs_c, const do
   c.timed("cam_assemble",
           double(c.Nc) * (4 + 8 * ts + (adj ? 3 * ts : 0)) +
               double(c.Pa) * double(sizeof(PtRec<T>)) +
-              double(c.Ca) * (21 * 8 + 21 * ts + 6 * 8 * 2 + 21 * 8),
+              double(c.Ca) * (double(c.D) * (c.D + 1) / 2 * (16 + ts) + c.D * 8 * 2),
           -1, [&] {
-            launch_cam_assemble<T>(s, adj, m, cp, om, lam, c.opt.diag_min, c.opt.diag_max,
+            launch_cam_assemble<T>(s, adj, c.D, m, cp, om, lam, c.opt.diag_min, c.opt.diag_max,
                                    static_cast<const PtRec<T>*>(c.prec), rhs_c, c.Uraw,
                                    static_cast<T*>(c.Ustar), c.gc, c.b, c.Minv);
           });
@@ -593,8 +598,8 @@ int run_pcg(ba_ctx& c, bool adj, double rel_tol, int max_iters, PcgState* out_st
     out_state->done = 1;
     return 0;
   }
-  MvCam<T>* mvt = static_cast<MvCam<T>*>(c.mvt);
-  launch_pcg_init<T>(s, c.Ca, c.b, c.Minv, c.x, c.r, c.u, c.p, c.sv, mvt, c.pcg,
+  void* mvt = c.mvt;
+  launch_pcg_init<T>(s, c.D, c.Ca, c.b, c.Minv, c.x, c.r, c.u, c.p, c.sv, mvt, c.pcg,
                      rel_tol * rel_tol, max_iters);
   HIP_LAUNCH_CHECK();
   const int every = std::max(1, c.opt.pcg_check_every);
@@ -605,18 +610,21 @@ int run_pcg(ba_ctx& c, bool adj, double rel_tol, int max_iters, PcgState* out_st
   while (true) {
     for (int k = 0; k < every && it < max_iters; ++k, ++it) {
       c.timed("schur_point", bp, it, [&] {
-        launch_schur_point<T>(s, adj, G, m, cp, om, mvt, static_cast<const T*>(c.Vinv), zq,
+        launch_schur_point<T>(s, adj, c.D, G, m, cp, om, mvt, static_cast<const T*>(c.Vinv), zq,
                               c.pcg, c.dl);
       });
       c.timed("schur_cam", bc, it, [&] {
-        launch_schur_cam<T>(s, adj, m, cp, om, static_cast<const T*>(c.Ustar), c.u, c.r, zq,
+        launch_schur_cam<T>(s, adj, c.D, m, cp, om, static_cast<const T*>(c.Ustar), c.u, c.r, zq,
                             c.wv, c.dots, c.pcg);
       });
       // per camera: its dot terms, M^-1, reads of u p w s x r, writes of p s x r u and its
       // matvec record's u
-      c.timed("pcg_update", double(c.Ca) * (3 * 8 + 21 * 8 + 6 * 8 * 11 + 6 * double(sizeof(T))),
+      c.timed("pcg_update",
+              double(c.Ca) * (3 * 8 + double(c.D) * (c.D + 1) / 2 * 8 + c.D * 8 * 11 +
+                              c.D * double(sizeof(T))),
               it, [&] {
-                launch_pcg_update<T>(s, c.Ca, it, c.Minv, c.dots, c.x, c.r, c.u, c.p, c.sv, c.wv,
+                launch_pcg_update<T>(s, c.D, c.Ca, it, c.Minv, c.dots, c.x, c.r, c.u, c.p, c.sv,
+                                     c.wv,
                                      mvt, c.pcg);
               });
     }
@@ -636,7 +644,7 @@ void backsub(ba_ctx& c, bool adj, const double* rhs_p) {
   Compact<T> cp = compact_view<T>(c);
   ObsMetric<T> om = metric_view<T>(c);
   c.timed("backsub", bytes_schur_point(c) + double(c.Pa) * 48, -1, [&] {
-    launch_backsub<T>(s, adj, lanes_per_point(c), m, cp, om, static_cast<const T*>(c.Vinv),
+    launch_backsub<T>(s, adj, c.D, lanes_per_point(c), m, cp, om, static_cast<const T*>(c.Vinv),
                       c.x, c.gp, rhs_p, c.dp);
   });
 }
@@ -697,19 +705,19 @@ ba_status lm_step_impl(ba_ctx& c, ba_step_report* rep) {
   backsub<T>(c, false, nullptr);
   c.timed("cam_candidate", double(c.Ca + c.n_fixed) * (56 + 120 + 56 + 120) + double(c.Ca) * 48,
           -1, [&] {
-            launch_cam_candidate(s, c.Ca, c.n_fixed, c.cam_src, c.x, c.d_cams, c.camd_hat,
+            launch_cam_candidate(s, c.Ca, c.n_fixed, c.D, c.cam_src, c.x, c.d_cams, c.camd_hat,
                                  c.d_cand_cams, c.d_cand_tab);
           });
   Compact<T> cp = compact_view<T>(c);
   c.timed("point_candidate",
           double(c.Nh) * (4 + 8 + 4 + ts) + double(c.Pa) * (4 + 24 * 4) + double(c.C) * 240, -1,
           [&] {
-            launch_point_candidate<T>(s, m, cp, c.d_cand_tab, c.x, c.dp, c.gp,
+            launch_point_candidate<T>(s, m, cp, c.D, c.d_cand_tab, c.x, c.dp, c.gp,
                                       static_cast<const T*>(c.w), c.Xcand, c.partials);
           });
   const int nb = int((c.Pa + kBlock - 1) / kBlock);
   // scal[4..] = decrease, quad, g_p.dp, bad, cost', g_c.x, max |g_c|
-  launch_reduce_partials(s, nb, 5, c.partials, 0x0u, c.Ca, c.gc, c.x, c.scal + 4);
+  launch_reduce_partials(s, nb, 5, c.partials, 0x0u, c.D * c.Ca, c.gc, c.x, c.scal + 4);
   HIP_LAUNCH_CHECK();
   HIP_CHECK(hipMemcpyAsync(c.h_pin, c.scal, 11 * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_CHECK(hipMemcpyAsync(c.h_pin + 11, c.flags + 1, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -746,8 +754,8 @@ ba_status lm_step_impl(ba_ctx& c, ba_step_report* rep) {
   c.step_valid = true;
   if (ok) {
     c.timed("scatter", double(c.Pa) * 52 + double(c.C) * 60, -1, [&] {
-      launch_scatter(s, c.Pa, c.Ca, c.pt_src, c.Xcand, c.cam_src, c.d_cand_cams, c.d_pts,
-                     c.d_cams);
+      launch_scatter(s, c.Pa, c.Ca, c.pt_src, c.Xcand, c.cam_src, c.d_cand_cams, c.d_cand_tab,
+                     c.d_pts, c.d_cams, c.D == 7 ? c.d_intr : nullptr);
     });
     c.lin_valid = false;
     const double f = std::max(1.0 / 3.0, 1.0 - std::pow(2.0 * ratio - 1.0, 3));
@@ -875,6 +883,7 @@ void ba_default_options(ba_options* o) {
   o->timing = 0;
   o->adjoint_max_iters = 5000;
   o->adjoint_damping = 0.0;
+  o->refine_focal = 0;
   o->adjoint_rel_tol = 1e-10;
   o->hip_stream = nullptr;
 }
@@ -901,7 +910,7 @@ ba_status ba_create(const ba_options* opt, int32_t n_cams, int32_t n_points, con
       o.img_w <= 0 || o.img_h <= 0 || !(o.lambda_min > 0) || !(o.lambda_max >= o.lambda_min) ||
       !(o.lambda_init > 0) || o.pcg_max_iters < 0 || !(o.pcg_rel_tol >= 0) ||
       !(o.diag_min > 0) || !(o.diag_max >= o.diag_min) || o.adjoint_max_iters < 0 ||
-      !(o.adjoint_damping >= 0) ||
+      !(o.adjoint_damping >= 0) || (o.refine_focal != 0 && o.refine_focal != 1) ||
       !(o.adjoint_rel_tol >= 0)) {
     g_create_error = "invalid options";
     return BA_ERR_ARG;
@@ -919,6 +928,7 @@ ba_status ba_create(const ba_options* opt, int32_t n_cams, int32_t n_points, con
     return BA_ERR_OOM;
   }
   c->opt = o;
+  c->D = o.refine_focal ? 7 : 6;
   c->C = n_cams;
   c->P = n_points;
   c->lam = o.lambda_init;
@@ -1176,6 +1186,17 @@ ba_status ba_get_params(const ba_ctx* cc, double* cams, double* points) {
   });
 }
 
+ba_status ba_get_intrinsics(const ba_ctx* cc, double* intr) {
+  ba_ctx* c = const_cast<ba_ctx*>(cc);
+  return guarded(c, [&]() -> ba_status {
+    if (!intr) return fail(c, BA_ERR_ARG, "intr is NULL");
+    HIP_CHECK(hipMemcpyAsync(intr, c->d_intr, sizeof(double) * 3 * size_t(c->C),
+                             hipMemcpyDefault, c->stream));
+    c->sync();
+    return BA_OK;
+  });
+}
+
 ba_status ba_set_params(ba_ctx* c, const double* cams, const double* points) {
   return guarded(c, [&]() -> ba_status {
     if (cams) {
@@ -1231,11 +1252,12 @@ ba_status ba_get_last_step(const ba_ctx* cc, double* dcams, double* dpoints) {
     if (!c->step_valid) return fail(c, BA_ERR_STATE, "no LM step has been computed");
     std::vector<int> src;
     if (dcams) {
-      std::vector<double> x, out(6 * size_t(c->C), 0.0);
-      download(*c, x, c->x, 6 * size_t(c->Ca));
+      const size_t D = size_t(c->D);
+      std::vector<double> x, out(D * size_t(c->C), 0.0);
+      download(*c, x, c->x, D * size_t(c->Ca));
       download(*c, src, c->cam_src, size_t(c->Ca));
       for (int s = 0; s < c->Ca; ++s)
-        for (int k = 0; k < 6; ++k) out[6 * size_t(src[s]) + k] = x[size_t(k) * c->Ca + s];
+        for (size_t k = 0; k < D; ++k) out[D * size_t(src[s]) + k] = x[k * c->Ca + s];
       store(*c, dcams, out.data(), out.size());
     }
     if (dpoints) {
@@ -1260,17 +1282,19 @@ ba_status ba_get_normal_blocks(const ba_ctx* cc, double* U, double* gcv, double*
     download(*c, csrc, c->cam_src, size_t(c->Ca));
     download(*c, psrc, c->pt_src, size_t(c->Pa));
     if (U || gcv) {
-      std::vector<double> u, g, Uo(36 * size_t(c->C), 0.0), go(6 * size_t(c->C), 0.0);
-      download(*c, u, c->Uraw, 21 * size_t(c->Ca));
-      download(*c, g, c->gc, 6 * size_t(c->Ca));
+      const int D = c->D;
+      const size_t ns = size_t(D) * (D + 1) / 2;
+      std::vector<double> u, g, Uo(size_t(D) * D * size_t(c->C), 0.0), go(size_t(D) * c->C, 0.0);
+      download(*c, u, c->Uraw, ns * size_t(c->Ca));
+      download(*c, g, c->gc, size_t(D) * c->Ca);
       for (int s = 0; s < c->Ca; ++s) {
         const size_t cam = size_t(csrc[s]);
-        for (int i = 0; i < 6; ++i) {
-          go[6 * cam + i] = g[size_t(i) * c->Ca + s];
-          for (int j = 0; j < 6; ++j) {
+        for (int i = 0; i < D; ++i) {
+          go[D * cam + i] = g[size_t(i) * c->Ca + s];
+          for (int j = 0; j < D; ++j) {
             const int a = std::min(i, j), b = std::max(i, j);
-            const int idx = a * 6 - (a * (a - 1)) / 2 + (b - a);
-            Uo[36 * cam + 6 * i + j] = u[21 * size_t(s) + idx];
+            const int idx = a * D - (a * (a - 1)) / 2 + (b - a);
+            Uo[size_t(D) * D * cam + D * i + j] = u[ns * size_t(s) + idx];
           }
         }
       }
@@ -1302,6 +1326,8 @@ ba_status ba_adjoint(ba_ctx* c, const double* grad_cams, const double* grad_poin
     if (!c->have_obs) return fail(c, BA_ERR_STATE, "ba_set_observations has not been called");
     if (!grad_cams || !grad_points || !grad_xy)
       return fail(c, BA_ERR_ARG, "grad_cams, grad_points and grad_xy are required");
+    if (c->D != 6)
+      return fail(c, BA_ERR_STATE, "the adjoint covers poses and points: refine_focal must be off");
     const bool metric = c->have_priors && c->lam_d > 0;
     if (c->n_fixed < 1 || (!metric && c->n_fixed < 2))
       return fail(c, BA_ERR_STATE,

@@ -48,6 +48,27 @@ struct alignas(16 * sizeof(T)) MvCam {
   T f;
   T u[6];
 };
+// With the focal length refined the camera unknown has a seventh component.
+template <typename T>
+struct alignas(4 * sizeof(T)) MvCamF {
+  T R[9];
+  T f;
+  T u[7];
+  T pad[3];
+};
+template <typename T, int D>
+struct MvRecOf {
+  using type = MvCam<T>;
+};
+template <typename T>
+struct MvRecOf<T, 7> {
+  using type = MvCamF<T>;
+};
+template <typename T, int D>
+using MvRec = typename MvRecOf<T, D>::type;
+
+// Entries of a symmetric D x D block stored as its upper triangle.
+constexpr int sym_count(int D) { return D * (D + 1) / 2; }
 
 // Residual-model constants shared by the kernels.
 struct Model {
@@ -164,7 +185,7 @@ void launch_compact_obs(hipStream_t s, int64_t N, const uint8_t* vrow, const int
                         int* cm_pt);
 // Matvec records of every slot (R, f from the compact table; u = 0).
 template <typename T>
-void launch_mv_table(hipStream_t s, int n, const Cam<double>* camd_hat, MvCam<T>* mvt);
+void launch_mv_table(hipStream_t s, int D, int n, const Cam<double>* camd_hat, void* mvt);
 
 // ------------------------------------------------------------------ linearisation
 // Per point: residuals (float64), robust weights, V = J_p^T M J_p (T products accumulated in
@@ -186,7 +207,7 @@ void launch_point_damp(hipStream_t s, int Pa, double lam, double dmin, double dm
 // Per camera slot: U = J_c^T M J_c, gc, b = rhs_c - sum W hp, S_cc = U* - sum W Vinv W^T and
 // its inverse (Cholesky, float64). rhs_c = -gc when rhs_c == nullptr. SoA outputs.
 template <typename T>
-void launch_cam_assemble(hipStream_t s, bool adj, const Model& m, const Compact<T>& cp,
+void launch_cam_assemble(hipStream_t s, bool adj, int D, const Model& m, const Compact<T>& cp,
                          ObsMetric<T> om, double lam, double dmin, double dmax,
                          const PtRec<T>* prec, const double* rhs_c, double* Uraw, T* Ustar,
                          double* gc, double* b, double* Minv);
@@ -194,9 +215,11 @@ void launch_cam_assemble(hipStream_t s, bool adj, const Model& m, const Compact<
 // ------------------------------------------------------------------ PCG on S
 // x = 0, r = b, u = M^-1 r (also into the matvec records), p = s = 0.
 template <typename T>
-void launch_pcg_init(hipStream_t s, int Ca, const double* b, const double* Minv, double* x,
-                     double* r, double* u, double* p, double* sv, MvCam<T>* mvt, PcgState* st,
-                     double tol2, int max_iter);
+void launch_pcg_init(hipStream_t s, int D, int Ca, const double* b, const double* Minv,
+                     double* x, double* r, double* u, double* p, double* sv, void* mvt,
+                     PcgState* st, double tol2, int max_iter);
+// Camera-side launchers take the camera dimension D: 6 (pose) or 7 (pose and focal length,
+// matvec records MvCamF); the adjoint mode runs with D = 6 only.
 // Device figures the launchers size persistent grids and LDS tables with.
 struct DevLimits {
   int n_cu = 0;            // compute units
@@ -208,44 +231,47 @@ struct DevLimits {
 // camera-major position of every observation of p in a solve camera (zq_cm, Nc entries).
 // When the Ca matvec records fit in LDS, a persistent grid stages them there.
 template <typename T>
-void launch_schur_point(hipStream_t s, bool adj, int G, const Model& m, const Compact<T>& cp,
-                        ObsMetric<T> om, const MvCam<T>* mvt, const T* Vinv, P3<T>* zq_cm,
-                        const PcgState* st, const DevLimits& dl);
+void launch_schur_point(hipStream_t s, bool adj, int D, int G, const Model& m,
+                        const Compact<T>& cp, ObsMetric<T> om, const void* mvt, const T* Vinv,
+                        P3<T>* zq_cm, const PcgState* st, const DevLimits& dl);
 // Camera-major pass, one workgroup per camera slot: w_s = U*_s u_s - sum_k W_k z_k with z
 // streamed in camera-major order, and the camera's terms of r.u, w.u and r.r (dots: 3
 // arrays of Ca, SoA).
 template <typename T>
-void launch_schur_cam(hipStream_t s, bool adj, const Model& m, const Compact<T>& cp,
+void launch_schur_cam(hipStream_t s, bool adj, int D, const Model& m, const Compact<T>& cp,
                       ObsMetric<T> om, const T* Ustar, const double* u, const double* r,
                       const P3<T>* zq, double* w, double* dots, const PcgState* st);
 // Fused reduction of the per-camera dots, convergence test, then p = u + beta p,
 // s = w + beta s, x += alpha p, r -= alpha s, u = M^-1 r.
 template <typename T>
-void launch_pcg_update(hipStream_t s, int Ca, int k, const double* Minv, const double* dots,
-                       double* x, double* r, double* u, double* p, double* sv, const double* w,
-                       MvCam<T>* mvt, PcgState* st);
+void launch_pcg_update(hipStream_t s, int D, int Ca, int k, const double* Minv,
+                       const double* dots, double* x, double* r, double* u, double* p,
+                       double* sv, const double* w, void* mvt, PcgState* st);
 // dp = Vinv (rhs_p - sum_k W_k^T x_c), rhs_p = -gp when nullptr.
 template <typename T>
-void launch_backsub(hipStream_t s, bool adj, int G, const Model& m, const Compact<T>& cp,
+void launch_backsub(hipStream_t s, bool adj, int D, int G, const Model& m, const Compact<T>& cp,
                     ObsMetric<T> om, const T* Vinv, const double* x, const double* gp,
                     const double* rhs_p, double* dp);
 
 // ------------------------------------------------------------------ candidate
 // Candidate camera table over all slots (retracted for s < Ca, copied for fixed slots).
-void launch_cam_candidate(hipStream_t s, int Ca, int Cf, const int* cam_src, const double* x,
-                          const double* cams, const Cam<double>* camd_hat, double* cand_cams,
-                          Cam<double>* cand_tab);
+// (D = 7: the focal length of the candidate is f + x_f)
+void launch_cam_candidate(hipStream_t s, int Ca, int Cf, int D, const int* cam_src,
+                          const double* x, const double* cams, const Cam<double>* camd_hat,
+                          double* cand_cams, Cam<double>* cand_tab);
 template <typename T>
-void launch_point_candidate(hipStream_t s, const Model& m, const Compact<T>& cp,
+void launch_point_candidate(hipStream_t s, const Model& m, const Compact<T>& cp, int D,
                             const Cam<double>* cand_tab, const double* x, const double* dp,
                             const double* gp, const T* w, double* Xcand, double* partials);
 // Sums per-block partials (K doubles per block) in a fixed order; with gc != nullptr also
-// out[K] = gc . x over 6 Ca values and out[K + 1] = max |gc|.
+// out[K] = gc . x over the ncu camera unknowns and out[K + 1] = max |gc|.
 void launch_reduce_partials(hipStream_t s, int nblocks, int K, const double* partials,
-                            unsigned max_mask, int Ca, const double* gc, const double* x,
+                            unsigned max_mask, int ncu, const double* gc, const double* x,
                             double* out);
+// Accepted candidate into the full arrays; intr != nullptr also takes the refined focal.
 void launch_scatter(hipStream_t s, int Pa, int Ca, const int* pt_src, const double* Xcand,
-                    const int* cam_src, const double* cand_cams, double* pts, double* cams);
+                    const int* cam_src, const double* cand_cams, const Cam<double>* cand_tab,
+                    double* pts, double* cams, double* intr);
 
 // ------------------------------------------------------------------ adjoint
 // rhs for the adjoint solve: tangent-mapped camera gradients (SoA) and point gradients, both

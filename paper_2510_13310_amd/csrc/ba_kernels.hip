@@ -16,6 +16,7 @@
 #include <hip/hip_ext.h>
 
 #include <cmath>
+#include <type_traits>
 
 namespace iba {
 namespace {
@@ -85,10 +86,12 @@ __device__ __forceinline__ void block_sum(T (&v)[K], T* smem) {
 }
 
 // ------------------------------------------------------------------ small linear algebra
-// Symmetric 6x6 stored as the upper triangle, row-major (21 values).
-__host__ __device__ constexpr int sym6(int i, int j) {
-  return i <= j ? i * 6 - (i * (i - 1)) / 2 + (j - i) : j * 6 - (j * (j - 1)) / 2 + (i - j);
+// Symmetric D x D stored as the upper triangle, row-major (D (D + 1) / 2 values).
+template <int D>
+__host__ __device__ constexpr int symd(int i, int j) {
+  return i <= j ? i * D - (i * (i - 1)) / 2 + (j - i) : j * D - (j * (j - 1)) / 2 + (i - j);
 }
+__host__ __device__ constexpr int sym6(int i, int j) { return symd<6>(i, j); }
 // Symmetric 3x3: [00, 01, 02, 11, 12, 22].
 __host__ __device__ constexpr int sym3(int i, int j) {
   return i <= j ? i * 3 - (i * (i - 1)) / 2 + (j - i) : j * 3 - (j * (j - 1)) / 2 + (i - j);
@@ -509,15 +512,15 @@ k_compact_obs(int64_t N, const uint8_t* __restrict__ vrow, const int* __restrict
 }
 
 
-template <typename T>
+template <typename T, int D>
 __global__ void __launch_bounds__(kBlock)
-k_mv_table(int n, const Cam<double>* __restrict__ camd_hat, MvCam<T>* __restrict__ mvt) {
+k_mv_table(int n, const Cam<double>* __restrict__ camd_hat, MvRec<T, D>* __restrict__ mvt) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
-  MvCam<T> v;
+  MvRec<T, D> v{};
   for (int i = 0; i < 9; ++i) v.R[i] = T(camd_hat[s].R[i]);
   v.f = T(camd_hat[s].f);
-  for (int i = 0; i < 6; ++i) v.u[i] = T(0);
+  for (int i = 0; i < D; ++i) v.u[i] = T(0);
   mvt[s] = v;
 }
 
@@ -689,58 +692,60 @@ k_point_damp(int Pa, double lam, double dmin, double dmax, const double* __restr
   prec[r] = rec;
 }
 
-// 6x6 SPD inverse through Cholesky (float64); returns false if not positive definite.
-__device__ bool spd6_inverse(const double* A21, double* out21) {
-  double L[6][6];
-  for (int i = 0; i < 6; ++i)
-    for (int j = 0; j < 6; ++j) L[i][j] = 0.0;
-  for (int j = 0; j < 6; ++j) {
-    double d = A21[sym6(j, j)];
+// D x D SPD inverse through Cholesky (float64); returns false if not positive definite.
+template <int D>
+__device__ bool spd_inverse(const double* A, double* out) {
+  double L[D][D];
+  for (int i = 0; i < D; ++i)
+    for (int j = 0; j < D; ++j) L[i][j] = 0.0;
+  for (int j = 0; j < D; ++j) {
+    double d = A[symd<D>(j, j)];
     for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
     if (!(d > 0.0) || !isfinite(d)) return false;
     const double ljj = sqrt(d);
     L[j][j] = ljj;
-    for (int i = j + 1; i < 6; ++i) {
-      double s = A21[sym6(i, j)];
+    for (int i = j + 1; i < D; ++i) {
+      double s = A[symd<D>(i, j)];
       for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
       L[i][j] = s / ljj;
     }
   }
   // inverse of L (lower triangular), then A^-1 = L^-T L^-1
-  double Li[6][6];
-  for (int i = 0; i < 6; ++i)
-    for (int j = 0; j < 6; ++j) Li[i][j] = 0.0;
-  for (int j = 0; j < 6; ++j) {
+  double Li[D][D];
+  for (int i = 0; i < D; ++i)
+    for (int j = 0; j < D; ++j) Li[i][j] = 0.0;
+  for (int j = 0; j < D; ++j) {
     Li[j][j] = 1.0 / L[j][j];
-    for (int i = j + 1; i < 6; ++i) {
+    for (int i = j + 1; i < D; ++i) {
       double s = 0.0;
       for (int k = j; k < i; ++k) s += L[i][k] * Li[k][j];
       Li[i][j] = -s / L[i][i];
     }
   }
-  for (int i = 0; i < 6; ++i)
-    for (int j = i; j < 6; ++j) {
+  for (int i = 0; i < D; ++i)
+    for (int j = i; j < D; ++j) {
       double s = 0.0;
-      for (int k = j; k < 6; ++k) s += Li[k][i] * Li[k][j];
-      out21[sym6(i, j)] = s;
+      for (int k = j; k < D; ++k) s += Li[k][i] * Li[k][j];
+      out[symd<D>(i, j)] = s;
     }
   return true;
 }
 
 
-template <typename T, bool ADJ>
+template <typename T, bool ADJ, int D>
 __global__ void __launch_bounds__(kBlock)
 k_cam_assemble(Model m, Compact<T> cp, ObsMetric<T> om, double lam, double dmin, double dmax,
                const PtRec<T>* __restrict__ prec,
                const double* __restrict__ rhs_c, double* __restrict__ Uraw,
                T* __restrict__ Ustar, double* __restrict__ gc, double* __restrict__ b,
                double* __restrict__ Minv) {
-  constexpr int K = 21 + 21 + 6 + 6;
+  constexpr int NS = sym_count(D);
+  constexpr int K = NS + NS + D + D;
   __shared__ double smem[K * (kBlock / kWave)];
   const int s = blockIdx.x;
   const int Ca = cp.Ca;
   const Cam<double> cm = cp.camd[s];
-  double acc[K];   // U (21), S = sum W Vinv W^T (21), gc (6), sum W hp (6)
+  double acc[K];   // U (NS), S = sum W Vinv W^T (NS), gc (D), sum W hp (D)
 #pragma unroll
   for (int i = 0; i < K; ++i) acc[i] = 0.0;
   for (int i = cp.cm_off[s] + threadIdx.x; i < cp.cm_off[s + 1]; i += blockDim.x) {
@@ -754,30 +759,35 @@ k_cam_assemble(Model m, Compact<T> cp, ObsMetric<T> om, double lam, double dmin,
     AMat<T, ADJ> A;
     A.set(T(cm.f), T(m.lam_d), Xt);
     if constexpr (ADJ) A.project(om.cm_eh + 3 * i);
-    T U[21], W[18];
+    T U[NS], W[3 * D];
 #pragma unroll
-    for (int q = 0; q < 21; ++q) U[q] = T(0);
+    for (int q = 0; q < NS; ++q) U[q] = T(0);
 #pragma unroll
-    for (int q = 0; q < 18; ++q) W[q] = T(0);
-    double g6[6] = {0, 0, 0, 0, 0, 0};
+    for (int q = 0; q < 3 * D; ++q) W[q] = T(0);
+    double g6[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) g6[q] = 0.0;
+    // de/df of the pinhole rows (focal length as the seventh unknown)
+    const T fcol[3] = {Xt[0] / Xt[2], Xt[1] / Xt[2], T(0)};
 #pragma unroll
     for (int row = 0; row < 3; ++row) {
-      T a[3], jc[6], jp[3];
+      T a[3], jc[D], jp[3];
       A.row(row, a);
       jc[0] = a[0]; jc[1] = a[1]; jc[2] = a[2];
       cross3(Xt, a, jc + 3);
+      if constexpr (D == 7) jc[6] = fcol[row];
       rot_tmul(cm, a, jp);
 #pragma unroll
-      for (int p = 0; p < 6; ++p) {
+      for (int p = 0; p < D; ++p) {
 #pragma unroll
-        for (int q = p; q < 6; ++q) U[sym6(p, q)] += wt * jc[p] * jc[q];
+        for (int q = p; q < D; ++q) U[symd<D>(p, q)] += wt * jc[p] * jc[q];
 #pragma unroll
         for (int q = 0; q < 3; ++q) W[3 * p + q] += wt * jc[p] * jp[q];
       }
       if constexpr (!ADJ) {
         const double we = double(wt) * e[row];
 #pragma unroll
-        for (int p = 0; p < 6; ++p) g6[p] += we * double(jc[p]);
+        for (int p = 0; p < D; ++p) g6[p] += we * double(jc[p]);
       }
     }
     // W Vinv W^T and W hp
@@ -785,93 +795,95 @@ k_cam_assemble(Model m, Compact<T> cp, ObsMetric<T> om, double lam, double dmin,
 #pragma unroll
     for (int q = 0; q < 6; ++q) vi[q] = pr.vinv[q];
     const double h0 = pr.hp[0], h1 = pr.hp[1], h2 = pr.hp[2];
-    T WV[18];
+    T WV[3 * D];
 #pragma unroll
-    for (int p = 0; p < 6; ++p) {
+    for (int p = 0; p < D; ++p) {
 #pragma unroll
       for (int q = 0; q < 3; ++q)
         WV[3 * p + q] = W[3 * p] * vi[sym3(0, q)] + W[3 * p + 1] * vi[sym3(1, q)] +
                         W[3 * p + 2] * vi[sym3(2, q)];
-      acc[42 + p] += g6[p];
-      acc[48 + p] += double(W[3 * p]) * h0 + double(W[3 * p + 1]) * h1 + double(W[3 * p + 2]) * h2;
+      acc[2 * NS + p] += g6[p];
+      acc[2 * NS + D + p] +=
+          double(W[3 * p]) * h0 + double(W[3 * p + 1]) * h1 + double(W[3 * p + 2]) * h2;
     }
 #pragma unroll
-    for (int p = 0; p < 6; ++p) {
+    for (int p = 0; p < D; ++p) {
 #pragma unroll
-      for (int q = p; q < 6; ++q) {
-        acc[sym6(p, q)] += double(U[sym6(p, q)]);
-        acc[21 + sym6(p, q)] += double(WV[3 * p] * W[3 * q] + WV[3 * p + 1] * W[3 * q + 1] +
-                                       WV[3 * p + 2] * W[3 * q + 2]);
+      for (int q = p; q < D; ++q) {
+        acc[symd<D>(p, q)] += double(U[symd<D>(p, q)]);
+        acc[NS + symd<D>(p, q)] += double(WV[3 * p] * W[3 * q] + WV[3 * p + 1] * W[3 * q + 1] +
+                                          WV[3 * p + 2] * W[3 * q + 2]);
       }
     }
   }
   block_sum<double, K>(acc, smem);
   if (threadIdx.x != 0) return;
-  double Us[21], Sc[21];
+  double Us[NS], Sc[NS];
 #pragma unroll
-  for (int q = 0; q < 21; ++q) {
-    Uraw[21 * s + q] = acc[q];
+  for (int q = 0; q < NS; ++q) {
+    Uraw[NS * s + q] = acc[q];
     Us[q] = acc[q];
   }
 #pragma unroll
-  for (int p = 0; p < 6; ++p) {
-    const int d = sym6(p, p);
+  for (int p = 0; p < D; ++p) {
+    const int d = symd<D>(p, p);
     Us[d] += lam * fmin(fmax(acc[d], dmin), dmax);
   }
 #pragma unroll
-  for (int q = 0; q < 21; ++q) {
+  for (int q = 0; q < NS; ++q) {
     Ustar[q * Ca + s] = T(Us[q]);
-    Sc[q] = Us[q] - acc[21 + q];
+    Sc[q] = Us[q] - acc[NS + q];
   }
 #pragma unroll
-  for (int p = 0; p < 6; ++p) {
-    gc[p * Ca + s] = acc[42 + p];
-    const double rhs = rhs_c ? rhs_c[p * Ca + s] : -acc[42 + p];
-    b[p * Ca + s] = rhs - acc[48 + p];
+  for (int p = 0; p < D; ++p) {
+    gc[p * Ca + s] = acc[2 * NS + p];
+    const double rhs = rhs_c ? rhs_c[p * Ca + s] : -acc[2 * NS + p];
+    b[p * Ca + s] = rhs - acc[2 * NS + D + p];
   }
-  double inv[21];
-  if (!spd6_inverse(Sc, inv)) {
+  double inv[NS];
+  if (!spd_inverse<D>(Sc, inv)) {
     // block not positive definite (rounding at tiny damping): Jacobi fallback on U*
 #pragma unroll
-    for (int q = 0; q < 21; ++q) inv[q] = 0.0;
+    for (int q = 0; q < NS; ++q) inv[q] = 0.0;
 #pragma unroll
-    for (int p = 0; p < 6; ++p) {
-      const double d = Us[sym6(p, p)];
-      inv[sym6(p, p)] = d > 0.0 ? 1.0 / d : 0.0;
+    for (int p = 0; p < D; ++p) {
+      const double d = Us[symd<D>(p, p)];
+      inv[symd<D>(p, p)] = d > 0.0 ? 1.0 / d : 0.0;
     }
   }
 #pragma unroll
-  for (int q = 0; q < 21; ++q) Minv[q * Ca + s] = inv[q];
+  for (int q = 0; q < NS; ++q) Minv[q * Ca + s] = inv[q];
 }
 
 // ------------------------------------------------------------------ PCG
-// y = M x for a symmetric 6x6 block stored SoA (21 arrays of length Ca).
-__device__ __forceinline__ void sym6_mul_soa(const double* M, int Ca, int s, const double* x,
+// y = M x for a symmetric D x D block stored SoA (D (D + 1) / 2 arrays of length Ca).
+template <int D>
+__device__ __forceinline__ void symd_mul_soa(const double* M, int Ca, int s, const double* x,
                                              double* y) {
-  double m[21];
+  double m[sym_count(D)];
 #pragma unroll
-  for (int k = 0; k < 21; ++k) m[k] = M[k * Ca + s];
+  for (int k = 0; k < sym_count(D); ++k) m[k] = M[k * Ca + s];
 #pragma unroll
-  for (int i = 0; i < 6; ++i) {
+  for (int i = 0; i < D; ++i) {
     double a = 0.0;
 #pragma unroll
-    for (int j = 0; j < 6; ++j) a += m[sym6(i, j)] * x[j];
+    for (int j = 0; j < D; ++j) a += m[symd<D>(i, j)] * x[j];
     y[i] = a;
   }
 }
 
-template <typename T>
+template <typename T, int D>
 __global__ void __launch_bounds__(1024)
 k_pcg_init(int Ca, const double* __restrict__ b, const double* __restrict__ Minv,
            double* __restrict__ x, double* __restrict__ r, double* __restrict__ u,
-           double* __restrict__ p, double* __restrict__ sv, MvCam<T>* __restrict__ mvt,
+           double* __restrict__ p, double* __restrict__ sv, MvRec<T, D>* __restrict__ mvt,
            PcgState* st, double tol2, int max_iter) {
   __shared__ double smem[1024 / kWave];
   double acc[1] = {0.0};   // b.b
   for (int s = threadIdx.x; s < Ca; s += blockDim.x) {
-    double rv[6], uv[6];
+    double rv[D], uv[D];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) {
+    for (int i = 0; i < D; ++i) {
       rv[i] = b[i * Ca + s];
       x[i * Ca + s] = 0.0;
       r[i * Ca + s] = rv[i];
@@ -879,9 +891,9 @@ k_pcg_init(int Ca, const double* __restrict__ b, const double* __restrict__ Minv
       sv[i * Ca + s] = 0.0;
       acc[0] += rv[i] * rv[i];
     }
-    sym6_mul_soa(Minv, Ca, s, rv, uv);
+    symd_mul_soa<D>(Minv, Ca, s, rv, uv);
 #pragma unroll
-    for (int i = 0; i < 6; ++i) {
+    for (int i = 0; i < D; ++i) {
       u[i * Ca + s] = uv[i];
       mvt[s].u[i] = T(uv[i]);
     }
@@ -911,10 +923,10 @@ k_pcg_init(int Ca, const double* __restrict__ b, const double* __restrict__ Minv
 // The point's z = Vinv y is then stored at the camera-major position of each of its
 // observations, so that the camera pass streams z instead of gathering it.
 // Every lane of a wave must call this together (shuffles); lanes with r >= rend do nothing.
-template <typename T, bool ADJ, int G>
+template <typename T, bool ADJ, int G, int D>
 __device__ __forceinline__ void schur_point_one(const Model& m, const Compact<T>& cp,
                                                 const ObsMetric<T>& om,
-                                                const MvCam<T>* __restrict__ tab,
+                                                const MvRec<T, D>* __restrict__ tab,
                                                 const T* __restrict__ Vinv,
                                                 P3<T>* __restrict__ zq_cm, int r, int rend,
                                                 int l) {
@@ -936,7 +948,7 @@ __device__ __forceinline__ void schur_point_one(const Model& m, const Compact<T>
       const int s = cp.cam[j];
       if (s >= cp.Ca) continue;   // fixed camera: no column in the solve
       const V4<T> xw = om.pm_xcw[j];
-      const MvCam<T> mc = tab[s];
+      const MvRec<T, D> mc = tab[s];
       const T Xc[3] = {xw.x, xw.y, xw.z};
       AMat<T, ADJ> A;
       A.set(mc.f, T(m.lam_d), Xc);
@@ -948,6 +960,11 @@ __device__ __forceinline__ void schur_point_one(const Model& m, const Compact<T>
       d[1] = mc.u[1] + o3[1];
       d[2] = mc.u[2] + o3[2];
       A.apply(d, tt);
+      if constexpr (D == 7) {   // focal column (x/z, y/z, 0) times the focal unknown
+        const T uf = mc.u[6] / Xc[2];
+        tt[0] += Xc[0] * uf;
+        tt[1] += Xc[1] * uf;
+      }
       A.applyT(tt, mm);
       mm[0] *= xw.w; mm[1] *= xw.w; mm[2] *= xw.w;
       // R^T m
@@ -985,16 +1002,16 @@ __device__ __forceinline__ void schur_point_one(const Model& m, const Compact<T>
 // The grid is a multiple of 8 and consecutive workgroups go to the 8 XCDs in turn; each XCD
 // takes one contiguous eighth of the point ranks, so the z stores of one XCD fill whole
 // cache lines of every camera segment (segments are sorted by point rank) in its own L2.
-template <typename T, bool ADJ, int G>
+template <typename T, bool ADJ, int G, int D>
 __global__ void __launch_bounds__(kBlock)
-k_schur_point(Model m, Compact<T> cp, ObsMetric<T> om, const MvCam<T>* __restrict__ mvt,
+k_schur_point(Model m, Compact<T> cp, ObsMetric<T> om, const MvRec<T, D>* __restrict__ mvt,
               const T* __restrict__ Vinv, P3<T>* __restrict__ zq_cm,
               const PcgState* __restrict__ st) {
   if (st->done) return;
   const int per = gridDim.x / 8;
   const int blk = (blockIdx.x % 8) * per + blockIdx.x / 8;
   const int t = blk * blockDim.x + threadIdx.x;
-  schur_point_one<T, ADJ, G>(m, cp, om, mvt, Vinv, zq_cm, t / G, cp.Pa, t % G);
+  schur_point_one<T, ADJ, G, D>(m, cp, om, mvt, Vinv, zq_cm, t / G, cp.Pa, t % G);
 }
 
 // Persistent variant for tables that fit in LDS: a few 1024-thread workgroups per CU each
@@ -1004,18 +1021,18 @@ k_schur_point(Model m, Compact<T> cp, ObsMetric<T> om, const MvCam<T>* __restric
 // stores into each camera segment fill whole cache lines while they are in its L2.
 constexpr int kPtLdsBlock = 1024;
 
-template <typename T, bool ADJ, int G>
+template <typename T, bool ADJ, int G, int D>
 __global__ void __launch_bounds__(kPtLdsBlock)
-k_schur_point_lds(Model m, Compact<T> cp, ObsMetric<T> om, const MvCam<T>* __restrict__ mvt,
+k_schur_point_lds(Model m, Compact<T> cp, ObsMetric<T> om, const MvRec<T, D>* __restrict__ mvt,
                   const T* __restrict__ Vinv, P3<T>* __restrict__ zq_cm,
                   const PcgState* __restrict__ st, int ppx) {
   extern __shared__ uint4 lds_tab[];   // cp.Ca records
   if (st->done) return;
-  const int nchunk = cp.Ca * int(sizeof(MvCam<T>) / sizeof(uint4));
+  const int nchunk = cp.Ca * int(sizeof(MvRec<T, D>) / sizeof(uint4));
   const uint4* src = reinterpret_cast<const uint4*>(mvt);
   for (int i = threadIdx.x; i < nchunk; i += kPtLdsBlock) lds_tab[i] = src[i];
   __syncthreads();
-  const MvCam<T>* tab = reinterpret_cast<const MvCam<T>*>(lds_tab);
+  const MvRec<T, D>* tab = reinterpret_cast<const MvRec<T, D>*>(lds_tab);
   const int per = gridDim.x / 8;            // workgroups per XCD
   const int xcd = blockIdx.x % 8;
   const int j = blockIdx.x / 8;
@@ -1023,8 +1040,8 @@ k_schur_point_lds(Model m, Compact<T> cp, ObsMetric<T> om, const MvCam<T>* __res
   const int hi = min(cp.Pa, lo + ppx);
   constexpr int tile = kPtLdsBlock / G;
   for (int base = lo + j * tile; base < hi; base += per * tile)
-    schur_point_one<T, ADJ, G>(m, cp, om, tab, Vinv, zq_cm, base + int(threadIdx.x) / G, hi,
-                               int(threadIdx.x) % G);
+    schur_point_one<T, ADJ, G, D>(m, cp, om, tab, Vinv, zq_cm, base + int(threadIdx.x) / G, hi,
+                                  int(threadIdx.x) % G);
 }
 
 // Camera-major pass of S u, one 1024-thread workgroup per camera slot:
@@ -1032,7 +1049,7 @@ k_schur_point_lds(Model m, Compact<T> cp, ObsMetric<T> om, const MvCam<T>* __res
 // Per observation two streamed 4-vectors: (X_c, w) and z (stored by the point pass).
 constexpr int kCamBlock = 512;   // 4 workgroups per CU: ~1000 cameras in one round
 
-template <typename T, bool ADJ>
+template <typename T, bool ADJ, int D>
 __global__ void __launch_bounds__(kCamBlock)
 k_schur_cam(Model m, Compact<T> cp, ObsMetric<T> om, const T* __restrict__ Ustar,
             const double* __restrict__ u, const double* __restrict__ r,
@@ -1046,16 +1063,19 @@ k_schur_cam(Model m, Compact<T> cp, ObsMetric<T> om, const T* __restrict__ Ustar
   const int s = (blockIdx.x % 8) * per + blockIdx.x / 8;
   const int Ca = cp.Ca;
   if (s >= Ca) return;
-  __shared__ T smem[6 * (kCamBlock / kWave)];
-  __shared__ double tail[33];   // U*_s (21), u_s (6), r_s (6), loaded while the stream runs
-  if (threadIdx.x < 21)
+  constexpr int NS = sym_count(D);
+  __shared__ T smem[D * (kCamBlock / kWave)];
+  __shared__ double tail[NS + 2 * D];   // U*_s, u_s, r_s, loaded while the stream runs
+  if (threadIdx.x < NS)
     tail[threadIdx.x] = double(Ustar[threadIdx.x * Ca + s]);
-  else if (threadIdx.x < 27)
-    tail[threadIdx.x] = u[(threadIdx.x - 21) * Ca + s];
-  else if (threadIdx.x < 33)
-    tail[threadIdx.x] = r[(threadIdx.x - 27) * Ca + s];
+  else if (threadIdx.x < NS + D)
+    tail[threadIdx.x] = u[(threadIdx.x - NS) * Ca + s];
+  else if (threadIdx.x < NS + 2 * D)
+    tail[threadIdx.x] = r[(threadIdx.x - NS - D) * Ca + s];
   const Cam<T> cm = cp.camt[s];
-  T acc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+  T acc[D];
+#pragma unroll
+  for (int q = 0; q < D; ++q) acc[q] = T(0);
   const int end = cp.cm_off[s + 1];
 #pragma unroll 2
   for (int i = cp.cm_off[s] + threadIdx.x; i < end; i += blockDim.x) {
@@ -1070,23 +1090,25 @@ k_schur_cam(Model m, Compact<T> cp, ObsMetric<T> om, const T* __restrict__ Ustar
     rot_mul(cm, z3, uu);
     A.apply(uu, t);
     A.applyT(t, mm);
+    if constexpr (D == 7)   // focal column: w (x/z, y/z, 0) . t
+      acc[6] += xw.w * (Xc[0] * t[0] + Xc[1] * t[1]) / Xc[2];
     mm[0] *= xw.w; mm[1] *= xw.w; mm[2] *= xw.w;
     cross3(Xc, mm, xm);
     acc[0] += mm[0]; acc[1] += mm[1]; acc[2] += mm[2];
     acc[3] += xm[0]; acc[4] += xm[1]; acc[5] += xm[2];
   }
-  block_sum<T, 6>(acc, smem);   // its barriers also publish tail[]
+  block_sum<T, D>(acc, smem);   // its barriers also publish tail[]
   if (threadIdx.x != 0) return;
-  const double* uv = tail + 21;
+  const double* uv = tail + NS;
   double g = 0.0, d = 0.0, rr = 0.0;
 #pragma unroll
-  for (int i = 0; i < 6; ++i) {
+  for (int i = 0; i < D; ++i) {
     double a = 0.0;
 #pragma unroll
-    for (int j = 0; j < 6; ++j) a += tail[sym6(i, j)] * uv[j];
+    for (int j = 0; j < D; ++j) a += tail[symd<D>(i, j)] * uv[j];
     const double wi = a - double(acc[i]);
     w[i * Ca + s] = wi;
-    const double ri = tail[27 + i];
+    const double ri = tail[NS + D + i];
     g += ri * uv[i];
     d += wi * uv[i];
     rr += ri * ri;
@@ -1106,21 +1128,21 @@ k_schur_cam(Model m, Compact<T> cp, ObsMetric<T> om, const T* __restrict__ Ustar
 constexpr int kUpdBlock = 256;
 constexpr int kUpdCams = 64;
 
-template <typename T>
+template <typename T, int D>
 __global__ void __launch_bounds__(kUpdBlock)
 k_pcg_update(int Ca, int k, const double* __restrict__ Minv, const double* __restrict__ dots,
              double* __restrict__ x, double* __restrict__ r, double* __restrict__ u,
              double* __restrict__ p, double* __restrict__ sv, const double* __restrict__ w,
-             MvCam<T>* __restrict__ mvt, PcgState* st) {
+             MvRec<T, D>* __restrict__ mvt, PcgState* st) {
   __shared__ double smem[3 * (kUpdBlock / kWave)];
   __shared__ double s_bcast[2];
   __shared__ int s_go;
   const int s = blockIdx.x * kUpdCams + threadIdx.x;
   const bool own = threadIdx.x < kUpdCams && s < Ca;
-  double pv[6], wv[6], sv0[6], rv[6], uv[6], m[21];
+  double pv[D], wv[D], sv0[D], rv[D], uv[D], m[sym_count(D)];
   if (own) {
 #pragma unroll
-    for (int i = 0; i < 6; ++i) {
+    for (int i = 0; i < D; ++i) {
       pv[i] = p[i * Ca + s];
       wv[i] = w[i * Ca + s];
       sv0[i] = sv[i * Ca + s];
@@ -1128,7 +1150,7 @@ k_pcg_update(int Ca, int k, const double* __restrict__ Minv, const double* __res
       uv[i] = u[i * Ca + s];
     }
 #pragma unroll
-    for (int q = 0; q < 21; ++q) m[q] = Minv[q * Ca + s];
+    for (int q = 0; q < sym_count(D); ++q) m[q] = Minv[q * Ca + s];
   }
   double acc[3] = {0.0, 0.0, 0.0};   // gamma, delta, rho
   for (int c = threadIdx.x; c < Ca; c += kUpdBlock) {
@@ -1184,7 +1206,7 @@ k_pcg_update(int Ca, int k, const double* __restrict__ Minv, const double* __res
   if (!s_go || !own) return;
   const double alpha = s_bcast[0], beta = s_bcast[1];
 #pragma unroll
-  for (int i = 0; i < 6; ++i) {
+  for (int i = 0; i < D; ++i) {
     const double pi = uv[i] + beta * pv[i];
     const double si = wv[i] + beta * sv0[i];
     p[i * Ca + s] = pi;
@@ -1194,17 +1216,17 @@ k_pcg_update(int Ca, int k, const double* __restrict__ Minv, const double* __res
     r[i * Ca + s] = rv[i];
   }
 #pragma unroll
-  for (int i = 0; i < 6; ++i) {
+  for (int i = 0; i < D; ++i) {
     double a = 0.0;
 #pragma unroll
-    for (int j = 0; j < 6; ++j) a += m[sym6(i, j)] * rv[j];
+    for (int j = 0; j < D; ++j) a += m[symd<D>(i, j)] * rv[j];
     u[i * Ca + s] = a;
     mvt[s].u[i] = T(a);
   }
 }
 
 // Back-substitution dp = Vinv (rhs_p - sum_k W_k^T x_c), same lane layout as the point pass.
-template <typename T, bool ADJ, int G>
+template <typename T, bool ADJ, int G, int D>
 __global__ void __launch_bounds__(kBlock)
 k_backsub(Model m, Compact<T> cp, ObsMetric<T> om, const T* __restrict__ Vinv,
           const double* __restrict__ x, const double* __restrict__ gp,
@@ -1233,6 +1255,11 @@ k_backsub(Model m, Compact<T> cp, ObsMetric<T> om, const T* __restrict__ Vinv,
       d[1] = T(x[Ca + s]) + o3[1];
       d[2] = T(x[2 * Ca + s]) + o3[2];
       A.apply(d, tt);
+      if constexpr (D == 7) {   // focal column times the camera's focal step
+        const T uf = T(x[6 * Ca + s]) / Xc[2];
+        tt[0] += Xc[0] * uf;
+        tt[1] += Xc[1] * uf;
+      }
       A.applyT(tt, mm);
       const T w = om.w[j];
       mm[0] *= w; mm[1] *= w; mm[2] *= w;
@@ -1260,9 +1287,10 @@ k_backsub(Model m, Compact<T> cp, ObsMetric<T> om, const T* __restrict__ Vinv,
 // ------------------------------------------------------------------ candidate
 // Left SE(3) update of a (quaternion, centre) camera: q' = q(phi) (x) q, c' = c - R'^T V rho.
 __global__ void __launch_bounds__(kBlock)
-k_cam_candidate(int Ca, int Cf, const int* __restrict__ cam_src, const double* __restrict__ x,
-                const double* __restrict__ cams, const Cam<double>* __restrict__ camd_hat,
-                double* __restrict__ cand_cams, Cam<double>* __restrict__ cand_tab) {
+k_cam_candidate(int Ca, int Cf, int D, const int* __restrict__ cam_src,
+                const double* __restrict__ x, const double* __restrict__ cams,
+                const Cam<double>* __restrict__ camd_hat, double* __restrict__ cand_cams,
+                Cam<double>* __restrict__ cand_tab) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= Ca + Cf) return;
   if (s >= Ca) {             // fixed camera: unchanged
@@ -1314,6 +1342,7 @@ k_cam_candidate(int Ca, int Cf, const int* __restrict__ cam_src, const double* _
   d.c[0] = cams[7 * c + 4] - rv[0];
   d.c[1] = cams[7 * c + 5] - rv[1];
   d.c[2] = cams[7 * c + 6] - rv[2];
+  if (D == 7) d.f += x[6 * Ca + s];   // additive focal update
   cand_tab[s] = d;
   cand_cams[7 * s] = nw;
   cand_cams[7 * s + 1] = nx;
@@ -1331,7 +1360,7 @@ k_cam_candidate(int Ca, int Cf, const int* __restrict__ cam_src, const double* _
 // depths <= min_depth; and the candidate cost itself.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_point_candidate(Model m, Compact<T> cp, const Cam<double>* __restrict__ cand_tab,
+k_point_candidate(Model m, Compact<T> cp, int D, const Cam<double>* __restrict__ cand_tab,
                   const double* __restrict__ x, const double* __restrict__ dp,
                   const double* __restrict__ gp, const T* __restrict__ w,
                   double* __restrict__ Xcand, double* __restrict__ partials) {
@@ -1380,6 +1409,11 @@ k_point_candidate(Model m, Compact<T> cp, const Cam<double>* __restrict__ cand_t
       AMat<double, false> A;
       A.set(cm.f, m.lam_d, Xl);
       A.apply(v, t);
+      if (D == 7 && s < Ca) {   // focal column times the camera's focal step
+        const double uf = x[6 * Ca + s] / Xl[2];
+        t[0] += Xl[0] * uf;
+        t[1] += Xl[1] * uf;
+      }
       acc[1] += double(w[j]) * (t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
     }
   }
@@ -1392,7 +1426,7 @@ k_point_candidate(Model m, Compact<T> cp, const Cam<double>* __restrict__ cand_t
 
 __global__ void __launch_bounds__(1024)
 k_reduce_partials(int nb, int K, const double* __restrict__ partials, unsigned max_mask,
-                  int Ca, const double* __restrict__ gc, const double* __restrict__ x,
+                  int ncu, const double* __restrict__ gc, const double* __restrict__ x,
                   double* __restrict__ out) {
   constexpr int KM = 8;
   __shared__ double smem[KM * (1024 / kWave)];
@@ -1407,8 +1441,8 @@ k_reduce_partials(int nb, int K, const double* __restrict__ partials, unsigned m
   unsigned mask = max_mask;
   int nout = K;
   if (gc) {
-    // gc . x over the 6 Ca camera unknowns, and max |gc|
-    for (int e = threadIdx.x; e < 6 * Ca; e += blockDim.x) {
+    // gc . x over the ncu camera unknowns (D per camera, SoA), and max |gc|
+    for (int e = threadIdx.x; e < ncu; e += blockDim.x) {
       acc[K] += gc[e] * x[e];
       acc[K + 1] = fmax(acc[K + 1], fabs(gc[e]));
     }
@@ -1433,7 +1467,8 @@ k_reduce_partials(int nb, int K, const double* __restrict__ partials, unsigned m
 __global__ void __launch_bounds__(kBlock)
 k_scatter(int Pa, int Ca, const int* __restrict__ pt_src, const double* __restrict__ Xcand,
           const int* __restrict__ cam_src, const double* __restrict__ cand_cams,
-          double* __restrict__ pts, double* __restrict__ cams) {
+          const Cam<double>* __restrict__ cand_tab, double* __restrict__ pts,
+          double* __restrict__ cams, double* __restrict__ intr) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < Pa) {
     const int p = pt_src[i];
@@ -1444,6 +1479,7 @@ k_scatter(int Pa, int Ca, const int* __restrict__ pt_src, const double* __restri
   if (i < Ca) {
     const int c = cam_src[i];
     for (int k = 0; k < 7; ++k) cams[7 * c + k] = cand_cams[7 * i + k];
+    if (intr) intr[3 * c] = cand_tab[i].f;   // refined focal length
   }
 }
 
@@ -1641,165 +1677,193 @@ void launch_point_damp(hipStream_t s, int Pa, double lam, double dmin, double dm
            gp, rhs_p, Vinv, hp, prec, bad);
 }
 
+// Camera-dimension dispatch: D = 6 (pose) or 7 (pose and focal length); the adjoint mode
+// exists for D = 6 only (the host rejects the other combination).
+template <class F>
+void with_dim(int D, F&& f) {
+  if (D == 7)
+    f(std::integral_constant<int, 7>{});
+  else
+    f(std::integral_constant<int, 6>{});
+}
+
 template <typename T>
-void launch_cam_assemble(hipStream_t s, bool adj, const Model& m, const Compact<T>& cp,
+void launch_cam_assemble(hipStream_t s, bool adj, int D, const Model& m, const Compact<T>& cp,
                          ObsMetric<T> om, double lam, double dmin, double dmax,
                          const PtRec<T>* prec, const double* rhs_c, double* Uraw, T* Ustar,
                          double* gc, double* b, double* Minv) {
   if (cp.Ca == 0) return;
   if (adj)
-    launch_k((k_cam_assemble<T, true>), dim3(cp.Ca), dim3(kBlock), 0, s, m, cp, om, lam, dmin,
-             dmax, prec, rhs_c, Uraw, Ustar, gc, b, Minv);
+    launch_k((k_cam_assemble<T, true, 6>), dim3(cp.Ca), dim3(kBlock), 0, s, m, cp, om, lam,
+             dmin, dmax, prec, rhs_c, Uraw, Ustar, gc, b, Minv);
   else
-    launch_k((k_cam_assemble<T, false>), dim3(cp.Ca), dim3(kBlock), 0, s, m, cp, om, lam, dmin,
-             dmax, prec, rhs_c, Uraw, Ustar, gc, b, Minv);
+    with_dim(D, [&](auto Dc) {
+      launch_k((k_cam_assemble<T, false, Dc()>), dim3(cp.Ca), dim3(kBlock), 0, s, m, cp, om,
+               lam, dmin, dmax, prec, rhs_c, Uraw, Ustar, gc, b, Minv);
+    });
 }
 
 template <typename T>
-void launch_mv_table(hipStream_t s, int n, const Cam<double>* camd_hat, MvCam<T>* mvt) {
+void launch_mv_table(hipStream_t s, int D, int n, const Cam<double>* camd_hat, void* mvt) {
   if (n == 0) return;
-  launch_k(k_mv_table<T>, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, camd_hat, mvt);
+  with_dim(D, [&](auto Dc) {
+    launch_k(k_mv_table<T, Dc()>, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, camd_hat,
+             static_cast<MvRec<T, Dc()>*>(mvt));
+  });
 }
 
 template <typename T>
-void launch_pcg_init(hipStream_t s, int Ca, const double* b, const double* Minv, double* x,
-                     double* r, double* u, double* p, double* sv, MvCam<T>* mvt, PcgState* st,
-                     double tol2, int max_iter) {
-  launch_k(k_pcg_init<T>, dim3(1), dim3(1024), 0, s, Ca, b, Minv, x, r, u, p, sv, mvt,
-                     st, tol2, max_iter);
+void launch_pcg_init(hipStream_t s, int D, int Ca, const double* b, const double* Minv,
+                     double* x, double* r, double* u, double* p, double* sv, void* mvt,
+                     PcgState* st, double tol2, int max_iter) {
+  with_dim(D, [&](auto Dc) {
+    launch_k(k_pcg_init<T, Dc()>, dim3(1), dim3(1024), 0, s, Ca, b, Minv, x, r, u, p, sv,
+             static_cast<MvRec<T, Dc()>*>(mvt), st, tol2, max_iter);
+  });
 }
 
-template <typename T, bool ADJ, int G>
+template <typename T, bool ADJ, int G, int D>
 void schur_point_launch(hipStream_t s, const Model& m, const Compact<T>& cp, ObsMetric<T> om,
-                        const MvCam<T>* mvt, const T* Vinv, P3<T>* zq, const PcgState* st,
+                        const MvRec<T, D>* mvt, const T* Vinv, P3<T>* zq, const PcgState* st,
                         const DevLimits& dl) {
-  const size_t tab = size_t(cp.Ca) * sizeof(MvCam<T>);
+  const size_t tab = size_t(cp.Ca) * sizeof(MvRec<T, D>);
   bool use_lds = dl.n_cu > 0 && cp.Ca > 0 && tab <= size_t(dl.lds_per_block);
   if (use_lds && tab > 65536)
-    use_lds = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_schur_point_lds<T, ADJ, G>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  int(tab)) == hipSuccess;
+    use_lds = hipFuncSetAttribute(
+                  reinterpret_cast<const void*>(&k_schur_point_lds<T, ADJ, G, D>),
+                  hipFuncAttributeMaxDynamicSharedMemorySize, int(tab)) == hipSuccess;
   if (use_lds) {
     const int per_cu = 2 * tab <= size_t(dl.lds_per_cu) ? 2 : 1;
     const int grid = (dl.n_cu * per_cu + 7) / 8 * 8;
     const int ppx = (cp.Pa + 7) / 8;
-    launch_k(k_schur_point_lds<T, ADJ, G>, dim3(grid), dim3(kPtLdsBlock), uint32_t(tab), s, m,
-             cp, om, mvt, Vinv, zq, st, ppx);
+    launch_k(k_schur_point_lds<T, ADJ, G, D>, dim3(grid), dim3(kPtLdsBlock), uint32_t(tab), s,
+             m, cp, om, mvt, Vinv, zq, st, ppx);
   } else {
     const unsigned nb = (blocks_for(int64_t(cp.Pa) * G) + 7) / 8 * 8;   // one share per XCD
-    launch_k(k_schur_point<T, ADJ, G>, dim3(nb), dim3(kBlock), 0, s, m, cp, om, mvt, Vinv, zq,
-             st);
+    launch_k(k_schur_point<T, ADJ, G, D>, dim3(nb), dim3(kBlock), 0, s, m, cp, om, mvt, Vinv,
+             zq, st);
   }
 }
 
-template <typename T, bool ADJ>
+template <typename T, bool ADJ, int D>
 void schur_point_g(hipStream_t s, int G, const Model& m, const Compact<T>& cp, ObsMetric<T> om,
-                   const MvCam<T>* mvt, const T* Vinv, P3<T>* zq, const PcgState* st,
+                   const MvRec<T, D>* mvt, const T* Vinv, P3<T>* zq, const PcgState* st,
                    const DevLimits& dl) {
   switch (G) {
-    case 2: schur_point_launch<T, ADJ, 2>(s, m, cp, om, mvt, Vinv, zq, st, dl); break;
-    case 4: schur_point_launch<T, ADJ, 4>(s, m, cp, om, mvt, Vinv, zq, st, dl); break;
-    case 16: schur_point_launch<T, ADJ, 16>(s, m, cp, om, mvt, Vinv, zq, st, dl); break;
-    default: schur_point_launch<T, ADJ, 8>(s, m, cp, om, mvt, Vinv, zq, st, dl);
+    case 2: schur_point_launch<T, ADJ, 2, D>(s, m, cp, om, mvt, Vinv, zq, st, dl); break;
+    case 4: schur_point_launch<T, ADJ, 4, D>(s, m, cp, om, mvt, Vinv, zq, st, dl); break;
+    case 16: schur_point_launch<T, ADJ, 16, D>(s, m, cp, om, mvt, Vinv, zq, st, dl); break;
+    default: schur_point_launch<T, ADJ, 8, D>(s, m, cp, om, mvt, Vinv, zq, st, dl);
   }
 }
 
 template <typename T>
-void launch_schur_point(hipStream_t s, bool adj, int G, const Model& m, const Compact<T>& cp,
-                        ObsMetric<T> om, const MvCam<T>* mvt, const T* Vinv, P3<T>* zq,
-                        const PcgState* st, const DevLimits& dl) {
+void launch_schur_point(hipStream_t s, bool adj, int D, int G, const Model& m,
+                        const Compact<T>& cp, ObsMetric<T> om, const void* mvt, const T* Vinv,
+                        P3<T>* zq, const PcgState* st, const DevLimits& dl) {
   if (adj)
-    schur_point_g<T, true>(s, G, m, cp, om, mvt, Vinv, zq, st, dl);
+    schur_point_g<T, true, 6>(s, G, m, cp, om, static_cast<const MvRec<T, 6>*>(mvt), Vinv, zq,
+                              st, dl);
   else
-    schur_point_g<T, false>(s, G, m, cp, om, mvt, Vinv, zq, st, dl);
+    with_dim(D, [&](auto Dc) {
+      schur_point_g<T, false, Dc()>(s, G, m, cp, om, static_cast<const MvRec<T, Dc()>*>(mvt),
+                                    Vinv, zq, st, dl);
+    });
 }
 
 template <typename T>
-void launch_schur_cam(hipStream_t s, bool adj, const Model& m, const Compact<T>& cp,
+void launch_schur_cam(hipStream_t s, bool adj, int D, const Model& m, const Compact<T>& cp,
                       ObsMetric<T> om, const T* Ustar, const double* u, const double* r,
                       const P3<T>* zq, double* w, double* dots, const PcgState* st) {
   if (cp.Ca <= 0) return;
   const unsigned grid = unsigned((cp.Ca + 7) / 8 * 8);   // one share per XCD
   if (adj)
-    launch_k((k_schur_cam<T, true>), dim3(grid), dim3(kCamBlock), 0, s, m, cp, om,
-                       Ustar, u, r, zq, w, dots, st);
+    launch_k((k_schur_cam<T, true, 6>), dim3(grid), dim3(kCamBlock), 0, s, m, cp, om, Ustar,
+             u, r, zq, w, dots, st);
   else
-    launch_k((k_schur_cam<T, false>), dim3(grid), dim3(kCamBlock), 0, s, m, cp, om,
-                       Ustar, u, r, zq, w, dots, st);
+    with_dim(D, [&](auto Dc) {
+      launch_k((k_schur_cam<T, false, Dc()>), dim3(grid), dim3(kCamBlock), 0, s, m, cp, om,
+               Ustar, u, r, zq, w, dots, st);
+    });
 }
 
 template <typename T>
-void launch_pcg_update(hipStream_t s, int Ca, int k, const double* Minv, const double* dots,
-                       double* x, double* r, double* u, double* p, double* sv, const double* w,
-                       MvCam<T>* mvt, PcgState* st) {
+void launch_pcg_update(hipStream_t s, int D, int Ca, int k, const double* Minv,
+                       const double* dots, double* x, double* r, double* u, double* p,
+                       double* sv, const double* w, void* mvt, PcgState* st) {
   if (Ca <= 0) return;
-  launch_k(k_pcg_update<T>, dim3((Ca + kUpdCams - 1) / kUpdCams), dim3(kUpdBlock), 0,
-                     s, Ca, k, Minv, dots, x, r, u, p, sv, w, mvt, st);
+  with_dim(D, [&](auto Dc) {
+    launch_k(k_pcg_update<T, Dc()>, dim3((Ca + kUpdCams - 1) / kUpdCams), dim3(kUpdBlock), 0,
+             s, Ca, k, Minv, dots, x, r, u, p, sv, w, static_cast<MvRec<T, Dc()>*>(mvt), st);
+  });
 }
 
-template <typename T, bool ADJ>
+template <typename T, bool ADJ, int D>
 void backsub_g(hipStream_t s, int G, const Model& m, const Compact<T>& cp, ObsMetric<T> om,
                const T* Vinv, const double* x, const double* gp, const double* rhs_p,
                double* dp) {
   const unsigned nb = blocks_for(int64_t(cp.Pa) * G);
   switch (G) {
     case 2:
-      launch_k((k_backsub<T, ADJ, 2>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, Vinv,
-                         x, gp, rhs_p, dp);
+      launch_k((k_backsub<T, ADJ, 2, D>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, Vinv, x, gp,
+               rhs_p, dp);
       break;
     case 4:
-      launch_k((k_backsub<T, ADJ, 4>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, Vinv,
-                         x, gp, rhs_p, dp);
+      launch_k((k_backsub<T, ADJ, 4, D>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, Vinv, x, gp,
+               rhs_p, dp);
       break;
     case 16:
-      launch_k((k_backsub<T, ADJ, 16>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, Vinv,
-                         x, gp, rhs_p, dp);
+      launch_k((k_backsub<T, ADJ, 16, D>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, Vinv, x,
+               gp, rhs_p, dp);
       break;
     default:
-      launch_k((k_backsub<T, ADJ, 8>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, Vinv,
-                         x, gp, rhs_p, dp);
+      launch_k((k_backsub<T, ADJ, 8, D>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, Vinv, x, gp,
+               rhs_p, dp);
   }
 }
 
 template <typename T>
-void launch_backsub(hipStream_t s, bool adj, int G, const Model& m, const Compact<T>& cp,
+void launch_backsub(hipStream_t s, bool adj, int D, int G, const Model& m, const Compact<T>& cp,
                     ObsMetric<T> om, const T* Vinv, const double* x, const double* gp,
                     const double* rhs_p, double* dp) {
   if (adj)
-    backsub_g<T, true>(s, G, m, cp, om, Vinv, x, gp, rhs_p, dp);
+    backsub_g<T, true, 6>(s, G, m, cp, om, Vinv, x, gp, rhs_p, dp);
   else
-    backsub_g<T, false>(s, G, m, cp, om, Vinv, x, gp, rhs_p, dp);
+    with_dim(D, [&](auto Dc) {
+      backsub_g<T, false, Dc()>(s, G, m, cp, om, Vinv, x, gp, rhs_p, dp);
+    });
 }
 
-void launch_cam_candidate(hipStream_t s, int Ca, int Cf, const int* cam_src, const double* x,
-                          const double* cams, const Cam<double>* camd_hat, double* cand_cams,
-                          Cam<double>* cand_tab) {
+void launch_cam_candidate(hipStream_t s, int Ca, int Cf, int D, const int* cam_src,
+                          const double* x, const double* cams, const Cam<double>* camd_hat,
+                          double* cand_cams, Cam<double>* cand_tab) {
   if (Ca + Cf == 0) return;
-  launch_k(k_cam_candidate, dim3(blocks_for(Ca + Cf)), dim3(kBlock), 0, s, Ca, Cf,
-                     cam_src, x, cams, camd_hat, cand_cams, cand_tab);
+  launch_k(k_cam_candidate, dim3(blocks_for(Ca + Cf)), dim3(kBlock), 0, s, Ca, Cf, D, cam_src,
+           x, cams, camd_hat, cand_cams, cand_tab);
 }
 
 template <typename T>
-void launch_point_candidate(hipStream_t s, const Model& m, const Compact<T>& cp,
+void launch_point_candidate(hipStream_t s, const Model& m, const Compact<T>& cp, int D,
                             const Cam<double>* cand_tab, const double* x, const double* dp,
                             const double* gp, const T* w, double* Xcand, double* partials) {
-  launch_k(k_point_candidate<T>, dim3(blocks_for(cp.Pa)), dim3(kBlock), 0, s, m, cp,
-                     cand_tab, x, dp, gp, w, Xcand, partials);
+  launch_k(k_point_candidate<T>, dim3(blocks_for(cp.Pa)), dim3(kBlock), 0, s, m, cp, D,
+           cand_tab, x, dp, gp, w, Xcand, partials);
 }
 
 void launch_reduce_partials(hipStream_t s, int nblocks, int K, const double* partials,
-                            unsigned max_mask, int Ca, const double* gc, const double* x,
+                            unsigned max_mask, int ncu, const double* gc, const double* x,
                             double* out) {
-  launch_k(k_reduce_partials, dim3(1), dim3(1024), 0, s, nblocks, K, partials,
-                     max_mask, Ca, gc, x, out);
+  launch_k(k_reduce_partials, dim3(1), dim3(1024), 0, s, nblocks, K, partials, max_mask, ncu,
+           gc, x, out);
 }
 
 void launch_scatter(hipStream_t s, int Pa, int Ca, const int* pt_src, const double* Xcand,
-                    const int* cam_src, const double* cand_cams, double* pts, double* cams) {
+                    const int* cam_src, const double* cand_cams, const Cam<double>* cand_tab,
+                    double* pts, double* cams, double* intr) {
   const int n = Pa > Ca ? Pa : Ca;
   if (n == 0) return;
-  launch_k(k_scatter, dim3(blocks_for(n)), dim3(kBlock), 0, s, Pa, Ca, pt_src, Xcand,
-                     cam_src, cand_cams, pts, cams);
+  launch_k(k_scatter, dim3(blocks_for(n)), dim3(kBlock), 0, s, Pa, Ca, pt_src, Xcand, cam_src,
+           cand_cams, cand_tab, pts, cams, intr);
 }
 
 void launch_adjoint_rhs(hipStream_t s, int Ca, int Pa, const int* cam_src, const double* cams,
@@ -1826,26 +1890,27 @@ void launch_adjoint_obs(hipStream_t s, const Model& m, const Compact<T>& cp, Obs
   template void launch_point_damp<T>(hipStream_t, int, double, double, double, const double*, \
                                      const double*, const double*, T*, double*, PtRec<T>*,    \
                                      int*);                                                    \
-  template void launch_cam_assemble<T>(hipStream_t, bool, const Model&, const Compact<T>&,    \
-                                       ObsMetric<T>, double, double, double, const PtRec<T>*, \
-                                       const double*, double*, T*, double*, double*, double*); \
-  template void launch_mv_table<T>(hipStream_t, int, const Cam<double>*, MvCam<T>*);         \
-  template void launch_pcg_init<T>(hipStream_t, int, const double*, const double*, double*,   \
-                                   double*, double*, double*, double*, MvCam<T>*, PcgState*,  \
-                                   double, int);                                               \
-  template void launch_schur_point<T>(hipStream_t, bool, int, const Model&, const Compact<T>&,\
-                                      ObsMetric<T>, const MvCam<T>*, const T*, P3<T>*,        \
-                                      const PcgState*, const DevLimits&);                      \
-  template void launch_schur_cam<T>(hipStream_t, bool, const Model&, const Compact<T>&,       \
+  template void launch_cam_assemble<T>(hipStream_t, bool, int, const Model&,                  \
+                                       const Compact<T>&, ObsMetric<T>, double, double, double,\
+                                       const PtRec<T>*, const double*, double*, T*, double*,  \
+                                       double*, double*);                                      \
+  template void launch_mv_table<T>(hipStream_t, int, int, const Cam<double>*, void*);         \
+  template void launch_pcg_init<T>(hipStream_t, int, int, const double*, const double*,       \
+                                   double*, double*, double*, double*, double*, void*,        \
+                                   PcgState*, double, int);                                    \
+  template void launch_schur_point<T>(hipStream_t, bool, int, int, const Model&,              \
+                                      const Compact<T>&, ObsMetric<T>, const void*, const T*, \
+                                      P3<T>*, const PcgState*, const DevLimits&);              \
+  template void launch_schur_cam<T>(hipStream_t, bool, int, const Model&, const Compact<T>&,  \
                                     ObsMetric<T>, const T*, const double*, const double*,     \
                                     const P3<T>*, double*, double*, const PcgState*);         \
-  template void launch_pcg_update<T>(hipStream_t, int, int, const double*, const double*, double*, \
-                                     double*, double*, double*, double*, const double*,       \
-                                     MvCam<T>*, PcgState*);                                    \
-  template void launch_backsub<T>(hipStream_t, bool, int, const Model&, const Compact<T>&,    \
-                                  ObsMetric<T>, const T*, const double*, const double*,       \
-                                  const double*, double*);                                     \
-  template void launch_point_candidate<T>(hipStream_t, const Model&, const Compact<T>&,       \
+  template void launch_pcg_update<T>(hipStream_t, int, int, int, const double*, const double*,\
+                                     double*, double*, double*, double*, double*,             \
+                                     const double*, void*, PcgState*);                        \
+  template void launch_backsub<T>(hipStream_t, bool, int, int, const Model&,                  \
+                                  const Compact<T>&, ObsMetric<T>, const T*, const double*,   \
+                                  const double*, const double*, double*);                      \
+  template void launch_point_candidate<T>(hipStream_t, const Model&, const Compact<T>&, int,  \
                                           const Cam<double>*, const double*, const double*,   \
                                           const double*, const T*, double*, double*);         \
   template void launch_adjoint_obs<T>(hipStream_t, const Model&, const Compact<T>&,           \

@@ -25,12 +25,12 @@ def gpu_setup(sc, precision="fp64", **kw):
     return ba
 
 
-def full_delta(ex, delta, n_cams, n_points):
-    """Scatter an oracle compact step into full (C x 6, P x 3) arrays."""
-    nc = 6 * ex.cams.size
-    dc = np.zeros((n_cams, 6))
+def full_delta(ex, delta, n_cams, n_points, d=6):
+    """Scatter an oracle compact step into full (C x d, P x 3) arrays."""
+    nc = d * ex.cams.size
+    dc = np.zeros((n_cams, d))
     dp = np.zeros((n_points, 3))
-    dc[ex.cams] = delta[:nc].reshape(-1, 6)
+    dc[ex.cams] = delta[:nc].reshape(-1, d)
     dp[ex.pts] = delta[nc:].reshape(-1, 3)
     return dc, dp
 
