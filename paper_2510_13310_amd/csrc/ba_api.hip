@@ -139,7 +139,8 @@ struct ba_ctx {
   double *gp = nullptr, *hp = nullptr, *dp = nullptr, *Xcand = nullptr, *rhs_p = nullptr;
   double *Uraw = nullptr, *gc = nullptr, *b = nullptr, *Minv = nullptr, *rhs_c = nullptr;
   double *x = nullptr, *r = nullptr, *u = nullptr, *p = nullptr, *sv = nullptr,
-         *wv = nullptr, *dots = nullptr;
+         *wv = nullptr, *dots = nullptr, *part = nullptr;
+  int *item_off = nullptr, *item_cam = nullptr;   // camera-pass items
   double *partials = nullptr, *scal = nullptr;
   double *grad_cams_d = nullptr, *grad_pts_d = nullptr;
   float *gxy_d = nullptr, *gdepth_d = nullptr;
@@ -388,8 +389,11 @@ void alloc_obs_buffers(ba_ctx& c) {
   c.u = A.alloc<double>(nd * size_t(C));
   c.p = A.alloc<double>(nd * size_t(C));
   c.sv = A.alloc<double>(nd * size_t(C));
-  c.wv = A.alloc<double>(nd * size_t(C));
-  c.dots = A.alloc<double>(3 * size_t(C));
+  c.wv = A.alloc<double>(nd * size_t(C));          // U* u of the current PCG direction
+  c.dots = A.alloc<double>(2 * 3 * size_t(C));     // per-camera terms, two parities
+  c.part = A.alloc<double>((nd + 1) * (size_t(C) + kCamChunks));   // camera-pass partials
+  c.item_off = A.alloc<int>(size_t(C) + 1);
+  c.item_cam = A.alloc<int>(size_t(C) + kCamChunks);
   c.partials = A.alloc<double>(5 * (size_t(P) / kBlock + 16));
   c.scal = A.alloc<double>(16);
   c.pcg = A.alloc<PcgState>(1);
@@ -523,11 +527,24 @@ double bytes_schur_point(const ba_ctx& c) {
          double(c.Pa) * (4 + 6 * ts) + double(c.Ca) * 16 * ts;
 }
 // Camera pass: per observation the (X_c, w) 4-vector and the z 3-vector; per camera its
-// offsets, table entry, U*, u, r, and the w and dot terms written.
+// offset, table entry and u; per partial slot its D + 1 values written.
 double bytes_schur_cam(const ba_ctx& c) {
   const double ts = double(c.tsize());
+  const double D = c.D;
+  int K = 0, nch = 0;
+  cam_chunking(c.Nc, K, nch);
+  return double(c.Nc) * 7 * ts + double(c.Ca) * (4 + 15 * ts + D * 8) +
+         double(c.Ca + nch) * (D + 1) * 8;
+}
+// PCG update: per camera its terms (read and written), offsets, M^-1, U*, the vectors
+// p s x r u and U* u (read and written) and its matvec record's u; every partial slot once.
+double bytes_pcg_update(const ba_ctx& c) {
+  const double ts = double(c.tsize());
   const double D = c.D, ns = D * (D + 1) / 2;
-  return double(c.Nc) * 7 * ts + double(c.Ca) * (4 + 15 * ts + ns * ts + 2 * D * 8 + (D + 3) * 8);
+  int K = 0, nch = 0;
+  cam_chunking(c.Nc, K, nch);
+  return double(c.Ca) * (2 * 3 * 8 + 4 + ns * 8 + ns * ts + 2 * 6 * D * 8 + D * ts) +
+         double(c.Ca + nch) * (D + 1) * 8;
 }
 int lanes_per_point(const ba_ctx& c) {
   const double mean = c.Pa > 0 ? double(c.Nh) / c.Pa : 1.0;
@@ -599,11 +616,16 @@ int run_pcg(ba_ctx& c, bool adj, double rel_tol, int max_iters, PcgState* out_st
     return 0;
   }
   void* mvt = c.mvt;
-  launch_pcg_init<T>(s, c.D, c.Ca, c.b, c.Minv, c.x, c.r, c.u, c.p, c.sv, mvt, c.pcg,
-                     rel_tol * rel_tol, max_iters);
+  const T* Ustar = static_cast<const T*>(c.Ustar);
+  int K = 0, nch = 0;
+  cam_chunking(c.Nc, K, nch);
+  launch_pcg_init<T>(s, c.D, c.Ca, c.b, c.Minv, Ustar, c.cm_off_hat, K, c.item_off, c.item_cam,
+                     c.x, c.r, c.u, c.p, c.sv, c.wv, c.dots, mvt, c.pcg, rel_tol * rel_tol,
+                     max_iters);
   HIP_LAUNCH_CHECK();
+  const int nslot = c.Ca + nch;
   const int every = std::max(1, c.opt.pcg_check_every);
-  const double bp = bytes_schur_point(c), bc = bytes_schur_cam(c);
+  const double bp = bytes_schur_point(c), bc = bytes_schur_cam(c), bu = bytes_pcg_update(c);
   const int G = lanes_per_point(c);
   P3<T>* zq = static_cast<P3<T>*>(c.zq);
   int it = 0;
@@ -614,19 +636,13 @@ int run_pcg(ba_ctx& c, bool adj, double rel_tol, int max_iters, PcgState* out_st
                               c.pcg, c.dl);
       });
       c.timed("schur_cam", bc, it, [&] {
-        launch_schur_cam<T>(s, adj, c.D, m, cp, om, static_cast<const T*>(c.Ustar), c.u, c.r, zq,
-                            c.wv, c.dots, c.pcg);
+        launch_schur_cam<T>(s, adj, c.D, m, cp, om, c.u, zq, K, c.item_off, c.item_cam, nslot,
+                            c.part, c.pcg);
       });
-      // per camera: its dot terms, M^-1, reads of u p w s x r, writes of p s x r u and its
-      // matvec record's u
-      c.timed("pcg_update",
-              double(c.Ca) * (3 * 8 + double(c.D) * (c.D + 1) / 2 * 8 + c.D * 8 * 11 +
-                              c.D * double(sizeof(T))),
-              it, [&] {
-                launch_pcg_update<T>(s, c.D, c.Ca, it, c.Minv, c.dots, c.x, c.r, c.u, c.p, c.sv,
-                                     c.wv,
-                                     mvt, c.pcg);
-              });
+      c.timed("pcg_update", bu, it, [&] {
+        launch_pcg_update<T>(s, c.D, c.Ca, it, c.Minv, Ustar, c.item_off, nslot, c.part, c.dots,
+                             c.x, c.r, c.u, c.p, c.sv, c.wv, mvt, c.pcg);
+      });
     }
     HIP_CHECK(hipMemcpyAsync(c.h_pin, c.pcg, sizeof(PcgState), hipMemcpyDeviceToHost, s));
     c.sync();

@@ -213,11 +213,24 @@ void launch_cam_assemble(hipStream_t s, bool adj, int D, const Model& m, const C
                          double* gc, double* b, double* Minv);
 
 // ------------------------------------------------------------------ PCG on S
-// x = 0, r = b, u = M^-1 r (also into the matvec records), p = s = 0.
+// x = 0, r = b, u = M^-1 r (also into the matvec records), p = s = 0, Uu = U* u and the
+// per-camera terms r.u, u.U*u, r.r of iteration 0 (terms: 2 x 3 arrays of Ca, SoA, the
+// first three for even iterations); the camera-pass items: camera s owns items
+// item_off[s] .. item_off[s + 1] - 1 (item_cam[i] = s), one per K positions of its segment.
 template <typename T>
 void launch_pcg_init(hipStream_t s, int D, int Ca, const double* b, const double* Minv,
-                     double* x, double* r, double* u, double* p, double* sv, void* mvt,
-                     PcgState* st, double tol2, int max_iter);
+                     const T* Ustar, const int* cm_off, int K, int* item_off, int* item_cam,
+                     double* x, double* r, double* u, double* p, double* sv, double* Uu,
+                     double* terms, void* mvt, PcgState* st, double tol2, int max_iter);
+// Item size of the camera pass: K = Nc / kCamChunks rounded up to a multiple of 64, at least
+// 512, so that there are nchunks = ceil(Nc / K) <= kCamChunks pieces of K positions and at most
+// Ca + nchunks items (each camera's segment adds one partial piece at most).
+constexpr int kCamChunks = 1024;
+inline void cam_chunking(int Nc, int& K, int& nchunks) {
+  const int per = (Nc + kCamChunks - 1) / kCamChunks;
+  K = per <= 512 ? 512 : (per + 63) / 64 * 64;
+  nchunks = Nc > 0 ? (Nc + K - 1) / K : 0;
+}
 // Camera-side launchers take the camera dimension D: 6 (pose) or 7 (pose and focal length,
 // matvec records MvCamF); the adjoint mode runs with D = 6 only.
 // Device figures the launchers size persistent grids and LDS tables with.
@@ -234,19 +247,22 @@ template <typename T>
 void launch_schur_point(hipStream_t s, bool adj, int D, int G, const Model& m,
                         const Compact<T>& cp, ObsMetric<T> om, const void* mvt, const T* Vinv,
                         P3<T>* zq_cm, const PcgState* st, const DevLimits& dl);
-// Camera-major pass, one workgroup per camera slot: w_s = U*_s u_s - sum_k W_k z_k with z
-// streamed in camera-major order, and the camera's terms of r.u, w.u and r.r (dots: 3
-// arrays of Ca, SoA).
+// Camera-major pass in items of at most K positions of one camera: per item i, sum_k W_k z_k
+// over its positions with z streamed in camera-major order (part: rows 0..D-1 of nslot
+// entries, SoA) and that sum's dot with u_s (row D). nslot >= the item count.
 template <typename T>
 void launch_schur_cam(hipStream_t s, bool adj, int D, const Model& m, const Compact<T>& cp,
-                      ObsMetric<T> om, const T* Ustar, const double* u, const double* r,
-                      const P3<T>* zq, double* w, double* dots, const PcgState* st);
-// Fused reduction of the per-camera dots, convergence test, then p = u + beta p,
-// s = w + beta s, x += alpha p, r -= alpha s, u = M^-1 r.
+                      ObsMetric<T> om, const double* u, const P3<T>* zq, int K,
+                      const int* item_off, const int* item_cam, int nslot, double* part,
+                      const PcgState* st);
+// w = U* u - (each camera's item partials), fused reduction of the per-camera terms, convergence
+// test, then p = u + beta p, s = w + beta s, x += alpha p, r -= alpha s, u = M^-1 r, and U* u
+// with the next iteration's terms.
 template <typename T>
-void launch_pcg_update(hipStream_t s, int D, int Ca, int k, const double* Minv,
-                       const double* dots, double* x, double* r, double* u, double* p,
-                       double* sv, const double* w, void* mvt, PcgState* st);
+void launch_pcg_update(hipStream_t s, int D, int Ca, int k, const double* Minv, const T* Ustar,
+                       const int* item_off, int nslot, const double* part, double* terms,
+                       double* x, double* r, double* u, double* p, double* sv, double* Uu,
+                       void* mvt, PcgState* st);
 // dp = Vinv (rhs_p - sum_k W_k^T x_c), rhs_p = -gp when nullptr.
 template <typename T>
 void launch_backsub(hipStream_t s, bool adj, int D, int G, const Model& m, const Compact<T>& cp,

@@ -875,10 +875,42 @@ __device__ __forceinline__ void symd_mul_soa(const double* M, int Ca, int s, con
 template <typename T, int D>
 __global__ void __launch_bounds__(1024)
 k_pcg_init(int Ca, const double* __restrict__ b, const double* __restrict__ Minv,
-           double* __restrict__ x, double* __restrict__ r, double* __restrict__ u,
-           double* __restrict__ p, double* __restrict__ sv, MvRec<T, D>* __restrict__ mvt,
-           PcgState* st, double tol2, int max_iter) {
+           const T* __restrict__ Ustar, const int* __restrict__ cm_off, int K,
+           int* __restrict__ item_off, int* __restrict__ item_cam, double* __restrict__ x,
+           double* __restrict__ r, double* __restrict__ u, double* __restrict__ p,
+           double* __restrict__ sv, double* __restrict__ Uu, double* __restrict__ terms,
+           MvRec<T, D>* __restrict__ mvt, PcgState* st, double tol2, int max_iter) {
   __shared__ double smem[1024 / kWave];
+  __shared__ int s_wave[1024 / kWave];
+  __shared__ int s_carry;
+  // items of the camera pass: ceil(n_s / K) per camera, numbered camera by camera (an
+  // exclusive scan over the cameras in tiles of the block)
+  if (threadIdx.x == 0) s_carry = 0;
+  __syncthreads();
+  for (int base = 0; base < Ca; base += 1024) {
+    const int s = base + int(threadIdx.x);
+    const int n = s < Ca ? (cm_off[s + 1] - cm_off[s] + K - 1) / K : 0;
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    int incl = n;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int t = __shfl_up(incl, o, kWave);
+      if (lane >= o) incl += t;
+    }
+    if (lane == kWave - 1) s_wave[wid] = incl;
+    __syncthreads();
+    int before = s_carry;
+    for (int w = 0; w < wid; ++w) before += s_wave[w];
+    const int first = before + incl - n;
+    if (s < Ca) {
+      item_off[s] = first;
+      for (int q = 0; q < n; ++q) item_cam[first + q] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 1023) s_carry = first + n;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) item_off[Ca] = s_carry;
   double acc[1] = {0.0};   // b.b
   for (int s = threadIdx.x; s < Ca; s += blockDim.x) {
     double rv[D], uv[D];
@@ -892,11 +924,22 @@ k_pcg_init(int Ca, const double* __restrict__ b, const double* __restrict__ Minv
       acc[0] += rv[i] * rv[i];
     }
     symd_mul_soa<D>(Minv, Ca, s, rv, uv);
+    double ru = 0.0, uUu = 0.0, rr = 0.0;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
       u[i * Ca + s] = uv[i];
       mvt[s].u[i] = T(uv[i]);
+      double a = 0.0;
+#pragma unroll
+      for (int j = 0; j < D; ++j) a += double(Ustar[symd<D>(i, j) * Ca + s]) * uv[j];
+      Uu[i * Ca + s] = a;
+      ru += rv[i] * uv[i];
+      uUu += uv[i] * a;
+      rr += rv[i] * rv[i];
     }
+    terms[s] = ru;
+    terms[Ca + s] = uUu;
+    terms[2 * Ca + s] = rr;
   }
   block_sum<double, 1>(acc, smem);
   if (threadIdx.x == 0) {
@@ -923,20 +966,28 @@ k_pcg_init(int Ca, const double* __restrict__ b, const double* __restrict__ Minv
 // The point's z = Vinv y is then stored at the camera-major position of each of its
 // observations, so that the camera pass streams z instead of gathering it.
 // Every lane of a wave must call this together (shuffles); lanes with r >= rend do nothing.
+// (b, e) is the point's observation range when the caller has loaded it (b >= 0), else the
+// function reads it.
 template <typename T, bool ADJ, int G, int D>
 __device__ __forceinline__ void schur_point_one(const Model& m, const Compact<T>& cp,
                                                 const ObsMetric<T>& om,
                                                 const MvRec<T, D>* __restrict__ tab,
                                                 const T* __restrict__ Vinv,
                                                 P3<T>* __restrict__ zq_cm, int r, int rend,
-                                                int l) {
+                                                int l, int b = -1, int e = 0) {
   T y[3] = {T(0), T(0), T(0)};
   T vi[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
-  int b = 0, e = 0, pos0 = -1;
+  int pos0 = -1;
   const bool live = r < rend;
+  if (!live) {
+    b = 0;
+    e = 0;
+  }
   if (live) {
-    b = cp.off[r];
-    e = cp.off[r + 1];
+    if (b < 0) {
+      b = cp.off[r];
+      e = cp.off[r + 1];
+    }
     // loads needed only after the reduction, issued now to overlap the stream (float32: the
     // registers are free; float64 keeps them for the stream)
     if constexpr (sizeof(T) == 4) {
@@ -1028,63 +1079,82 @@ k_schur_point_lds(Model m, Compact<T> cp, ObsMetric<T> om, const MvRec<T, D>* __
                   const PcgState* __restrict__ st, int ppx) {
   extern __shared__ uint4 lds_tab[];   // cp.Ca records
   if (st->done) return;
-  const int nchunk = cp.Ca * int(sizeof(MvRec<T, D>) / sizeof(uint4));
-  const uint4* src = reinterpret_cast<const uint4*>(mvt);
-  for (int i = threadIdx.x; i < nchunk; i += kPtLdsBlock) lds_tab[i] = src[i];
-  __syncthreads();
-  const MvRec<T, D>* tab = reinterpret_cast<const MvRec<T, D>*>(lds_tab);
   const int per = gridDim.x / 8;            // workgroups per XCD
   const int xcd = blockIdx.x % 8;
   const int j = blockIdx.x / 8;
   const int lo = xcd * ppx;
   const int hi = min(cp.Pa, lo + ppx);
   constexpr int tile = kPtLdsBlock / G;
-  for (int base = lo + j * tile; base < hi; base += per * tile)
-    schur_point_one<T, ADJ, G, D>(m, cp, om, tab, Vinv, zq_cm, base + int(threadIdx.x) / G, hi,
-                                  int(threadIdx.x) % G);
+  const int step = per * tile;
+  const int l = int(threadIdx.x) % G;
+  // the point ranges of the next tile are loaded while the current one is processed (the
+  // first ones while the table is staged)
+  int r = lo + j * tile + int(threadIdx.x) / G;
+  int bn = 0, en = 0;
+  if (r < hi) {
+    bn = cp.off[r];
+    en = cp.off[r + 1];
+  }
+  const int nchunk = cp.Ca * int(sizeof(MvRec<T, D>) / sizeof(uint4));
+  const uint4* src = reinterpret_cast<const uint4*>(mvt);
+  for (int i = threadIdx.x; i < nchunk; i += kPtLdsBlock) lds_tab[i] = src[i];
+  __syncthreads();
+  const MvRec<T, D>* tab = reinterpret_cast<const MvRec<T, D>*>(lds_tab);
+  for (int base = lo + j * tile; base < hi; base += step, r += step) {
+    const int b = bn, e = en;
+    if (r + step < hi) {
+      bn = cp.off[r + step];
+      en = cp.off[r + step + 1];
+    }
+    schur_point_one<T, ADJ, G, D>(m, cp, om, tab, Vinv, zq_cm, r, hi, l, b, e);
+  }
 }
 
-// Camera-major pass of S u, one 1024-thread workgroup per camera slot:
-//   w_s = U*_s u_s - sum_k W_k z_k, then the camera's terms of r.u, w.u and r.r.
-// Per observation two streamed 4-vectors: (X_c, w) and z (stored by the point pass).
-constexpr int kCamBlock = 512;   // 4 workgroups per CU: ~1000 cameras in one round
+// Camera-major pass of S u in bounded items. Each camera's segment of the camera-major stream
+// is cut into items of at most K positions (item_off, item_cam: set by the PCG init); the
+// workgroup of item i sums W_k z_k over its positions (z streamed as stored by the point pass)
+// into partial i, and writes the partial's dot with u_s to the last row (zero for the
+// workgroups beyond the last item, so that row needs no item count to be summed). No workgroup has more
+// than K positions whatever the spread of observations per camera, and the update kernel adds
+// a camera's partials in item order, so the result does not depend on scheduling. Two-wave
+// workgroups walking items of a few thousand positions stream best (measured against 64-512
+// threads and 512-4096 items on the 1000-camera workload).
+constexpr int kCamBlock = 128;
 
 template <typename T, bool ADJ, int D>
 __global__ void __launch_bounds__(kCamBlock)
-k_schur_cam(Model m, Compact<T> cp, ObsMetric<T> om, const T* __restrict__ Ustar,
-            const double* __restrict__ u, const double* __restrict__ r,
-            const P3<T>* __restrict__ zq, double* __restrict__ w, double* __restrict__ dots,
+k_schur_cam(Model m, Compact<T> cp, ObsMetric<T> om, const double* __restrict__ u,
+            const P3<T>* __restrict__ zq, int K, const int* __restrict__ item_off,
+            const int* __restrict__ item_cam, int nslot, double* __restrict__ part,
             const PcgState* __restrict__ st) {
   if (st->done) return;
-  // The grid is a multiple of 8: consecutive workgroups are dealt to the 8 XCDs in turn, and
-  // slot = xcd * per + i keeps each XCD on a contiguous camera range, so the z vectors of
-  // points shared by neighbouring cameras are reused from its own L2.
-  const int per = gridDim.x / 8;
-  const int s = (blockIdx.x % 8) * per + blockIdx.x / 8;
   const int Ca = cp.Ca;
-  if (s >= Ca) return;
-  constexpr int NS = sym_count(D);
+  const int i = blockIdx.x;
+  if (i >= item_off[Ca]) {   // beyond the last item: a zero dot, so the update sums all nslot
+    if (threadIdx.x == 0) part[D * nslot + i] = 0.0;
+    return;
+  }
+  const int s = item_cam[i];
+  const int sb = cp.cm_off[s] + (i - item_off[s]) * K;
+  const int se = min(sb + K, cp.cm_off[s + 1]);
+  double us[D];
+  if (threadIdx.x == 0) {   // needed after the reduction: loaded while the stream runs
+#pragma unroll
+    for (int q = 0; q < D; ++q) us[q] = u[q * Ca + s];
+  }
   __shared__ T smem[D * (kCamBlock / kWave)];
-  __shared__ double tail[NS + 2 * D];   // U*_s, u_s, r_s, loaded while the stream runs
-  if (threadIdx.x < NS)
-    tail[threadIdx.x] = double(Ustar[threadIdx.x * Ca + s]);
-  else if (threadIdx.x < NS + D)
-    tail[threadIdx.x] = u[(threadIdx.x - NS) * Ca + s];
-  else if (threadIdx.x < NS + 2 * D)
-    tail[threadIdx.x] = r[(threadIdx.x - NS - D) * Ca + s];
   const Cam<T> cm = cp.camt[s];
   T acc[D];
 #pragma unroll
   for (int q = 0; q < D; ++q) acc[q] = T(0);
-  const int end = cp.cm_off[s + 1];
 #pragma unroll 2
-  for (int i = cp.cm_off[s] + threadIdx.x; i < end; i += blockDim.x) {
-    const V4<T> xw = om.xcw[i];
-    const P3<T> zv = zq[i];
+  for (int k = sb + threadIdx.x; k < se; k += kCamBlock) {
+    const V4<T> xw = om.xcw[k];
+    const P3<T> zv = zq[k];
     const T Xc[3] = {xw.x, xw.y, xw.z};
     AMat<T, ADJ> A;
     A.set(cm.f, T(m.lam_d), Xc);
-    if constexpr (ADJ) A.project(om.cm_eh + 3 * i);
+    if constexpr (ADJ) A.project(om.cm_eh + 3 * k);
     const T z3[3] = {zv.x, zv.y, zv.z};
     T uu[3], t[3], mm[3], xm[3];
     rot_mul(cm, z3, uu);
@@ -1097,67 +1167,89 @@ k_schur_cam(Model m, Compact<T> cp, ObsMetric<T> om, const T* __restrict__ Ustar
     acc[0] += mm[0]; acc[1] += mm[1]; acc[2] += mm[2];
     acc[3] += xm[0]; acc[4] += xm[1]; acc[5] += xm[2];
   }
-  block_sum<T, D>(acc, smem);   // its barriers also publish tail[]
-  if (threadIdx.x != 0) return;
-  const double* uv = tail + NS;
-  double g = 0.0, d = 0.0, rr = 0.0;
+  block_sum<T, D>(acc, smem);
+  if (threadIdx.x == 0) {
+    double pd = 0.0;
 #pragma unroll
-  for (int i = 0; i < D; ++i) {
-    double a = 0.0;
-#pragma unroll
-    for (int j = 0; j < D; ++j) a += tail[symd<D>(i, j)] * uv[j];
-    const double wi = a - double(acc[i]);
-    w[i * Ca + s] = wi;
-    const double ri = tail[NS + D + i];
-    g += ri * uv[i];
-    d += wi * uv[i];
-    rr += ri * ri;
+    for (int q = 0; q < D; ++q) {
+      const double v = double(acc[q]);
+      part[q * nslot + i] = v;
+      pd += us[q] * v;
+    }
+    part[D * nslot + i] = pd;
   }
-  dots[s] = g;
-  dots[Ca + s] = d;
-  dots[2 * Ca + s] = rr;
 }
 
-// One Chronopoulos-Gear PCG iteration k after the matvec w = S u:
-//   gamma = r.u, delta = w.u, rho = r.r (one reduction of the per-camera terms);
+// One Chronopoulos-Gear PCG iteration k after the matvec w = S u, with w_s = U*_s u_s minus the
+// camera's item partials:
+//   gamma = r.u, delta = w.u = u.U*u - (the items' partial . u), rho = r.r (one reduction);
 //   stop if rho <= tol^2 b.b; beta = gamma / gamma_prev, alpha = gamma / (delta - beta gamma /
-//   alpha_prev); p = u + beta p; s = w + beta s; x += alpha p; r -= alpha s; u = M^-1 r.
-// Every workgroup reduces all per-camera terms in the same fixed order (so all of them take
-// the same scalars and the same decision) and updates its own kUpdCams cameras, whose vectors
-// it loads before the reduction. Workgroup 0 records the scalars.
-constexpr int kUpdBlock = 256;
+//   alpha_prev); p = u + beta p; s = w + beta s; x += alpha p; r -= alpha s; u = M^-1 r;
+//   then U*u and the camera's terms r.u, u.U*u, r.r of the next iteration.
+// The per-camera terms are double-buffered by iteration parity, since every workgroup reduces
+// all of them (in the same fixed order, so all take the same scalars and the same decision)
+// while owners write the next ones. Workgroup 0 records the scalars.
+constexpr int kUpdBlock = 512;
 constexpr int kUpdCams = 64;
+constexpr int kUpdItems = 4;   // a camera's partials up to this count are loaded at once
 
 template <typename T, int D>
 __global__ void __launch_bounds__(kUpdBlock)
-k_pcg_update(int Ca, int k, const double* __restrict__ Minv, const double* __restrict__ dots,
-             double* __restrict__ x, double* __restrict__ r, double* __restrict__ u,
-             double* __restrict__ p, double* __restrict__ sv, const double* __restrict__ w,
-             MvRec<T, D>* __restrict__ mvt, PcgState* st) {
+k_pcg_update(int Ca, int k, const double* __restrict__ Minv, const T* __restrict__ Ustar,
+             const int* __restrict__ item_off, int nslot, const double* __restrict__ part,
+             double* __restrict__ terms, double* __restrict__ x, double* __restrict__ r,
+             double* __restrict__ u, double* __restrict__ p, double* __restrict__ sv,
+             double* __restrict__ Uu, MvRec<T, D>* __restrict__ mvt, PcgState* st) {
   __shared__ double smem[3 * (kUpdBlock / kWave)];
   __shared__ double s_bcast[2];
   __shared__ int s_go;
+  const double* tin = terms + (k & 1) * 3 * Ca;
+  double* tout = terms + ((k + 1) & 1) * 3 * Ca;
   const int s = blockIdx.x * kUpdCams + threadIdx.x;
   const bool own = threadIdx.x < kUpdCams && s < Ca;
-  double pv[D], wv[D], sv0[D], rv[D], uv[D], m[sym_count(D)];
+  // every load the owner needs is issued before the reduction
+  double pv[D], wv[D], sv0[D], rv[D], uv[D], xv[D], m[sym_count(D)];
+  T us[sym_count(D)];
   if (own) {
 #pragma unroll
     for (int i = 0; i < D; ++i) {
       pv[i] = p[i * Ca + s];
-      wv[i] = w[i * Ca + s];
+      wv[i] = Uu[i * Ca + s];
       sv0[i] = sv[i * Ca + s];
       rv[i] = r[i * Ca + s];
       uv[i] = u[i * Ca + s];
+      xv[i] = x[i * Ca + s];
     }
 #pragma unroll
-    for (int q = 0; q < sym_count(D); ++q) m[q] = Minv[q * Ca + s];
+    for (int q = 0; q < sym_count(D); ++q) {
+      m[q] = Minv[q * Ca + s];
+      us[q] = Ustar[q * Ca + s];
+    }
+    const int i0 = item_off[s], i1 = item_off[s + 1];
+    double pt[kUpdItems][D];
+#pragma unroll
+    for (int q = 0; q < kUpdItems; ++q) {
+#pragma unroll
+      for (int i = 0; i < D; ++i) pt[q][i] = i0 + q < i1 ? part[i * nslot + i0 + q] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kUpdItems; ++q) {
+#pragma unroll
+      for (int i = 0; i < D; ++i) wv[i] -= pt[q][i];
+    }
+    for (int it = i0 + kUpdItems; it < i1; ++it) {
+#pragma unroll
+      for (int i = 0; i < D; ++i) wv[i] -= part[i * nslot + it];
+    }
   }
   double acc[3] = {0.0, 0.0, 0.0};   // gamma, delta, rho
   for (int c = threadIdx.x; c < Ca; c += kUpdBlock) {
-    acc[0] += dots[c];
-    acc[1] += dots[Ca + c];
-    acc[2] += dots[2 * Ca + c];
+    acc[0] += tin[c];
+    acc[1] += tin[Ca + c];
+    acc[2] += tin[2 * Ca + c];
   }
+#pragma unroll 4
+  for (int j = threadIdx.x; j < nslot; j += kUpdBlock) acc[1] -= part[D * nslot + j];
   // thread 0 reads the state once for the whole workgroup
   int done0 = 0;
   double tol2 = 0.0, bb = 0.0, gprev = 0.0, aprev = 0.0;
@@ -1211,7 +1303,7 @@ k_pcg_update(int Ca, int k, const double* __restrict__ Minv, const double* __res
     const double si = wv[i] + beta * sv0[i];
     p[i * Ca + s] = pi;
     sv[i * Ca + s] = si;
-    x[i * Ca + s] += alpha * pi;
+    x[i * Ca + s] = xv[i] + alpha * pi;
     rv[i] -= alpha * si;
     r[i * Ca + s] = rv[i];
   }
@@ -1220,9 +1312,24 @@ k_pcg_update(int Ca, int k, const double* __restrict__ Minv, const double* __res
     double a = 0.0;
 #pragma unroll
     for (int j = 0; j < D; ++j) a += m[symd<D>(i, j)] * rv[j];
+    uv[i] = a;
     u[i * Ca + s] = a;
     mvt[s].u[i] = T(a);
   }
+  double ru = 0.0, uUu = 0.0, rr = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    double a = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) a += double(us[symd<D>(i, j)]) * uv[j];
+    Uu[i * Ca + s] = a;
+    ru += rv[i] * uv[i];
+    uUu += uv[i] * a;
+    rr += rv[i] * rv[i];
+  }
+  tout[s] = ru;
+  tout[Ca + s] = uUu;
+  tout[2 * Ca + s] = rr;
 }
 
 // Back-substitution dp = Vinv (rhs_p - sum_k W_k^T x_c), same lane layout as the point pass.
@@ -1714,11 +1821,13 @@ void launch_mv_table(hipStream_t s, int D, int n, const Cam<double>* camd_hat, v
 
 template <typename T>
 void launch_pcg_init(hipStream_t s, int D, int Ca, const double* b, const double* Minv,
-                     double* x, double* r, double* u, double* p, double* sv, void* mvt,
-                     PcgState* st, double tol2, int max_iter) {
+                     const T* Ustar, const int* cm_off, int K, int* item_off, int* item_cam,
+                     double* x, double* r, double* u, double* p, double* sv, double* Uu,
+                     double* terms, void* mvt, PcgState* st, double tol2, int max_iter) {
   with_dim(D, [&](auto Dc) {
-    launch_k(k_pcg_init<T, Dc()>, dim3(1), dim3(1024), 0, s, Ca, b, Minv, x, r, u, p, sv,
-             static_cast<MvRec<T, Dc()>*>(mvt), st, tol2, max_iter);
+    launch_k(k_pcg_init<T, Dc()>, dim3(1), dim3(1024), 0, s, Ca, b, Minv, Ustar, cm_off, K,
+             item_off, item_cam, x, r, u, p, sv, Uu, terms, static_cast<MvRec<T, Dc()>*>(mvt),
+             st, tol2, max_iter);
   });
 }
 
@@ -1773,28 +1882,31 @@ void launch_schur_point(hipStream_t s, bool adj, int D, int G, const Model& m,
 
 template <typename T>
 void launch_schur_cam(hipStream_t s, bool adj, int D, const Model& m, const Compact<T>& cp,
-                      ObsMetric<T> om, const T* Ustar, const double* u, const double* r,
-                      const P3<T>* zq, double* w, double* dots, const PcgState* st) {
-  if (cp.Ca <= 0) return;
-  const unsigned grid = unsigned((cp.Ca + 7) / 8 * 8);   // one share per XCD
+                      ObsMetric<T> om, const double* u, const P3<T>* zq, int K,
+                      const int* item_off, const int* item_cam, int nslot, double* part,
+                      const PcgState* st) {
+  if (cp.Ca <= 0 || nslot <= 0) return;
+  const unsigned grid = unsigned(nslot);   // items <= nslot; the others return at once
   if (adj)
-    launch_k((k_schur_cam<T, true, 6>), dim3(grid), dim3(kCamBlock), 0, s, m, cp, om, Ustar,
-             u, r, zq, w, dots, st);
+    launch_k((k_schur_cam<T, true, 6>), dim3(grid), dim3(kCamBlock), 0, s, m, cp, om, u, zq, K,
+             item_off, item_cam, nslot, part, st);
   else
     with_dim(D, [&](auto Dc) {
-      launch_k((k_schur_cam<T, false, Dc()>), dim3(grid), dim3(kCamBlock), 0, s, m, cp, om,
-               Ustar, u, r, zq, w, dots, st);
+      launch_k((k_schur_cam<T, false, Dc()>), dim3(grid), dim3(kCamBlock), 0, s, m, cp, om, u,
+               zq, K, item_off, item_cam, nslot, part, st);
     });
 }
 
 template <typename T>
-void launch_pcg_update(hipStream_t s, int D, int Ca, int k, const double* Minv,
-                       const double* dots, double* x, double* r, double* u, double* p,
-                       double* sv, const double* w, void* mvt, PcgState* st) {
+void launch_pcg_update(hipStream_t s, int D, int Ca, int k, const double* Minv, const T* Ustar,
+                       const int* item_off, int nslot, const double* part, double* terms,
+                       double* x, double* r, double* u, double* p, double* sv, double* Uu,
+                       void* mvt, PcgState* st) {
   if (Ca <= 0) return;
   with_dim(D, [&](auto Dc) {
     launch_k(k_pcg_update<T, Dc()>, dim3((Ca + kUpdCams - 1) / kUpdCams), dim3(kUpdBlock), 0,
-             s, Ca, k, Minv, dots, x, r, u, p, sv, w, static_cast<MvRec<T, Dc()>*>(mvt), st);
+             s, Ca, k, Minv, Ustar, item_off, nslot, part, terms, x, r, u, p, sv, Uu,
+             static_cast<MvRec<T, Dc()>*>(mvt), st);
   });
 }
 
@@ -1896,17 +2008,19 @@ void launch_adjoint_obs(hipStream_t s, const Model& m, const Compact<T>& cp, Obs
                                        double*, double*);                                      \
   template void launch_mv_table<T>(hipStream_t, int, int, const Cam<double>*, void*);         \
   template void launch_pcg_init<T>(hipStream_t, int, int, const double*, const double*,       \
+                                   const T*, const int*, int, int*, int*, double*, double*,   \
                                    double*, double*, double*, double*, double*, void*,        \
                                    PcgState*, double, int);                                    \
   template void launch_schur_point<T>(hipStream_t, bool, int, int, const Model&,              \
                                       const Compact<T>&, ObsMetric<T>, const void*, const T*, \
                                       P3<T>*, const PcgState*, const DevLimits&);              \
   template void launch_schur_cam<T>(hipStream_t, bool, int, const Model&, const Compact<T>&,  \
-                                    ObsMetric<T>, const T*, const double*, const double*,     \
-                                    const P3<T>*, double*, double*, const PcgState*);         \
-  template void launch_pcg_update<T>(hipStream_t, int, int, int, const double*, const double*,\
-                                     double*, double*, double*, double*, double*,             \
-                                     const double*, void*, PcgState*);                        \
+                                    ObsMetric<T>, const double*, const P3<T>*, int,           \
+                                    const int*, const int*, int, double*, const PcgState*);   \
+  template void launch_pcg_update<T>(hipStream_t, int, int, int, const double*, const T*,     \
+                                     const int*, int, const double*, double*, double*,        \
+                                     double*, double*, double*, double*, double*, void*,      \
+                                     PcgState*);                                               \
   template void launch_backsub<T>(hipStream_t, bool, int, int, const Model&,                  \
                                   const Compact<T>&, ObsMetric<T>, const T*, const double*,   \
                                   const double*, const double*, double*);                      \
