@@ -14,7 +14,9 @@ computes, written from the paper:
 * ``extract``   dynamic parameter extraction, Eqs. (10)-(15);
 * ``lm``        the LM system Eq. (3) with a dense Schur complement and Cholesky, gain
                 ratio, Nielsen damping update, scatter of the compact update;
-* ``adjoint``   implicit-function adjoint of the converged solution, solved directly.
+* ``adjoint``   implicit-function adjoint of the converged solution, solved directly;
+* ``gp``        depth-constrained global positioning, Eqs. (1), (4), (5), (8): camera centres,
+                points and free per-observation scales, pinned scales from valid depth.
 
 Every function is pinned by ``tests/test_oracle_*.py`` against finite differences, library
 routines, brute force on tiny inputs, closed forms or exact recovery of noise-free scenes.
