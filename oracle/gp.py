@@ -21,7 +21,9 @@ partition of Eq. (8) (Sec. III-A, Sec. IV-A):
   its own free scale, so 3 rows when pinned and 2 when free; a point needs 3, a camera 3 and
   must not be fixed; the greatest fixpoint of that pruning as in BA;
 * LM exactly as in ``lm.py`` (Marquardt diagonal floored, Nielsen update, gain ratio on the
-  per-observation actual reduction); the damped system is solved directly (sparse LU); a
+  per-observation actual reduction); the damped system is solved directly: the scale block is
+  diagonal (each scale has one observation), so it is eliminated exactly, then the points
+  (3x3 blocks) by the dense camera Schur complement and Cholesky of ``lm.schur_solve``; a
   candidate with a free scale <= 0 is rejected (a scale is an inverse distance);
 * free scales start at the inverse distance of the current estimate, ``1 / |X - c|``.
 """
@@ -30,11 +32,11 @@ from __future__ import annotations
 from dataclasses import dataclass, field
 import numpy as np
 import scipy.sparse as sp
-import scipy.sparse.linalg as spla
 
 from .geometry import quat_to_rot
 from .model import Problem, huber
 from .extract import activity_fixpoint, ranks
+from .lm import schur_solve
 
 
 @dataclass
@@ -194,6 +196,22 @@ def gp_damped(H: sp.spmatrix, lam: float, opts: GpOptions) -> sp.csr_matrix:
     return (H + sp.diags(lam * D)).tocsr()
 
 
+def gp_solve_system(Hd: sp.spmatrix, rhs: np.ndarray, nc: int, npt: int) -> np.ndarray:
+    """Solve the damped GP system: eliminate the diagonal scale block, then the points and
+    cameras with the dense Schur complement + Cholesky."""
+    Hd = Hd.tocsr()
+    m = nc + npt
+    Hss = Hd[m:, m:]
+    hs = Hss.diagonal()
+    assert (Hss - sp.diags(hs)).count_nonzero() == 0, "scale block must be diagonal"
+    B = Hd[:m, m:]
+    Hr = Hd[:m, :m] - B @ sp.diags(1.0 / hs) @ B.T
+    rr = rhs[:m] - B @ (rhs[m:] / hs)
+    xcp = schur_solve(Hr, rr, nc)
+    xs = (rhs[m:] - B.T @ xcp) / hs
+    return np.concatenate([xcp, xs])
+
+
 @dataclass
 class GpStepReport:
     status: str = "ok"
@@ -235,7 +253,7 @@ def gp_step(prob: Problem, q, st: GpState, opts: GpOptions):
     rep.cost_before = F
     rep.rms = float(np.sqrt(np.mean(np.sum(lin.u * lin.u, axis=1))))
     rep.grad_inf = float(np.max(np.abs(g))) if g.size else 0.0
-    delta = spla.spsolve(gp_damped(H, st.lam, opts).tocsc(), -g)
+    delta = gp_solve_system(gp_damped(H, st.lam, opts), -g, lin.ncol_cam, lin.ncol_pt)
     rep.delta = delta
     Jd = (lin.J @ delta).reshape(lin.u.shape)
     model = -(float(g @ delta) + 0.5 * float(np.sum(lin.w[:, None] * Jd * Jd)))

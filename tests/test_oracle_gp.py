@@ -4,6 +4,7 @@
 * the residual vanishes at the ground truth of a noise-free scene with exact priors, for
   pinned scales 1 / (d_hat |a|) and for free scales 1 / |X - c| (closed form);
 * the Jacobian columns (centre, point, free scale) against central differences;
+* the scale-then-point elimination against a dense solve of the whole damped system;
 * the GP activity fixpoint (3 rows pinned, 2 free; points and cameras need 3) against brute
   force over all observation subsets of tiny incidences;
 * noise-free recovery: from centres and points at 1.5x the true scale and perturbed, with
@@ -16,8 +17,8 @@ import numpy as np
 import pytest
 
 from oracle.geometry import quat_to_rot
-from oracle.gp import (GpOptions, GpState, gp_extract, gp_linearize, gp_residuals, gp_solve,
-                       rays)
+from oracle.gp import (GpOptions, GpState, gp_damped, gp_extract, gp_linearize,
+                       gp_normal_equations, gp_residuals, gp_solve, gp_solve_system, rays)
 from oracle.model import Problem
 from scenes import make_scene
 from tests._align import aligned_error
@@ -89,6 +90,21 @@ def test_jacobian_matches_central_differences():
         np.testing.assert_allclose(J[:, col], fd, rtol=1e-6, atol=1e-9)
         cols.append(col)
     assert len(set(cols)) == len(cols)
+
+
+@pytest.mark.parametrize("lam", [1e-4, 1.0])
+def test_elimination_equals_dense_solve(lam):
+    sc = make_scene("tiny", prior_frac=0.5, use_depth=True, lambda_d=1.0, n_points=150)
+    prob = Problem.from_scene(sc)
+    q = sc.cams_gt[:, :4]
+    st = GpState.initial(prob, q, sc.cams0, sc.points0, GpOptions())
+    ex = gp_extract(prob)
+    lin = gp_linearize(prob, q, st, ex, 0.1)
+    H, g = gp_normal_equations(lin)
+    Hd = gp_damped(H, lam, GpOptions())
+    x = gp_solve_system(Hd, -g, lin.ncol_cam, lin.ncol_pt)
+    ref = np.linalg.solve(Hd.toarray(), -g)
+    np.testing.assert_allclose(x, ref, rtol=1e-8, atol=1e-9 * np.abs(ref).max())
 
 
 @pytest.mark.parametrize("seed", range(6))
