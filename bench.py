@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "BA LM iters/s + Jacobian obs/s, FP32-mixed vs FP64, 1000-cam synthetic scene"
 HBM_PEAK_GBS = 8000.0
-LINEARIZE_KERNELS = ("lin_point", "cam_assemble")
+LINEARIZE_KERNELS = ("lin_point", "cam_assemble", "gp_lin", "gp_cam_assemble")
 
 
 def parse():
@@ -63,8 +63,25 @@ def parse():
     ap.add_argument("--refine-focal", action="store_true",
                     help="refine each camera's focal length too (7-parameter cameras), "
                          "starting from focal lengths off by up to 2%%")
+    ap.add_argument("--gp", action="store_true",
+                    help="time depth-constrained global positioning steps instead of BA steps "
+                         "(true rotations, perturbed centres and points, free scales where the "
+                         "depth prior is invalid)")
+    ap.add_argument("--gp-huber", type=float, default=0.1)
     ap.add_argument("--verbose", action="store_true")
     return ap.parse_args()
+
+
+GP_METRIC = ("GP LM iters/s (depth-constrained global positioning), FP32-mixed vs FP64, "
+             "1000-cam synthetic scene")
+
+
+def gp_start(sc):
+    """Global positioning takes the rotations as given: the true ones, with the scene's
+    perturbed centres and points."""
+    from dataclasses import replace
+    cams0 = np.concatenate([sc.cams_gt[:, :4], sc.cams0[:, 4:7]], axis=1)
+    return replace(sc, cams0=cams0)
 
 
 def focal_start(sc):
@@ -85,20 +102,21 @@ def run_gpu(sc, precision, steps, warmup, args, torch, timing):
                         huber_px=sc.huber_px, filter_px=sc.filter_px, img_w=sc.img_w,
                         img_h=sc.img_h, pcg_rel_tol=args.pcg_tol, pcg_max_iters=args.pcg_max,
                         pcg_check_every=args.check_every, timing=timing,
-                        refine_focal=int(args.refine_focal))
+                        refine_focal=int(args.refine_focal), gp_huber=args.gp_huber)
     ba.set_observations(t(sc.cam_idx, torch.int32), t(sc.pt_idx, torch.int32),
                         t(sc.xy, torch.float32))
     if sc.use_depth:
         ba.set_depth_priors(t(sc.depth, torch.float32), t(sc.depth_valid, torch.uint8),
                             sc.lambda_d)
+    step = ba.gp_step if args.gp else ba.lm_step
     for _ in range(warmup):
-        ba.lm_step()
+        step()
     torch.cuda.synchronize()
     ba.reset_kernel_stats()
     reps = []
     t0 = time.perf_counter()
     for _ in range(steps):
-        reps.append(ba.lm_step())
+        reps.append(step())
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     stats = ba.kernel_stats()
@@ -238,6 +256,44 @@ def roofline(res, scene):
     return out
 
 
+def cpu_baseline_gp(sc, frac, steps, n_obs_full, huber_gp):
+    """The FP64 GP oracle on a random fraction of the points (all cameras), per LM step, the
+    rate rescaled to the full observation count."""
+    from dataclasses import replace
+    from oracle.gp import GpOptions, GpState, gp_step
+    from oracle.model import Problem
+    rng = np.random.default_rng(1234)
+    keep = np.sort(rng.choice(sc.n_points, max(1, int(frac * sc.n_points)), replace=False))
+    m = np.zeros(sc.n_points, bool)
+    m[keep] = True
+    ob = m[sc.pt_idx]
+    pmap = np.full(sc.n_points, -1)
+    pmap[keep] = np.arange(keep.size)
+    sub = replace(sc, points_gt=sc.points_gt[keep], points0=sc.points0[keep],
+                  cam_idx=sc.cam_idx[ob], pt_idx=pmap[sc.pt_idx[ob]].astype(np.int32),
+                  xy=sc.xy[ob], depth=sc.depth[ob], depth_valid=sc.depth_valid[ob],
+                  is_outlier=sc.is_outlier[ob])
+    opts = GpOptions(huber=huber_gp)
+    prob = Problem.from_scene(sub)
+    q = sub.cams0[:, :4]
+    st = GpState.initial(prob, q, sub.cams0, sub.points0, opts)
+    t0 = time.perf_counter()
+    nobs = []
+    for _ in range(steps):
+        st, rep = gp_step(prob, q, st, opts)
+        nobs.append(rep.n_obs)
+    dt = time.perf_counter() - t0
+    its_sample = steps / dt
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=round(its_sample * sub.cam_idx.size / n_obs_full, 5), unit="GP LM iters/s",
+                cores=cores, kind="oracle",
+                sample=(f"{steps} FP64 GP oracle LM steps on {100 * frac:.0f}% of the points "
+                        f"({sub.cam_idx.size} of {n_obs_full} observations, all cameras), "
+                        f"{dt:.1f} s; rate rescaled by the observation ratio"),
+                sample_iters_per_s=round(its_sample, 4),
+                obs_per_s=round(its_sample * float(np.mean(nobs)), 1))
+
+
 def cpu_baseline(sc, frac, steps, n_obs_full, refine_focal=False):
     """The FP64 oracle on a random fraction of the points (all cameras), timed per LM step;
     the rate is rescaled to the full observation count (per-observation work dominates)."""
@@ -281,6 +337,9 @@ def main():
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(multi-GPU point sharding is design-only).", file=sys.stderr)
         sys.exit(2)
+    if args.gp and (args.refine_focal or args.forward_adjoint):
+        print("bench.py: --gp times global positioning alone", file=sys.stderr)
+        sys.exit(2)
     if args.refine_focal and args.forward_adjoint:
         print("bench.py: the adjoint covers poses and points; --forward-adjoint needs focal "
               "refinement off", file=sys.stderr)
@@ -307,7 +366,9 @@ def main():
     sc = make_scene(args.scene)
     if args.refine_focal:
         sc = focal_start(sc)
-    workload_key = args.scene + ("+focal" if args.refine_focal else "")
+    if args.gp:
+        sc = gp_start(sc)
+    workload_key = args.scene + ("+focal" if args.refine_focal else "") + ("+gp" if args.gp else "")
     t_gen = time.perf_counter() - t0
     if args.verbose:
         print(f"scene {args.scene}: C={sc.n_cams} P={sc.n_points} N={sc.n_obs} "
@@ -331,9 +392,9 @@ def main():
     head = precs[0]
     ins, summ = out[head]
     line = {
-        "metric": METRIC,
+        "metric": GP_METRIC if args.gp else METRIC,
         "value": round(summ["lm_iters_per_s"], 3),
-        "unit": "LM iters/s",
+        "unit": "GP LM iters/s" if args.gp else "LM iters/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -349,7 +410,11 @@ def main():
                                 f"{100 * sc.depth_valid.mean():.0f}%, Huber "
                                 f"{sc.huber_px:g} px, {sc.filter_px:g} px filter"
                                 + (", focal lengths refined (7-parameter cameras, start "
-                                   "off by up to 2%)" if args.refine_focal else "")),
+                                   "off by up to 2%)" if args.refine_focal else "")
+                                + (f"; global positioning: true rotations, camera centres, "
+                                   f"points and {100 * (1 - sc.depth_valid.mean()):.0f}% free "
+                                   f"scales, Huber {args.gp_huber:g} on the ray residual"
+                                   if args.gp else "")),
                    "pcg_rel_tol": args.pcg_tol, "pcg_max_iters": args.pcg_max,
                    "pcg_check_every": args.check_every},
         "obs_per_s": round(summ["obs_per_s"], 1),
@@ -368,9 +433,14 @@ def main():
         line["rms_diff_px"] = abs(out["mixed"][1]["rms_px_last"] - out["fp64"][1]["rms_px_last"])
     if args.forward_adjoint > 0:
         line["forward_adjoint"] = forward_adjoint(sc, args.forward_adjoint, args, torch)
-    line["cpu_baseline"] = (None if args.no_cpu else
-                            cpu_baseline(sc, args.cpu_frac, args.cpu_steps, sc.n_obs,
-                                         args.refine_focal))
+    if args.no_cpu:
+        line["cpu_baseline"] = None
+    elif args.gp:
+        line["cpu_baseline"] = cpu_baseline_gp(sc, args.cpu_frac, args.cpu_steps, sc.n_obs,
+                                               args.gp_huber)
+    else:
+        line["cpu_baseline"] = cpu_baseline(sc, args.cpu_frac, args.cpu_steps, sc.n_obs,
+                                            args.refine_focal)
     print(json.dumps(line), flush=True)
 
 

@@ -89,6 +89,8 @@ typedef struct ba_options {
                               derivative) fails with BA_ERR_NUMERIC when H is singular, e.g.
                               a two-view point whose observations are both in the Huber
                               regime; a small value (1e-6) regularises such blocks; 0 */
+  double gp_huber;         /* Huber threshold of global positioning on |u| (unit-ray units);
+                              <= 0: L2; 0.1 */
   void* hip_stream;        /* hipStream_t to run on; NULL: a stream owned by the context */
 } ba_options;
 
@@ -208,6 +210,30 @@ ba_status ba_reset_kernel_stats(ba_ctx* ctx);
 
 /* Device bytes currently allocated by the context. */
 int64_t ba_device_bytes(const ba_ctx* ctx);
+
+
+/* ---------------------------------------------------------------- global positioning
+ * Depth-constrained global positioning (Sec. III-A, Eq. (1); Sec. IV-A, Eqs. (4), (5), (8)) on
+ * the same context: camera rotations are held at the cams' quaternions; the unknowns are the
+ * camera centres (cams entries 4..6), the points and one scale s per observation, residual
+ * u = v - s (X - c) on the unit world ray v = R^T K^-1 [x, y, 1] / |K^-1 [x, y, 1]|, Huber
+ * (gp_huber) on |u|^2. An observation with a valid depth prior (ba_set_depth_priors; any
+ * lambda_d) is pinned at s = 1 / (d_hat |K^-1 [x, y, 1]|), the inverse distance along the
+ * ray of a z-depth d_hat, and its scale column leaves the system (Eq. (8)); the other scales
+ * are free. Extraction keeps every observation with finite data; an observation brings 3
+ * rows when pinned and 2 when free, a point needs 3 and a camera 3 (fixed cameras keep their
+ * centre). One LM iteration: free scales eliminated per observation, points per point, PCG
+ * with block-Jacobi on the 3 x 3 camera-centre Schur complement, back-substitution, the
+ * candidate's cost over the same observations (a free scale <= 0 rejects it), Nielsen's
+ * damping rule on a damping of its own. Free scales start at the inverse distance of the
+ * estimate at the first GP call (again after ba_set_params, ba_set_depth_priors or
+ * ba_gp_reset). A GP step leaves the BA state to re-extract at its next step. */
+ba_status ba_gp_step(ba_ctx* ctx, ba_step_report* rep);   /* rms_px: RMS of |u| */
+ba_status ba_gp_solve(ba_ctx* ctx, ba_solve_report* rep); /* same stopping rules as ba_solve */
+/* Current scales, N doubles in the caller's observation order (pinned ones included). */
+ba_status ba_gp_get_scales(const ba_ctx* ctx, double* scales);
+/* Re-initialise the free scales from the current estimate and restart the GP damping. */
+ba_status ba_gp_reset(ba_ctx* ctx);
 
 /* Message of the last error on ctx (or of the last failed ba_create when ctx is NULL). */
 const char* ba_last_error(const ba_ctx* ctx);

@@ -12,7 +12,8 @@ from .api import (BundleAdjuster, make_options, ba_default_options, ba_create,
                   ba_solve, ba_get_params, ba_get_intrinsics, ba_set_params, ba_get_active,
                   ba_get_last_step,
                   ba_get_normal_blocks, ba_adjoint, ba_kernel_stats, ba_reset_kernel_stats,
-                  ba_device_bytes, ba_last_error, ba_destroy)
+                  ba_device_bytes, ba_last_error, ba_destroy, ba_gp_step, ba_gp_solve,
+                  ba_gp_get_scales, ba_gp_reset)
 
 __all__ = [
     "BAError", "BA_OK", "BA_EMPTY", "BA_ERR_ARG", "BA_ERR_STATE", "BA_ERR_OOM",
@@ -22,5 +23,6 @@ __all__ = [
     "ba_solve", "ba_get_params", "ba_get_intrinsics", "ba_set_params", "ba_get_active",
     "ba_get_last_step",
     "ba_get_normal_blocks", "ba_adjoint", "ba_kernel_stats", "ba_reset_kernel_stats",
-    "ba_device_bytes", "ba_last_error", "ba_destroy",
+    "ba_device_bytes", "ba_last_error", "ba_destroy", "ba_gp_step", "ba_gp_solve",
+    "ba_gp_get_scales", "ba_gp_reset",
 ]

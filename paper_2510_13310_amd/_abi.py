@@ -39,7 +39,8 @@ class BaOptions(Structure):
         ("pcg_rel_tol", c_double), ("cost_rel_tol", c_double), ("grad_tol", c_double),
         ("max_lm_iters", c_int32), ("timing", c_int32), ("adjoint_max_iters", c_int32),
         ("refine_focal", c_int32),
-        ("adjoint_rel_tol", c_double), ("adjoint_damping", c_double), ("hip_stream", c_void_p),
+        ("adjoint_rel_tol", c_double), ("adjoint_damping", c_double), ("gp_huber", c_double),
+        ("hip_stream", c_void_p),
     ]
 
 
@@ -90,6 +91,10 @@ EXPORTS = {
     "ba_get_params": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "ba_set_params": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "ba_get_intrinsics": (c_int32, [c_void_p, c_void_p]),
+    "ba_gp_step": (c_int32, [c_void_p, POINTER(BaStepReport)]),
+    "ba_gp_solve": (c_int32, [c_void_p, POINTER(BaSolveReport)]),
+    "ba_gp_get_scales": (c_int32, [c_void_p, c_void_p]),
+    "ba_gp_reset": (c_int32, [c_void_p]),
     "ba_get_active": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "ba_get_last_step": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "ba_get_normal_blocks": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),

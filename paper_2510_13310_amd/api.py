@@ -107,6 +107,35 @@ def ba_solve(ctx: int) -> dict:
     return d
 
 
+def ba_gp_step(ctx: int) -> dict:
+    lib = _abi.load()
+    rep = BaStepReport()
+    st = _check(lib, ctx, lib.ba_gp_step(ctx, byref(rep)))
+    d = struct_to_dict(rep)
+    d["status"] = st
+    return d
+
+
+def ba_gp_solve(ctx: int) -> dict:
+    lib = _abi.load()
+    rep = BaSolveReport()
+    st = _check(lib, ctx, lib.ba_gp_solve(ctx, byref(rep)))
+    d = struct_to_dict(rep)
+    d["status"] = st
+    return d
+
+
+def ba_gp_get_scales(ctx: int, scales_out) -> int:
+    lib = _abi.load()
+    ps, _ = _ptr(scales_out, F64)
+    return _check(lib, ctx, lib.ba_gp_get_scales(ctx, ps))
+
+
+def ba_gp_reset(ctx: int) -> int:
+    lib = _abi.load()
+    return _check(lib, ctx, lib.ba_gp_reset(ctx))
+
+
 def ba_get_params(ctx: int, cams_out, points_out) -> int:
     lib = _abi.load()
     pc, _ = _ptr(cams_out, F64)
@@ -259,6 +288,21 @@ class BundleAdjuster:
 
     def solve(self) -> dict:
         return ba_solve(self.ctx)
+
+    # depth-constrained global positioning
+    def gp_step(self) -> dict:
+        return ba_gp_step(self.ctx)
+
+    def gp_solve(self) -> dict:
+        return ba_gp_solve(self.ctx)
+
+    def gp_scales(self):
+        out = np.empty(self.n_obs)
+        ba_gp_get_scales(self.ctx, out)
+        return out
+
+    def gp_reset(self):
+        return ba_gp_reset(self.ctx)
 
     # outputs
     def get_params(self):

@@ -141,6 +141,14 @@ struct ba_ctx {
   double *x = nullptr, *r = nullptr, *u = nullptr, *p = nullptr, *sv = nullptr,
          *wv = nullptr, *dots = nullptr, *part = nullptr;
   int *item_off = nullptr, *item_cam = nullptr;   // camera-pass items
+
+  // global positioning (allocated on its first step)
+  double* gp_s = nullptr;                       // N scales, caller's observation order
+  double* gp_scand = nullptr;                   // compact candidate scales
+  void *gp_lin_pm = nullptr, *gp_lin_cm = nullptr, *gp_a_pm = nullptr, *gp_a_cm = nullptr;
+  bool gp_ready = false;                        // scales initialised
+  bool gp_lin_valid = false;                    // GP linearisation of the current estimate
+  double gp_lam = 1e-3, gp_nu = 2.0, gp_last_decrease = 0.0;
   double *partials = nullptr, *scal = nullptr;
   double *grad_cams_d = nullptr, *grad_pts_d = nullptr;
   float *gxy_d = nullptr, *gdepth_d = nullptr;
@@ -366,6 +374,8 @@ void alloc_obs_buffers(ba_ctx& c) {
   c.pm_xcw = A.alloc<char>(4 * ts * N);
   c.eh = nullptr;
   c.cm_eh = nullptr;
+  c.gp_s = nullptr;
+  c.gp_ready = false;
   c.V = A.alloc<char>(sizeof(double) * 6 * P);
   c.Vinv = A.alloc<char>(ts * 6 * P);
   c.prec = A.alloc<char>((ts == 8 ? sizeof(PtRec<double>) : sizeof(PtRec<float>)) * P);
@@ -454,25 +464,35 @@ ObsMetric<T> metric_view(ba_ctx& c) {
 
 // ------------------------------------------------------------------ extraction
 // Validity, activity fixpoint, ranks and compaction at the current parameters.
-void extract(ba_ctx& c) {
+// Dynamic parameter extraction. gp selects the global-positioning rules: validity is finite
+// data only, 3 rows per pinned and 2 per free observation, cameras need 3 rows.
+void extract(ba_ctx& c, bool gp = false) {
+  c.gp_lin_valid = false;   // the compaction buffers are rebuilt
   const Model m = c.model();
   hipStream_t s = c.stream;
   const int64_t N = c.N;
   c.timed("cam_table", double(c.C) * (56 + 24 + 120 + 60), -1,
           [&] { launch_cam_table(s, c.C, c.d_cams, c.d_intr, c.d_camd, c.d_camf); });
-  c.timed("validate", double(N) * (4 + 4 + 8 + 4 + 24 + 1 + 4 + 1), -1, [&] {
-    launch_validate(s, N, m, c.pm_cam, c.pm_pt, c.pm_xy, c.pm_depth, c.d_pts, c.d_camd,
-                    c.inv_cm, c.vrow, c.vrow_cm);
-  });
+  if (gp)
+    c.timed("gp_validate", double(N) * (8 + 4 + 4 + 1 + 1), -1, [&] {
+      launch_gp_validate(s, N, c.pm_xy, c.pm_depth, c.inv_cm, c.vrow, c.vrow_cm);
+    });
+  else
+    c.timed("validate", double(N) * (4 + 4 + 8 + 4 + 24 + 1 + 4 + 1), -1, [&] {
+      launch_validate(s, N, m, c.pm_cam, c.pm_pt, c.pm_xy, c.pm_depth, c.d_pts, c.d_camd,
+                      c.inv_cm, c.vrow, c.vrow_cm);
+    });
+  const int need_cam = gp ? 3 : c.need_cam();
+  const int need_pt = gp ? 3 : c.need_pt();
   int rounds = 0;
   while (true) {
     ++rounds;
     HIP_CHECK(hipMemsetAsync(c.flags, 0, sizeof(int), s));
     c.timed("cam_rows", double(N) * 1, -1, [&] {
-      launch_cam_rows(s, c.C, c.cm_off, c.vrow_cm, c.d_fixed, c.need_cam(), c.act_c);
+      launch_cam_rows(s, c.C, c.cm_off, c.vrow_cm, c.d_fixed, need_cam, c.act_c);
     });
     c.timed("point_rows_prune", double(N) * 5 + double(c.P) * 5, -1, [&] {
-      launch_point_rows_prune(s, c.P, c.pt_off, c.pm_cam, c.act_c, c.d_fixed, c.need_pt(),
+      launch_point_rows_prune(s, c.P, c.pt_off, c.pm_cam, c.act_c, c.d_fixed, need_pt,
                               c.inv_cm, c.vrow, c.vrow_cm, c.act_p, c.flags);
     });
     HIP_CHECK(hipMemcpyAsync(c.h_pin, c.flags, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -509,7 +529,9 @@ void extract(ba_ctx& c) {
     launch_compact_obs(s, N, c.vrow, c.pos_pm, c.pm_cam, c.slot_all, c.pm_xy, c.pm_depth,
                        c.pm_orig, c.Ca, c.inv_cm, c.pos_cm, c.pm_pt, c.rank_p, c.cam_hat,
                        c.xy_hat, c.depth_hat, c.orig_hat, c.pm_cm, c.cm_pt);
-    if (c.tsize() == 8)
+    if (gp)
+      ;   // the global-positioning matvec records hold u only, set by the PCG init
+    else if (c.tsize() == 8)
       launch_mv_table<double>(s, c.D, c.Ca + c.n_fixed, c.camd_hat, c.mvt);
     else
       launch_mv_table<float>(s, c.D, c.Ca + c.n_fixed, c.camd_hat, c.mvt);
@@ -553,6 +575,7 @@ int lanes_per_point(const ba_ctx& c) {
 
 template <typename T>
 void linearize(ba_ctx& c, bool adj) {
+  c.gp_lin_valid = false;   // shares the point-gradient and scalar buffers
   hipStream_t s = c.stream;
   const Model m = c.model();
   Compact<T> cp = compact_view<T>(c);
@@ -800,6 +823,239 @@ ba_status lm_step_dispatch(ba_ctx& c, ba_step_report* rep) {
                                               : lm_step_impl<float>(c, rep);
 }
 
+// ------------------------------------------------------------------ global positioning
+void ensure_gp_buffers(ba_ctx& c) {
+  if (c.gp_s) return;
+  const size_t ts = c.tsize(), N = size_t(c.N);
+  c.gp_s = c.obs.alloc<double>(N);
+  c.gp_scand = c.obs.alloc<double>(N);
+  c.gp_lin_pm = c.obs.alloc<char>(8 * ts * N);
+  c.gp_lin_cm = c.obs.alloc<char>(8 * ts * N);
+  c.gp_a_pm = c.obs.alloc<char>(4 * ts * N);
+  c.gp_a_cm = c.obs.alloc<char>(4 * ts * N);
+}
+
+// Free scales at the inverse distance of the current estimate, pinned ones from the priors;
+// the GP damping restarts.
+void gp_init(ba_ctx& c) {
+  ensure_gp_buffers(c);
+  hipStream_t s = c.stream;
+  launch_cam_table(s, c.C, c.d_cams, c.d_intr, c.d_camd, c.d_camf);
+  HIP_LAUNCH_CHECK();
+  launch_gp_init_scales(s, c.N, c.pm_cam, c.pm_pt, c.pm_orig, c.pm_xy, c.pm_depth, c.d_pts,
+                        c.d_camd, c.gp_s);
+  HIP_LAUNCH_CHECK();
+  c.gp_lam = c.opt.lambda_init;
+  c.gp_nu = 2.0;
+  c.gp_ready = true;
+  c.gp_lin_valid = false;
+}
+
+// PCG on the camera-centre Schur complement (D = 3); returns the number of matvecs.
+template <typename T>
+int gp_run_pcg(ba_ctx& c, PcgState* out_state) {
+  hipStream_t s = c.stream;
+  Compact<T> cp = compact_view<T>(c);
+  PcgState st{};
+  if (c.Ca == 0) {
+    *out_state = st;
+    out_state->done = 1;
+    return 0;
+  }
+  const T* Ustar = static_cast<const T*>(c.Ustar);
+  int K = 0, nch = 0;
+  cam_chunking(c.Nc, K, nch);
+  const int nslot = c.Ca + nch;
+  launch_pcg_init<T>(s, 3, c.Ca, c.b, c.Minv, Ustar, c.cm_off_hat, K, c.item_off, c.item_cam,
+                     c.x, c.r, c.u, c.p, c.sv, c.wv, c.dots, c.mvt, c.pcg,
+                     c.opt.pcg_rel_tol * c.opt.pcg_rel_tol, c.opt.pcg_max_iters);
+  HIP_LAUNCH_CHECK();
+  const double ts = double(sizeof(T));
+  const int G = lanes_per_point(c);
+  const V4<T>* a_pm = static_cast<const V4<T>*>(c.gp_a_pm);
+  const V4<T>* a_cm = static_cast<const V4<T>*>(c.gp_a_cm);
+  P3<T>* zq = static_cast<P3<T>*>(c.zq);
+  // per observation: slot, A record, camera-major position and z written; per point offset
+  // and Vinv; per camera its record
+  const double bp = double(c.Nh) * (4 + 4 * ts) + double(c.Nc) * (4 + 3 * ts) +
+                    double(c.Pa) * (4 + 6 * ts) + double(c.Ca) * 4 * ts;
+  const double bc = double(c.Nc) * 7 * ts + double(c.Ca) * (8 + 24) + double(nslot) * 32;
+  const double bu = double(c.Ca) * (48 + 4 + 48 + 6 * ts + 288 + 3 * ts) + double(nslot) * 32;
+  const int every = std::max(1, c.opt.pcg_check_every);
+  int it = 0;
+  while (true) {
+    for (int k = 0; k < every && it < c.opt.pcg_max_iters; ++k, ++it) {
+      c.timed("gp_schur_point", bp, it, [&] {
+        launch_gp_schur_point<T>(s, G, cp, a_pm, c.mvt, static_cast<const T*>(c.Vinv), zq,
+                                 c.pcg);
+      });
+      c.timed("gp_schur_cam", bc, it, [&] {
+        launch_gp_schur_cam<T>(s, cp, a_cm, c.u, zq, K, c.item_off, c.item_cam, nslot, c.part,
+                               c.pcg);
+      });
+      c.timed("gp_pcg_update", bu, it, [&] {
+        launch_pcg_update<T>(s, 3, c.Ca, it, c.Minv, Ustar, c.item_off, nslot, c.part, c.dots,
+                             c.x, c.r, c.u, c.p, c.sv, c.wv, c.mvt, c.pcg);
+      });
+    }
+    HIP_CHECK(hipMemcpyAsync(c.h_pin, c.pcg, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+    c.sync();
+    std::memcpy(&st, c.h_pin, sizeof(PcgState));
+    if (st.done || it >= c.opt.pcg_max_iters) break;
+  }
+  *out_state = st;
+  return st.matvecs;
+}
+
+template <typename T>
+ba_status gp_step_impl(ba_ctx& c, ba_step_report* rep) {
+  const double t0 = now_ms();
+  ba_step_report R;
+  std::memset(&R, 0, sizeof(R));
+  if (!c.gp_ready) gp_init(c);
+  R.lambda = c.gp_lam;
+  hipStream_t s = c.stream;
+  const double ts = double(sizeof(T));
+  const double lam = c.gp_lam, dmin = c.opt.diag_min, dmax = c.opt.diag_max;
+  const double delta = c.opt.gp_huber;
+  Compact<T> cp;
+  GpLin<T>* lin_pm = static_cast<GpLin<T>*>(c.gp_lin_pm);
+  GpLin<T>* lin_cm = static_cast<GpLin<T>*>(c.gp_lin_cm);
+  V4<T>* a_pm = static_cast<V4<T>*>(c.gp_a_pm);
+  V4<T>* a_cm = static_cast<V4<T>*>(c.gp_a_cm);
+  double ta = now_ms();
+  if (!c.gp_lin_valid) {
+    extract(c, true);
+    // the compaction buffers now hold the GP active sets: the BA step must extract again
+    c.lin_valid = false;
+    c.step_valid = c.blocks_valid = false;
+    R.ms_extract = now_ms() - ta;
+    R.relinearized = 1;
+    if (c.Nh == 0) {
+      c.flush_timing(0);
+      R.status = BA_EMPTY;
+      R.fixpoint_rounds = c.rounds;
+      R.ms_total = now_ms() - t0;
+      if (rep) *rep = R;
+      return BA_EMPTY;
+    }
+    cp = compact_view<T>(c);
+    ta = now_ms();
+    c.timed("gp_lin", double(c.Nh) * (4 + 8 + 4 + 4 + 8 + 8 * ts) + double(c.Nc) * 8 * ts +
+                          double(c.Pa) * (4 + 24 + 24) + double(c.C) * 120,
+            -1, [&] {
+              launch_gp_lin<T>(s, lanes_per_point(c), cp, c.orig_hat, c.gp_s, delta, lin_pm,
+                               lin_cm, c.gp, c.partials);
+            });
+    launch_reduce_partials(s, lin_point_blocks(c.Pa), 3, c.partials, 0x4u, 0, nullptr, nullptr,
+                           c.scal);
+    HIP_LAUNCH_CHECK();
+    R.ms_linearize = now_ms() - ta;
+    c.gp_lin_valid = true;
+  }
+  cp = compact_view<T>(c);
+  const int G = lanes_per_point(c);
+  R.fixpoint_rounds = c.rounds;
+  R.n_cams_active = c.Ca;
+  R.n_points_active = c.Pa;
+  R.n_obs_active = c.Nh;
+  ta = now_ms();
+  HIP_CHECK(hipMemsetAsync(c.flags + 1, 0, sizeof(int), s));
+  c.timed("gp_point_setup", double(c.Nh) * (8 * ts + 4 + 4 * ts) + double(c.Nc) * 4 * ts +
+                                double(c.Pa) * (4 + 6 * ts + 24 + double(sizeof(PtRec<T>))),
+          -1, [&] {
+            launch_gp_point_setup<T>(s, G, cp, lam, dmin, dmax, lin_pm, a_pm, a_cm,
+                                     static_cast<T*>(c.Vinv), c.hp,
+                                     static_cast<PtRec<T>*>(c.prec), c.flags + 1);
+          });
+  c.timed("gp_cam_assemble",
+          double(c.Nc) * (4 + 12 * ts) + double(c.Pa) * double(sizeof(PtRec<T>)) +
+              double(c.Ca) * (8 + 6 * ts + 6 * 8 + 6 * 8),
+          -1, [&] {
+            launch_gp_cam_assemble<T>(s, cp, lam, dmin, dmax, lin_cm, a_cm,
+                                      static_cast<const PtRec<T>*>(c.prec),
+                                      static_cast<T*>(c.Ustar), c.gc, c.b, c.Minv);
+          });
+  HIP_LAUNCH_CHECK();
+  R.ms_setup = now_ms() - ta;
+  ta = now_ms();
+  PcgState st{};
+  const int iters = gp_run_pcg<T>(c, &st);
+  R.pcg_iters = st.iter;
+  R.pcg_breakdown = st.breakdown;
+  R.pcg_rel_residual = st.bb > 0 ? std::sqrt(std::max(0.0, st.rr) / st.bb) : 0.0;
+  R.ms_pcg = now_ms() - ta;
+  ta = now_ms();
+  c.timed("gp_backsub", double(c.Nh) * (4 + 4 * ts) + double(c.Pa) * (4 + 6 * ts + 48) +
+                            double(c.Ca) * 24,
+          -1, [&] {
+            launch_gp_backsub<T>(s, G, cp, a_pm, static_cast<const T*>(c.Vinv), c.hp, c.x, c.dp);
+          });
+  c.timed("gp_candidate", double(c.Nh) * (4 + 8 + 4 + 4 + 8 + 8) + double(c.Pa) * (4 + 24 * 4) +
+                              double(c.C) * 240,
+          -1, [&] {
+            launch_gp_candidate<T>(s, cp, c.orig_hat, c.gp_s, delta, lam, dmin, dmax, c.x, c.dp,
+                                   c.gp, c.Xcand, c.gp_scand, c.partials);
+          });
+  const int nb = int((c.Pa + kBlock - 1) / kBlock);
+  // scal[4..] = decrease, quad, g_X.dX + g_s.ds, bad, cost', g_c.dc, max |g_c|
+  launch_reduce_partials(s, nb, 5, c.partials, 0x0u, 3 * c.Ca, c.gc, c.x, c.scal + 4);
+  HIP_LAUNCH_CHECK();
+  HIP_CHECK(hipMemcpyAsync(c.h_pin, c.scal, 11 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(c.h_pin + 11, c.flags + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+  c.sync();
+  double sc[11];
+  std::memcpy(sc, c.h_pin, sizeof(sc));
+  int damp_bad = 0;
+  std::memcpy(&damp_bad, c.h_pin + 11, sizeof(int));
+  const double F = sc[0];
+  R.cost_before = F;
+  R.rms_px = std::sqrt(sc[1] / double(c.Nh));
+  const bool finite_c = !(sc[7] > 0) && std::isfinite(sc[8]);
+  const double dF = sc[4];
+  c.gp_last_decrease = dF;
+  R.cost_after = finite_c ? F - dF : std::numeric_limits<double>::infinity();
+  const double model = -(sc[6] + sc[9] + 0.5 * sc[5]);
+  R.model_decrease = model;
+  R.grad_inf = std::max(sc[2], c.Ca > 0 ? sc[10] : 0.0);
+  if (!std::isfinite(F)) {
+    c.flush_timing(iters);
+    R.ms_total = now_ms() - t0;
+    if (rep) *rep = R;
+    throw BaError{BA_ERR_NUMERIC, "non-finite GP cost at the current parameters"};
+  }
+  const double ratio = (model > 0 && finite_c) ? dF / model
+                                               : -std::numeric_limits<double>::infinity();
+  R.gain_ratio = ratio;
+  const bool ok = finite_c && dF > 0 && ratio > c.opt.accept_ratio && !st.breakdown && !damp_bad;
+  R.accepted = ok ? 1 : 0;
+  if (ok) {
+    c.timed("gp_scatter", double(c.Pa) * 52 + double(c.Ca) * 60 + double(c.Nh) * 16, -1, [&] {
+      launch_gp_scatter(s, c.Pa, c.Ca, c.Nh, c.pt_src, c.Xcand, c.cam_src, c.x, c.depth_hat,
+                        c.orig_hat, c.gp_scand, c.d_pts, c.d_cams, c.gp_s);
+    });
+    c.gp_lin_valid = false;
+    const double f = std::max(1.0 / 3.0, 1.0 - std::pow(2.0 * ratio - 1.0, 3));
+    c.gp_lam = std::max(c.opt.lambda_min, std::min(c.opt.lambda_max, c.gp_lam * f));
+    c.gp_nu = 2.0;
+  } else {
+    c.gp_lam = std::min(c.gp_lam * c.gp_nu, c.opt.lambda_max);
+    c.gp_nu *= 2.0;
+  }
+  c.sync();
+  R.ms_candidate = now_ms() - ta;
+  c.flush_timing(iters);
+  R.ms_total = now_ms() - t0;
+  if (rep) *rep = R;
+  return BA_OK;
+}
+
+ba_status gp_step_dispatch(ba_ctx& c, ba_step_report* rep) {
+  if (!c.have_obs) throw BaError{BA_ERR_STATE, "ba_set_observations has not been called"};
+  return c.opt.precision == BA_PRECISION_FP64 ? gp_step_impl<double>(c, rep)
+                                              : gp_step_impl<float>(c, rep);
+}
+
 template <typename T>
 void adjoint_impl(ba_ctx& c, const double* grad_cams, const double* grad_points, float* gxy,
                   float* gdepth) {
@@ -900,6 +1156,7 @@ void ba_default_options(ba_options* o) {
   o->adjoint_max_iters = 5000;
   o->adjoint_damping = 0.0;
   o->refine_focal = 0;
+  o->gp_huber = 0.1;
   o->adjoint_rel_tol = 1e-10;
   o->hip_stream = nullptr;
 }
@@ -927,6 +1184,7 @@ ba_status ba_create(const ba_options* opt, int32_t n_cams, int32_t n_points, con
       !(o.lambda_init > 0) || o.pcg_max_iters < 0 || !(o.pcg_rel_tol >= 0) ||
       !(o.diag_min > 0) || !(o.diag_max >= o.diag_min) || o.adjoint_max_iters < 0 ||
       !(o.adjoint_damping >= 0) || (o.refine_focal != 0 && o.refine_focal != 1) ||
+      !std::isfinite(o.gp_huber) ||
       !(o.adjoint_rel_tol >= 0)) {
     g_create_error = "invalid options";
     return BA_ERR_ARG;
@@ -1084,6 +1342,7 @@ ba_status ba_set_observations(ba_ctx* c, int64_t n_obs, const int32_t* cam_idx,
     c->lam = c->opt.lambda_init;
     c->nu = 2.0;
     c->lin_valid = c->ext_valid = c->step_valid = c->blocks_valid = false;
+    c->gp_lin_valid = false;
     return BA_OK;
   });
 }
@@ -1108,8 +1367,10 @@ ba_status ba_set_depth_priors(ba_ctx* c, const float* depth, const uint8_t* vali
     }
     store(*c, c->pm_depth, pm.data(), pm.size());
     c->have_priors = true;
+    c->gp_ready = false;   // pinned scales change with the priors
     c->lam_d = lambda_d;
     c->lin_valid = c->ext_valid = c->step_valid = c->blocks_valid = false;
+    c->gp_lin_valid = false;
     return BA_OK;
   });
 }
@@ -1132,6 +1393,7 @@ ba_status ba_set_fixed_cameras(ba_ctx* c, int32_t n, const int32_t* ids) {
     store(*c, c->d_fixed, f.data(), f.size());
     store(*c, c->d_fixed_rank, fr.data(), fr.size());
     c->lin_valid = c->ext_valid = c->step_valid = c->blocks_valid = false;
+    c->gp_lin_valid = false;
     return BA_OK;
   });
 }
@@ -1184,6 +1446,76 @@ ba_status ba_solve(ba_ctx* c, ba_solve_report* rep) {
   });
 }
 
+ba_status ba_gp_step(ba_ctx* c, ba_step_report* rep) {
+  return guarded(c, [&]() -> ba_status { return gp_step_dispatch(*c, rep); });
+}
+
+ba_status ba_gp_solve(ba_ctx* c, ba_solve_report* rep) {
+  return guarded(c, [&]() -> ba_status {
+    const double t0 = now_ms();
+    ba_solve_report S;
+    std::memset(&S, 0, sizeof(S));
+    ba_step_report R;
+    ba_status st = BA_OK;
+    bool first = true;
+    for (int it = 0; it < c->opt.max_lm_iters; ++it) {
+      st = gp_step_dispatch(*c, &R);
+      S.iterations += 1;
+      if (st == BA_EMPTY) {
+        S.stop_reason = 4;
+        break;
+      }
+      if (first) {
+        S.initial_cost = R.cost_before;
+        S.initial_rms_px = R.rms_px;
+        first = false;
+      }
+      S.total_pcg_iters += R.pcg_iters;
+      S.accepted += R.accepted;
+      S.final_cost = R.accepted ? R.cost_after : R.cost_before;
+      S.final_rms_px = R.rms_px;
+      if (R.grad_inf <= c->opt.grad_tol) {
+        S.stop_reason = 2;
+        break;
+      }
+      if (R.accepted && c->gp_last_decrease <= c->opt.cost_rel_tol * R.cost_before) {
+        S.stop_reason = 1;
+        break;
+      }
+      if (!R.accepted && R.lambda >= c->opt.lambda_max) {
+        S.stop_reason = 3;
+        break;
+      }
+    }
+    S.lambda = c->gp_lam;
+    S.ms_total = now_ms() - t0;
+    if (rep) *rep = S;
+    return st == BA_EMPTY ? BA_EMPTY : BA_OK;
+  });
+}
+
+ba_status ba_gp_get_scales(const ba_ctx* cc, double* scales) {
+  ba_ctx* c = const_cast<ba_ctx*>(cc);
+  return guarded(c, [&]() -> ba_status {
+    if (!scales) return fail(c, BA_ERR_ARG, "scales is NULL");
+    if (!c->have_obs) return fail(c, BA_ERR_STATE, "ba_set_observations has not been called");
+    if (!c->gp_ready) gp_init(*c);
+    HIP_CHECK(hipMemcpyAsync(scales, c->gp_s, sizeof(double) * size_t(c->N), hipMemcpyDefault,
+                             c->stream));
+    c->sync();
+    return BA_OK;
+  });
+}
+
+ba_status ba_gp_reset(ba_ctx* c) {
+  return guarded(c, [&]() -> ba_status {
+    if (!c->have_obs) return fail(c, BA_ERR_STATE, "ba_set_observations has not been called");
+    gp_init(*c);
+    c->sync();
+    return BA_OK;
+  });
+}
+
 ba_status ba_get_params(const ba_ctx* cc, double* cams, double* points) {
   ba_ctx* c = const_cast<ba_ctx*>(cc);
   return guarded(c, [&]() -> ba_status {
@@ -1233,6 +1565,7 @@ ba_status ba_set_params(ba_ctx* c, const double* cams, const double* points) {
     c->lam = c->opt.lambda_init;
     c->nu = 2.0;
     c->lin_valid = c->step_valid = c->blocks_valid = false;
+    c->gp_ready = c->gp_lin_valid = false;   // free GP scales restart from the new estimate
     return BA_OK;
   });
 }

@@ -64,6 +64,16 @@ template <typename T>
 struct MvRecOf<T, 7> {
   using type = MvCamF<T>;
 };
+// Global positioning: the camera unknown is its centre (3 values); the point pass only needs u.
+template <typename T>
+struct alignas(4 * sizeof(T)) GpMv {
+  T u[3];
+  T pad;
+};
+template <typename T>
+struct MvRecOf<T, 3> {
+  using type = GpMv<T>;
+};
 template <typename T, int D>
 using MvRec = typename MvRecOf<T, D>::type;
 
@@ -299,5 +309,77 @@ template <typename T>
 void launch_adjoint_obs(hipStream_t s, const Model& m, const Compact<T>& cp, ObsMetric<T> om,
                         const double* x, const double* dp, const int* orig, float* gxy,
                         float* gdepth);
+
+// ------------------------------------------------------------------ global positioning
+// Depth-constrained global positioning (Eqs. (1), (4), (5), (8)): rotations fixed, unknowns the
+// camera centres (3 per camera, PCG with D = 3), the points and the free per-observation scales
+// (eliminated per observation before the points). Residual u = v - s (X - c) on the unit world
+// ray v = R^T a / |a|, a = K^-1 [x, y, 1]; a valid depth prior pins s = 1 / (d_hat |a|).
+//
+// Per compact observation the linearisation keeps, in both orders: d = X - c, the scale (stored
+// negated when pinned), u and the robust weight w.
+template <typename T>
+struct alignas(8 * sizeof(T)) GpLin {
+  T d[3];
+  T s;
+  T u[3];
+  T w;
+};
+// After eliminating a free scale with its damped diagonal h* = h + lambda clamp(h), h = w |d|^2,
+// the observation couples its camera centre and point through A = a0 I - e e^T with
+// a0 = w s^2 and e = (w s / sqrt(h*)) d (e = 0 when pinned); the record stores (e, a0).
+
+// Row counts (3 pinned, 2 free, 0 with non-finite data) in both orders.
+void launch_gp_validate(hipStream_t s, int64_t N, const float2* pm_xy, const float* pm_depth,
+                        const int* inv_cm, uint8_t* vrow, uint8_t* vrow_cm);
+// Free scales (user order) at the inverse distance of the current estimate; pinned ones at
+// 1 / (d_hat |a|).
+void launch_gp_init_scales(hipStream_t s, int64_t N, const int* pm_cam, const int* pm_pt,
+                           const int* pm_orig, const float2* pm_xy, const float* pm_depth,
+                           const double* pts, const Cam<double>* camd, double* scales);
+// Residuals, weights, the records above, g_X = -sum w s u per point (gX, P x 3) and block
+// partials {cost, sum |u|^2, max |g|} (3 per block of lin_point_blocks(Pa)).
+template <typename T>
+void launch_gp_lin(hipStream_t s, int G, const Compact<T>& cp, const int* orig,
+                   const double* scales, double delta, GpLin<T>* lin_pm, GpLin<T>* lin_cm,
+                   double* gX, double* partials);
+// Per point: the (e, a0) records in both orders, V* = sum A + lambda clamp(sum a0) I inverted
+// in float64, hp = V*^-1 r_X with r_X = sum w s (u + d g_s / h*), packed into prec.
+template <typename T>
+void launch_gp_point_setup(hipStream_t s, int G, const Compact<T>& cp, double lam, double dmin,
+                           double dmax, const GpLin<T>* lin_pm, V4<T>* a_pm, V4<T>* a_cm,
+                           T* Vinv, double* hp, PtRec<T>* prec, int* bad);
+// Per camera: U* = sum A + lambda clamp(sum a0) I, g_c = sum w s u, b = r_c + sum A hp with
+// r_c = -sum w s (u + d g_s / h*), S_cc = U* - sum A V*^-1 A and its inverse (SoA, D = 3).
+template <typename T>
+void launch_gp_cam_assemble(hipStream_t s, const Compact<T>& cp, double lam, double dmin,
+                            double dmax, const GpLin<T>* lin_cm, const V4<T>* a_cm,
+                            const PtRec<T>* prec, T* Ustar, double* gc, double* b,
+                            double* Minv);
+// The two PCG passes of S u = U* u - sum_c A V*^-1 sum_p A u (camera records GpMv).
+template <typename T>
+void launch_gp_schur_point(hipStream_t s, int G, const Compact<T>& cp, const V4<T>* a_pm,
+                           const void* mvt, const T* Vinv, P3<T>* zq_cm, const PcgState* st);
+template <typename T>
+void launch_gp_schur_cam(hipStream_t s, const Compact<T>& cp, const V4<T>* a_cm,
+                         const double* u, const P3<T>* zq, int K, const int* item_off,
+                         const int* item_cam, int nslot, double* part, const PcgState* st);
+// dX = hp + V*^-1 sum A dc.
+template <typename T>
+void launch_gp_backsub(hipStream_t s, int G, const Compact<T>& cp, const V4<T>* a_pm,
+                       const T* Vinv, const double* hp, const double* x, double* dp);
+// Candidate (float64, recomputed from the compact data): centres c + dc, points X + dX, free
+// scales s + ds with ds = (-g_s + w s d.(dc - dX)) / h*; per block {actual decrease, sum w
+// |J delta|^2, g_X.dX + g_s ds, scales <= 0, candidate cost} (5 per block of kBlock points).
+template <typename T>
+void launch_gp_candidate(hipStream_t s, const Compact<T>& cp, const int* orig,
+                         const double* scales, double delta, double lam, double dmin,
+                         double dmax, const double* x, const double* dp, const double* gX,
+                         double* Xcand, double* s_cand, double* partials);
+// Accepted step: points, camera centres (cams C x 7, entries 4..6) and free scales.
+void launch_gp_scatter(hipStream_t s, int Pa, int Ca, int64_t Nh, const int* pt_src,
+                       const double* Xcand, const int* cam_src, const double* x,
+                       const float* depth_hat, const int* orig, const double* s_cand,
+                       double* pts, double* cams, double* scales);
 
 }  // namespace iba

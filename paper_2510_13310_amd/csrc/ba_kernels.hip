@@ -1676,6 +1676,569 @@ k_adjoint_obs(Model m, Compact<T> cp, ObsMetric<T> om, const double* __restrict_
   }
 }
 
+// ------------------------------------------------------------------ global positioning
+// Unit world ray of an observation: v = R^T a / |a| with a = K^-1 [x, y, 1]; returns |a|.
+__device__ __forceinline__ double gp_ray(const Cam<double>& cm, float2 xy, double v[3]) {
+  const double a[3] = {(double(xy.x) - cm.cx) / cm.f, (double(xy.y) - cm.cy) / cm.f, 1.0};
+  const double na = sqrt(a[0] * a[0] + a[1] * a[1] + 1.0);
+  double t[3];
+  rot_tmul(cm, a, t);
+  v[0] = t[0] / na;
+  v[1] = t[1] / na;
+  v[2] = t[2] / na;
+  return na;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_gp_validate(int64_t N, const float2* __restrict__ xy, const float* __restrict__ depth,
+              const int* __restrict__ inv_cm, uint8_t* __restrict__ vrow,
+              uint8_t* __restrict__ vrow_cm) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  const float2 p = xy[k];
+  const uint8_t rows = (isfinite(p.x) && isfinite(p.y)) ? (depth[k] > 0.0f ? 3 : 2) : 0;
+  vrow[k] = rows;
+  vrow_cm[inv_cm[k]] = rows;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_gp_init_scales(int64_t N, const int* __restrict__ pm_cam, const int* __restrict__ pm_pt,
+                 const int* __restrict__ pm_orig, const float2* __restrict__ xy,
+                 const float* __restrict__ depth, const double* __restrict__ pts,
+                 const Cam<double>* __restrict__ camd, double* __restrict__ scales) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  const Cam<double> cm = camd[pm_cam[k]];
+  const int p = pm_pt[k];
+  double v[3];
+  const double na = gp_ray(cm, xy[k], v);
+  const float dh = depth[k];
+  double sc;
+  if (dh > 0.0f) {
+    sc = 1.0 / (double(dh) * na);
+  } else {
+    const double d0 = pts[3 * p] - cm.c[0], d1 = pts[3 * p + 1] - cm.c[1];
+    const double d2 = pts[3 * p + 2] - cm.c[2];
+    sc = 1.0 / fmax(sqrt(d0 * d0 + d1 * d1 + d2 * d2), 1e-12);
+  }
+  scales[pm_orig[k]] = sc;
+}
+
+// Residual of one compact observation at the current estimate (float64).
+struct GpObs {
+  double v[3], d[3], u[3], s;
+  bool pinned;
+};
+__device__ __forceinline__ GpObs gp_obs(const Cam<double>& cm, float2 xy, float dh,
+                                        const double X[3], double s_free) {
+  GpObs o;
+  const double na = gp_ray(cm, xy, o.v);
+  o.pinned = dh > 0.0f;
+  o.s = o.pinned ? 1.0 / (double(dh) * na) : s_free;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    o.d[i] = X[i] - cm.c[i];
+    o.u[i] = o.v[i] - o.s * o.d[i];
+  }
+  return o;
+}
+
+template <typename T, int G>
+__global__ void __launch_bounds__(kBlock)
+k_gp_lin(Compact<T> cp, const int* __restrict__ orig, const double* __restrict__ scales,
+         double delta, GpLin<T>* __restrict__ lin_pm, GpLin<T>* __restrict__ lin_cm,
+         double* __restrict__ gX, double* __restrict__ partials) {
+  __shared__ double smem[3 * (kBlock / kWave)];
+  const int per = gridDim.x / 8;
+  const int blk = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  constexpr int tile = kBlock / G;
+  const int l = int(threadIdx.x) % G;
+  double acc[3] = {0.0, 0.0, 0.0};   // cost, sum |u|^2, max |g|
+  for (int t = 0; t < G; ++t) {
+    const int r = blk * kBlock + t * tile + int(threadIdx.x) / G;
+    const bool live = r < cp.Pa;
+    double g[3] = {0.0, 0.0, 0.0};
+    if (live) {
+      const double X[3] = {cp.Xd[3 * r], cp.Xd[3 * r + 1], cp.Xd[3 * r + 2]};
+      for (int j = cp.off[r] + l; j < cp.off[r + 1]; j += G) {
+        const Cam<double> cm = cp.camd[cp.cam[j]];
+        const float dh = cp.depth[j];
+        const GpObs o = gp_obs(cm, cp.xy[j], dh, X, dh > 0.0f ? 0.0 : scales[orig[j]]);
+        const double e2 = o.u[0] * o.u[0] + o.u[1] * o.u[1] + o.u[2] * o.u[2];
+        double rho, w, d2;
+        huber(e2, delta, rho, w, d2);
+        acc[0] += 0.5 * rho;
+        acc[1] += e2;
+        const double ws = w * o.s;
+        g[0] -= ws * o.u[0];
+        g[1] -= ws * o.u[1];
+        g[2] -= ws * o.u[2];
+        if (!o.pinned) {   // g_s = -w d.u
+          const double gs = -w * (o.d[0] * o.u[0] + o.d[1] * o.u[1] + o.d[2] * o.u[2]);
+          acc[2] = fmax(acc[2], fabs(gs));
+        }
+        GpLin<T> rec;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          rec.d[i] = T(o.d[i]);
+          rec.u[i] = T(o.u[i]);
+        }
+        rec.s = T(o.pinned ? -o.s : o.s);
+        rec.w = T(w);
+        lin_pm[j] = rec;
+        const int ic = cp.pm_cm[j];
+        if (ic >= 0) lin_cm[ic] = rec;
+      }
+    }
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) g[i] += __shfl_xor(g[i], o, kWave);
+    }
+    if (live && l == 0) {
+      gX[3 * r] = g[0];
+      gX[3 * r + 1] = g[1];
+      gX[3 * r + 2] = g[2];
+      acc[2] = fmax(acc[2], fmax(fabs(g[0]), fmax(fabs(g[1]), fabs(g[2]))));
+    }
+  }
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  acc[0] = wave_sum(acc[0]);
+  acc[1] = wave_sum(acc[1]);
+  acc[2] = wave_max(acc[2]);
+  if (lane == 0) {
+    smem[3 * wid] = acc[0];
+    smem[3 * wid + 1] = acc[1];
+    smem[3 * wid + 2] = acc[2];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int w = 0; w < int(blockDim.x) / kWave; ++w) {
+      a0 += smem[3 * w];
+      a1 += smem[3 * w + 1];
+      a2 = fmax(a2, smem[3 * w + 2]);
+    }
+    partials[3 * blk] = a0;
+    partials[3 * blk + 1] = a1;
+    partials[3 * blk + 2] = a2;
+  }
+}
+
+// Scale elimination of one linearised observation: a0 = w s^2, the coupling vector e (zero
+// when pinned), and q = w s (u + d g_s / h*) (the observation's share of the reduced RHS).
+template <typename T>
+__device__ __forceinline__ void gp_reduce(const GpLin<T>& L, double lam, double dmin,
+                                          double dmax, double e[3], double& a0, double q[3]) {
+  const double w = double(L.w);
+  const bool pinned = L.s < T(0);
+  const double s = pinned ? -double(L.s) : double(L.s);
+  const double d[3] = {double(L.d[0]), double(L.d[1]), double(L.d[2])};
+  const double u[3] = {double(L.u[0]), double(L.u[1]), double(L.u[2])};
+  a0 = w * s * s;
+  double f = 0.0, ce = 0.0;
+  if (!pinned) {
+    const double h = w * (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    const double hs = h + lam * fmin(fmax(h, dmin), dmax);
+    const double gs = -w * (d[0] * u[0] + d[1] * u[1] + d[2] * u[2]);
+    f = gs / hs;
+    ce = w * s / sqrt(hs);
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    e[i] = ce * d[i];
+    q[i] = w * s * (u[i] + d[i] * f);
+  }
+}
+
+// A x = a0 x - e (e . x)
+template <typename T>
+__device__ __forceinline__ void gp_apply(const V4<T>& a, const T x[3], T y[3]) {
+  const T ex = a.x * x[0] + a.y * x[1] + a.z * x[2];
+  y[0] = a.w * x[0] - a.x * ex;
+  y[1] = a.w * x[1] - a.y * ex;
+  y[2] = a.w * x[2] - a.z * ex;
+}
+
+template <typename T, int G>
+__global__ void __launch_bounds__(kBlock)
+k_gp_point_setup(Compact<T> cp, double lam, double dmin, double dmax,
+                 const GpLin<T>* __restrict__ lin_pm, V4<T>* __restrict__ a_pm,
+                 V4<T>* __restrict__ a_cm, T* __restrict__ Vinv, double* __restrict__ hp,
+                 PtRec<T>* __restrict__ prec, int* __restrict__ bad) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = t / G;
+  const int l = t % G;
+  double v[7] = {0, 0, 0, 0, 0, 0, 0};   // sum A (6, upper triangle), sum a0
+  double q[3] = {0, 0, 0};
+  if (r < cp.Pa) {
+    for (int j = cp.off[r] + l; j < cp.off[r + 1]; j += G) {
+      double e[3], a0, qk[3];
+      gp_reduce(lin_pm[j], lam, dmin, dmax, e, a0, qk);
+      V4<T> rec;
+      rec.x = T(e[0]);
+      rec.y = T(e[1]);
+      rec.z = T(e[2]);
+      rec.w = T(a0);
+      a_pm[j] = rec;
+      const int ic = cp.pm_cm[j];
+      if (ic >= 0) a_cm[ic] = rec;
+#pragma unroll
+      for (int p = 0; p < 3; ++p) {
+#pragma unroll
+        for (int k = p; k < 3; ++k) v[sym3(p, k)] += (p == k ? a0 : 0.0) - e[p] * e[k];
+        q[p] += qk[p];
+      }
+      v[6] += a0;
+    }
+  }
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) {
+#pragma unroll
+    for (int i = 0; i < 7; ++i) v[i] += __shfl_xor(v[i], o, kWave);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) q[i] += __shfl_xor(q[i], o, kWave);
+  }
+  if (r >= cp.Pa || l != 0) return;
+  const double dmp = lam * fmin(fmax(v[6], dmin), dmax);
+  const double v00 = v[0] + dmp, v01 = v[1], v02 = v[2];
+  const double v11 = v[3] + dmp, v12 = v[4], v22 = v[5] + dmp;
+  const double c00 = v11 * v22 - v12 * v12;
+  const double c01 = v02 * v12 - v01 * v22;
+  const double c02 = v01 * v12 - v02 * v11;
+  const double c11 = v00 * v22 - v02 * v02;
+  const double c12 = v01 * v02 - v00 * v12;
+  const double c22 = v00 * v11 - v01 * v01;
+  const double det = v00 * c00 + v01 * c01 + v02 * c02;
+  double inv[6] = {0, 0, 0, 0, 0, 0};
+  if (det > 0.0 && isfinite(det)) {
+    const double id = 1.0 / det;
+    inv[0] = c00 * id; inv[1] = c01 * id; inv[2] = c02 * id;
+    inv[3] = c11 * id; inv[4] = c12 * id; inv[5] = c22 * id;
+  } else {
+    *bad = 1;
+  }
+  PtRec<T> rec;
+  rec.hp[0] = inv[0] * q[0] + inv[1] * q[1] + inv[2] * q[2];
+  rec.hp[1] = inv[1] * q[0] + inv[3] * q[1] + inv[4] * q[2];
+  rec.hp[2] = inv[2] * q[0] + inv[4] * q[1] + inv[5] * q[2];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) hp[3 * r + i] = rec.hp[i];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    rec.vinv[i] = T(inv[i]);
+    Vinv[6 * r + i] = T(inv[i]);
+  }
+  prec[r] = rec;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_gp_cam_assemble(Compact<T> cp, double lam, double dmin, double dmax,
+                  const GpLin<T>* __restrict__ lin_cm, const V4<T>* __restrict__ a_cm,
+                  const PtRec<T>* __restrict__ prec, T* __restrict__ Ustar,
+                  double* __restrict__ gc, double* __restrict__ b, double* __restrict__ Minv) {
+  constexpr int K = 6 + 1 + 6 + 3 + 3 + 3;   // U, sum a0, sum A Vinv A, g_c, r_c, sum A hp
+  __shared__ double smem[K * (kBlock / kWave)];
+  const int s = blockIdx.x;
+  const int Ca = cp.Ca;
+  double acc[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) acc[i] = 0.0;
+  for (int i = cp.cm_off[s] + threadIdx.x; i < cp.cm_off[s + 1]; i += blockDim.x) {
+    const GpLin<T> L = lin_cm[i];
+    const V4<T> ar = a_cm[i];
+    const PtRec<T> pr = prec[cp.cm_pt[i]];
+    double e[3], a0, q[3];
+    gp_reduce(L, lam, dmin, dmax, e, a0, q);
+    const double w = double(L.w);
+    const double sc = L.s < T(0) ? -double(L.s) : double(L.s);
+    // A (float64 from the record's own values) and A Vinv A
+    double Am[3][3];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        Am[p][k] = (p == k ? double(ar.w) : 0.0) -
+                   double(p == 0 ? ar.x : p == 1 ? ar.y : ar.z) *
+                       double(k == 0 ? ar.x : k == 1 ? ar.y : ar.z);
+    double AV[3][3];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        AV[p][k] = Am[p][0] * double(pr.vinv[sym3(0, k)]) +
+                   Am[p][1] * double(pr.vinv[sym3(1, k)]) +
+                   Am[p][2] * double(pr.vinv[sym3(2, k)]);
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+#pragma unroll
+      for (int k = p; k < 3; ++k) {
+        acc[sym3(p, k)] += Am[p][k];
+        acc[7 + sym3(p, k)] += AV[p][0] * Am[0][k] + AV[p][1] * Am[1][k] + AV[p][2] * Am[2][k];
+      }
+      acc[13 + p] += w * sc * double(L.u[p]);
+      acc[16 + p] -= q[p];
+      acc[19 + p] += Am[p][0] * pr.hp[0] + Am[p][1] * pr.hp[1] + Am[p][2] * pr.hp[2];
+    }
+    acc[6] += a0;
+  }
+  block_sum<double, K>(acc, smem);
+  if (threadIdx.x != 0) return;
+  const double dmp = lam * fmin(fmax(acc[6], dmin), dmax);
+  double Us[6], Sc[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) Us[q] = acc[q];
+  Us[sym3(0, 0)] += dmp;
+  Us[sym3(1, 1)] += dmp;
+  Us[sym3(2, 2)] += dmp;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    Ustar[q * Ca + s] = T(Us[q]);
+    Sc[q] = Us[q] - acc[7 + q];
+  }
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+    gc[p * Ca + s] = acc[13 + p];
+    b[p * Ca + s] = acc[16 + p] + acc[19 + p];
+  }
+  double inv[6];
+  if (!spd_inverse<3>(Sc, inv)) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) inv[q] = 0.0;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      const double d = Us[sym3(p, p)];
+      inv[sym3(p, p)] = d > 0.0 ? 1.0 / d : 0.0;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 6; ++q) Minv[q * Ca + s] = inv[q];
+}
+
+// Point pass: y_p = sum_k A_k u_c, zz_p = V*^-1 y_p stored at the camera-major position of
+// each observation of p in a solve camera. XCD-contiguous point ranges as in BA.
+template <typename T, int G>
+__global__ void __launch_bounds__(kBlock)
+k_gp_schur_point(Compact<T> cp, const V4<T>* __restrict__ a_pm,
+                 const GpMv<T>* __restrict__ mvt, const T* __restrict__ Vinv,
+                 P3<T>* __restrict__ zq_cm, const PcgState* __restrict__ st) {
+  if (st->done) return;
+  const int per = gridDim.x / 8;
+  const int blk = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  const int t = blk * blockDim.x + threadIdx.x;
+  const int r = t / G;
+  const int l = t % G;
+  T y[3] = {T(0), T(0), T(0)};
+  int b = 0, e = 0;
+  const bool live = r < cp.Pa;
+  if (live) {
+    b = cp.off[r];
+    e = cp.off[r + 1];
+    for (int j = b + l; j < e; j += G) {
+      const int s = cp.cam[j];
+      if (s >= cp.Ca) continue;
+      const GpMv<T> mc = mvt[s];
+      T o[3];
+      gp_apply(a_pm[j], mc.u, o);
+      y[0] += o[0];
+      y[1] += o[1];
+      y[2] += o[2];
+    }
+  }
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) {
+    y[0] += __shfl_xor(y[0], o, kWave);
+    y[1] += __shfl_xor(y[1], o, kWave);
+    y[2] += __shfl_xor(y[2], o, kWave);
+  }
+  if (!live) return;
+  T vi[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) vi[q] = Vinv[6 * r + q];
+  P3<T> z;
+  z.x = vi[0] * y[0] + vi[1] * y[1] + vi[2] * y[2];
+  z.y = vi[1] * y[0] + vi[3] * y[1] + vi[4] * y[2];
+  z.z = vi[2] * y[0] + vi[4] * y[1] + vi[5] * y[2];
+  for (int j = b + l; j < e; j += G) {
+    const int pos = cp.pm_cm[j];
+    if (pos >= 0) zq_cm[pos] = z;
+  }
+}
+
+// Camera pass in the items of the BA camera pass: partial i = sum A_k zz_k over the item.
+template <typename T>
+__global__ void __launch_bounds__(kCamBlock)
+k_gp_schur_cam(Compact<T> cp, const V4<T>* __restrict__ a_cm, const double* __restrict__ u,
+               const P3<T>* __restrict__ zq, int K, const int* __restrict__ item_off,
+               const int* __restrict__ item_cam, int nslot, double* __restrict__ part,
+               const PcgState* __restrict__ st) {
+  if (st->done) return;
+  const int Ca = cp.Ca;
+  const int i = blockIdx.x;
+  if (i >= item_off[Ca]) {
+    if (threadIdx.x == 0) part[3 * nslot + i] = 0.0;
+    return;
+  }
+  const int s = item_cam[i];
+  const int sb = cp.cm_off[s] + (i - item_off[s]) * K;
+  const int se = min(sb + K, cp.cm_off[s + 1]);
+  double us[3];
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) us[q] = u[q * Ca + s];
+  }
+  __shared__ T smem[3 * (kCamBlock / kWave)];
+  T acc[3] = {T(0), T(0), T(0)};
+#pragma unroll 2
+  for (int k = sb + threadIdx.x; k < se; k += kCamBlock) {
+    const P3<T> zv = zq[k];
+    const T z3[3] = {zv.x, zv.y, zv.z};
+    T o[3];
+    gp_apply(a_cm[k], z3, o);
+    acc[0] += o[0];
+    acc[1] += o[1];
+    acc[2] += o[2];
+  }
+  block_sum<T, 3>(acc, smem);
+  if (threadIdx.x == 0) {
+    double pd = 0.0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const double v = double(acc[q]);
+      part[q * nslot + i] = v;
+      pd += us[q] * v;
+    }
+    part[3 * nslot + i] = pd;
+  }
+}
+
+template <typename T, int G>
+__global__ void __launch_bounds__(kBlock)
+k_gp_backsub(Compact<T> cp, const V4<T>* __restrict__ a_pm, const T* __restrict__ Vinv,
+             const double* __restrict__ hp, const double* __restrict__ x,
+             double* __restrict__ dp) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = t / G;
+  const int l = t % G;
+  const int Ca = cp.Ca;
+  double y[3] = {0.0, 0.0, 0.0};
+  if (r < cp.Pa) {
+    for (int j = cp.off[r] + l; j < cp.off[r + 1]; j += G) {
+      const int s = cp.cam[j];
+      if (s >= Ca) continue;
+      const V4<T> a = a_pm[j];
+      const double dc[3] = {x[s], x[Ca + s], x[2 * Ca + s]};
+      const double ex = double(a.x) * dc[0] + double(a.y) * dc[1] + double(a.z) * dc[2];
+      y[0] += double(a.w) * dc[0] - double(a.x) * ex;
+      y[1] += double(a.w) * dc[1] - double(a.y) * ex;
+      y[2] += double(a.w) * dc[2] - double(a.z) * ex;
+    }
+  }
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) y[i] += __shfl_xor(y[i], o, kWave);
+  }
+  if (r >= cp.Pa || l != 0) return;
+  double vi[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) vi[q] = double(Vinv[6 * r + q]);
+  dp[3 * r] = hp[3 * r] + vi[0] * y[0] + vi[1] * y[1] + vi[2] * y[2];
+  dp[3 * r + 1] = hp[3 * r + 1] + vi[1] * y[0] + vi[3] * y[1] + vi[4] * y[2];
+  dp[3 * r + 2] = hp[3 * r + 2] + vi[2] * y[0] + vi[4] * y[1] + vi[5] * y[2];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_gp_candidate(Compact<T> cp, const int* __restrict__ orig, const double* __restrict__ scales,
+               double delta, double lam, double dmin, double dmax, const double* __restrict__ x,
+               const double* __restrict__ dp, const double* __restrict__ gX,
+               double* __restrict__ Xcand, double* __restrict__ s_cand,
+               double* __restrict__ partials) {
+  __shared__ double smem[5 * (kBlock / kWave)];
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int Ca = cp.Ca;
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // decrease, quad, g.delta, bad, cost'
+  if (r < cp.Pa) {
+    const double X[3] = {cp.Xd[3 * r], cp.Xd[3 * r + 1], cp.Xd[3 * r + 2]};
+    const double dX[3] = {dp[3 * r], dp[3 * r + 1], dp[3 * r + 2]};
+    const double Xn[3] = {X[0] + dX[0], X[1] + dX[1], X[2] + dX[2]};
+    Xcand[3 * r] = Xn[0];
+    Xcand[3 * r + 1] = Xn[1];
+    Xcand[3 * r + 2] = Xn[2];
+    acc[2] = gX[3 * r] * dX[0] + gX[3 * r + 1] * dX[1] + gX[3 * r + 2] * dX[2];
+    for (int j = cp.off[r]; j < cp.off[r + 1]; ++j) {
+      const int s = cp.cam[j];
+      const Cam<double> cm = cp.camd[s];
+      const float dh = cp.depth[j];
+      const GpObs o = gp_obs(cm, cp.xy[j], dh, X, dh > 0.0f ? 0.0 : scales[orig[j]]);
+      double rho0, w, d2;
+      huber(o.u[0] * o.u[0] + o.u[1] * o.u[1] + o.u[2] * o.u[2], delta, rho0, w, d2);
+      double dc[3] = {0.0, 0.0, 0.0};
+      if (s < Ca) {
+        dc[0] = x[s];
+        dc[1] = x[Ca + s];
+        dc[2] = x[2 * Ca + s];
+      }
+      const double dd[3] = {dc[0] - dX[0], dc[1] - dX[1], dc[2] - dX[2]};
+      double ds = 0.0;
+      if (!o.pinned) {
+        const double h = w * (o.d[0] * o.d[0] + o.d[1] * o.d[1] + o.d[2] * o.d[2]);
+        const double hs = h + lam * fmin(fmax(h, dmin), dmax);
+        const double gs = -w * (o.d[0] * o.u[0] + o.d[1] * o.u[1] + o.d[2] * o.u[2]);
+        ds = (-gs + w * o.s * (o.d[0] * dd[0] + o.d[1] * dd[1] + o.d[2] * dd[2])) / hs;
+        acc[2] += gs * ds;
+      }
+      const double sn = o.s + ds;
+      s_cand[j] = sn;
+      // model term at the linearisation point: J delta = s (dc - dX) - d ds
+      double jd[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) jd[i] = o.s * dd[i] - o.d[i] * ds;
+      acc[1] += w * (jd[0] * jd[0] + jd[1] * jd[1] + jd[2] * jd[2]);
+      if (!o.pinned && !(sn > 0.0)) {
+        acc[3] += 1.0;
+      } else {
+        double u2[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) u2[i] = o.v[i] - sn * (Xn[i] - (cm.c[i] + dc[i]));
+        double rho, d1;
+        huber(u2[0] * u2[0] + u2[1] * u2[1] + u2[2] * u2[2], delta, rho, d1, d2);
+        acc[0] += 0.5 * (rho0 - rho);
+        acc[4] += 0.5 * rho;
+      }
+    }
+  }
+  block_sum<double, 5>(acc, smem);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < 5; ++i) partials[5 * blockIdx.x + i] = acc[i];
+  }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_gp_scatter(int Pa, int Ca, int64_t Nh, const int* __restrict__ pt_src,
+             const double* __restrict__ Xcand, const int* __restrict__ cam_src,
+             const double* __restrict__ x, const float* __restrict__ depth_hat,
+             const int* __restrict__ orig, const double* __restrict__ s_cand,
+             double* __restrict__ pts, double* __restrict__ cams, double* __restrict__ scales) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < Pa) {
+    const int p = pt_src[i];
+    pts[3 * p] = Xcand[3 * i];
+    pts[3 * p + 1] = Xcand[3 * i + 1];
+    pts[3 * p + 2] = Xcand[3 * i + 2];
+  }
+  if (i < Ca) {
+    const int c = cam_src[i];
+    cams[7 * c + 4] += x[i];
+    cams[7 * c + 5] += x[Ca + i];
+    cams[7 * c + 6] += x[2 * Ca + i];
+  }
+  if (i < Nh && !(depth_hat[i] > 0.0f)) scales[orig[i]] = s_cand[i];
+}
+
 inline unsigned blocks_for(int64_t n, int b = kBlock) { return unsigned((n + b - 1) / b); }
 
 }  // namespace
@@ -1819,12 +2382,21 @@ void launch_mv_table(hipStream_t s, int D, int n, const Cam<double>* camd_hat, v
   });
 }
 
+// The PCG vector kernels also serve global positioning (D = 3).
+template <class F>
+void with_dim_pcg(int D, F&& f) {
+  if (D == 3)
+    f(std::integral_constant<int, 3>{});
+  else
+    with_dim(D, f);
+}
+
 template <typename T>
 void launch_pcg_init(hipStream_t s, int D, int Ca, const double* b, const double* Minv,
                      const T* Ustar, const int* cm_off, int K, int* item_off, int* item_cam,
                      double* x, double* r, double* u, double* p, double* sv, double* Uu,
                      double* terms, void* mvt, PcgState* st, double tol2, int max_iter) {
-  with_dim(D, [&](auto Dc) {
+  with_dim_pcg(D, [&](auto Dc) {
     launch_k(k_pcg_init<T, Dc()>, dim3(1), dim3(1024), 0, s, Ca, b, Minv, Ustar, cm_off, K,
              item_off, item_cam, x, r, u, p, sv, Uu, terms, static_cast<MvRec<T, Dc()>*>(mvt),
              st, tol2, max_iter);
@@ -1903,7 +2475,7 @@ void launch_pcg_update(hipStream_t s, int D, int Ca, int k, const double* Minv, 
                        double* x, double* r, double* u, double* p, double* sv, double* Uu,
                        void* mvt, PcgState* st) {
   if (Ca <= 0) return;
-  with_dim(D, [&](auto Dc) {
+  with_dim_pcg(D, [&](auto Dc) {
     launch_k(k_pcg_update<T, Dc()>, dim3((Ca + kUpdCams - 1) / kUpdCams), dim3(kUpdBlock), 0,
              s, Ca, k, Minv, Ustar, item_off, nslot, part, terms, x, r, u, p, sv, Uu,
              static_cast<MvRec<T, Dc()>*>(mvt), st);
@@ -2033,6 +2605,139 @@ void launch_adjoint_obs(hipStream_t s, const Model& m, const Compact<T>& cp, Obs
 
 IBA_INSTANTIATE(float)
 IBA_INSTANTIATE(double)
+
+// ------------------------------------------------------------------ global positioning launchers
+template <class F>
+void with_lanes(int G, F&& f) {
+  switch (G) {
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 16: f(std::integral_constant<int, 16>{}); break;
+    default: f(std::integral_constant<int, 8>{});
+  }
+}
+
+void launch_gp_validate(hipStream_t s, int64_t N, const float2* pm_xy, const float* pm_depth,
+                        const int* inv_cm, uint8_t* vrow, uint8_t* vrow_cm) {
+  if (N == 0) return;
+  launch_k(k_gp_validate, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, pm_xy, pm_depth, inv_cm,
+           vrow, vrow_cm);
+}
+
+void launch_gp_init_scales(hipStream_t s, int64_t N, const int* pm_cam, const int* pm_pt,
+                           const int* pm_orig, const float2* pm_xy, const float* pm_depth,
+                           const double* pts, const Cam<double>* camd, double* scales) {
+  if (N == 0) return;
+  launch_k(k_gp_init_scales, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, pm_cam, pm_pt, pm_orig,
+           pm_xy, pm_depth, pts, camd, scales);
+}
+
+template <typename T>
+void launch_gp_lin(hipStream_t s, int G, const Compact<T>& cp, const int* orig,
+                   const double* scales, double delta, GpLin<T>* lin_pm, GpLin<T>* lin_cm,
+                   double* gX, double* partials) {
+  with_lanes(G, [&](auto Gc) {
+    launch_k(k_gp_lin<T, Gc()>, dim3(lin_point_blocks(cp.Pa)), dim3(kBlock), 0, s, cp, orig,
+             scales, delta, lin_pm, lin_cm, gX, partials);
+  });
+}
+
+template <typename T>
+void launch_gp_point_setup(hipStream_t s, int G, const Compact<T>& cp, double lam, double dmin,
+                           double dmax, const GpLin<T>* lin_pm, V4<T>* a_pm, V4<T>* a_cm,
+                           T* Vinv, double* hp, PtRec<T>* prec, int* bad) {
+  if (cp.Pa == 0) return;
+  with_lanes(G, [&](auto Gc) {
+    launch_k(k_gp_point_setup<T, Gc()>, dim3(blocks_for(int64_t(cp.Pa) * Gc())), dim3(kBlock),
+             0, s, cp, lam, dmin, dmax, lin_pm, a_pm, a_cm, Vinv, hp, prec, bad);
+  });
+}
+
+template <typename T>
+void launch_gp_cam_assemble(hipStream_t s, const Compact<T>& cp, double lam, double dmin,
+                            double dmax, const GpLin<T>* lin_cm, const V4<T>* a_cm,
+                            const PtRec<T>* prec, T* Ustar, double* gc, double* b,
+                            double* Minv) {
+  if (cp.Ca == 0) return;
+  launch_k(k_gp_cam_assemble<T>, dim3(cp.Ca), dim3(kBlock), 0, s, cp, lam, dmin, dmax, lin_cm,
+           a_cm, prec, Ustar, gc, b, Minv);
+}
+
+template <typename T>
+void launch_gp_schur_point(hipStream_t s, int G, const Compact<T>& cp, const V4<T>* a_pm,
+                           const void* mvt, const T* Vinv, P3<T>* zq_cm, const PcgState* st) {
+  if (cp.Pa == 0) return;
+  with_lanes(G, [&](auto Gc) {
+    const unsigned nb = (blocks_for(int64_t(cp.Pa) * Gc()) + 7) / 8 * 8;
+    launch_k(k_gp_schur_point<T, Gc()>, dim3(nb), dim3(kBlock), 0, s, cp, a_pm,
+             static_cast<const GpMv<T>*>(mvt), Vinv, zq_cm, st);
+  });
+}
+
+template <typename T>
+void launch_gp_schur_cam(hipStream_t s, const Compact<T>& cp, const V4<T>* a_cm,
+                         const double* u, const P3<T>* zq, int K, const int* item_off,
+                         const int* item_cam, int nslot, double* part, const PcgState* st) {
+  if (cp.Ca <= 0 || nslot <= 0) return;
+  launch_k(k_gp_schur_cam<T>, dim3(nslot), dim3(kCamBlock), 0, s, cp, a_cm, u, zq, K, item_off,
+           item_cam, nslot, part, st);
+}
+
+template <typename T>
+void launch_gp_backsub(hipStream_t s, int G, const Compact<T>& cp, const V4<T>* a_pm,
+                       const T* Vinv, const double* hp, const double* x, double* dp) {
+  if (cp.Pa == 0) return;
+  with_lanes(G, [&](auto Gc) {
+    launch_k(k_gp_backsub<T, Gc()>, dim3(blocks_for(int64_t(cp.Pa) * Gc())), dim3(kBlock), 0, s,
+             cp, a_pm, Vinv, hp, x, dp);
+  });
+}
+
+template <typename T>
+void launch_gp_candidate(hipStream_t s, const Compact<T>& cp, const int* orig,
+                         const double* scales, double delta, double lam, double dmin,
+                         double dmax, const double* x, const double* dp, const double* gX,
+                         double* Xcand, double* s_cand, double* partials) {
+  if (cp.Pa == 0) return;
+  launch_k(k_gp_candidate<T>, dim3(blocks_for(cp.Pa)), dim3(kBlock), 0, s, cp, orig, scales,
+           delta, lam, dmin, dmax, x, dp, gX, Xcand, s_cand, partials);
+}
+
+void launch_gp_scatter(hipStream_t s, int Pa, int Ca, int64_t Nh, const int* pt_src,
+                       const double* Xcand, const int* cam_src, const double* x,
+                       const float* depth_hat, const int* orig, const double* s_cand,
+                       double* pts, double* cams, double* scales) {
+  const int64_t n = std::max<int64_t>(Nh, std::max(Pa, Ca));
+  if (n == 0) return;
+  launch_k(k_gp_scatter, dim3(blocks_for(n)), dim3(kBlock), 0, s, Pa, Ca, Nh, pt_src, Xcand,
+           cam_src, x, depth_hat, orig, s_cand, pts, cams, scales);
+}
+
+#define IBA_GP_INSTANTIATE(T)                                                                  \
+  template void launch_gp_lin<T>(hipStream_t, int, const Compact<T>&, const int*,             \
+                                 const double*, double, GpLin<T>*, GpLin<T>*, double*,        \
+                                 double*);                                                     \
+  template void launch_gp_point_setup<T>(hipStream_t, int, const Compact<T>&, double, double, \
+                                         double, const GpLin<T>*, V4<T>*, V4<T>*, T*, double*,\
+                                         PtRec<T>*, int*);                                     \
+  template void launch_gp_cam_assemble<T>(hipStream_t, const Compact<T>&, double, double,     \
+                                          double, const GpLin<T>*, const V4<T>*,              \
+                                          const PtRec<T>*, T*, double*, double*, double*);    \
+  template void launch_gp_schur_point<T>(hipStream_t, int, const Compact<T>&, const V4<T>*,   \
+                                         const void*, const T*, P3<T>*, const PcgState*);     \
+  template void launch_gp_schur_cam<T>(hipStream_t, const Compact<T>&, const V4<T>*,          \
+                                       const double*, const P3<T>*, int, const int*,          \
+                                       const int*, int, double*, const PcgState*);            \
+  template void launch_gp_backsub<T>(hipStream_t, int, const Compact<T>&, const V4<T>*,       \
+                                     const T*, const double*, const double*, double*);        \
+  template void launch_gp_candidate<T>(hipStream_t, const Compact<T>&, const int*,            \
+                                       const double*, double, double, double, double,         \
+                                       const double*, const double*, const double*, double*,  \
+                                       double*, double*);
+
+IBA_GP_INSTANTIATE(float)
+IBA_GP_INSTANTIATE(double)
+
 
 void set_launch_events(hipEvent_t start, hipEvent_t stop) {
   g_ev_start = start;
