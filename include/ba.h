@@ -113,6 +113,9 @@ typedef struct ba_step_report {
   double rms_px;           /* sqrt(mean |r_2d|^2) over the active observations, before */
   double grad_inf;         /* max |g| over the compact parameters, before */
   double ms_extract, ms_linearize, ms_setup, ms_pcg, ms_candidate, ms_total;
+                           /* host wall times per phase; without timing the linearisation and
+                              setup are not waited for separately, so their device time shows
+                              in the next phase that synchronises */
 } ba_step_report;
 
 typedef struct ba_solve_report {

@@ -717,7 +717,7 @@ ba_status lm_step_impl(ba_ctx& c, ba_step_report* rep) {
     }
     ta = now_ms();
     linearize<T>(c, false);
-    c.sync();
+    if (c.opt.timing) c.sync();   // phase times only; the stream orders the work
     t_lin = now_ms() - ta;
     c.lin_valid = true;
   }
@@ -728,7 +728,7 @@ ba_status lm_step_impl(ba_ctx& c, ba_step_report* rep) {
 
   double ta = now_ms();
   setup_system<T>(c, false, c.lam, nullptr, nullptr);
-  c.sync();
+  if (c.opt.timing) c.sync();
   t_setup = now_ms() - ta;
   c.blocks_valid = true;
 
