@@ -68,6 +68,8 @@ def parse():
                          "(true rotations, perturbed centres and points, free scales where the "
                          "depth prior is invalid)")
     ap.add_argument("--gp-huber", type=float, default=0.1)
+    ap.add_argument("--solver", default="implicit", choices=["implicit", "explicit"],
+                    help="matrix-free Schur PCG, or PCG on the assembled reduced camera system")
     ap.add_argument("--verbose", action="store_true")
     return ap.parse_args()
 
@@ -102,7 +104,8 @@ def run_gpu(sc, precision, steps, warmup, args, torch, timing):
                         huber_px=sc.huber_px, filter_px=sc.filter_px, img_w=sc.img_w,
                         img_h=sc.img_h, pcg_rel_tol=args.pcg_tol, pcg_max_iters=args.pcg_max,
                         pcg_check_every=args.check_every, timing=timing,
-                        refine_focal=int(args.refine_focal), gp_huber=args.gp_huber)
+                        refine_focal=int(args.refine_focal), gp_huber=args.gp_huber,
+                        solver=args.solver)
     ba.set_observations(t(sc.cam_idx, torch.int32), t(sc.pt_idx, torch.int32),
                         t(sc.xy, torch.float32))
     if sc.use_depth:
@@ -368,7 +371,8 @@ def main():
         sc = focal_start(sc)
     if args.gp:
         sc = gp_start(sc)
-    workload_key = args.scene + ("+focal" if args.refine_focal else "") + ("+gp" if args.gp else "")
+    workload_key = (args.scene + ("+focal" if args.refine_focal else "") +
+                    ("+gp" if args.gp else "") + ("+explicit" if args.solver == "explicit" else ""))
     t_gen = time.perf_counter() - t0
     if args.verbose:
         print(f"scene {args.scene}: C={sc.n_cams} P={sc.n_points} N={sc.n_obs} "
@@ -414,9 +418,11 @@ def main():
                                 + (f"; global positioning: true rotations, camera centres, "
                                    f"points and {100 * (1 - sc.depth_valid.mean()):.0f}% free "
                                    f"scales, Huber {args.gp_huber:g} on the ray residual"
-                                   if args.gp else "")),
+                                   if args.gp else "")
+                                + ("; explicit reduced camera system (assembled 6x6 blocks)"
+                                   if args.solver == "explicit" else "")),
                    "pcg_rel_tol": args.pcg_tol, "pcg_max_iters": args.pcg_max,
-                   "pcg_check_every": args.check_every},
+                   "pcg_check_every": args.check_every, "solver": args.solver},
         "obs_per_s": round(summ["obs_per_s"], 1),
         "jacobian_obs_per_s": (round(summ["jacobian_obs_per_s"], 1)
                                if summ["jacobian_obs_per_s"] else None),

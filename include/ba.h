@@ -58,6 +58,14 @@ typedef int32_t ba_status;
                                  (rows: 2 per observation, +1 with a valid depth prior) */
 #define BA_ACTIVITY_LITERAL 1 /* active with >= 1 valid observation (Eqs. (11)-(12)) */
 
+#define BA_SOLVER_IMPLICIT 0  /* PCG on the camera Schur complement applied matrix-free: two
+                                 passes over the observations per iteration (Sec. IV-B) */
+#define BA_SOLVER_EXPLICIT 1  /* the same PCG on the reduced camera system assembled as D x D
+                                 blocks: per extraction the block pattern (a stable sort of the
+                                 camera pairs of every point), per LM step the blocks
+                                 S_ij = -sum_p W_ip V*_p^-1 W_jp^T, per iteration one sparse
+                                 block product. The adjoint always runs matrix-free */
+
 typedef struct ba_options {
   int32_t precision;       /* BA_PRECISION_*; default MIXED */
   int32_t img_w, img_h;    /* frustum for the validity test; default 640 x 480 */
@@ -78,6 +86,7 @@ typedef struct ba_options {
   int32_t max_lm_iters;    /* ba_solve iteration cap; 100 */
   int32_t timing;          /* 1: time phases and kernels with HIP events (ba_kernel_stats) */
   int32_t adjoint_max_iters;/* PCG cap of the (undamped) adjoint solve; 5000 */
+  int32_t solver;          /* BA_SOLVER_*; default IMPLICIT */
   int32_t refine_focal;    /* 1: the focal length f of each camera's intrinsics (Sec. III-B
                               lists K among the BA parameters) is a seventh camera unknown:
                               7 x 7 camera blocks, de/df = (x/z, y/z, 0), additive update, a

@@ -215,6 +215,7 @@ def ba_destroy(ctx: int) -> None:
 # ---------------------------------------------------------------- owning wrapper
 _PRECISION = {"fp64": 0, "mixed": 1}
 _RULE = {"rows": 0, "literal": 1}
+_SOLVER = {"implicit": 0, "explicit": 1}
 
 
 def make_options(precision="mixed", **kw) -> BaOptions:
@@ -222,6 +223,8 @@ def make_options(precision="mixed", **kw) -> BaOptions:
     o.precision = _PRECISION[precision] if isinstance(precision, str) else int(precision)
     if "activity_rule" in kw and isinstance(kw["activity_rule"], str):
         kw["activity_rule"] = _RULE[kw["activity_rule"]]
+    if "solver" in kw and isinstance(kw["solver"], str):
+        kw["solver"] = _SOLVER[kw["solver"]]
     if "stream" in kw:
         kw["hip_stream"] = kw.pop("stream")
     names = {f for f, _ in BaOptions._fields_}

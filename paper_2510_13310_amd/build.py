@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB_NAME = "libinstantba.so"
 LIB_PATH = os.path.join(HERE, LIB_NAME)
-SOURCES = ["ba_kernels.hip", "ba_api.hip"]
+SOURCES = ["ba_kernels.hip", "ba_api.hip", "ba_sort.hip"]
 ARCH = "gfx950"
 
 COMMON = [

@@ -142,6 +142,23 @@ struct ba_ctx {
          *wv = nullptr, *dots = nullptr, *part = nullptr;
   int *item_off = nullptr, *item_cam = nullptr;   // camera-pass items
 
+  // explicit reduced camera system (solver = BA_SOLVER_EXPLICIT), sized per extraction
+  Arena ex;
+  int64_t ex_cap = 0;                 // contributions the buffers hold
+  int64_t ex_bytes = 0;               // bytes of the contribution-sized buffers
+  int64_t ex_nc = 0, ex_nb = 0;       // contributions, off-diagonal blocks
+  uint32_t *ex_key = nullptr, *ex_skey = nullptr;
+  uint64_t *ex_val = nullptr, *ex_sval = nullptr;   // (a, b) point-major positions
+  int* ex_pm_rank = nullptr;
+  int64_t *ex_flag = nullptr, *ex_bidx = nullptr, *ex_cnt = nullptr, *ex_coff = nullptr;
+  uint32_t* ex_bkey = nullptr;
+  int64_t *ex_bstart = nullptr, *ex_row_ptr = nullptr;
+  void* ex_sblk = nullptr;
+  double* ex_scc = nullptr;
+  void* ex_tmp = nullptr;
+  size_t ex_tmp_bytes = 0;
+  bool ex_valid = false;              // pattern of the current extraction
+
   // global positioning (allocated on its first step)
   double* gp_s = nullptr;                       // N scales, caller's observation order
   double* gp_scand = nullptr;                   // compact candidate scales
@@ -168,7 +185,25 @@ struct ba_ctx {
   std::vector<Pending> pending;
   std::vector<hipEvent_t> pool;
 
+  void release_explicit() {
+    for (void* p : {(void*)ex_key, (void*)ex_val, (void*)ex_skey, (void*)ex_sval,
+                    (void*)ex_flag, (void*)ex_bidx, (void*)ex_bkey, (void*)ex_bstart, ex_sblk,
+                    ex_tmp})
+      if (p) (void)hipFree(p);
+    ex_key = ex_skey = ex_bkey = nullptr;
+    ex_val = ex_sval = nullptr;
+    ex_pm_rank = nullptr;
+    ex_flag = ex_bidx = ex_cnt = ex_coff = ex_bstart = ex_row_ptr = nullptr;
+    ex_sblk = ex_tmp = nullptr;
+    ex_scc = nullptr;
+    ex_tmp_bytes = 0;
+    ex_cap = ex_nc = ex_nb = ex_bytes = 0;
+    ex_valid = false;
+    ex.release();
+  }
+
   ~ba_ctx() {
+    release_explicit();
     for (auto& pe : pending) {
       (void)hipEventDestroy(pe.a);
       (void)hipEventDestroy(pe.b);
@@ -328,6 +363,7 @@ ba_status guarded(ba_ctx* c, F&& f) {
 
 // ------------------------------------------------------------------ buffers
 void alloc_obs_buffers(ba_ctx& c) {
+  c.release_explicit();
   c.obs.release();
   Arena& A = c.obs;
   const int64_t N = c.N;
@@ -595,6 +631,119 @@ void linearize(ba_ctx& c, bool adj) {
   HIP_LAUNCH_CHECK();
 }
 
+bool explicit_solver(const ba_ctx& c) { return c.opt.solver == BA_SOLVER_EXPLICIT; }
+
+// Block pattern of the reduced camera system for the current extraction: every ordered pair of
+// distinct solve-camera observations of a point is one contribution, keyed by its camera pair;
+// a stable sort groups the contributions of each block in point order.
+template <typename T>
+void build_schur_pattern(ba_ctx& c) {
+  hipStream_t s = c.stream;
+  Compact<T> cp = compact_view<T>(c);
+  const int Pa = c.Pa;
+  if (!c.ex_pm_rank) {
+    c.ex_pm_rank = c.ex.alloc<int>(size_t(c.N));
+    c.ex_cnt = c.ex.alloc<int64_t>(size_t(c.P) + 1);
+    c.ex_coff = c.ex.alloc<int64_t>(size_t(c.P) + 1);
+    c.ex_row_ptr = c.ex.alloc<int64_t>(size_t(c.C) + 1);
+    c.ex_scc = c.ex.alloc<double>(size_t(c.D) * (c.D + 1) / 2 * size_t(c.C));
+  }
+  HIP_CHECK(hipMemsetAsync(c.ex_cnt + Pa, 0, sizeof(int64_t), s));
+  c.timed_multi("schur_pattern", double(c.Nh) * 8 + double(Pa) * 16, [&] {
+    launch_pair_counts<T>(s, cp, c.ex_cnt, c.ex_pm_rank);
+  });
+  size_t tb = exclusive_sum_temp_bytes(Pa + 1);
+  void* tmp = nullptr;
+  Arena scan_tmp;
+  tmp = scan_tmp.alloc<char>(tb);
+  HIP_CHECK(exclusive_sum(tmp, tb, c.ex_cnt, c.ex_coff, Pa + 1, s));
+  int64_t nc = 0;
+  HIP_CHECK(hipMemcpyAsync(&nc, c.ex_coff + Pa, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  c.sync();
+  scan_tmp.release();
+  if (nc >= (int64_t(1) << 31))
+    throw BaError{BA_ERR_ARG, "explicit reduced system: more than 2^31 block contributions"};
+  if (int64_t(c.Ca) * int64_t(c.Ca) >= (int64_t(1) << 32))
+    throw BaError{BA_ERR_ARG, "explicit reduced system: too many cameras for 32-bit block keys"};
+  c.ex_nc = nc;
+  c.ex_nb = 0;
+  int end_bit = 1;
+  while ((uint64_t(1) << end_bit) < uint64_t(c.Ca) * uint64_t(c.Ca)) ++end_bit;
+  if (nc > c.ex_cap) {
+    // contribution-sized buffers grow with the pattern (25 % headroom)
+    const int64_t cap = nc + nc / 4 + 1024;
+    for (void* p : {(void*)c.ex_key, (void*)c.ex_val, (void*)c.ex_skey, (void*)c.ex_sval,
+                    (void*)c.ex_flag, (void*)c.ex_bidx, (void*)c.ex_bkey, (void*)c.ex_bstart,
+                    c.ex_sblk, c.ex_tmp})
+      if (p) (void)hipFree(p);
+    c.ex_bytes = 0;
+    auto grab = [&](size_t bytes) {
+      void* p = nullptr;
+      bytes = std::max<size_t>(bytes, 256);
+      if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        throw BaError{BA_ERR_OOM, "explicit reduced system: device allocation failed"};
+      }
+      c.ex_bytes += int64_t(bytes);
+      return p;
+    };
+    c.ex_key = static_cast<uint32_t*>(grab(4 * size_t(cap)));
+    c.ex_val = static_cast<uint64_t*>(grab(8 * size_t(cap)));
+    c.ex_skey = static_cast<uint32_t*>(grab(4 * size_t(cap)));
+    c.ex_sval = static_cast<uint64_t*>(grab(8 * size_t(cap)));
+    c.ex_flag = static_cast<int64_t*>(grab(8 * size_t(cap)));
+    c.ex_bidx = static_cast<int64_t*>(grab(8 * size_t(cap)));
+    c.ex_bkey = static_cast<uint32_t*>(grab(4 * size_t(cap)));
+    c.ex_bstart = static_cast<int64_t*>(grab(8 * (size_t(cap) + 1)));
+    c.ex_sblk = grab(size_t(c.tsize()) * size_t(c.D) * c.D * size_t(cap));
+    c.ex_tmp_bytes = std::max(sort_pairs64_temp_bytes(int(cap), 32),
+                              exclusive_sum_temp_bytes(int(cap)));
+    c.ex_tmp = grab(c.ex_tmp_bytes);
+    c.ex_cap = cap;
+  }
+  if (nc > 0) {
+    c.timed_multi("schur_pattern", double(Pa) * 24 + double(nc) * 12, [&] {
+      launch_pair_keys<T>(s, cp, c.ex_coff, c.ex_key, c.ex_val);
+    });
+    c.timed_multi("schur_pattern", double(nc) * 48, [&] {
+      HIP_CHECK(sort_pairs64(c.ex_tmp, c.ex_tmp_bytes, c.ex_key, c.ex_skey, c.ex_val,
+                             c.ex_sval, int(nc), end_bit, s));
+    });
+    launch_run_flags(s, nc, c.ex_skey, c.ex_flag);
+    HIP_CHECK(exclusive_sum(c.ex_tmp, c.ex_tmp_bytes, c.ex_flag, c.ex_bidx, int(nc), s));
+    int64_t tail[2] = {0, 0};
+    HIP_CHECK(hipMemcpyAsync(&tail[0], c.ex_bidx + nc - 1, sizeof(int64_t),
+                             hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipMemcpyAsync(&tail[1], c.ex_flag + nc - 1, sizeof(int64_t),
+                             hipMemcpyDeviceToHost, s));
+    c.sync();
+    c.ex_nb = tail[0] + tail[1];
+    launch_block_list(s, nc, c.ex_skey, c.ex_flag, c.ex_bidx, c.ex_bkey, c.ex_bstart);
+    HIP_CHECK(hipMemcpyAsync(c.ex_bstart + c.ex_nb, &nc, sizeof(int64_t), hipMemcpyHostToDevice,
+                             s));
+  }
+  launch_block_rows(s, c.Ca, c.ex_nb, c.ex_bkey, c.ex_row_ptr);
+  HIP_LAUNCH_CHECK();
+  c.sync();   // the host values above are stack copies
+  c.ex_valid = true;
+}
+
+// Off-diagonal blocks at the current damping (V*^-1 from the point setup).
+template <typename T>
+void assemble_schur_blocks(ba_ctx& c) {
+  if (c.ex_nb == 0) return;
+  const double ts = double(c.tsize());
+  const double DD = double(c.D) * c.D;
+  c.timed("schur_blocks",
+          double(c.ex_nc) * (8 + 4 + 2 * 4 * ts + 6 * ts) + double(c.ex_nb) * (4 + 8 + DD * ts),
+          -1, [&] {
+            launch_schur_blocks<T>(c.stream, c.D, c.model(), compact_view<T>(c), metric_view<T>(c),
+                                   static_cast<const T*>(c.Vinv), c.ex_pm_rank, c.ex_nb,
+                                   c.ex_bkey, c.ex_bstart, c.ex_sval,
+                                   static_cast<T*>(c.ex_sblk));
+          });
+}
+
 // Damping-dependent setup: point inverses, camera blocks, Schur RHS, preconditioner.
 template <typename T>
 void setup_system(ba_ctx& c, bool adj, double lam, const double* rhs_c, const double* rhs_p) {
@@ -619,7 +768,8 @@ void setup_system(ba_ctx& c, bool adj, double lam, const double* rhs_c, const do
           -1, [&] {
             launch_cam_assemble<T>(s, adj, c.D, m, cp, om, lam, c.opt.diag_min, c.opt.diag_max,
                                    static_cast<const PtRec<T>*>(c.prec), rhs_c, c.Uraw,
-                                   static_cast<T*>(c.Ustar), c.gc, c.b, c.Minv);
+                                   static_cast<T*>(c.Ustar), c.gc, c.b, c.Minv,
+                                   explicit_solver(c) && !adj ? c.ex_scc : nullptr);
           });
 }
 
@@ -642,6 +792,11 @@ int run_pcg(ba_ctx& c, bool adj, double rel_tol, int max_iters, PcgState* out_st
   const T* Ustar = static_cast<const T*>(c.Ustar);
   int K = 0, nch = 0;
   cam_chunking(c.Nc, K, nch);
+  const bool expl = explicit_solver(c) && !adj;
+  if (expl) {   // one item per camera: the product of the explicit system is its partial
+    K = std::numeric_limits<int>::max() / 2;
+    nch = 0;
+  }
   launch_pcg_init<T>(s, c.D, c.Ca, c.b, c.Minv, Ustar, c.cm_off_hat, K, c.item_off, c.item_cam,
                      c.x, c.r, c.u, c.p, c.sv, c.wv, c.dots, mvt, c.pcg, rel_tol * rel_tol,
                      max_iters);
@@ -649,19 +804,31 @@ int run_pcg(ba_ctx& c, bool adj, double rel_tol, int max_iters, PcgState* out_st
   const int nslot = c.Ca + nch;
   const int every = std::max(1, c.opt.pcg_check_every);
   const double bp = bytes_schur_point(c), bc = bytes_schur_cam(c), bu = bytes_pcg_update(c);
+  // explicit product: every block (D x D values and its key) and the row pointers once, the
+  // camera vectors and S_cc
+  const double bs = double(c.ex_nb) * (4 + double(c.D) * c.D * double(sizeof(T))) +
+                    double(c.Ca) * (8 + double(c.D) * (c.D + 1) / 2 * 8 + 3 * c.D * 8 + 8);
   const int G = lanes_per_point(c);
   P3<T>* zq = static_cast<P3<T>*>(c.zq);
   int it = 0;
   while (true) {
     for (int k = 0; k < every && it < max_iters; ++k, ++it) {
-      c.timed("schur_point", bp, it, [&] {
-        launch_schur_point<T>(s, adj, c.D, G, m, cp, om, mvt, static_cast<const T*>(c.Vinv), zq,
-                              c.pcg, c.dl);
-      });
-      c.timed("schur_cam", bc, it, [&] {
-        launch_schur_cam<T>(s, adj, c.D, m, cp, om, c.u, zq, K, c.item_off, c.item_cam, nslot,
-                            c.part, c.pcg);
-      });
+      if (expl) {
+        c.timed("schur_spmv", bs, it, [&] {
+          launch_schur_spmv<T>(s, c.D, c.Ca, c.ex_row_ptr, c.ex_bkey,
+                               static_cast<const T*>(c.ex_sblk), c.ex_scc, c.u, c.wv, nslot,
+                               c.part, c.pcg);
+        });
+      } else {
+        c.timed("schur_point", bp, it, [&] {
+          launch_schur_point<T>(s, adj, c.D, G, m, cp, om, mvt, static_cast<const T*>(c.Vinv),
+                                zq, c.pcg, c.dl);
+        });
+        c.timed("schur_cam", bc, it, [&] {
+          launch_schur_cam<T>(s, adj, c.D, m, cp, om, c.u, zq, K, c.item_off, c.item_cam, nslot,
+                              c.part, c.pcg);
+        });
+      }
       c.timed("pcg_update", bu, it, [&] {
         launch_pcg_update<T>(s, c.D, c.Ca, it, c.Minv, Ustar, c.item_off, nslot, c.part, c.dots,
                              c.x, c.r, c.u, c.p, c.sv, c.wv, mvt, c.pcg);
@@ -717,6 +884,7 @@ ba_status lm_step_impl(ba_ctx& c, ba_step_report* rep) {
     }
     ta = now_ms();
     linearize<T>(c, false);
+    if (explicit_solver(c)) build_schur_pattern<T>(c);
     if (c.opt.timing) c.sync();   // phase times only; the stream orders the work
     t_lin = now_ms() - ta;
     c.lin_valid = true;
@@ -728,6 +896,7 @@ ba_status lm_step_impl(ba_ctx& c, ba_step_report* rep) {
 
   double ta = now_ms();
   setup_system<T>(c, false, c.lam, nullptr, nullptr);
+  if (explicit_solver(c)) assemble_schur_blocks<T>(c);
   if (c.opt.timing) c.sync();
   t_setup = now_ms() - ta;
   c.blocks_valid = true;
@@ -1157,6 +1326,7 @@ void ba_default_options(ba_options* o) {
   o->adjoint_damping = 0.0;
   o->refine_focal = 0;
   o->gp_huber = 0.1;
+  o->solver = BA_SOLVER_IMPLICIT;
   o->adjoint_rel_tol = 1e-10;
   o->hip_stream = nullptr;
 }
@@ -1185,6 +1355,7 @@ ba_status ba_create(const ba_options* opt, int32_t n_cams, int32_t n_points, con
       !(o.diag_min > 0) || !(o.diag_max >= o.diag_min) || o.adjoint_max_iters < 0 ||
       !(o.adjoint_damping >= 0) || (o.refine_focal != 0 && o.refine_focal != 1) ||
       !std::isfinite(o.gp_huber) ||
+      (o.solver != BA_SOLVER_IMPLICIT && o.solver != BA_SOLVER_EXPLICIT) ||
       !(o.adjoint_rel_tol >= 0)) {
     g_create_error = "invalid options";
     return BA_ERR_ARG;
@@ -1720,7 +1891,9 @@ ba_status ba_reset_kernel_stats(ba_ctx* c) {
   });
 }
 
-int64_t ba_device_bytes(const ba_ctx* c) { return c ? c->par.bytes + c->obs.bytes : 0; }
+int64_t ba_device_bytes(const ba_ctx* c) {
+  return c ? c->par.bytes + c->obs.bytes + c->ex.bytes + c->ex_bytes : 0;
+}
 
 const char* ba_last_error(const ba_ctx* c) {
   return c ? c->err.c_str() : g_create_error.c_str();

@@ -216,11 +216,12 @@ void launch_point_damp(hipStream_t s, int Pa, double lam, double dmin, double dm
                        double* hp, PtRec<T>* prec, int* bad);
 // Per camera slot: U = J_c^T M J_c, gc, b = rhs_c - sum W hp, S_cc = U* - sum W Vinv W^T and
 // its inverse (Cholesky, float64). rhs_c = -gc when rhs_c == nullptr. SoA outputs.
+// Scc (optional, SoA like Minv) receives S_cc itself for the explicit reduced system.
 template <typename T>
 void launch_cam_assemble(hipStream_t s, bool adj, int D, const Model& m, const Compact<T>& cp,
                          ObsMetric<T> om, double lam, double dmin, double dmax,
                          const PtRec<T>* prec, const double* rhs_c, double* Uraw, T* Ustar,
-                         double* gc, double* b, double* Minv);
+                         double* gc, double* b, double* Minv, double* Scc = nullptr);
 
 // ------------------------------------------------------------------ PCG on S
 // x = 0, r = b, u = M^-1 r (also into the matvec records), p = s = 0, Uu = U* u and the
@@ -309,6 +310,51 @@ template <typename T>
 void launch_adjoint_obs(hipStream_t s, const Model& m, const Compact<T>& cp, ObsMetric<T> om,
                         const double* x, const double* dp, const int* orig, float* gxy,
                         float* gdepth);
+
+// ------------------------------------------------------------------ explicit reduced system
+// The reduced camera system S = U* - W V*^-1 W^T assembled as D x D blocks (a solver variant of
+// the matrix-free Schur PCG). Off-diagonal block (i, j) = - sum over the points p seen by both
+// cameras of W_ip V*_p^-1 W_jp^T; the diagonal blocks S_cc come from the camera assembly.
+//
+// hipCUB primitives (ba_sort.hip): stable radix sort of 32-bit keys with 64-bit values over
+// the low end_bit bits of the keys, exclusive prefix sum of int64.
+size_t sort_pairs64_temp_bytes(int n, int end_bit);
+hipError_t sort_pairs64(void* temp, size_t temp_bytes, const uint32_t* keys_in,
+                        uint32_t* keys_out, const uint64_t* vals_in, uint64_t* vals_out, int n,
+                        int end_bit, hipStream_t s);
+size_t exclusive_sum_temp_bytes(int n);
+hipError_t exclusive_sum(void* temp, size_t temp_bytes, const int64_t* in, int64_t* out, int n,
+                         hipStream_t s);
+// Per active point: cnt[r] = m (m - 1) with m its observations in solve cameras (ordered pairs
+// of distinct observations), and the point rank of every point-major observation.
+template <typename T>
+void launch_pair_counts(hipStream_t s, const Compact<T>& cp, int64_t* cnt, int* pm_rank);
+// Contribution c = coff[r] + (pairs of point r in order): key = cam(a) Ca + cam(b), value =
+// the point-major positions of a (high 32 bits) and b (low 32 bits).
+template <typename T>
+void launch_pair_keys(hipStream_t s, const Compact<T>& cp, const int64_t* coff, uint32_t* key,
+                      uint64_t* val);
+// Flags of run starts in the sorted keys (1 where key differs from its predecessor).
+void launch_run_flags(hipStream_t s, int64_t n, const uint32_t* key, int64_t* flag);
+// Block list from the run starts: bkey[b], bstart[b] (the first sorted position of block b).
+void launch_block_list(hipStream_t s, int64_t n, const uint32_t* key, const int64_t* flag,
+                       const int64_t* bidx, uint32_t* bkey, int64_t* bstart);
+// Row pointers of the block rows (blocks are sorted row-major): row_ptr[i] = first block of
+// row >= i, i = 0..Ca.
+void launch_block_rows(hipStream_t s, int Ca, int64_t nb, const uint32_t* bkey, int64_t* row_ptr);
+// One wave per off-diagonal block: S_b = - sum over its contributions (sorted order) of
+// W_k V*^-1 W_l^T, stored row-major D x D in T.
+template <typename T>
+void launch_schur_blocks(hipStream_t s, int D, const Model& m, const Compact<T>& cp,
+                         ObsMetric<T> om, const T* Vinv, const int* pm_rank, int64_t nb,
+                         const uint32_t* bkey, const int64_t* bstart, const uint64_t* sval,
+                         T* sblk);
+// One wave per block row: w_i = S_cc u_i + sum_b S_b u_col(b), written as the single item
+// partial Uu_i - w_i (and its dot with u_i) that the PCG update consumes.
+template <typename T>
+void launch_schur_spmv(hipStream_t s, int D, int Ca, const int64_t* row_ptr,
+                       const uint32_t* bkey, const T* sblk, const double* Scc, const double* u,
+                       const double* Uu, int nslot, double* part, const PcgState* st);
 
 // ------------------------------------------------------------------ global positioning
 // Depth-constrained global positioning (Eqs. (1), (4), (5), (8)): rotations fixed, unknowns the

@@ -738,7 +738,7 @@ k_cam_assemble(Model m, Compact<T> cp, ObsMetric<T> om, double lam, double dmin,
                const PtRec<T>* __restrict__ prec,
                const double* __restrict__ rhs_c, double* __restrict__ Uraw,
                T* __restrict__ Ustar, double* __restrict__ gc, double* __restrict__ b,
-               double* __restrict__ Minv) {
+               double* __restrict__ Minv, double* __restrict__ Scc) {
   constexpr int NS = sym_count(D);
   constexpr int K = NS + NS + D + D;
   __shared__ double smem[K * (kBlock / kWave)];
@@ -833,6 +833,7 @@ k_cam_assemble(Model m, Compact<T> cp, ObsMetric<T> om, double lam, double dmin,
   for (int q = 0; q < NS; ++q) {
     Ustar[q * Ca + s] = T(Us[q]);
     Sc[q] = Us[q] - acc[NS + q];
+    if (Scc) Scc[q * Ca + s] = Sc[q];
   }
 #pragma unroll
   for (int p = 0; p < D; ++p) {
@@ -1676,6 +1677,208 @@ k_adjoint_obs(Model m, Compact<T> cp, ObsMetric<T> om, const double* __restrict_
   }
 }
 
+// ------------------------------------------------------------------ explicit reduced system
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_pair_counts(Compact<T> cp, int64_t* __restrict__ cnt, int* __restrict__ pm_rank) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= cp.Pa) return;
+  int64_t m = 0;
+  for (int j = cp.off[r]; j < cp.off[r + 1]; ++j) {
+    pm_rank[j] = r;
+    m += cp.cam[j] < cp.Ca ? 1 : 0;
+  }
+  cnt[r] = m * (m - 1);
+}
+
+// G lanes per point; lane l writes the contributions whose first observation is its a-th
+// solve observation (a = l, l + G, ...), in the order (a, then b) of the point's list.
+template <typename T, int G>
+__global__ void __launch_bounds__(kBlock)
+k_pair_keys(Compact<T> cp, const int64_t* __restrict__ coff, uint32_t* __restrict__ key,
+            uint64_t* __restrict__ val) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = t / G, l = t % G;
+  if (r >= cp.Pa) return;
+  const uint32_t Ca = uint32_t(cp.Ca);
+  const int b0 = cp.off[r], b1 = cp.off[r + 1];
+  int64_t m = 0;
+  for (int j = b0; j < b1; ++j) m += cp.cam[j] < cp.Ca ? 1 : 0;
+  int ia = 0;   // index of a among the solve observations
+  for (int a = b0; a < b1; ++a) {
+    const int sa = cp.cam[a];
+    if (sa >= cp.Ca) continue;
+    if (ia % G == l) {
+      int64_t c = coff[r] + int64_t(ia) * (m - 1);
+      for (int b = b0; b < b1; ++b) {
+        const int sb = cp.cam[b];
+        if (b == a || sb >= cp.Ca) continue;
+        key[c] = uint32_t(sa) * Ca + uint32_t(sb);
+        val[c] = (uint64_t(uint32_t(a)) << 32) | uint64_t(uint32_t(b));
+        ++c;
+      }
+    }
+    ++ia;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_run_flags(int64_t n, const uint32_t* __restrict__ key, int64_t* __restrict__ flag) {
+  const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  flag[c] = (c == 0 || key[c] != key[c - 1]) ? 1 : 0;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_block_list(int64_t n, const uint32_t* __restrict__ key, const int64_t* __restrict__ flag,
+             const int64_t* __restrict__ bidx, uint32_t* __restrict__ bkey,
+             int64_t* __restrict__ bstart) {
+  const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= n || !flag[c]) return;
+  bkey[bidx[c]] = key[c];
+  bstart[bidx[c]] = c;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_block_rows(int Ca, int64_t nb, const uint32_t* __restrict__ bkey, int64_t* __restrict__ row_ptr) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > Ca) return;
+  // first block whose row is >= i
+  const uint32_t target = uint32_t(i) * uint32_t(Ca);
+  int64_t lo = 0, hi = nb;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) / 2;
+    if (bkey[mid] < target) lo = mid + 1;
+    else hi = mid;
+  }
+  row_ptr[i] = lo;
+}
+
+// W = J_c^T w J_p (D x 3) of one observation from its (X_c, w) and its camera.
+template <typename T, int D>
+__device__ __forceinline__ void w_block(const Cam<T>& cm, T lam_d, const V4<T>& xw,
+                                        T W[D][3]) {
+  const T Xc[3] = {xw.x, xw.y, xw.z};
+  AMat<T, false> A;
+  A.set(cm.f, lam_d, Xc);
+#pragma unroll
+  for (int p = 0; p < D; ++p) W[p][0] = W[p][1] = W[p][2] = T(0);
+#pragma unroll
+  for (int row = 0; row < 3; ++row) {
+    T a[3], jc[D], jp[3];
+    A.row(row, a);
+    jc[0] = a[0];
+    jc[1] = a[1];
+    jc[2] = a[2];
+    cross3(Xc, a, jc + 3);
+    if constexpr (D == 7) jc[6] = row < 2 ? Xc[row] / Xc[2] : T(0);
+    rot_tmul(cm, a, jp);
+#pragma unroll
+    for (int p = 0; p < D; ++p) {
+      const T wj = xw.w * jc[p];
+      W[p][0] += wj * jp[0];
+      W[p][1] += wj * jp[1];
+      W[p][2] += wj * jp[2];
+    }
+  }
+}
+
+// One wave per off-diagonal block (i, j): lanes take its contributions in turn, the wave sums
+// them in a fixed shuffle order.
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock)
+k_schur_blocks(Model m, Compact<T> cp, ObsMetric<T> om, const T* __restrict__ Vinv,
+               const int* __restrict__ pm_rank, int64_t nb, const uint32_t* __restrict__ bkey,
+               const int64_t* __restrict__ bstart, const uint64_t* __restrict__ sval,
+               T* __restrict__ sblk) {
+  const int64_t b = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (b >= nb) return;   // whole waves leave together
+  const uint32_t Ca = uint32_t(cp.Ca);
+  const int ci = int(bkey[b] / Ca), cj = int(bkey[b] % Ca);
+  const Cam<T> cmi = cp.camt[ci], cmj = cp.camt[cj];
+  const T lam_d = T(m.lam_d);
+  T acc[D * D];
+#pragma unroll
+  for (int q = 0; q < D * D; ++q) acc[q] = T(0);
+  for (int64_t c = bstart[b] + lane; c < bstart[b + 1]; c += kWave) {
+    const uint64_t v = sval[c];
+    const int k = int(v >> 32), l = int(v & 0xffffffffu);
+    const int r = pm_rank[k];
+    T Wk[D][3], Wl[D][3];
+    w_block<T, D>(cmi, lam_d, om.pm_xcw[k], Wk);
+    w_block<T, D>(cmj, lam_d, om.pm_xcw[l], Wl);
+    T vi[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) vi[q] = Vinv[6 * r + q];
+    T Y[D][3];
+#pragma unroll
+    for (int p = 0; p < D; ++p)
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        Y[p][q] = Wk[p][0] * vi[sym3(0, q)] + Wk[p][1] * vi[sym3(1, q)] +
+                  Wk[p][2] * vi[sym3(2, q)];
+#pragma unroll
+    for (int p = 0; p < D; ++p)
+#pragma unroll
+      for (int q = 0; q < D; ++q)
+        acc[p * D + q] += Y[p][0] * Wl[q][0] + Y[p][1] * Wl[q][1] + Y[p][2] * Wl[q][2];
+  }
+#pragma unroll
+  for (int q = 0; q < D * D; ++q) acc[q] = wave_sum(acc[q]);
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < D * D; ++q) sblk[b * (D * D) + q] = -acc[q];
+  }
+}
+
+// One wave per block row of S: w_i = S_cc u_i + sum over its off-diagonal blocks S_b u_j.
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock)
+k_schur_spmv(int Ca, const int64_t* __restrict__ row_ptr, const uint32_t* __restrict__ bkey,
+             const T* __restrict__ sblk, const double* __restrict__ Scc,
+             const double* __restrict__ u, const double* __restrict__ Uu, int nslot,
+             double* __restrict__ part, const PcgState* __restrict__ st) {
+  if (st->done) return;
+  const int i = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (i >= Ca) return;
+  T y[D];
+#pragma unroll
+  for (int p = 0; p < D; ++p) y[p] = T(0);
+  for (int64_t b = row_ptr[i] + lane; b < row_ptr[i + 1]; b += kWave) {
+    const int j = int(bkey[b] % uint32_t(Ca));
+    T uj[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) uj[q] = T(u[q * Ca + j]);
+    const T* S = sblk + b * (D * D);
+#pragma unroll
+    for (int p = 0; p < D; ++p) {
+      T a = T(0);
+#pragma unroll
+      for (int q = 0; q < D; ++q) a += S[p * D + q] * uj[q];
+      y[p] += a;
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < D; ++p) y[p] = wave_sum(y[p]);
+  if (lane != 0) return;
+  double ui[D];
+#pragma unroll
+  for (int q = 0; q < D; ++q) ui[q] = u[q * Ca + i];
+  double pd = 0.0;
+#pragma unroll
+  for (int p = 0; p < D; ++p) {
+    double w = double(y[p]);
+#pragma unroll
+    for (int q = 0; q < D; ++q) w += Scc[symd<D>(p, q) * Ca + i] * ui[q];
+    const double pt = Uu[p * Ca + i] - w;
+    part[p * nslot + i] = pt;
+    pd += ui[p] * pt;
+  }
+  part[D * nslot + i] = pd;
+}
+
 // ------------------------------------------------------------------ global positioning
 // Unit world ray of an observation: v = R^T a / |a| with a = K^-1 [x, y, 1]; returns |a|.
 __device__ __forceinline__ double gp_ray(const Cam<double>& cm, float2 xy, double v[3]) {
@@ -2361,15 +2564,15 @@ template <typename T>
 void launch_cam_assemble(hipStream_t s, bool adj, int D, const Model& m, const Compact<T>& cp,
                          ObsMetric<T> om, double lam, double dmin, double dmax,
                          const PtRec<T>* prec, const double* rhs_c, double* Uraw, T* Ustar,
-                         double* gc, double* b, double* Minv) {
+                         double* gc, double* b, double* Minv, double* Scc) {
   if (cp.Ca == 0) return;
   if (adj)
     launch_k((k_cam_assemble<T, true, 6>), dim3(cp.Ca), dim3(kBlock), 0, s, m, cp, om, lam,
-             dmin, dmax, prec, rhs_c, Uraw, Ustar, gc, b, Minv);
+             dmin, dmax, prec, rhs_c, Uraw, Ustar, gc, b, Minv, Scc);
   else
     with_dim(D, [&](auto Dc) {
       launch_k((k_cam_assemble<T, false, Dc()>), dim3(cp.Ca), dim3(kBlock), 0, s, m, cp, om,
-               lam, dmin, dmax, prec, rhs_c, Uraw, Ustar, gc, b, Minv);
+               lam, dmin, dmax, prec, rhs_c, Uraw, Ustar, gc, b, Minv, Scc);
     });
 }
 
@@ -2577,7 +2780,7 @@ void launch_adjoint_obs(hipStream_t s, const Model& m, const Compact<T>& cp, Obs
   template void launch_cam_assemble<T>(hipStream_t, bool, int, const Model&,                  \
                                        const Compact<T>&, ObsMetric<T>, double, double, double,\
                                        const PtRec<T>*, const double*, double*, T*, double*,  \
-                                       double*, double*);                                      \
+                                       double*, double*, double*);                             \
   template void launch_mv_table<T>(hipStream_t, int, int, const Cam<double>*, void*);         \
   template void launch_pcg_init<T>(hipStream_t, int, int, const double*, const double*,       \
                                    const T*, const int*, int, int*, int*, double*, double*,   \
@@ -2605,6 +2808,76 @@ void launch_adjoint_obs(hipStream_t s, const Model& m, const Compact<T>& cp, Obs
 
 IBA_INSTANTIATE(float)
 IBA_INSTANTIATE(double)
+
+// ------------------------------------------------------------------ explicit system launchers
+template <typename T>
+void launch_pair_counts(hipStream_t s, const Compact<T>& cp, int64_t* cnt, int* pm_rank) {
+  if (cp.Pa == 0) return;
+  launch_k(k_pair_counts<T>, dim3(blocks_for(cp.Pa)), dim3(kBlock), 0, s, cp, cnt, pm_rank);
+}
+
+template <typename T>
+void launch_pair_keys(hipStream_t s, const Compact<T>& cp, const int64_t* coff, uint32_t* key,
+                      uint64_t* val) {
+  if (cp.Pa == 0) return;
+  constexpr int G = 8;
+  launch_k(k_pair_keys<T, G>, dim3(blocks_for(int64_t(cp.Pa) * G)), dim3(kBlock), 0, s, cp,
+           coff, key, val);
+}
+
+void launch_run_flags(hipStream_t s, int64_t n, const uint32_t* key, int64_t* flag) {
+  if (n == 0) return;
+  launch_k(k_run_flags, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, key, flag);
+}
+
+void launch_block_list(hipStream_t s, int64_t n, const uint32_t* key, const int64_t* flag,
+                       const int64_t* bidx, uint32_t* bkey, int64_t* bstart) {
+  if (n == 0) return;
+  launch_k(k_block_list, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, key, flag, bidx, bkey,
+           bstart);
+}
+
+void launch_block_rows(hipStream_t s, int Ca, int64_t nb, const uint32_t* bkey, int64_t* row_ptr) {
+  launch_k(k_block_rows, dim3(blocks_for(int64_t(Ca) + 1)), dim3(kBlock), 0, s, Ca, nb, bkey,
+           row_ptr);
+}
+
+template <typename T>
+void launch_schur_blocks(hipStream_t s, int D, const Model& m, const Compact<T>& cp,
+                         ObsMetric<T> om, const T* Vinv, const int* pm_rank, int64_t nb,
+                         const uint32_t* bkey, const int64_t* bstart, const uint64_t* sval,
+                         T* sblk) {
+  if (nb == 0) return;
+  with_dim(D, [&](auto Dc) {
+    launch_k(k_schur_blocks<T, Dc()>, dim3(blocks_for(nb * kWave)), dim3(kBlock), 0, s, m, cp,
+             om, Vinv, pm_rank, nb, bkey, bstart, sval, sblk);
+  });
+}
+
+template <typename T>
+void launch_schur_spmv(hipStream_t s, int D, int Ca, const int64_t* row_ptr,
+                       const uint32_t* bkey, const T* sblk, const double* Scc, const double* u,
+                       const double* Uu, int nslot, double* part, const PcgState* st) {
+  if (Ca == 0) return;
+  with_dim(D, [&](auto Dc) {
+    launch_k(k_schur_spmv<T, Dc()>, dim3(blocks_for(int64_t(Ca) * kWave)), dim3(kBlock), 0, s,
+             Ca, row_ptr, bkey, sblk, Scc, u, Uu, nslot, part, st);
+  });
+}
+
+#define IBA_EXPLICIT_INSTANTIATE(T)                                                            \
+  template void launch_pair_counts<T>(hipStream_t, const Compact<T>&, int64_t*, int*);        \
+  template void launch_pair_keys<T>(hipStream_t, const Compact<T>&, const int64_t*, uint32_t*, \
+                                    uint64_t*);                                               \
+  template void launch_schur_blocks<T>(hipStream_t, int, const Model&, const Compact<T>&,     \
+                                       ObsMetric<T>, const T*, const int*, int64_t,           \
+                                       const uint32_t*, const int64_t*, const uint64_t*, T*); \
+  template void launch_schur_spmv<T>(hipStream_t, int, int, const int64_t*, const uint32_t*,  \
+                                     const T*, const double*, const double*, const double*,   \
+                                     int, double*, const PcgState*);
+
+IBA_EXPLICIT_INSTANTIATE(float)
+IBA_EXPLICIT_INSTANTIATE(double)
 
 // ------------------------------------------------------------------ global positioning launchers
 template <class F>
