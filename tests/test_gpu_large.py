@@ -165,3 +165,30 @@ def test_large_focal_mixed_tracks_fp64():
     # focal length trades off against camera distance along the optical axis (a weak
     # direction that a truncated PCG resolves least); 1e-4 of f = 1000 px is 0.1 px
     assert df < 1e-4
+
+
+def test_many_cameras_point_pass_from_l2():
+    """3000 cameras: the matvec records no longer fit in LDS, so the point pass reads them
+    through L2 (the path of the 5000-camera workload). One float64 step equals the explicit
+    reduced system's step (independent matvec) and the extraction equals the oracle's."""
+    sc = make_scene("xl", n_seq=30, n_points=150000)
+    assert sc.n_cams * 64 > 160 * 1024
+    prob = Problem.from_scene(sc)
+    opts = Options(huber_px=sc.huber_px, filter_px=sc.filter_px)
+    st = State.initial(sc.cams0, sc.points0, opts)
+    ex = extract(prob, st, opts)
+    steps = {}
+    for solver in ("implicit", "explicit"):
+        ba = gpu_setup(sc, "fp64", solver=solver, lambda_init=1e-2, pcg_rel_tol=1e-12,
+                       pcg_max_iters=3000)
+        rep = ba.lm_step()
+        ac, ap, ao = ba.get_active()
+        np.testing.assert_array_equal(ao, ex.obs_active)
+        np.testing.assert_array_equal(ac, ex.cam_active)
+        steps[solver] = ba.get_last_step() + (rep,)
+        ba.close()
+    (ci, pi, ri), (ce, pe, re) = steps["implicit"], steps["explicit"]
+    print(f"3000 cameras: steps differ by {rel_err(ci, ce):.2e} (cams), {rel_err(pi, pe):.2e} "
+          f"(points); PCG {ri['pcg_iters']} / {re['pcg_iters']}")
+    assert rel_err(ci, ce) < 1e-6 and rel_err(pi, pe) < 1e-6
+    assert ri["accepted"] == re["accepted"]
