@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--pcg-tol", type=float, default=1e-6)
     ap.add_argument("--pcg-max", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--cpu-frac", type=float, default=0.05,
+    ap.add_argument("--cpu-frac", type=float, default=0.15,
                     help="fraction of points in the oracle's timed sample")
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--check-every", type=int, default=8,
