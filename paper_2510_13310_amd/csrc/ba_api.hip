@@ -407,7 +407,10 @@ void alloc_obs_buffers(ba_ctx& c) {
   c.w = A.alloc<char>(ts * N);
   c.xcw = A.alloc<char>(4 * ts * N);
   c.cm_e = A.alloc<char>(4 * ts * N);
-  c.pm_xcw = A.alloc<char>(4 * ts * N);
+  // the point-major Jacobian stream: read by the float64 point pass and by the explicit
+  // system's block assembly (the float32 point pass forms X_c itself)
+  c.pm_xcw = (ts == 8 || c.opt.solver == BA_SOLVER_EXPLICIT) ? A.alloc<char>(4 * ts * N)
+                                                             : nullptr;
   c.eh = nullptr;
   c.cm_eh = nullptr;
   c.gp_s = nullptr;
@@ -419,7 +422,7 @@ void alloc_obs_buffers(ba_ctx& c) {
   const size_t ns = size_t(c.D) * (c.D + 1) / 2;   // entries of a symmetric camera block
   const size_t nd = size_t(c.D);
   c.Ustar = A.alloc<char>(ts * ns * C);
-  c.mvt = A.alloc<char>(ts * 20 * C);   // MvCam (16 T) or MvCamF (20 T) records
+  c.mvt = A.alloc<char>(ts * 20 * C);   // MvCam or MvCamF records (at most 20 T each)
   c.gp = A.alloc<double>(3 * size_t(P));
   c.hp = A.alloc<double>(3 * size_t(P));
   c.dp = A.alloc<double>(3 * size_t(P));
@@ -576,13 +579,16 @@ void extract(ba_ctx& c, bool gp = false) {
 }
 
 // Algorithmic bytes of the two PCG passes (unique data each must touch once).
-// Point pass: per observation its slot and (X_c, w) 4-vector, and for solve cameras its
-// camera-major position and the packed z 3-vector written there; per point the CSR offset
-// and Vinv; every matvec record once.
+// Point pass: per observation its slot and, in float32, its weight (X_c is formed from the
+// point) or, in float64, its (X_c, w) 4-vector; for solve cameras its camera-major position
+// and the packed z 3-vector written there; per point the CSR offset, Vinv and, in float32,
+// the point; every matvec record once.
 double bytes_schur_point(const ba_ctx& c) {
   const double ts = double(c.tsize());
-  return double(c.Nh) * (4 + 4 * ts) + double(c.Nc) * (4 + 3 * ts) +
-         double(c.Pa) * (4 + 6 * ts) + double(c.Ca) * 16 * ts;
+  const bool form = ts == 4;
+  const double rec = form || c.D == 7 ? 20 : 16;   // matvec record values
+  return double(c.Nh) * (4 + (form ? 1 : 4) * ts) + double(c.Nc) * (4 + 3 * ts) +
+         double(c.Pa) * (4 + (form ? 9 : 6) * ts) + double(c.Ca) * rec * ts;
 }
 // Camera pass: per observation the (X_c, w) 4-vector and the z 3-vector; per camera its
 // offset, table entry and u; per partial slot its D + 1 values written.
@@ -1390,8 +1396,6 @@ ba_status ba_create(const ba_options* opt, int32_t n_cams, int32_t n_points, con
     HIP_CHECK(hipDeviceGetAttribute(&c->dl.n_cu, hipDeviceAttributeMultiprocessorCount, dev));
     HIP_CHECK(hipDeviceGetAttribute(&c->dl.lds_per_block,
                                     hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    HIP_CHECK(hipDeviceGetAttribute(&c->dl.lds_per_cu,
-                                    hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev));
     Arena& A = c->par;
     c->d_cams = A.alloc<double>(7 * size_t(n_cams));
     c->d_intr = A.alloc<double>(3 * size_t(n_cams));

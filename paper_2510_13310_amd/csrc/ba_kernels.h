@@ -39,22 +39,38 @@ struct P3 {
   T x, y, z;
 };
 
-// Per-slot record read by the PCG point pass: rotation, focal length and the current camera
-// direction u of the Schur matvec, 16 values so that one aligned half (float) or full
-// (double) cache line serves an observation.
+// Per-slot record read by the PCG point pass: rotation, centre and focal length (the values
+// of the T camera table, so that X_c = R (X - c) formed from it equals the other kernels'),
+// and the current camera direction u of the Schur matvec; 20 values. The float64 pass reads
+// X_c from its stream, so its record has no centre (16 values, one 128-byte line).
 template <typename T>
-struct alignas(16 * sizeof(T)) MvCam {
+struct alignas(4 * sizeof(T)) MvCam {
   T R[9];
+  T c[3];
   T f;
   T u[6];
+  T pad;
+};
+template <>
+struct alignas(128) MvCam<double> {
+  double R[9];
+  double f;
+  double u[6];
 };
 // With the focal length refined the camera unknown has a seventh component.
 template <typename T>
 struct alignas(4 * sizeof(T)) MvCamF {
   T R[9];
+  T c[3];
   T f;
   T u[7];
-  T pad[3];
+};
+template <>
+struct alignas(32) MvCamF<double> {
+  double R[9];
+  double f;
+  double u[7];
+  double pad[3];
 };
 template <typename T, int D>
 struct MvRecOf {
@@ -76,6 +92,9 @@ struct MvRecOf<T, 3> {
 };
 template <typename T, int D>
 using MvRec = typename MvRecOf<T, D>::type;
+// the point pass stages the records in LDS as 16-byte chunks
+static_assert(sizeof(MvCam<float>) == 80 && sizeof(MvCamF<float>) == 80, "record layout");
+static_assert(sizeof(MvCam<double>) == 128 && sizeof(MvCamF<double>) == 160, "record layout");
 
 // Entries of a symmetric D x D block stored as its upper triangle.
 constexpr int sym_count(int D) { return D * (D + 1) / 2; }
@@ -142,7 +161,8 @@ template <typename T>
 struct ObsMetric {
   T* w;          // Nh: rho'
   T* eh;         // Nh x 3: unit residual direction (adjoint only, else nullptr)
-  V4<T>* pm_xcw; // Nh: camera-frame point and w, point-major order
+  V4<T>* pm_xcw; // Nh: camera-frame point and w, point-major order (float64, and the
+                 //     explicit solver; else nullptr: the float32 point pass forms X_c)
   V4<T>* xcw;    // Nc: camera-frame point and w, camera-major order
   V4<T>* cm_e;   // Nc: residual e (3, w slot unused) at the linearisation point, camera-major
   T* cm_eh;      // Nc x 3 (adjoint only)
@@ -248,7 +268,6 @@ inline void cam_chunking(int Nc, int& K, int& nchunks) {
 struct DevLimits {
   int n_cu = 0;            // compute units
   int lds_per_block = 0;   // bytes of LDS one workgroup may use
-  int lds_per_cu = 0;      // bytes of LDS per compute unit
 };
 
 // z_p = Vinv sum_k W_k^T u_c (point-major pass, G lanes per point), written to the

@@ -113,6 +113,21 @@ __device__ __forceinline__ void cam_frame(const Cam<S>& cm, T X0, T X1, T X2, T 
   Xc[2] = T(cm.R[6]) * d0 + T(cm.R[7]) * d1 + T(cm.R[8]) * d2;
 }
 
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// R (X - c) in T from T-valued rotation, centre and point, with one fixed order of fused
+// multiply-adds: the Jacobian kernels of the solve (streams written by the linearisation,
+// the PCG point pass, back-substitution) all form X_c with it, so they see the same bits.
+template <typename T>
+__device__ __forceinline__ void frame_t(const T R[9], const T c[3], T X0, T X1, T X2,
+                                        T Xc[3]) {
+  const T d0 = X0 - c[0], d1 = X1 - c[1], d2 = X2 - c[2];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    Xc[i] = fma_t(R[3 * i + 2], d2, fma_t(R[3 * i + 1], d1, R[3 * i] * d0));
+}
+
 // R v and R^T v for a row-major camera rotation.
 template <typename T, typename S>
 __device__ __forceinline__ void rot_mul(const Cam<S>& cm, const T v[3], T o[3]) {
@@ -519,6 +534,8 @@ k_mv_table(int n, const Cam<double>* __restrict__ camd_hat, MvRec<T, D>* __restr
   if (s >= n) return;
   MvRec<T, D> v{};
   for (int i = 0; i < 9; ++i) v.R[i] = T(camd_hat[s].R[i]);
+  if constexpr (sizeof(T) == 4)
+    for (int i = 0; i < 3; ++i) v.c[i] = T(camd_hat[s].c[i]);
   v.f = T(camd_hat[s].f);
   for (int i = 0; i < D; ++i) v.u[i] = T(0);
   mvt[s] = v;
@@ -545,6 +562,7 @@ k_lin_point(Model m, Compact<T> cp, ObsMetric<T> om, double* __restrict__ V,
     double g[3] = {0.0, 0.0, 0.0};
     if (live) {
       const double X0 = cp.Xd[3 * r], X1 = cp.Xd[3 * r + 1], X2 = cp.Xd[3 * r + 2];
+      const T Xt0 = cp.Xt[3 * r], Xt1 = cp.Xt[3 * r + 1], Xt2 = cp.Xt[3 * r + 2];
       for (int j = cp.off[r] + l; j < cp.off[r + 1]; j += G) {
         const Cam<double> cm = cp.camd[cp.cam[j]];
         double Xc[3], e[3];
@@ -556,12 +574,20 @@ k_lin_point(Model m, Compact<T> cp, ObsMetric<T> om, double* __restrict__ V,
         acc[0] += 0.5 * rho;
         acc[1] += e[0] * e[0] + e[1] * e[1];
         om.w[j] = T(w);
+        // the Jacobian streams carry X_c formed in T from the T tables, as the PCG point pass
+        // and back-substitution form it
+        T Rt[9], ct[3], Xct[3];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) Rt[i] = T(cm.R[i]);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) ct[i] = T(cm.c[i]);
+        frame_t(Rt, ct, Xt0, Xt1, Xt2, Xct);
         V4<T> xw;
-        xw.x = T(Xc[0]);
-        xw.y = T(Xc[1]);
-        xw.z = T(Xc[2]);
+        xw.x = Xct[0];
+        xw.y = Xct[1];
+        xw.z = Xct[2];
         xw.w = T(w);
-        om.pm_xcw[j] = xw;
+        if (om.pm_xcw) om.pm_xcw[j] = xw;
         const int ic = cp.pm_cm[j];   // camera-major copies (solve cameras only)
         if (ic >= 0) {
           om.xcw[ic] = xw;
@@ -963,66 +989,117 @@ k_pcg_init(int Ca, const double* __restrict__ b, const double* __restrict__ Minv
 
 // Point-major pass of S u: G lanes share one point, each walks every G-th observation of
 // the point's segment, and the lanes combine their sums with shuffles (G divides 64). Per
-// observation: the streamed (X_c, w) 4-vector and the matvec record of its camera (R, f, u).
+// observation: its camera slot and the matvec record of its camera (R, c, f, u). In float32
+// the observation adds its weight w and X_c = R (X - c) is formed from the point, read once
+// per point; in float64 it streams the stored (X_c, w) 4-vector (forming X_c there costs
+// more in float64 arithmetic and in 160-byte records than the 24 bytes it saves).
 // The point's z = Vinv y is then stored at the camera-major position of each of its
 // observations, so that the camera pass streams z instead of gathering it.
-// Every lane of a wave must call this together (shuffles); lanes with r >= rend do nothing.
-// (b, e) is the point's observation range when the caller has loaded it (b >= 0), else the
-// function reads it.
+
+// What a lane needs before it can start on its point: the point's observation range and
+// coordinates, and its own first observation (camera slot, weight, camera-major position).
+// The persistent pass loads these one tile ahead, so that a tile starts on data already in
+// registers instead of waiting on the chain offsets -> slot -> record.
+template <typename T>
+struct PtLoad {
+  int b, e;     // observation range; b = e for a lane without a point
+  int s0;       // first observation's camera slot (Ca: none)
+  int pos0;     // its camera-major position (-1: none, or a fixed camera)
+  V4<T> xw0;    // its weight in w; in float64 also its X_c (the stored 4-vector)
+  T X[3];       // the point (float32)
+};
+// X_c is formed in the point pass in float32 and streamed in float64.
+template <typename T>
+constexpr bool kFormXc = sizeof(T) == 4;
+
+// Fills the per-lane part of p for point r; p.b and p.e must be set.
+template <typename T>
+__device__ __forceinline__ void pt_load_first(const Compact<T>& cp, const ObsMetric<T>& om,
+                                              int r, int l, PtLoad<T>& p) {
+  p.s0 = cp.Ca;
+  p.pos0 = -1;
+  p.xw0.x = p.xw0.y = p.xw0.z = p.xw0.w = T(0);
+  p.X[0] = p.X[1] = p.X[2] = T(0);
+  if (kFormXc<T> && p.b < p.e) {
+    p.X[0] = cp.Xt[3 * r];
+    p.X[1] = cp.Xt[3 * r + 1];
+    p.X[2] = cp.Xt[3 * r + 2];
+  }
+  if (p.b + l < p.e) {
+    p.s0 = cp.cam[p.b + l];
+    if constexpr (kFormXc<T>)
+      p.xw0.w = om.w[p.b + l];
+    else
+      p.xw0 = om.pm_xcw[p.b + l];
+    p.pos0 = cp.pm_cm[p.b + l];
+  }
+}
+
+// Every lane of a wave must call this together (shuffles); lanes with !live do nothing.
 template <typename T, bool ADJ, int G, int D>
 __device__ __forceinline__ void schur_point_one(const Model& m, const Compact<T>& cp,
                                                 const ObsMetric<T>& om,
                                                 const MvRec<T, D>* __restrict__ tab,
                                                 const T* __restrict__ Vinv,
-                                                P3<T>* __restrict__ zq_cm, int r, int rend,
-                                                int l, int b = -1, int e = 0) {
+                                                P3<T>* __restrict__ zq_cm, int r, bool live,
+                                                int l, const PtLoad<T>& p) {
   T y[3] = {T(0), T(0), T(0)};
   T vi[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
-  int pos0 = -1;
-  const bool live = r < rend;
-  if (!live) {
-    b = 0;
-    e = 0;
-  }
-  if (live) {
-    if (b < 0) {
-      b = cp.off[r];
-      e = cp.off[r + 1];
+  // y += R^T W (J_c u) for one observation: W = w A^T A, A the rows of de/dX_c
+  auto obs = [&](int j, int s, const V4<T>& xw) {
+    if (s >= cp.Ca) return;   // fixed camera: no column in the solve
+    const MvRec<T, D> mc = tab[s];
+    const T wj = xw.w;
+    T Xc[3];
+    if constexpr (kFormXc<T>) {
+      frame_t(mc.R, mc.c, p.X[0], p.X[1], p.X[2], Xc);
+    } else {
+      Xc[0] = xw.x;
+      Xc[1] = xw.y;
+      Xc[2] = xw.z;
     }
+    AMat<T, ADJ> A;
+    A.set(mc.f, T(m.lam_d), Xc);
+    if constexpr (ADJ) A.project(om.eh + 3 * j);
+    T o3[3], d[3], tt[3], mm[3];
+    const T w3[3] = {mc.u[3], mc.u[4], mc.u[5]};
+    cross3(w3, Xc, o3);
+    d[0] = mc.u[0] + o3[0];
+    d[1] = mc.u[1] + o3[1];
+    d[2] = mc.u[2] + o3[2];
+    A.apply(d, tt);
+    if constexpr (D == 7) {   // focal column (x/z, y/z, 0) times the focal unknown
+      const T uf = mc.u[6] / Xc[2];
+      tt[0] += Xc[0] * uf;
+      tt[1] += Xc[1] * uf;
+    }
+    A.applyT(tt, mm);
+    mm[0] *= wj; mm[1] *= wj; mm[2] *= wj;
+    // R^T m
+    y[0] += mc.R[0] * mm[0] + mc.R[3] * mm[1] + mc.R[6] * mm[2];
+    y[1] += mc.R[1] * mm[0] + mc.R[4] * mm[1] + mc.R[7] * mm[2];
+    y[2] += mc.R[2] * mm[0] + mc.R[5] * mm[1] + mc.R[8] * mm[2];
+  };
+  if (live) {
     // loads needed only after the reduction, issued now to overlap the stream (float32: the
     // registers are free; float64 keeps them for the stream)
     if constexpr (sizeof(T) == 4) {
 #pragma unroll
       for (int q = 0; q < 6; ++q) vi[q] = Vinv[6 * r + q];
     }
-    if (b + l < e) pos0 = cp.pm_cm[b + l];
-    for (int j = b + l; j < e; j += G) {
-      const int s = cp.cam[j];
-      if (s >= cp.Ca) continue;   // fixed camera: no column in the solve
-      const V4<T> xw = om.pm_xcw[j];
-      const MvRec<T, D> mc = tab[s];
-      const T Xc[3] = {xw.x, xw.y, xw.z};
-      AMat<T, ADJ> A;
-      A.set(mc.f, T(m.lam_d), Xc);
-      if constexpr (ADJ) A.project(om.eh + 3 * j);
-      T o3[3], d[3], tt[3], mm[3];
-      const T w3[3] = {mc.u[3], mc.u[4], mc.u[5]};
-      cross3(w3, Xc, o3);
-      d[0] = mc.u[0] + o3[0];
-      d[1] = mc.u[1] + o3[1];
-      d[2] = mc.u[2] + o3[2];
-      A.apply(d, tt);
-      if constexpr (D == 7) {   // focal column (x/z, y/z, 0) times the focal unknown
-        const T uf = mc.u[6] / Xc[2];
-        tt[0] += Xc[0] * uf;
-        tt[1] += Xc[1] * uf;
+    int j = p.b + l;
+    if (j < p.e) {
+      obs(j, p.s0, p.xw0);
+      for (j += G; j < p.e; j += G) {
+        V4<T> xw;
+        if constexpr (kFormXc<T>) {
+          xw.x = xw.y = xw.z = T(0);
+          xw.w = om.w[j];
+        } else {
+          xw = om.pm_xcw[j];
+        }
+        obs(j, cp.cam[j], xw);
       }
-      A.applyT(tt, mm);
-      mm[0] *= xw.w; mm[1] *= xw.w; mm[2] *= xw.w;
-      // R^T m
-      y[0] += mc.R[0] * mm[0] + mc.R[3] * mm[1] + mc.R[6] * mm[2];
-      y[1] += mc.R[1] * mm[0] + mc.R[4] * mm[1] + mc.R[7] * mm[2];
-      y[2] += mc.R[2] * mm[0] + mc.R[5] * mm[1] + mc.R[8] * mm[2];
     }
   }
 #pragma unroll
@@ -1042,8 +1119,8 @@ __device__ __forceinline__ void schur_point_one(const Model& m, const Compact<T>
     z.x = vi[0] * y[0] + vi[1] * y[1] + vi[2] * y[2];
     z.y = vi[1] * y[0] + vi[3] * y[1] + vi[4] * y[2];
     z.z = vi[2] * y[0] + vi[4] * y[1] + vi[5] * y[2];
-    if (pos0 >= 0) zq_cm[pos0] = z;
-    for (int j = b + l + G; j < e; j += G) {
+    if (p.pos0 >= 0) zq_cm[p.pos0] = z;
+    for (int j = p.b + l + G; j < p.e; j += G) {
       const int pos = cp.pm_cm[j];
       if (pos >= 0) zq_cm[pos] = z;
     }
@@ -1063,14 +1140,23 @@ k_schur_point(Model m, Compact<T> cp, ObsMetric<T> om, const MvRec<T, D>* __rest
   const int per = gridDim.x / 8;
   const int blk = (blockIdx.x % 8) * per + blockIdx.x / 8;
   const int t = blk * blockDim.x + threadIdx.x;
-  schur_point_one<T, ADJ, G, D>(m, cp, om, mvt, Vinv, zq_cm, t / G, cp.Pa, t % G);
+  const int r = t / G, l = t % G;
+  const bool live = r < cp.Pa;
+  PtLoad<T> p;
+  p.b = live ? cp.off[r] : 0;
+  p.e = live ? cp.off[r + 1] : 0;
+  pt_load_first(cp, om, r, l, p);
+  schur_point_one<T, ADJ, G, D>(m, cp, om, mvt, Vinv, zq_cm, r, live, l, p);
 }
 
-// Persistent variant for tables that fit in LDS: a few 1024-thread workgroups per CU each
-// copy the camera records into LDS once, so the random per-observation record reads hit LDS.
+// Grid-stride variant for tables that fit in LDS: each 1024-thread workgroup (one resident
+// per CU) copies the camera records into LDS once, so the random per-observation record
+// reads hit LDS.
 // XCD x owns the x-th eighth of the point ranks (ppx points) and its workgroups take that
 // range's tiles round-robin: the XCD works on consecutive tiles at any moment, so the z
 // stores into each camera segment fill whole cache lines while they are in its L2.
+// Loads run ahead of the work: the offsets two tiles ahead and, in float32, the next tile's
+// first-observation data are issued before the current tile is processed.
 constexpr int kPtLdsBlock = 1024;
 
 template <typename T, bool ADJ, int G, int D>
@@ -1082,32 +1168,42 @@ k_schur_point_lds(Model m, Compact<T> cp, ObsMetric<T> om, const MvRec<T, D>* __
   if (st->done) return;
   const int per = gridDim.x / 8;            // workgroups per XCD
   const int xcd = blockIdx.x % 8;
-  const int j = blockIdx.x / 8;
+  const int jw = blockIdx.x / 8;
   const int lo = xcd * ppx;
   const int hi = min(cp.Pa, lo + ppx);
   constexpr int tile = kPtLdsBlock / G;
   const int step = per * tile;
   const int l = int(threadIdx.x) % G;
-  // the point ranges of the next tile are loaded while the current one is processed (the
-  // first ones while the table is staged)
-  int r = lo + j * tile + int(threadIdx.x) / G;
-  int bn = 0, en = 0;
-  if (r < hi) {
-    bn = cp.off[r];
-    en = cp.off[r + 1];
+  int r = lo + jw * tile + int(threadIdx.x) / G;
+  PtLoad<T> cur;
+  cur.b = r < hi ? cp.off[r] : 0;
+  cur.e = r < hi ? cp.off[r + 1] : 0;
+  if constexpr (kFormXc<T>) pt_load_first(cp, om, r, l, cur);
+  int bn = 0, en = 0;   // offsets of the next tile
+  if (r + step < hi) {
+    bn = cp.off[r + step];
+    en = cp.off[r + step + 1];
   }
   const int nchunk = cp.Ca * int(sizeof(MvRec<T, D>) / sizeof(uint4));
   const uint4* src = reinterpret_cast<const uint4*>(mvt);
   for (int i = threadIdx.x; i < nchunk; i += kPtLdsBlock) lds_tab[i] = src[i];
   __syncthreads();
   const MvRec<T, D>* tab = reinterpret_cast<const MvRec<T, D>*>(lds_tab);
-  for (int base = lo + j * tile; base < hi; base += step, r += step) {
-    const int b = bn, e = en;
-    if (r + step < hi) {
-      bn = cp.off[r + step];
-      en = cp.off[r + step + 1];
+  for (int base = lo + jw * tile; base < hi; base += step, r += step) {
+    PtLoad<T> nxt;
+    nxt.b = bn;
+    nxt.e = en;
+    if constexpr (kFormXc<T>)
+      pt_load_first(cp, om, r + step, l, nxt);   // float32: one tile ahead
+    else
+      pt_load_first(cp, om, r, l, cur);          // float64: in the tile (measured faster)
+    bn = en = 0;
+    if (r + 2 * step < hi) {
+      bn = cp.off[r + 2 * step];
+      en = cp.off[r + 2 * step + 1];
     }
-    schur_point_one<T, ADJ, G, D>(m, cp, om, tab, Vinv, zq_cm, r, hi, l, b, e);
+    schur_point_one<T, ADJ, G, D>(m, cp, om, tab, Vinv, zq_cm, r, r < hi, l, cur);
+    cur = nxt;
   }
 }
 
@@ -1352,7 +1448,7 @@ k_backsub(Model m, Compact<T> cp, ObsMetric<T> om, const T* __restrict__ Vinv,
       if (s >= Ca) continue;
       const Cam<T>& cm = cp.camt[s];
       T Xc[3];
-      cam_frame(cm, X0, X1, X2, Xc);
+      frame_t(cm.R, cm.c, X0, X1, X2, Xc);
       AMat<T, ADJ> A;
       A.set(cm.f, T(m.lam_d), Xc);
       if constexpr (ADJ) A.project(om.eh + 3 * j);
@@ -2617,8 +2713,12 @@ void schur_point_launch(hipStream_t s, const Model& m, const Compact<T>& cp, Obs
                   reinterpret_cast<const void*>(&k_schur_point_lds<T, ADJ, G, D>),
                   hipFuncAttributeMaxDynamicSharedMemorySize, int(tab)) == hipSuccess;
   if (use_lds) {
-    const int per_cu = 2 * tab <= size_t(dl.lds_per_cu) ? 2 : 1;
-    const int grid = (dl.n_cu * per_cu + 7) / 8 * 8;
+    // float32 (80-byte records, two could share a CU): one workgroup per CU; with the next
+    // tile's loads in flight, 16 waves per CU stream better than 32 sharing the L1 (30 us
+    // against 38 us on the 1000-camera workload) or than more workgroups queued per CU.
+    // float64 (128-byte records, one workgroup per CU): four workgroups per CU queued, so
+    // that CUs that finish early take more tiles (96 us against 104 us with one).
+    const int grid = (dl.n_cu * (sizeof(T) == 8 ? 4 : 1) + 7) / 8 * 8;
     const int ppx = (cp.Pa + 7) / 8;
     launch_k(k_schur_point_lds<T, ADJ, G, D>, dim3(grid), dim3(kPtLdsBlock), uint32_t(tab), s,
              m, cp, om, mvt, Vinv, zq, st, ppx);
