@@ -435,11 +435,13 @@ k_scan_add(int64_t n, const int* __restrict__ tile_sums, int* __restrict__ out) 
   }
 }
 
+__global__ void k_zero_count(int* __restrict__ out) { *out = 0; }
+
 template <class F>
 void scan_impl(hipStream_t s, int64_t n, F flag, int* out, int* tmp) {
   const int nt = int((n + kScanTile - 1) / kScanTile);
-  if (nt == 0) {
-    hipMemsetAsync(out, 0, sizeof(int), s);
+  if (nt == 0) {   // empty input: the total is zero (a kernel, like every other step)
+    launch_k(k_zero_count, dim3(1), dim3(1), 0, s, out);
     return;
   }
   launch_k(k_scan_tile<F>, dim3(nt), dim3(kBlock), 0, s, n, flag, out, tmp);
