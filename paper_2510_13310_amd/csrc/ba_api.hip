@@ -1062,7 +1062,7 @@ int gp_run_pcg(ba_ctx& c, PcgState* out_state) {
     for (int k = 0; k < every && it < c.opt.pcg_max_iters; ++k, ++it) {
       c.timed("gp_schur_point", bp, it, [&] {
         launch_gp_schur_point<T>(s, G, cp, a_pm, c.mvt, static_cast<const T*>(c.Vinv), zq,
-                                 c.pcg);
+                                 c.pcg, c.dl);
       });
       c.timed("gp_schur_cam", bc, it, [&] {
         launch_gp_schur_cam<T>(s, cp, a_cm, c.u, zq, K, c.item_off, c.item_cam, nslot, c.part,

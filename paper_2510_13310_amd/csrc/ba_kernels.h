@@ -424,7 +424,8 @@ void launch_gp_cam_assemble(hipStream_t s, const Compact<T>& cp, double lam, dou
 // The two PCG passes of S u = U* u - sum_c A V*^-1 sum_p A u (camera records GpMv).
 template <typename T>
 void launch_gp_schur_point(hipStream_t s, int G, const Compact<T>& cp, const V4<T>* a_pm,
-                           const void* mvt, const T* Vinv, P3<T>* zq_cm, const PcgState* st);
+                           const void* mvt, const T* Vinv, P3<T>* zq_cm, const PcgState* st,
+                           const DevLimits& dl);
 template <typename T>
 void launch_gp_schur_cam(hipStream_t s, const Compact<T>& cp, const V4<T>* a_cm,
                          const double* u, const P3<T>* zq, int K, const int* item_off,
