@@ -121,7 +121,9 @@ struct ba_ctx {
   // extraction
   uint8_t *vrow = nullptr, *vrow_cm = nullptr, *act_c = nullptr, *act_p = nullptr;
   int *rank_c = nullptr, *rank_p = nullptr, *pos_pm = nullptr, *pos_cm = nullptr;
-  int *scan_tmp = nullptr, *flags = nullptr;   // flags[0] changed, flags[1] bad damping
+  void* scan_temp = nullptr;                   // device-wide scan workspace
+  size_t scan_temp_size = 0;
+  int* flags = nullptr;                        // flags[0] changed, flags[1] bad damping
   int *cam_hat = nullptr, *orig_hat = nullptr, *off_hat = nullptr, *pt_src = nullptr;
   int *cam_src = nullptr, *slot_all = nullptr, *cm_off_hat = nullptr, *cm_pt = nullptr,
       *pm_cm = nullptr;
@@ -387,7 +389,10 @@ void alloc_obs_buffers(ba_ctx& c) {
   c.rank_p = A.alloc<int>(P + 1);
   c.pos_pm = A.alloc<int>(N + 1);
   c.pos_cm = A.alloc<int>(N + 1);
-  c.scan_tmp = A.alloc<int>(scan_tmp_ints(std::max<int64_t>({N, int64_t(P), int64_t(C)})));
+  if (std::max<int64_t>({N, int64_t(P), int64_t(C)}) + 1 > int64_t(INT32_MAX))
+    throw BaError{BA_ERR_ARG, "more than 2^31 - 2 observations, points or cameras"};
+  c.scan_temp_size = scan_temp_bytes(std::max<int64_t>({N, int64_t(P), int64_t(C)}));
+  c.scan_temp = A.alloc<char>(c.scan_temp_size);
   c.flags = A.alloc<int>(4);
   c.cam_hat = A.alloc<int>(N);
   c.orig_hat = A.alloc<int>(N);
@@ -543,10 +548,11 @@ void extract(ba_ctx& c, bool gp = false) {
   }
   c.rounds = rounds;
   c.timed_multi("scan", double(c.C) * 5 + double(c.P) * 5 + double(N) * 14, [&] {
-    launch_scan_u8(s, c.C, c.act_c, c.rank_c, c.scan_tmp);
-    launch_scan_u8(s, c.P, c.act_p, c.rank_p, c.scan_tmp);
-    launch_scan_u8(s, N, c.vrow, c.pos_pm, c.scan_tmp);
-    launch_scan_cm(s, N, c.vrow_cm, c.cm_cam, c.d_fixed, c.pos_cm, c.scan_tmp);
+    const size_t tb = c.scan_temp_size;
+    HIP_CHECK(launch_scan_u8(s, c.C, c.act_c, c.rank_c, c.scan_temp, tb));
+    HIP_CHECK(launch_scan_u8(s, c.P, c.act_p, c.rank_p, c.scan_temp, tb));
+    HIP_CHECK(launch_scan_u8(s, N, c.vrow, c.pos_pm, c.scan_temp, tb));
+    HIP_CHECK(launch_scan_cm(s, N, c.vrow_cm, c.cm_cam, c.d_fixed, c.pos_cm, c.scan_temp, tb));
   });
   int* hp = reinterpret_cast<int*>(c.h_pin);
   HIP_CHECK(hipMemcpyAsync(hp + 0, c.rank_c + c.C, sizeof(int), hipMemcpyDeviceToHost, s));

@@ -16,8 +16,6 @@
 namespace iba {
 
 constexpr int kBlock = 256;           // threads per block for streaming kernels
-constexpr int kScanItems = 16;        // elements per thread in the block scan
-constexpr int kScanTile = kBlock * kScanItems;
 
 // Camera table entry: rotation (row-major, world to camera), centre, intrinsics.
 template <typename T>
@@ -190,11 +188,14 @@ void launch_point_rows_prune(hipStream_t s, int P, const int* pt_off, const int*
                              const uint8_t* act_c, const uint8_t* fixed, int need,
                              const int* inv_cm, uint8_t* vrow, uint8_t* vrow_cm,
                              uint8_t* act_p, int* changed);
-// Exclusive scans; out has n + 1 entries (out[n] = total). tmp needs scan_tmp_ints(n) ints.
-int64_t scan_tmp_ints(int64_t n);
-void launch_scan_u8(hipStream_t s, int64_t n, const uint8_t* flags, int* out, int* tmp);
-void launch_scan_cm(hipStream_t s, int64_t n, const uint8_t* vrow_cm, const int* cm_cam,
-                    const uint8_t* fixed, int* out, int* tmp);
+// Exclusive scans of 0/1 flags (device-wide single-pass scans from hipCUB, ba_sort.hip); out
+// has n + 1 entries (out[n] = total); temp needs scan_temp_bytes(n) bytes, n < 2^31 - 1.
+// scan_cm flags camera-major observation m when it is valid and its camera is not fixed.
+size_t scan_temp_bytes(int64_t n);
+hipError_t launch_scan_u8(hipStream_t s, int64_t n, const uint8_t* flags, int* out, void* temp,
+                          size_t temp_bytes);
+hipError_t launch_scan_cm(hipStream_t s, int64_t n, const uint8_t* vrow_cm, const int* cm_cam,
+                          const uint8_t* fixed, int* out, void* temp, size_t temp_bytes);
 void launch_compact_points(hipStream_t s, int P, const uint8_t* act_p, const int* rank_p,
                            const int* pt_off, const int* pos_pm, const double* pts,
                            int* pt_src, int* off_hat, double* Xd, float* Xf);

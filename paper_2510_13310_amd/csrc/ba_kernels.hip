@@ -345,110 +345,6 @@ k_point_rows_prune(int P, const int* __restrict__ pt_off, const int* __restrict_
   if (drop) *changed = 1;   // every writer stores the same value
 }
 
-// ------------------------------------------------------------------ exclusive scan
-struct FlagU8 {
-  const uint8_t* a;
-  __device__ __forceinline__ int operator()(int64_t i) const { return a[i] != 0; }
-};
-// Camera-major observation m stays in the solve: valid and its camera not fixed.
-struct FlagCM {
-  const uint8_t* vrow_cm;
-  const int* cm_cam;
-  const uint8_t* fixed;
-  __device__ __forceinline__ int operator()(int64_t m) const {
-    return vrow_cm[m] != 0 && !fixed[cm_cam[m]];
-  }
-};
-
-template <class F>
-__global__ void __launch_bounds__(kBlock)
-k_scan_tile(int64_t n, F flag, int* __restrict__ out, int* __restrict__ tile_sums) {
-  __shared__ int s_wave[kBlock / kWave];
-  const int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * kScanItems;
-  int vals[kScanItems];
-  int sum = 0;
-#pragma unroll
-  for (int i = 0; i < kScanItems; ++i) {
-    const int64_t idx = base + i;
-    const int f = idx < n ? flag(idx) : 0;
-    vals[i] = sum;
-    sum += f;
-  }
-  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  int incl = sum;
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    const int t = __shfl_up(incl, o, kWave);
-    if (lane >= o) incl += t;
-  }
-  if (lane == kWave - 1) s_wave[wid] = incl;
-  __syncthreads();
-  int woff = 0;
-  for (int w = 0; w < wid; ++w) woff += s_wave[w];
-  const int excl = woff + incl - sum;
-#pragma unroll
-  for (int i = 0; i < kScanItems; ++i) {
-    const int64_t idx = base + i;
-    if (idx < n) out[idx] = vals[i] + excl;
-  }
-  if (threadIdx.x == blockDim.x - 1) tile_sums[blockIdx.x] = excl + sum;
-}
-
-// Exclusive scan of the tile sums in one block; writes the grand total to *total.
-__global__ void __launch_bounds__(1024)
-k_scan_tiles(int nt, int* __restrict__ tile_sums, int* __restrict__ total) {
-  __shared__ int s_wave[1024 / kWave];
-  const int per = (nt + blockDim.x - 1) / blockDim.x;
-  const int b = threadIdx.x * per;
-  int sum = 0;
-  for (int i = 0; i < per; ++i)
-    if (b + i < nt) sum += tile_sums[b + i];
-  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  int incl = sum;
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    const int t = __shfl_up(incl, o, kWave);
-    if (lane >= o) incl += t;
-  }
-  if (lane == kWave - 1) s_wave[wid] = incl;
-  __syncthreads();
-  int woff = 0;
-  for (int w = 0; w < wid; ++w) woff += s_wave[w];
-  int run = woff + incl - sum;
-  for (int i = 0; i < per; ++i) {
-    if (b + i < nt) {
-      const int v = tile_sums[b + i];
-      tile_sums[b + i] = run;
-      run += v;
-    }
-  }
-  if (threadIdx.x == blockDim.x - 1) *total = woff + incl;
-}
-
-__global__ void __launch_bounds__(kBlock)
-k_scan_add(int64_t n, const int* __restrict__ tile_sums, int* __restrict__ out) {
-  const int add = tile_sums[blockIdx.x];
-  const int64_t base = int64_t(blockIdx.x) * kScanTile;
-  for (int i = threadIdx.x; i < kScanTile; i += blockDim.x) {
-    const int64_t idx = base + i;
-    if (idx < n) out[idx] += add;
-  }
-}
-
-__global__ void k_zero_count(int* __restrict__ out) { *out = 0; }
-
-template <class F>
-void scan_impl(hipStream_t s, int64_t n, F flag, int* out, int* tmp) {
-  const int nt = int((n + kScanTile - 1) / kScanTile);
-  if (nt == 0) {   // empty input: the total is zero (a kernel, like every other step)
-    launch_k(k_zero_count, dim3(1), dim3(1), 0, s, out);
-    return;
-  }
-  launch_k(k_scan_tile<F>, dim3(nt), dim3(kBlock), 0, s, n, flag, out, tmp);
-  launch_k(k_scan_tiles, dim3(1), dim3(1024), 0, s, nt, tmp, out + n);
-  launch_k(k_scan_add, dim3(nt), dim3(kBlock), 0, s, n, tmp, out);
-}
-
 // ------------------------------------------------------------------ compaction kernels
 __global__ void __launch_bounds__(kBlock)
 k_compact_points(int P, const uint8_t* __restrict__ act_p, const int* __restrict__ rank_p,
@@ -2676,17 +2572,6 @@ void launch_point_rows_prune(hipStream_t s, int P, const int* pt_off, const int*
                              uint8_t* act_p, int* changed) {
   launch_k(k_point_rows_prune, dim3(blocks_for(P)), dim3(kBlock), 0, s, P, pt_off, pm_cam,
            act_c, fixed, need, inv_cm, vrow, vrow_cm, act_p, changed);
-}
-
-int64_t scan_tmp_ints(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
-
-void launch_scan_u8(hipStream_t s, int64_t n, const uint8_t* flags, int* out, int* tmp) {
-  scan_impl(s, n, FlagU8{flags}, out, tmp);
-}
-
-void launch_scan_cm(hipStream_t s, int64_t n, const uint8_t* vrow_cm, const int* cm_cam,
-                    const uint8_t* fixed, int* out, int* tmp) {
-  scan_impl(s, n, FlagCM{vrow_cm, cm_cam, fixed}, out, tmp);
 }
 
 void launch_compact_points(hipStream_t s, int P, const uint8_t* act_p, const int* rank_p,
