@@ -523,8 +523,8 @@ void extract(ba_ctx& c, bool gp = false) {
     });
   else
     c.timed("validate", double(N) * (4 + 4 + 8 + 4 + 24 + 1 + 4 + 1), -1, [&] {
-      launch_validate(s, N, m, c.pm_cam, c.pm_pt, c.pm_xy, c.pm_depth, c.d_pts, c.d_camd,
-                      c.inv_cm, c.vrow, c.vrow_cm);
+      launch_validate_lds(s, N, c.C, m, c.pm_cam, c.pm_pt, c.pm_xy, c.pm_depth, c.d_pts,
+                          c.d_camd, c.inv_cm, c.vrow, c.vrow_cm, c.dl, 1);
     });
   const int need_cam = gp ? 3 : c.need_cam();
   const int need_pt = gp ? 3 : c.need_pt();

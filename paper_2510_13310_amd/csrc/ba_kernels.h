@@ -173,6 +173,12 @@ struct alignas(16) PtRec {
   T vinv[6];      // damped inverse point block (symmetric 3x3)
 };
 
+// Device figures the launchers size persistent grids and LDS tables with.
+struct DevLimits {
+  int n_cu = 0;            // compute units
+  int lds_per_block = 0;   // bytes of LDS one workgroup may use
+};
+
 // ------------------------------------------------------------------ extraction
 void launch_cam_table(hipStream_t s, int C, const double* cams, const double* intr,
                       Cam<double>* camd, Cam<float>* camf);
@@ -182,6 +188,12 @@ void launch_validate(hipStream_t s, int64_t N, const Model& m, const int* pm_cam
                      const int* pm_pt, const float2* xy, const float* depth,
                      const double* pts, const Cam<double>* camd, const int* inv_cm,
                      uint8_t* vrow, uint8_t* vrow_cm);
+// The same with the C camera records staged in LDS when they fit (else launch_validate), over
+// a grid of per_cu workgroups per CU.
+void launch_validate_lds(hipStream_t s, int64_t N, int C, const Model& m, const int* pm_cam,
+                         const int* pm_pt, const float2* xy, const float* depth,
+                         const double* pts, const Cam<double>* camd, const int* inv_cm,
+                         uint8_t* vrow, uint8_t* vrow_cm, const DevLimits& dl, int per_cu);
 void launch_cam_rows(hipStream_t s, int C, const int* cm_off, const uint8_t* vrow_cm,
                      const uint8_t* fixed, int need, uint8_t* act_c);
 void launch_point_rows_prune(hipStream_t s, int P, const int* pt_off, const int* pm_cam,
@@ -265,11 +277,6 @@ inline void cam_chunking(int Nc, int& K, int& nchunks) {
 }
 // Camera-side launchers take the camera dimension D: 6 (pose) or 7 (pose and focal length,
 // matvec records MvCamF); the adjoint mode runs with D = 6 only.
-// Device figures the launchers size persistent grids and LDS tables with.
-struct DevLimits {
-  int n_cu = 0;            // compute units
-  int lds_per_block = 0;   // bytes of LDS one workgroup may use
-};
 
 // z_p = Vinv sum_k W_k^T u_c (point-major pass, G lanes per point), written to the
 // camera-major position of every observation of p in a solve camera (zq_cm, Nc entries).

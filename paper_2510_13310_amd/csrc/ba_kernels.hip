@@ -15,6 +15,7 @@
 
 #include <hip/hip_ext.h>
 
+#include <algorithm>
 #include <cmath>
 #include <type_traits>
 
@@ -303,6 +304,46 @@ k_validate(int64_t N, Model m, const int* __restrict__ pm_cam, const int* __rest
   const uint8_t v = ok ? uint8_t(rows) : uint8_t(0);
   vrow[k] = v;
   vrow_cm[inv_cm[k]] = v;
+}
+
+// The same over a grid-stride walk with the camera table staged in LDS (C records of 120 B),
+// so the per-observation camera reads hit LDS instead of L2.
+constexpr int kLdsWalkBlock = 1024;
+
+__global__ void __launch_bounds__(kLdsWalkBlock)
+k_validate_lds(int64_t N, int C, Model m, const int* __restrict__ pm_cam,
+               const int* __restrict__ pm_pt, const float2* __restrict__ xy,
+               const float* __restrict__ depth, const double* __restrict__ pts,
+               const Cam<double>* __restrict__ camd, const int* __restrict__ inv_cm,
+               uint8_t* __restrict__ vrow, uint8_t* __restrict__ vrow_cm) {
+  extern __shared__ double lds_cam[];   // C records
+  const int nwords = C * int(sizeof(Cam<double>) / sizeof(double));
+  const double* src = reinterpret_cast<const double*>(camd);
+  for (int i = threadIdx.x; i < nwords; i += kLdsWalkBlock) lds_cam[i] = src[i];
+  __syncthreads();
+  const Cam<double>* tab = reinterpret_cast<const Cam<double>*>(lds_cam);
+  const int64_t stride = int64_t(gridDim.x) * kLdsWalkBlock;
+  for (int64_t k = int64_t(blockIdx.x) * kLdsWalkBlock + threadIdx.x; k < N; k += stride) {
+    const Cam<double> cm = tab[pm_cam[k]];
+    const int p = pm_pt[k];
+    double Xc[3];
+    cam_frame(cm, pts[3 * p], pts[3 * p + 1], pts[3 * p + 2], Xc);
+    bool ok = Xc[2] > m.min_depth;
+    if (ok) {
+      const double u = cm.f * Xc[0] / Xc[2] + cm.cx;
+      const double v = cm.f * Xc[1] / Xc[2] + cm.cy;
+      ok = u >= 0.0 && u < double(m.img_w) && v >= 0.0 && v < double(m.img_h);
+      if (ok && m.filter_px > 0.0) {
+        double e[3];
+        residual(cm, Xc, xy[k], 0.0f, 0.0, e);
+        ok = e[0] * e[0] + e[1] * e[1] <= m.filter_px * m.filter_px;
+      }
+    }
+    const int rows = 2 + ((m.lam_d > 0.0 && depth[k] > 0.0f) ? 1 : 0);
+    const uint8_t v = ok ? uint8_t(rows) : uint8_t(0);
+    vrow[k] = v;
+    vrow_cm[inv_cm[k]] = v;
+  }
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -2559,6 +2600,27 @@ void launch_validate(hipStream_t s, int64_t N, const Model& m, const int* pm_cam
   if (N == 0) return;
   launch_k(k_validate, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, m, pm_cam, pm_pt, xy, depth,
            pts, camd, inv_cm, vrow, vrow_cm);
+}
+
+void launch_validate_lds(hipStream_t s, int64_t N, int C, const Model& m, const int* pm_cam,
+                         const int* pm_pt, const float2* xy, const float* depth,
+                         const double* pts, const Cam<double>* camd, const int* inv_cm,
+                         uint8_t* vrow, uint8_t* vrow_cm, const DevLimits& dl, int per_cu) {
+  if (N == 0) return;
+  const size_t tab = size_t(C) * sizeof(Cam<double>);
+  bool use_lds = dl.n_cu > 0 && C > 0 && tab <= size_t(dl.lds_per_block);
+  if (use_lds && tab > 65536)
+    use_lds = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_validate_lds),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(tab)) ==
+              hipSuccess;
+  if (!use_lds) {
+    launch_validate(s, N, m, pm_cam, pm_pt, xy, depth, pts, camd, inv_cm, vrow, vrow_cm);
+    return;
+  }
+  const int64_t need = (N + kLdsWalkBlock - 1) / kLdsWalkBlock;
+  const int grid = int(std::min<int64_t>(need, int64_t(dl.n_cu) * per_cu));
+  launch_k(k_validate_lds, dim3(grid), dim3(kLdsWalkBlock), uint32_t(tab), s, N, C, m, pm_cam,
+           pm_pt, xy, depth, pts, camd, inv_cm, vrow, vrow_cm);
 }
 
 void launch_cam_rows(hipStream_t s, int C, const int* cm_off, const uint8_t* vrow_cm,
