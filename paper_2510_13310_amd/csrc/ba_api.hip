@@ -629,16 +629,18 @@ void linearize(ba_ctx& c, bool adj) {
   Compact<T> cp = compact_view<T>(c);
   ObsMetric<T> om = metric_view<T>(c);
   const double ts = double(sizeof(T));
-  // per observation: slot, xy, depth and camera-major position read; w and the (X_c, w)
-  // stream written, plus the camera-major (X_c, w) and e (and eh) for solve cameras
-  c.timed("lin_point", double(c.Nh) * (4 + 8 + 4 + 4 + ts + 4 * ts + (adj ? 3 * ts : 0)) +
+  // per observation: slot, xy, depth and camera-major position read; w written (and the
+  // point-major (X_c, w) where kept), plus the camera-major (X_c, w) and e (and eh) for solve
+  // cameras
+  const double pm_stream = c.pm_xcw ? 4 * ts : 0.0;
+  int nb = 0;
+  c.timed("lin_point", double(c.Nh) * (4 + 8 + 4 + 4 + ts + pm_stream + (adj ? 3 * ts : 0)) +
                            double(c.Nc) * (8 * ts + (adj ? 3 * ts : 0)) +
                            double(c.Pa) * (4 + 24 + 48 + 24) + double(c.C) * 120,
           -1, [&] {
-            launch_lin_point<T>(s, adj, lanes_per_point(c), m, cp, om,
-                                static_cast<double*>(c.V), c.gp, c.partials);
+            nb = launch_lin_point<T>(s, adj, lanes_per_point(c), m, cp, om,
+                                     static_cast<double*>(c.V), c.gp, c.partials, c.dl);
           });
-  const int nb = lin_point_blocks(c.Pa);
   launch_reduce_partials(s, nb, 3, c.partials, 0x4u, 0, nullptr, nullptr, c.scal);
   HIP_LAUNCH_CHECK();
 }
@@ -929,13 +931,14 @@ ba_status lm_step_impl(ba_ctx& c, ba_step_report* rep) {
                                  c.d_cand_cams, c.d_cand_tab);
           });
   Compact<T> cp = compact_view<T>(c);
+  int nb = 0;
   c.timed("point_candidate",
           double(c.Nh) * (4 + 8 + 4 + ts) + double(c.Pa) * (4 + 24 * 4) + double(c.C) * 240, -1,
           [&] {
-            launch_point_candidate<T>(s, m, cp, c.D, c.d_cand_tab, c.x, c.dp, c.gp,
-                                      static_cast<const T*>(c.w), c.Xcand, c.partials);
+            nb = launch_point_candidate<T>(s, m, cp, c.D, c.d_cand_tab, c.x, c.dp, c.gp,
+                                           static_cast<const T*>(c.w), c.Xcand, c.partials,
+                                           c.dl);
           });
-  const int nb = int((c.Pa + kBlock - 1) / kBlock);
   // scal[4..] = decrease, quad, g_p.dp, bad, cost', g_c.x, max |g_c|
   launch_reduce_partials(s, nb, 5, c.partials, 0x0u, c.D * c.Ca, c.gc, c.x, c.scal + 4);
   HIP_LAUNCH_CHECK();

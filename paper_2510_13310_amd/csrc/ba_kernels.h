@@ -238,9 +238,12 @@ void launch_mv_table(hipStream_t s, int D, int n, const Cam<double>* camd_hat, v
 // G lanes per point; one workgroup per 256 points, grid lin_point_blocks(Pa) (partials
 // needs 3 doubles per workgroup).
 inline int lin_point_blocks(int Pa) { return ((Pa + kBlock - 1) / kBlock + 7) / 8 * 8; }
+inline int lin_point_blocks_lds(int Pa) { return ((Pa + 1023) / 1024 + 7) / 8 * 8; }
+// Returns the number of partial triples written (one per workgroup).
 template <typename T>
-void launch_lin_point(hipStream_t s, bool adj, int G, const Model& m, const Compact<T>& cp,
-                      ObsMetric<T> om, double* V, double* gp, double* partials);
+int launch_lin_point(hipStream_t s, bool adj, int G, const Model& m, const Compact<T>& cp,
+                     ObsMetric<T> om, double* V, double* gp, double* partials,
+                     const DevLimits& dl);
 // V* = V + lam clamp(diag V); Vinv (inverted in float64, stored as T); hp = Vinv rhs_p.
 // rhs_p = -gp when rhs_p == nullptr.
 template <typename T>
@@ -314,9 +317,10 @@ void launch_cam_candidate(hipStream_t s, int Ca, int Cf, int D, const int* cam_s
                           const double* x, const double* cams, const Cam<double>* camd_hat,
                           double* cand_cams, Cam<double>* cand_tab);
 template <typename T>
-void launch_point_candidate(hipStream_t s, const Model& m, const Compact<T>& cp, int D,
-                            const Cam<double>* cand_tab, const double* x, const double* dp,
-                            const double* gp, const T* w, double* Xcand, double* partials);
+int launch_point_candidate(hipStream_t s, const Model& m, const Compact<T>& cp, int D,
+                           const Cam<double>* cand_tab, const double* x, const double* dp,
+                           const double* gp, const T* w, double* Xcand, double* partials,
+                           const DevLimits& dl);
 // Sums per-block partials (K doubles per block) in a fixed order; with gc != nullptr also
 // out[K] = gc . x over the ncu camera unknowns and out[K + 1] = max |gc|.
 void launch_reduce_partials(hipStream_t s, int nblocks, int K, const double* partials,

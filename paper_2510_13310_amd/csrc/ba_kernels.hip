@@ -483,19 +483,30 @@ k_mv_table(int n, const Cam<double>* __restrict__ camd_hat, MvRec<T, D>* __restr
 // ------------------------------------------------------------------ linearisation
 // Workgroup b (XCD-mapped as in the PCG point pass) linearises points [256 b, 256 b + 256) in
 // G tiles, with G lanes per point; lanes combine V and gp with shuffles. Partials per
-// workgroup: cost, sum |r_2d|^2, max |gp|.
-template <typename T, bool ADJ, int G>
-__global__ void __launch_bounds__(kBlock)
+// workgroup: cost, sum |r_2d|^2, max |gp|. With LDS, B = 1024-thread workgroups first copy
+// the compact camera table (Ca + Cf records of 120 B) into LDS, so the per-observation camera
+// reads hit LDS instead of L2.
+template <typename T, bool ADJ, int G, int B, bool LDS>
+__global__ void __launch_bounds__(B)
 k_lin_point(Model m, Compact<T> cp, ObsMetric<T> om, double* __restrict__ V,
             double* __restrict__ gp, double* __restrict__ partials) {
-  __shared__ double smem[3 * (kBlock / kWave)];
+  __shared__ double smem[3 * (B / kWave)];
+  extern __shared__ double lds_cam[];   // LDS: the compact camera table
+  const Cam<double>* camtab = cp.camd;
+  if constexpr (LDS) {
+    const int nwords = (cp.Ca + cp.Cf) * int(sizeof(Cam<double>) / sizeof(double));
+    const double* src = reinterpret_cast<const double*>(cp.camd);
+    for (int i = threadIdx.x; i < nwords; i += B) lds_cam[i] = src[i];
+    __syncthreads();
+    camtab = reinterpret_cast<const Cam<double>*>(lds_cam);
+  }
   const int per = gridDim.x / 8;
   const int blk = (blockIdx.x % 8) * per + blockIdx.x / 8;
-  constexpr int tile = kBlock / G;
+  constexpr int tile = B / G;
   const int l = int(threadIdx.x) % G;
   double acc[3] = {0.0, 0.0, 0.0};   // cost, sum |r_2d|^2, max |gp|
   for (int t = 0; t < G; ++t) {
-    const int r = blk * kBlock + t * tile + int(threadIdx.x) / G;
+    const int r = blk * B + t * tile + int(threadIdx.x) / G;
     const bool live = r < cp.Pa;
     double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     double g[3] = {0.0, 0.0, 0.0};
@@ -503,7 +514,7 @@ k_lin_point(Model m, Compact<T> cp, ObsMetric<T> om, double* __restrict__ V,
       const double X0 = cp.Xd[3 * r], X1 = cp.Xd[3 * r + 1], X2 = cp.Xd[3 * r + 2];
       const T Xt0 = cp.Xt[3 * r], Xt1 = cp.Xt[3 * r + 1], Xt2 = cp.Xt[3 * r + 2];
       for (int j = cp.off[r] + l; j < cp.off[r + 1]; j += G) {
-        const Cam<double> cm = cp.camd[cp.cam[j]];
+        const Cam<double> cm = camtab[cp.cam[j]];
         double Xc[3], e[3];
         cam_frame(cm, X0, X1, X2, Xc);
         residual(cm, Xc, cp.xy[j], cp.depth[j], m.lam_d, e);
@@ -1501,13 +1512,23 @@ k_cam_candidate(int Ca, int Cf, int D, const int* __restrict__ cam_src,
 // the changes rather than with the cost; the quadratic term of the model decrease
 // sum w |J delta|^2 (Jacobian at the linearisation point); g_p.dp; the number of candidate
 // depths <= min_depth; and the candidate cost itself.
-template <typename T>
-__global__ void __launch_bounds__(kBlock)
+// With LDS, B = 1024-thread workgroups first copy the candidate camera table into LDS (one
+// 120-byte table fits; the current table stays in L2).
+template <typename T, int B, bool LDS>
+__global__ void __launch_bounds__(B)
 k_point_candidate(Model m, Compact<T> cp, int D, const Cam<double>* __restrict__ cand_tab,
                   const double* __restrict__ x, const double* __restrict__ dp,
                   const double* __restrict__ gp, const T* __restrict__ w,
                   double* __restrict__ Xcand, double* __restrict__ partials) {
-  __shared__ double smem[5 * (kBlock / kWave)];
+  __shared__ double smem[5 * (B / kWave)];
+  extern __shared__ double lds_cand[];   // LDS: the candidate camera table
+  if constexpr (LDS) {
+    const int nwords = (cp.Ca + cp.Cf) * int(sizeof(Cam<double>) / sizeof(double));
+    const double* src = reinterpret_cast<const double*>(cand_tab);
+    for (int i = threadIdx.x; i < nwords; i += B) lds_cand[i] = src[i];
+    __syncthreads();
+    cand_tab = reinterpret_cast<const Cam<double>*>(lds_cand);
+  }
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   const int Ca = cp.Ca;
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // decrease, quad, g_p.dp, bad, cost'
@@ -2671,25 +2692,48 @@ void launch_compact_obs(hipStream_t s, int64_t N, const uint8_t* vrow, const int
 }
 
 
-template <typename T, bool ADJ>
-void lin_point_g(hipStream_t s, int G, const Model& m, const Compact<T>& cp, ObsMetric<T> om,
-                 double* V, double* gp, double* partials) {
-  const unsigned nb = unsigned(lin_point_blocks(cp.Pa));
+// Lanes-per-point dispatch: G = 2, 4, 8 or 16 as a compile-time constant.
+template <class F>
+void with_lanes(int G, F&& f) {
   switch (G) {
-    case 2: launch_k(k_lin_point<T, ADJ, 2>, dim3(nb), dim3(kBlock), 0, s, m, cp, om, V, gp, partials); break;
-    case 4: launch_k(k_lin_point<T, ADJ, 4>, dim3(nb), dim3(kBlock), 0, s, m, cp, om, V, gp, partials); break;
-    case 16: launch_k(k_lin_point<T, ADJ, 16>, dim3(nb), dim3(kBlock), 0, s, m, cp, om, V, gp, partials); break;
-    default: launch_k(k_lin_point<T, ADJ, 8>, dim3(nb), dim3(kBlock), 0, s, m, cp, om, V, gp, partials);
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 16: f(std::integral_constant<int, 16>{}); break;
+    default: f(std::integral_constant<int, 8>{});
   }
 }
 
+template <typename T, bool ADJ>
+int lin_point_g(hipStream_t s, int G, const Model& m, const Compact<T>& cp, ObsMetric<T> om,
+                double* V, double* gp, double* partials, const DevLimits& dl) {
+  const size_t tab = size_t(cp.Ca + cp.Cf) * sizeof(Cam<double>);
+  const bool lds = dl.n_cu > 0 && cp.Ca + cp.Cf > 0 && tab + 3 * 16 * 8 <= size_t(dl.lds_per_block);
+  int nb = 0;
+  with_lanes(G, [&](auto Gc) {
+    constexpr int g = Gc();
+    bool use = lds;
+    if (use && tab > 65536)
+      use = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lin_point<T, ADJ, g, 1024, true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(tab)) == hipSuccess;
+    if (use) {
+      nb = lin_point_blocks_lds(cp.Pa);
+      launch_k(k_lin_point<T, ADJ, g, 1024, true>, dim3(nb), dim3(1024), uint32_t(tab), s, m, cp,
+               om, V, gp, partials);
+    } else {
+      nb = lin_point_blocks(cp.Pa);
+      launch_k(k_lin_point<T, ADJ, g, kBlock, false>, dim3(nb), dim3(kBlock), 0, s, m, cp, om,
+               V, gp, partials);
+    }
+  });
+  return nb;
+}
+
 template <typename T>
-void launch_lin_point(hipStream_t s, bool adj, int G, const Model& m, const Compact<T>& cp,
-                      ObsMetric<T> om, double* V, double* gp, double* partials) {
-  if (adj)
-    lin_point_g<T, true>(s, G, m, cp, om, V, gp, partials);
-  else
-    lin_point_g<T, false>(s, G, m, cp, om, V, gp, partials);
+int launch_lin_point(hipStream_t s, bool adj, int G, const Model& m, const Compact<T>& cp,
+                     ObsMetric<T> om, double* V, double* gp, double* partials,
+                     const DevLimits& dl) {
+  if (adj) return lin_point_g<T, true>(s, G, m, cp, om, V, gp, partials, dl);
+  return lin_point_g<T, false>(s, G, m, cp, om, V, gp, partials, dl);
 }
 
 template <typename T>
@@ -2884,11 +2928,25 @@ void launch_cam_candidate(hipStream_t s, int Ca, int Cf, int D, const int* cam_s
 }
 
 template <typename T>
-void launch_point_candidate(hipStream_t s, const Model& m, const Compact<T>& cp, int D,
-                            const Cam<double>* cand_tab, const double* x, const double* dp,
-                            const double* gp, const T* w, double* Xcand, double* partials) {
-  launch_k(k_point_candidate<T>, dim3(blocks_for(cp.Pa)), dim3(kBlock), 0, s, m, cp, D,
+int launch_point_candidate(hipStream_t s, const Model& m, const Compact<T>& cp, int D,
+                           const Cam<double>* cand_tab, const double* x, const double* dp,
+                           const double* gp, const T* w, double* Xcand, double* partials,
+                           const DevLimits& dl) {
+  const size_t tab = size_t(cp.Ca + cp.Cf) * sizeof(Cam<double>);
+  bool lds = dl.n_cu > 0 && cp.Ca + cp.Cf > 0 && tab + 5 * 16 * 8 <= size_t(dl.lds_per_block);
+  if (lds && tab > 65536)
+    lds = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_point_candidate<T, 1024, true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, int(tab)) == hipSuccess;
+  if (lds) {
+    const int nb = (cp.Pa + 1023) / 1024;
+    launch_k(k_point_candidate<T, 1024, true>, dim3(nb), dim3(1024), uint32_t(tab), s, m, cp, D,
+             cand_tab, x, dp, gp, w, Xcand, partials);
+    return nb;
+  }
+  const int nb = int(blocks_for(cp.Pa));
+  launch_k(k_point_candidate<T, kBlock, false>, dim3(nb), dim3(kBlock), 0, s, m, cp, D,
            cand_tab, x, dp, gp, w, Xcand, partials);
+  return nb;
 }
 
 void launch_reduce_partials(hipStream_t s, int nblocks, int K, const double* partials,
@@ -2926,8 +2984,8 @@ void launch_adjoint_obs(hipStream_t s, const Model& m, const Compact<T>& cp, Obs
 
 // explicit instantiations for the two precisions
 #define IBA_INSTANTIATE(T)                                                                    \
-  template void launch_lin_point<T>(hipStream_t, bool, int, const Model&, const Compact<T>&,  \
-                                    ObsMetric<T>, double*, double*, double*);                 \
+  template int launch_lin_point<T>(hipStream_t, bool, int, const Model&, const Compact<T>&,   \
+                                   ObsMetric<T>, double*, double*, double*, const DevLimits&); \
   template void launch_point_damp<T>(hipStream_t, int, double, double, double, const double*, \
                                      const double*, const double*, T*, double*, PtRec<T>*,    \
                                      int*);                                                    \
@@ -2953,9 +3011,10 @@ void launch_adjoint_obs(hipStream_t s, const Model& m, const Compact<T>& cp, Obs
   template void launch_backsub<T>(hipStream_t, bool, int, int, const Model&,                  \
                                   const Compact<T>&, ObsMetric<T>, const T*, const double*,   \
                                   const double*, const double*, double*);                      \
-  template void launch_point_candidate<T>(hipStream_t, const Model&, const Compact<T>&, int,  \
-                                          const Cam<double>*, const double*, const double*,   \
-                                          const double*, const T*, double*, double*);         \
+  template int launch_point_candidate<T>(hipStream_t, const Model&, const Compact<T>&, int,   \
+                                         const Cam<double>*, const double*, const double*,    \
+                                         const double*, const T*, double*, double*,           \
+                                         const DevLimits&);                                   \
   template void launch_adjoint_obs<T>(hipStream_t, const Model&, const Compact<T>&,           \
                                       ObsMetric<T>, const double*, const double*, const int*, \
                                       float*, float*);
@@ -3034,16 +3093,6 @@ IBA_EXPLICIT_INSTANTIATE(float)
 IBA_EXPLICIT_INSTANTIATE(double)
 
 // ------------------------------------------------------------------ global positioning launchers
-template <class F>
-void with_lanes(int G, F&& f) {
-  switch (G) {
-    case 2: f(std::integral_constant<int, 2>{}); break;
-    case 4: f(std::integral_constant<int, 4>{}); break;
-    case 16: f(std::integral_constant<int, 16>{}); break;
-    default: f(std::integral_constant<int, 8>{});
-  }
-}
-
 void launch_gp_validate(hipStream_t s, int64_t N, const float2* pm_xy, const float* pm_depth,
                         const int* inv_cm, uint8_t* vrow, uint8_t* vrow_cm) {
   if (N == 0) return;
