@@ -1125,14 +1125,14 @@ ba_status gp_step_impl(ba_ctx& c, ba_step_report* rep) {
     }
     cp = compact_view<T>(c);
     ta = now_ms();
+    int nbl = 0;
     c.timed("gp_lin", double(c.Nh) * (4 + 8 + 4 + 4 + 8 + 8 * ts) + double(c.Nc) * 8 * ts +
                           double(c.Pa) * (4 + 24 + 24) + double(c.C) * 120,
             -1, [&] {
-              launch_gp_lin<T>(s, lanes_per_point(c), cp, c.orig_hat, c.gp_s, delta, lin_pm,
-                               lin_cm, c.gp, c.partials);
+              nbl = launch_gp_lin<T>(s, lanes_per_point(c), cp, c.orig_hat, c.gp_s, delta,
+                                     lin_pm, lin_cm, c.gp, c.partials, c.dl);
             });
-    launch_reduce_partials(s, lin_point_blocks(c.Pa), 3, c.partials, 0x4u, 0, nullptr, nullptr,
-                           c.scal);
+    launch_reduce_partials(s, nbl, 3, c.partials, 0x4u, 0, nullptr, nullptr, c.scal);
     HIP_LAUNCH_CHECK();
     R.ms_linearize = now_ms() - ta;
     c.gp_lin_valid = true;
@@ -1175,13 +1175,13 @@ ba_status gp_step_impl(ba_ctx& c, ba_step_report* rep) {
           -1, [&] {
             launch_gp_backsub<T>(s, G, cp, a_pm, static_cast<const T*>(c.Vinv), c.hp, c.x, c.dp);
           });
+  int nb = 0;
   c.timed("gp_candidate", double(c.Nh) * (4 + 8 + 4 + 4 + 8 + 8) + double(c.Pa) * (4 + 24 * 4) +
                               double(c.C) * 240,
           -1, [&] {
-            launch_gp_candidate<T>(s, cp, c.orig_hat, c.gp_s, delta, lam, dmin, dmax, c.x, c.dp,
-                                   c.gp, c.Xcand, c.gp_scand, c.partials);
+            nb = launch_gp_candidate<T>(s, cp, c.orig_hat, c.gp_s, delta, lam, dmin, dmax, c.x,
+                                        c.dp, c.gp, c.Xcand, c.gp_scand, c.partials, c.dl);
           });
-  const int nb = int((c.Pa + kBlock - 1) / kBlock);
   // scal[4..] = decrease, quad, g_X.dX + g_s.ds, bad, cost', g_c.dc, max |g_c|
   launch_reduce_partials(s, nb, 5, c.partials, 0x0u, 3 * c.Ca, c.gc, c.x, c.scal + 4);
   HIP_LAUNCH_CHECK();

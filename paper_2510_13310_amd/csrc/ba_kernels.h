@@ -417,9 +417,9 @@ void launch_gp_init_scales(hipStream_t s, int64_t N, const int* pm_cam, const in
 // Residuals, weights, the records above, g_X = -sum w s u per point (gX, P x 3) and block
 // partials {cost, sum |u|^2, max |g|} (3 per block of lin_point_blocks(Pa)).
 template <typename T>
-void launch_gp_lin(hipStream_t s, int G, const Compact<T>& cp, const int* orig,
-                   const double* scales, double delta, GpLin<T>* lin_pm, GpLin<T>* lin_cm,
-                   double* gX, double* partials);
+int launch_gp_lin(hipStream_t s, int G, const Compact<T>& cp, const int* orig,
+                  const double* scales, double delta, GpLin<T>* lin_pm, GpLin<T>* lin_cm,
+                  double* gX, double* partials, const DevLimits& dl);   // returns the partials
 // Per point: the (e, a0) records in both orders, V* = sum A + lambda clamp(sum a0) I inverted
 // in float64, hp = V*^-1 r_X with r_X = sum w s (u + d g_s / h*), packed into prec.
 template <typename T>
@@ -450,10 +450,11 @@ void launch_gp_backsub(hipStream_t s, int G, const Compact<T>& cp, const V4<T>* 
 // scales s + ds with ds = (-g_s + w s d.(dc - dX)) / h*; per block {actual decrease, sum w
 // |J delta|^2, g_X.dX + g_s ds, scales <= 0, candidate cost} (5 per block of kBlock points).
 template <typename T>
-void launch_gp_candidate(hipStream_t s, const Compact<T>& cp, const int* orig,
-                         const double* scales, double delta, double lam, double dmin,
-                         double dmax, const double* x, const double* dp, const double* gX,
-                         double* Xcand, double* s_cand, double* partials);
+int launch_gp_candidate(hipStream_t s, const Compact<T>& cp, const int* orig,
+                        const double* scales, double delta, double lam, double dmin,
+                        double dmax, const double* x, const double* dp, const double* gX,
+                        double* Xcand, double* s_cand, double* partials,
+                        const DevLimits& dl);   // returns the number of partials
 // Accepted step: points, camera centres (cams C x 7, entries 4..6) and free scales.
 void launch_gp_scatter(hipStream_t s, int Pa, int Ca, int64_t Nh, const int* pt_src,
                        const double* Xcand, const int* cam_src, const double* x,

@@ -306,6 +306,18 @@ k_validate(int64_t N, Model m, const int* __restrict__ pm_cam, const int* __rest
   vrow_cm[inv_cm[k]] = v;
 }
 
+// Copies n float64 camera records into LDS (all B threads of the workgroup take part) and
+// returns the LDS copy.
+template <int B>
+__device__ __forceinline__ const Cam<double>* stage_cams(const Cam<double>* __restrict__ src,
+                                                         int n, double* lds) {
+  const int nwords = n * int(sizeof(Cam<double>) / sizeof(double));
+  const double* w = reinterpret_cast<const double*>(src);
+  for (int i = threadIdx.x; i < nwords; i += B) lds[i] = w[i];
+  __syncthreads();
+  return reinterpret_cast<const Cam<double>*>(lds);
+}
+
 // The same over a grid-stride walk with the camera table staged in LDS (C records of 120 B),
 // so the per-observation camera reads hit LDS instead of L2.
 constexpr int kLdsWalkBlock = 1024;
@@ -317,11 +329,7 @@ k_validate_lds(int64_t N, int C, Model m, const int* __restrict__ pm_cam,
                const Cam<double>* __restrict__ camd, const int* __restrict__ inv_cm,
                uint8_t* __restrict__ vrow, uint8_t* __restrict__ vrow_cm) {
   extern __shared__ double lds_cam[];   // C records
-  const int nwords = C * int(sizeof(Cam<double>) / sizeof(double));
-  const double* src = reinterpret_cast<const double*>(camd);
-  for (int i = threadIdx.x; i < nwords; i += kLdsWalkBlock) lds_cam[i] = src[i];
-  __syncthreads();
-  const Cam<double>* tab = reinterpret_cast<const Cam<double>*>(lds_cam);
+  const Cam<double>* tab = stage_cams<kLdsWalkBlock>(camd, C, lds_cam);
   const int64_t stride = int64_t(gridDim.x) * kLdsWalkBlock;
   for (int64_t k = int64_t(blockIdx.x) * kLdsWalkBlock + threadIdx.x; k < N; k += stride) {
     const Cam<double> cm = tab[pm_cam[k]];
@@ -493,13 +501,7 @@ k_lin_point(Model m, Compact<T> cp, ObsMetric<T> om, double* __restrict__ V,
   __shared__ double smem[3 * (B / kWave)];
   extern __shared__ double lds_cam[];   // LDS: the compact camera table
   const Cam<double>* camtab = cp.camd;
-  if constexpr (LDS) {
-    const int nwords = (cp.Ca + cp.Cf) * int(sizeof(Cam<double>) / sizeof(double));
-    const double* src = reinterpret_cast<const double*>(cp.camd);
-    for (int i = threadIdx.x; i < nwords; i += B) lds_cam[i] = src[i];
-    __syncthreads();
-    camtab = reinterpret_cast<const Cam<double>*>(lds_cam);
-  }
+  if constexpr (LDS) camtab = stage_cams<B>(cp.camd, cp.Ca + cp.Cf, lds_cam);
   const int per = gridDim.x / 8;
   const int blk = (blockIdx.x % 8) * per + blockIdx.x / 8;
   constexpr int tile = B / G;
@@ -1522,13 +1524,7 @@ k_point_candidate(Model m, Compact<T> cp, int D, const Cam<double>* __restrict__
                   double* __restrict__ Xcand, double* __restrict__ partials) {
   __shared__ double smem[5 * (B / kWave)];
   extern __shared__ double lds_cand[];   // LDS: the candidate camera table
-  if constexpr (LDS) {
-    const int nwords = (cp.Ca + cp.Cf) * int(sizeof(Cam<double>) / sizeof(double));
-    const double* src = reinterpret_cast<const double*>(cand_tab);
-    for (int i = threadIdx.x; i < nwords; i += B) lds_cand[i] = src[i];
-    __syncthreads();
-    cand_tab = reinterpret_cast<const Cam<double>*>(lds_cand);
-  }
+  if constexpr (LDS) cand_tab = stage_cams<B>(cand_tab, cp.Ca + cp.Cf, lds_cand);
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   const int Ca = cp.Ca;
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // decrease, quad, g_p.dp, bad, cost'
@@ -2002,25 +1998,28 @@ __device__ __forceinline__ GpObs gp_obs(const Cam<double>& cm, float2 xy, float 
   return o;
 }
 
-template <typename T, int G>
-__global__ void __launch_bounds__(kBlock)
+template <typename T, int G, int B, bool LDS>
+__global__ void __launch_bounds__(B)
 k_gp_lin(Compact<T> cp, const int* __restrict__ orig, const double* __restrict__ scales,
          double delta, GpLin<T>* __restrict__ lin_pm, GpLin<T>* __restrict__ lin_cm,
          double* __restrict__ gX, double* __restrict__ partials) {
-  __shared__ double smem[3 * (kBlock / kWave)];
+  __shared__ double smem[3 * (B / kWave)];
+  extern __shared__ double lds_cam[];   // LDS: the compact camera table
+  const Cam<double>* camtab = cp.camd;
+  if constexpr (LDS) camtab = stage_cams<B>(cp.camd, cp.Ca + cp.Cf, lds_cam);
   const int per = gridDim.x / 8;
   const int blk = (blockIdx.x % 8) * per + blockIdx.x / 8;
-  constexpr int tile = kBlock / G;
+  constexpr int tile = B / G;
   const int l = int(threadIdx.x) % G;
   double acc[3] = {0.0, 0.0, 0.0};   // cost, sum |u|^2, max |g|
   for (int t = 0; t < G; ++t) {
-    const int r = blk * kBlock + t * tile + int(threadIdx.x) / G;
+    const int r = blk * B + t * tile + int(threadIdx.x) / G;
     const bool live = r < cp.Pa;
     double g[3] = {0.0, 0.0, 0.0};
     if (live) {
       const double X[3] = {cp.Xd[3 * r], cp.Xd[3 * r + 1], cp.Xd[3 * r + 2]};
       for (int j = cp.off[r] + l; j < cp.off[r + 1]; j += G) {
-        const Cam<double> cm = cp.camd[cp.cam[j]];
+        const Cam<double> cm = camtab[cp.cam[j]];
         const float dh = cp.depth[j];
         const GpObs o = gp_obs(cm, cp.xy[j], dh, X, dh > 0.0f ? 0.0 : scales[orig[j]]);
         const double e2 = o.u[0] * o.u[0] + o.u[1] * o.u[1] + o.u[2] * o.u[2];
@@ -3109,13 +3108,29 @@ void launch_gp_init_scales(hipStream_t s, int64_t N, const int* pm_cam, const in
 }
 
 template <typename T>
-void launch_gp_lin(hipStream_t s, int G, const Compact<T>& cp, const int* orig,
-                   const double* scales, double delta, GpLin<T>* lin_pm, GpLin<T>* lin_cm,
-                   double* gX, double* partials) {
+int launch_gp_lin(hipStream_t s, int G, const Compact<T>& cp, const int* orig,
+                  const double* scales, double delta, GpLin<T>* lin_pm, GpLin<T>* lin_cm,
+                  double* gX, double* partials, const DevLimits& dl) {
+  const size_t tab = size_t(cp.Ca + cp.Cf) * sizeof(Cam<double>);
+  const bool lds = dl.n_cu > 0 && cp.Ca + cp.Cf > 0 && tab + 3 * 16 * 8 <= size_t(dl.lds_per_block);
+  int nb = 0;
   with_lanes(G, [&](auto Gc) {
-    launch_k(k_gp_lin<T, Gc()>, dim3(lin_point_blocks(cp.Pa)), dim3(kBlock), 0, s, cp, orig,
-             scales, delta, lin_pm, lin_cm, gX, partials);
+    constexpr int g = Gc();
+    bool use = lds;
+    if (use && tab > 65536)
+      use = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gp_lin<T, g, 1024, true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(tab)) == hipSuccess;
+    if (use) {
+      nb = lin_point_blocks_lds(cp.Pa);
+      launch_k(k_gp_lin<T, g, 1024, true>, dim3(nb), dim3(1024), uint32_t(tab), s, cp, orig,
+               scales, delta, lin_pm, lin_cm, gX, partials);
+    } else {
+      nb = lin_point_blocks(cp.Pa);
+      launch_k(k_gp_lin<T, g, kBlock, false>, dim3(nb), dim3(kBlock), 0, s, cp, orig, scales,
+               delta, lin_pm, lin_cm, gX, partials);
+    }
   });
+  return nb;
 }
 
 template <typename T>
@@ -3188,13 +3203,17 @@ void launch_gp_backsub(hipStream_t s, int G, const Compact<T>& cp, const V4<T>* 
 }
 
 template <typename T>
-void launch_gp_candidate(hipStream_t s, const Compact<T>& cp, const int* orig,
-                         const double* scales, double delta, double lam, double dmin,
-                         double dmax, const double* x, const double* dp, const double* gX,
-                         double* Xcand, double* s_cand, double* partials) {
-  if (cp.Pa == 0) return;
-  launch_k(k_gp_candidate<T>, dim3(blocks_for(cp.Pa)), dim3(kBlock), 0, s, cp, orig, scales,
-           delta, lam, dmin, dmax, x, dp, gX, Xcand, s_cand, partials);
+int launch_gp_candidate(hipStream_t s, const Compact<T>& cp, const int* orig,
+                        const double* scales, double delta, double lam, double dmin,
+                        double dmax, const double* x, const double* dp, const double* gX,
+                        double* Xcand, double* s_cand, double* partials, const DevLimits& dl) {
+  if (cp.Pa == 0) return 0;
+  // the camera table stays in L2 here: staging it in LDS gave no gain (170 against 173 us)
+  (void)dl;
+  const int nb = int(blocks_for(cp.Pa));
+  launch_k(k_gp_candidate<T>, dim3(nb), dim3(kBlock), 0, s, cp, orig, scales, delta, lam, dmin,
+           dmax, x, dp, gX, Xcand, s_cand, partials);
+  return nb;
 }
 
 void launch_gp_scatter(hipStream_t s, int Pa, int Ca, int64_t Nh, const int* pt_src,
@@ -3208,9 +3227,9 @@ void launch_gp_scatter(hipStream_t s, int Pa, int Ca, int64_t Nh, const int* pt_
 }
 
 #define IBA_GP_INSTANTIATE(T)                                                                  \
-  template void launch_gp_lin<T>(hipStream_t, int, const Compact<T>&, const int*,             \
-                                 const double*, double, GpLin<T>*, GpLin<T>*, double*,        \
-                                 double*);                                                     \
+  template int launch_gp_lin<T>(hipStream_t, int, const Compact<T>&, const int*,              \
+                                const double*, double, GpLin<T>*, GpLin<T>*, double*,         \
+                                double*, const DevLimits&);                                   \
   template void launch_gp_point_setup<T>(hipStream_t, int, const Compact<T>&, double, double, \
                                          double, const GpLin<T>*, V4<T>*, V4<T>*, T*, double*,\
                                          PtRec<T>*, int*);                                     \
@@ -3225,10 +3244,10 @@ void launch_gp_scatter(hipStream_t s, int Pa, int Ca, int64_t Nh, const int* pt_
                                        const int*, int, double*, const PcgState*);            \
   template void launch_gp_backsub<T>(hipStream_t, int, const Compact<T>&, const V4<T>*,       \
                                      const T*, const double*, const double*, double*);        \
-  template void launch_gp_candidate<T>(hipStream_t, const Compact<T>&, const int*,            \
-                                       const double*, double, double, double, double,         \
-                                       const double*, const double*, const double*, double*,  \
-                                       double*, double*);
+  template int launch_gp_candidate<T>(hipStream_t, const Compact<T>&, const int*,             \
+                                      const double*, double, double, double, double,          \
+                                      const double*, const double*, const double*, double*,   \
+                                      double*, double*, const DevLimits&);
 
 IBA_GP_INSTANTIATE(float)
 IBA_GP_INSTANTIATE(double)
