@@ -10,7 +10,9 @@ observations), in the launch configuration bench.py times (PCG eta = 1e-6, 100 i
 * with focal-length refinement (7-parameter cameras, focal lengths off by up to 2 %): active
   sets bit-exact, 7 x 7 camera blocks of 6 sampled cameras and point blocks of 300 sampled
   points against the oracle's linearisation of just those observations (1e-9), and mixed
-  following float64 over 3 LM steps (costs 1e-5 relative, RMS 1e-4 px, focal lengths 1e-4).
+  following float64 over 3 LM steps (costs 1e-5 relative, RMS 1e-4 px, focal lengths 1e-4);
+* solved for 200 LM iterations in both precisions: final RMS equal within 1e-3 px and final
+  costs within 1e-4 relative.
 """
 from dataclasses import replace
 
@@ -192,3 +194,23 @@ def test_many_cameras_point_pass_from_l2():
           f"(points); PCG {ri['pcg_iters']} / {re['pcg_iters']}")
     assert rel_err(ci, ce) < 1e-6 and rel_err(pi, pe) < 1e-6
     assert ri["accepted"] == re["accepted"]
+
+
+def test_large_solve_final_rms_mixed_equals_fp64():
+    """Both precisions solve the 1000-camera workload (benchmark PCG settings, 200 LM
+    iterations, by which the RMS has levelled off): final RMS reprojection errors equal within
+    1e-3 px, final costs within 1e-4 relative, both well below the starting RMS."""
+    sc, _, _, _ = large()
+    reps = {}
+    for prec in ("mixed", "fp64"):
+        ba = gpu_setup(sc, prec, max_lm_iters=200, **BENCH)
+        reps[prec] = ba.solve()
+        ba.close()
+    m, f = reps["mixed"], reps["fp64"]
+    print(f"final rms mixed {m['final_rms_px']:.7f} px, fp64 {f['final_rms_px']:.7f} px "
+          f"(from {f['initial_rms_px']:.4f}); costs {m['final_cost']:.6e} / {f['final_cost']:.6e}; "
+          f"iterations {m['iterations']}/{f['iterations']}, PCG {m['total_pcg_iters']}/"
+          f"{f['total_pcg_iters']}")
+    assert abs(m["final_rms_px"] - f["final_rms_px"]) <= 1e-3
+    assert abs(m["final_cost"] - f["final_cost"]) <= 1e-4 * f["final_cost"]
+    assert f["final_rms_px"] < f["initial_rms_px"] - 0.3
