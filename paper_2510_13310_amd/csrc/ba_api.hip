@@ -448,7 +448,8 @@ void alloc_obs_buffers(ba_ctx& c) {
   c.part = A.alloc<double>((nd + 1) * (size_t(C) + kCamChunks));   // camera-pass partials
   c.item_off = A.alloc<int>(size_t(C) + 1);
   c.item_cam = A.alloc<int>(size_t(C) + kCamChunks);
-  c.partials = A.alloc<double>(5 * (size_t(P) / kBlock + 16));
+  // 5 sums per workgroup; the global-positioning candidate runs up to 16 lanes per point
+  c.partials = A.alloc<double>(5 * (size_t(P) * 16 / kBlock + 16));
   c.scal = A.alloc<double>(16);
   c.pcg = A.alloc<PcgState>(1);
   c.grad_cams_d = nullptr;
@@ -1179,8 +1180,9 @@ ba_status gp_step_impl(ba_ctx& c, ba_step_report* rep) {
   c.timed("gp_candidate", double(c.Nh) * (4 + 8 + 4 + 4 + 8 + 8) + double(c.Pa) * (4 + 24 * 4) +
                               double(c.C) * 240,
           -1, [&] {
-            nb = launch_gp_candidate<T>(s, cp, c.orig_hat, c.gp_s, delta, lam, dmin, dmax, c.x,
-                                        c.dp, c.gp, c.Xcand, c.gp_scand, c.partials, c.dl);
+            nb = launch_gp_candidate<T>(s, lanes_per_point(c), cp, c.orig_hat, c.gp_s, delta,
+                                        lam, dmin, dmax, c.x, c.dp, c.gp, c.Xcand, c.gp_scand,
+                                        c.partials, c.dl);
           });
   // scal[4..] = decrease, quad, g_X.dX + g_s.ds, bad, cost', g_c.dc, max |g_c|
   launch_reduce_partials(s, nb, 5, c.partials, 0x0u, 3 * c.Ca, c.gc, c.x, c.scal + 4);

@@ -448,9 +448,10 @@ void launch_gp_backsub(hipStream_t s, int G, const Compact<T>& cp, const V4<T>* 
                        const T* Vinv, const double* hp, const double* x, double* dp);
 // Candidate (float64, recomputed from the compact data): centres c + dc, points X + dX, free
 // scales s + ds with ds = (-g_s + w s d.(dc - dX)) / h*; per block {actual decrease, sum w
-// |J delta|^2, g_X.dX + g_s ds, scales <= 0, candidate cost} (5 per block of kBlock points).
+// |J delta|^2, g_X.dX + g_s ds, scales <= 0, candidate cost} (5 per workgroup of kBlock
+// threads, G lanes per point). Returns the number of workgroups.
 template <typename T>
-int launch_gp_candidate(hipStream_t s, const Compact<T>& cp, const int* orig,
+int launch_gp_candidate(hipStream_t s, int G, const Compact<T>& cp, const int* orig,
                         const double* scales, double delta, double lam, double dmin,
                         double dmax, const double* x, const double* dp, const double* gX,
                         double* Xcand, double* s_cand, double* partials,

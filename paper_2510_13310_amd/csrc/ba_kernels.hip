@@ -2512,7 +2512,9 @@ k_gp_backsub(Compact<T> cp, const V4<T>* __restrict__ a_pm, const T* __restrict_
   dp[3 * r + 2] = hp[3 * r + 2] + vi[2] * y[0] + vi[4] * y[1] + vi[5] * y[2];
 }
 
-template <typename T>
+// G lanes per point, each taking every G-th observation of the point's segment; the five
+// sums are over observations, so the lanes need no combine step before the block sums.
+template <typename T, int G>
 __global__ void __launch_bounds__(kBlock)
 k_gp_candidate(Compact<T> cp, const int* __restrict__ orig, const double* __restrict__ scales,
                double delta, double lam, double dmin, double dmax, const double* __restrict__ x,
@@ -2520,18 +2522,21 @@ k_gp_candidate(Compact<T> cp, const int* __restrict__ orig, const double* __rest
                double* __restrict__ Xcand, double* __restrict__ s_cand,
                double* __restrict__ partials) {
   __shared__ double smem[5 * (kBlock / kWave)];
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = t / G, l = t % G;
   const int Ca = cp.Ca;
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // decrease, quad, g.delta, bad, cost'
   if (r < cp.Pa) {
     const double X[3] = {cp.Xd[3 * r], cp.Xd[3 * r + 1], cp.Xd[3 * r + 2]};
     const double dX[3] = {dp[3 * r], dp[3 * r + 1], dp[3 * r + 2]};
     const double Xn[3] = {X[0] + dX[0], X[1] + dX[1], X[2] + dX[2]};
-    Xcand[3 * r] = Xn[0];
-    Xcand[3 * r + 1] = Xn[1];
-    Xcand[3 * r + 2] = Xn[2];
-    acc[2] = gX[3 * r] * dX[0] + gX[3 * r + 1] * dX[1] + gX[3 * r + 2] * dX[2];
-    for (int j = cp.off[r]; j < cp.off[r + 1]; ++j) {
+    if (l == 0) {
+      Xcand[3 * r] = Xn[0];
+      Xcand[3 * r + 1] = Xn[1];
+      Xcand[3 * r + 2] = Xn[2];
+      acc[2] += gX[3 * r] * dX[0] + gX[3 * r + 1] * dX[1] + gX[3 * r + 2] * dX[2];
+    }
+    for (int j = cp.off[r] + l; j < cp.off[r + 1]; j += G) {
       const int s = cp.cam[j];
       const Cam<double> cm = cp.camd[s];
       const float dh = cp.depth[j];
@@ -3203,16 +3208,19 @@ void launch_gp_backsub(hipStream_t s, int G, const Compact<T>& cp, const V4<T>* 
 }
 
 template <typename T>
-int launch_gp_candidate(hipStream_t s, const Compact<T>& cp, const int* orig,
+int launch_gp_candidate(hipStream_t s, int G, const Compact<T>& cp, const int* orig,
                         const double* scales, double delta, double lam, double dmin,
                         double dmax, const double* x, const double* dp, const double* gX,
                         double* Xcand, double* s_cand, double* partials, const DevLimits& dl) {
   if (cp.Pa == 0) return 0;
   // the camera table stays in L2 here: staging it in LDS gave no gain (170 against 173 us)
   (void)dl;
-  const int nb = int(blocks_for(cp.Pa));
-  launch_k(k_gp_candidate<T>, dim3(nb), dim3(kBlock), 0, s, cp, orig, scales, delta, lam, dmin,
-           dmax, x, dp, gX, Xcand, s_cand, partials);
+  int nb = 0;
+  with_lanes(G, [&](auto Gc) {
+    nb = int(blocks_for(int64_t(cp.Pa) * Gc()));
+    launch_k(k_gp_candidate<T, Gc()>, dim3(nb), dim3(kBlock), 0, s, cp, orig, scales, delta,
+             lam, dmin, dmax, x, dp, gX, Xcand, s_cand, partials);
+  });
   return nb;
 }
 
@@ -3244,7 +3252,7 @@ void launch_gp_scatter(hipStream_t s, int Pa, int Ca, int64_t Nh, const int* pt_
                                        const int*, int, double*, const PcgState*);            \
   template void launch_gp_backsub<T>(hipStream_t, int, const Compact<T>&, const V4<T>*,       \
                                      const T*, const double*, const double*, double*);        \
-  template int launch_gp_candidate<T>(hipStream_t, const Compact<T>&, const int*,             \
+  template int launch_gp_candidate<T>(hipStream_t, int, const Compact<T>&, const int*,        \
                                       const double*, double, double, double, double,          \
                                       const double*, const double*, const double*, double*,   \
                                       double*, double*, const DevLimits&);
