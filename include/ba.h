@@ -149,13 +149,13 @@ typedef struct ba_kernel_stat {
 void ba_default_options(ba_options* opt);
 
 /* Create a context on the current HIP device holding the parameters. opt may be NULL
- * (defaults). n_cams >= 1, n_points >= 1. Returns BA_ERR_DEVICE when no GPU is usable. */
+ * (defaults). 1 <= n_cams, n_points < 2^31 - 1. Returns BA_ERR_DEVICE when no GPU is usable. */
 ba_status ba_create(const ba_options* opt, int32_t n_cams, int32_t n_points,
                     const double* cams, const double* intr, const double* points,
                     ba_ctx** out);
 
 /* Set the observation list: observation k sees point pt_idx[k] in camera cam_idx[k] at pixel
- * (xy[2k], xy[2k+1]) (float32). 0 <= n_obs < 2^31. Indices are range-checked (BA_ERR_ARG).
+ * (xy[2k], xy[2k+1]) (float32). 0 <= n_obs < 2^31 - 1. Indices are range-checked (BA_ERR_ARG).
  * Resets the LM state (lambda), clears depth priors and invalidates the linearisation. The
  * library sorts the observations point-major and renumbers points internally; every output
  * is reported in the caller's order. */

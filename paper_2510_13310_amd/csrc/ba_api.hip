@@ -1361,8 +1361,10 @@ ba_status ba_create(const ba_options* opt, int32_t n_cams, int32_t n_points, con
     o = *opt;
   else
     ba_default_options(&o);
-  if (n_cams < 1 || n_points < 1 || !cams || !intr || !points) {
-    g_create_error = "need n_cams >= 1, n_points >= 1 and non-NULL cams, intr, points";
+  if (n_cams < 1 || n_points < 1 || n_cams == INT32_MAX || n_points == INT32_MAX || !cams ||
+      !intr || !points) {
+    g_create_error =
+        "need 1 <= n_cams, n_points < 2^31 - 1 and non-NULL cams, intr, points";
     return BA_ERR_ARG;
   }
   if ((o.precision != BA_PRECISION_FP64 && o.precision != BA_PRECISION_MIXED) ||
@@ -1453,8 +1455,8 @@ ba_status ba_create(const ba_options* opt, int32_t n_cams, int32_t n_points, con
 ba_status ba_set_observations(ba_ctx* c, int64_t n_obs, const int32_t* cam_idx,
                               const int32_t* pt_idx, const float* xy) {
   return guarded(c, [&]() -> ba_status {
-    if (n_obs < 0 || n_obs >= (int64_t(1) << 31))
-      return fail(c, BA_ERR_ARG, "n_obs must be in [0, 2^31)");
+    if (n_obs < 0 || n_obs >= (int64_t(1) << 31) - 1)   // scans hold n_obs + 1 entries
+      return fail(c, BA_ERR_ARG, "n_obs must be in [0, 2^31 - 1)");
     if (n_obs > 0 && (!cam_idx || !pt_idx || !xy))
       return fail(c, BA_ERR_ARG, "NULL observation array");
     std::vector<int32_t> hc, hp;

@@ -265,6 +265,14 @@ def test_abi_errors_on_device():
     with pytest.raises(BAError) as e:
         ba.set_fixed_cameras(np.array([-1], np.int32))
     assert e.value.status == -1
+    # sizes beyond what the scans index are refused before any array is read
+    import ctypes
+    from paper_2510_13310_amd import _abi
+    lib = _abi.load()
+    assert lib.ba_set_observations(ba.ctx, ctypes.c_int64(2**31 - 1), None, None, None) == -1
+    assert lib.ba_set_observations(ba.ctx, ctypes.c_int64(-1), None, None, None) == -1
+    out = ctypes.c_void_p()
+    assert lib.ba_create(None, 2**31 - 1, 10, None, None, None, ctypes.byref(out)) == -1
     ba.set_observations(sc.cam_idx, sc.pt_idx, sc.xy)
     with pytest.raises(BAError) as e:
         ba.adjoint(np.zeros((sc.n_cams, 7)), np.zeros((sc.n_points, 3)))
