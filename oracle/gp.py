@@ -36,7 +36,7 @@ import scipy.sparse as sp
 from .geometry import quat_to_rot
 from .model import Problem, huber
 from .extract import activity_fixpoint, ranks
-from .lm import schur_solve
+from .lm import schur_solve, nielsen_update
 
 
 @dataclass
@@ -271,15 +271,10 @@ def gp_step(prob: Problem, q, st: GpState, opts: GpOptions):
     rep.gain_ratio = ratio
     rep.extra["actual_decrease"] = dF
     rep.accepted = bool(np.isfinite(F2) and dF > 0 and ratio > opts.accept_ratio)
-    if rep.accepted:
-        cand.lam = max(opts.lambda_min,
-                       min(opts.lambda_max, st.lam * max(1.0 / 3, 1 - (2 * ratio - 1) ** 3)))
-        cand.nu = 2.0
-        return cand, rep
-    new = st.copy()
-    new.lam = min(st.lam * st.nu, opts.lambda_max)
-    new.nu = st.nu * 2
-    return new, rep
+    out = cand if rep.accepted else st.copy()
+    out.lam, out.nu = nielsen_update(st.lam, st.nu, rep.accepted, ratio, opts.lambda_min,
+                                     opts.lambda_max)
+    return out, rep
 
 
 def gp_solve(prob: Problem, q, st: GpState, opts: GpOptions, max_iters: int | None = None):

@@ -199,21 +199,43 @@ def _point_block_inverse(Hpp: sp.spmatrix) -> sp.csr_matrix:
     return sp.csr_matrix((inv.ravel(), (ri.ravel(), ci.ravel())), shape=(3 * n, 3 * n))
 
 
+def reduced_camera_system(H: sp.spmatrix, rhs: np.ndarray, nc: int):
+    """The camera Schur complement of Eq. (3)'s system after eliminating the 3x3 point blocks:
+    ``S = U - W V^-1 W^T`` as a dense matrix and ``b = rhs_c - W V^-1 rhs_p``. Returns
+    ``(S, b, Vinv, W)``."""
+    H = H.tocsr()
+    Vinv = _point_block_inverse(H[nc:, nc:])
+    U = H[:nc, :nc]
+    W = H[:nc, nc:]
+    S = (U - W @ Vinv @ W.T).toarray()
+    b = rhs[:nc] - W @ (Vinv @ rhs[nc:])
+    return S, b, Vinv, W
+
+
 def schur_solve(H: sp.spmatrix, rhs: np.ndarray, nc: int) -> np.ndarray:
     """Solve H x = rhs by eliminating the 3x3 point blocks: a dense Schur complement on the
     camera columns, Cholesky, and back-substitution. Raises LinAlgError if S is not SPD."""
     H = H.tocsr()
-    Vinv = _point_block_inverse(H[nc:, nc:])
     rp = rhs[nc:]
     if nc == 0:
-        return Vinv @ rp
-    U = H[:nc, :nc]
-    W = H[:nc, nc:]
-    S = (U - W @ Vinv @ W.T).toarray()
-    b = rhs[:nc] - W @ (Vinv @ rp)
+        return _point_block_inverse(H) @ rp
+    S, b, Vinv, W = reduced_camera_system(H, rhs, nc)
     xc = sla.cho_solve(sla.cho_factor(S, lower=True), b)
     xp = Vinv @ (rp - W.T @ xc)
     return np.concatenate([xc, xp])
+
+
+def nielsen_update(lam: float, nu: float, accepted: bool, ratio: float, lambda_min: float,
+                   lambda_max: float):
+    """Damping schedule of Nielsen (1999), as given by Madsen, Nielsen and Tingleff (2004):
+    after an accepted step with gain ratio ``ratio`` the damping is scaled by
+    ``max(1/3, 1 - (2 ratio - 1)^3)`` and ``nu`` resets to 2; after a rejection it is scaled
+    by ``nu`` and ``nu`` doubles. The damping is clamped to ``[lambda_min, lambda_max]``.
+    Returns ``(lam, nu)``."""
+    if accepted:
+        f = max(1.0 / 3.0, 1.0 - (2.0 * ratio - 1.0) ** 3)
+        return max(lambda_min, min(lambda_max, lam * f)), 2.0
+    return min(lam * nu, lambda_max), nu * 2.0
 
 
 def damped(H: sp.spmatrix, lam: float, opts: Options) -> sp.csr_matrix:
@@ -274,8 +296,8 @@ def lm_step(prob: Problem, st: State, opts: Options):
         delta = schur_solve(damped(H, st.lam, opts), -g, lin.ncol_cam)
     except np.linalg.LinAlgError:
         rep.status = "singular"
-        new.lam = min(st.lam * st.nu, opts.lambda_max)
-        new.nu = st.nu * 2
+        new.lam, new.nu = nielsen_update(st.lam, st.nu, False, 0.0, opts.lambda_min,
+                                         opts.lambda_max)
         return new, rep
     rep.delta = delta
     Jd = (lin.J @ delta).reshape(lin.e.shape)
@@ -297,14 +319,10 @@ def lm_step(prob: Problem, st: State, opts: Options):
     rep.gain_ratio = ratio
     rep.extra["actual_decrease"] = dF
     rep.accepted = bool(np.isfinite(F2) and dF > 0 and ratio > opts.accept_ratio)
-    if rep.accepted:
-        cand.lam = max(opts.lambda_min,
-                       min(opts.lambda_max, st.lam * max(1.0 / 3, 1 - (2 * ratio - 1) ** 3)))
-        cand.nu = 2.0
-        return cand, rep
-    new.lam = min(st.lam * st.nu, opts.lambda_max)
-    new.nu = st.nu * 2
-    return new, rep
+    out = cand if rep.accepted else new
+    out.lam, out.nu = nielsen_update(st.lam, st.nu, rep.accepted, ratio, opts.lambda_min,
+                                     opts.lambda_max)
+    return out, rep
 
 
 def solve(prob: Problem, st: State, opts: Options, max_iters: int | None = None):

@@ -13,15 +13,19 @@
 * without any pinned prior the same start converges to a similarity of the truth at about
   the starting scale, so the metric information comes from the pinned rows.
 """
+from dataclasses import replace
+
 import numpy as np
 import pytest
 
 from oracle.geometry import quat_to_rot
 from oracle.gp import (GpOptions, GpState, gp_damped, gp_extract, gp_linearize,
-                       gp_normal_equations, gp_residuals, gp_solve, gp_solve_system, rays)
-from oracle.model import Problem
+                       gp_normal_equations, gp_residuals, gp_solve, gp_solve_system, gp_step,
+                       rays)
+from oracle.model import Problem, huber
 from scenes import make_scene
 from tests._align import aligned_error
+from tests._constructed import gp_behind_scene
 from tests.test_oracle_extract import _brute_force_greatest_closed_set, _random_incidence
 
 
@@ -161,3 +165,90 @@ def test_without_priors_scale_stays_free():
     err_sim, (s, R, t) = aligned_error(est, st.X, sc.cams_gt, sc.points_gt)
     assert err_sim < 1e-6
     assert abs(s - 1.0 / 1.5) < 0.05, s
+
+
+# ---------------------------------------------------------------- Huber-weighted system
+def _huber_system(huber_t):
+    sc = replace(make_scene("tiny", prior_frac=0.5, use_depth=True, lambda_d=1.0, n_points=150),
+                 fixed=np.array([0], np.int32))
+    prob = Problem.from_scene(sc)
+    q = sc.cams_gt[:, :4]
+    opts = GpOptions(huber=huber_t)
+    st = GpState.initial(prob, q, sc.cams0, sc.points0, opts)
+    ex = gp_extract(prob)
+    lin = gp_linearize(prob, q, st, ex, huber_t)
+    return prob, q, opts, st, ex, lin
+
+
+def _gp_cost(prob, q, st, obs, huber_t):
+    u, _ = gp_residuals(prob, q, st, obs)
+    return 0.5 * float(np.sum(huber(np.sum(u * u, axis=1), huber_t)[0]))
+
+
+def test_huber_gradient_is_derivative_of_cost():
+    """g = J^T W u is the gradient of F = 1/2 sum rho(|u|^2) (Eq. (1) with Huber): central
+    differences of the cost over camera centres, points and free scales, with residuals on
+    both sides of the threshold (a missing, squared or misplaced weight fails here)."""
+    ht = 0.012
+    prob, q, opts, st, ex, lin = _huber_system(ht)
+    assert (lin.w < 1).sum() > 50 and (lin.w == 1).sum() > 50   # both Huber regimes
+    H, g = gp_normal_equations(lin)
+    nc, npt = 3 * ex.cams.size, 3 * ex.pts.size
+    h = 1e-6
+    coords = ([("c", i, k) for i in ex.cams for k in range(3)] +
+              [("X", j, k) for j in ex.pts[::7] for k in range(3)] +
+              [("s", o, None) for o in ex.free[::13]])
+    for arr, idx, k in coords:
+        sp_, sm = st.copy(), st.copy()
+        if arr == "s":
+            sp_.s[idx] += h
+            sm.s[idx] -= h
+            col = nc + npt + ex.free_rank[idx]
+        else:
+            getattr(sp_, arr)[idx, k] += h
+            getattr(sm, arr)[idx, k] -= h
+            col = 3 * ex.cam_rank[idx] + k if arr == "c" else nc + 3 * ex.pt_rank[idx] + k
+        fd = (_gp_cost(prob, q, sp_, ex.obs, ht) - _gp_cost(prob, q, sm, ex.obs, ht)) / (2 * h)
+        assert abs(g[col] - fd) <= 1e-6 * abs(fd) + 1e-8 * np.abs(g).max(), (arr, idx, k)
+
+
+def test_irls_step_is_weighted_least_squares():
+    """The undamped IRLS step solves min_d sum_k w_k |u_k + J_k d|^2: the normal equations
+    H = J^T W J, g = J^T W u must give the same step as a QR least-squares solve of the
+    sqrt(w)-scaled Jacobian (camera 0 fixed, pinned scales fix the metric scale)."""
+    prob, q, opts, st, ex, lin = _huber_system(0.012)
+    H, g = gp_normal_equations(lin)
+    x = gp_solve_system(gp_damped(H, 0.0, opts), -g, lin.ncol_cam, lin.ncol_pt)
+    sw = np.repeat(np.sqrt(lin.w), 3)
+    A = lin.J.toarray() * sw[:, None]
+    ref, *_ = np.linalg.lstsq(A, -sw * lin.u.ravel(), rcond=None)
+    np.testing.assert_allclose(x, ref, rtol=1e-7, atol=1e-8 * np.abs(ref).max())
+
+
+# ---------------------------------------------------------------- free scale <= 0
+def test_candidate_with_nonpositive_free_scale_rejected():
+    """A point 2 m behind a fixed camera that sees it at its principal point: that free
+    scale's own optimum is -0.5 from a start of 0.5, so the lightly damped candidate takes it
+    below 0 and the step is rejected with an infinite cost; as the damping grows a step is
+    accepted and every free scale stays positive."""
+    sc = gp_behind_scene()
+    prob = Problem.from_scene(sc)
+    q = sc.cams0[:, :4]
+    opts = GpOptions(huber=0.0)
+    st = GpState.initial(prob, q, sc.cams0, sc.points0, opts)
+    k = sc.n_obs - int((sc.pt_idx == sc.n_points - 1).sum())   # camera 0's observation
+    assert sc.cam_idx[k] == 0 and not prob.prior_mask[k]
+    assert st.s[k] == pytest.approx(0.5, rel=0.02)   # the start centre is perturbed by 2 cm
+    decisions = []
+    for _ in range(8):
+        st2, rep = gp_step(prob, q, st, opts)
+        ex = rep.extraction
+        assert ex.obs_active[k]
+        s_cand = st.s[k] + rep.delta[3 * ex.cams.size + 3 * ex.pts.size + ex.free_rank[k]]
+        if s_cand <= 0:
+            assert not rep.accepted and rep.cost_after == np.inf
+            np.testing.assert_array_equal(st2.s, st.s)
+        decisions.append(rep.accepted)
+        st = st2
+    assert decisions[0] is False and any(decisions)
+    assert (st.s > 0).all()

@@ -6,8 +6,9 @@ import pytest
 
 from oracle.model import Problem
 from oracle.lm import (Options, State, lm_step, solve, extract, linearize, normal_equations,
-                       schur_solve, damped)
+                       schur_solve, damped, nielsen_update)
 from scenes import make_scene
+from tests._constructed import near_depth_scene, embedded_near_depth_scene
 from tests._align import aligned_error, rotation_error
 
 
@@ -103,3 +104,90 @@ def test_monotone_cost_and_report_consistency_medium():
             assert st2.lam > rep.lam
             np.testing.assert_array_equal(st2.X, st.X)
         st = st2
+
+
+# ---------------------------------------------------------------- damping schedule
+@pytest.mark.parametrize("ratio,factor", [
+    (0.5, 1.0),              # 1 - 0^3
+    (0.75, 0.875),           # 1 - 0.5^3
+    (0.25, 1.125),           # 1 - (-0.5)^3
+    (0.9, 0.488),            # 1 - 0.8^3
+    (1.0, 1.0 / 3.0),        # 1 - 1 = 0, floored at 1/3
+    (0.95, 1.0 / 3.0),       # 1 - 0.729 = 0.271, floored at 1/3
+    (0.001, 1.994011992),    # 1 - (-0.998)^3
+])
+def test_nielsen_factor_after_acceptance(ratio, factor):
+    """Madsen, Nielsen and Tingleff (2004), Eq. (2.21): the damping after an accepted step is
+    scaled by max(1/3, 1 - (2 rho - 1)^3) and nu resets to 2. The factors are worked out by
+    hand for the listed gain ratios."""
+    lam, nu = nielsen_update(1e-2, 16.0, True, ratio, 1e-12, 1e12)
+    assert lam == pytest.approx(1e-2 * factor, rel=1e-12)
+    assert nu == 2.0
+
+
+def test_nielsen_rejections_and_clamps():
+    """After a rejection the damping is multiplied by nu and nu doubles: from (1e-3, 2),
+    three rejections give 2e-3, 8e-3 and 6.4e-2; the damping stays within its bounds."""
+    lam, nu, seen = 1e-3, 2.0, []
+    for _ in range(3):
+        lam, nu = nielsen_update(lam, nu, False, -1.0, 1e-12, 1e12)
+        seen.append((lam, nu))
+    assert seen == [(2e-3, 4.0), (8e-3, 8.0), (6.4e-2, 16.0)]
+    assert nielsen_update(1e12, 2.0, False, 0.0, 1e-12, 1e12) == (1e12, 4.0)
+    assert nielsen_update(1e-12, 8.0, True, 1.0, 1e-12, 1e12) == (1e-12, 2.0)
+
+
+# ---------------------------------------------------------------- candidate below min depth
+def test_candidate_below_min_depth_rejected_closed_form():
+    """A point 0.2 m in front of a fixed camera with a 0.05 m depth prior: the damped step on
+    its depth is (z - z^2/d) / (1 + lambda), so the candidate depth 0.2 - 0.6 / (1 + lambda)
+    is at or below the 0.1 m bound (Eq. (10)) for every lambda < 5. Those candidates are
+    rejected with an infinite cost and the damping grows by nu = 2, 4, 8, 16, 32; the sixth
+    step, at lambda = 1e-3 * 2^15, is accepted at the closed-form depth."""
+    sc = near_depth_scene()
+    d = float(np.float32(0.05))
+    opts = Options()
+    prob = Problem.from_scene(sc)
+    st = State.initial(sc.cams0, sc.points0, opts)
+    lams = [1e-3 * 2.0 ** e for e in (0, 1, 3, 6, 10, 15)]
+    for k, lam in enumerate(lams):
+        z = st.X[0, 2]
+        st2, rep = lm_step(prob, st, opts)
+        assert rep.lam == pytest.approx(lam, rel=1e-14)
+        assert rep.n_points == 1 and rep.n_cams == 0 and rep.n_obs == 1
+        assert rep.cost_before == pytest.approx(0.5 * (1.0 / z - 1.0 / d) ** 2, rel=1e-12)
+        dz = (z - z * z / d) / (1.0 + lam)
+        np.testing.assert_allclose(rep.delta, [0.0, 0.0, dz], rtol=1e-10, atol=1e-15)
+        if k < 5:
+            assert 0.2 + dz <= 0.1
+            assert not rep.accepted and rep.cost_after == np.inf
+            np.testing.assert_array_equal(st2.X, st.X)
+        else:
+            assert 0.2 + dz > 0.1
+            assert rep.accepted
+            assert st2.X[0, 2] == pytest.approx(z + dz, rel=1e-12)
+            znew = st2.X[0, 2]
+            assert rep.cost_after == pytest.approx(0.5 * (1.0 / znew - 1.0 / d) ** 2, rel=1e-9)
+        st = st2
+
+
+def test_candidate_below_min_depth_inside_a_scene():
+    """The same point inside the tiny scene (camera 0 fixed, so the point's block is
+    decoupled from the free cameras): the whole step is rejected with an infinite cost while
+    the damping is small, and no parameter moves meanwhile. (The camera's axes are not the
+    world axes here, so the Marquardt diagonal mixes the point's coordinates and the closed
+    form above holds only approximately: the first accepted damping is 1.024.)"""
+    sc = embedded_near_depth_scene()
+    opts = Options()
+    prob = Problem.from_scene(sc)
+    st = State.initial(sc.cams0, sc.points0, opts)
+    decisions = []
+    for _ in range(6):
+        st2, rep = lm_step(prob, st, opts)
+        decisions.append(rep.accepted)
+        if not rep.accepted:
+            assert rep.cost_after == np.inf
+            np.testing.assert_array_equal(st2.X, st.X)
+            np.testing.assert_array_equal(st2.cams(), st.cams())
+        st = st2
+    assert decisions[:5] == [False] * 4 + [True]
