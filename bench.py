@@ -23,6 +23,12 @@ import os
 import sys
 import time
 
+# the oracle's CPU baseline uses every host core the process may run on (set before NumPy
+# loads its BLAS; an environment that already fixes the counts keeps them)
+for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+    os.environ.setdefault(_v, str(len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+                                  else (os.cpu_count() or 1)))
+
 import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -46,6 +52,10 @@ def parse():
     ap.add_argument("--cpu-frac", type=float, default=0.15,
                     help="fraction of points in the oracle's timed sample")
     ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-full-steps", type=int, default=1,
+                    help="oracle LM steps timed on the whole scene, the baseline value (about "
+                         "20 s each for the 1000-camera scene on a 16-thread host); 0: the "
+                         "rescaled sample only")
     ap.add_argument("--check-every", type=int, default=8,
                     help="PCG iterations enqueued between convergence read-backs")
     ap.add_argument("--calib-copy", action="store_true",
@@ -181,8 +191,15 @@ def forward_adjoint(sc, iters, args, torch):
     return out
 
 
+def _mean_ms(reps, keep):
+    v = [r["ms_total"] for r in reps if keep(r)]
+    return round(float(np.mean(v)), 4) if v else None
+
+
 def summarize(res, n_obs_total):
-    """Throughput of one timed region (every step counted, accepted or rejected)."""
+    """Throughput of one timed region (every step counted, accepted or rejected), with the
+    host wall time of the steps split by outcome: a step re-extracts and re-linearises only
+    after an accepted one, so accepted and rejected steps cost different amounts."""
     reps = res["reports"]
     K = len(reps)
     its = K / res["seconds"]
@@ -193,6 +210,10 @@ def summarize(res, n_obs_total):
         pcg_iters_mean=float(np.mean([r["pcg_iters"] for r in reps])),
         accepted=int(sum(r["accepted"] for r in reps)),
         relinearized=int(sum(r["relinearized"] for r in reps)),
+        ms_step_accepted=_mean_ms(reps, lambda r: r["accepted"]),
+        ms_step_rejected=_mean_ms(reps, lambda r: not r["accepted"]),
+        ms_step_relinearized=_mean_ms(reps, lambda r: r["relinearized"]),
+        ms_step_reused=_mean_ms(reps, lambda r: not r["relinearized"]),
         rms_px_first=reps[0]["rms_px"], rms_px_last=reps[-1]["rms_px"],
         cost_last=reps[-1]["cost_before"], device_gb=res["device_bytes"] / 1e9)
 
@@ -207,9 +228,19 @@ def kernel_summary(res):
     lin_launch = max((st[k]["launches"] for k in LINEARIZE_KERNELS if k in st), default=0)
     jac = (nh * lin_launch) / (lin_ms / 1e3) if lin_ms > 0 else None
     kern_ms = sum(s["total_ms"] for s in res["stats"])
+    # one PCG iteration = the two matvec passes (or the explicit product) and the update
+    pcg_names = ("schur_point", "schur_cam", "schur_spmv", "pcg_update", "gp_schur_point",
+                 "gp_schur_cam")
+    pcg_ms = sum(st[k]["total_ms"] for k in pcg_names if k in st)
+    pcg_n = st["pcg_update"]["launches"] if "pcg_update" in st else 0
+    true_res = [r["pcg_true_residual"] for r in reps if r["pcg_true_residual"] >= 0]
     return dict(
         ms_per_step_instrumented=1e3 * res["seconds"] / K, kernel_ms_per_step=kern_ms / K,
         jacobian_obs_per_s=jac,
+        us_per_pcg_iter=round(1e3 * pcg_ms / pcg_n, 3) if pcg_n else None,
+        pcg_true_residual_mean=float(np.mean(true_res)) if true_res else None,
+        pcg_true_residual_max=float(np.max(true_res)) if true_res else None,
+        pcg_recursive_residual_mean=float(np.mean([r["pcg_rel_residual"] for r in reps])),
         kernels={s["name"]: dict(launches=s["launches"], ms=round(s["total_ms"], 4),
                                  avg_us=round(1e3 * s["total_ms"] / s["launches"], 2),
                                  gbs=(round(s["total_bytes"] / (s["total_ms"] * 1e6), 1)
@@ -287,9 +318,9 @@ def cpu_baseline_gp(sc, frac, steps, n_obs_full, huber_gp):
         nobs.append(rep.n_obs)
     dt = time.perf_counter() - t0
     its_sample = steps / dt
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores, model = cpu_info()
     return dict(value=round(its_sample * sub.cam_idx.size / n_obs_full, 5), unit="GP LM iters/s",
-                cores=cores, kind="oracle",
+                cores=cores, kind="oracle", cpu_model=model,
                 sample=(f"{steps} FP64 GP oracle LM steps on {100 * frac:.0f}% of the points "
                         f"({sub.cam_idx.size} of {n_obs_full} observations, all cameras), "
                         f"{dt:.1f} s; rate rescaled by the observation ratio"),
@@ -297,9 +328,41 @@ def cpu_baseline_gp(sc, frac, steps, n_obs_full, huber_gp):
                 obs_per_s=round(its_sample * float(np.mean(nobs)), 1))
 
 
-def cpu_baseline(sc, frac, steps, n_obs_full, refine_focal=False):
-    """The FP64 oracle on a random fraction of the points (all cameras), timed per LM step;
-    the rate is rescaled to the full observation count (per-observation work dominates)."""
+def cpu_info():
+    """Threads the oracle's BLAS and NumPy may use, and the host CPU model."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)), model
+
+
+def cpu_full(sc, steps, refine_focal=False):
+    """The FP64 oracle timed on the whole scene for `steps` LM steps (the first from the
+    scene's start, like the GPU's first timed step after its own warm-up)."""
+    from oracle.lm import Options, State, lm_step
+    from oracle.model import Problem
+    opts = Options(huber_px=sc.huber_px, filter_px=sc.filter_px, refine_focal=refine_focal)
+    prob = Problem.from_scene(sc)
+    st = State.initial(sc.cams0, sc.points0, opts, focal=sc.intr[:, 0])
+    t0 = time.perf_counter()
+    nobs = []
+    for _ in range(steps):
+        st, rep = lm_step(prob, st, opts)
+        nobs.append(rep.n_obs)
+    dt = time.perf_counter() - t0
+    return steps / dt, dt, float(np.mean(nobs))
+
+
+def cpu_baseline(sc, frac, steps, n_obs_full, refine_focal=False, full_steps=1):
+    """The FP64 oracle, untouched: `full_steps` LM steps on the whole scene give the value;
+    the rate of `steps` steps on a random fraction of the points (all cameras), rescaled by the
+    observation ratio, is reported beside it with its error against the full-scene rate (the
+    dense camera Schur complement and its Cholesky do not shrink with the sample)."""
     from dataclasses import replace
     from oracle.lm import Options, State, lm_step
     from oracle.model import Problem
@@ -324,14 +387,26 @@ def cpu_baseline(sc, frac, steps, n_obs_full, refine_focal=False):
         nobs.append(rep.n_obs)
     dt = time.perf_counter() - t0
     its_sample = steps / dt
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return dict(value=round(its_sample * sub.n_obs / n_obs_full, 5), unit="LM iters/s",
-                cores=cores, kind="oracle",
-                sample=(f"{steps} FP64 oracle LM steps on {100 * frac:.0f}% of the points "
-                        f"({sub.n_obs} of {n_obs_full} observations, all cameras), "
-                        f"{dt:.1f} s; rate rescaled by the observation ratio"),
-                sample_iters_per_s=round(its_sample, 4),
-                obs_per_s=round(its_sample * float(np.mean(nobs)), 1))
+    cores, model = cpu_info()
+    scaled = its_sample * sub.n_obs / n_obs_full
+    out = dict(value=round(scaled, 5), unit="LM iters/s", cores=cores, kind="oracle",
+               cpu_model=model,
+               sample=(f"{steps} FP64 oracle LM steps on {100 * frac:.0f}% of the points "
+                       f"({sub.n_obs} of {n_obs_full} observations, all cameras), "
+                       f"{dt:.1f} s; rate rescaled by the observation ratio"),
+               sample_iters_per_s=round(its_sample, 4),
+               obs_per_s=round(its_sample * float(np.mean(nobs)), 1))
+    if full_steps > 0:
+        its_full, dt_full, nobs_full = cpu_full(sc, full_steps, refine_focal)
+        out.update(value=round(its_full, 5),
+                   sample=(f"{full_steps} FP64 oracle LM step(s) on the whole scene "
+                           f"({n_obs_full} observations), {dt_full:.1f} s"),
+                   obs_per_s=round(its_full * nobs_full, 1),
+                   sampled_value=round(scaled, 5),
+                   sampled_desc=(f"{steps} steps on {100 * frac:.0f}% of the points, "
+                                 f"{dt:.1f} s, rescaled by the observation ratio"),
+                   sampling_error=round(scaled / its_full - 1.0, 4))
+    return out
 
 
 def main():
@@ -436,6 +511,10 @@ def main():
     if "fp64" in out and "mixed" in out:
         line["mixed_over_fp64"] = round(out["mixed"][1]["lm_iters_per_s"] /
                                         out["fp64"][1]["lm_iters_per_s"], 3)
+        # the same ratio per PCG iteration (PCG kernels only): the speed of the precision
+        # itself, apart from the two paths stopping their PCG after different counts
+        um, uf = out["mixed"][1]["us_per_pcg_iter"], out["fp64"][1]["us_per_pcg_iter"]
+        line["mixed_over_fp64_per_pcg_iter"] = round(uf / um, 3) if um and uf else None
         line["rms_diff_px"] = abs(out["mixed"][1]["rms_px_last"] - out["fp64"][1]["rms_px_last"])
     if args.forward_adjoint > 0:
         line["forward_adjoint"] = forward_adjoint(sc, args.forward_adjoint, args, torch)
@@ -446,7 +525,7 @@ def main():
                                                args.gp_huber)
     else:
         line["cpu_baseline"] = cpu_baseline(sc, args.cpu_frac, args.cpu_steps, sc.n_obs,
-                                            args.refine_focal)
+                                            args.refine_focal, args.cpu_full_steps)
     print(json.dumps(line), flush=True)
 
 

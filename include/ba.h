@@ -44,6 +44,9 @@ typedef struct ba_ctx ba_ctx;
 typedef int32_t ba_status;
 #define BA_OK 0            /* success */
 #define BA_EMPTY 1         /* no active observation: the step changed nothing */
+#define BA_NOT_CONVERGED 2 /* ba_adjoint: the PCG stopped at adjoint_max_iters above
+                              adjoint_rel_tol; the gradients were written from its last
+                              iterate and ba_last_error() gives the residual reached */
 #define BA_ERR_ARG (-1)    /* invalid argument (size, index out of range, NULL) */
 #define BA_ERR_STATE (-2)  /* call out of order (e.g. lm_step before set_observations) */
 #define BA_ERR_OOM (-3)    /* device allocation failed */
@@ -125,6 +128,10 @@ typedef struct ba_step_report {
                            /* host wall times per phase; without timing the linearisation and
                               setup are not waited for separately, so their device time shows
                               in the next phase that synchronises */
+  double pcg_true_residual;/* |b - S x| / |b| of the PCG solution x, S applied once more by the
+                              solve's own matvec kernels (float32 products in MIXED, float64 in
+                              FP64); computed only with opt.timing = 1 and the implicit solver,
+                              else -1 */
 } ba_step_report;
 
 typedef struct ba_solve_report {
@@ -148,23 +155,35 @@ typedef struct ba_kernel_stat {
 /* Fill *opt with the defaults listed above. */
 void ba_default_options(ba_options* opt);
 
-/* Create a context on the current HIP device holding the parameters. opt may be NULL
- * (defaults). 1 <= n_cams, n_points < 2^31 - 1. Returns BA_ERR_DEVICE when no GPU is usable. */
+/* Create a context on the current HIP device holding the BA parameters of Sec. III-B: the
+ * camera extrinsics {centre, quaternion} and the intrinsics K of every camera, and the 3-D
+ * points. opt may be NULL (defaults). 1 <= n_cams, n_points <= 2^27 - 1 (the kernels index
+ * per-point arrays with 32-bit products of up to 16 P), else BA_ERR_ARG; cams C x 7, intr
+ * C x 3 and points P x 3 (layouts above) are copied in, non-finite values and zero
+ * quaternions are BA_ERR_ARG. Returns BA_ERR_DEVICE when no GPU is usable. *out is NULL on
+ * any error. */
 ba_status ba_create(const ba_options* opt, int32_t n_cams, int32_t n_points,
                     const double* cams, const double* intr, const double* points,
                     ba_ctx** out);
 
-/* Set the observation list: observation k sees point pt_idx[k] in camera cam_idx[k] at pixel
- * (xy[2k], xy[2k+1]) (float32). 0 <= n_obs < 2^31 - 1. Indices are range-checked (BA_ERR_ARG).
- * Resets the LM state (lambda), clears depth priors and invalidates the linearisation. The
- * library sorts the observations point-major and renumbers points internally; every output
- * is reported in the caller's order. */
+/* Set the observation list: observation k is the 2-D keypoint x_ij of Eq. (2), point
+ * pt_idx[k] seen in camera cam_idx[k] at pixel (xy[2k], xy[2k+1]) (float32, row-major N x 2);
+ * its residual is the reprojection error pi(zeta_i, X_j, K_i) - x_ij. 0 <= n_obs <= 2^29 - 1
+ * (per-observation arrays hold up to 3 values indexed with 32-bit products), else BA_ERR_ARG.
+ * Indices are range-checked (BA_ERR_ARG, nothing changed). Resets the LM state (lambda),
+ * clears depth priors and invalidates the linearisation. The library sorts the observations
+ * point-major and renumbers points internally; every output is reported in the caller's
+ * order. */
 ba_status ba_set_observations(ba_ctx* ctx, int64_t n_obs, const int32_t* cam_idx,
                               const int32_t* pt_idx, const float* xy);
 
-/* Metric depth priors d_hat (metres, camera-frame z), one per observation, with optional
- * validity mask (NULL: all valid). Non-finite or <= 0 depths count as invalid (m = 0).
- * lambda_d >= 0 weighs the depth row (px * m); 0 disables the depth rows. */
+/* Metric depth priors d_hat (metres, camera-frame z), one per observation (N float32, the
+ * order of ba_set_observations), with the optional validity mask m of Eq. (9) (N bytes, NULL:
+ * all valid). Each observation then gets the inverse-depth row r^d = 1/z - m/d_hat of
+ * Eq. (6) with the masked reference of Eq. (9), weighted by lambda_d and stacked with the
+ * reprojection row under one robustifier (Eq. (7)). Non-finite or <= 0 depths count as
+ * invalid (m = 0: target 0, a weak far-depth row). lambda_d >= 0 (px * m); 0 disables the
+ * depth rows. BA_ERR_STATE before ba_set_observations; invalidates the linearisation. */
 ba_status ba_set_depth_priors(ba_ctx* ctx, const float* depth, const uint8_t* valid,
                               double lambda_d);
 
@@ -172,14 +191,24 @@ ba_status ba_set_depth_priors(ba_ctx* ctx, const float* depth, const uint8_t* va
  * observations constrain points. n = 0 clears the list. */
 ba_status ba_set_fixed_cameras(ba_ctx* ctx, int32_t n, const int32_t* cam_ids);
 
-/* Exactly one LM iteration (extraction, linearisation, Schur-PCG solve, candidate, accept or
- * reject, scatter). rep may be NULL. Returns BA_EMPTY when nothing is active. */
+/* Exactly one LM iteration (Eq. (3), Sec. IV-B): dynamic parameter extraction at the current
+ * parameters (Eqs. (10)-(15)), linearisation, the damped normal equations reduced to the
+ * camera Schur complement and solved by block-Jacobi PCG, back-substitution of the points,
+ * the candidate's cost over the same observations, acceptance by gain ratio, and the scatter
+ * of an accepted update into the full parameters (inactive ones untouched). After a rejected
+ * step the next call reuses the extraction and linearisation with a larger damping. rep may
+ * be NULL. Returns BA_EMPTY when nothing is active, BA_ERR_STATE before
+ * ba_set_observations, BA_ERR_NUMERIC (parameters unchanged) for a non-finite cost. */
 ba_status ba_lm_step(ba_ctx* ctx, ba_step_report* rep);
 
-/* Iterate ba_lm_step until max_lm_iters, the cost or gradient tolerance, or lambda_max. */
+/* The LM loop of Eq. (3): iterate ba_lm_step until max_lm_iters, the relative cost decrease
+ * of an accepted step falls to cost_rel_tol, max |g| to grad_tol, or a rejection reaches
+ * lambda_max (rep->stop_reason). rep may be NULL. Errors as ba_lm_step. */
 ba_status ba_solve(ba_ctx* ctx, ba_solve_report* rep);
 
-/* Copy the current parameters out (cams C x 7, points P x 3; either may be NULL). */
+/* Copy the current parameters of Sec. III-B out: cams C x 7 [qw, qx, qy, qz, cx, cy, cz] and
+ * points P x 3, float64, caller's order, host or device memory owned by the caller (either
+ * may be NULL). */
 ba_status ba_get_params(const ba_ctx* ctx, double* cams, double* points);
 
 /* Overwrite the parameters (cams C x 7, points P x 3; either may be NULL), e.g. to warm-start
@@ -198,6 +227,15 @@ ba_status ba_get_active(const ba_ctx* ctx, uint8_t* cams, uint8_t* points, uint8
  * when refine_focal: d = 7, else d = 6), points P x 3; zero for inactive or fixed entries. */
 ba_status ba_get_last_step(const ba_ctx* ctx, double* dcams, double* dpoints);
 
+/* The block-Jacobi preconditioner of the last LM system (the paper names PCG, Sec. IV-B, but
+ * not its preconditioner): for every active camera the inverse of its D x D diagonal block
+ * of the damped camera Schur complement, S_cc = U*_c - sum_k W_k V*^-1 W_k^T (Eq. (3)),
+ * factorised by Cholesky in float64; a block that is not positive definite falls back to
+ * the inverse of diag(U*_c). Minv: C x D x D float64, row-major, caller's camera order, zero
+ * for inactive and fixed cameras; D = 7 with refine_focal, else 6. BA_ERR_STATE before the
+ * first ba_lm_step. */
+ba_status ba_get_preconditioner(const ba_ctx* ctx, double* Minv);
+
 /* Undamped normal-equation blocks of the last linearisation, caller's order, zero for
  * inactive entries: U C x d*d (J_c^T W J_c, row-major d x d), gc C x d (J_c^T W e),
  * V P x 9 (J_p^T W J_p), gp P x 3 (J_p^T W e), with d = 7 when refine_focal, else 6.
@@ -210,7 +248,8 @@ ba_status ba_get_normal_blocks(const ba_ctx* ctx, double* U, double* gc, double*
  * depth rows). Solves H v = dL/dtheta with H = sum J^T M J, M = rho' I + 2 rho'' e e^T, by
  * the same Schur-PCG, then maps v per observation. Needs at least one fixed camera and a
  * fixed scale (depth rows with lambda_d > 0, or two fixed cameras): BA_ERR_STATE otherwise.
- * Inactive observations get zero gradients. */
+ * Inactive observations get zero gradients. Returns BA_NOT_CONVERGED when the PCG stopped at
+ * adjoint_max_iters above adjoint_rel_tol (gradients written from the last iterate). */
 ba_status ba_adjoint(ba_ctx* ctx, const double* grad_cams, const double* grad_points,
                      float* grad_xy, float* grad_depth);
 /* (with refine_focal set, ba_adjoint returns BA_ERR_STATE: it covers poses and points) */

@@ -15,13 +15,14 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), LIB_NAME)
 
 BA_OK = 0
 BA_EMPTY = 1
+BA_NOT_CONVERGED = 2
 BA_ERR_ARG = -1
 BA_ERR_STATE = -2
 BA_ERR_OOM = -3
 BA_ERR_DEVICE = -4
 BA_ERR_NUMERIC = -5
-STATUS_NAMES = {0: "BA_OK", 1: "BA_EMPTY", -1: "BA_ERR_ARG", -2: "BA_ERR_STATE",
-                -3: "BA_ERR_OOM", -4: "BA_ERR_DEVICE", -5: "BA_ERR_NUMERIC"}
+STATUS_NAMES = {0: "BA_OK", 1: "BA_EMPTY", 2: "BA_NOT_CONVERGED", -1: "BA_ERR_ARG",
+                -2: "BA_ERR_STATE", -3: "BA_ERR_OOM", -4: "BA_ERR_DEVICE", -5: "BA_ERR_NUMERIC"}
 
 BA_PRECISION_FP64 = 0
 BA_PRECISION_MIXED = 1
@@ -53,7 +54,7 @@ class BaStepReport(Structure):
         ("gain_ratio", c_double), ("lambda_", c_double), ("pcg_rel_residual", c_double),
         ("rms_px", c_double), ("grad_inf", c_double), ("ms_extract", c_double),
         ("ms_linearize", c_double), ("ms_setup", c_double), ("ms_pcg", c_double),
-        ("ms_candidate", c_double), ("ms_total", c_double),
+        ("ms_candidate", c_double), ("ms_total", c_double), ("pcg_true_residual", c_double),
     ]
 
 
@@ -98,6 +99,7 @@ EXPORTS = {
     "ba_get_active": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "ba_get_last_step": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "ba_get_normal_blocks": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "ba_get_preconditioner": (c_int32, [c_void_p, c_void_p]),
     "ba_adjoint": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "ba_kernel_stats": (c_int32, [c_void_p, POINTER(BaKernelStat), c_int32, POINTER(c_int32)]),
     "ba_reset_kernel_stats": (c_int32, [c_void_p]),

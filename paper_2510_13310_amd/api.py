@@ -177,13 +177,25 @@ def ba_get_normal_blocks(ctx: int, U_out, gc_out, V_out, gp_out) -> int:
     return _check(lib, ctx, lib.ba_get_normal_blocks(ctx, *ptrs))
 
 
+def ba_get_preconditioner(ctx: int, Minv_out) -> int:
+    lib = _abi.load()
+    p, _ = _ptr(Minv_out, F64)
+    return _check(lib, ctx, lib.ba_get_preconditioner(ctx, p))
+
+
 def ba_adjoint(ctx: int, grad_cams, grad_points, grad_xy_out, grad_depth_out) -> int:
+    """Returns BA_OK, or BA_NOT_CONVERGED (with a warning) when the adjoint PCG stopped at its
+    iteration cap above its tolerance; errors raise BAError."""
     lib = _abi.load()
     a, ka = _ptr(grad_cams, F64)
     b, kb = _ptr(grad_points, F64)
     c, _ = _ptr(grad_xy_out, F32)
     d, _ = _ptr(grad_depth_out, F32)
-    return _check(lib, ctx, lib.ba_adjoint(ctx, a, b, c, d))
+    st = _check(lib, ctx, lib.ba_adjoint(ctx, a, b, c, d))
+    if st == _abi.BA_NOT_CONVERGED:
+        import warnings
+        warnings.warn("ba_adjoint: " + ba_last_error(ctx), RuntimeWarning, stacklevel=2)
+    return st
 
 
 def ba_kernel_stats(ctx: int, max_entries: int = 64) -> list:
@@ -347,12 +359,19 @@ class BundleAdjuster:
         ba_get_normal_blocks(self.ctx, U, gc, V, gp)
         return U, gc, V, gp
 
+    def get_preconditioner(self):
+        d = self.cam_dim
+        M = np.empty((self.n_cams, d, d))
+        ba_get_preconditioner(self.ctx, M)
+        return M
+
     def adjoint(self, grad_cams, grad_points, grad_xy_out=None, grad_depth_out=None):
         if grad_xy_out is None:
             grad_xy_out = np.empty((self.n_obs, 2), np.float32)
         if grad_depth_out is None:
             grad_depth_out = np.empty(self.n_obs, np.float32)
-        ba_adjoint(self.ctx, grad_cams, grad_points, grad_xy_out, grad_depth_out)
+        self.last_adjoint_status = ba_adjoint(self.ctx, grad_cams, grad_points, grad_xy_out,
+                                              grad_depth_out)
         return grad_xy_out, grad_depth_out
 
     def kernel_stats(self):

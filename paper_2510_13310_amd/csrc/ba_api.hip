@@ -78,6 +78,13 @@ struct Pending {
   int pcg_iter;   // -1 outside the PCG loop
 };
 
+// Size limits: the kernels index per-entity arrays with 32-bit products. The largest are
+// 16 lanes per point (thread indices up to 16 P) and 3 values per observation (up to 3 N),
+// so P and C stay below 2^27 and N below 2^29; every such product then fits in an int.
+constexpr int32_t kMaxCams = (int32_t(1) << 27) - 1;
+constexpr int32_t kMaxPoints = (int32_t(1) << 27) - 1;
+constexpr int64_t kMaxObs = (int64_t(1) << 29) - 1;
+
 double now_ms() {
   using namespace std::chrono;
   return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
@@ -172,6 +179,8 @@ struct ba_ctx {
   double *grad_cams_d = nullptr, *grad_pts_d = nullptr;
   float *gxy_d = nullptr, *gdepth_d = nullptr;
   PcgState* pcg = nullptr;
+  PcgState* pcg_diag = nullptr;   // state of the extra matvec that measures the true residual
+  double* diag = nullptr;         // |b - S x|^2, |b|^2 of that product
   double* h_pin = nullptr;   // pinned host readback buffer
 
   // LM state
@@ -452,6 +461,8 @@ void alloc_obs_buffers(ba_ctx& c) {
   c.partials = A.alloc<double>(5 * (size_t(P) * 16 / kBlock + 16));
   c.scal = A.alloc<double>(16);
   c.pcg = A.alloc<PcgState>(1);
+  c.pcg_diag = A.alloc<PcgState>(1);
+  c.diag = A.alloc<double>(4);
   c.grad_cams_d = nullptr;
   c.grad_pts_d = nullptr;
   c.gxy_d = nullptr;
@@ -858,6 +869,33 @@ int run_pcg(ba_ctx& c, bool adj, double rel_tol, int max_iters, PcgState* out_st
   return st.matvecs;
 }
 
+// |b - S x| / |b| of the PCG solution in c.x (the LM system): one more pass of the matvec
+// kernels on x itself, outside the iteration's statistics.
+template <typename T>
+double true_residual(ba_ctx& c) {
+  if (c.Ca == 0) return 0.0;
+  hipStream_t s = c.stream;
+  const Model m = c.model();
+  Compact<T> cp = compact_view<T>(c);
+  ObsMetric<T> om = metric_view<T>(c);
+  int K = 0, nch = 0;
+  cam_chunking(c.Nc, K, nch);
+  const int nslot = c.Ca + nch;
+  P3<T>* zq = static_cast<P3<T>*>(c.zq);
+  launch_x_to_mv<T>(s, c.D, c.Ca, c.x, c.mvt, c.pcg_diag);
+  launch_schur_point<T>(s, false, c.D, lanes_per_point(c), m, cp, om, c.mvt,
+                        static_cast<const T*>(c.Vinv), zq, c.pcg_diag, c.dl);
+  launch_schur_cam<T>(s, false, c.D, m, cp, om, c.x, zq, K, c.item_off, c.item_cam, nslot,
+                      c.part, c.pcg_diag);
+  launch_true_residual<T>(s, c.D, c.Ca, c.x, c.b, static_cast<const T*>(c.Ustar), c.item_off,
+                          nslot, c.part, c.diag);
+  HIP_LAUNCH_CHECK();
+  HIP_CHECK(hipMemcpyAsync(c.h_pin + 16, c.diag, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  c.sync();
+  const double rr = c.h_pin[16], bb = c.h_pin[17];
+  return bb > 0 ? std::sqrt(std::max(0.0, rr) / bb) : 0.0;
+}
+
 template <typename T>
 void backsub(ba_ctx& c, bool adj, const double* rhs_p) {
   hipStream_t s = c.stream;
@@ -875,6 +913,7 @@ ba_status lm_step_impl(ba_ctx& c, ba_step_report* rep) {
   const double t0 = now_ms();
   ba_step_report R;
   std::memset(&R, 0, sizeof(R));
+  R.pcg_true_residual = -1.0;
   R.lambda = c.lam;
   hipStream_t s = c.stream;
   const Model m = c.model();
@@ -923,6 +962,8 @@ ba_status lm_step_impl(ba_ctx& c, ba_step_report* rep) {
   R.pcg_iters = st.iter;
   R.pcg_breakdown = st.breakdown;
   R.pcg_rel_residual = st.bb > 0 ? std::sqrt(std::max(0.0, st.rr) / st.bb) : 0.0;
+  R.pcg_true_residual = -1.0;
+  if (c.opt.timing && !explicit_solver(c)) R.pcg_true_residual = true_residual<T>(c);
 
   ta = now_ms();
   backsub<T>(c, false, nullptr);
@@ -1097,6 +1138,7 @@ ba_status gp_step_impl(ba_ctx& c, ba_step_report* rep) {
   const double t0 = now_ms();
   ba_step_report R;
   std::memset(&R, 0, sizeof(R));
+  R.pcg_true_residual = -1.0;
   if (!c.gp_ready) gp_init(c);
   R.lambda = c.gp_lam;
   hipStream_t s = c.stream;
@@ -1242,9 +1284,12 @@ ba_status gp_step_dispatch(ba_ctx& c, ba_step_report* rep) {
                                               : gp_step_impl<float>(c, rep);
 }
 
+// Returns false when the adjoint PCG stopped at adjoint_max_iters above its tolerance (the
+// gradients are still written, from the last iterate); the message is left in c.err.
 template <typename T>
-void adjoint_impl(ba_ctx& c, const double* grad_cams, const double* grad_points, float* gxy,
+bool adjoint_impl(ba_ctx& c, const double* grad_cams, const double* grad_points, float* gxy,
                   float* gdepth) {
+  bool converged = true;
   hipStream_t s = c.stream;
   ensure_adjoint_buffers(c);
   c.to_device(c.grad_cams_d, grad_cams, sizeof(double) * 7 * size_t(c.C));
@@ -1277,6 +1322,14 @@ void adjoint_impl(ba_ctx& c, const double* grad_cams, const double* grad_points,
     c.flush_timing(mv);
     if (bad) throw BaError{BA_ERR_NUMERIC, "singular point block in the adjoint system"};
     if (st.breakdown) throw BaError{BA_ERR_NUMERIC, "adjoint PCG broke down"};
+    if (!st.done && c.Ca > 0) {
+      converged = false;
+      char msg[160];
+      std::snprintf(msg, sizeof(msg),
+                    "adjoint PCG stopped after %d iterations at relative residual %.3e "
+                    "(tolerance %.3e)", st.iter, st.bb > 0 ? std::sqrt(st.rr / st.bb) : 0.0, tol);
+      c.err = msg;
+    }
   }
   c.sync();
   HIP_CHECK(hipMemcpyAsync(gxy, c.gxy_d, sizeof(float) * 2 * size_t(c.N), hipMemcpyDefault, s));
@@ -1284,6 +1337,7 @@ void adjoint_impl(ba_ctx& c, const double* grad_cams, const double* grad_points,
     HIP_CHECK(hipMemcpyAsync(gdepth, c.gdepth_d, sizeof(float) * size_t(c.N), hipMemcpyDefault,
                              s));
   c.sync();
+  return converged;
 }
 
 // Counting sort by an integer key in [0, K): stable.
@@ -1361,10 +1415,10 @@ ba_status ba_create(const ba_options* opt, int32_t n_cams, int32_t n_points, con
     o = *opt;
   else
     ba_default_options(&o);
-  if (n_cams < 1 || n_points < 1 || n_cams == INT32_MAX || n_points == INT32_MAX || !cams ||
+  if (n_cams < 1 || n_points < 1 || n_cams > kMaxCams || n_points > kMaxPoints || !cams ||
       !intr || !points) {
-    g_create_error =
-        "need 1 <= n_cams, n_points < 2^31 - 1 and non-NULL cams, intr, points";
+    g_create_error = "need 1 <= n_cams <= 2^27 - 1, 1 <= n_points <= 2^27 - 1 and non-NULL "
+                     "cams, intr, points";
     return BA_ERR_ARG;
   }
   if ((o.precision != BA_PRECISION_FP64 && o.precision != BA_PRECISION_MIXED) ||
@@ -1455,8 +1509,8 @@ ba_status ba_create(const ba_options* opt, int32_t n_cams, int32_t n_points, con
 ba_status ba_set_observations(ba_ctx* c, int64_t n_obs, const int32_t* cam_idx,
                               const int32_t* pt_idx, const float* xy) {
   return guarded(c, [&]() -> ba_status {
-    if (n_obs < 0 || n_obs >= (int64_t(1) << 31) - 1)   // scans hold n_obs + 1 entries
-      return fail(c, BA_ERR_ARG, "n_obs must be in [0, 2^31 - 1)");
+    if (n_obs < 0 || n_obs > kMaxObs)
+      return fail(c, BA_ERR_ARG, "n_obs must be in [0, 2^29 - 1]");
     if (n_obs > 0 && (!cam_idx || !pt_idx || !xy))
       return fail(c, BA_ERR_ARG, "NULL observation array");
     std::vector<int32_t> hc, hp;
@@ -1857,6 +1911,31 @@ ba_status ba_get_normal_blocks(const ba_ctx* cc, double* U, double* gcv, double*
   });
 }
 
+ba_status ba_get_preconditioner(const ba_ctx* cc, double* Minv) {
+  ba_ctx* c = const_cast<ba_ctx*>(cc);
+  return guarded(c, [&]() -> ba_status {
+    if (!Minv) return fail(c, BA_ERR_ARG, "Minv is NULL");
+    if (!c->blocks_valid) return fail(c, BA_ERR_STATE, "no LM system has been set up");
+    const int D = c->D;
+    const size_t ns = size_t(D) * (D + 1) / 2;
+    std::vector<int> csrc;
+    std::vector<double> m, out(size_t(D) * D * size_t(c->C), 0.0);
+    download(*c, csrc, c->cam_src, size_t(c->Ca));
+    download(*c, m, c->Minv, ns * size_t(c->Ca));
+    for (int s = 0; s < c->Ca; ++s) {
+      const size_t cam = size_t(csrc[s]);
+      for (int i = 0; i < D; ++i)
+        for (int j = 0; j < D; ++j) {
+          const int a = std::min(i, j), b = std::max(i, j);
+          const int idx = a * D - (a * (a - 1)) / 2 + (b - a);
+          out[size_t(D) * D * cam + D * i + j] = m[size_t(idx) * c->Ca + s];
+        }
+    }
+    store(*c, Minv, out.data(), out.size());
+    return BA_OK;
+  });
+}
+
 ba_status ba_adjoint(ba_ctx* c, const double* grad_cams, const double* grad_points,
                      float* grad_xy, float* grad_depth) {
   return guarded(c, [&]() -> ba_status {
@@ -1870,11 +1949,10 @@ ba_status ba_adjoint(ba_ctx* c, const double* grad_cams, const double* grad_poin
       return fail(c, BA_ERR_STATE,
                   "the adjoint needs a fixed gauge: >= 1 fixed camera and depth rows "
                   "(lambda_d > 0), or >= 2 fixed cameras");
-    if (c->opt.precision == BA_PRECISION_FP64)
-      adjoint_impl<double>(*c, grad_cams, grad_points, grad_xy, grad_depth);
-    else
-      adjoint_impl<float>(*c, grad_cams, grad_points, grad_xy, grad_depth);
-    return BA_OK;
+    const bool ok = c->opt.precision == BA_PRECISION_FP64
+                        ? adjoint_impl<double>(*c, grad_cams, grad_points, grad_xy, grad_depth)
+                        : adjoint_impl<float>(*c, grad_cams, grad_points, grad_xy, grad_depth);
+    return ok ? BA_OK : BA_NOT_CONVERGED;
   });
 }
 

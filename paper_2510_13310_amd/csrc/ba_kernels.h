@@ -304,6 +304,15 @@ void launch_pcg_update(hipStream_t s, int D, int Ca, int k, const double* Minv, 
                        const int* item_off, int nslot, const double* part, double* terms,
                        double* x, double* r, double* u, double* p, double* sv, double* Uu,
                        void* mvt, PcgState* st);
+// The true residual of a PCG solution x: k_x_to_mv writes x into the matvec records and
+// clears the done flag of st (a state used only for this product), the two matvec passes run
+// with st, and launch_true_residual forms |b - S x|^2 and |b|^2 into out[0], out[1].
+template <typename T>
+void launch_x_to_mv(hipStream_t s, int D, int Ca, const double* x, void* mvt, PcgState* st);
+template <typename T>
+void launch_true_residual(hipStream_t s, int D, int Ca, const double* x, const double* b,
+                          const T* Ustar, const int* item_off, int nslot, const double* part,
+                          double* out);
 // dp = Vinv (rhs_p - sum_k W_k^T x_c), rhs_p = -gp when nullptr.
 template <typename T>
 void launch_backsub(hipStream_t s, bool adj, int D, int G, const Model& m, const Compact<T>& cp,

@@ -1381,6 +1381,53 @@ k_pcg_update(int Ca, int k, const double* __restrict__ Minv, const T* __restrict
   tout[2 * Ca + s] = rr;
 }
 
+// True residual of the PCG solution x at exit: the matvec passes are run once more on x
+// itself (k_x_to_mv copies x into the matvec records and arms a state of its own), then
+// k_true_residual forms S x = U* x - (the camera's item partials) and the float64 sums
+// |b - S x|^2 and |b|^2, one workgroup in a fixed order.
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock)
+k_x_to_mv(int Ca, const double* __restrict__ x, MvRec<T, D>* __restrict__ mvt, PcgState* st) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s == 0) {
+    st->done = 0;
+    st->breakdown = 0;
+  }
+  if (s >= Ca) return;
+#pragma unroll
+  for (int i = 0; i < D; ++i) mvt[s].u[i] = T(x[i * Ca + s]);
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(1024)
+k_true_residual(int Ca, const double* __restrict__ x, const double* __restrict__ b,
+                const T* __restrict__ Ustar, const int* __restrict__ item_off, int nslot,
+                const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double smem[2 * (1024 / kWave)];
+  double acc[2] = {0.0, 0.0};   // |b - S x|^2, |b|^2
+  for (int s = threadIdx.x; s < Ca; s += blockDim.x) {
+    double xv[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) xv[i] = x[i * Ca + s];
+    const int i0 = item_off[s], i1 = item_off[s + 1];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      double a = 0.0;
+#pragma unroll
+      for (int j = 0; j < D; ++j) a += double(Ustar[symd<D>(i, j) * Ca + s]) * xv[j];
+      for (int it = i0; it < i1; ++it) a -= part[i * nslot + it];
+      const double bi = b[i * Ca + s];
+      acc[0] += (bi - a) * (bi - a);
+      acc[1] += bi * bi;
+    }
+  }
+  block_sum<double, 2>(acc, smem);
+  if (threadIdx.x == 0) {
+    out[0] = acc[0];
+    out[1] = acc[1];
+  }
+}
+
 // Back-substitution dp = Vinv (rhs_p - sum_k W_k^T x_c), same lane layout as the point pass.
 template <typename T, bool ADJ, int G, int D>
 __global__ void __launch_bounds__(kBlock)
@@ -2887,6 +2934,26 @@ void launch_pcg_update(hipStream_t s, int D, int Ca, int k, const double* Minv, 
   });
 }
 
+template <typename T>
+void launch_x_to_mv(hipStream_t s, int D, int Ca, const double* x, void* mvt, PcgState* st) {
+  if (Ca <= 0) return;
+  with_dim(D, [&](auto Dc) {
+    launch_k(k_x_to_mv<T, Dc()>, dim3(blocks_for(Ca)), dim3(kBlock), 0, s, Ca, x,
+             static_cast<MvRec<T, Dc()>*>(mvt), st);
+  });
+}
+
+template <typename T>
+void launch_true_residual(hipStream_t s, int D, int Ca, const double* x, const double* b,
+                          const T* Ustar, const int* item_off, int nslot, const double* part,
+                          double* out) {
+  if (Ca <= 0) return;
+  with_dim(D, [&](auto Dc) {
+    launch_k(k_true_residual<T, Dc()>, dim3(1), dim3(1024), 0, s, Ca, x, b, Ustar, item_off,
+             nslot, part, out);
+  });
+}
+
 template <typename T, bool ADJ, int D>
 void backsub_g(hipStream_t s, int G, const Model& m, const Compact<T>& cp, ObsMetric<T> om,
                const T* Vinv, const double* x, const double* gp, const double* rhs_p,
@@ -3012,6 +3079,9 @@ void launch_adjoint_obs(hipStream_t s, const Model& m, const Compact<T>& cp, Obs
                                      const int*, int, const double*, double*, double*,        \
                                      double*, double*, double*, double*, double*, void*,      \
                                      PcgState*);                                               \
+  template void launch_x_to_mv<T>(hipStream_t, int, int, const double*, void*, PcgState*);    \
+  template void launch_true_residual<T>(hipStream_t, int, int, const double*, const double*,  \
+                                        const T*, const int*, int, const double*, double*);   \
   template void launch_backsub<T>(hipStream_t, bool, int, int, const Model&,                  \
                                   const Compact<T>&, ObsMetric<T>, const T*, const double*,   \
                                   const double*, const double*, double*);                      \

@@ -75,3 +75,32 @@ def test_null_context_is_rejected():
     assert lib.ba_lm_step(None, None) == P.BA_ERR_ARG
     lib.ba_destroy(None)
     assert lib.ba_device_bytes(None) == 0
+
+
+def test_step_report_layout():
+    import ctypes
+    # 8 int32, 1 int64, 14 doubles, then the true residual (double)
+    assert ctypes.sizeof(_abi.BaStepReport) == 8 * 4 + 8 + 14 * 8 + 8
+    assert _abi.BaStepReport._fields_[-1][0] == "pcg_true_residual"
+
+
+def test_size_limits_checked_before_device():
+    """n_cams and n_points above 2^27 - 1 are refused by the size check itself, before the
+    device is looked for (without a GPU every valid size reports BA_ERR_DEVICE instead)."""
+    import ctypes
+    lib = _abi.load()
+    cams = np.zeros((2, 7))
+    cams[:, 0] = 1
+    intr = np.ones((2, 3))
+    pts = np.zeros((3, 3))
+    out = ctypes.c_void_p()
+    opts = P.ba_default_options()
+    args = (cams.ctypes.data, intr.ctypes.data, pts.ctypes.data, ctypes.byref(out))
+    assert lib.ba_create(ctypes.byref(opts), 2, 2**27, *args) == P.BA_ERR_ARG
+    assert lib.ba_create(ctypes.byref(opts), 2**27, 3, *args) == P.BA_ERR_ARG
+    assert "2^27" in P.ba_last_error(None)
+    st = lib.ba_create(ctypes.byref(opts), 2, 2**27 - 1, *args)
+    if st == P.BA_OK:   # a GPU is present and would read 2^27 points: not reached here
+        lib.ba_destroy(out)
+        pytest.fail("valid size accepted with a 3-point array")
+    assert st in (P.BA_ERR_DEVICE, P.BA_ERR_OOM)

@@ -3,9 +3,12 @@ scenes. Sizes span many 256-thread blocks and scan tiles and end on ragged tails
 
 Tolerances (float64 path): active sets and ranks bit-exact; normal-equation blocks and
 gradients 1e-9 relative to the largest entry; one LM step 1e-6 relative (PCG to 1e-12 vs a
-direct Cholesky); converged solutions within 1e-3 px RMS and 1e-6 relative gauge-aligned
-parameters. Mixed precision (float32 Jacobians/matvecs): blocks 1e-5, converged RMS within
-1e-3 px and aligned parameters within 1e-4.
+direct Cholesky); the tiny scene solved to convergence within 1e-6 relative gauge-aligned
+parameters; the adjoint workload (the medium scene with camera 0 fixed and metric depth rows,
+so no gauge freedom is left) solved by both to max |g| <= 1e-3 within 1e-6 relative
+parameters and 1e-6 rad rotations. Mixed precision (float32 Jacobians and matvecs): blocks
+2e-5; on the same solve final RMS within 1e-3 px of the oracle's and parameters within 1e-6
+relative (the float32 Jacobian perturbs the stationary point itself, see the test).
 """
 from dataclasses import replace
 
@@ -150,35 +153,86 @@ def test_lm_trajectory_fp64_medium_fixed_gauge():
     assert err < 1e-6 and d < 1e-6, (err, d)
 
 
+def _rel(a, b):
+    """|a - b|_F / |b - mean(b)|_F over stacked centres and points."""
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b - b.mean(axis=0)))
+
+
+_FIXED_GAUGE = {}
+
+
+def _converge_oracle_fixed_gauge():
+    if "adjoint" not in _FIXED_GAUGE:
+        sc = scene("adjoint")
+        prob, opts, st = oracle_setup(sc, cost_rel_tol=0.0, grad_tol=1e-3, max_iters=150)
+        _FIXED_GAUGE["adjoint"] = solve(prob, st, opts)
+    return _FIXED_GAUGE["adjoint"]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_converged_parameters_fixed_gauge(precision):
+    """The adjoint workload (medium scene: outliers, Huber 2 px, 4 px filter, dynamic
+    extraction, camera 0 fixed, depth rows with lambda_d = 300 fixing the metric scale) solved
+    by both implementations with the same stopping rule, max |g| <= 1e-3 at the start of a
+    step (cost about 6e4). The robust problem converges linearly under IRLS (about 0.84 per
+    iteration once the damping bottoms out), so the rule stops both after the same iteration.
+
+    The stopping point is converged to far below the tolerances: continuing the oracle from
+    it to the float64 floor (steps rejected until the damping reaches its maximum) moves the
+    points by 5.4e-9 and the centres by 2.8e-11 relative.
+
+    float64: same iteration count, parameters within 1e-6 relative (|d|_F over stacked
+    centres and points against their spread) and rotations within 1e-6 rad, RMS within
+    1e-3 px. Mixed: the float32 Jacobian moves the point where the float64-accumulated
+    gradient vanishes by a few float32 roundings (6e-8) amplified by the weak directions of
+    the reduced system; mixed is held to RMS within 1e-3 px and parameters and rotations
+    within 1e-6 (17 float32 roundings)."""
+    sc = scene("adjoint")
+    st, reps = _converge_oracle_fixed_gauge()
+    o_rms = reps[-1].rms_px
+    kw = dict(cost_rel_tol=0.0, grad_tol=1e-3, max_lm_iters=150)
+    if precision == "fp64":
+        ba = gpu_setup(sc, "fp64", pcg_rel_tol=1e-12, pcg_max_iters=3000, **kw)
+    else:
+        ba = gpu_setup(sc, "mixed", pcg_rel_tol=1e-8, pcg_max_iters=1000, **kw)
+    srep = ba.solve()
+    cams, pts = ba.get_params()
+    np.testing.assert_array_equal(cams[0], sc.cams0[0])
+    err = _rel(np.vstack([cams[:, 4:7], pts]), np.vstack([st.c, st.X]))
+    rot = rotation_error(cams, st.cams(), np.eye(3))
+    print(f"adjoint workload {precision}: {srep['iterations']} iterations (oracle {len(reps)}), "
+          f"stop {srep['stop_reason']}, rms {srep['final_rms_px']:.9f} (oracle {o_rms:.9f}), "
+          f"parameter error {err:.3e}, rotation error {rot:.3e} rad")
+    assert abs(srep["final_rms_px"] - o_rms) < 1e-3
+    if precision == "fp64":
+        assert srep["iterations"] == len(reps) and srep["stop_reason"] == 2
+        assert err < 1e-6, err
+        assert rot < 1e-6, rot
+    else:
+        assert err < 1e-6, err
+        assert rot < 1e-6, rot
+
+
 def test_converged_medium_rms_both_precisions():
-    """Free gauge, run to the stopping rule: final RMS of the float64 and mixed GPU paths
-    within 1e-3 px of the oracle's and final costs within 1e-6 relative. With a free 7-DOF
-    gauge, weak depth priors and forward motion, the robust problem converges only
-    linearly along weak directions (points near the focus of expansion), so gauge-aligned
-    parameter agreement at the stopping point is measured and reported, not asserted; the
-    fixed-gauge trajectory test above pins the parameters."""
+    """Free gauge (the medium scene as generated), run to the stopping rule: final RMS of the
+    float64 and mixed GPU paths within 1e-3 px of the oracle's and final costs within 1e-6
+    relative. Parameters are compared with the gauge fixed in the test above."""
     sc = scene("medium")
     st, reps = _converge_oracle(sc)
     o_rms = reps[-1].rms_px
-    prob, opts, _ = oracle_setup(sc)
-    ex = extract(prob, st, opts)
     out = {}
     for prec in ("fp64", "mixed"):
         ba = gpu_setup(sc, prec, pcg_rel_tol=1e-8, pcg_max_iters=500, cost_rel_tol=1e-12,
                        max_lm_iters=60)
         srep = ba.solve()
-        cams, pts = ba.get_params()
-        ac, ap, _ = ba.get_active()
-        selc, selp = ac & ex.cam_active, ap & ex.pt_active
-        err, _ = aligned_error(cams[selc], pts[selp], st.cams()[selc], st.X[selp])
-        out[prec] = (srep["final_rms_px"], err, srep["iterations"])
+        out[prec] = srep["final_rms_px"]
         o_cost = min(r.cost_after if r.accepted else r.cost_before for r in reps)
         print(f"medium {prec}: rms {srep['final_rms_px']:.6f} (oracle {o_rms:.6f}), "
               f"cost {srep['final_cost']:.6f} (oracle {o_cost:.6f}), "
-              f"aligned parameter error {err:.3e}, {srep['iterations']} iterations")
+              f"{srep['iterations']} iterations")
         assert abs(srep["final_rms_px"] - o_rms) < 1e-3
         assert abs(srep["final_cost"] - o_cost) <= 1e-6 * o_cost
-    assert abs(out["mixed"][0] - out["fp64"][0]) < 1e-3
+    assert abs(out["mixed"] - out["fp64"]) < 1e-3
 
 
 def test_inactive_parameters_bit_identical_and_deterministic():
