@@ -201,6 +201,19 @@ ba_status ba_set_fixed_cameras(ba_ctx* ctx, int32_t n, const int32_t* cam_ids);
  * ba_set_observations, BA_ERR_NUMERIC (parameters unchanged) for a non-finite cost. */
 ba_status ba_lm_step(ba_ctx* ctx, ba_step_report* rep);
 
+/* ba_lm_step for callers that cannot allocate device memory (serving loops, code that must
+ * not call hipMalloc): the same LM iteration with the same results, but its per-step scratch
+ * (fixpoint and damping flags, PCG states, reduction and camera-pass partials, item tables,
+ * the scan workspace) lives in a static device array of 32 MiB that each GPU holds from
+ * library load to process end; the call itself allocates nothing. The context's other
+ * buffers are those of ba_create and ba_set_observations. BA_ERR_ARG when the problem needs
+ * more scratch than the array holds (about 2.5 bytes per point, 112 bytes per camera and the
+ * scan workspace: e.g. 2M points and 5000 cameras fit), BA_ERR_STATE with opt.timing = 1 or
+ * the explicit solver (both allocate). Every call on one GPU shares that GPU's array and
+ * leaves its contents behind: calls that overlap in time on one GPU (from several threads or
+ * streams) race and must be serialised by the caller. */
+ba_status ba_lm_step_noalloc(ba_ctx* ctx, ba_step_report* rep);
+
 /* The LM loop of Eq. (3): iterate ba_lm_step until max_lm_iters, the relative cost decrease
  * of an accepted step falls to cost_rel_tol, max |g| to grad_tol, or a rejection reaches
  * lambda_max (rep->stop_reason). rep may be NULL. Errors as ba_lm_step. */

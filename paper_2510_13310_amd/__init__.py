@@ -9,7 +9,7 @@ from ._abi import (BAError, BA_OK, BA_EMPTY, BA_NOT_CONVERGED, BA_ERR_ARG, BA_ER
                    LIB_PATH, load)
 from .api import (BundleAdjuster, make_options, ba_default_options, ba_create,
                   ba_set_observations, ba_set_depth_priors, ba_set_fixed_cameras, ba_lm_step,
-                  ba_solve, ba_get_params, ba_get_intrinsics, ba_set_params, ba_get_active,
+                  ba_lm_step_noalloc, ba_solve, ba_get_params, ba_get_intrinsics, ba_set_params, ba_get_active,
                   ba_get_last_step,
                   ba_get_normal_blocks, ba_get_preconditioner, ba_adjoint, ba_kernel_stats, ba_reset_kernel_stats,
                   ba_device_bytes, ba_last_error, ba_destroy, ba_gp_step, ba_gp_solve,
@@ -20,7 +20,7 @@ __all__ = [
     "BA_ERR_DEVICE", "BA_ERR_NUMERIC", "BA_PRECISION_FP64", "BA_PRECISION_MIXED", "LIB_PATH",
     "load", "BundleAdjuster", "make_options", "ba_default_options", "ba_create",
     "ba_set_observations", "ba_set_depth_priors", "ba_set_fixed_cameras", "ba_lm_step",
-    "ba_solve", "ba_get_params", "ba_get_intrinsics", "ba_set_params", "ba_get_active",
+    "ba_lm_step_noalloc", "ba_solve", "ba_get_params", "ba_get_intrinsics", "ba_set_params", "ba_get_active",
     "ba_get_last_step",
     "ba_get_normal_blocks", "ba_get_preconditioner", "ba_adjoint", "ba_kernel_stats", "ba_reset_kernel_stats",
     "ba_device_bytes", "ba_last_error", "ba_destroy", "ba_gp_step", "ba_gp_solve",

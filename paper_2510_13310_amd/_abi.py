@@ -88,6 +88,7 @@ EXPORTS = {
     "ba_set_depth_priors": (c_int32, [c_void_p, c_void_p, c_void_p, c_double]),
     "ba_set_fixed_cameras": (c_int32, [c_void_p, c_int32, c_void_p]),
     "ba_lm_step": (c_int32, [c_void_p, POINTER(BaStepReport)]),
+    "ba_lm_step_noalloc": (c_int32, [c_void_p, POINTER(BaStepReport)]),
     "ba_solve": (c_int32, [c_void_p, POINTER(BaSolveReport)]),
     "ba_get_params": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "ba_set_params": (c_int32, [c_void_p, c_void_p, c_void_p]),

@@ -98,6 +98,15 @@ def ba_lm_step(ctx: int) -> dict:
     return d
 
 
+def ba_lm_step_noalloc(ctx: int) -> dict:
+    lib = _abi.load()
+    rep = BaStepReport()
+    st = _check(lib, ctx, lib.ba_lm_step_noalloc(ctx, byref(rep)))
+    d = struct_to_dict(rep)
+    d["status"] = st
+    return d
+
+
 def ba_solve(ctx: int) -> dict:
     lib = _abi.load()
     rep = BaSolveReport()
@@ -300,6 +309,9 @@ class BundleAdjuster:
     # solve
     def lm_step(self) -> dict:
         return ba_lm_step(self.ctx)
+
+    def lm_step_noalloc(self) -> dict:
+        return ba_lm_step_noalloc(self.ctx)
 
     def solve(self) -> dict:
         return ba_solve(self.ctx)

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -84,6 +85,37 @@ struct Pending {
 constexpr int32_t kMaxCams = (int32_t(1) << 27) - 1;
 constexpr int32_t kMaxPoints = (int32_t(1) << 27) - 1;
 constexpr int64_t kMaxObs = (int64_t(1) << 29) - 1;
+
+// ------------------------------------------------------------------ static scratch
+// Scratch of ba_lm_step_noalloc: the per-step buffers of an LM step (fixpoint and damping
+// flags, PCG states, reduction partials, camera-pass partials and terms, item tables, the scan
+// workspace) live in this array instead of the context's own buffers. Every GPU the library
+// runs on holds one copy from the moment the code object loads until the process ends; its
+// device address is looked up once per device (scratch_address, from ba_create with that
+// device current) and only that address is handed to kernels and copies.
+constexpr size_t kScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 256;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of the scratch array on device dev, which must be current (looked up on the
+// first call per device and kept).
+void* scratch_address(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_addr[dev] = p;
+  }
+  return g_scratch_addr[dev];
+}
 
 double now_ms() {
   using namespace std::chrono;
@@ -191,6 +223,8 @@ struct ba_ctx {
   double last_decrease = 0.0;   // per-observation actual reduction of the last step
 
   iba::DevLimits dl;   // compute units and LDS sizes of the context's device
+  int device = 0;      // HIP device the context was created on
+  void* scratch_dev = nullptr;   // that device's static scratch array (ba_lm_step_noalloc)
   // timing
   std::vector<KStat> stats;
   std::vector<Pending> pending;
@@ -1365,6 +1399,74 @@ void points_internal_to_user(ba_ctx& c, const std::vector<double>& internal,
     for (int k = 0; k < 3; ++k) user[3 * size_t(c.pt_user[i]) + k] = internal[3 * size_t(i) + k];
 }
 
+// Where ba_lm_step_noalloc puts each per-step buffer inside the static scratch array (the
+// sizes the context allocates for the same buffers, each slice aligned to 256 bytes).
+struct ScratchPlan {
+  size_t flags = 0, pcg = 0, pcg_diag = 0, diag = 0, partials = 0, dots = 0, part = 0,
+         item_off = 0, item_cam = 0, scan = 0, total = 0;
+};
+
+ScratchPlan plan_scratch(const ba_ctx& c) {
+  ScratchPlan p;
+  auto take = [&](size_t bytes) {
+    const size_t o = p.total;
+    p.total += (bytes + 255) / 256 * 256;
+    return o;
+  };
+  const size_t C = size_t(c.C), nd = size_t(c.D);
+  p.flags = take(4 * sizeof(int));
+  p.pcg = take(sizeof(PcgState));
+  p.pcg_diag = take(sizeof(PcgState));
+  p.diag = take(4 * sizeof(double));
+  p.partials = take(5 * (size_t(c.P) * 16 / kBlock + 16) * sizeof(double));
+  p.dots = take(2 * 3 * C * sizeof(double));
+  p.part = take((nd + 1) * (C + kCamChunks) * sizeof(double));
+  p.item_off = take((C + 1) * sizeof(int));
+  p.item_cam = take((C + kCamChunks) * sizeof(int));
+  p.scan = take(c.scan_temp_size);
+  return p;
+}
+
+// Points the context's per-step buffers into the scratch array for one call and restores
+// them afterwards (also when the step throws).
+struct ScratchSwap {
+  ba_ctx& c;
+  int* flags;
+  PcgState *pcg, *pcg_diag;
+  double *diag, *partials, *dots, *part;
+  int *item_off, *item_cam;
+  void* scan;
+  ScratchSwap(ba_ctx& cc, char* base, const ScratchPlan& p)
+      : c(cc), flags(cc.flags), pcg(cc.pcg), pcg_diag(cc.pcg_diag), diag(cc.diag),
+        partials(cc.partials), dots(cc.dots), part(cc.part), item_off(cc.item_off),
+        item_cam(cc.item_cam), scan(cc.scan_temp) {
+    c.flags = reinterpret_cast<int*>(base + p.flags);
+    c.pcg = reinterpret_cast<PcgState*>(base + p.pcg);
+    c.pcg_diag = reinterpret_cast<PcgState*>(base + p.pcg_diag);
+    c.diag = reinterpret_cast<double*>(base + p.diag);
+    c.partials = reinterpret_cast<double*>(base + p.partials);
+    c.dots = reinterpret_cast<double*>(base + p.dots);
+    c.part = reinterpret_cast<double*>(base + p.part);
+    c.item_off = reinterpret_cast<int*>(base + p.item_off);
+    c.item_cam = reinterpret_cast<int*>(base + p.item_cam);
+    c.scan_temp = base + p.scan;
+  }
+  ~ScratchSwap() {
+    c.flags = flags;
+    c.pcg = pcg;
+    c.pcg_diag = pcg_diag;
+    c.diag = diag;
+    c.partials = partials;
+    c.dots = dots;
+    c.part = part;
+    c.item_off = item_off;
+    c.item_cam = item_cam;
+    c.scan_temp = scan;
+  }
+  ScratchSwap(const ScratchSwap&) = delete;
+  ScratchSwap& operator=(const ScratchSwap&) = delete;
+};
+
 }  // namespace
 
 // ================================================================== C ABI
@@ -1460,6 +1562,8 @@ ba_status ba_create(const ba_options* opt, int32_t n_cams, int32_t n_points, con
     HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&c->h_pin), 64 * sizeof(double)));
     int dev = 0;
     HIP_CHECK(hipGetDevice(&dev));
+    c->device = dev;
+    c->scratch_dev = scratch_address(dev);
     HIP_CHECK(hipDeviceGetAttribute(&c->dl.n_cu, hipDeviceAttributeMultiprocessorCount, dev));
     HIP_CHECK(hipDeviceGetAttribute(&c->dl.lds_per_block,
                                     hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
@@ -1642,6 +1746,27 @@ ba_status ba_set_fixed_cameras(ba_ctx* c, int32_t n, const int32_t* ids) {
 
 ba_status ba_lm_step(ba_ctx* c, ba_step_report* rep) {
   return guarded(c, [&]() -> ba_status { return lm_step_dispatch(*c, rep); });
+}
+
+ba_status ba_lm_step_noalloc(ba_ctx* c, ba_step_report* rep) {
+  return guarded(c, [&]() -> ba_status {
+    if (!c->have_obs) return fail(c, BA_ERR_STATE, "ba_set_observations has not been called");
+    if (c->opt.solver == BA_SOLVER_EXPLICIT)
+      return fail(c, BA_ERR_STATE,
+                  "ba_lm_step_noalloc: the explicit solver allocates its block pattern");
+    if (c->opt.timing)
+      return fail(c, BA_ERR_STATE, "ba_lm_step_noalloc: timing creates events; set timing = 0");
+    const ScratchPlan p = plan_scratch(*c);
+    if (p.total > kScratchBytes)
+      return fail(c, BA_ERR_ARG,
+                  "ba_lm_step_noalloc: this problem needs " + std::to_string(p.total) +
+                      " bytes of step scratch, more than the " + std::to_string(kScratchBytes) +
+                      "-byte static array (use ba_lm_step)");
+    if (!c->scratch_dev)
+      return fail(c, BA_ERR_DEVICE, "ba_lm_step_noalloc: no scratch address on this device");
+    ScratchSwap swap(*c, static_cast<char*>(c->scratch_dev), p);
+    return lm_step_dispatch(*c, rep);
+  });
 }
 
 ba_status ba_solve(ba_ctx* c, ba_solve_report* rep) {
