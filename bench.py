@@ -122,6 +122,7 @@ def run_gpu(sc, precision, steps, warmup, args, torch, timing):
         ba.set_depth_priors(t(sc.depth, torch.float32), t(sc.depth_valid, torch.uint8),
                             sc.lambda_d)
     step = ba.gp_step if args.gp else ba.lm_step
+    min_free = torch.cuda.mem_get_info()[0]
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
@@ -130,12 +131,16 @@ def run_gpu(sc, precision, steps, warmup, args, torch, timing):
     t0 = time.perf_counter()
     for _ in range(steps):
         reps.append(step())
+        if timing:   # device memory in use (hipMemGetInfo), sampled after every step
+            min_free = min(min_free, torch.cuda.mem_get_info()[0])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     stats = ba.kernel_stats()
     mem = ba.device_bytes()
+    total = torch.cuda.mem_get_info()[1]
     ba.close()
-    return dict(seconds=dt, reports=reps, stats=stats, device_bytes=mem)
+    return dict(seconds=dt, reports=reps, stats=stats, device_bytes=mem,
+                device_used_peak=total - min_free)
 
 
 def forward_adjoint(sc, iters, args, torch):
@@ -462,6 +467,7 @@ def main():
         ins = run_gpu(sc, p, args.steps, args.warmup, args, torch, timing=1)
         summ = summarize(res, sc.n_obs)
         summ.update(kernel_summary(ins))
+        summ["device_used_peak_gb"] = ins["device_used_peak"] / 1e9   # whole process
         summ["same_steps"] = ([r["cost_before"] for r in res["reports"]] ==
                               [r["cost_before"] for r in ins["reports"]])
         out[p] = (ins, summ)

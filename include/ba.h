@@ -55,7 +55,11 @@ typedef int32_t ba_status;
 
 #define BA_PRECISION_FP64 0  /* every stage in float64 */
 #define BA_PRECISION_MIXED 1 /* float32 Jacobians, J^T J blocks and PCG matvecs; float64
-                                PCG dots and norms, cost, gain ratio, 3x3 inversions */
+                                PCG dots and norms, cost, gain ratio, 3x3 inversions. The LM
+                                damping stays at or above max(lambda_min, 1e-5): a smaller
+                                Marquardt damping is lost in the float32 rounding of the
+                                damped blocks, whose reduced system then turns singular or
+                                indefinite at float32 resolution (PCG breakdown) */
 
 #define BA_ACTIVITY_ROWS 0    /* point active with >= 3 residual rows, camera with >= 6
                                  (rows: 2 per observation, +1 with a valid depth prior) */
@@ -69,6 +73,14 @@ typedef int32_t ba_status;
                                  S_ij = -sum_p W_ip V*_p^-1 W_jp^T, per iteration one sparse
                                  block product. The adjoint always runs matrix-free */
 
+#define BA_ADJOINT_FULL 0          /* the exact Hessian of the cost at the solution: the
+                                      robust-corrected Gauss-Newton blocks plus, per
+                                      observation, the curvature of its residual rows weighted
+                                      by rho' e and the second-order part of the SE(3)
+                                      retraction (the implicit derivative itself) */
+#define BA_ADJOINT_GAUSS_NEWTON 1  /* sum J^T (rho' I + 2 rho'' e e^T) J only: drops those
+                                      terms, which vanish with the residuals */
+
 typedef struct ba_options {
   int32_t precision;       /* BA_PRECISION_*; default MIXED */
   int32_t img_w, img_h;    /* frustum for the validity test; default 640 x 480 */
@@ -77,7 +89,7 @@ typedef struct ba_options {
   double huber_px;         /* Huber threshold on the stacked residual norm; <= 0: L2 */
   double filter_px;        /* validity needs 2-D reprojection error <= filter_px; <= 0 off */
   double lambda_init;      /* initial LM damping; 1e-3 */
-  double lambda_min, lambda_max; /* damping clamp; 1e-12, 1e12 */
+  double lambda_min, lambda_max; /* damping clamp; 1e-12, 1e12 (MIXED: at least 1e-5) */
   double diag_min, diag_max;     /* clamp of the Marquardt diagonal diag(J^T J); 1e-6, 1e32 */
   double accept_ratio;     /* accept a step when the cost drops and gain ratio > this; 1e-3 */
   int32_t pcg_max_iters;   /* 100 */
@@ -95,6 +107,7 @@ typedef struct ba_options {
                               7 x 7 camera blocks, de/df = (x/z, y/z, 0), additive update, a
                               camera needs 7 residual rows; cx, cy stay fixed. The adjoint
                               needs it off. Default 0 */
+  int32_t adjoint_hessian; /* BA_ADJOINT_*: the Hessian of the adjoint system; default FULL */
   double adjoint_rel_tol;  /* PCG tolerance of the adjoint solve; 1e-10 */
   double adjoint_damping;  /* Tikhonov damping of the adjoint system, added as
                               lambda clamp(diag H) like the LM damping: 0 (the exact implicit
@@ -258,9 +271,12 @@ ba_status ba_get_normal_blocks(const ba_ctx* ctx, double* U, double* gc, double*
 
 /* Implicit adjoint of the current (converged) solution: given dL/dcams (C x 7) and
  * dL/dpoints (P x 3), write dL/dxy (N x 2 float32) and dL/ddepth (N float32, zeros without
- * depth rows). Solves H v = dL/dtheta with H = sum J^T M J, M = rho' I + 2 rho'' e e^T, by
- * the same Schur-PCG, then maps v per observation. Needs at least one fixed camera and a
- * fixed scale (depth rows with lambda_d > 0, or two fixed cameras): BA_ERR_STATE otherwise.
+ * depth rows). Solves H v = dL/dtheta by the same Schur-PCG, with H the exact Hessian of the
+ * cost (adjoint_hessian = BA_ADJOINT_FULL) or its robust-corrected Gauss-Newton part
+ * sum J^T M J, M = rho' I + 2 rho'' e e^T (BA_ADJOINT_GAUSS_NEWTON), then maps v per
+ * observation (implicit function theorem on the vanishing gradient at the solution). Needs at
+ * least one fixed camera and a fixed scale (depth rows with lambda_d > 0, or two fixed
+ * cameras): BA_ERR_STATE otherwise.
  * Inactive observations get zero gradients. Returns BA_NOT_CONVERGED when the PCG stopped at
  * adjoint_max_iters above adjoint_rel_tol (gradients written from the last iterate). */
 ba_status ba_adjoint(ba_ctx* ctx, const double* grad_cams, const double* grad_points,

@@ -28,6 +28,8 @@ BA_PRECISION_FP64 = 0
 BA_PRECISION_MIXED = 1
 BA_ACTIVITY_ROWS = 0
 BA_ACTIVITY_LITERAL = 1
+BA_ADJOINT_FULL = 0
+BA_ADJOINT_GAUSS_NEWTON = 1
 
 
 class BaOptions(Structure):
@@ -39,7 +41,7 @@ class BaOptions(Structure):
         ("accept_ratio", c_double), ("pcg_max_iters", c_int32), ("pcg_check_every", c_int32),
         ("pcg_rel_tol", c_double), ("cost_rel_tol", c_double), ("grad_tol", c_double),
         ("max_lm_iters", c_int32), ("timing", c_int32), ("adjoint_max_iters", c_int32),
-        ("solver", c_int32), ("refine_focal", c_int32),
+        ("solver", c_int32), ("refine_focal", c_int32), ("adjoint_hessian", c_int32),
         ("adjoint_rel_tol", c_double), ("adjoint_damping", c_double), ("gp_huber", c_double),
         ("hip_stream", c_void_p),
     ]

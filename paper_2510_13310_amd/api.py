@@ -237,6 +237,7 @@ def ba_destroy(ctx: int) -> None:
 _PRECISION = {"fp64": 0, "mixed": 1}
 _RULE = {"rows": 0, "literal": 1}
 _SOLVER = {"implicit": 0, "explicit": 1}
+_ADJ_HESSIAN = {"full": 0, "gauss_newton": 1}
 
 
 def make_options(precision="mixed", **kw) -> BaOptions:
@@ -246,6 +247,8 @@ def make_options(precision="mixed", **kw) -> BaOptions:
         kw["activity_rule"] = _RULE[kw["activity_rule"]]
     if "solver" in kw and isinstance(kw["solver"], str):
         kw["solver"] = _SOLVER[kw["solver"]]
+    if "adjoint_hessian" in kw and isinstance(kw["adjoint_hessian"], str):
+        kw["adjoint_hessian"] = _ADJ_HESSIAN[kw["adjoint_hessian"]]
     if "stream" in kw:
         kw["hip_stream"] = kw.pop("stream")
     names = {f for f, _ in BaOptions._fields_}

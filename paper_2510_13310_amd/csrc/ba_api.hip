@@ -175,6 +175,8 @@ struct ba_ctx {
 
   // precision-typed buffers (float in MIXED, double in FP64)
   void *cm_e = nullptr, *prec = nullptr;
+  void *ce = nullptr, *cm_ce = nullptr;   // rho' e per observation (full-Hessian adjoint)
+  bool ce_on = false;                     // set while the full-Hessian adjoint runs
   void *w = nullptr, *eh = nullptr, *xcw = nullptr, *pm_xcw = nullptr, *cm_eh = nullptr,
        *V = nullptr, *Vinv = nullptr, *zq = nullptr, *Ustar = nullptr, *mvt = nullptr;
   double *gp = nullptr, *hp = nullptr, *dp = nullptr, *Xcand = nullptr, *rhs_p = nullptr;
@@ -461,6 +463,8 @@ void alloc_obs_buffers(ba_ctx& c) {
                                                              : nullptr;
   c.eh = nullptr;
   c.cm_eh = nullptr;
+  c.ce = nullptr;
+  c.cm_ce = nullptr;
   c.gp_s = nullptr;
   c.gp_ready = false;
   c.V = A.alloc<char>(sizeof(double) * 6 * P);
@@ -508,6 +512,8 @@ void ensure_adjoint_buffers(ba_ctx& c) {
   const size_t ts = c.tsize();
   c.eh = c.obs.alloc<char>(ts * 3 * size_t(c.N));
   c.cm_eh = c.obs.alloc<char>(ts * 3 * size_t(c.N));
+  c.ce = c.obs.alloc<char>(ts * 3 * size_t(c.N));
+  c.cm_ce = c.obs.alloc<char>(ts * 3 * size_t(c.N));
   c.grad_cams_d = c.obs.alloc<double>(7 * size_t(c.C));
   c.grad_pts_d = c.obs.alloc<double>(3 * size_t(c.P));
   c.gxy_d = c.obs.alloc<float>(2 * size_t(c.N));
@@ -549,6 +555,8 @@ ObsMetric<T> metric_view(ba_ctx& c) {
   om.pm_xcw = static_cast<V4<T>*>(c.pm_xcw);
   om.eh = static_cast<T*>(c.eh);
   om.cm_eh = static_cast<T*>(c.cm_eh);
+  om.ce = c.ce_on ? static_cast<T*>(c.ce) : nullptr;
+  om.cm_ce = c.ce_on ? static_cast<T*>(c.cm_ce) : nullptr;
   return om;
 }
 
@@ -662,6 +670,18 @@ double bytes_pcg_update(const ba_ctx& c) {
   return double(c.Ca) * (2 * 3 * 8 + 4 + ns * 8 + ns * ts + 2 * 6 * D * 8 + D * ts) +
          double(c.Ca + nch) * (D + 1) * 8;
 }
+// Smallest LM damping. In mixed precision the damped blocks U*, V*^-1 and the matvec are
+// float32: a Marquardt damping of the order of their rounding (6e-8) amplified by the
+// summation over a camera's observations is lost, the damped reduced system is then singular
+// or indefinite at float32 resolution along its weakest directions (the gauge, the depth of
+// far points), and its PCG diverges into non-positive curvature. Mixed precision therefore
+// keeps the damping at 1e-5 or more; float64 uses lambda_min as given.
+constexpr double kMixedLambdaFloor = 1e-5;
+double lambda_floor(const ba_ctx& c) {
+  return c.opt.precision == BA_PRECISION_MIXED ? std::max(c.opt.lambda_min, kMixedLambdaFloor)
+                                               : c.opt.lambda_min;
+}
+
 int lanes_per_point(const ba_ctx& c) {
   const double mean = c.Pa > 0 ? double(c.Nh) / c.Pa : 1.0;
   return mean <= 2.5 ? 2 : mean <= 4.5 ? 4 : mean <= 9.0 ? 8 : 16;
@@ -945,6 +965,7 @@ void backsub(ba_ctx& c, bool adj, const double* rhs_p) {
 template <typename T>
 ba_status lm_step_impl(ba_ctx& c, ba_step_report* rep) {
   const double t0 = now_ms();
+  c.lam = std::max(c.lam, lambda_floor(c));
   ba_step_report R;
   std::memset(&R, 0, sizeof(R));
   R.pcg_true_residual = -1.0;
@@ -1058,7 +1079,7 @@ ba_status lm_step_impl(ba_ctx& c, ba_step_report* rep) {
     });
     c.lin_valid = false;
     const double f = std::max(1.0 / 3.0, 1.0 - std::pow(2.0 * ratio - 1.0, 3));
-    c.lam = std::max(c.opt.lambda_min, std::min(c.opt.lambda_max, c.lam * f));
+    c.lam = std::max(lambda_floor(c), std::min(c.opt.lambda_max, c.lam * f));
     c.nu = 2.0;
   } else {
     c.lam = std::min(c.lam * c.nu, c.opt.lambda_max);
@@ -1174,6 +1195,7 @@ ba_status gp_step_impl(ba_ctx& c, ba_step_report* rep) {
   std::memset(&R, 0, sizeof(R));
   R.pcg_true_residual = -1.0;
   if (!c.gp_ready) gp_init(c);
+  c.gp_lam = std::max(c.gp_lam, lambda_floor(c));
   R.lambda = c.gp_lam;
   hipStream_t s = c.stream;
   const double ts = double(sizeof(T));
@@ -1298,7 +1320,7 @@ ba_status gp_step_impl(ba_ctx& c, ba_step_report* rep) {
     });
     c.gp_lin_valid = false;
     const double f = std::max(1.0 / 3.0, 1.0 - std::pow(2.0 * ratio - 1.0, 3));
-    c.gp_lam = std::max(c.opt.lambda_min, std::min(c.opt.lambda_max, c.gp_lam * f));
+    c.gp_lam = std::max(lambda_floor(c), std::min(c.opt.lambda_max, c.gp_lam * f));
     c.gp_nu = 2.0;
   } else {
     c.gp_lam = std::min(c.gp_lam * c.gp_nu, c.opt.lambda_max);
@@ -1326,6 +1348,12 @@ bool adjoint_impl(ba_ctx& c, const double* grad_cams, const double* grad_points,
   bool converged = true;
   hipStream_t s = c.stream;
   ensure_adjoint_buffers(c);
+  // the full Hessian's terms are read by the adjoint-mode kernels while this call runs
+  struct CeScope {
+    ba_ctx& c;
+    CeScope(ba_ctx& cc, bool on) : c(cc) { c.ce_on = on; }
+    ~CeScope() { c.ce_on = false; }
+  } ce_scope(c, c.opt.adjoint_hessian == BA_ADJOINT_FULL);
   c.to_device(c.grad_cams_d, grad_cams, sizeof(double) * 7 * size_t(c.C));
   c.to_device(c.grad_pts_d, grad_points, sizeof(double) * 3 * size_t(c.P));
   HIP_CHECK(hipMemsetAsync(c.gxy_d, 0, sizeof(float) * 2 * size_t(c.N), s));
@@ -1500,6 +1528,7 @@ void ba_default_options(ba_options* o) {
   o->refine_focal = 0;
   o->gp_huber = 0.1;
   o->solver = BA_SOLVER_IMPLICIT;
+  o->adjoint_hessian = BA_ADJOINT_FULL;
   o->adjoint_rel_tol = 1e-10;
   o->hip_stream = nullptr;
 }
@@ -1531,6 +1560,7 @@ ba_status ba_create(const ba_options* opt, int32_t n_cams, int32_t n_points, con
       !(o.adjoint_damping >= 0) || (o.refine_focal != 0 && o.refine_focal != 1) ||
       !std::isfinite(o.gp_huber) ||
       (o.solver != BA_SOLVER_IMPLICIT && o.solver != BA_SOLVER_EXPLICIT) ||
+      (o.adjoint_hessian != BA_ADJOINT_FULL && o.adjoint_hessian != BA_ADJOINT_GAUSS_NEWTON) ||
       !(o.adjoint_rel_tol >= 0)) {
     g_create_error = "invalid options";
     return BA_ERR_ARG;

@@ -164,6 +164,9 @@ struct ObsMetric {
   V4<T>* xcw;    // Nc: camera-frame point and w, camera-major order
   V4<T>* cm_e;   // Nc: residual e (3, w slot unused) at the linearisation point, camera-major
   T* cm_eh;      // Nc x 3 (adjoint only)
+  T* ce;         // Nh x 3: c = rho' e (adjoint with the full Hessian only, else nullptr): the
+                 //     second-order residual and retraction terms of the exact Hessian
+  T* cm_ce;      // Nc x 3: the same, camera-major
 };
 
 // Point data the camera assembly gathers once per observation, packed in one record.

@@ -215,6 +215,38 @@ struct AMat<T, true> {
   }
 };
 
+// Second-order terms of one observation in the exact Hessian of its cost (the adjoint with
+// the full Hessian). With c = rho' e (the observation's cost gradient with respect to its
+// residual), a = A^T c is its gradient with respect to X_c (A = de/dX_c, not projected), and
+// S = sum_i c_i d^2 e_i / dX_c^2 is the curvature of the pinhole and inverse-depth rows:
+//   S02 = -c0 f / z^2, S12 = -c1 f / z^2, S22 = 2 (f (c0 x + c1 y) + lam_d c2) / z^3.
+// Together with the second-order part of the left SE(3) retraction of X_c,
+// (1/2) [phi]x^2 X_c + [phi]x R dX + (1/2) [phi]x rho, they add to the observation's block:
+//   camera-camera  J_c^T S J_c + [[0, [a]x/2], [-[a]x/2, (a X^T + X a^T)/2 - (a.X) I]],
+//   camera-point   J_c^T S R + [0 ; -[a]x R],   point-point  R^T S R.
+template <typename T>
+struct Curv {
+  T a[3];
+  T s02, s12, s22;
+  __device__ __forceinline__ void set(T f, T lam_d, const T Xc[3], const T c[3]) {
+    const T iz = T(1) / Xc[2];
+    const T fz = f * iz;
+    const T cxy = c[0] * Xc[0] + c[1] * Xc[1];
+    a[0] = fz * c[0];
+    a[1] = fz * c[1];
+    a[2] = -fz * iz * cxy - lam_d * iz * iz * c[2];
+    s02 = -c[0] * fz * iz;
+    s12 = -c[1] * fz * iz;
+    s22 = T(2) * iz * iz * (fz * cxy + lam_d * c[2] * iz);
+  }
+  // m += S d
+  __device__ __forceinline__ void add_s(const T d[3], T m[3]) const {
+    m[0] += s02 * d[2];
+    m[1] += s12 * d[2];
+    m[2] += s02 * d[0] + s12 * d[1] + s22 * d[2];
+  }
+};
+
 // Huber on the squared norm s: rho, rho', rho''.
 __device__ __forceinline__ void huber(double s, double delta, double& rho, double& d1,
                                       double& d2) {
@@ -565,6 +597,26 @@ k_lin_point(Model m, Compact<T> cp, ObsMetric<T> om, double* __restrict__ V,
             om.cm_eh[3 * ic + 1] = T(eh[1]);
             om.cm_eh[3 * ic + 2] = T(eh[2]);
           }
+          if (om.ce) {   // full Hessian: c = rho' e, and V += R^T S R (float64 here)
+            const double c3[3] = {w * e[0], w * e[1], w * e[2]};
+#pragma unroll
+            for (int i = 0; i < 3; ++i) om.ce[3 * j + i] = T(c3[i]);
+            if (ic >= 0) {
+#pragma unroll
+              for (int i = 0; i < 3; ++i) om.cm_ce[3 * ic + i] = T(c3[i]);
+            }
+            Curv<double> K;
+            K.set(cm.f, m.lam_d, Xc, c3);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {   // column q of R, then S times it
+              const double rq[3] = {cm.R[q], cm.R[3 + q], cm.R[6 + q]};
+              double sr[3] = {0.0, 0.0, 0.0};
+              K.add_s(rq, sr);
+#pragma unroll
+              for (int p2 = 0; p2 <= q; ++p2)
+                v[sym3(p2, q)] += cm.R[p2] * sr[0] + cm.R[3 + p2] * sr[1] + cm.R[6 + p2] * sr[2];
+            }
+          }
           A.project(eh);
         }
   #pragma unroll
@@ -766,6 +818,60 @@ k_cam_assemble(Model m, Compact<T> cp, ObsMetric<T> om, double lam, double dmin,
         const double we = double(wt) * e[row];
 #pragma unroll
         for (int p = 0; p < D; ++p) g6[p] += we * double(jc[p]);
+      }
+    }
+    if constexpr (ADJ) {
+      if (om.cm_ce) {   // full Hessian: the curvature and retraction terms (see Curv)
+        const T c3[3] = {om.cm_ce[3 * i], om.cm_ce[3 * i + 1], om.cm_ce[3 * i + 2]};
+        Curv<T> K;
+        K.set(T(cm.f), T(m.lam_d), Xt, c3);
+        // columns of dX_c / d(rho, phi): e_k, then e_k x X
+        T Jc[6][3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const T ek[3] = {T(k == 0), T(k == 1), T(k == 2)};
+          Jc[k][0] = ek[0]; Jc[k][1] = ek[1]; Jc[k][2] = ek[2];
+          cross3(ek, Xt, Jc[3 + k]);
+        }
+        T SJ[6][3];
+#pragma unroll
+        for (int p = 0; p < 6; ++p) {
+          SJ[p][0] = SJ[p][1] = SJ[p][2] = T(0);
+          K.add_s(Jc[p], SJ[p]);
+        }
+#pragma unroll
+        for (int p = 0; p < 6; ++p) {
+#pragma unroll
+          for (int q = p; q < 6; ++q)
+            U[symd<D>(p, q)] += Jc[p][0] * SJ[q][0] + Jc[p][1] * SJ[q][1] + Jc[p][2] * SJ[q][2];
+        }
+        // retraction terms: rho-phi [a]x / 2, phi-phi (a X^T + X a^T) / 2 - (a.X) I
+        const T* a = K.a;
+        const T ax[3][3] = {{T(0), -a[2], a[1]}, {a[2], T(0), -a[0]}, {-a[1], a[0], T(0)}};
+        const T aX = a[0] * Xt[0] + a[1] * Xt[1] + a[2] * Xt[2];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+#pragma unroll
+          for (int l = 0; l < 3; ++l) U[symd<D>(k, 3 + l)] += T(0.5) * ax[k][l];
+#pragma unroll
+          for (int l = k; l < 3; ++l)
+            U[symd<D>(3 + k, 3 + l)] +=
+                T(0.5) * (a[k] * Xt[l] + Xt[k] * a[l]) - (k == l ? aX : T(0));
+        }
+        // camera-point: J_c^T S R + [0 ; -[a]x R]
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const T rq[3] = {T(cm.R[q]), T(cm.R[3 + q]), T(cm.R[6 + q])};
+          T sr[3] = {T(0), T(0), T(0)};
+          K.add_s(rq, sr);
+          T axr[3];
+          cross3(a, rq, axr);
+#pragma unroll
+          for (int p = 0; p < 6; ++p)
+            W[3 * p + q] += Jc[p][0] * sr[0] + Jc[p][1] * sr[1] + Jc[p][2] * sr[2];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) W[3 * (3 + k) + q] -= axr[k];
+        }
       }
     }
     // W Vinv W^T and W hp
@@ -1027,6 +1133,17 @@ __device__ __forceinline__ void schur_point_one(const Model& m, const Compact<T>
     }
     A.applyT(tt, mm);
     mm[0] *= wj; mm[1] *= wj; mm[2] *= wj;
+    if constexpr (ADJ) {
+      if (om.ce) {   // full Hessian: + S d + a x u_phi (see Curv)
+        const T c3[3] = {om.ce[3 * j], om.ce[3 * j + 1], om.ce[3 * j + 2]};
+        Curv<T> K;
+        K.set(mc.f, T(m.lam_d), Xc, c3);
+        K.add_s(d, mm);
+        T au[3];
+        cross3(K.a, w3, au);
+        mm[0] += au[0]; mm[1] += au[1]; mm[2] += au[2];
+      }
+    }
     // R^T m
     y[0] += mc.R[0] * mm[0] + mc.R[3] * mm[1] + mc.R[6] * mm[2];
     y[1] += mc.R[1] * mm[0] + mc.R[4] * mm[1] + mc.R[7] * mm[2];
@@ -1212,9 +1329,19 @@ k_schur_cam(Model m, Compact<T> cp, ObsMetric<T> om, const double* __restrict__ 
     if constexpr (D == 7)   // focal column: w (x/z, y/z, 0) . t
       acc[6] += xw.w * (Xc[0] * t[0] + Xc[1] * t[1]) / Xc[2];
     mm[0] *= xw.w; mm[1] *= xw.w; mm[2] *= xw.w;
+    T ua[3] = {T(0), T(0), T(0)};
+    if constexpr (ADJ) {
+      if (om.cm_ce) {   // full Hessian: + S (R z), and (R z) x a in the rotation rows
+        const T c3[3] = {om.cm_ce[3 * k], om.cm_ce[3 * k + 1], om.cm_ce[3 * k + 2]};
+        Curv<T> K;
+        K.set(cm.f, T(m.lam_d), Xc, c3);
+        K.add_s(uu, mm);
+        cross3(uu, K.a, ua);
+      }
+    }
     cross3(Xc, mm, xm);
     acc[0] += mm[0]; acc[1] += mm[1]; acc[2] += mm[2];
-    acc[3] += xm[0]; acc[4] += xm[1]; acc[5] += xm[2];
+    acc[3] += xm[0] + ua[0]; acc[4] += xm[1] + ua[1]; acc[5] += xm[2] + ua[2];
   }
   block_sum<T, D>(acc, smem);
   if (threadIdx.x == 0) {
@@ -1466,6 +1593,17 @@ k_backsub(Model m, Compact<T> cp, ObsMetric<T> om, const T* __restrict__ Vinv,
       A.applyT(tt, mm);
       const T w = om.w[j];
       mm[0] *= w; mm[1] *= w; mm[2] *= w;
+      if constexpr (ADJ) {
+        if (om.ce) {   // full Hessian: + S d + a x x_phi (see Curv)
+          const T c3[3] = {om.ce[3 * j], om.ce[3 * j + 1], om.ce[3 * j + 2]};
+          Curv<T> K;
+          K.set(cm.f, T(m.lam_d), Xc, c3);
+          K.add_s(d, mm);
+          T au[3];
+          cross3(K.a, w3, au);
+          mm[0] += au[0]; mm[1] += au[1]; mm[2] += au[2];
+        }
+      }
       rot_tmul(cm, mm, rt);
       y[0] += rt[0]; y[1] += rt[1]; y[2] += rt[2];
     }

@@ -29,8 +29,8 @@ def test_every_declared_symbol_is_exported():
 
 def test_struct_sizes_match_header_layout():
     import ctypes
-    # ba_options: 4 int32, 9 doubles, 2 int32, 3 doubles, 5 int32 (+4 pad), 3 doubles, pointer
-    assert ctypes.sizeof(_abi.BaOptions) == 4 * 4 + 9 * 8 + 2 * 4 + 3 * 8 + 5 * 4 + 4 + 3 * 8 + 8
+    # ba_options: 4 int32, 9 doubles, 2 int32, 3 doubles, 6 int32, 3 doubles, pointer
+    assert ctypes.sizeof(_abi.BaOptions) == 4 * 4 + 9 * 8 + 2 * 4 + 3 * 8 + 6 * 4 + 3 * 8 + 8
     assert ctypes.sizeof(_abi.BaKernelStat) == 32 + 8 + 8 + 8
 
 
@@ -43,7 +43,7 @@ def test_default_options():
     assert o.diag_min == 1e-6 and o.lambda_max == 1e12
     assert o.adjoint_max_iters == 5000 and o.adjoint_rel_tol == 1e-10
     assert o.adjoint_damping == 0.0 and o.refine_focal == 0 and o.gp_huber == 0.1
-    assert o.solver == 0
+    assert o.solver == 0 and o.adjoint_hessian == 0
 
 
 def test_argument_errors_before_device():

@@ -5,10 +5,11 @@
   1e-5 of the largest gradient (the ABI returns float32 gradients), float64 path.
 * Against central differences of converged GPU re-solves on the medium scene (camera 0
   fixed, loss = sum of squared camera-centre errors): 50 coordinates (40 pixel, 10 depth),
-  steps 1e-3 px and 1e-4 d_hat, coordinates away from the Huber and filter thresholds.
-  Without noise the Gauss-Newton Hessian is exact at the optimum (bound 1e-3); with the
-  workload's noise it drops the second-derivative residual term, whose gap is measured and
-  printed (median bound 3e-2, max 0.25, relative to the largest gradient).
+  steps 1e-3 px and 1e-4 d_hat, coordinates away from the Huber and filter thresholds. The
+  full Hessian (default) is held to 1e-3 of the largest difference, noise-free or not; the
+  Gauss-Newton Hessian is exact only where the residuals vanish (noise-free: 1e-3) and its
+  gap on the noisy workload (the dropped second-order terms) is printed. On the noisy
+  workload the differences carry the LM re-solves' convergence floor (see the test).
 """
 from dataclasses import replace
 
@@ -44,29 +45,38 @@ def _loss(sc, cams, pts, W):
     return float(np.sum((cams[:, 4:7] - sc.cams_gt[:, 4:7]) ** 2) + np.sum(W * pts))
 
 
-def _oracle_at(sc, cams, pts, g_c, g_p):
+def _oracle_at(sc, cams, pts, g_c, g_p, hessian="gauss_newton"):
     prob = Problem.from_scene(sc)
     opts = Options(huber_px=sc.huber_px, filter_px=sc.filter_px)
     st = State(q=cams[:, :4].copy(), c=cams[:, 4:7].copy(), X=pts.copy(), lam=0.0)
-    gxy, gd, _ = oracle_adjoint(prob, st, opts, g_c, g_p)
+    gxy, gd, _ = oracle_adjoint(prob, st, opts, g_c, g_p, hessian=hessian)
     return gxy, gd, extract(prob, st, opts)
 
 
-@pytest.mark.parametrize("which", ["tiny-exact-priors", "adjoint-sub-cams0-9"])
-def test_adjoint_matches_oracle_direct_solve(which):
+@pytest.mark.parametrize("which,hessian", [
+    ("tiny-exact-priors", "gauss_newton"), ("adjoint-sub-cams0-9", "gauss_newton"),
+    ("tiny-exact-priors", "full"), ("adjoint-sub-cams0-9-small", "full")])
+def test_adjoint_matches_oracle_direct_solve(which, hessian):
+    """Both Hessians against the oracle's direct solve at the GPU's converged parameters: the
+    Gauss-Newton one against the oracle's sparse robust-corrected system, the full one
+    against the oracle's dense Hessian from central differences of the exact gradient
+    (pinned on the CPU by differences of exact re-solves), on sub-scenes small enough for a
+    dense Hessian."""
     rng = np.random.default_rng(3)
     if which == "tiny-exact-priors":
         sc = make_scene("tiny", n_points=150, noise_px=0.5, prior_frac=0.7, use_depth=True,
                         lambda_d=30.0)
         sc = replace(sc, fixed=np.array([0], np.int32))
-    else:
+    elif which == "adjoint-sub-cams0-9":
         sc = subscene(make_scene("adjoint"), np.arange(10), max_points=1500, seed=1)
-    ba = gpu_setup(sc, "fp64", **SOLVE)
+    else:
+        sc = subscene(make_scene("adjoint"), np.arange(10), max_points=300, seed=1)
+    ba = gpu_setup(sc, "fp64", adjoint_hessian=hessian, **SOLVE)
     ba.solve()
     cams, pts = ba.get_params()
     g_c, g_p = _loss_grads(sc, cams, pts, rng)
     gxy, gd = ba.adjoint(g_c, g_p)
-    ogxy, ogd, ex = _oracle_at(sc, cams, pts, g_c, g_p)
+    ogxy, ogd, ex = _oracle_at(sc, cams, pts, g_c, g_p, hessian)
     _, _, act = ba.get_active()
     np.testing.assert_array_equal(act, ex.obs_active)
     scale = max(np.abs(ogxy).max(), np.abs(ogd).max())
@@ -77,7 +87,7 @@ def test_adjoint_matches_oracle_direct_solve(which):
         from oracle.model import residuals
         e, _, _ = residuals(prob, cams[:, :4], cams[:, 4:], pts, ex.obs)
         huber_obs = int(np.sum(np.sum(e * e, axis=1) > sc.huber_px ** 2))
-    print(f"{which}: adjoint vs oracle direct solve, max rel error {err:.3e} "
+    print(f"{which} ({hessian}): adjoint vs oracle direct solve, max rel error {err:.3e} "
           f"({ex.obs.size} active observations, {huber_obs} in the Huber regime)")
     assert err < 1e-5, err
     assert np.all(gxy[~act] == 0) and np.all(gd[~act] == 0)
@@ -85,10 +95,11 @@ def test_adjoint_matches_oracle_direct_solve(which):
 
 def test_damped_adjoint_matches_oracle():
     """adjoint_damping > 0: the GPU's damped Schur/PCG solve against the oracle's damped
-    direct solve (same Marquardt diagonal), float64, 1e-5 of the largest gradient."""
+    direct solve (same Marquardt diagonal, Gauss-Newton Hessian), float64, 1e-5 of the
+    largest gradient."""
     rng = np.random.default_rng(9)
     sc = subscene(make_scene("adjoint"), np.arange(10), max_points=1500, seed=1)
-    ba = gpu_setup(sc, "fp64", adjoint_damping=1e-2, **SOLVE)
+    ba = gpu_setup(sc, "fp64", adjoint_damping=1e-2, adjoint_hessian="gauss_newton", **SOLVE)
     ba.solve()
     cams, pts = ba.get_params()
     g_c, g_p = _loss_grads(sc, cams, pts, rng)
@@ -118,8 +129,22 @@ def test_adjoint_mixed_precision_close_to_fp64():
     out = bm.adjoint(g_c, g_p)
     scale = max(np.abs(ref[0]).max(), np.abs(ref[1]).max())
     err = max(np.abs(out[0] - ref[0]).max(), np.abs(out[1] - ref[1]).max()) / scale
-    print(f"mixed vs fp64 adjoint: max rel error {err:.3e}")
-    assert err < 1e-2, err
+    # the mixed solve applies a float32 operator: its relative error (a few float32 roundings,
+    # 6e-8 each) is amplified by the condition number of the diagonally scaled system, which
+    # the block-Jacobi PCG sees
+    prob = Problem.from_scene(sc)
+    opts = Options(huber_px=sc.huber_px, filter_px=sc.filter_px)
+    st = State(q=cams[:, :4].copy(), c=cams[:, 4:7].copy(), X=pts.copy(), lam=0.0)
+    from oracle.lm import linearize, normal_equations
+    ex = extract(prob, st, opts)
+    H = normal_equations(linearize(prob, st, ex, opts.huber_px), robust_correction=True)[0]
+    H = H.toarray()
+    dsc = 1.0 / np.sqrt(np.diag(H))
+    ev = np.linalg.eigvalsh(H * dsc[:, None] * dsc[None, :])
+    bound = 2 * (ev[-1] / ev[0]) * 6e-8
+    print(f"mixed vs fp64 adjoint: max rel error {err:.3e} (bound 2 x cond {ev[-1] / ev[0]:.3e}"
+          f" x 6e-8 = {bound:.3e})")
+    assert err < bound, (err, bound)
 
 
 def _pick_coords(sc, cams, pts, act, rng, n_xy=40, n_d=10, margin=0.05):
@@ -142,7 +167,10 @@ def _pick_coords(sc, cams, pts, act, rng, n_xy=40, n_d=10, margin=0.05):
     return [(int(k), int(rng.integers(2))) for k in xy_k] + [(int(k), 2) for k in d_k]
 
 
-def _fd_check(sc, rng, tag):
+def _fd_check(sc, rng, tag, h_px=1e-3, h_rel=1e-4):
+    """Central differences of converged GPU re-solves against the full-Hessian and the
+    Gauss-Newton adjoints at the same solution, steps h_px for pixels and h_rel d_hat for
+    depths. Returns the two errors relative to the largest difference."""
     ba = gpu_setup(sc, "fp64", **FD_SOLVE)
     srep = ba.solve()
     cams0, pts0 = ba.get_params()
@@ -150,10 +178,13 @@ def _fd_check(sc, rng, tag):
     g_c = np.zeros_like(cams0)
     g_c[:, 4:7] = 2.0 * (cams0[:, 4:7] - sc.cams_gt[:, 4:7])
     gxy, gd = ba.adjoint(g_c, np.zeros_like(pts0))
+    bg = gpu_setup(sc, "fp64", adjoint_hessian="gauss_newton", **FD_SOLVE)
+    bg.set_params(cams0, pts0)
+    gxy_gn, gd_gn = bg.adjoint(g_c, np.zeros_like(pts0))
     coords = _pick_coords(sc, cams0, pts0, act, rng)
-    fds, refs = [], []
+    fds, refs, gns, same = [], [], [], []
     for k, j in coords:
-        h = 1e-3 if j < 2 else 1e-4 * float(sc.depth[k])
+        h = h_px if j < 2 else h_rel * float(sc.depth[k])
         vals = []
         for sgn in (1.0, -1.0):
             xy = sc.xy.copy()
@@ -169,39 +200,55 @@ def _fd_check(sc, rng, tag):
             ba.set_params(cams0, pts0)
             ba.solve()
             c1, p1 = ba.get_params()
-            vals.append((float(np.sum((c1[:, 4:7] - sc.cams_gt[:, 4:7]) ** 2)), step))
+            _, _, act1 = ba.get_active()
+            vals.append((float(np.sum((c1[:, 4:7] - sc.cams_gt[:, 4:7]) ** 2)), step,
+                         bool(np.array_equal(act1, act))))
         fds.append((vals[0][0] - vals[1][0]) / (vals[0][1] - vals[1][1]))
         refs.append(gxy[k, j] if j < 2 else gd[k])
-    fds, refs = np.array(fds), np.array(refs)
-    scale = np.max(np.abs(refs))
-    err = np.max(np.abs(fds - refs)) / scale
-    med = np.median(np.abs(fds - refs)) / scale
-    print(f"{tag}: adjoint vs central differences ({len(coords)} coordinates, "
-          f"{srep['iterations']} LM iterations in the base solve, stop {srep['stop_reason']}): "
-          f"max rel error {err:.3e}, median {med:.3e}")
-    return err, fds, refs
+        gns.append(gxy_gn[k, j] if j < 2 else gd_gn[k])
+        same.append(vals[0][2] and vals[1][2])
+    fds, refs, gns, same = np.array(fds), np.array(refs), np.array(gns), np.array(same)
+    scale = np.max(np.abs(fds[same]))
+    e_full = np.abs(fds - refs)[same] / scale
+    e_gn = np.abs(fds - gns)[same] / scale
+    print(f"{tag}: adjoint vs central differences ({same.sum()} of {len(coords)} coordinates "
+          f"whose re-solves keep the active set, {srep['iterations']} LM iterations in the base "
+          f"solve, stop {srep['stop_reason']}): full Hessian max {e_full.max():.3e} median "
+          f"{np.median(e_full):.3e}; Gauss-Newton max {e_gn.max():.3e} median "
+          f"{np.median(e_gn):.3e} (relative to the largest difference); where a re-solve "
+          f"changes the active set: {np.abs(fds - refs)[~same] / scale}")
+    return e_full, e_gn
 
 
 def test_adjoint_finite_differences_noise_free_scene():
     """The adjoint workload without pixel noise, outliers or depth-prior noise: residuals
-    vanish at the optimum, the Gauss-Newton Hessian is exact there, and the implicit
-    gradient must match central differences of converged re-solves closely."""
+    vanish at the optimum, so both Hessians are exact there and the implicit gradient must
+    match central differences of converged re-solves closely."""
     sc = make_scene("adjoint", noise_px=0.0, outlier_frac=0.0, all_outlier_points=0,
                     depth_sigma=0.0)
-    err, fds, refs = _fd_check(sc, np.random.default_rng(7), "noise-free adjoint scene")
-    assert err < 1e-3, np.c_[fds, refs]
+    e_full, e_gn = _fd_check(sc, np.random.default_rng(7), "noise-free adjoint scene")
+    assert e_full.max() < 1e-3 and e_gn.max() < 1e-3, (e_full, e_gn)
 
 
 def test_adjoint_medium_finite_differences():
-    """The adjoint workload (medium scene, camera 0 fixed) with its noise and outliers. The
-    Gauss-Newton Hessian drops the second-order residual term; on this workload the gap is
-    about 1 % at the median and up to ~15 % on weakly determined coordinates (the oracle's
-    robust-metric pin shows the same few-percent gap on a small noisy scene). The bounds
-    below are that measured gap with margin."""
+    """The adjoint workload (medium scene, camera 0 fixed) with its noise and outliers, 50
+    coordinates. The implicit derivative holds while the active set stays the same; a
+    perturbation that moves another observation across the 4 px filter changes the problem
+    itself, so coordinates whose re-solves change the active set are reported and left out.
+
+    The differences are only as good as the re-solves. LM stops where its steps no longer
+    lower the cost measurably, which leaves the weakest directions determined to about 1e-5
+    (on the CPU, for the ten-camera sub-scene of this workload: Newton polishing moves the LM
+    solution by 1e-5, differences of LM re-solves miss the exact derivative by 4e-3 to 5e-2
+    at a 1e-3 px step, differences of Newton-polished re-solves match the full-Hessian adjoint
+    to 6e-7). Steps of 1e-2 px and 1e-3 d_hat shrink that floor's share tenfold while their own
+    truncation error stays near 1e-4; the bounds are median 5e-3 and max 5e-2 of the largest
+    difference for the full Hessian (the default). The Gauss-Newton gap is printed."""
     sc = make_scene("adjoint")
-    err, fds, refs = _fd_check(sc, np.random.default_rng(2510), "adjoint scene")
-    med = np.median(np.abs(fds - refs)) / np.max(np.abs(refs))
-    assert med < 0.03 and err < 0.25, np.c_[fds, refs]
+    e_full, e_gn = _fd_check(sc, np.random.default_rng(2510), "adjoint scene", 1e-2, 1e-3)
+    assert e_full.size >= 40
+    assert np.median(e_full) < 5e-3 and e_full.max() < 5e-2, e_full
+    assert e_gn.max() < 0.25, e_gn
 
 
 def test_autograd_function_backward_matches_adjoint():
