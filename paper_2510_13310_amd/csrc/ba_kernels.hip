@@ -62,6 +62,33 @@ __device__ __forceinline__ T wave_max(T v) {
   return v;
 }
 
+// Sum over aligned groups of G lanes (G = 1, 2, 4, 8 or 16), every lane of a group getting the
+// group's sum. float32 uses DPP lane moves within rows of 16 lanes (no trip through the LDS
+// crossbar): xor 1 and xor 2 by quad permutations, then the mirror within each 8 lanes and
+// within each 16 lanes; after the quad steps all lanes of a quad hold the quad's sum, so a
+// mirror pairs each lane with the other half. Every lane adds the same two operands (in
+// swapped order), so all lanes of a group hold the bitwise same sum. float64 uses shuffles.
+template <int Ctrl>
+__device__ __forceinline__ float dpp_move(float x) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), Ctrl, 0xF, 0xF, false));
+}
+template <int G>
+__device__ __forceinline__ float group_sum(float v) {
+  static_assert(G >= 1 && G <= 16 && (G & (G - 1)) == 0, "lane groups of 1 to 16");
+  if constexpr (G >= 2) v += dpp_move<0xB1>(v);    // quad_perm [1,0,3,2]
+  if constexpr (G >= 4) v += dpp_move<0x4E>(v);    // quad_perm [2,3,0,1]
+  if constexpr (G >= 8) v += dpp_move<0x141>(v);   // row_half_mirror
+  if constexpr (G >= 16) v += dpp_move<0x140>(v);  // row_mirror
+  return v;
+}
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
 // Sums K per-thread values over the block; the result is valid in thread 0.
 // smem holds K * (blockDim.x / 64) values.
 template <typename T, int K>
@@ -143,6 +170,13 @@ __device__ __forceinline__ void rot_tmul(const Cam<S>& cm, const T v[3], T o[3])
   o[2] = T(cm.R[2]) * v[0] + T(cm.R[5]) * v[1] + T(cm.R[8]) * v[2];
 }
 
+// 1 / z of a camera-frame depth (z > 0.1 wherever a Jacobian is formed): float32 takes the
+// hardware reciprocal (within 1 ulp) instead of the correctly rounded division sequence;
+// every float32 Jacobian row goes through AMat or Curv, so all float32 kernels use the same
+// value. float64 divides.
+__device__ __forceinline__ float recip(float z) { return __builtin_amdgcn_rcpf(z); }
+__device__ __forceinline__ double recip(double z) { return 1.0 / z; }
+
 // Rows of de/dX_c (3 x 3): pinhole rows (f/z)[1 0 -x/z], (f/z)[0 1 -y/z] and the
 // inverse-depth row [0 0 -lam_d/z^2]. The plain form keeps the five structural non-zeros;
 // the projected form (adjoint metric) is a full matrix (I - eh eh^T) A.
@@ -153,7 +187,7 @@ template <typename T>
 struct AMat<T, false> {
   T a00, a02, a11, a12, a22;
   __device__ __forceinline__ void set(T f, T lam_d, const T Xc[3]) {
-    const T iz = T(1) / Xc[2];
+    const T iz = recip(Xc[2]);
     a00 = f * iz;
     a11 = a00;
     a02 = -a00 * Xc[0] * iz;
@@ -182,7 +216,7 @@ template <typename T>
 struct AMat<T, true> {
   T a[9];
   __device__ __forceinline__ void set(T f, T lam_d, const T Xc[3]) {
-    const T iz = T(1) / Xc[2];
+    const T iz = recip(Xc[2]);
     const T fz = f * iz;
     a[0] = fz; a[1] = T(0); a[2] = -fz * Xc[0] * iz;
     a[3] = T(0); a[4] = fz; a[5] = -fz * Xc[1] * iz;
@@ -229,7 +263,7 @@ struct Curv {
   T a[3];
   T s02, s12, s22;
   __device__ __forceinline__ void set(T f, T lam_d, const T Xc[3], const T c[3]) {
-    const T iz = T(1) / Xc[2];
+    const T iz = recip(Xc[2]);
     const T fz = f * iz;
     const T cxy = c[0] * Xc[0] + c[1] * Xc[1];
     a[0] = fz * c[0];
@@ -639,12 +673,9 @@ k_lin_point(Model m, Compact<T> cp, ObsMetric<T> om, double* __restrict__ V,
       }
     }
 #pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) {
+    for (int i = 0; i < 6; ++i) v[i] = group_sum<G>(v[i]);
 #pragma unroll
-      for (int i = 0; i < 6; ++i) v[i] += __shfl_xor(v[i], o, kWave);
-#pragma unroll
-      for (int i = 0; i < 3; ++i) g[i] += __shfl_xor(g[i], o, kWave);
-    }
+    for (int i = 0; i < 3; ++i) g[i] = group_sum<G>(g[i]);
     if (live && l == 0) {
 #pragma unroll
       for (int i = 0; i < 6; ++i) V[6 * r + i] = v[i];
@@ -1093,6 +1124,47 @@ __device__ __forceinline__ void pt_load_first(const Compact<T>& cp, const ObsMet
   }
 }
 
+// One observation's term of y_p = sum_k R_k^T W_k (J_c u)_k, added to y: W = w A^T A with A
+// the rows of de/dX_c at X_c (projected in the adjoint metric; with the full Hessian, plus the
+// curvature and retraction terms of the observation j).
+template <typename T, bool ADJ, int D>
+__device__ __forceinline__ void point_obs_term(const Model& m, const ObsMetric<T>& om,
+                                               const MvRec<T, D>& mc, const T Xc[3], T wj,
+                                               int j, T y[3]) {
+  AMat<T, ADJ> A;
+  A.set(mc.f, T(m.lam_d), Xc);
+  if constexpr (ADJ) A.project(om.eh + 3 * j);
+  T o3[3], d[3], tt[3], mm[3];
+  const T w3[3] = {mc.u[3], mc.u[4], mc.u[5]};
+  cross3(w3, Xc, o3);
+  d[0] = mc.u[0] + o3[0];
+  d[1] = mc.u[1] + o3[1];
+  d[2] = mc.u[2] + o3[2];
+  A.apply(d, tt);
+  if constexpr (D == 7) {   // focal column (x/z, y/z, 0) times the focal unknown
+    const T uf = mc.u[6] / Xc[2];
+    tt[0] += Xc[0] * uf;
+    tt[1] += Xc[1] * uf;
+  }
+  A.applyT(tt, mm);
+  mm[0] *= wj; mm[1] *= wj; mm[2] *= wj;
+  if constexpr (ADJ) {
+    if (om.ce) {   // full Hessian: + S d + a x u_phi (see Curv)
+      const T c3[3] = {om.ce[3 * j], om.ce[3 * j + 1], om.ce[3 * j + 2]};
+      Curv<T> K;
+      K.set(mc.f, T(m.lam_d), Xc, c3);
+      K.add_s(d, mm);
+      T au[3];
+      cross3(K.a, w3, au);
+      mm[0] += au[0]; mm[1] += au[1]; mm[2] += au[2];
+    }
+  }
+  // R^T m
+  y[0] += mc.R[0] * mm[0] + mc.R[3] * mm[1] + mc.R[6] * mm[2];
+  y[1] += mc.R[1] * mm[0] + mc.R[4] * mm[1] + mc.R[7] * mm[2];
+  y[2] += mc.R[2] * mm[0] + mc.R[5] * mm[1] + mc.R[8] * mm[2];
+}
+
 // Every lane of a wave must call this together (shuffles); lanes with !live do nothing.
 template <typename T, bool ADJ, int G, int D>
 __device__ __forceinline__ void schur_point_one(const Model& m, const Compact<T>& cp,
@@ -1103,11 +1175,10 @@ __device__ __forceinline__ void schur_point_one(const Model& m, const Compact<T>
                                                 int l, const PtLoad<T>& p) {
   T y[3] = {T(0), T(0), T(0)};
   T vi[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
-  // y += R^T W (J_c u) for one observation: W = w A^T A, A the rows of de/dX_c
+  // y += R^T W (J_c u) for one observation
   auto obs = [&](int j, int s, const V4<T>& xw) {
     if (s >= cp.Ca) return;   // fixed camera: no column in the solve
     const MvRec<T, D> mc = tab[s];
-    const T wj = xw.w;
     T Xc[3];
     if constexpr (kFormXc<T>) {
       frame_t(mc.R, mc.c, p.X[0], p.X[1], p.X[2], Xc);
@@ -1116,38 +1187,7 @@ __device__ __forceinline__ void schur_point_one(const Model& m, const Compact<T>
       Xc[1] = xw.y;
       Xc[2] = xw.z;
     }
-    AMat<T, ADJ> A;
-    A.set(mc.f, T(m.lam_d), Xc);
-    if constexpr (ADJ) A.project(om.eh + 3 * j);
-    T o3[3], d[3], tt[3], mm[3];
-    const T w3[3] = {mc.u[3], mc.u[4], mc.u[5]};
-    cross3(w3, Xc, o3);
-    d[0] = mc.u[0] + o3[0];
-    d[1] = mc.u[1] + o3[1];
-    d[2] = mc.u[2] + o3[2];
-    A.apply(d, tt);
-    if constexpr (D == 7) {   // focal column (x/z, y/z, 0) times the focal unknown
-      const T uf = mc.u[6] / Xc[2];
-      tt[0] += Xc[0] * uf;
-      tt[1] += Xc[1] * uf;
-    }
-    A.applyT(tt, mm);
-    mm[0] *= wj; mm[1] *= wj; mm[2] *= wj;
-    if constexpr (ADJ) {
-      if (om.ce) {   // full Hessian: + S d + a x u_phi (see Curv)
-        const T c3[3] = {om.ce[3 * j], om.ce[3 * j + 1], om.ce[3 * j + 2]};
-        Curv<T> K;
-        K.set(mc.f, T(m.lam_d), Xc, c3);
-        K.add_s(d, mm);
-        T au[3];
-        cross3(K.a, w3, au);
-        mm[0] += au[0]; mm[1] += au[1]; mm[2] += au[2];
-      }
-    }
-    // R^T m
-    y[0] += mc.R[0] * mm[0] + mc.R[3] * mm[1] + mc.R[6] * mm[2];
-    y[1] += mc.R[1] * mm[0] + mc.R[4] * mm[1] + mc.R[7] * mm[2];
-    y[2] += mc.R[2] * mm[0] + mc.R[5] * mm[1] + mc.R[8] * mm[2];
+    point_obs_term<T, ADJ, D>(m, om, mc, Xc, xw.w, j, y);
   };
   if (live) {
     // loads needed only after the reduction, issued now to overlap the stream (float32: the
@@ -1171,12 +1211,9 @@ __device__ __forceinline__ void schur_point_one(const Model& m, const Compact<T>
       }
     }
   }
-#pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) {
-    y[0] += __shfl_xor(y[0], o, kWave);
-    y[1] += __shfl_xor(y[1], o, kWave);
-    y[2] += __shfl_xor(y[2], o, kWave);
-  }
+  y[0] = group_sum<G>(y[0]);
+  y[1] = group_sum<G>(y[1]);
+  y[2] = group_sum<G>(y[2]);
   // every lane of the group now holds y; each computes z and stores its observations' copies
   // (pm_cm is -1 for an observation of a fixed camera)
   if (live) {
@@ -1608,12 +1645,9 @@ k_backsub(Model m, Compact<T> cp, ObsMetric<T> om, const T* __restrict__ Vinv,
       y[0] += rt[0]; y[1] += rt[1]; y[2] += rt[2];
     }
   }
-#pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) {
-    y[0] += __shfl_xor(y[0], o, kWave);
-    y[1] += __shfl_xor(y[1], o, kWave);
-    y[2] += __shfl_xor(y[2], o, kWave);
-  }
+  y[0] = group_sum<G>(y[0]);
+  y[1] = group_sum<G>(y[1]);
+  y[2] = group_sum<G>(y[2]);
   if (r < cp.Pa && l == 0) {
     double b[3];
     for (int i = 0; i < 3; ++i)
@@ -2234,10 +2268,7 @@ k_gp_lin(Compact<T> cp, const int* __restrict__ orig, const double* __restrict__
       }
     }
 #pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) {
-#pragma unroll
-      for (int i = 0; i < 3; ++i) g[i] += __shfl_xor(g[i], o, kWave);
-    }
+    for (int i = 0; i < 3; ++i) g[i] = group_sum<G>(g[i]);
     if (live && l == 0) {
       gX[3 * r] = g[0];
       gX[3 * r + 1] = g[1];
@@ -2336,12 +2367,9 @@ k_gp_point_setup(Compact<T> cp, double lam, double dmin, double dmax,
     }
   }
 #pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) {
+  for (int i = 0; i < 7; ++i) v[i] = group_sum<G>(v[i]);
 #pragma unroll
-    for (int i = 0; i < 7; ++i) v[i] += __shfl_xor(v[i], o, kWave);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) q[i] += __shfl_xor(q[i], o, kWave);
-  }
+  for (int i = 0; i < 3; ++i) q[i] = group_sum<G>(q[i]);
   if (r >= cp.Pa || l != 0) return;
   const double dmp = lam * fmin(fmax(v[6], dmin), dmax);
   const double v00 = v[0] + dmp, v01 = v[1], v02 = v[2];
@@ -2489,12 +2517,9 @@ k_gp_schur_point(Compact<T> cp, const V4<T>* __restrict__ a_pm,
       y[2] += o[2];
     }
   }
-#pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) {
-    y[0] += __shfl_xor(y[0], o, kWave);
-    y[1] += __shfl_xor(y[1], o, kWave);
-    y[2] += __shfl_xor(y[2], o, kWave);
-  }
+  y[0] = group_sum<G>(y[0]);
+  y[1] = group_sum<G>(y[1]);
+  y[2] = group_sum<G>(y[2]);
   if (!live) return;
   T vi[6];
 #pragma unroll
@@ -2593,12 +2618,9 @@ k_gp_schur_point_lds(Compact<T> cp, const V4<T>* __restrict__ a_pm,
         for (j += G; j < cur.e; j += G) obs(cp.cam[j], a_pm[j]);
       }
     }
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) {
-      y[0] += __shfl_xor(y[0], o, kWave);
-      y[1] += __shfl_xor(y[1], o, kWave);
-      y[2] += __shfl_xor(y[2], o, kWave);
-    }
+    y[0] = group_sum<G>(y[0]);
+    y[1] = group_sum<G>(y[1]);
+    y[2] = group_sum<G>(y[2]);
     if (live) {
       P3<T> z;
       z.x = vi[0] * y[0] + vi[1] * y[1] + vi[2] * y[2];
@@ -2684,10 +2706,7 @@ k_gp_backsub(Compact<T> cp, const V4<T>* __restrict__ a_pm, const T* __restrict_
     }
   }
 #pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) {
-#pragma unroll
-    for (int i = 0; i < 3; ++i) y[i] += __shfl_xor(y[i], o, kWave);
-  }
+  for (int i = 0; i < 3; ++i) y[i] = group_sum<G>(y[i]);
   if (r >= cp.Pa || l != 0) return;
   double vi[6];
 #pragma unroll
@@ -2995,10 +3014,10 @@ void schur_point_launch(hipStream_t s, const Model& m, const Compact<T>& cp, Obs
                         const DevLimits& dl) {
   const size_t tab = size_t(cp.Ca) * sizeof(MvRec<T, D>);
   bool use_lds = dl.n_cu > 0 && cp.Ca > 0 && tab <= size_t(dl.lds_per_block);
+  const void* fn = reinterpret_cast<const void*>(&k_schur_point_lds<T, ADJ, G, D>);
   if (use_lds && tab > 65536)
-    use_lds = hipFuncSetAttribute(
-                  reinterpret_cast<const void*>(&k_schur_point_lds<T, ADJ, G, D>),
-                  hipFuncAttributeMaxDynamicSharedMemorySize, int(tab)) == hipSuccess;
+    use_lds = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(tab)) ==
+              hipSuccess;
   if (use_lds) {
     // float32 (80-byte records, two could share a CU): one workgroup per CU; with the next
     // tile's loads in flight, 16 waves per CU stream better than 32 sharing the L1 (30 us
