@@ -183,7 +183,11 @@ struct ba_ctx {
   double *Uraw = nullptr, *gc = nullptr, *b = nullptr, *Minv = nullptr, *rhs_c = nullptr;
   double *x = nullptr, *r = nullptr, *u = nullptr, *p = nullptr, *sv = nullptr,
          *wv = nullptr, *dots = nullptr, *part = nullptr;
-  int *item_off = nullptr, *item_cam = nullptr;   // camera-pass items
+  // camera-pass items (CamItems) of the current solve, and the point-range bounds of the
+  // camera segments they are cut at
+  int *item_off = nullptr, *rb = nullptr;
+  int4* item_at = nullptr;
+  int it_R = 1, it_cap = 0, it_nslot = 0, it_slots = 0, it_count = 0;
 
   // explicit reduced camera system (solver = BA_SOLVER_EXPLICIT), sized per extraction
   Arena ex;
@@ -409,6 +413,9 @@ ba_status guarded(ba_ctx* c, F&& f) {
 }
 
 // ------------------------------------------------------------------ buffers
+// Most camera-pass items a solve can have (CamItems: R Ca + nchunks, R <= 8).
+size_t item_slots(int C) { return size_t(kMaxRanges) * size_t(C) + kCamChunks; }
+
 void alloc_obs_buffers(ba_ctx& c) {
   c.release_explicit();
   c.obs.release();
@@ -470,7 +477,7 @@ void alloc_obs_buffers(ba_ctx& c) {
   c.V = A.alloc<char>(sizeof(double) * 6 * P);
   c.Vinv = A.alloc<char>(ts * 6 * P);
   c.prec = A.alloc<char>((ts == 8 ? sizeof(PtRec<double>) : sizeof(PtRec<float>)) * P);
-  c.zq = A.alloc<char>(3 * ts * N);
+  c.zq = A.alloc<char>(3 * ts * std::max<int64_t>(N, P));   // per point, or per position (GP)
   const size_t ns = size_t(c.D) * (c.D + 1) / 2;   // entries of a symmetric camera block
   const size_t nd = size_t(c.D);
   c.Ustar = A.alloc<char>(ts * ns * C);
@@ -492,9 +499,10 @@ void alloc_obs_buffers(ba_ctx& c) {
   c.sv = A.alloc<double>(nd * size_t(C));
   c.wv = A.alloc<double>(nd * size_t(C));          // U* u of the current PCG direction
   c.dots = A.alloc<double>(2 * 3 * size_t(C));     // per-camera terms, two parities
-  c.part = A.alloc<double>((nd + 1) * (size_t(C) + kCamChunks));   // camera-pass partials
-  c.item_off = A.alloc<int>(size_t(C) + 1);
-  c.item_cam = A.alloc<int>(size_t(C) + kCamChunks);
+  c.part = A.alloc<double>((nd + 1) * item_slots(C));   // camera-pass partials
+  c.item_off = A.alloc<int>(size_t(C) + 2);
+  c.item_at = A.alloc<int4>(size_t(kMaxRanges) * (size_t(C) + kCamChunks));
+  c.rb = A.alloc<int>(size_t(kMaxRanges) * C);
   // 5 sums per workgroup; the global-positioning candidate runs up to 16 lanes per point
   c.partials = A.alloc<double>(5 * (size_t(P) * 16 / kBlock + 16));
   c.scal = A.alloc<double>(16);
@@ -558,6 +566,42 @@ ObsMetric<T> metric_view(ba_ctx& c) {
   om.ce = c.ce_on ? static_cast<T*>(c.ce) : nullptr;
   om.cm_ce = c.ce_on ? static_cast<T*>(c.cm_ce) : nullptr;
   return om;
+}
+
+// The camera-pass items of the current solve.
+CamItems items_view(const ba_ctx& c) {
+  CamItems it;
+  it.R = c.it_R;
+  it.cap = c.it_cap;
+  it.off = c.item_off;
+  it.at = c.item_at;
+  it.slots = c.it_slots;
+  return it;
+}
+
+// Sets up the items of a solve over R point ranges (8 for the matrix-free LM passes: the
+// eighths of the point ranks the point pass gives the XCDs, ppx = ceil(Pa / 8) each; 1 for
+// whole camera segments) and returns the partial-slot count; the PCG init builds them.
+int plan_items(ba_ctx& c, int R, int nch) {
+  c.it_R = R;
+  c.it_cap = c.Ca + nch;
+  c.it_nslot = R * c.Ca + nch;
+  c.it_slots = c.it_cap;
+  if (R > 1)
+    launch_range_bounds(c.stream, c.Ca, R, (c.Pa + R - 1) / R, c.cm_off_hat, c.cm_pt, c.rb);
+  return c.it_nslot;
+}
+
+// After the PCG init: the item count and the largest item count of a range, which size the
+// update's reduction and the camera-pass grid (one host round trip per solve).
+void read_item_counts(ba_ctx& c) {
+  HIP_CHECK(hipMemcpyAsync(c.h_pin + 24, c.item_off + c.Ca, 2 * sizeof(int),
+                           hipMemcpyDeviceToHost, c.stream));
+  c.sync();
+  int n[2] = {0, 0};
+  std::memcpy(n, c.h_pin + 24, sizeof(n));
+  c.it_count = std::max(0, std::min(n[0], c.it_nslot));
+  c.it_slots = std::max(0, std::min(n[1], c.it_cap));
 }
 
 // ------------------------------------------------------------------ extraction
@@ -640,25 +684,26 @@ void extract(ba_ctx& c, bool gp = false) {
 
 // Algorithmic bytes of the two PCG passes (unique data each must touch once).
 // Point pass: per observation its slot and, in float32, its weight (X_c is formed from the
-// point) or, in float64, its (X_c, w) 4-vector; for solve cameras its camera-major position
-// and the packed z 3-vector written there; per point the CSR offset, Vinv and, in float32,
-// the point; every matvec record once.
+// point) or, in float64, its (X_c, w) 4-vector; per point the CSR offset, Vinv, in float32 the
+// point, and its z 3-vector written; every matvec record once.
 double bytes_schur_point(const ba_ctx& c) {
   const double ts = double(c.tsize());
   const bool form = ts == 4;
   const double rec = form || c.D == 7 ? 20 : 16;   // matvec record values
-  return double(c.Nh) * (4 + (form ? 1 : 4) * ts) + double(c.Nc) * (4 + 3 * ts) +
-         double(c.Pa) * (4 + (form ? 9 : 6) * ts) + double(c.Ca) * rec * ts;
+  return double(c.Nh) * (4 + (form ? 1 : 4) * ts) +
+         double(c.Pa) * (4 + (form ? 9 : 6) * ts + 3 * ts) + double(c.Ca) * rec * ts;
 }
-// Camera pass: per observation the (X_c, w) 4-vector and the z 3-vector; per camera its
-// offset, table entry and u; per partial slot its D + 1 values written.
+// Camera pass: per camera-major position the (X_c, w) 4-vector and the point rank; the z
+// vectors once (each XCD reads its eighth of the points, gathered through its L2); per item
+// its bounds, camera, table entry and u, and its D + 1 partial values written.
 double bytes_schur_cam(const ba_ctx& c) {
   const double ts = double(c.tsize());
   const double D = c.D;
   int K = 0, nch = 0;
   cam_chunking(c.Nc, K, nch);
-  return double(c.Nc) * 7 * ts + double(c.Ca) * (4 + 15 * ts + D * 8) +
-         double(c.Ca + nch) * (D + 1) * 8;
+  const double items = double(kMaxRanges) * c.Ca + nch;
+  return double(c.Nc) * (4 * ts + 4) + double(c.Pa) * 3 * ts +
+         items * (16 + 15 * ts + D * 8 + (D + 1) * 8);
 }
 // PCG update: per camera its terms (read and written), offsets, M^-1, U*, the vectors
 // p s x r u and U* u (read and written) and its matvec record's u; every partial slot once.
@@ -668,7 +713,7 @@ double bytes_pcg_update(const ba_ctx& c) {
   int K = 0, nch = 0;
   cam_chunking(c.Nc, K, nch);
   return double(c.Ca) * (2 * 3 * 8 + 4 + ns * 8 + ns * ts + 2 * 6 * D * 8 + D * ts) +
-         double(c.Ca + nch) * (D + 1) * 8;
+         (double(kMaxRanges) * c.Ca + nch) * (D + 1) * 8;
 }
 // Smallest LM damping. In mixed precision the damped blocks U*, V*^-1 and the matvec are
 // float32: a Marquardt damping of the order of their rounding (6e-8) amplified by the
@@ -877,11 +922,12 @@ int run_pcg(ba_ctx& c, bool adj, double rel_tol, int max_iters, PcgState* out_st
     K = std::numeric_limits<int>::max() / 2;
     nch = 0;
   }
-  launch_pcg_init<T>(s, c.D, c.Ca, c.b, c.Minv, Ustar, c.cm_off_hat, K, c.item_off, c.item_cam,
-                     c.x, c.r, c.u, c.p, c.sv, c.wv, c.dots, mvt, c.pcg, rel_tol * rel_tol,
-                     max_iters);
+  const int nslot = plan_items(c, expl ? 1 : kMaxRanges, nch);
+  launch_pcg_init<T>(s, c.D, c.Ca, c.b, c.Minv, Ustar, c.cm_off_hat, c.rb, K, items_view(c), c.x,
+                     c.r, c.u, c.p, c.sv, c.wv, c.dots, mvt, c.pcg, rel_tol * rel_tol, max_iters);
   HIP_LAUNCH_CHECK();
-  const int nslot = c.Ca + nch;
+  read_item_counts(c);
+  const CamItems items = items_view(c);
   const int every = std::max(1, c.opt.pcg_check_every);
   const double bp = bytes_schur_point(c), bc = bytes_schur_cam(c), bu = bytes_pcg_update(c);
   // explicit product: every block (D x D values and its key) and the row pointers once, the
@@ -905,13 +951,13 @@ int run_pcg(ba_ctx& c, bool adj, double rel_tol, int max_iters, PcgState* out_st
                                 zq, c.pcg, c.dl);
         });
         c.timed("schur_cam", bc, it, [&] {
-          launch_schur_cam<T>(s, adj, c.D, m, cp, om, c.u, zq, K, c.item_off, c.item_cam, nslot,
-                              c.part, c.pcg);
+          launch_schur_cam<T>(s, adj, c.D, m, cp, om, c.u, zq, items, nslot, c.part, c.pcg,
+                              c.dl);
         });
       }
       c.timed("pcg_update", bu, it, [&] {
-        launch_pcg_update<T>(s, c.D, c.Ca, it, c.Minv, Ustar, c.item_off, nslot, c.part, c.dots,
-                             c.x, c.r, c.u, c.p, c.sv, c.wv, mvt, c.pcg);
+        launch_pcg_update<T>(s, c.D, c.Ca, it, c.Minv, Ustar, c.item_off, c.it_count, nslot,
+                             c.part, c.dots, c.x, c.r, c.u, c.p, c.sv, c.wv, mvt, c.pcg);
       });
     }
     HIP_CHECK(hipMemcpyAsync(c.h_pin, c.pcg, sizeof(PcgState), hipMemcpyDeviceToHost, s));
@@ -932,15 +978,13 @@ double true_residual(ba_ctx& c) {
   const Model m = c.model();
   Compact<T> cp = compact_view<T>(c);
   ObsMetric<T> om = metric_view<T>(c);
-  int K = 0, nch = 0;
-  cam_chunking(c.Nc, K, nch);
-  const int nslot = c.Ca + nch;
+  const int nslot = c.it_nslot;   // the items of the solve that produced x
   P3<T>* zq = static_cast<P3<T>*>(c.zq);
   launch_x_to_mv<T>(s, c.D, c.Ca, c.x, c.mvt, c.pcg_diag);
   launch_schur_point<T>(s, false, c.D, lanes_per_point(c), m, cp, om, c.mvt,
                         static_cast<const T*>(c.Vinv), zq, c.pcg_diag, c.dl);
-  launch_schur_cam<T>(s, false, c.D, m, cp, om, c.x, zq, K, c.item_off, c.item_cam, nslot,
-                      c.part, c.pcg_diag);
+  launch_schur_cam<T>(s, false, c.D, m, cp, om, c.x, zq, items_view(c), nslot, c.part,
+                      c.pcg_diag, c.dl);
   launch_true_residual<T>(s, c.D, c.Ca, c.x, c.b, static_cast<const T*>(c.Ustar), c.item_off,
                           nslot, c.part, c.diag);
   HIP_LAUNCH_CHECK();
@@ -1146,10 +1190,13 @@ int gp_run_pcg(ba_ctx& c, PcgState* out_state) {
   const T* Ustar = static_cast<const T*>(c.Ustar);
   int K = 0, nch = 0;
   cam_chunking(c.Nc, K, nch);
-  const int nslot = c.Ca + nch;
-  launch_pcg_init<T>(s, 3, c.Ca, c.b, c.Minv, Ustar, c.cm_off_hat, K, c.item_off, c.item_cam,
-                     c.x, c.r, c.u, c.p, c.sv, c.wv, c.dots, c.mvt, c.pcg,
+  const int nslot = plan_items(c, 1, nch);   // z per camera-major position: no ranges
+  launch_pcg_init<T>(s, 3, c.Ca, c.b, c.Minv, Ustar, c.cm_off_hat, c.rb, K, items_view(c), c.x,
+                     c.r, c.u, c.p, c.sv, c.wv, c.dots, c.mvt, c.pcg,
                      c.opt.pcg_rel_tol * c.opt.pcg_rel_tol, c.opt.pcg_max_iters);
+  HIP_LAUNCH_CHECK();
+  read_item_counts(c);
+  const CamItems items = items_view(c);
   HIP_LAUNCH_CHECK();
   const double ts = double(sizeof(T));
   const int G = lanes_per_point(c);
@@ -1171,12 +1218,11 @@ int gp_run_pcg(ba_ctx& c, PcgState* out_state) {
                                  c.pcg, c.dl);
       });
       c.timed("gp_schur_cam", bc, it, [&] {
-        launch_gp_schur_cam<T>(s, cp, a_cm, c.u, zq, K, c.item_off, c.item_cam, nslot, c.part,
-                               c.pcg);
+        launch_gp_schur_cam<T>(s, cp, a_cm, c.u, zq, items, nslot, c.part, c.pcg, c.dl);
       });
       c.timed("gp_pcg_update", bu, it, [&] {
-        launch_pcg_update<T>(s, 3, c.Ca, it, c.Minv, Ustar, c.item_off, nslot, c.part, c.dots,
-                             c.x, c.r, c.u, c.p, c.sv, c.wv, c.mvt, c.pcg);
+        launch_pcg_update<T>(s, 3, c.Ca, it, c.Minv, Ustar, c.item_off, c.it_count, nslot,
+                             c.part, c.dots, c.x, c.r, c.u, c.p, c.sv, c.wv, c.mvt, c.pcg);
       });
     }
     HIP_CHECK(hipMemcpyAsync(c.h_pin, c.pcg, sizeof(PcgState), hipMemcpyDeviceToHost, s));
@@ -1431,7 +1477,7 @@ void points_internal_to_user(ba_ctx& c, const std::vector<double>& internal,
 // sizes the context allocates for the same buffers, each slice aligned to 256 bytes).
 struct ScratchPlan {
   size_t flags = 0, pcg = 0, pcg_diag = 0, diag = 0, partials = 0, dots = 0, part = 0,
-         item_off = 0, item_cam = 0, scan = 0, total = 0;
+         item_off = 0, item_at = 0, rb = 0, scan = 0, total = 0;
 };
 
 ScratchPlan plan_scratch(const ba_ctx& c) {
@@ -1448,9 +1494,10 @@ ScratchPlan plan_scratch(const ba_ctx& c) {
   p.diag = take(4 * sizeof(double));
   p.partials = take(5 * (size_t(c.P) * 16 / kBlock + 16) * sizeof(double));
   p.dots = take(2 * 3 * C * sizeof(double));
-  p.part = take((nd + 1) * (C + kCamChunks) * sizeof(double));
-  p.item_off = take((C + 1) * sizeof(int));
-  p.item_cam = take((C + kCamChunks) * sizeof(int));
+  p.part = take((nd + 1) * item_slots(c.C) * sizeof(double));
+  p.item_off = take((C + 2) * sizeof(int));
+  p.item_at = take(kMaxRanges * (C + kCamChunks) * sizeof(int4));
+  p.rb = take(kMaxRanges * C * sizeof(int));
   p.scan = take(c.scan_temp_size);
   return p;
 }
@@ -1462,12 +1509,13 @@ struct ScratchSwap {
   int* flags;
   PcgState *pcg, *pcg_diag;
   double *diag, *partials, *dots, *part;
-  int *item_off, *item_cam;
+  int *item_off, *rb;
+  int4* item_at;
   void* scan;
   ScratchSwap(ba_ctx& cc, char* base, const ScratchPlan& p)
       : c(cc), flags(cc.flags), pcg(cc.pcg), pcg_diag(cc.pcg_diag), diag(cc.diag),
         partials(cc.partials), dots(cc.dots), part(cc.part), item_off(cc.item_off),
-        item_cam(cc.item_cam), scan(cc.scan_temp) {
+        rb(cc.rb), item_at(cc.item_at), scan(cc.scan_temp) {
     c.flags = reinterpret_cast<int*>(base + p.flags);
     c.pcg = reinterpret_cast<PcgState*>(base + p.pcg);
     c.pcg_diag = reinterpret_cast<PcgState*>(base + p.pcg_diag);
@@ -1476,7 +1524,8 @@ struct ScratchSwap {
     c.dots = reinterpret_cast<double*>(base + p.dots);
     c.part = reinterpret_cast<double*>(base + p.part);
     c.item_off = reinterpret_cast<int*>(base + p.item_off);
-    c.item_cam = reinterpret_cast<int*>(base + p.item_cam);
+    c.item_at = reinterpret_cast<int4*>(base + p.item_at);
+    c.rb = reinterpret_cast<int*>(base + p.rb);
     c.scan_temp = base + p.scan;
   }
   ~ScratchSwap() {
@@ -1488,7 +1537,8 @@ struct ScratchSwap {
     c.dots = dots;
     c.part = part;
     c.item_off = item_off;
-    c.item_cam = item_cam;
+    c.item_at = item_at;
+    c.rb = rb;
     c.scan_temp = scan;
   }
   ScratchSwap(const ScratchSwap&) = delete;

@@ -267,46 +267,66 @@ void launch_cam_assemble(hipStream_t s, bool adj, int D, const Model& m, const C
 // per-camera terms r.u, u.U*u, r.r of iteration 0 (terms: 2 x 3 arrays of Ca, SoA, the
 // first three for even iterations); the camera-pass items: camera s owns items
 // item_off[s] .. item_off[s + 1] - 1 (item_cam[i] = s), one per K positions of its segment.
-template <typename T>
-void launch_pcg_init(hipStream_t s, int D, int Ca, const double* b, const double* Minv,
-                     const T* Ustar, const int* cm_off, int K, int* item_off, int* item_cam,
-                     double* x, double* r, double* u, double* p, double* sv, double* Uu,
-                     double* terms, void* mvt, PcgState* st, double tol2, int max_iter);
-// Item size of the camera pass: K = Nc / kCamChunks rounded up to a multiple of 64, at least
-// 512, so that there are nchunks = ceil(Nc / K) <= kCamChunks pieces of K positions and at most
-// Ca + nchunks items (each camera's segment adds one partial piece at most).
+// Items of the camera pass. A camera's segment of camera-major positions (sorted by point
+// rank) is split at the boundaries of R point ranges (R = 1, or 8: the eighths of the point
+// ranks that the point pass gives the 8 XCDs), and every piece is cut into items of at most K
+// positions. A camera's items are numbered consecutively from off[s] (off[Ca] = the item
+// count), so the update kernel sums their partials in a fixed order. at[r * cap + q] describes
+// the q-th item of range r as (item, camera, first position, end position), or has item -1
+// past the range's last item: the camera pass takes range r's items on the workgroups of XCD
+// r, whose L2 holds that range's point vectors z after the point pass, and reads one record
+// per item. Built on the device by the PCG init.
+constexpr int kMaxRanges = 8;
+struct CamItems {
+  int R, cap;   // ranges; capacity of each range's list in at
+  int* off;     // Ca + 2: off[Ca + 1] = the largest item count of a range
+  int4* at;     // R * cap
+  int slots;    // slots per range the camera pass covers (<= cap; set from off[Ca + 1])
+};
+// Item size: K = Nc / kCamChunks rounded up to a multiple of 64, at least 512, so that
+// nchunks = ceil(Nc / K) <= kCamChunks. There are at most R Ca + nchunks items in all (each
+// camera's piece of a range adds one partial item at most) and at most Ca + nchunks in a range.
 constexpr int kCamChunks = 1024;
 inline void cam_chunking(int Nc, int& K, int& nchunks) {
   const int per = (Nc + kCamChunks - 1) / kCamChunks;
   K = per <= 512 ? 512 : (per + 63) / 64 * 64;
   nchunks = Nc > 0 ? (Nc + K - 1) / K : 0;
 }
+// rb[r * Ca + s] = the first position of camera s's segment whose point rank is at least
+// r * ppx (r = 1 .. R - 1; row 0 is the segment start).
+void launch_range_bounds(hipStream_t s, int Ca, int R, int ppx, const int* cm_off,
+                         const int* cm_pt, int* rb);
+template <typename T>
+void launch_pcg_init(hipStream_t s, int D, int Ca, const double* b, const double* Minv,
+                     const T* Ustar, const int* cm_off, const int* rb, int K, CamItems it,
+                     double* x, double* r, double* u, double* p, double* sv, double* Uu,
+                     double* terms, void* mvt, PcgState* st, double tol2, int max_iter);
 // Camera-side launchers take the camera dimension D: 6 (pose) or 7 (pose and focal length,
 // matvec records MvCamF); the adjoint mode runs with D = 6 only.
 
-// z_p = Vinv sum_k W_k^T u_c (point-major pass, G lanes per point), written to the
-// camera-major position of every observation of p in a solve camera (zq_cm, Nc entries).
-// When the Ca matvec records fit in LDS, a persistent grid stages them there.
+// z_p = Vinv sum_k W_k^T u_c (point-major pass, G lanes per point), one 3-vector per point
+// rank (zq, Pa entries). When the Ca matvec records fit in LDS, a persistent grid stages them
+// there, XCD x taking the x-th eighth of the point ranks.
 template <typename T>
 void launch_schur_point(hipStream_t s, bool adj, int D, int G, const Model& m,
                         const Compact<T>& cp, ObsMetric<T> om, const void* mvt, const T* Vinv,
-                        P3<T>* zq_cm, const PcgState* st, const DevLimits& dl);
-// Camera-major pass in items of at most K positions of one camera: per item i, sum_k W_k z_k
-// over its positions with z streamed in camera-major order (part: rows 0..D-1 of nslot
-// entries, SoA) and that sum's dot with u_s (row D). nslot >= the item count.
+                        P3<T>* zq, const PcgState* st, const DevLimits& dl);
+// Camera-major pass over the items: per item i, sum_k W_k z_k over its positions, z gathered
+// through the position's point rank (part: rows 0..D-1 of nslot entries, SoA) and that sum's
+// dot with u_s (row D). nslot >= the item count; one workgroup per slot, R it.slots.
 template <typename T>
 void launch_schur_cam(hipStream_t s, bool adj, int D, const Model& m, const Compact<T>& cp,
-                      ObsMetric<T> om, const double* u, const P3<T>* zq, int K,
-                      const int* item_off, const int* item_cam, int nslot, double* part,
-                      const PcgState* st);
-// w = U* u - (each camera's item partials), fused reduction of the per-camera terms, convergence
+                      ObsMetric<T> om, const double* u, const P3<T>* zq, CamItems it,
+                      int nslot, double* part, const PcgState* st, const DevLimits& dl);
+// w = U* u - (each camera's item partials; nit items in all), fused reduction of the per-camera
+// terms, convergence
 // test, then p = u + beta p, s = w + beta s, x += alpha p, r -= alpha s, u = M^-1 r, and U* u
 // with the next iteration's terms.
 template <typename T>
 void launch_pcg_update(hipStream_t s, int D, int Ca, int k, const double* Minv, const T* Ustar,
-                       const int* item_off, int nslot, const double* part, double* terms,
-                       double* x, double* r, double* u, double* p, double* sv, double* Uu,
-                       void* mvt, PcgState* st);
+                       const int* item_off, int nit, int nslot, const double* part,
+                       double* terms, double* x, double* r, double* u, double* p, double* sv,
+                       double* Uu, void* mvt, PcgState* st);
 // The true residual of a PCG solution x: k_x_to_mv writes x into the matvec records and
 // clears the done flag of st (a state used only for this product), the two matvec passes run
 // with st, and launch_true_residual forms |b - S x|^2 and |b|^2 into out[0], out[1].
@@ -452,8 +472,8 @@ void launch_gp_schur_point(hipStream_t s, int G, const Compact<T>& cp, const V4<
                            const DevLimits& dl);
 template <typename T>
 void launch_gp_schur_cam(hipStream_t s, const Compact<T>& cp, const V4<T>* a_cm,
-                         const double* u, const P3<T>* zq, int K, const int* item_off,
-                         const int* item_cam, int nslot, double* part, const PcgState* st);
+                         const double* u, const P3<T>* zq_cm, CamItems it, int nslot,
+                         double* part, const PcgState* st, const DevLimits& dl);
 // dX = hp + V*^-1 sum A dc.
 template <typename T>
 void launch_gp_backsub(hipStream_t s, int G, const Compact<T>& cp, const V4<T>* a_pm,

@@ -988,45 +988,112 @@ __device__ __forceinline__ void symd_mul_soa(const double* M, int Ca, int s, con
   }
 }
 
+// One thread per camera and range r >= 1: the first position of the camera's segment (sorted
+// by point rank) whose rank is at least r * ppx, by binary search.
+__global__ void __launch_bounds__(kBlock)
+k_range_bounds(int Ca, int R, int ppx, const int* __restrict__ cm_off,
+               const int* __restrict__ cm_pt, int* __restrict__ rb) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= Ca * R) return;
+  const int r = t / Ca, s = t % Ca;
+  int lo = cm_off[s], hi = cm_off[s + 1];
+  if (r > 0) {
+    const int64_t key = int64_t(r) * ppx;
+    while (lo < hi) {
+      const int mid = lo + (hi - lo) / 2;
+      if (cm_pt[mid] < key)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+  }
+  rb[t] = lo;
+}
+
 template <typename T, int D>
 __global__ void __launch_bounds__(1024)
 k_pcg_init(int Ca, const double* __restrict__ b, const double* __restrict__ Minv,
-           const T* __restrict__ Ustar, const int* __restrict__ cm_off, int K,
-           int* __restrict__ item_off, int* __restrict__ item_cam, double* __restrict__ x,
+           const T* __restrict__ Ustar, const int* __restrict__ cm_off,
+           const int* __restrict__ rb, int K, CamItems it, double* __restrict__ x,
            double* __restrict__ r, double* __restrict__ u, double* __restrict__ p,
            double* __restrict__ sv, double* __restrict__ Uu, double* __restrict__ terms,
            MvRec<T, D>* __restrict__ mvt, PcgState* st, double tol2, int max_iter) {
   __shared__ double smem[1024 / kWave];
-  __shared__ int s_wave[1024 / kWave];
-  __shared__ int s_carry;
-  // items of the camera pass: ceil(n_s / K) per camera, numbered camera by camera (an
-  // exclusive scan over the cameras in tiles of the block)
-  if (threadIdx.x == 0) s_carry = 0;
+  // items of the camera pass (see CamItems): R + 1 exclusive scans over the cameras in tiles
+  // of the block, of each camera's item count (numbering camera by camera) and of its count
+  // in every range (the per-range lists)
+  constexpr int NV = kMaxRanges + 1;
+  __shared__ int s_wave[NV][1024 / kWave];
+  __shared__ int s_carry[NV];
+  const int R = it.R;
+  if (threadIdx.x < NV) s_carry[threadIdx.x] = 0;
+  for (int q = threadIdx.x; q < R * it.cap; q += blockDim.x) it.at[q] = make_int4(-1, 0, 0, 0);
   __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   for (int base = 0; base < Ca; base += 1024) {
     const int s = base + int(threadIdx.x);
-    const int n = s < Ca ? (cm_off[s + 1] - cm_off[s] + K - 1) / K : 0;
-    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    int incl = n;
+    int lo[kMaxRanges + 1], cnt[NV], incl[NV];
 #pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-      const int t = __shfl_up(incl, o, kWave);
-      if (lane >= o) incl += t;
-    }
-    if (lane == kWave - 1) s_wave[wid] = incl;
-    __syncthreads();
-    int before = s_carry;
-    for (int w = 0; w < wid; ++w) before += s_wave[w];
-    const int first = before + incl - n;
+    for (int v = 0; v < NV; ++v) cnt[v] = 0;
     if (s < Ca) {
-      item_off[s] = first;
-      for (int q = 0; q < n; ++q) item_cam[first + q] = s;
+#pragma unroll
+      for (int q = 0; q < kMaxRanges; ++q)
+        if (q < R) lo[q] = q == 0 ? cm_off[s] : rb[q * Ca + s];
+      const int end = cm_off[s + 1];
+#pragma unroll
+      for (int q = 0; q < kMaxRanges; ++q) {
+        if (q < R) {
+          const int hi = q + 1 < R ? lo[q + 1] : end;
+          cnt[1 + q] = (hi - lo[q] + K - 1) / K;
+          cnt[0] += cnt[1 + q];
+        }
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      incl[v] = cnt[v];
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const int t = __shfl_up(incl[v], o, kWave);
+        if (lane >= o) incl[v] += t;
+      }
+      if (lane == kWave - 1) s_wave[v][wid] = incl[v];
     }
     __syncthreads();
-    if (threadIdx.x == 1023) s_carry = first + n;
+    int first[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      int before = s_carry[v];
+      for (int w = 0; w < wid; ++w) before += s_wave[v][w];
+      first[v] = before + incl[v] - cnt[v];
+    }
+    if (s < Ca) {
+      it.off[s] = first[0];
+      int i = first[0];
+      const int end = cm_off[s + 1];
+#pragma unroll
+      for (int q = 0; q < kMaxRanges; ++q) {
+        if (q < R) {
+          const int hi = q + 1 < R ? lo[q + 1] : end;
+          for (int c = 0; c < cnt[1 + q]; ++c, ++i)
+            it.at[q * it.cap + first[1 + q] + c] =
+                make_int4(i, s, lo[q] + c * K, min(lo[q] + (c + 1) * K, hi));
+        }
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 1023) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) s_carry[v] = first[v] + cnt[v];
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) item_off[Ca] = s_carry;
+  if (threadIdx.x == 0) {
+    it.off[Ca] = s_carry[0];
+    int mx = 0;
+    for (int q = 0; q < R; ++q) mx = max(mx, s_carry[1 + q]);
+    it.off[Ca + 1] = mx;
+  }
   double acc[1] = {0.0};   // b.b
   for (int s = threadIdx.x; s < Ca; s += blockDim.x) {
     double rv[D], uv[D];
@@ -1093,7 +1160,6 @@ template <typename T>
 struct PtLoad {
   int b, e;     // observation range; b = e for a lane without a point
   int s0;       // first observation's camera slot (Ca: none)
-  int pos0;     // its camera-major position (-1: none, or a fixed camera)
   V4<T> xw0;    // its weight in w; in float64 also its X_c (the stored 4-vector)
   T X[3];       // the point (float32)
 };
@@ -1106,7 +1172,6 @@ template <typename T>
 __device__ __forceinline__ void pt_load_first(const Compact<T>& cp, const ObsMetric<T>& om,
                                               int r, int l, PtLoad<T>& p) {
   p.s0 = cp.Ca;
-  p.pos0 = -1;
   p.xw0.x = p.xw0.y = p.xw0.z = p.xw0.w = T(0);
   p.X[0] = p.X[1] = p.X[2] = T(0);
   if (kFormXc<T> && p.b < p.e) {
@@ -1120,7 +1185,6 @@ __device__ __forceinline__ void pt_load_first(const Compact<T>& cp, const ObsMet
       p.xw0.w = om.w[p.b + l];
     else
       p.xw0 = om.pm_xcw[p.b + l];
-    p.pos0 = cp.pm_cm[p.b + l];
   }
 }
 
@@ -1171,7 +1235,7 @@ __device__ __forceinline__ void schur_point_one(const Model& m, const Compact<T>
                                                 const ObsMetric<T>& om,
                                                 const MvRec<T, D>* __restrict__ tab,
                                                 const T* __restrict__ Vinv,
-                                                P3<T>* __restrict__ zq_cm, int r, bool live,
+                                                P3<T>* __restrict__ zq, int r, bool live,
                                                 int l, const PtLoad<T>& p) {
   T y[3] = {T(0), T(0), T(0)};
   T vi[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
@@ -1193,8 +1257,10 @@ __device__ __forceinline__ void schur_point_one(const Model& m, const Compact<T>
     // loads needed only after the reduction, issued now to overlap the stream (float32: the
     // registers are free; float64 keeps them for the stream)
     if constexpr (sizeof(T) == 4) {
+      if (l == 0) {
 #pragma unroll
-      for (int q = 0; q < 6; ++q) vi[q] = Vinv[6 * r + q];
+        for (int q = 0; q < 6; ++q) vi[q] = Vinv[6 * r + q];
+      }
     }
     int j = p.b + l;
     if (j < p.e) {
@@ -1214,9 +1280,9 @@ __device__ __forceinline__ void schur_point_one(const Model& m, const Compact<T>
   y[0] = group_sum<G>(y[0]);
   y[1] = group_sum<G>(y[1]);
   y[2] = group_sum<G>(y[2]);
-  // every lane of the group now holds y; each computes z and stores its observations' copies
-  // (pm_cm is -1 for an observation of a fixed camera)
-  if (live) {
+  // every lane of the group now holds y; the first lane stores the point's z (consecutive
+  // groups store consecutive points, so the stores fill whole cache lines)
+  if (live && l == 0) {
     if constexpr (sizeof(T) != 4) {
 #pragma unroll
       for (int q = 0; q < 6; ++q) vi[q] = Vinv[6 * r + q];
@@ -1225,11 +1291,7 @@ __device__ __forceinline__ void schur_point_one(const Model& m, const Compact<T>
     z.x = vi[0] * y[0] + vi[1] * y[1] + vi[2] * y[2];
     z.y = vi[1] * y[0] + vi[3] * y[1] + vi[4] * y[2];
     z.z = vi[2] * y[0] + vi[4] * y[1] + vi[5] * y[2];
-    if (p.pos0 >= 0) zq_cm[p.pos0] = z;
-    for (int j = p.b + l + G; j < p.e; j += G) {
-      const int pos = cp.pm_cm[j];
-      if (pos >= 0) zq_cm[pos] = z;
-    }
+    zq[r] = z;
   }
 }
 
@@ -1240,7 +1302,7 @@ __device__ __forceinline__ void schur_point_one(const Model& m, const Compact<T>
 template <typename T, bool ADJ, int G, int D>
 __global__ void __launch_bounds__(kBlock)
 k_schur_point(Model m, Compact<T> cp, ObsMetric<T> om, const MvRec<T, D>* __restrict__ mvt,
-              const T* __restrict__ Vinv, P3<T>* __restrict__ zq_cm,
+              const T* __restrict__ Vinv, P3<T>* __restrict__ zq,
               const PcgState* __restrict__ st) {
   if (st->done) return;
   const int per = gridDim.x / 8;
@@ -1252,7 +1314,7 @@ k_schur_point(Model m, Compact<T> cp, ObsMetric<T> om, const MvRec<T, D>* __rest
   p.b = live ? cp.off[r] : 0;
   p.e = live ? cp.off[r + 1] : 0;
   pt_load_first(cp, om, r, l, p);
-  schur_point_one<T, ADJ, G, D>(m, cp, om, mvt, Vinv, zq_cm, r, live, l, p);
+  schur_point_one<T, ADJ, G, D>(m, cp, om, mvt, Vinv, zq, r, live, l, p);
 }
 
 // Grid-stride variant for tables that fit in LDS: each 1024-thread workgroup (one resident
@@ -1268,7 +1330,7 @@ constexpr int kPtLdsBlock = 1024;
 template <typename T, bool ADJ, int G, int D>
 __global__ void __launch_bounds__(kPtLdsBlock)
 k_schur_point_lds(Model m, Compact<T> cp, ObsMetric<T> om, const MvRec<T, D>* __restrict__ mvt,
-                  const T* __restrict__ Vinv, P3<T>* __restrict__ zq_cm,
+                  const T* __restrict__ Vinv, P3<T>* __restrict__ zq,
                   const PcgState* __restrict__ st, int ppx) {
   extern __shared__ uint4 lds_tab[];   // cp.Ca records
   if (st->done) return;
@@ -1308,52 +1370,41 @@ k_schur_point_lds(Model m, Compact<T> cp, ObsMetric<T> om, const MvRec<T, D>* __
       bn = cp.off[r + 2 * step];
       en = cp.off[r + 2 * step + 1];
     }
-    schur_point_one<T, ADJ, G, D>(m, cp, om, tab, Vinv, zq_cm, r, r < hi, l, cur);
+    schur_point_one<T, ADJ, G, D>(m, cp, om, tab, Vinv, zq, r, r < hi, l, cur);
     cur = nxt;
   }
 }
 
-// Camera-major pass of S u in bounded items. Each camera's segment of the camera-major stream
-// is cut into items of at most K positions (item_off, item_cam: set by the PCG init); the
-// workgroup of item i sums W_k z_k over its positions (z streamed as stored by the point pass)
-// into partial i, and writes the partial's dot with u_s to the last row (zero for the
-// workgroups beyond the last item, so that row needs no item count to be summed). No workgroup has more
-// than K positions whatever the spread of observations per camera, and the update kernel adds
-// a camera's partials in item order, so the result does not depend on scheduling. Two-wave
-// workgroups walking items of a few thousand positions stream best (measured against 64-512
-// threads and 512-4096 items on the 1000-camera workload).
+// Camera-major pass of S u over the items of CamItems: a workgroup sums W_k z_k over an item's
+// positions into partial i (z gathered by the position's point rank) and writes the partial's
+// dot with u_s to the last row. No item has more than K positions whatever the spread of
+// observations per camera, and the update kernel adds a camera's partials in item order, so
+// the result does not depend on scheduling. Workgroup b takes slot b / R of range b % R: the
+// workgroups of XCD r (b % 8 = r) take range r's items, whose z vectors the point pass has
+// just written through that XCD's L2 (without the split, 43 us and 2.9x the fetched bytes on
+// the 1000-camera workload). Two-wave workgroups.
 constexpr int kCamBlock = 128;
 
+// One item of the camera pass (all threads of the workgroup).
 template <typename T, bool ADJ, int D>
-__global__ void __launch_bounds__(kCamBlock)
-k_schur_cam(Model m, Compact<T> cp, ObsMetric<T> om, const double* __restrict__ u,
-            const P3<T>* __restrict__ zq, int K, const int* __restrict__ item_off,
-            const int* __restrict__ item_cam, int nslot, double* __restrict__ part,
-            const PcgState* __restrict__ st) {
-  if (st->done) return;
-  const int Ca = cp.Ca;
-  const int i = blockIdx.x;
-  if (i >= item_off[Ca]) {   // beyond the last item: a zero dot, so the update sums all nslot
-    if (threadIdx.x == 0) part[D * nslot + i] = 0.0;
-    return;
-  }
-  const int s = item_cam[i];
-  const int sb = cp.cm_off[s] + (i - item_off[s]) * K;
-  const int se = min(sb + K, cp.cm_off[s + 1]);
+__device__ __forceinline__ void cam_item(const Model& m, const Compact<T>& cp,
+                                         const ObsMetric<T>& om, const double* __restrict__ u,
+                                         const P3<T>* __restrict__ zq, int4 rec, int nslot,
+                                         double* __restrict__ part, T* smem, int Ca) {
+  const int i = rec.x, s = rec.y, sb = rec.z, se = rec.w;
   double us[D];
   if (threadIdx.x == 0) {   // needed after the reduction: loaded while the stream runs
 #pragma unroll
     for (int q = 0; q < D; ++q) us[q] = u[q * Ca + s];
   }
-  __shared__ T smem[D * (kCamBlock / kWave)];
   const Cam<T> cm = cp.camt[s];
   T acc[D];
 #pragma unroll
   for (int q = 0; q < D; ++q) acc[q] = T(0);
-#pragma unroll 2
+#pragma unroll 4
   for (int k = sb + threadIdx.x; k < se; k += kCamBlock) {
     const V4<T> xw = om.xcw[k];
-    const P3<T> zv = zq[k];
+    const P3<T> zv = zq[cp.cm_pt[k]];
     const T Xc[3] = {xw.x, xw.y, xw.z};
     AMat<T, ADJ> A;
     A.set(cm.f, T(m.lam_d), Xc);
@@ -1393,6 +1444,18 @@ k_schur_cam(Model m, Compact<T> cp, ObsMetric<T> om, const double* __restrict__ 
   }
 }
 
+template <typename T, bool ADJ, int D>
+__global__ void __launch_bounds__(kCamBlock)
+k_schur_cam(Model m, Compact<T> cp, ObsMetric<T> om, const double* __restrict__ u,
+            const P3<T>* __restrict__ zq, CamItems it, int nslot, double* __restrict__ part,
+            const PcgState* __restrict__ st) {
+  if (st->done) return;
+  const int4 rec = it.at[(blockIdx.x % it.R) * it.cap + blockIdx.x / it.R];
+  if (rec.x < 0) return;   // past the range's last item
+  __shared__ T smem[D * (kCamBlock / kWave)];
+  cam_item<T, ADJ, D>(m, cp, om, u, zq, rec, nslot, part, smem, cp.Ca);
+}
+
 // One Chronopoulos-Gear PCG iteration k after the matvec w = S u, with w_s = U*_s u_s minus the
 // camera's item partials:
 //   gamma = r.u, delta = w.u = u.U*u - (the items' partial . u), rho = r.r (one reduction);
@@ -1404,22 +1467,46 @@ k_schur_cam(Model m, Compact<T> cp, ObsMetric<T> om, const double* __restrict__ 
 // while owners write the next ones. Workgroup 0 records the scalars.
 constexpr int kUpdBlock = 512;
 constexpr int kUpdCams = 64;
-constexpr int kUpdItems = 4;   // a camera's partials up to this count are loaded at once
+constexpr int kUpdDots = 8;   // item dots per thread loaded at once
 
 template <typename T, int D>
 __global__ void __launch_bounds__(kUpdBlock)
 k_pcg_update(int Ca, int k, const double* __restrict__ Minv, const T* __restrict__ Ustar,
-             const int* __restrict__ item_off, int nslot, const double* __restrict__ part,
+             const int* __restrict__ item_off, int nit, int nslot, const double* __restrict__ part,
              double* __restrict__ terms, double* __restrict__ x, double* __restrict__ r,
              double* __restrict__ u, double* __restrict__ p, double* __restrict__ sv,
              double* __restrict__ Uu, MvRec<T, D>* __restrict__ mvt, PcgState* st) {
   __shared__ double smem[3 * (kUpdBlock / kWave)];
   __shared__ double s_bcast[2];
+  __shared__ double s_items[kUpdCams][D];
   __shared__ int s_go;
   const double* tin = terms + (k & 1) * 3 * Ca;
   double* tout = terms + ((k + 1) & 1) * 3 * Ca;
   const int s = blockIdx.x * kUpdCams + threadIdx.x;
   const bool own = threadIdx.x < kUpdCams && s < Ca;
+  {
+    // a camera's item partials, summed by a group of kUpdLanes lanes: lane g takes items
+    // g, g + kUpdLanes, ... in order, then a fixed tree over the group
+    constexpr int kUpdLanes = kUpdBlock / kUpdCams;
+    const int jc = int(threadIdx.x) / kUpdLanes, g = int(threadIdx.x) % kUpdLanes;
+    const int sc = blockIdx.x * kUpdCams + jc;
+    double ws[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) ws[i] = 0.0;
+    if (sc < Ca) {
+      const int i1 = item_off[sc + 1];
+      for (int it = item_off[sc] + g; it < i1; it += kUpdLanes) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) ws[i] += part[i * nslot + it];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < D; ++i) ws[i] = group_sum<kUpdLanes>(ws[i]);
+    if (g == 0) {
+#pragma unroll
+      for (int i = 0; i < D; ++i) s_items[jc][i] = ws[i];
+    }
+  }
   // every load the owner needs is issued before the reduction
   double pv[D], wv[D], sv0[D], rv[D], uv[D], xv[D], m[sym_count(D)];
   T us[sym_count(D)];
@@ -1438,22 +1525,6 @@ k_pcg_update(int Ca, int k, const double* __restrict__ Minv, const T* __restrict
       m[q] = Minv[q * Ca + s];
       us[q] = Ustar[q * Ca + s];
     }
-    const int i0 = item_off[s], i1 = item_off[s + 1];
-    double pt[kUpdItems][D];
-#pragma unroll
-    for (int q = 0; q < kUpdItems; ++q) {
-#pragma unroll
-      for (int i = 0; i < D; ++i) pt[q][i] = i0 + q < i1 ? part[i * nslot + i0 + q] : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < kUpdItems; ++q) {
-#pragma unroll
-      for (int i = 0; i < D; ++i) wv[i] -= pt[q][i];
-    }
-    for (int it = i0 + kUpdItems; it < i1; ++it) {
-#pragma unroll
-      for (int i = 0; i < D; ++i) wv[i] -= part[i * nslot + it];
-    }
   }
   double acc[3] = {0.0, 0.0, 0.0};   // gamma, delta, rho
   for (int c = threadIdx.x; c < Ca; c += kUpdBlock) {
@@ -1461,8 +1532,19 @@ k_pcg_update(int Ca, int k, const double* __restrict__ Minv, const T* __restrict
     acc[1] += tin[Ca + c];
     acc[2] += tin[2 * Ca + c];
   }
-#pragma unroll 4
-  for (int j = threadIdx.x; j < nslot; j += kUpdBlock) acc[1] -= part[D * nslot + j];
+  {   // the items' dots: a first batch of loads all in flight, then the rest
+    const double* dot = part + size_t(D) * nslot;
+    double dd[kUpdDots];
+#pragma unroll
+    for (int q = 0; q < kUpdDots; ++q) {
+      const int j = int(threadIdx.x) + q * kUpdBlock;
+      dd[q] = j < nit ? dot[j] : 0.0;
+    }
+    for (int j = int(threadIdx.x) + kUpdDots * kUpdBlock; j < nit; j += kUpdBlock)
+      acc[1] -= dot[j];
+#pragma unroll
+    for (int q = 0; q < kUpdDots; ++q) acc[1] -= dd[q];
+  }
   // thread 0 reads the state once for the whole workgroup
   int done0 = 0;
   double tol2 = 0.0, bb = 0.0, gprev = 0.0, aprev = 0.0;
@@ -1510,6 +1592,8 @@ k_pcg_update(int Ca, int k, const double* __restrict__ Minv, const T* __restrict
   __syncthreads();
   if (!s_go || !own) return;
   const double alpha = s_bcast[0], beta = s_bcast[1];
+#pragma unroll
+  for (int i = 0; i < D; ++i) wv[i] -= s_items[threadIdx.x][i];   // w = U* u - the partials
 #pragma unroll
   for (int i = 0; i < D; ++i) {
     const double pi = uv[i] + beta * pv[i];
@@ -2640,29 +2724,23 @@ k_gp_schur_point_lds(Compact<T> cp, const V4<T>* __restrict__ a_pm,
 template <typename T>
 __global__ void __launch_bounds__(kCamBlock)
 k_gp_schur_cam(Compact<T> cp, const V4<T>* __restrict__ a_cm, const double* __restrict__ u,
-               const P3<T>* __restrict__ zq, int K, const int* __restrict__ item_off,
-               const int* __restrict__ item_cam, int nslot, double* __restrict__ part,
-               const PcgState* __restrict__ st) {
+               const P3<T>* __restrict__ zq_cm, CamItems it, int nslot,
+               double* __restrict__ part, const PcgState* __restrict__ st) {
   if (st->done) return;
+  const int4 rec = it.at[(blockIdx.x % it.R) * it.cap + blockIdx.x / it.R];
+  if (rec.x < 0) return;
   const int Ca = cp.Ca;
-  const int i = blockIdx.x;
-  if (i >= item_off[Ca]) {
-    if (threadIdx.x == 0) part[3 * nslot + i] = 0.0;
-    return;
-  }
-  const int s = item_cam[i];
-  const int sb = cp.cm_off[s] + (i - item_off[s]) * K;
-  const int se = min(sb + K, cp.cm_off[s + 1]);
+  const int i = rec.x, s = rec.y, sb = rec.z, se = rec.w;
+  __shared__ T smem[3 * (kCamBlock / kWave)];
   double us[3];
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int q = 0; q < 3; ++q) us[q] = u[q * Ca + s];
+    for (int c = 0; c < 3; ++c) us[c] = u[c * Ca + s];
   }
-  __shared__ T smem[3 * (kCamBlock / kWave)];
   T acc[3] = {T(0), T(0), T(0)};
 #pragma unroll 2
   for (int k = sb + threadIdx.x; k < se; k += kCamBlock) {
-    const P3<T> zv = zq[k];
+    const P3<T> zv = zq_cm[k];
     const T z3[3] = {zv.x, zv.y, zv.z};
     T o[3];
     gp_apply(a_cm[k], z3, o);
@@ -2674,10 +2752,10 @@ k_gp_schur_cam(Compact<T> cp, const V4<T>* __restrict__ a_cm, const double* __re
   if (threadIdx.x == 0) {
     double pd = 0.0;
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const double v = double(acc[q]);
-      part[q * nslot + i] = v;
-      pd += us[q] * v;
+    for (int c = 0; c < 3; ++c) {
+      const double v = double(acc[c]);
+      part[c * nslot + i] = v;
+      pd += us[c] * v;
     }
     part[3 * nslot + i] = pd;
   }
@@ -2996,16 +3074,31 @@ void with_dim_pcg(int D, F&& f) {
     with_dim(D, f);
 }
 
+void launch_range_bounds(hipStream_t s, int Ca, int R, int ppx, const int* cm_off,
+                         const int* cm_pt, int* rb) {
+  if (Ca <= 0 || R <= 1) return;
+  launch_k(k_range_bounds, dim3(blocks_for(int64_t(Ca) * R)), dim3(kBlock), 0, s, Ca, R, ppx,
+           cm_off, cm_pt, rb);
+}
+
 template <typename T>
 void launch_pcg_init(hipStream_t s, int D, int Ca, const double* b, const double* Minv,
-                     const T* Ustar, const int* cm_off, int K, int* item_off, int* item_cam,
+                     const T* Ustar, const int* cm_off, const int* rb, int K, CamItems it,
                      double* x, double* r, double* u, double* p, double* sv, double* Uu,
                      double* terms, void* mvt, PcgState* st, double tol2, int max_iter) {
   with_dim_pcg(D, [&](auto Dc) {
-    launch_k(k_pcg_init<T, Dc()>, dim3(1), dim3(1024), 0, s, Ca, b, Minv, Ustar, cm_off, K,
-             item_off, item_cam, x, r, u, p, sv, Uu, terms, static_cast<MvRec<T, Dc()>*>(mvt),
-             st, tol2, max_iter);
+    launch_k(k_pcg_init<T, Dc()>, dim3(1), dim3(1024), 0, s, Ca, b, Minv, Ustar, cm_off, rb, K,
+             it, x, r, u, p, sv, Uu, terms, static_cast<MvRec<T, Dc()>*>(mvt), st, tol2,
+             max_iter);
   });
+}
+
+// Camera-pass grid: one workgroup per item slot up to the largest range's count (workgroups
+// past their own range's last item return at once), so that the hardware hands items to CUs
+// as they free up: item sizes vary by orders of magnitude (26.5 us against 31.4 us for a
+// persistent grid of 8 workgroups per CU on the 1000-camera workload).
+unsigned cam_grid(const CamItems& it, const DevLimits&) {
+  return unsigned(std::max(1, std::min(it.slots, it.cap))) * unsigned(it.R);
 }
 
 template <typename T, bool ADJ, int G, int D>
@@ -3063,30 +3156,29 @@ void launch_schur_point(hipStream_t s, bool adj, int D, int G, const Model& m,
 
 template <typename T>
 void launch_schur_cam(hipStream_t s, bool adj, int D, const Model& m, const Compact<T>& cp,
-                      ObsMetric<T> om, const double* u, const P3<T>* zq, int K,
-                      const int* item_off, const int* item_cam, int nslot, double* part,
-                      const PcgState* st) {
+                      ObsMetric<T> om, const double* u, const P3<T>* zq, CamItems it,
+                      int nslot, double* part, const PcgState* st, const DevLimits& dl) {
   if (cp.Ca <= 0 || nslot <= 0) return;
-  const unsigned grid = unsigned(nslot);   // items <= nslot; the others return at once
+  const unsigned grid = cam_grid(it, dl);
   if (adj)
-    launch_k((k_schur_cam<T, true, 6>), dim3(grid), dim3(kCamBlock), 0, s, m, cp, om, u, zq, K,
-             item_off, item_cam, nslot, part, st);
+    launch_k((k_schur_cam<T, true, 6>), dim3(grid), dim3(kCamBlock), 0, s, m, cp, om, u, zq, it,
+             nslot, part, st);
   else
     with_dim(D, [&](auto Dc) {
       launch_k((k_schur_cam<T, false, Dc()>), dim3(grid), dim3(kCamBlock), 0, s, m, cp, om, u,
-               zq, K, item_off, item_cam, nslot, part, st);
+               zq, it, nslot, part, st);
     });
 }
 
 template <typename T>
 void launch_pcg_update(hipStream_t s, int D, int Ca, int k, const double* Minv, const T* Ustar,
-                       const int* item_off, int nslot, const double* part, double* terms,
-                       double* x, double* r, double* u, double* p, double* sv, double* Uu,
-                       void* mvt, PcgState* st) {
+                       const int* item_off, int nit, int nslot, const double* part,
+                       double* terms, double* x, double* r, double* u, double* p, double* sv,
+                       double* Uu, void* mvt, PcgState* st) {
   if (Ca <= 0) return;
   with_dim_pcg(D, [&](auto Dc) {
     launch_k(k_pcg_update<T, Dc()>, dim3((Ca + kUpdCams - 1) / kUpdCams), dim3(kUpdBlock), 0,
-             s, Ca, k, Minv, Ustar, item_off, nslot, part, terms, x, r, u, p, sv, Uu,
+             s, Ca, k, Minv, Ustar, item_off, nit, nslot, part, terms, x, r, u, p, sv, Uu,
              static_cast<MvRec<T, Dc()>*>(mvt), st);
   });
 }
@@ -3223,17 +3315,17 @@ void launch_adjoint_obs(hipStream_t s, const Model& m, const Compact<T>& cp, Obs
                                        double*, double*, double*);                             \
   template void launch_mv_table<T>(hipStream_t, int, int, const Cam<double>*, void*);         \
   template void launch_pcg_init<T>(hipStream_t, int, int, const double*, const double*,       \
-                                   const T*, const int*, int, int*, int*, double*, double*,   \
-                                   double*, double*, double*, double*, double*, void*,        \
-                                   PcgState*, double, int);                                    \
+                                   const T*, const int*, const int*, int, CamItems, double*,  \
+                                   double*, double*, double*, double*, double*, double*,      \
+                                   void*, PcgState*, double, int);                             \
   template void launch_schur_point<T>(hipStream_t, bool, int, int, const Model&,              \
                                       const Compact<T>&, ObsMetric<T>, const void*, const T*, \
                                       P3<T>*, const PcgState*, const DevLimits&);              \
   template void launch_schur_cam<T>(hipStream_t, bool, int, const Model&, const Compact<T>&,  \
-                                    ObsMetric<T>, const double*, const P3<T>*, int,           \
-                                    const int*, const int*, int, double*, const PcgState*);   \
+                                    ObsMetric<T>, const double*, const P3<T>*, CamItems, int, \
+                                    double*, const PcgState*, const DevLimits&);              \
   template void launch_pcg_update<T>(hipStream_t, int, int, int, const double*, const T*,     \
-                                     const int*, int, const double*, double*, double*,        \
+                                     const int*, int, int, const double*, double*, double*,   \
                                      double*, double*, double*, double*, double*, void*,      \
                                      PcgState*);                                               \
   template void launch_x_to_mv<T>(hipStream_t, int, int, const double*, void*, PcgState*);    \
@@ -3417,11 +3509,11 @@ void launch_gp_schur_point(hipStream_t s, int G, const Compact<T>& cp, const V4<
 
 template <typename T>
 void launch_gp_schur_cam(hipStream_t s, const Compact<T>& cp, const V4<T>* a_cm,
-                         const double* u, const P3<T>* zq, int K, const int* item_off,
-                         const int* item_cam, int nslot, double* part, const PcgState* st) {
+                         const double* u, const P3<T>* zq_cm, CamItems it, int nslot,
+                         double* part, const PcgState* st, const DevLimits& dl) {
   if (cp.Ca <= 0 || nslot <= 0) return;
-  launch_k(k_gp_schur_cam<T>, dim3(nslot), dim3(kCamBlock), 0, s, cp, a_cm, u, zq, K, item_off,
-           item_cam, nslot, part, st);
+  launch_k(k_gp_schur_cam<T>, dim3(cam_grid(it, dl)), dim3(kCamBlock), 0, s, cp, a_cm, u,
+           zq_cm, it, nslot, part, st);
 }
 
 template <typename T>
@@ -3475,8 +3567,8 @@ void launch_gp_scatter(hipStream_t s, int Pa, int Ca, int64_t Nh, const int* pt_
                                          const void*, const T*, P3<T>*, const PcgState*,      \
                                          const DevLimits&);                                   \
   template void launch_gp_schur_cam<T>(hipStream_t, const Compact<T>&, const V4<T>*,          \
-                                       const double*, const P3<T>*, int, const int*,          \
-                                       const int*, int, double*, const PcgState*);            \
+                                       const double*, const P3<T>*, CamItems, int, double*,   \
+                                       const PcgState*, const DevLimits&);                    \
   template void launch_gp_backsub<T>(hipStream_t, int, const Compact<T>&, const V4<T>*,       \
                                      const T*, const double*, const double*, double*);        \
   template int launch_gp_candidate<T>(hipStream_t, int, const Compact<T>&, const int*,        \
