@@ -187,7 +187,8 @@ struct ba_ctx {
   // camera segments they are cut at
   int *item_off = nullptr, *rb = nullptr;
   int4* item_at = nullptr;
-  int it_R = 1, it_cap = 0, it_nslot = 0, it_slots = 0, it_count = 0;
+  int it_R = 1, it_cap = 0, it_nslot = 0, it_slots = 0, it_count = 0, it_K = 0;
+  bool items_ok = false;   // the items match the current extraction (and it_R, it_K)
 
   // explicit reduced camera system (solver = BA_SOLVER_EXPLICIT), sized per extraction
   Arena ex;
@@ -500,6 +501,7 @@ void alloc_obs_buffers(ba_ctx& c) {
   c.wv = A.alloc<double>(nd * size_t(C));          // U* u of the current PCG direction
   c.dots = A.alloc<double>(2 * 3 * size_t(C));     // per-camera terms, two parities
   c.part = A.alloc<double>((nd + 1) * item_slots(C));   // camera-pass partials
+  c.items_ok = false;
   c.item_off = A.alloc<int>(size_t(C) + 2);
   c.item_at = A.alloc<int4>(size_t(kMaxRanges) * (size_t(C) + kCamChunks));
   c.rb = A.alloc<int>(size_t(kMaxRanges) * C);
@@ -592,8 +594,8 @@ int plan_items(ba_ctx& c, int R, int nch) {
   return c.it_nslot;
 }
 
-// After the PCG init: the item count and the largest item count of a range, which size the
-// update's reduction and the camera-pass grid (one host round trip per solve).
+// After the item build: the item count and the largest item count of a range, which size the
+// update's reduction and the camera-pass grids (one host round trip per build).
 void read_item_counts(ba_ctx& c) {
   HIP_CHECK(hipMemcpyAsync(c.h_pin + 24, c.item_off + c.Ca, 2 * sizeof(int),
                            hipMemcpyDeviceToHost, c.stream));
@@ -604,12 +606,26 @@ void read_item_counts(ba_ctx& c) {
   c.it_slots = std::max(0, std::min(n[1], c.it_cap));
 }
 
+// Builds the camera-pass items (R ranges, at most K positions each, nch = ceil(Nc / K)) unless
+// the current ones are those; returns the partial-slot count.
+int ensure_items(ba_ctx& c, int R, int K, int nch) {
+  if (c.items_ok && c.it_R == R && c.it_K == K) return c.it_nslot;
+  plan_items(c, R, nch);
+  launch_build_items(c.stream, c.Ca, c.cm_off_hat, c.rb, K, items_view(c));
+  HIP_LAUNCH_CHECK();
+  read_item_counts(c);
+  c.it_K = K;
+  c.items_ok = true;
+  return c.it_nslot;
+}
+
 // ------------------------------------------------------------------ extraction
 // Validity, activity fixpoint, ranks and compaction at the current parameters.
 // Dynamic parameter extraction. gp selects the global-positioning rules: validity is finite
 // data only, 3 rows per pinned and 2 per free observation, cameras need 3 rows.
 void extract(ba_ctx& c, bool gp = false) {
   c.gp_lin_valid = false;   // the compaction buffers are rebuilt
+  c.items_ok = false;
   const Model m = c.model();
   hipStream_t s = c.stream;
   const int64_t N = c.N;
@@ -922,11 +938,10 @@ int run_pcg(ba_ctx& c, bool adj, double rel_tol, int max_iters, PcgState* out_st
     K = std::numeric_limits<int>::max() / 2;
     nch = 0;
   }
-  const int nslot = plan_items(c, expl ? 1 : kMaxRanges, nch);
-  launch_pcg_init<T>(s, c.D, c.Ca, c.b, c.Minv, Ustar, c.cm_off_hat, c.rb, K, items_view(c), c.x,
-                     c.r, c.u, c.p, c.sv, c.wv, c.dots, mvt, c.pcg, rel_tol * rel_tol, max_iters);
+  const int nslot = ensure_items(c, expl ? 1 : kMaxRanges, K, nch);
+  launch_pcg_init<T>(s, c.D, c.Ca, c.b, c.Minv, Ustar, c.x, c.r, c.u, c.p, c.sv, c.wv, c.dots,
+                     mvt, c.pcg, rel_tol * rel_tol, max_iters);
   HIP_LAUNCH_CHECK();
-  read_item_counts(c);
   const CamItems items = items_view(c);
   const int every = std::max(1, c.opt.pcg_check_every);
   const double bp = bytes_schur_point(c), bc = bytes_schur_cam(c), bu = bytes_pcg_update(c);
@@ -1190,12 +1205,10 @@ int gp_run_pcg(ba_ctx& c, PcgState* out_state) {
   const T* Ustar = static_cast<const T*>(c.Ustar);
   int K = 0, nch = 0;
   cam_chunking(c.Nc, K, nch);
-  const int nslot = plan_items(c, 1, nch);   // z per camera-major position: no ranges
-  launch_pcg_init<T>(s, 3, c.Ca, c.b, c.Minv, Ustar, c.cm_off_hat, c.rb, K, items_view(c), c.x,
-                     c.r, c.u, c.p, c.sv, c.wv, c.dots, c.mvt, c.pcg,
-                     c.opt.pcg_rel_tol * c.opt.pcg_rel_tol, c.opt.pcg_max_iters);
+  const int nslot = ensure_items(c, 1, K, nch);   // z per camera-major position: no ranges
+  launch_pcg_init<T>(s, 3, c.Ca, c.b, c.Minv, Ustar, c.x, c.r, c.u, c.p, c.sv, c.wv, c.dots,
+                     c.mvt, c.pcg, c.opt.pcg_rel_tol * c.opt.pcg_rel_tol, c.opt.pcg_max_iters);
   HIP_LAUNCH_CHECK();
-  read_item_counts(c);
   const CamItems items = items_view(c);
   HIP_LAUNCH_CHECK();
   const double ts = double(sizeof(T));
@@ -1516,6 +1529,7 @@ struct ScratchSwap {
       : c(cc), flags(cc.flags), pcg(cc.pcg), pcg_diag(cc.pcg_diag), diag(cc.diag),
         partials(cc.partials), dots(cc.dots), part(cc.part), item_off(cc.item_off),
         rb(cc.rb), item_at(cc.item_at), scan(cc.scan_temp) {
+    c.items_ok = false;   // the items live in the buffers being swapped
     c.flags = reinterpret_cast<int*>(base + p.flags);
     c.pcg = reinterpret_cast<PcgState*>(base + p.pcg);
     c.pcg_diag = reinterpret_cast<PcgState*>(base + p.pcg_diag);
@@ -1540,6 +1554,7 @@ struct ScratchSwap {
     c.item_at = item_at;
     c.rb = rb;
     c.scan_temp = scan;
+    c.items_ok = false;
   }
   ScratchSwap(const ScratchSwap&) = delete;
   ScratchSwap& operator=(const ScratchSwap&) = delete;

@@ -253,20 +253,6 @@ template <typename T>
 void launch_point_damp(hipStream_t s, int Pa, double lam, double dmin, double dmax,
                        const double* V, const double* gp, const double* rhs_p, T* Vinv,
                        double* hp, PtRec<T>* prec, int* bad);
-// Per camera slot: U = J_c^T M J_c, gc, b = rhs_c - sum W hp, S_cc = U* - sum W Vinv W^T and
-// its inverse (Cholesky, float64). rhs_c = -gc when rhs_c == nullptr. SoA outputs.
-// Scc (optional, SoA like Minv) receives S_cc itself for the explicit reduced system.
-template <typename T>
-void launch_cam_assemble(hipStream_t s, bool adj, int D, const Model& m, const Compact<T>& cp,
-                         ObsMetric<T> om, double lam, double dmin, double dmax,
-                         const PtRec<T>* prec, const double* rhs_c, double* Uraw, T* Ustar,
-                         double* gc, double* b, double* Minv, double* Scc = nullptr);
-
-// ------------------------------------------------------------------ PCG on S
-// x = 0, r = b, u = M^-1 r (also into the matvec records), p = s = 0, Uu = U* u and the
-// per-camera terms r.u, u.U*u, r.r of iteration 0 (terms: 2 x 3 arrays of Ca, SoA, the
-// first three for even iterations); the camera-pass items: camera s owns items
-// item_off[s] .. item_off[s + 1] - 1 (item_cam[i] = s), one per K positions of its segment.
 // Items of the camera pass. A camera's segment of camera-major positions (sorted by point
 // rank) is split at the boundaries of R point ranges (R = 1, or 8: the eighths of the point
 // ranks that the point pass gives the 8 XCDs), and every piece is cut into items of at most K
@@ -296,11 +282,28 @@ inline void cam_chunking(int Nc, int& K, int& nchunks) {
 // r * ppx (r = 1 .. R - 1; row 0 is the segment start).
 void launch_range_bounds(hipStream_t s, int Ca, int R, int ppx, const int* cm_off,
                          const int* cm_pt, int* rb);
+// Builds the items: K positions at most, R ranges cut at rb (R = 1: rb unused).
+void launch_build_items(hipStream_t s, int Ca, const int* cm_off, const int* rb, int K,
+                        CamItems it);
+// Per camera slot: U = J_c^T M J_c, gc, b = rhs_c - sum W hp, S_cc = U* - sum W Vinv W^T and
+// its inverse (Cholesky, float64). rhs_c = -gc when rhs_c == nullptr. SoA outputs.
+// Scc (optional, SoA like Minv) receives S_cc itself for the explicit reduced system.
+template <typename T>
+void launch_cam_assemble(hipStream_t s, bool adj, int D, const Model& m, const Compact<T>& cp,
+                         ObsMetric<T> om, double lam, double dmin, double dmax,
+                         const PtRec<T>* prec, const double* rhs_c, double* Uraw, T* Ustar,
+                         double* gc, double* b, double* Minv, double* Scc = nullptr);
+
+// ------------------------------------------------------------------ PCG on S
+// x = 0, r = b, u = M^-1 r (also into the matvec records), p = s = 0, Uu = U* u and the
+// per-camera terms r.u, u.U*u, r.r of iteration 0 (terms: 2 x 3 arrays of Ca, SoA, the
+// first three for even iterations); the camera-pass items: camera s owns items
+// item_off[s] .. item_off[s + 1] - 1 (item_cam[i] = s), one per K positions of its segment.
 template <typename T>
 void launch_pcg_init(hipStream_t s, int D, int Ca, const double* b, const double* Minv,
-                     const T* Ustar, const int* cm_off, const int* rb, int K, CamItems it,
-                     double* x, double* r, double* u, double* p, double* sv, double* Uu,
-                     double* terms, void* mvt, PcgState* st, double tol2, int max_iter);
+                     const T* Ustar, double* x, double* r, double* u, double* p, double* sv,
+                     double* Uu, double* terms, void* mvt, PcgState* st, double tol2,
+                     int max_iter);
 // Camera-side launchers take the camera dimension D: 6 (pose) or 7 (pose and focal length,
 // matvec records MvCamF); the adjoint mode runs with D = 6 only.
 

@@ -1010,18 +1010,12 @@ k_range_bounds(int Ca, int R, int ppx, const int* __restrict__ cm_off,
   rb[t] = lo;
 }
 
-template <typename T, int D>
+// Builds the items of the camera passes (see CamItems): R + 1 exclusive scans over the
+// cameras in tiles of the block, of each camera's item count (numbering camera by camera) and
+// of its count in every range (the per-range lists). One workgroup of 1024 threads.
 __global__ void __launch_bounds__(1024)
-k_pcg_init(int Ca, const double* __restrict__ b, const double* __restrict__ Minv,
-           const T* __restrict__ Ustar, const int* __restrict__ cm_off,
-           const int* __restrict__ rb, int K, CamItems it, double* __restrict__ x,
-           double* __restrict__ r, double* __restrict__ u, double* __restrict__ p,
-           double* __restrict__ sv, double* __restrict__ Uu, double* __restrict__ terms,
-           MvRec<T, D>* __restrict__ mvt, PcgState* st, double tol2, int max_iter) {
-  __shared__ double smem[1024 / kWave];
-  // items of the camera pass (see CamItems): R + 1 exclusive scans over the cameras in tiles
-  // of the block, of each camera's item count (numbering camera by camera) and of its count
-  // in every range (the per-range lists)
+k_build_items(int Ca, const int* __restrict__ cm_off, const int* __restrict__ rb, int K,
+              CamItems it) {
   constexpr int NV = kMaxRanges + 1;
   __shared__ int s_wave[NV][1024 / kWave];
   __shared__ int s_carry[NV];
@@ -1094,6 +1088,16 @@ k_pcg_init(int Ca, const double* __restrict__ b, const double* __restrict__ Minv
     for (int q = 0; q < R; ++q) mx = max(mx, s_carry[1 + q]);
     it.off[Ca + 1] = mx;
   }
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(1024)
+k_pcg_init(int Ca, const double* __restrict__ b, const double* __restrict__ Minv,
+           const T* __restrict__ Ustar, double* __restrict__ x,
+           double* __restrict__ r, double* __restrict__ u, double* __restrict__ p,
+           double* __restrict__ sv, double* __restrict__ Uu, double* __restrict__ terms,
+           MvRec<T, D>* __restrict__ mvt, PcgState* st, double tol2, int max_iter) {
+  __shared__ double smem[1024 / kWave];
   double acc[1] = {0.0};   // b.b
   for (int s = threadIdx.x; s < Ca; s += blockDim.x) {
     double rv[D], uv[D];
@@ -3040,6 +3044,14 @@ void with_dim(int D, F&& f) {
     f(std::integral_constant<int, 6>{});
 }
 
+// Camera-pass grid: one workgroup per item slot up to the largest range's count (workgroups
+// past their own range's last item return at once), so that the hardware hands items to CUs
+// as they free up: item sizes vary by orders of magnitude (26.5 us against 31.4 us for a
+// persistent grid of 8 workgroups per CU on the 1000-camera workload).
+unsigned cam_grid(const CamItems& it, const DevLimits&) {
+  return unsigned(std::max(1, std::min(it.slots, it.cap))) * unsigned(it.R);
+}
+
 template <typename T>
 void launch_cam_assemble(hipStream_t s, bool adj, int D, const Model& m, const Compact<T>& cp,
                          ObsMetric<T> om, double lam, double dmin, double dmax,
@@ -3081,25 +3093,22 @@ void launch_range_bounds(hipStream_t s, int Ca, int R, int ppx, const int* cm_of
            cm_off, cm_pt, rb);
 }
 
+void launch_build_items(hipStream_t s, int Ca, const int* cm_off, const int* rb, int K,
+                        CamItems it) {
+  launch_k(k_build_items, dim3(1), dim3(1024), 0, s, Ca, cm_off, rb, K, it);
+}
+
 template <typename T>
 void launch_pcg_init(hipStream_t s, int D, int Ca, const double* b, const double* Minv,
-                     const T* Ustar, const int* cm_off, const int* rb, int K, CamItems it,
-                     double* x, double* r, double* u, double* p, double* sv, double* Uu,
-                     double* terms, void* mvt, PcgState* st, double tol2, int max_iter) {
+                     const T* Ustar, double* x, double* r, double* u, double* p, double* sv,
+                     double* Uu, double* terms, void* mvt, PcgState* st, double tol2,
+                     int max_iter) {
   with_dim_pcg(D, [&](auto Dc) {
-    launch_k(k_pcg_init<T, Dc()>, dim3(1), dim3(1024), 0, s, Ca, b, Minv, Ustar, cm_off, rb, K,
-             it, x, r, u, p, sv, Uu, terms, static_cast<MvRec<T, Dc()>*>(mvt), st, tol2,
-             max_iter);
+    launch_k(k_pcg_init<T, Dc()>, dim3(1), dim3(1024), 0, s, Ca, b, Minv, Ustar, x, r, u, p, sv,
+             Uu, terms, static_cast<MvRec<T, Dc()>*>(mvt), st, tol2, max_iter);
   });
 }
 
-// Camera-pass grid: one workgroup per item slot up to the largest range's count (workgroups
-// past their own range's last item return at once), so that the hardware hands items to CUs
-// as they free up: item sizes vary by orders of magnitude (26.5 us against 31.4 us for a
-// persistent grid of 8 workgroups per CU on the 1000-camera workload).
-unsigned cam_grid(const CamItems& it, const DevLimits&) {
-  return unsigned(std::max(1, std::min(it.slots, it.cap))) * unsigned(it.R);
-}
 
 template <typename T, bool ADJ, int G, int D>
 void schur_point_launch(hipStream_t s, const Model& m, const Compact<T>& cp, ObsMetric<T> om,
@@ -3312,12 +3321,11 @@ void launch_adjoint_obs(hipStream_t s, const Model& m, const Compact<T>& cp, Obs
   template void launch_cam_assemble<T>(hipStream_t, bool, int, const Model&,                  \
                                        const Compact<T>&, ObsMetric<T>, double, double, double,\
                                        const PtRec<T>*, const double*, double*, T*, double*,  \
-                                       double*, double*, double*);                             \
+                                       double*, double*, double*);                                      \
   template void launch_mv_table<T>(hipStream_t, int, int, const Cam<double>*, void*);         \
   template void launch_pcg_init<T>(hipStream_t, int, int, const double*, const double*,       \
-                                   const T*, const int*, const int*, int, CamItems, double*,  \
-                                   double*, double*, double*, double*, double*, double*,      \
-                                   void*, PcgState*, double, int);                             \
+                                   const T*, double*, double*, double*, double*, double*,     \
+                                   double*, double*, void*, PcgState*, double, int);           \
   template void launch_schur_point<T>(hipStream_t, bool, int, int, const Model&,              \
                                       const Compact<T>&, ObsMetric<T>, const void*, const T*, \
                                       P3<T>*, const PcgState*, const DevLimits&);              \
