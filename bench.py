@@ -254,17 +254,20 @@ def kernel_summary(res):
     )
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "schur_point_large_mixed_traffic.txt")
+def traffic_file(kernel, scene):
+    """The committed counter summary of `kernel` on `scene` (mixed precision)."""
+    return os.path.join(ROOT, "profiles", f"{kernel}_{scene}_mixed_traffic.txt")
 
 
 def measured_traffic(kernel, scene):
-    """HBM bytes per launch of `kernel` from the committed counter summary, or None when the
-    summary is for another kernel or workload, or the library sources changed since."""
+    """HBM bytes per launch of `kernel` from its committed counter summary, or None when there
+    is none for this kernel and workload, or the library sources changed since."""
     import hashlib
-    if not os.path.exists(TRAFFIC_FILE):
+    path = traffic_file(kernel, scene)
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if line.strip() and not line.startswith("#"):
             k, _, v = line.strip().partition(" ")
             kv[k] = v.strip()

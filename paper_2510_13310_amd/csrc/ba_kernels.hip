@@ -1321,12 +1321,11 @@ k_schur_point(Model m, Compact<T> cp, ObsMetric<T> om, const MvRec<T, D>* __rest
   schur_point_one<T, ADJ, G, D>(m, cp, om, mvt, Vinv, zq, r, live, l, p);
 }
 
-// Grid-stride variant for tables that fit in LDS: each 1024-thread workgroup (one resident
-// per CU) copies the camera records into LDS once, so the random per-observation record
-// reads hit LDS.
+// Grid-stride variant for tables that fit in LDS: each 1024-thread workgroup copies the camera
+// records into LDS once, so the random per-observation record reads hit LDS.
 // XCD x owns the x-th eighth of the point ranks (ppx points) and its workgroups take that
-// range's tiles round-robin: the XCD works on consecutive tiles at any moment, so the z
-// stores into each camera segment fill whole cache lines while they are in its L2.
+// range's tiles round-robin, so the z vectors of a range are written through the L2 of the
+// XCD whose camera-pass workgroups read them (CamItems).
 // Loads run ahead of the work: the offsets two tiles ahead and, in float32, the next tile's
 // first-observation data are issued before the current tile is processed.
 constexpr int kPtLdsBlock = 1024;
@@ -1386,8 +1385,14 @@ k_schur_point_lds(Model m, Compact<T> cp, ObsMetric<T> om, const MvRec<T, D>* __
 // the result does not depend on scheduling. Workgroup b takes slot b / R of range b % R: the
 // workgroups of XCD r (b % 8 = r) take range r's items, whose z vectors the point pass has
 // just written through that XCD's L2 (without the split, 43 us and 2.9x the fetched bytes on
-// the 1000-camera workload). Two-wave workgroups.
-constexpr int kCamBlock = 128;
+// the 1000-camera workload). float32: one-wave workgroups (an item averages some 650
+// positions; 26.0 us against 26.6 us with two); float64: two-wave workgroups (58.3 us against
+// 62.5 us with one).
+template <typename T>
+constexpr int cam_block() {
+  return sizeof(T) == 4 ? 64 : 128;
+}
+constexpr int kCamBlock = 128;   // global-positioning camera pass
 
 // One item of the camera pass (all threads of the workgroup).
 template <typename T, bool ADJ, int D>
@@ -1406,7 +1411,7 @@ __device__ __forceinline__ void cam_item(const Model& m, const Compact<T>& cp,
 #pragma unroll
   for (int q = 0; q < D; ++q) acc[q] = T(0);
 #pragma unroll 4
-  for (int k = sb + threadIdx.x; k < se; k += kCamBlock) {
+  for (int k = sb + threadIdx.x; k < se; k += cam_block<T>()) {
     const V4<T> xw = om.xcw[k];
     const P3<T> zv = zq[cp.cm_pt[k]];
     const T Xc[3] = {xw.x, xw.y, xw.z};
@@ -1449,14 +1454,14 @@ __device__ __forceinline__ void cam_item(const Model& m, const Compact<T>& cp,
 }
 
 template <typename T, bool ADJ, int D>
-__global__ void __launch_bounds__(kCamBlock)
+__global__ void __launch_bounds__(cam_block<T>())
 k_schur_cam(Model m, Compact<T> cp, ObsMetric<T> om, const double* __restrict__ u,
             const P3<T>* __restrict__ zq, CamItems it, int nslot, double* __restrict__ part,
             const PcgState* __restrict__ st) {
   if (st->done) return;
   const int4 rec = it.at[(blockIdx.x % it.R) * it.cap + blockIdx.x / it.R];
   if (rec.x < 0) return;   // past the range's last item
-  __shared__ T smem[D * (kCamBlock / kWave)];
+  __shared__ T smem[D * (cam_block<T>() / kWave)];
   cam_item<T, ADJ, D>(m, cp, om, u, zq, rec, nslot, part, smem, cp.Ca);
 }
 
@@ -3121,12 +3126,10 @@ void schur_point_launch(hipStream_t s, const Model& m, const Compact<T>& cp, Obs
     use_lds = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(tab)) ==
               hipSuccess;
   if (use_lds) {
-    // float32 (80-byte records, two could share a CU): one workgroup per CU; with the next
-    // tile's loads in flight, 16 waves per CU stream better than 32 sharing the L1 (30 us
-    // against 38 us on the 1000-camera workload) or than more workgroups queued per CU.
-    // float64 (128-byte records, one workgroup per CU): four workgroups per CU queued, so
-    // that CUs that finish early take more tiles (96 us against 104 us with one).
-    const int grid = (dl.n_cu * (sizeof(T) == 8 ? 4 : 1) + 7) / 8 * 8;
+    // float32 (80-byte records): two workgroups per CU share it (17.1 us against 19.3 us
+    // with one on the 1000-camera workload). float64 (128-byte records, one workgroup per
+    // CU): four workgroups per CU queued, so that CUs that finish early take more tiles.
+    const int grid = (dl.n_cu * (sizeof(T) == 8 ? 4 : 2) + 7) / 8 * 8;
     const int ppx = (cp.Pa + 7) / 8;
     launch_k(k_schur_point_lds<T, ADJ, G, D>, dim3(grid), dim3(kPtLdsBlock), uint32_t(tab), s,
              m, cp, om, mvt, Vinv, zq, st, ppx);
@@ -3169,13 +3172,14 @@ void launch_schur_cam(hipStream_t s, bool adj, int D, const Model& m, const Comp
                       int nslot, double* part, const PcgState* st, const DevLimits& dl) {
   if (cp.Ca <= 0 || nslot <= 0) return;
   const unsigned grid = cam_grid(it, dl);
+  const dim3 block(cam_block<T>());
   if (adj)
-    launch_k((k_schur_cam<T, true, 6>), dim3(grid), dim3(kCamBlock), 0, s, m, cp, om, u, zq, it,
-             nslot, part, st);
+    launch_k((k_schur_cam<T, true, 6>), dim3(grid), block, 0, s, m, cp, om, u, zq, it, nslot,
+             part, st);
   else
     with_dim(D, [&](auto Dc) {
-      launch_k((k_schur_cam<T, false, Dc()>), dim3(grid), dim3(kCamBlock), 0, s, m, cp, om, u,
-               zq, it, nslot, part, st);
+      launch_k((k_schur_cam<T, false, Dc()>), dim3(grid), block, 0, s, m, cp, om, u, zq, it,
+               nslot, part, st);
     });
 }
 
