@@ -221,6 +221,7 @@ struct ba_ctx {
   PcgState* pcg_diag = nullptr;   // state of the extra matvec that measures the true residual
   double* diag = nullptr;         // |b - S x|^2, |b|^2 of that product
   double* h_pin = nullptr;   // pinned host readback buffer
+  hipEvent_t pcg_ev[2] = {nullptr, nullptr};   // the PCG state copies of two batches
 
   // LM state
   double lam = 1e-3, nu = 2.0;
@@ -261,6 +262,8 @@ struct ba_ctx {
       (void)hipEventDestroy(pe.b);
     }
     for (auto e : pool) (void)hipEventDestroy(e);
+    for (auto e : pcg_ev)
+      if (e) (void)hipEventDestroy(e);
     obs.release();
     par.release();
     if (h_pin) (void)hipHostFree(h_pin);
@@ -914,9 +917,45 @@ void setup_system(ba_ctx& c, bool adj, double lam, const double* rhs_c, const do
           });
 }
 
-// PCG on the camera Schur complement; returns the iteration count. The loop enqueues
-// pcg_check_every iterations between host reads of the device-side state; iterations after
-// convergence return at their first instruction.
+// Runs PCG iterations in batches of pcg_check_every, batch(it0, it1) enqueuing iterations
+// [it0, it1). The host reads the device-side state after each batch while the next batch is
+// already queued (two pinned slots, one event each), so the GPU does not wait for the check;
+// iterations enqueued after convergence return at their first instruction. Returns the state
+// after the last batch that did work.
+static_assert(sizeof(PcgState) <= 16 * sizeof(double), "a pinned slot holds one state");
+template <class Batch>
+PcgState pcg_batches(ba_ctx& c, int max_iters, Batch&& batch) {
+  const int every = std::max(1, c.opt.pcg_check_every);
+  hipStream_t s = c.stream;
+  int it = 0, n = 0;   // iterations and batches enqueued
+  auto slot = [&](int k) { return c.h_pin + 32 + 16 * (k & 1); };
+  auto enqueue = [&] {
+    const int it1 = std::min(max_iters, it + every);
+    batch(it, it1);
+    it = it1;
+    HIP_CHECK(hipMemcpyAsync(slot(n), c.pcg, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipEventRecord(c.pcg_ev[n & 1], s));
+    ++n;
+  };
+  PcgState st{};
+  auto read = [&](int k) {
+    HIP_CHECK(hipEventSynchronize(c.pcg_ev[k & 1]));
+    std::memcpy(&st, slot(k), sizeof(PcgState));
+  };
+  enqueue();
+  while (true) {
+    if (it >= max_iters) {   // every iteration is queued: the last batch's state
+      read(n - 1);
+      break;
+    }
+    enqueue();
+    read(n - 2);
+    if (st.done) break;   // the batch just queued returns at once
+  }
+  return st;
+}
+
+// PCG on the camera Schur complement; returns the iteration count (pcg_batches).
 template <typename T>
 int run_pcg(ba_ctx& c, bool adj, double rel_tol, int max_iters, PcgState* out_state) {
   hipStream_t s = c.stream;
@@ -943,7 +982,6 @@ int run_pcg(ba_ctx& c, bool adj, double rel_tol, int max_iters, PcgState* out_st
                      mvt, c.pcg, rel_tol * rel_tol, max_iters);
   HIP_LAUNCH_CHECK();
   const CamItems items = items_view(c);
-  const int every = std::max(1, c.opt.pcg_check_every);
   const double bp = bytes_schur_point(c), bc = bytes_schur_cam(c), bu = bytes_pcg_update(c);
   // explicit product: every block (D x D values and its key) and the row pointers once, the
   // camera vectors and S_cc
@@ -951,9 +989,8 @@ int run_pcg(ba_ctx& c, bool adj, double rel_tol, int max_iters, PcgState* out_st
                     double(c.Ca) * (8 + double(c.D) * (c.D + 1) / 2 * 8 + 3 * c.D * 8 + 8);
   const int G = lanes_per_point(c);
   P3<T>* zq = static_cast<P3<T>*>(c.zq);
-  int it = 0;
-  while (true) {
-    for (int k = 0; k < every && it < max_iters; ++k, ++it) {
+  st = pcg_batches(c, max_iters, [&](int it0, int it1) {
+    for (int it = it0; it < it1; ++it) {
       if (expl) {
         c.timed("schur_spmv", bs, it, [&] {
           launch_schur_spmv<T>(s, c.D, c.Ca, c.ex_row_ptr, c.ex_bkey,
@@ -975,11 +1012,7 @@ int run_pcg(ba_ctx& c, bool adj, double rel_tol, int max_iters, PcgState* out_st
                              c.part, c.dots, c.x, c.r, c.u, c.p, c.sv, c.wv, mvt, c.pcg);
       });
     }
-    HIP_CHECK(hipMemcpyAsync(c.h_pin, c.pcg, sizeof(PcgState), hipMemcpyDeviceToHost, s));
-    c.sync();
-    std::memcpy(&st, c.h_pin, sizeof(PcgState));
-    if (st.done || it >= max_iters) break;
-  }
+  });
   *out_state = st;
   return st.matvecs;
 }
@@ -1222,10 +1255,8 @@ int gp_run_pcg(ba_ctx& c, PcgState* out_state) {
                     double(c.Pa) * (4 + 6 * ts) + double(c.Ca) * 4 * ts;
   const double bc = double(c.Nc) * 7 * ts + double(c.Ca) * (8 + 24) + double(nslot) * 32;
   const double bu = double(c.Ca) * (48 + 4 + 48 + 6 * ts + 288 + 3 * ts) + double(nslot) * 32;
-  const int every = std::max(1, c.opt.pcg_check_every);
-  int it = 0;
-  while (true) {
-    for (int k = 0; k < every && it < c.opt.pcg_max_iters; ++k, ++it) {
+  st = pcg_batches(c, c.opt.pcg_max_iters, [&](int it0, int it1) {
+    for (int it = it0; it < it1; ++it) {
       c.timed("gp_schur_point", bp, it, [&] {
         launch_gp_schur_point<T>(s, G, cp, a_pm, c.mvt, static_cast<const T*>(c.Vinv), zq,
                                  c.pcg, c.dl);
@@ -1238,11 +1269,7 @@ int gp_run_pcg(ba_ctx& c, PcgState* out_state) {
                              c.part, c.dots, c.x, c.r, c.u, c.p, c.sv, c.wv, c.mvt, c.pcg);
       });
     }
-    HIP_CHECK(hipMemcpyAsync(c.h_pin, c.pcg, sizeof(PcgState), hipMemcpyDeviceToHost, s));
-    c.sync();
-    std::memcpy(&st, c.h_pin, sizeof(PcgState));
-    if (st.done || it >= c.opt.pcg_max_iters) break;
-  }
+  });
   *out_state = st;
   return st.matvecs;
 }
@@ -1655,6 +1682,7 @@ ba_status ba_create(const ba_options* opt, int32_t n_cams, int32_t n_points, con
       c->own_stream = true;
     }
     HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&c->h_pin), 64 * sizeof(double)));
+    for (auto& e : c->pcg_ev) HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     int dev = 0;
     HIP_CHECK(hipGetDevice(&dev));
     c->device = dev;
