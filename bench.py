@@ -70,6 +70,8 @@ def parse():
                     help="Tikhonov damping of the --forward-adjoint system (singular point "
                          "blocks under the robust-corrected metric)")
     ap.add_argument("--adjoint-precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--adjoint-hessian", default="full", choices=["full", "gauss_newton"],
+                    help="Hessian of the --forward-adjoint system (the library's default: full)")
     ap.add_argument("--refine-focal", action="store_true",
                     help="refine each camera's focal length too (7-parameter cameras), "
                          "starting from focal lengths off by up to 2%%")
@@ -154,7 +156,8 @@ def forward_adjoint(sc, iters, args, torch):
                         t(sc.points0, torch.float64), precision=args.adjoint_precision,
                         huber_px=sc.huber_px, filter_px=sc.filter_px, img_w=sc.img_w,
                         img_h=sc.img_h, pcg_rel_tol=args.pcg_tol, pcg_max_iters=args.pcg_max,
-                        max_lm_iters=iters, adjoint_damping=args.adjoint_damping, timing=1)
+                        max_lm_iters=iters, adjoint_damping=args.adjoint_damping,
+                        adjoint_hessian=args.adjoint_hessian, timing=1)
     ba.set_observations(t(sc.cam_idx, torch.int32), t(sc.pt_idx, torch.int32),
                         t(sc.xy, torch.float32))
     ba.set_depth_priors(t(sc.depth, torch.float32), t(sc.depth_valid, torch.uint8),
@@ -182,7 +185,7 @@ def forward_adjoint(sc, iters, args, torch):
     t_adj = time.perf_counter() - t0
     st = {k["name"]: k for k in ba.kernel_stats()}
     out = dict(precision=args.adjoint_precision, lambda_d=args.adjoint_lambda_d,
-               adjoint_damping=args.adjoint_damping,
+               adjoint_damping=args.adjoint_damping, adjoint_hessian=args.adjoint_hessian,
                fixed_cameras=[0],
                lm_iterations=srep["iterations"], stop_reason=srep["stop_reason"],
                initial_rms_px=round(srep["initial_rms_px"], 6),
