@@ -107,6 +107,27 @@ def test_single_step_matches_cholesky(name, lam):
     np.testing.assert_allclose(pts, new.X, rtol=0, atol=1e-9 * np.abs(new.X).max())
 
 
+@pytest.mark.parametrize("n_points", [5, 13])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-6), ("mixed", 1e-5)])
+def test_single_step_few_points(n_points, precision, tol):
+    """Fewer active points than the 8 point ranges of the matrix-free passes (4 and 13 here):
+    some XCD ranges are empty and every camera's segment splits into one-point items; the
+    step still equals the oracle's dense Schur + Cholesky step."""
+    sc = make_scene("tiny", n_points=n_points)
+    prob, opts, st = oracle_setup(sc, lambda_init=1.0)
+    new, orep = lm_step(prob, st, opts)
+    ba = gpu_setup(sc, precision, lambda_init=1.0, pcg_rel_tol=1e-13, pcg_max_iters=2000)
+    rep = ba.lm_step()
+    assert rep["n_obs_active"] == orep.extraction.obs.size
+    dc, dp = ba.get_last_step()
+    odc, odp = full_delta(orep.extraction, orep.delta, sc.n_cams, sc.n_points)
+    print(f"{n_points} points {precision}: step error cameras {rel_err(dc, odc):.2e}, "
+          f"points {rel_err(dp, odp):.2e}")
+    assert rel_err(dc, odc) < tol, rel_err(dc, odc)
+    assert rel_err(dp, odp) < tol, rel_err(dp, odp)
+    assert bool(rep["accepted"]) == orep.accepted
+
+
 _CONVERGED = {}
 
 
