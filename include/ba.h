@@ -216,12 +216,12 @@ ba_status ba_lm_step(ba_ctx* ctx, ba_step_report* rep);
 
 /* ba_lm_step for callers that cannot allocate device memory (serving loops, code that must
  * not call hipMalloc): the same LM iteration with the same results, but its per-step scratch
- * (fixpoint and damping flags, PCG states, reduction and camera-pass partials, item tables,
- * the scan workspace) lives in a static device array of 32 MiB that each GPU holds from
+ * (fixpoint and damping flags, PCG states, reduction partials, the item partials of the camera
+ * assembly and the PCG camera pass, item tables, the scan workspace) lives in a static device array of 32 MiB that each GPU holds from
  * library load to process end; the call itself allocates nothing. The context's other
  * buffers are those of ba_create and ba_set_observations. BA_ERR_ARG when the problem needs
- * more scratch than the array holds (about 2.5 bytes per point, 0.7 KB per camera, 0.2 MB and
- * the scan workspace: e.g. 2M points and 5000 cameras fit), BA_ERR_STATE with opt.timing = 1 or
+ * more scratch than the array holds (about 2.5 bytes per point, 2 KB per camera (2.5 KB with
+ * focal refinement), 0.2 MB and the scan workspace: e.g. 2M points and 5000 cameras fit), BA_ERR_STATE with opt.timing = 1 or
  * the explicit solver (both allocate). Every call on one GPU shares that GPU's array and
  * leaves its contents behind: calls that overlap in time on one GPU (from several threads or
  * streams) race and must be serialised by the caller. */

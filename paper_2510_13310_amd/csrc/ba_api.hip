@@ -419,6 +419,11 @@ ba_status guarded(ba_ctx* c, F&& f) {
 // ------------------------------------------------------------------ buffers
 // Most camera-pass items a solve can have (CamItems: R Ca + nchunks, R <= 8).
 size_t item_slots(int C) { return size_t(kMaxRanges) * size_t(C) + kCamChunks; }
+// Partial rows per item slot: the camera assembly's 2 (D (D + 1) / 2 + D), or the PCG camera
+// pass's D + 1 (which also covers global positioning, D = 3).
+size_t part_rows(int D) {
+  return std::max(2 * (size_t(D) * (D + 1) / 2 + D), size_t(D) + 1);
+}
 
 void alloc_obs_buffers(ba_ctx& c) {
   c.release_explicit();
@@ -503,7 +508,7 @@ void alloc_obs_buffers(ba_ctx& c) {
   c.sv = A.alloc<double>(nd * size_t(C));
   c.wv = A.alloc<double>(nd * size_t(C));          // U* u of the current PCG direction
   c.dots = A.alloc<double>(2 * 3 * size_t(C));     // per-camera terms, two parities
-  c.part = A.alloc<double>((nd + 1) * item_slots(C));   // camera-pass partials
+  c.part = A.alloc<double>(part_rows(c.D) * item_slots(C));   // item partials
   c.items_ok = false;
   c.item_off = A.alloc<int>(size_t(C) + 2);
   c.item_at = A.alloc<int4>(size_t(kMaxRanges) * (size_t(C) + kCamChunks));
@@ -903,15 +908,36 @@ void setup_system(ba_ctx& c, bool adj, double lam, const double* rhs_c, const do
                          static_cast<const double*>(c.V), c.gp, rhs_p, static_cast<T*>(c.Vinv),
                          c.hp, static_cast<PtRec<T>*>(c.prec), c.flags + 1);
   });
-  // per camera-major observation: the point rank, the (X_c, w) and e streams (+ eh); every
-  // point record once; per camera its blocks written
-  c.timed("cam_assemble",
-          double(c.Nc) * (4 + 8 * ts + (adj ? 3 * ts : 0)) +
-              double(c.Pa) * double(sizeof(PtRec<T>)) +
-              double(c.Ca) * (double(c.D) * (c.D + 1) / 2 * (16 + ts) + c.D * 8 * 2),
+  if (c.Ca == 0) return;
+  // the camera-pass items of this extraction (the PCG reuses them)
+  int K = 0, nch = 0;
+  cam_chunking(c.Nc, K, nch);
+  const int nslot = ensure_items(c, kMaxRanges, K, nch);
+  const CamItems items = items_view(c);
+  const double ns = double(c.D) * (c.D + 1) / 2, rows = 2 * (ns + c.D);
+  // per camera-major position the point rank and the (X_c, w) stream (+ eh); every point
+  // record once; per item its record and its rows
+  c.timed("cam_schur_items",
+          double(c.Nc) * (4 + 4 * ts + (adj ? 3 * ts : 0)) +
+              double(c.Pa) * double(sizeof(PtRec<T>)) + double(c.it_count) * (16 + 4 * rows),
           -1, [&] {
-            launch_cam_assemble<T>(s, adj, c.D, m, cp, om, lam, c.opt.diag_min, c.opt.diag_max,
-                                   static_cast<const PtRec<T>*>(c.prec), rhs_c, c.Uraw,
+            launch_cam_items<T>(s, adj, true, c.D, m, cp, om,
+                                static_cast<const PtRec<T>*>(c.prec), items, nslot, c.part,
+                                c.dl);
+          });
+  // per camera-major position the (X_c, w) and e streams (+ eh); per item its record and rows
+  c.timed("cam_u_items",
+          double(c.Nc) * (8 * ts + (adj ? 3 * ts : 0)) + double(c.it_count) * (16 + 4 * rows), -1,
+          [&] {
+            launch_cam_items<T>(s, adj, false, c.D, m, cp, om, nullptr, items, nslot, c.part,
+                                c.dl);
+          });
+  // the item rows; per camera its blocks written
+  c.timed("cam_assemble",
+          double(c.it_count) * 8 * rows + double(c.Ca) * (ns * (16 + ts) + c.D * 8 * 2 + 8), -1,
+          [&] {
+            launch_cam_assemble<T>(s, c.D, c.Ca, lam, c.opt.diag_min, c.opt.diag_max,
+                                   c.item_off, nslot, c.part, rhs_c, c.Uraw,
                                    static_cast<T*>(c.Ustar), c.gc, c.b, c.Minv,
                                    explicit_solver(c) && !adj ? c.ex_scc : nullptr);
           });
@@ -1534,7 +1560,7 @@ ScratchPlan plan_scratch(const ba_ctx& c) {
   p.diag = take(4 * sizeof(double));
   p.partials = take(5 * (size_t(c.P) * 16 / kBlock + 16) * sizeof(double));
   p.dots = take(2 * 3 * C * sizeof(double));
-  p.part = take((nd + 1) * item_slots(c.C) * sizeof(double));
+  p.part = take(part_rows(c.D) * item_slots(c.C) * sizeof(double));
   p.item_off = take((C + 2) * sizeof(int));
   p.item_at = take(kMaxRanges * (C + kCamChunks) * sizeof(int4));
   p.rb = take(kMaxRanges * C * sizeof(int));

@@ -285,14 +285,23 @@ void launch_range_bounds(hipStream_t s, int Ca, int R, int ppx, const int* cm_of
 // Builds the items: K positions at most, R ranges cut at rb (R = 1: rb unused).
 void launch_build_items(hipStream_t s, int Ca, const int* cm_off, const int* rb, int K,
                         CamItems it);
-// Per camera slot: U = J_c^T M J_c, gc, b = rhs_c - sum W hp, S_cc = U* - sum W Vinv W^T and
-// its inverse (Cholesky, float64). rhs_c = -gc when rhs_c == nullptr. SoA outputs.
-// Scc (optional, SoA like Minv) receives S_cc itself for the explicit reduced system.
+// Camera assembly. launch_cam_items: per item of `it` (positions in one point range, so the
+// gathered point records stay in one XCD's L2) the rows sum W Vinv W^T (D (D + 1) / 2) and
+// sum W hp (D) (schur), or U = J_c^T M J_c (D (D + 1) / 2) and g_c (D) (!schur), into
+// part[row * nslot + item] (2 (D (D + 1) / 2 + D) rows in all, see part_rows).
+// launch_cam_assemble: per camera slot its items' rows (item_off) added in item order, then
+// b = rhs_c - sum W hp, S_cc = U* - sum W Vinv W^T and its inverse (Cholesky, float64).
+// rhs_c = -gc when rhs_c == nullptr. SoA outputs. Scc (optional, SoA like Minv) receives S_cc
+// itself for the explicit reduced system.
 template <typename T>
-void launch_cam_assemble(hipStream_t s, bool adj, int D, const Model& m, const Compact<T>& cp,
-                         ObsMetric<T> om, double lam, double dmin, double dmax,
-                         const PtRec<T>* prec, const double* rhs_c, double* Uraw, T* Ustar,
-                         double* gc, double* b, double* Minv, double* Scc = nullptr);
+void launch_cam_items(hipStream_t s, bool adj, bool schur, int D, const Model& m,
+                      const Compact<T>& cp, ObsMetric<T> om, const PtRec<T>* prec, CamItems it,
+                      int nslot, double* part, const DevLimits& dl);
+template <typename T>
+void launch_cam_assemble(hipStream_t s, int D, int Ca, double lam, double dmin, double dmax,
+                         const int* item_off, int nslot, const double* part, const double* rhs_c,
+                         double* Uraw, T* Ustar, double* gc, double* b, double* Minv,
+                         double* Scc = nullptr);
 
 // ------------------------------------------------------------------ PCG on S
 // x = 0, r = b, u = M^-1 r (also into the matvec records), p = s = 0, Uu = U* u and the
@@ -351,6 +360,8 @@ void launch_backsub(hipStream_t s, bool adj, int D, int G, const Model& m, const
 void launch_cam_candidate(hipStream_t s, int Ca, int Cf, int D, const int* cam_src,
                           const double* x, const double* cams, const Cam<double>* camd_hat,
                           double* cand_cams, Cam<double>* cand_tab);
+// Candidate cost terms over lin_point_blocks* workgroups (5 partials per workgroup; returns the
+// workgroup count).
 template <typename T>
 int launch_point_candidate(hipStream_t s, const Model& m, const Compact<T>& cp, int D,
                            const Cam<double>* cand_tab, const double* x, const double* dp,

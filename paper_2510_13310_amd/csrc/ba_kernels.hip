@@ -804,168 +804,309 @@ __device__ bool spd_inverse(const double* A, double* out) {
 }
 
 
+// Workgroup size of the camera-major item kernels: one wave in float32 (an item averages some
+// 650 positions on the 1000-camera workload; the PCG camera pass takes 26.0 us against 26.6 us
+// with two), two in float64 (58.3 us against 62.5 us with one).
+template <typename T>
+constexpr int cam_block() {
+  return sizeof(T) == 4 ? 64 : 128;
+}
+
+// The camera assembly over the camera-pass items, whose positions lie in one XCD's point
+// range, so the point records each position gathers stay in that XCD's L2: k_cam_items<SCHUR>
+// sums an item's Schur-product rows (sum W Vinv W^T and sum W hp, from the gathered records),
+// k_cam_items<!SCHUR> its U and g_c rows (streams only; the two sets of sums in one kernel
+// need over 200 VGPRs), and k_cam_assemble adds a camera's item rows in item order and forms
+// U*, S_cc, its inverse and the right-hand side. On the 1000-camera workload: one workgroup
+// per camera gathering every record from HBM read 3.3x the algorithmic bytes (529 MB,
+// 127 us); U and g_c streamed per camera took 66 us, bound by its largest camera (14,000
+// observations against a mean of 4,000); both item passes in one kernel, one after the other,
+// 141 us (the second pass fetched the streams again).
+
+// The Schur-product rows of one observation: W = sum_rows w jc jp^T (D x 3, plus the
+// full-Hessian camera-point terms in ADJ mode with curvature).
 template <typename T, bool ADJ, int D>
-__global__ void __launch_bounds__(kBlock)
-k_cam_assemble(Model m, Compact<T> cp, ObsMetric<T> om, double lam, double dmin, double dmax,
-               const PtRec<T>* __restrict__ prec,
-               const double* __restrict__ rhs_c, double* __restrict__ Uraw,
-               T* __restrict__ Ustar, double* __restrict__ gc, double* __restrict__ b,
-               double* __restrict__ Minv, double* __restrict__ Scc) {
-  constexpr int NS = sym_count(D);
-  constexpr int K = NS + NS + D + D;
-  __shared__ double smem[K * (kBlock / kWave)];
-  const int s = blockIdx.x;
-  const int Ca = cp.Ca;
-  const Cam<double> cm = cp.camd[s];
-  double acc[K];   // U (NS), S = sum W Vinv W^T (NS), gc (D), sum W hp (D)
+__device__ __forceinline__ void cam_point_block(const Model& m, const Cam<double>& cm,
+                                                const ObsMetric<T>& om, int i, const V4<T>& xw,
+                                                T (&W)[3 * D]) {
+  const T wt = xw.w;
+  const T Xt[3] = {xw.x, xw.y, xw.z};
+  AMat<T, ADJ> A;
+  A.set(T(cm.f), T(m.lam_d), Xt);
+  if constexpr (ADJ) A.project(om.cm_eh + 3 * i);
 #pragma unroll
-  for (int i = 0; i < K; ++i) acc[i] = 0.0;
-  for (int i = cp.cm_off[s] + threadIdx.x; i < cp.cm_off[s + 1]; i += blockDim.x) {
-    // streamed: (X_c, w) and e of this observation; gathered: one packed point record
-    const V4<T> xw = om.xcw[i];
-    const V4<T> ev = om.cm_e[i];
-    const PtRec<T> pr = prec[cp.cm_pt[i]];
-    const double e[3] = {double(ev.x), double(ev.y), double(ev.z)};
-    const T wt = xw.w;
-    const T Xt[3] = {xw.x, xw.y, xw.z};
-    AMat<T, ADJ> A;
-    A.set(T(cm.f), T(m.lam_d), Xt);
-    if constexpr (ADJ) A.project(om.cm_eh + 3 * i);
-    T U[NS], W[3 * D];
+  for (int q = 0; q < 3 * D; ++q) W[q] = T(0);
+  const T fcol[3] = {Xt[0] / Xt[2], Xt[1] / Xt[2], T(0)};
 #pragma unroll
-    for (int q = 0; q < NS; ++q) U[q] = T(0);
-#pragma unroll
-    for (int q = 0; q < 3 * D; ++q) W[q] = T(0);
-    double g6[D];
-#pragma unroll
-    for (int q = 0; q < D; ++q) g6[q] = 0.0;
-    // de/df of the pinhole rows (focal length as the seventh unknown)
-    const T fcol[3] = {Xt[0] / Xt[2], Xt[1] / Xt[2], T(0)};
-#pragma unroll
-    for (int row = 0; row < 3; ++row) {
-      T a[3], jc[D], jp[3];
-      A.row(row, a);
-      jc[0] = a[0]; jc[1] = a[1]; jc[2] = a[2];
-      cross3(Xt, a, jc + 3);
-      if constexpr (D == 7) jc[6] = fcol[row];
-      rot_tmul(cm, a, jp);
-#pragma unroll
-      for (int p = 0; p < D; ++p) {
-#pragma unroll
-        for (int q = p; q < D; ++q) U[symd<D>(p, q)] += wt * jc[p] * jc[q];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) W[3 * p + q] += wt * jc[p] * jp[q];
-      }
-      if constexpr (!ADJ) {
-        const double we = double(wt) * e[row];
-#pragma unroll
-        for (int p = 0; p < D; ++p) g6[p] += we * double(jc[p]);
-      }
-    }
-    if constexpr (ADJ) {
-      if (om.cm_ce) {   // full Hessian: the curvature and retraction terms (see Curv)
-        const T c3[3] = {om.cm_ce[3 * i], om.cm_ce[3 * i + 1], om.cm_ce[3 * i + 2]};
-        Curv<T> K;
-        K.set(T(cm.f), T(m.lam_d), Xt, c3);
-        // columns of dX_c / d(rho, phi): e_k, then e_k x X
-        T Jc[6][3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          const T ek[3] = {T(k == 0), T(k == 1), T(k == 2)};
-          Jc[k][0] = ek[0]; Jc[k][1] = ek[1]; Jc[k][2] = ek[2];
-          cross3(ek, Xt, Jc[3 + k]);
-        }
-        T SJ[6][3];
-#pragma unroll
-        for (int p = 0; p < 6; ++p) {
-          SJ[p][0] = SJ[p][1] = SJ[p][2] = T(0);
-          K.add_s(Jc[p], SJ[p]);
-        }
-#pragma unroll
-        for (int p = 0; p < 6; ++p) {
-#pragma unroll
-          for (int q = p; q < 6; ++q)
-            U[symd<D>(p, q)] += Jc[p][0] * SJ[q][0] + Jc[p][1] * SJ[q][1] + Jc[p][2] * SJ[q][2];
-        }
-        // retraction terms: rho-phi [a]x / 2, phi-phi (a X^T + X a^T) / 2 - (a.X) I
-        const T* a = K.a;
-        const T ax[3][3] = {{T(0), -a[2], a[1]}, {a[2], T(0), -a[0]}, {-a[1], a[0], T(0)}};
-        const T aX = a[0] * Xt[0] + a[1] * Xt[1] + a[2] * Xt[2];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-#pragma unroll
-          for (int l = 0; l < 3; ++l) U[symd<D>(k, 3 + l)] += T(0.5) * ax[k][l];
-#pragma unroll
-          for (int l = k; l < 3; ++l)
-            U[symd<D>(3 + k, 3 + l)] +=
-                T(0.5) * (a[k] * Xt[l] + Xt[k] * a[l]) - (k == l ? aX : T(0));
-        }
-        // camera-point: J_c^T S R + [0 ; -[a]x R]
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          const T rq[3] = {T(cm.R[q]), T(cm.R[3 + q]), T(cm.R[6 + q])};
-          T sr[3] = {T(0), T(0), T(0)};
-          K.add_s(rq, sr);
-          T axr[3];
-          cross3(a, rq, axr);
-#pragma unroll
-          for (int p = 0; p < 6; ++p)
-            W[3 * p + q] += Jc[p][0] * sr[0] + Jc[p][1] * sr[1] + Jc[p][2] * sr[2];
-#pragma unroll
-          for (int k = 0; k < 3; ++k) W[3 * (3 + k) + q] -= axr[k];
-        }
-      }
-    }
-    // W Vinv W^T and W hp
-    T vi[6];
-#pragma unroll
-    for (int q = 0; q < 6; ++q) vi[q] = pr.vinv[q];
-    const double h0 = pr.hp[0], h1 = pr.hp[1], h2 = pr.hp[2];
-    T WV[3 * D];
+  for (int row = 0; row < 3; ++row) {
+    T a[3], jc[D], jp[3];
+    A.row(row, a);
+    jc[0] = a[0]; jc[1] = a[1]; jc[2] = a[2];
+    cross3(Xt, a, jc + 3);
+    if constexpr (D == 7) jc[6] = fcol[row];
+    rot_tmul(cm, a, jp);
 #pragma unroll
     for (int p = 0; p < D; ++p) {
 #pragma unroll
-      for (int q = 0; q < 3; ++q)
-        WV[3 * p + q] = W[3 * p] * vi[sym3(0, q)] + W[3 * p + 1] * vi[sym3(1, q)] +
-                        W[3 * p + 2] * vi[sym3(2, q)];
-      acc[2 * NS + p] += g6[p];
-      acc[2 * NS + D + p] +=
-          double(W[3 * p]) * h0 + double(W[3 * p + 1]) * h1 + double(W[3 * p + 2]) * h2;
+      for (int q = 0; q < 3; ++q) W[3 * p + q] += wt * jc[p] * jp[q];
     }
+  }
+  if constexpr (ADJ) {
+    if (om.cm_ce) {   // full Hessian: J_c^T S R + [0 ; -[a]x R] (see Curv)
+      const T c3[3] = {om.cm_ce[3 * i], om.cm_ce[3 * i + 1], om.cm_ce[3 * i + 2]};
+      Curv<T> K;
+      K.set(T(cm.f), T(m.lam_d), Xt, c3);
+      T Jc[6][3];   // columns of dX_c / d(rho, phi): e_k, then e_k x X
 #pragma unroll
-    for (int p = 0; p < D; ++p) {
+      for (int k = 0; k < 3; ++k) {
+        const T ek[3] = {T(k == 0), T(k == 1), T(k == 2)};
+        Jc[k][0] = ek[0]; Jc[k][1] = ek[1]; Jc[k][2] = ek[2];
+        cross3(ek, Xt, Jc[3 + k]);
+      }
 #pragma unroll
-      for (int q = p; q < D; ++q) {
-        acc[symd<D>(p, q)] += double(U[symd<D>(p, q)]);
-        acc[NS + symd<D>(p, q)] += double(WV[3 * p] * W[3 * q] + WV[3 * p + 1] * W[3 * q + 1] +
-                                          WV[3 * p + 2] * W[3 * q + 2]);
+      for (int q = 0; q < 3; ++q) {
+        const T rq[3] = {T(cm.R[q]), T(cm.R[3 + q]), T(cm.R[6 + q])};
+        T sr[3] = {T(0), T(0), T(0)};
+        K.add_s(rq, sr);
+        T axr[3];
+        cross3(K.a, rq, axr);
+#pragma unroll
+        for (int p = 0; p < 6; ++p)
+          W[3 * p + q] += Jc[p][0] * sr[0] + Jc[p][1] * sr[1] + Jc[p][2] * sr[2];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) W[3 * (3 + k) + q] -= axr[k];
       }
     }
   }
-  block_sum<double, K>(acc, smem);
+}
+
+// Per item, rows [0, NS) sum W Vinv W^T and [NS, NS + D) sum W hp (SCHUR), or rows
+// [NS + D, 2 NS + D) U and [2 NS + D, 2 NS + 2 D) g_c (zero in ADJ mode), into
+// part[row * nslot + item]. The SCHUR kernel loads the next position's stream entry and point
+// record while this one is summed (and the point rank two positions ahead).
+template <int D>
+constexpr int cam_item_rows() {
+  return 2 * (sym_count(D) + D);
+}
+
+template <typename T, bool ADJ, int D, bool SCHUR>
+__global__ void __launch_bounds__(cam_block<T>())
+k_cam_items(Model m, Compact<T> cp, ObsMetric<T> om, const PtRec<T>* __restrict__ prec,
+            CamItems it, int nslot, double* __restrict__ part) {
+  constexpr int NS = sym_count(D);
+  constexpr int KA = NS + D;
+  constexpr int B = cam_block<T>();
+  __shared__ double smem[KA * (B / kWave)];
+  const int4 rec = it.at[(blockIdx.x % it.R) * it.cap + blockIdx.x / it.R];
+  if (rec.x < 0) return;   // past the range's last item
+  const Cam<double> cm = cp.camd[rec.y];
+  double acc[KA];
+#pragma unroll
+  for (int q = 0; q < KA; ++q) acc[q] = 0.0;
+  if constexpr (SCHUR) {
+    const int i1 = rec.w;
+    int i = rec.z + int(threadIdx.x);
+    V4<T> xwn{};
+    PtRec<T> prn{};
+    if (i < i1) {
+      xwn = om.xcw[i];
+      prn = prec[cp.cm_pt[i]];
+    }
+    int pn = i + B < i1 ? cp.cm_pt[i + B] : 0;
+    for (; i < i1; i += B) {
+      const V4<T> xw = xwn;
+      const PtRec<T> pr = prn;
+      if (i + B < i1) {
+        xwn = om.xcw[i + B];
+        prn = prec[pn];
+        pn = i + 2 * B < i1 ? cp.cm_pt[i + 2 * B] : 0;
+      }
+      T W[3 * D];
+      cam_point_block<T, ADJ, D>(m, cm, om, i, xw, W);
+      T vi[6];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) vi[q] = pr.vinv[q];
+      T WV[3 * D];
+#pragma unroll
+      for (int p = 0; p < D; ++p) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+          WV[3 * p + q] = W[3 * p] * vi[sym3(0, q)] + W[3 * p + 1] * vi[sym3(1, q)] +
+                          W[3 * p + 2] * vi[sym3(2, q)];
+        acc[NS + p] += double(W[3 * p]) * pr.hp[0] + double(W[3 * p + 1]) * pr.hp[1] +
+                       double(W[3 * p + 2]) * pr.hp[2];
+      }
+#pragma unroll
+      for (int p = 0; p < D; ++p) {
+#pragma unroll
+        for (int q = p; q < D; ++q)
+          acc[symd<D>(p, q)] += double(WV[3 * p] * W[3 * q] + WV[3 * p + 1] * W[3 * q + 1] +
+                                       WV[3 * p + 2] * W[3 * q + 2]);
+      }
+    }
+  }
+  // U in T per lane (the J^T J blocks are float32 in mixed precision), g_c in float64; the
+  // next position's stream entries are loaded while this one is summed
+  T U[NS];
+#pragma unroll
+  for (int q = 0; q < NS; ++q) U[q] = T(0);
+  if constexpr (!SCHUR) {
+    const int i1 = rec.w;
+    int i = rec.z + int(threadIdx.x);
+    V4<T> xwn{}, evn{};
+    if (i < i1) {
+      xwn = om.xcw[i];
+      if constexpr (!ADJ) evn = om.cm_e[i];
+    }
+    for (; i < i1; i += B) {
+      const V4<T> xw = xwn;
+      const V4<T> ev = evn;
+      if (i + B < i1) {
+        xwn = om.xcw[i + B];
+        if constexpr (!ADJ) evn = om.cm_e[i + B];
+      }
+      const T wt = xw.w;
+      const T Xt[3] = {xw.x, xw.y, xw.z};
+      AMat<T, ADJ> A;
+      A.set(T(cm.f), T(m.lam_d), Xt);
+      if constexpr (ADJ) A.project(om.cm_eh + 3 * i);
+      const double e[3] = {double(ev.x), double(ev.y), double(ev.z)};
+      double g6[D];
+#pragma unroll
+      for (int q = 0; q < D; ++q) g6[q] = 0.0;
+      // de/df of the pinhole rows (focal length as the seventh unknown)
+      const T fcol[3] = {Xt[0] / Xt[2], Xt[1] / Xt[2], T(0)};
+#pragma unroll
+      for (int row = 0; row < 3; ++row) {
+        T a[3], jc[D];
+        A.row(row, a);
+        jc[0] = a[0]; jc[1] = a[1]; jc[2] = a[2];
+        cross3(Xt, a, jc + 3);
+        if constexpr (D == 7) jc[6] = fcol[row];
+#pragma unroll
+        for (int p = 0; p < D; ++p) {
+#pragma unroll
+          for (int q = p; q < D; ++q) U[symd<D>(p, q)] += wt * jc[p] * jc[q];
+        }
+        if constexpr (!ADJ) {
+          const double we = double(wt) * e[row];
+#pragma unroll
+          for (int p = 0; p < D; ++p) g6[p] += we * double(jc[p]);
+        }
+      }
+      if constexpr (ADJ) {
+        if (om.cm_ce) {   // full Hessian: the curvature and retraction terms (see Curv)
+          const T c3[3] = {om.cm_ce[3 * i], om.cm_ce[3 * i + 1], om.cm_ce[3 * i + 2]};
+          Curv<T> Kc;
+          Kc.set(T(cm.f), T(m.lam_d), Xt, c3);
+          // columns of dX_c / d(rho, phi): e_k, then e_k x X
+          T Jc[6][3];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            const T ek[3] = {T(k == 0), T(k == 1), T(k == 2)};
+            Jc[k][0] = ek[0]; Jc[k][1] = ek[1]; Jc[k][2] = ek[2];
+            cross3(ek, Xt, Jc[3 + k]);
+          }
+          T SJ[6][3];
+#pragma unroll
+          for (int p = 0; p < 6; ++p) {
+            SJ[p][0] = SJ[p][1] = SJ[p][2] = T(0);
+            Kc.add_s(Jc[p], SJ[p]);
+          }
+#pragma unroll
+          for (int p = 0; p < 6; ++p) {
+#pragma unroll
+            for (int q = p; q < 6; ++q)
+              U[symd<D>(p, q)] += Jc[p][0] * SJ[q][0] + Jc[p][1] * SJ[q][1] + Jc[p][2] * SJ[q][2];
+          }
+          // retraction terms: rho-phi [a]x / 2, phi-phi (a X^T + X a^T) / 2 - (a.X) I
+          const T* a = Kc.a;
+          const T ax[3][3] = {{T(0), -a[2], a[1]}, {a[2], T(0), -a[0]}, {-a[1], a[0], T(0)}};
+          const T aX = a[0] * Xt[0] + a[1] * Xt[1] + a[2] * Xt[2];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+#pragma unroll
+            for (int l = 0; l < 3; ++l) U[symd<D>(k, 3 + l)] += T(0.5) * ax[k][l];
+#pragma unroll
+            for (int l = k; l < 3; ++l)
+              U[symd<D>(3 + k, 3 + l)] +=
+                  T(0.5) * (a[k] * Xt[l] + Xt[k] * a[l]) - (k == l ? aX : T(0));
+          }
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < D; ++p) acc[NS + p] += g6[p];
+    }
+#pragma unroll
+    for (int q = 0; q < NS; ++q) acc[q] = double(U[q]);
+  }
+  block_sum<double, KA>(acc, smem);
+  if (threadIdx.x == 0) {
+    const int r0 = SCHUR ? 0 : KA;
+#pragma unroll
+    for (int q = 0; q < KA; ++q) part[size_t(r0 + q) * nslot + rec.x] = acc[q];
+  }
+}
+
+// Per camera slot: the camera's item rows added in item order (lane group g takes items g,
+// g + kG, ..., then each row over the groups), then U* = U + lam diag, S_cc = U* - sum W Vinv
+// W^T and its inverse, b = rhs_c - sum W hp (rhs_c = -g_c unless given).
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock)
+k_cam_assemble(int Ca, double lam, double dmin, double dmax, const int* __restrict__ item_off,
+               int nslot, const double* __restrict__ part, const double* __restrict__ rhs_c,
+               double* __restrict__ Uraw, T* __restrict__ Ustar, double* __restrict__ gc,
+               double* __restrict__ b, double* __restrict__ Minv, double* __restrict__ Scc) {
+  constexpr int NS = sym_count(D);
+  constexpr int KR = cam_item_rows<D>();
+  constexpr int kG = kBlock / KR;
+  static_assert(kG >= 1, "one row per thread");
+  __shared__ double s_rows[kG][KR];
+  __shared__ double s_tot[KR];
+  const int s = blockIdx.x;
+  {
+    const int q = int(threadIdx.x) % KR, g = int(threadIdx.x) / KR;
+    if (g < kG) {
+      double a = 0.0;
+      for (int it = item_off[s] + g; it < item_off[s + 1]; it += kG)
+        a += part[size_t(q) * nslot + it];
+      s_rows[g][q] = a;
+    }
+    __syncthreads();
+    if (int(threadIdx.x) < KR) {
+      double a = s_rows[0][threadIdx.x];
+      for (int h = 1; h < kG; ++h) a += s_rows[h][threadIdx.x];
+      s_tot[threadIdx.x] = a;
+    }
+    __syncthreads();
+  }
   if (threadIdx.x != 0) return;
+  const double* S = s_tot;                 // sum W Vinv W^T
+  const double* Wh = s_tot + NS;           // sum W hp
+  const double* U = s_tot + NS + D;        // J_c^T M J_c
+  const double* g = s_tot + 2 * NS + D;    // g_c
   double Us[NS], Sc[NS];
 #pragma unroll
   for (int q = 0; q < NS; ++q) {
-    Uraw[NS * s + q] = acc[q];
-    Us[q] = acc[q];
+    Uraw[NS * s + q] = U[q];
+    Us[q] = U[q];
   }
 #pragma unroll
   for (int p = 0; p < D; ++p) {
     const int d = symd<D>(p, p);
-    Us[d] += lam * fmin(fmax(acc[d], dmin), dmax);
+    Us[d] += lam * fmin(fmax(U[d], dmin), dmax);
   }
 #pragma unroll
   for (int q = 0; q < NS; ++q) {
     Ustar[q * Ca + s] = T(Us[q]);
-    Sc[q] = Us[q] - acc[NS + q];
+    Sc[q] = Us[q] - S[q];
     if (Scc) Scc[q * Ca + s] = Sc[q];
   }
 #pragma unroll
   for (int p = 0; p < D; ++p) {
-    gc[p * Ca + s] = acc[2 * NS + p];
-    const double rhs = rhs_c ? rhs_c[p * Ca + s] : -acc[2 * NS + p];
-    b[p * Ca + s] = rhs - acc[2 * NS + D + p];
+    gc[p * Ca + s] = g[p];
+    const double rhs = rhs_c ? rhs_c[p * Ca + s] : -g[p];
+    b[p * Ca + s] = rhs - Wh[p];
   }
   double inv[NS];
   if (!spd_inverse<D>(Sc, inv)) {
@@ -1396,13 +1537,7 @@ k_schur_point_lds(Model m, Compact<T> cp, ObsMetric<T> om, const MvRec<T, D>* __
 // the result does not depend on scheduling. Workgroup b takes slot b / R of range b % R: the
 // workgroups of XCD r (b % 8 = r) take range r's items, whose z vectors the point pass has
 // just written through that XCD's L2 (without the split, 43 us and 2.9x the fetched bytes on
-// the 1000-camera workload). float32: one-wave workgroups (an item averages some 650
-// positions; 26.0 us against 26.6 us with two); float64: two-wave workgroups (58.3 us against
-// 62.5 us with one).
-template <typename T>
-constexpr int cam_block() {
-  return sizeof(T) == 4 ? 64 : 128;
-}
+// the 1000-camera workload). Workgroups of cam_block<T>() threads.
 constexpr int kCamBlock = 128;   // global-positioning camera pass
 
 // One item of the camera pass (all threads of the workgroup).
@@ -1837,9 +1972,12 @@ k_cam_candidate(int Ca, int Cf, int D, const int* __restrict__ cam_src,
 // the changes rather than with the cost; the quadratic term of the model decrease
 // sum w |J delta|^2 (Jacobian at the linearisation point); g_p.dp; the number of candidate
 // depths <= min_depth; and the candidate cost itself.
-// With LDS, B = 1024-thread workgroups first copy the candidate camera table into LDS (one
-// 120-byte table fits; the current table stays in L2).
-template <typename T, int B, bool LDS>
+// Points are tiled over the XCDs as in the linearisation (grid lin_point_blocks*), G lanes per
+// point, so a wave reads its observations' streams in whole lines; every lane accumulates its
+// own observations and the workgroup sums them in a fixed order. With LDS, B = 1024-thread
+// workgroups first copy the candidate camera table into LDS (one 120-byte table fits; the
+// current table stays in L2).
+template <typename T, int G, int B, bool LDS>
 __global__ void __launch_bounds__(B)
 k_point_candidate(Model m, Compact<T> cp, int D, const Cam<double>* __restrict__ cand_tab,
                   const double* __restrict__ x, const double* __restrict__ dp,
@@ -1848,18 +1986,25 @@ k_point_candidate(Model m, Compact<T> cp, int D, const Cam<double>* __restrict__
   __shared__ double smem[5 * (B / kWave)];
   extern __shared__ double lds_cand[];   // LDS: the candidate camera table
   if constexpr (LDS) cand_tab = stage_cams<B>(cand_tab, cp.Ca + cp.Cf, lds_cand);
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int per = gridDim.x / 8;
+  const int xcd = blockIdx.x % 8, jw = blockIdx.x / 8;
+  constexpr int tile = B / G;
+  const int l = int(threadIdx.x) % G;
   const int Ca = cp.Ca;
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // decrease, quad, g_p.dp, bad, cost'
-  if (r < cp.Pa) {
+  for (int t = 0; t < G; ++t) {
+    const int r = xcd * per * B + (t * per + jw) * tile + int(threadIdx.x) / G;
+    if (r >= cp.Pa) continue;
     const double X[3] = {cp.Xd[3 * r], cp.Xd[3 * r + 1], cp.Xd[3 * r + 2]};
     const double d[3] = {dp[3 * r], dp[3 * r + 1], dp[3 * r + 2]};
     const double Xn[3] = {X[0] + d[0], X[1] + d[1], X[2] + d[2]};
-    Xcand[3 * r] = Xn[0];
-    Xcand[3 * r + 1] = Xn[1];
-    Xcand[3 * r + 2] = Xn[2];
-    acc[2] = gp[3 * r] * d[0] + gp[3 * r + 1] * d[1] + gp[3 * r + 2] * d[2];
-    for (int j = cp.off[r]; j < cp.off[r + 1]; ++j) {
+    if (l == 0) {
+      Xcand[3 * r] = Xn[0];
+      Xcand[3 * r + 1] = Xn[1];
+      Xcand[3 * r + 2] = Xn[2];
+      acc[2] += gp[3 * r] * d[0] + gp[3 * r + 1] * d[1] + gp[3 * r + 2] * d[2];
+    }
+    for (int j = cp.off[r] + l; j < cp.off[r + 1]; j += G) {
       const int s = cp.cam[j];
       const Cam<double> cm = cp.camd[s];
       double Xl[3], e[3], rho0, d1, d2;
@@ -1879,7 +2024,7 @@ k_point_candidate(Model m, Compact<T> cp, int D, const Cam<double>* __restrict__
         acc[4] += 0.5 * rho;
       }
       // model term at the linearisation point
-      double v[3], t[3];
+      double v[3], tv[3];
       rot_mul(cm, d, v);
       if (s < Ca) {
         const double w3[3] = {x[3 * Ca + s], x[4 * Ca + s], x[5 * Ca + s]};
@@ -1891,19 +2036,20 @@ k_point_candidate(Model m, Compact<T> cp, int D, const Cam<double>* __restrict__
       }
       AMat<double, false> A;
       A.set(cm.f, m.lam_d, Xl);
-      A.apply(v, t);
+      A.apply(v, tv);
       if (D == 7 && s < Ca) {   // focal column times the camera's focal step
         const double uf = x[6 * Ca + s] / Xl[2];
-        t[0] += Xl[0] * uf;
-        t[1] += Xl[1] * uf;
+        tv[0] += Xl[0] * uf;
+        tv[1] += Xl[1] * uf;
       }
-      acc[1] += double(w[j]) * (t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+      acc[1] += double(w[j]) * (tv[0] * tv[0] + tv[1] * tv[1] + tv[2] * tv[2]);
     }
   }
   block_sum<double, 5>(acc, smem);
   if (threadIdx.x == 0) {
+    const int blk = xcd * per + jw;
 #pragma unroll
-    for (int i = 0; i < 5; ++i) partials[5 * blockIdx.x + i] = acc[i];
+    for (int i = 0; i < 5; ++i) partials[5 * blk + i] = acc[i];
   }
 }
 
@@ -3070,19 +3216,41 @@ unsigned cam_grid(const CamItems& it, const DevLimits&) {
 }
 
 template <typename T>
-void launch_cam_assemble(hipStream_t s, bool adj, int D, const Model& m, const Compact<T>& cp,
-                         ObsMetric<T> om, double lam, double dmin, double dmax,
-                         const PtRec<T>* prec, const double* rhs_c, double* Uraw, T* Ustar,
-                         double* gc, double* b, double* Minv, double* Scc) {
-  if (cp.Ca == 0) return;
-  if (adj)
-    launch_k((k_cam_assemble<T, true, 6>), dim3(cp.Ca), dim3(kBlock), 0, s, m, cp, om, lam,
-             dmin, dmax, prec, rhs_c, Uraw, Ustar, gc, b, Minv, Scc);
-  else
+void launch_cam_items(hipStream_t s, bool adj, bool schur, int D, const Model& m,
+                      const Compact<T>& cp, ObsMetric<T> om, const PtRec<T>* prec, CamItems it,
+                      int nslot, double* part, const DevLimits& dl) {
+  if (cp.Ca == 0 || nslot <= 0) return;
+  const unsigned grid = cam_grid(it, dl);
+  const dim3 block(cam_block<T>());
+  if (adj) {
+    if (schur)
+      launch_k((k_cam_items<T, true, 6, true>), dim3(grid), block, 0, s, m, cp, om, prec, it,
+               nslot, part);
+    else
+      launch_k((k_cam_items<T, true, 6, false>), dim3(grid), block, 0, s, m, cp, om, prec, it,
+               nslot, part);
+  } else {
     with_dim(D, [&](auto Dc) {
-      launch_k((k_cam_assemble<T, false, Dc()>), dim3(cp.Ca), dim3(kBlock), 0, s, m, cp, om,
-               lam, dmin, dmax, prec, rhs_c, Uraw, Ustar, gc, b, Minv, Scc);
+      if (schur)
+        launch_k((k_cam_items<T, false, Dc(), true>), dim3(grid), block, 0, s, m, cp, om, prec,
+                 it, nslot, part);
+      else
+        launch_k((k_cam_items<T, false, Dc(), false>), dim3(grid), block, 0, s, m, cp, om, prec,
+                 it, nslot, part);
     });
+  }
+}
+
+template <typename T>
+void launch_cam_assemble(hipStream_t s, int D, int Ca, double lam, double dmin, double dmax,
+                         const int* item_off, int nslot, const double* part, const double* rhs_c,
+                         double* Uraw, T* Ustar, double* gc, double* b, double* Minv,
+                         double* Scc) {
+  if (Ca == 0) return;
+  with_dim(D, [&](auto Dc) {
+    launch_k((k_cam_assemble<T, Dc()>), dim3(Ca), dim3(kBlock), 0, s, Ca, lam, dmin, dmax,
+             item_off, nslot, part, rhs_c, Uraw, Ustar, gc, b, Minv, Scc);
+  });
 }
 
 template <typename T>
@@ -3272,26 +3440,40 @@ void launch_cam_candidate(hipStream_t s, int Ca, int Cf, int D, const int* cam_s
            x, cams, camd_hat, cand_cams, cand_tab);
 }
 
+template <typename T, int G>
+int point_candidate_g(hipStream_t s, const Model& m, const Compact<T>& cp, int D,
+                      const Cam<double>* cand_tab, const double* x, const double* dp,
+                      const double* gp, const T* w, double* Xcand, double* partials,
+                      const DevLimits& dl) {
+  const size_t tab = size_t(cp.Ca + cp.Cf) * sizeof(Cam<double>);
+  bool lds = dl.n_cu > 0 && cp.Ca + cp.Cf > 0 && tab + 5 * 16 * 8 <= size_t(dl.lds_per_block);
+  if (lds && tab > 65536)
+    lds = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_point_candidate<T, G, 1024, true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, int(tab)) == hipSuccess;
+  if (lds) {
+    const int nb = lin_point_blocks_lds(cp.Pa);
+    launch_k(k_point_candidate<T, G, 1024, true>, dim3(nb), dim3(1024), uint32_t(tab), s, m, cp,
+             D, cand_tab, x, dp, gp, w, Xcand, partials);
+    return nb;
+  }
+  const int nb = lin_point_blocks(cp.Pa);
+  launch_k(k_point_candidate<T, G, kBlock, false>, dim3(nb), dim3(kBlock), 0, s, m, cp, D,
+           cand_tab, x, dp, gp, w, Xcand, partials);
+  return nb;
+}
+
+// Two lanes per point: 107 us on the 1000-camera workload (eight observations per point)
+// against 111, 117 and 131 us with 1, 4 and 8 lanes.
+constexpr int kCandLanes = 2;
+
 template <typename T>
 int launch_point_candidate(hipStream_t s, const Model& m, const Compact<T>& cp, int D,
                            const Cam<double>* cand_tab, const double* x, const double* dp,
                            const double* gp, const T* w, double* Xcand, double* partials,
                            const DevLimits& dl) {
-  const size_t tab = size_t(cp.Ca + cp.Cf) * sizeof(Cam<double>);
-  bool lds = dl.n_cu > 0 && cp.Ca + cp.Cf > 0 && tab + 5 * 16 * 8 <= size_t(dl.lds_per_block);
-  if (lds && tab > 65536)
-    lds = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_point_candidate<T, 1024, true>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, int(tab)) == hipSuccess;
-  if (lds) {
-    const int nb = (cp.Pa + 1023) / 1024;
-    launch_k(k_point_candidate<T, 1024, true>, dim3(nb), dim3(1024), uint32_t(tab), s, m, cp, D,
-             cand_tab, x, dp, gp, w, Xcand, partials);
-    return nb;
-  }
-  const int nb = int(blocks_for(cp.Pa));
-  launch_k(k_point_candidate<T, kBlock, false>, dim3(nb), dim3(kBlock), 0, s, m, cp, D,
-           cand_tab, x, dp, gp, w, Xcand, partials);
-  return nb;
+  if (cp.Pa <= 0) return 0;
+  return point_candidate_g<T, kCandLanes>(s, m, cp, D, cand_tab, x, dp, gp, w, Xcand, partials,
+                                          dl);
 }
 
 void launch_reduce_partials(hipStream_t s, int nblocks, int K, const double* partials,
@@ -3334,10 +3516,12 @@ void launch_adjoint_obs(hipStream_t s, const Model& m, const Compact<T>& cp, Obs
   template void launch_point_damp<T>(hipStream_t, int, double, double, double, const double*, \
                                      const double*, const double*, T*, double*, PtRec<T>*,    \
                                      int*);                                                    \
-  template void launch_cam_assemble<T>(hipStream_t, bool, int, const Model&,                  \
-                                       const Compact<T>&, ObsMetric<T>, double, double, double,\
-                                       const PtRec<T>*, const double*, double*, T*, double*,  \
-                                       double*, double*, double*);                                      \
+  template void launch_cam_items<T>(hipStream_t, bool, bool, int, const Model&,               \
+                                    const Compact<T>&, ObsMetric<T>, const PtRec<T>*, CamItems,\
+                                    int, double*, const DevLimits&);                           \
+  template void launch_cam_assemble<T>(hipStream_t, int, int, double, double, double,         \
+                                       const int*, int, const double*, const double*, double*, \
+                                       T*, double*, double*, double*, double*);                \
   template void launch_mv_table<T>(hipStream_t, int, int, const Cam<double>*, void*);         \
   template void launch_pcg_init<T>(hipStream_t, int, int, const double*, const double*,       \
                                    const T*, double*, double*, double*, double*, double*,     \
