@@ -222,6 +222,9 @@ struct ba_ctx {
   double* diag = nullptr;         // |b - S x|^2, |b|^2 of that product
   double* h_pin = nullptr;   // pinned host readback buffer
   hipEvent_t pcg_ev[2] = {nullptr, nullptr};   // the PCG state copies of two batches
+  int pcg_pending = -1;   // batch whose state copy the LM step reads at its next sync
+  hipEvent_t items_ev = nullptr;   // the item counts' copy after an item build
+  bool items_pending = false;      // it_count / it_slots still the upper bounds
 
   // LM state
   double lam = 1e-3, nu = 2.0;
@@ -262,6 +265,7 @@ struct ba_ctx {
       (void)hipEventDestroy(pe.b);
     }
     for (auto e : pool) (void)hipEventDestroy(e);
+    if (items_ev) (void)hipEventDestroy(items_ev);
     for (auto e : pcg_ev)
       if (e) (void)hipEventDestroy(e);
     obs.release();
@@ -603,15 +607,27 @@ int plan_items(ba_ctx& c, int R, int nch) {
 }
 
 // After the item build: the item count and the largest item count of a range, which size the
-// update's reduction and the camera-pass grids (one host round trip per build).
-void read_item_counts(ba_ctx& c) {
+// update's reduction and the camera-pass grids. They are copied with an event and read when
+// the PCG starts (resolve_items), by which time the stream is busy with the work queued since
+// the build; until then it_count and it_slots hold their upper bounds (the camera assembly's
+// grids cover cap slots per range, the slots past a range's last item return at once).
+void request_item_counts(ba_ctx& c) {
   HIP_CHECK(hipMemcpyAsync(c.h_pin + 24, c.item_off + c.Ca, 2 * sizeof(int),
                            hipMemcpyDeviceToHost, c.stream));
-  c.sync();
+  HIP_CHECK(hipEventRecord(c.items_ev, c.stream));
+  c.it_count = c.it_nslot;
+  c.it_slots = c.it_cap;
+  c.items_pending = true;
+}
+
+void resolve_items(ba_ctx& c) {
+  if (!c.items_pending) return;
+  HIP_CHECK(hipEventSynchronize(c.items_ev));
   int n[2] = {0, 0};
   std::memcpy(n, c.h_pin + 24, sizeof(n));
   c.it_count = std::max(0, std::min(n[0], c.it_nslot));
   c.it_slots = std::max(0, std::min(n[1], c.it_cap));
+  c.items_pending = false;
 }
 
 // Builds the camera-pass items (R ranges, at most K positions each, nch = ceil(Nc / K)) unless
@@ -621,7 +637,8 @@ int ensure_items(ba_ctx& c, int R, int K, int nch) {
   plan_items(c, R, nch);
   launch_build_items(c.stream, c.Ca, c.cm_off_hat, c.rb, K, items_view(c));
   HIP_LAUNCH_CHECK();
-  read_item_counts(c);
+  request_item_counts(c);
+  if (c.opt.timing) resolve_items(c);   // exact byte models; timing syncs anyway
   c.it_K = K;
   c.items_ok = true;
   return c.it_nslot;
@@ -650,22 +667,32 @@ void extract(ba_ctx& c, bool gp = false) {
     });
   const int need_cam = gp ? 3 : c.need_cam();
   const int need_pt = gp ? 3 : c.need_pt();
+  // two rounds per host check: a round at the fixpoint changes nothing, so the second round
+  // of a pair is harmless when the first one settled it (flags[0] and flags[2] say whether
+  // each round changed anything)
   int rounds = 0;
   while (true) {
-    ++rounds;
-    HIP_CHECK(hipMemsetAsync(c.flags, 0, sizeof(int), s));
-    c.timed("cam_rows", double(N) * 1, -1, [&] {
-      launch_cam_rows(s, c.C, c.cm_off, c.vrow_cm, c.d_fixed, need_cam, c.act_c);
-    });
-    c.timed("point_rows_prune", double(N) * 5 + double(c.P) * 5, -1, [&] {
-      launch_point_rows_prune(s, c.P, c.pt_off, c.pm_cam, c.act_c, c.d_fixed, need_pt,
-                              c.inv_cm, c.vrow, c.vrow_cm, c.act_p, c.flags);
-    });
-    HIP_CHECK(hipMemcpyAsync(c.h_pin, c.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    for (int k = 0; k < 2; ++k) {
+      int* changed = c.flags + 2 * k;
+      HIP_CHECK(hipMemsetAsync(changed, 0, sizeof(int), s));
+      c.timed("cam_rows", double(N) * 1, -1, [&] {
+        launch_cam_rows(s, c.C, c.cm_off, c.vrow_cm, c.d_fixed, need_cam, c.act_c);
+      });
+      c.timed("point_rows_prune", double(N) * 5 + double(c.P) * 5, -1, [&] {
+        launch_point_rows_prune(s, c.P, c.pt_off, c.pm_cam, c.act_c, c.d_fixed, need_pt,
+                                c.inv_cm, c.vrow, c.vrow_cm, c.act_p, changed);
+      });
+    }
+    HIP_CHECK(hipMemcpyAsync(c.h_pin, c.flags, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
     c.sync();
-    int changed = 0;
-    std::memcpy(&changed, c.h_pin, sizeof(int));
-    if (!changed) break;
+    int f[3] = {0, 0, 0};
+    std::memcpy(f, c.h_pin, sizeof(f));
+    if (!f[0]) {
+      rounds += 1;
+      break;
+    }
+    rounds += 2;
+    if (!f[2]) break;
     if (rounds > 1000000) throw BaError{BA_ERR_DEVICE, "activity fixpoint did not settle"};
   }
   c.rounds = rounds;
@@ -947,14 +974,18 @@ void setup_system(ba_ctx& c, bool adj, double lam, const double* rhs_c, const do
 // [it0, it1). The host reads the device-side state after each batch while the next batch is
 // already queued (two pinned slots, one event each), so the GPU does not wait for the check;
 // iterations enqueued after convergence return at their first instruction. Returns the state
-// after the last batch that did work.
+// after the last batch that did work; with defer, once every iteration is queued it returns
+// without waiting for them and leaves the last state's copy to the caller's next stream sync
+// (c.pcg_pending names its slot, pcg_slot).
 static_assert(sizeof(PcgState) <= 16 * sizeof(double), "a pinned slot holds one state");
+double* pcg_slot(ba_ctx& c, int k) { return c.h_pin + 32 + 16 * (k & 1); }
+
 template <class Batch>
-PcgState pcg_batches(ba_ctx& c, int max_iters, Batch&& batch) {
+PcgState pcg_batches(ba_ctx& c, int max_iters, Batch&& batch, bool defer = false) {
   const int every = std::max(1, c.opt.pcg_check_every);
   hipStream_t s = c.stream;
   int it = 0, n = 0;   // iterations and batches enqueued
-  auto slot = [&](int k) { return c.h_pin + 32 + 16 * (k & 1); };
+  auto slot = [&](int k) { return pcg_slot(c, k); };
   auto enqueue = [&] {
     const int it1 = std::min(max_iters, it + every);
     batch(it, it1);
@@ -971,7 +1002,10 @@ PcgState pcg_batches(ba_ctx& c, int max_iters, Batch&& batch) {
   enqueue();
   while (true) {
     if (it >= max_iters) {   // every iteration is queued: the last batch's state
-      read(n - 1);
+      if (defer)
+        c.pcg_pending = n - 1;
+      else
+        read(n - 1);
       break;
     }
     enqueue();
@@ -983,7 +1017,8 @@ PcgState pcg_batches(ba_ctx& c, int max_iters, Batch&& batch) {
 
 // PCG on the camera Schur complement; returns the iteration count (pcg_batches).
 template <typename T>
-int run_pcg(ba_ctx& c, bool adj, double rel_tol, int max_iters, PcgState* out_state) {
+int run_pcg(ba_ctx& c, bool adj, double rel_tol, int max_iters, PcgState* out_state,
+            bool defer = false) {
   hipStream_t s = c.stream;
   const Model m = c.model();
   Compact<T> cp = compact_view<T>(c);
@@ -1004,6 +1039,7 @@ int run_pcg(ba_ctx& c, bool adj, double rel_tol, int max_iters, PcgState* out_st
     nch = 0;
   }
   const int nslot = ensure_items(c, expl ? 1 : kMaxRanges, K, nch);
+  resolve_items(c);
   launch_pcg_init<T>(s, c.D, c.Ca, c.b, c.Minv, Ustar, c.x, c.r, c.u, c.p, c.sv, c.wv, c.dots,
                      mvt, c.pcg, rel_tol * rel_tol, max_iters);
   HIP_LAUNCH_CHECK();
@@ -1038,7 +1074,7 @@ int run_pcg(ba_ctx& c, bool adj, double rel_tol, int max_iters, PcgState* out_st
                              c.part, c.dots, c.x, c.r, c.u, c.p, c.sv, c.wv, mvt, c.pcg);
       });
     }
-  });
+  }, defer);
   *out_state = st;
   return st.matvecs;
 }
@@ -1130,12 +1166,11 @@ ba_status lm_step_impl(ba_ctx& c, ba_step_report* rep) {
 
   ta = now_ms();
   PcgState st{};
-  const int iters = run_pcg<T>(c, false, c.opt.pcg_rel_tol, c.opt.pcg_max_iters, &st);
+  // the final PCG state is read with the candidate's scalars (no wait between the solve and
+  // the back-substitution), except when timing
+  c.pcg_pending = -1;
+  int iters = run_pcg<T>(c, false, c.opt.pcg_rel_tol, c.opt.pcg_max_iters, &st, !c.opt.timing);
   t_pcg = now_ms() - ta;
-  R.pcg_iters = st.iter;
-  R.pcg_breakdown = st.breakdown;
-  R.pcg_rel_residual = st.bb > 0 ? std::sqrt(std::max(0.0, st.rr) / st.bb) : 0.0;
-  R.pcg_true_residual = -1.0;
   if (c.opt.timing && !explicit_solver(c)) R.pcg_true_residual = true_residual<T>(c);
 
   ta = now_ms();
@@ -1160,6 +1195,14 @@ ba_status lm_step_impl(ba_ctx& c, ba_step_report* rep) {
   HIP_CHECK(hipMemcpyAsync(c.h_pin, c.scal, 11 * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_CHECK(hipMemcpyAsync(c.h_pin + 11, c.flags + 1, sizeof(int), hipMemcpyDeviceToHost, s));
   c.sync();
+  if (c.pcg_pending >= 0) {   // the solve's last state, copied before the sync
+    std::memcpy(&st, pcg_slot(c, c.pcg_pending), sizeof(PcgState));
+    iters = st.matvecs;
+    c.pcg_pending = -1;
+  }
+  R.pcg_iters = st.iter;
+  R.pcg_breakdown = st.breakdown;
+  R.pcg_rel_residual = st.bb > 0 ? std::sqrt(std::max(0.0, st.rr) / st.bb) : 0.0;
   double sc[11];
   std::memcpy(sc, c.h_pin, sizeof(sc));
   int damp_bad = 0;
@@ -1265,6 +1308,7 @@ int gp_run_pcg(ba_ctx& c, PcgState* out_state) {
   int K = 0, nch = 0;
   cam_chunking(c.Nc, K, nch);
   const int nslot = ensure_items(c, 1, K, nch);   // z per camera-major position: no ranges
+  resolve_items(c);
   launch_pcg_init<T>(s, 3, c.Ca, c.b, c.Minv, Ustar, c.x, c.r, c.u, c.p, c.sv, c.wv, c.dots,
                      c.mvt, c.pcg, c.opt.pcg_rel_tol * c.opt.pcg_rel_tol, c.opt.pcg_max_iters);
   HIP_LAUNCH_CHECK();
@@ -1583,6 +1627,7 @@ struct ScratchSwap {
         partials(cc.partials), dots(cc.dots), part(cc.part), item_off(cc.item_off),
         rb(cc.rb), item_at(cc.item_at), scan(cc.scan_temp) {
     c.items_ok = false;   // the items live in the buffers being swapped
+    settle_items();
     c.flags = reinterpret_cast<int*>(base + p.flags);
     c.pcg = reinterpret_cast<PcgState*>(base + p.pcg);
     c.pcg_diag = reinterpret_cast<PcgState*>(base + p.pcg_diag);
@@ -1608,6 +1653,13 @@ struct ScratchSwap {
     c.rb = rb;
     c.scan_temp = scan;
     c.items_ok = false;
+    settle_items();
+  }
+  // a pending item-count copy reads the buffers being swapped: let it land (the counts are
+  // rebuilt with the items)
+  void settle_items() {
+    if (c.items_pending) (void)hipEventSynchronize(c.items_ev);
+    c.items_pending = false;
   }
   ScratchSwap(const ScratchSwap&) = delete;
   ScratchSwap& operator=(const ScratchSwap&) = delete;
@@ -1709,6 +1761,7 @@ ba_status ba_create(const ba_options* opt, int32_t n_cams, int32_t n_points, con
     }
     HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&c->h_pin), 64 * sizeof(double)));
     for (auto& e : c->pcg_ev) HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    HIP_CHECK(hipEventCreateWithFlags(&c->items_ev, hipEventDisableTiming));
     int dev = 0;
     HIP_CHECK(hipGetDevice(&dev));
     c->device = dev;
