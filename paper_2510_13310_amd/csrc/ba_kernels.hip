@@ -1640,30 +1640,8 @@ k_pcg_update(int Ca, int k, const double* __restrict__ Minv, const T* __restrict
   double* tout = terms + ((k + 1) & 1) * 3 * Ca;
   const int s = blockIdx.x * kUpdCams + threadIdx.x;
   const bool own = threadIdx.x < kUpdCams && s < Ca;
-  {
-    // a camera's item partials, summed by a group of kUpdLanes lanes: lane g takes items
-    // g, g + kUpdLanes, ... in order, then a fixed tree over the group
-    constexpr int kUpdLanes = kUpdBlock / kUpdCams;
-    const int jc = int(threadIdx.x) / kUpdLanes, g = int(threadIdx.x) % kUpdLanes;
-    const int sc = blockIdx.x * kUpdCams + jc;
-    double ws[D];
-#pragma unroll
-    for (int i = 0; i < D; ++i) ws[i] = 0.0;
-    if (sc < Ca) {
-      const int i1 = item_off[sc + 1];
-      for (int it = item_off[sc] + g; it < i1; it += kUpdLanes) {
-#pragma unroll
-        for (int i = 0; i < D; ++i) ws[i] += part[i * nslot + it];
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < D; ++i) ws[i] = group_sum<kUpdLanes>(ws[i]);
-    if (g == 0) {
-#pragma unroll
-      for (int i = 0; i < D; ++i) s_items[jc][i] = ws[i];
-    }
-  }
-  // every load the owner needs is issued before the reduction
+  // every load the owner needs is issued first, then the global sums' and the camera's item
+  // partials (summed after the sums: 7.5 us against 7.9 us with the partials first)
   double pv[D], wv[D], sv0[D], rv[D], uv[D], xv[D], m[sym_count(D)];
   T us[sym_count(D)];
   if (own) {
@@ -1709,6 +1687,29 @@ k_pcg_update(int Ca, int k, const double* __restrict__ Minv, const T* __restrict
     }
 #pragma unroll
     for (int q = 0; q < kUpdDots; ++q) acc[1] -= dd[q];
+  }
+  {
+    // a camera's item partials, summed by a group of kUpdLanes lanes: lane g takes items
+    // g, g + kUpdLanes, ... in order, then a fixed tree over the group
+    constexpr int kUpdLanes = kUpdBlock / kUpdCams;
+    const int jc = int(threadIdx.x) / kUpdLanes, g = int(threadIdx.x) % kUpdLanes;
+    const int sc = blockIdx.x * kUpdCams + jc;
+    double ws[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) ws[i] = 0.0;
+    if (sc < Ca) {
+      const int i1 = item_off[sc + 1];
+      for (int it = item_off[sc] + g; it < i1; it += kUpdLanes) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) ws[i] += part[i * nslot + it];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < D; ++i) ws[i] = group_sum<kUpdLanes>(ws[i]);
+    if (g == 0) {
+#pragma unroll
+      for (int i = 0; i < D; ++i) s_items[jc][i] = ws[i];
+    }
   }
   // thread 0 reads the state once for the whole workgroup
   int done0 = 0;
