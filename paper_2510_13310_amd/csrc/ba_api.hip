@@ -423,8 +423,8 @@ ba_status guarded(ba_ctx* c, F&& f) {
 // ------------------------------------------------------------------ buffers
 // Most camera-pass items a solve can have (CamItems: R Ca + nchunks, R <= 8).
 size_t item_slots(int C) { return size_t(kMaxRanges) * size_t(C) + kCamChunks; }
-// Partial rows per item slot: the camera assembly's 2 (D (D + 1) / 2 + D), or the PCG camera
-// pass's D + 1 (which also covers global positioning, D = 3).
+// Partial values per item slot: the camera assembly's 2 (D (D + 1) / 2 + D) (item-major), or
+// the PCG camera pass's D + 1 rows (which also covers global positioning, D = 3).
 size_t part_rows(int D) {
   return std::max(2 * (size_t(D) * (D + 1) / 2 + D), size_t(D) + 1);
 }
@@ -964,7 +964,7 @@ void setup_system(ba_ctx& c, bool adj, double lam, const double* rhs_c, const do
           double(c.it_count) * 8 * rows + double(c.Ca) * (ns * (16 + ts) + c.D * 8 * 2 + 8), -1,
           [&] {
             launch_cam_assemble<T>(s, c.D, c.Ca, lam, c.opt.diag_min, c.opt.diag_max,
-                                   c.item_off, nslot, c.part, rhs_c, c.Uraw,
+                                   c.item_off, c.part, rhs_c, c.Uraw,
                                    static_cast<T*>(c.Ustar), c.gc, c.b, c.Minv,
                                    explicit_solver(c) && !adj ? c.ex_scc : nullptr);
           });

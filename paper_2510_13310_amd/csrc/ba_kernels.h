@@ -288,7 +288,7 @@ void launch_build_items(hipStream_t s, int Ca, const int* cm_off, const int* rb,
 // Camera assembly. launch_cam_items: per item of `it` (positions in one point range, so the
 // gathered point records stay in one XCD's L2) the rows sum W Vinv W^T (D (D + 1) / 2) and
 // sum W hp (D) (schur), or U = J_c^T M J_c (D (D + 1) / 2) and g_c (D) (!schur), into
-// part[row * nslot + item] (2 (D (D + 1) / 2 + D) rows in all, see part_rows).
+// part[item * 2 (D (D + 1) / 2 + D) + row] (see part_rows); nslot is the item capacity.
 // launch_cam_assemble: per camera slot its items' rows (item_off) added in item order, then
 // b = rhs_c - sum W hp, S_cc = U* - sum W Vinv W^T and its inverse (Cholesky, float64).
 // rhs_c = -gc when rhs_c == nullptr. SoA outputs. Scc (optional, SoA like Minv) receives S_cc
@@ -299,7 +299,7 @@ void launch_cam_items(hipStream_t s, bool adj, bool schur, int D, const Model& m
                       int nslot, double* part, const DevLimits& dl);
 template <typename T>
 void launch_cam_assemble(hipStream_t s, int D, int Ca, double lam, double dmin, double dmax,
-                         const int* item_off, int nslot, const double* part, const double* rhs_c,
+                         const int* item_off, const double* part, const double* rhs_c,
                          double* Uraw, T* Ustar, double* gc, double* b, double* Minv,
                          double* Scc = nullptr);
 

@@ -882,7 +882,8 @@ __device__ __forceinline__ void cam_point_block(const Model& m, const Cam<double
 
 // Per item, rows [0, NS) sum W Vinv W^T and [NS, NS + D) sum W hp (SCHUR), or rows
 // [NS + D, 2 NS + D) U and [2 NS + D, 2 NS + 2 D) g_c (zero in ADJ mode), into
-// part[row * nslot + item]. The SCHUR kernel loads the next position's stream entry and point
+// part[item * 2 (NS + D) + row] (item-major: one contiguous write per item, and a camera's
+// items are adjacent). The SCHUR kernel loads the next position's stream entry and point
 // record while this one is summed (and the point rank two positions ahead).
 template <int D>
 constexpr int cam_item_rows() {
@@ -892,7 +893,7 @@ constexpr int cam_item_rows() {
 template <typename T, bool ADJ, int D, bool SCHUR>
 __global__ void __launch_bounds__(cam_block<T>())
 k_cam_items(Model m, Compact<T> cp, ObsMetric<T> om, const PtRec<T>* __restrict__ prec,
-            CamItems it, int nslot, double* __restrict__ part) {
+            CamItems it, double* __restrict__ part) {
   constexpr int NS = sym_count(D);
   constexpr int KA = NS + D;
   constexpr int B = cam_block<T>();
@@ -1042,9 +1043,9 @@ k_cam_items(Model m, Compact<T> cp, ObsMetric<T> om, const PtRec<T>* __restrict_
   }
   block_sum<double, KA>(acc, smem);
   if (threadIdx.x == 0) {
-    const int r0 = SCHUR ? 0 : KA;
+    double* row = part + size_t(rec.x) * (2 * KA) + (SCHUR ? 0 : KA);
 #pragma unroll
-    for (int q = 0; q < KA; ++q) part[size_t(r0 + q) * nslot + rec.x] = acc[q];
+    for (int q = 0; q < KA; ++q) row[q] = acc[q];
   }
 }
 
@@ -1054,7 +1055,7 @@ k_cam_items(Model m, Compact<T> cp, ObsMetric<T> om, const PtRec<T>* __restrict_
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock)
 k_cam_assemble(int Ca, double lam, double dmin, double dmax, const int* __restrict__ item_off,
-               int nslot, const double* __restrict__ part, const double* __restrict__ rhs_c,
+               const double* __restrict__ part, const double* __restrict__ rhs_c,
                double* __restrict__ Uraw, T* __restrict__ Ustar, double* __restrict__ gc,
                double* __restrict__ b, double* __restrict__ Minv, double* __restrict__ Scc) {
   constexpr int NS = sym_count(D);
@@ -1069,7 +1070,7 @@ k_cam_assemble(int Ca, double lam, double dmin, double dmax, const int* __restri
     if (g < kG) {
       double a = 0.0;
       for (int it = item_off[s] + g; it < item_off[s + 1]; it += kG)
-        a += part[size_t(q) * nslot + it];
+        a += part[size_t(it) * KR + q];
       s_rows[g][q] = a;
     }
     __syncthreads();
@@ -3236,31 +3237,31 @@ void launch_cam_items(hipStream_t s, bool adj, bool schur, int D, const Model& m
   if (adj) {
     if (schur)
       launch_k((k_cam_items<T, true, 6, true>), dim3(grid), block, 0, s, m, cp, om, prec, it,
-               nslot, part);
+               part);
     else
       launch_k((k_cam_items<T, true, 6, false>), dim3(grid), block, 0, s, m, cp, om, prec, it,
-               nslot, part);
+               part);
   } else {
     with_dim(D, [&](auto Dc) {
       if (schur)
         launch_k((k_cam_items<T, false, Dc(), true>), dim3(grid), block, 0, s, m, cp, om, prec,
-                 it, nslot, part);
+                 it, part);
       else
         launch_k((k_cam_items<T, false, Dc(), false>), dim3(grid), block, 0, s, m, cp, om, prec,
-                 it, nslot, part);
+                 it, part);
     });
   }
 }
 
 template <typename T>
 void launch_cam_assemble(hipStream_t s, int D, int Ca, double lam, double dmin, double dmax,
-                         const int* item_off, int nslot, const double* part, const double* rhs_c,
+                         const int* item_off, const double* part, const double* rhs_c,
                          double* Uraw, T* Ustar, double* gc, double* b, double* Minv,
                          double* Scc) {
   if (Ca == 0) return;
   with_dim(D, [&](auto Dc) {
     launch_k((k_cam_assemble<T, Dc()>), dim3(Ca), dim3(kBlock), 0, s, Ca, lam, dmin, dmax,
-             item_off, nslot, part, rhs_c, Uraw, Ustar, gc, b, Minv, Scc);
+             item_off, part, rhs_c, Uraw, Ustar, gc, b, Minv, Scc);
   });
 }
 
@@ -3531,8 +3532,8 @@ void launch_adjoint_obs(hipStream_t s, const Model& m, const Compact<T>& cp, Obs
                                     const Compact<T>&, ObsMetric<T>, const PtRec<T>*, CamItems,\
                                     int, double*, const DevLimits&);                           \
   template void launch_cam_assemble<T>(hipStream_t, int, int, double, double, double,         \
-                                       const int*, int, const double*, const double*, double*, \
-                                       T*, double*, double*, double*, double*);                \
+                                       const int*, const double*, const double*, double*, T*,  \
+                                       double*, double*, double*, double*);                    \
   template void launch_mv_table<T>(hipStream_t, int, int, const Cam<double>*, void*);         \
   template void launch_pcg_init<T>(hipStream_t, int, int, const double*, const double*,       \
                                    const T*, double*, double*, double*, double*, double*,     \
