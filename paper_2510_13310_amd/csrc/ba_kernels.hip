@@ -823,8 +823,8 @@ constexpr int cam_block() {
 // observations against a mean of 4,000); both item passes in one kernel, one after the other,
 // 141 us (the second pass fetched the streams again).
 
-// The Schur-product rows of one observation: W = sum_rows w jc jp^T (D x 3, plus the
-// full-Hessian camera-point terms in ADJ mode with curvature).
+// The camera-point block of one observation, W = sum over its residual rows of w jc jp^T
+// (D x 3), plus the full-Hessian camera-point terms in ADJ mode with curvature.
 template <typename T, bool ADJ, int D>
 __device__ __forceinline__ void cam_point_block(const Model& m, const Cam<double>& cm,
                                                 const ObsMetric<T>& om, int i, const V4<T>& xw,
