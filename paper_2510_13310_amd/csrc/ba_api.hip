@@ -1105,14 +1105,23 @@ double true_residual(ba_ctx& c) {
 }
 
 template <typename T>
-void backsub(ba_ctx& c, bool adj, const double* rhs_p) {
+// The point step of the solve: the PCG point pass run once more on x (the camera step) gives
+// z = V*^-1 sum_k W_k^T x_c per point, and dp = hp - z with hp = V*^-1 b_p from the damping
+// setup, whose b_p (rhs_p, or -g_p) is the one this step's setup_system used.
+void backsub(ba_ctx& c, bool adj) {
   hipStream_t s = c.stream;
   const Model m = c.model();
   Compact<T> cp = compact_view<T>(c);
   ObsMetric<T> om = metric_view<T>(c);
-  c.timed("backsub", bytes_schur_point(c) + double(c.Pa) * 48, -1, [&] {
-    launch_backsub<T>(s, adj, c.D, lanes_per_point(c), m, cp, om, static_cast<const T*>(c.Vinv),
-                      c.x, c.gp, rhs_p, c.dp);
+  P3<T>* zq = static_cast<P3<T>*>(c.zq);
+  const bool use_z = c.Ca > 0;
+  c.timed_multi("backsub", bytes_schur_point(c) + double(c.Pa) * 48, [&] {
+    if (use_z) {
+      launch_x_to_mv<T>(s, c.D, c.Ca, c.x, c.mvt, c.pcg_diag);
+      launch_schur_point<T>(s, adj, c.D, lanes_per_point(c), m, cp, om, c.mvt,
+                            static_cast<const T*>(c.Vinv), zq, c.pcg_diag, c.dl);
+    }
+    launch_backsub<T>(s, c.Pa, c.hp, zq, use_z, c.dp);
   });
 }
 
@@ -1174,7 +1183,7 @@ ba_status lm_step_impl(ba_ctx& c, ba_step_report* rep) {
   if (c.opt.timing && !explicit_solver(c)) R.pcg_true_residual = true_residual<T>(c);
 
   ta = now_ms();
-  backsub<T>(c, false, nullptr);
+  backsub<T>(c, false);
   c.timed("cam_candidate", double(c.Ca + c.n_fixed) * (56 + 120 + 56 + 120) + double(c.Ca) * 48,
           -1, [&] {
             launch_cam_candidate(s, c.Ca, c.n_fixed, c.D, c.cam_src, c.x, c.d_cams, c.camd_hat,
@@ -1528,7 +1537,7 @@ bool adjoint_impl(ba_ctx& c, const double* grad_cams, const double* grad_points,
     const double tol = c.opt.adjoint_rel_tol;
     const int maxit = c.opt.adjoint_max_iters;
     const int mv = run_pcg<T>(c, true, tol, maxit, &st);
-    backsub<T>(c, true, c.rhs_p);
+    backsub<T>(c, true);
     Compact<T> cp = compact_view<T>(c);
     launch_adjoint_obs<T>(s, c.model(), cp, metric_view<T>(c), c.x, c.dp, c.orig_hat, c.gxy_d,
                           c.gdepth_d);

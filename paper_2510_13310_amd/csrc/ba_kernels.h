@@ -348,11 +348,12 @@ template <typename T>
 void launch_true_residual(hipStream_t s, int D, int Ca, const double* x, const double* b,
                           const T* Ustar, const int* item_off, int nslot, const double* part,
                           double* out);
-// dp = Vinv (rhs_p - sum_k W_k^T x_c), rhs_p = -gp when nullptr.
+// Back-substitution dp = Vinv (b_p - sum_k W_k^T x_c) = hp - z per point: hp = Vinv b_p from
+// launch_point_damp, z = Vinv sum_k W_k^T x_c from launch_schur_point run on the matvec records
+// holding x (launch_x_to_mv); use_z = false (no solve camera) gives dp = hp.
 template <typename T>
-void launch_backsub(hipStream_t s, bool adj, int D, int G, const Model& m, const Compact<T>& cp,
-                    ObsMetric<T> om, const T* Vinv, const double* x, const double* gp,
-                    const double* rhs_p, double* dp);
+void launch_backsub(hipStream_t s, int Pa, const double* hp, const P3<T>* zq, bool use_z,
+                    double* dp);
 
 // ------------------------------------------------------------------ candidate
 // Candidate camera table over all slots (retracted for s < Ca, copied for fixed slots).

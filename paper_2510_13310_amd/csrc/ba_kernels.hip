@@ -1843,71 +1843,20 @@ k_true_residual(int Ca, const double* __restrict__ x, const double* __restrict__
   }
 }
 
-// Back-substitution dp = Vinv (rhs_p - sum_k W_k^T x_c), same lane layout as the point pass.
-template <typename T, bool ADJ, int G, int D>
+// Back-substitution dp = Vinv (b_p - sum_k W_k^T x_c) = hp - z, where hp = Vinv b_p comes from
+// the damping setup and z = Vinv sum_k W_k^T x_c from the PCG point pass run on x (the camera
+// step copied into the matvec records); with no solve camera (Ca = 0) dp = hp.
+template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_backsub(Model m, Compact<T> cp, ObsMetric<T> om, const T* __restrict__ Vinv,
-          const double* __restrict__ x, const double* __restrict__ gp,
-          const double* __restrict__ rhs_p, double* __restrict__ dp) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = t / G;
-  const int l = t % G;
-  const int Ca = cp.Ca;
-  T y[3] = {T(0), T(0), T(0)};
-  if (r < cp.Pa) {
-    const T X0 = cp.Xt[3 * r], X1 = cp.Xt[3 * r + 1], X2 = cp.Xt[3 * r + 2];
-    const int e = cp.off[r + 1];
-    for (int j = cp.off[r] + l; j < e; j += G) {
-      const int s = cp.cam[j];
-      if (s >= Ca) continue;
-      const Cam<T>& cm = cp.camt[s];
-      T Xc[3];
-      frame_t(cm.R, cm.c, X0, X1, X2, Xc);
-      AMat<T, ADJ> A;
-      A.set(cm.f, T(m.lam_d), Xc);
-      if constexpr (ADJ) A.project(om.eh + 3 * j);
-      const T w3[3] = {T(x[3 * Ca + s]), T(x[4 * Ca + s]), T(x[5 * Ca + s])};
-      T o3[3], d[3], tt[3], mm[3], rt[3];
-      cross3(w3, Xc, o3);
-      d[0] = T(x[s]) + o3[0];
-      d[1] = T(x[Ca + s]) + o3[1];
-      d[2] = T(x[2 * Ca + s]) + o3[2];
-      A.apply(d, tt);
-      if constexpr (D == 7) {   // focal column times the camera's focal step
-        const T uf = T(x[6 * Ca + s]) / Xc[2];
-        tt[0] += Xc[0] * uf;
-        tt[1] += Xc[1] * uf;
-      }
-      A.applyT(tt, mm);
-      const T w = om.w[j];
-      mm[0] *= w; mm[1] *= w; mm[2] *= w;
-      if constexpr (ADJ) {
-        if (om.ce) {   // full Hessian: + S d + a x x_phi (see Curv)
-          const T c3[3] = {om.ce[3 * j], om.ce[3 * j + 1], om.ce[3 * j + 2]};
-          Curv<T> K;
-          K.set(cm.f, T(m.lam_d), Xc, c3);
-          K.add_s(d, mm);
-          T au[3];
-          cross3(K.a, w3, au);
-          mm[0] += au[0]; mm[1] += au[1]; mm[2] += au[2];
-        }
-      }
-      rot_tmul(cm, mm, rt);
-      y[0] += rt[0]; y[1] += rt[1]; y[2] += rt[2];
-    }
-  }
-  y[0] = group_sum<G>(y[0]);
-  y[1] = group_sum<G>(y[1]);
-  y[2] = group_sum<G>(y[2]);
-  if (r < cp.Pa && l == 0) {
-    double b[3];
-    for (int i = 0; i < 3; ++i)
-      b[i] = (rhs_p ? rhs_p[3 * r + i] : -gp[3 * r + i]) - double(y[i]);
-    const T* vi = Vinv + 6 * r;
-    dp[3 * r] = double(vi[0]) * b[0] + double(vi[1]) * b[1] + double(vi[2]) * b[2];
-    dp[3 * r + 1] = double(vi[1]) * b[0] + double(vi[3]) * b[1] + double(vi[4]) * b[2];
-    dp[3 * r + 2] = double(vi[2]) * b[0] + double(vi[4]) * b[1] + double(vi[5]) * b[2];
-  }
+k_backsub(int Pa, const double* __restrict__ hp, const P3<T>* __restrict__ zq, int use_z,
+          double* __restrict__ dp) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= Pa) return;
+  P3<T> z{T(0), T(0), T(0)};
+  if (use_z) z = zq[r];
+  dp[3 * r] = hp[3 * r] - double(z.x);
+  dp[3 * r + 1] = hp[3 * r + 1] - double(z.y);
+  dp[3 * r + 2] = hp[3 * r + 2] - double(z.z);
 }
 
 // ------------------------------------------------------------------ candidate
@@ -3408,40 +3357,11 @@ void launch_true_residual(hipStream_t s, int D, int Ca, const double* x, const d
   });
 }
 
-template <typename T, bool ADJ, int D>
-void backsub_g(hipStream_t s, int G, const Model& m, const Compact<T>& cp, ObsMetric<T> om,
-               const T* Vinv, const double* x, const double* gp, const double* rhs_p,
-               double* dp) {
-  const unsigned nb = blocks_for(int64_t(cp.Pa) * G);
-  switch (G) {
-    case 2:
-      launch_k((k_backsub<T, ADJ, 2, D>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, Vinv, x, gp,
-               rhs_p, dp);
-      break;
-    case 4:
-      launch_k((k_backsub<T, ADJ, 4, D>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, Vinv, x, gp,
-               rhs_p, dp);
-      break;
-    case 16:
-      launch_k((k_backsub<T, ADJ, 16, D>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, Vinv, x,
-               gp, rhs_p, dp);
-      break;
-    default:
-      launch_k((k_backsub<T, ADJ, 8, D>), dim3(nb), dim3(kBlock), 0, s, m, cp, om, Vinv, x, gp,
-               rhs_p, dp);
-  }
-}
-
 template <typename T>
-void launch_backsub(hipStream_t s, bool adj, int D, int G, const Model& m, const Compact<T>& cp,
-                    ObsMetric<T> om, const T* Vinv, const double* x, const double* gp,
-                    const double* rhs_p, double* dp) {
-  if (adj)
-    backsub_g<T, true, 6>(s, G, m, cp, om, Vinv, x, gp, rhs_p, dp);
-  else
-    with_dim(D, [&](auto Dc) {
-      backsub_g<T, false, Dc()>(s, G, m, cp, om, Vinv, x, gp, rhs_p, dp);
-    });
+void launch_backsub(hipStream_t s, int Pa, const double* hp, const P3<T>* zq, bool use_z,
+                    double* dp) {
+  if (Pa <= 0) return;
+  launch_k(k_backsub<T>, dim3(blocks_for(Pa)), dim3(kBlock), 0, s, Pa, hp, zq, int(use_z), dp);
 }
 
 void launch_cam_candidate(hipStream_t s, int Ca, int Cf, int D, const int* cam_src,
@@ -3551,9 +3471,8 @@ void launch_adjoint_obs(hipStream_t s, const Model& m, const Compact<T>& cp, Obs
   template void launch_x_to_mv<T>(hipStream_t, int, int, const double*, void*, PcgState*);    \
   template void launch_true_residual<T>(hipStream_t, int, int, const double*, const double*,  \
                                         const T*, const int*, int, const double*, double*);   \
-  template void launch_backsub<T>(hipStream_t, bool, int, int, const Model&,                  \
-                                  const Compact<T>&, ObsMetric<T>, const T*, const double*,   \
-                                  const double*, const double*, double*);                      \
+  template void launch_backsub<T>(hipStream_t, int, const double*, const P3<T>*, bool,        \
+                                  double*);                                                    \
   template int launch_point_candidate<T>(hipStream_t, const Model&, const Compact<T>&, int,   \
                                          const Cam<double>*, const double*, const double*,    \
                                          const double*, const T*, double*, double*,           \
