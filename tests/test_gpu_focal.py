@@ -77,6 +77,27 @@ def test_focal_extraction_and_normal_blocks(precision, tol):
     assert rel_err(gp, gpo) < (1e-9 if precision == "fp64" else 1e-5)
 
 
+def test_focal_single_step_split_items():
+    """7 x 7 camera blocks summed over split items: 80,000 observations on the 10 tiny-scene
+    cameras, every camera's piece of each of the 8 point ranges longer than the 512-position
+    item bound; one float64 step against the oracle's Cholesky step (1e-6)."""
+    sc = focal_scene("tiny", n_points=20_000)
+    prob, opts, st = oracle_focal(sc, lambda_init=1.0)
+    new, orep = lm_step(prob, st, opts)
+    ba = gpu_setup(sc, "fp64", refine_focal=1, lambda_init=1.0, pcg_rel_tol=1e-13,
+                   pcg_max_iters=3000)
+    rep = ba.lm_step()
+    assert rep["n_obs_active"] == orep.extraction.obs.size
+    dc, dp = ba.get_last_step()
+    odc, odp = full_delta(orep.extraction, orep.delta, sc.n_cams, sc.n_points, d=7)
+    print(f"focal split items: step error cameras {rel_err(dc, odc):.2e}, focal "
+          f"{rel_err(dc[:, 6], odc[:, 6]):.2e}, points {rel_err(dp, odp):.2e}")
+    assert rel_err(dc, odc) < 1e-6, rel_err(dc, odc)
+    assert rel_err(dc[:, 6], odc[:, 6]) < 1e-6
+    assert rel_err(dp, odp) < 1e-6, rel_err(dp, odp)
+    assert bool(rep["accepted"]) == orep.accepted
+
+
 @pytest.mark.parametrize("name,lam", [("tiny", 1e-3), ("medium", 1e-2), ("medium", 1.0)])
 def test_focal_single_step_matches_cholesky(name, lam):
     sc = focal_scene(name)
